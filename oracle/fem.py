@@ -1,0 +1,302 @@
+"""FP64 reference energies and derivatives (test infrastructure only).
+
+Everything is written out from the definitions in the paper, vectorised over
+elements with NumPy. The Hessian is assembled explicitly (no matrix-free
+products), so this module shares no algorithm with the GPU path.
+
+  * Element energy: neo-Hookean density (Sec. 3, Eq. 3) with the quadratic
+    stand-in for log J that the paper uses for inverted elements, plus the
+    contractile fibre term (Eq. 2) written per element along a material
+    direction; F is linear in x (Sec. 3).
+  * Vertex energies: ground contact (Sec. 5.2, Eq. 15), friction through the
+    velocity v(x) = (x - x0)/h (Eq. 16-17), gravity.
+  * Objectives: quasistatic E (Eq. 1) and backward Euler
+    1/2 |x - (x0 + h v0)|_M^2 + h^2 E (Eq. 14).
+
+Readings where the paper is silent (all listed in the design doc):
+  log J is replaced by l(J) = (J-1) - (J-1)^2/2 for every J; I1 - d in 3D;
+  one fibre per element with l/l0 = |F d|; lumped mass rho W / (d+1) per corner;
+  contact has no 1/2 and an indicator [y < 0]; friction factor
+  ReLU(-y0 + eps) on the tangential components; gravity lives inside E.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import scipy.sparse as sp
+
+
+# --------------------------------------------------------------------------------------------
+# geometry (Sec. 3: F is a linear function of x)
+# --------------------------------------------------------------------------------------------
+def edge_matrix(x: np.ndarray, T: np.ndarray) -> np.ndarray:
+    """D[e] = [x_{T[e,1]} - x_{T[e,0]}, ..., x_{T[e,d]} - x_{T[e,0]}] as columns, [n_e, d, d]."""
+    e = x[T[:, 1:]] - x[T[:, :1]]          # [n_e, d (edge), d (coord)]
+    return np.swapaxes(e, 1, 2)
+
+
+def det(F: np.ndarray) -> np.ndarray:
+    d = F.shape[-1]
+    if d == 2:
+        return F[..., 0, 0] * F[..., 1, 1] - F[..., 0, 1] * F[..., 1, 0]
+    return np.linalg.det(F)
+
+
+def cofactor(F: np.ndarray) -> np.ndarray:
+    """cof F = dJ/dF (= J F^-T when F is invertible)."""
+    d = F.shape[-1]
+    C = np.empty_like(F)
+    if d == 2:
+        C[..., 0, 0] = F[..., 1, 1]
+        C[..., 0, 1] = -F[..., 1, 0]
+        C[..., 1, 0] = -F[..., 0, 1]
+        C[..., 1, 1] = F[..., 0, 0]
+        return C
+    c0, c1, c2 = F[..., :, 0], F[..., :, 1], F[..., :, 2]
+    C[..., :, 0] = np.cross(c1, c2)
+    C[..., :, 1] = np.cross(c2, c0)
+    C[..., :, 2] = np.cross(c0, c1)
+    return C
+
+
+def cofactor_diff(F: np.ndarray, dF: np.ndarray) -> np.ndarray:
+    """Directional derivative of cof F along dF."""
+    d = F.shape[-1]
+    if d == 2:
+        return cofactor(dF)
+    C = np.empty_like(F)
+    f = [F[..., :, k] for k in range(3)]
+    g = [dF[..., :, k] for k in range(3)]
+    for k in range(3):
+        i, j = (k + 1) % 3, (k + 2) % 3
+        C[..., :, k] = np.cross(g[i], f[j]) + np.cross(f[i], g[j])
+    return C
+
+
+class Mesh:
+    """Rest-shape quantities of a simplicial mesh (Sec. 3; lumped M of Eq. 14)."""
+
+    def __init__(self, X, T, rho):
+        self.X = np.asarray(X, dtype=np.float64)
+        self.T = np.asarray(T, dtype=np.int64)
+        self.n_v, self.d = self.X.shape
+        self.n_e = self.T.shape[0]
+        Dm = edge_matrix(self.X, self.T)
+        self.W = det(Dm) / math.factorial(self.d)
+        if np.any(self.W <= 0):
+            raise ValueError("non-positive rest volume")
+        self.DmInv = np.linalg.inv(Dm)
+        self.mass = np.zeros(self.n_v)
+        np.add.at(self.mass, self.T, (np.asarray(rho, dtype=np.float64) * self.W / (self.d + 1))[:, None])
+
+    def F(self, x):
+        return edge_matrix(x, self.T) @ self.DmInv
+
+
+# --------------------------------------------------------------------------------------------
+# element energy density and its first and second derivatives (Eq. 2, Eq. 3)
+# --------------------------------------------------------------------------------------------
+def logq(J):
+    """Quadratic replacement of log J about J = 1 (finite for J <= 0)."""
+    return (J - 1.0) - 0.5 * (J - 1.0) ** 2
+
+
+def logq_d(J):
+    return 2.0 - J
+
+
+LOGQ_DD = -1.0
+
+
+def psi(F, mu, lam, kf, a, fd):
+    """Energy density: mu/2 (I1 - d) - mu l(J) + lam/2 l(J)^2 + kf/2 (|F fd| / a - 1)^2."""
+    d = F.shape[-1]
+    I1 = np.sum(F * F, axis=(-2, -1))
+    lJ = logq(det(F))
+    s = np.linalg.norm(np.einsum("eij,ej->ei", F, fd), axis=-1)
+    return 0.5 * mu * (I1 - d) - mu * lJ + 0.5 * lam * lJ ** 2 + 0.5 * kf * (s / a - 1.0) ** 2
+
+
+def stress(F, mu, lam, kf, a, fd):
+    """First Piola stress P = d psi / dF."""
+    J = det(F)
+    lJ, dl = logq(J), logq_d(J)
+    C = cofactor(F)
+    P = mu[:, None, None] * F + ((lam * lJ - mu) * dl)[:, None, None] * C
+    Ffd = np.einsum("eij,ej->ei", F, fd)
+    s = np.linalg.norm(Ffd, axis=-1)
+    n = Ffd / s[:, None]
+    P += ((kf / a) * (s / a - 1.0))[:, None, None] * np.einsum("ei,ej->eij", n, fd)
+    return P
+
+
+def stress_diff(F, dF, mu, lam, kf, a, fd):
+    """dP = (d^2 psi / dF^2) : dF."""
+    J = det(F)
+    lJ, dl = logq(J), logq_d(J)
+    C = cofactor(F)
+    dJ = np.sum(C * dF, axis=(-2, -1))
+    dP = mu[:, None, None] * dF
+    dP += ((lam * lJ - mu) * dl)[:, None, None] * cofactor_diff(F, dF)
+    dP += ((lam * dl * dl + (lam * lJ - mu) * LOGQ_DD) * dJ)[:, None, None] * C
+    Ffd = np.einsum("eij,ej->ei", F, fd)
+    s = np.linalg.norm(Ffd, axis=-1)
+    n = Ffd / s[:, None]
+    q = np.einsum("eij,ej->ei", dF, fd)                   # dF fd
+    nq = np.sum(n * q, axis=-1)
+    dn = (q - n * nq[:, None]) / s[:, None]               # d(n) = (I - n n^T) dF fd / s
+    dP += ((kf / (a * a)) * nq)[:, None, None] * np.einsum("ei,ej->eij", n, fd)
+    dP += ((kf / a) * (s / a - 1.0))[:, None, None] * np.einsum("ei,ej->eij", dn, fd)
+    return dP
+
+
+# --------------------------------------------------------------------------------------------
+# per-element vertex gradients and Hessian blocks
+# --------------------------------------------------------------------------------------------
+def corner_grads(mesh: Mesh, G):
+    """Map a per-element dE/dF-shaped quantity G [n_e, d, d] to per-corner gradients.
+
+    E_e depends on x through F = D_s(x) Dm^-1, so dE_e/dD_s = W G Dm^-T; column j of it is the
+    gradient at corner j+1 and corner 0 takes minus their sum. Returns [n_e, d+1, d].
+    """
+    H = mesh.W[:, None, None] * (G @ np.swapaxes(mesh.DmInv, 1, 2))
+    out = np.empty((mesh.n_e, mesh.d + 1, mesh.d))
+    out[:, 1:, :] = np.swapaxes(H, 1, 2)
+    out[:, 0, :] = -out[:, 1:, :].sum(axis=1)
+    return out
+
+
+def corner_dF(mesh: Mesh, j: int, c: int):
+    """dF of every element for a unit displacement of its corner j along axis c."""
+    dDs = np.zeros((mesh.n_e, mesh.d, mesh.d))
+    if j == 0:
+        dDs[:, c, :] = -1.0
+    else:
+        dDs[:, c, j - 1] = 1.0
+    return dDs @ mesh.DmInv
+
+
+def element_hessians(mesh: Mesh, x, mu, lam, kf, a, fd):
+    """Dense element Hessians [n_e, (d+1)d, (d+1)d] of E_e = W psi(F), row/col index = corner*d + axis."""
+    F = mesh.F(x)
+    nd = (mesh.d + 1) * mesh.d
+    K = np.empty((mesh.n_e, nd, nd))
+    for j in range(mesh.d + 1):
+        for c in range(mesh.d):
+            dP = stress_diff(F, corner_dF(mesh, j, c), mu, lam, kf, a, fd)
+            K[:, :, j * mesh.d + c] = corner_grads(mesh, dP).reshape(mesh.n_e, nd)
+    return K
+
+
+# --------------------------------------------------------------------------------------------
+# the step objective g(x) (Eq. 1 quasistatic, Eq. 14 backward Euler) and its derivatives
+# --------------------------------------------------------------------------------------------
+class Problem:
+    """One body: mesh, material, scene constants. All arrays FP64; x is [n_v, d]."""
+
+    def __init__(self, X, T, pinned, mu, lam, kf, fdir, rho, scene):
+        self.mesh = Mesh(X, T, rho)
+        self.pinned = np.asarray(pinned, dtype=bool)
+        self.free = ~self.pinned.ravel()
+        self.mu = np.asarray(mu, dtype=np.float64)
+        self.lam = np.asarray(lam, dtype=np.float64)
+        self.kf = np.asarray(kf, dtype=np.float64)
+        self.fd = np.asarray(fdir, dtype=np.float64)
+        self.sc = dict(scene)
+        self.be = self.sc["integrator"] == "be"
+        self.h = float(self.sc["h"])
+        # the potential energy is scaled by h^2 in the backward-Euler objective (Eq. 14)
+        self.s_pot = self.h ** 2 if self.be else 1.0
+
+    @classmethod
+    def from_workload(cls, w):
+        return cls(w.X, w.T, w.pinned, w.mu, w.lam, w.kf, w.fdir, w.rho, w.scene)
+
+    # ---- vertex terms (Eq. 15-17 and gravity) ----
+    def friction_factor(self, x0):
+        return np.maximum(-x0[:, 1] + self.sc["eps_friction"], 0.0)
+
+    def tangential(self):
+        return [0] if self.mesh.d == 2 else [0, 2]
+
+    def vertex_energy(self, x, x0):
+        """Per-vertex potential energy [n_v] (gravity + contact + friction)."""
+        m, g = self.mesh.mass, self.sc["gravity"]
+        y = x[:, 1]
+        e = m * g * y + self.sc["k_contact"] * np.maximum(-y, 0.0) ** 2
+        if self.sc["k_friction"] != 0.0:
+            cv = self.friction_factor(x0)
+            vt = (x[:, self.tangential()] - x0[:, self.tangential()]) / self.h
+            e = e + self.sc["k_friction"] * cv * np.sum(vt * vt, axis=1)
+        return e
+
+    def vertex_grad(self, x, x0):
+        m, g = self.mesh.mass, self.sc["gravity"]
+        G = np.zeros_like(x)
+        G[:, 1] = m * g - 2.0 * self.sc["k_contact"] * np.maximum(-x[:, 1], 0.0)
+        if self.sc["k_friction"] != 0.0:
+            cv = self.friction_factor(x0)
+            t = self.tangential()
+            G[:, t] += (2.0 * self.sc["k_friction"] * cv / self.h ** 2)[:, None] * (x[:, t] - x0[:, t])
+        return G
+
+    def vertex_hess_diag(self, x, x0):
+        Hd = np.zeros_like(x)
+        Hd[:, 1] = 2.0 * self.sc["k_contact"] * (x[:, 1] < 0.0)
+        if self.sc["k_friction"] != 0.0:
+            cv = self.friction_factor(x0)
+            Hd[:, self.tangential()] += (2.0 * self.sc["k_friction"] * cv / self.h ** 2)[:, None]
+        return Hd
+
+    # ---- element terms ----
+    def element_energy(self, x, a):
+        F = self.mesh.F(x)
+        return self.mesh.W * psi(F, self.mu, self.lam, self.kf, a, self.fd)
+
+    def element_grad(self, x, a):
+        """Assembled gradient of sum_e E_e, [n_v, d]."""
+        F = self.mesh.F(x)
+        cg = corner_grads(self.mesh, stress(F, self.mu, self.lam, self.kf, a, self.fd))
+        G = np.zeros_like(x)
+        np.add.at(G, self.mesh.T, cg)
+        return G
+
+    # ---- objective ----
+    def x_hat(self, x0, v0):
+        return x0 + self.h * v0 if self.be else x0
+
+    def energy_terms(self, x, x0, v0, a):
+        """(per-element terms, per-vertex terms) of g; their total sum is g(x)."""
+        ee = self.s_pot * self.element_energy(x, a)
+        ev = self.s_pot * self.vertex_energy(x, x0)
+        if self.be:
+            dx = x - self.x_hat(x0, v0)
+            ev = ev + 0.5 * self.mesh.mass * np.sum(dx * dx, axis=1)
+        return ee, ev
+
+    def energy(self, x, x0, v0, a):
+        ee, ev = self.energy_terms(x, x0, v0, a)
+        return float(np.sum(ee) + np.sum(ev))
+
+    def grad(self, x, x0, v0, a):
+        """dg/dx [n_v, d]; pinned DOFs are not masked here."""
+        G = self.s_pot * (self.element_grad(x, a) + self.vertex_grad(x, x0))
+        if self.be:
+            G += self.mesh.mass[:, None] * (x - self.x_hat(x0, v0))
+        return G
+
+    def hessian(self, x, x0, a) -> sp.csr_matrix:
+        """Assembled d^2 g / dx^2 over all n_v*d DOFs (row-major DOF = v*d + axis)."""
+        d = self.mesh.d
+        K = self.s_pot * element_hessians(self.mesh, x, self.mu, self.lam, self.kf, a, self.fd)
+        dofs = (self.mesh.T[:, :, None] * d + np.arange(d)[None, None, :]).reshape(self.mesh.n_e, -1)
+        rows = np.repeat(dofs, dofs.shape[1], axis=1).ravel()
+        cols = np.tile(dofs, (1, dofs.shape[1])).ravel()
+        n = self.mesh.n_v * d
+        H = sp.coo_matrix((K.ravel(), (rows, cols)), shape=(n, n)).tocsr()
+        diag = self.s_pot * self.vertex_hess_diag(x, x0)
+        if self.be:
+            diag = diag + self.mesh.mass[:, None]
+        H = H + sp.diags(diag.ravel())
+        return H.tocsr()
