@@ -1,0 +1,219 @@
+/*
+ * isb.h - C ABI of the implicit soft-body step and its adjoint (libisb.so, gfx950).
+ *
+ * One call of isb_step advances every body of an uploaded mesh by one implicit
+ * step posed as energy minimisation:
+ *   quasistatic      x1 = argmin_x E(x, a)                                 (Sec. 3, Eq. 1)
+ *   backward Euler   x1 = argmin_x 1/2 |x - (x0 + h v0)|_M^2 + h^2 E(x, a)  (Sec. 5, Eq. 13-14)
+ *                    v1 = (x1 - x0) / h
+ * E is, per element, the neo-Hookean density of Eq. 3 (log J replaced by its
+ * quadratic expansion about J = 1, as Sec. 3 prescribes for inverted elements)
+ * plus the contractile fibre term of Eq. 2 taken along a per-element material
+ * direction d (l / l0 = |F d|), scaled by the rest volume W; and, per vertex,
+ * gravity m g y, ground contact k_c ReLU(-y)^2 (Eq. 15) and friction
+ * k_fr ((x_t - x0_t)/h)^2 ReLU(-y0 + eps) on the tangential axes (Eq. 16-17).
+ * The minimiser is found by Newton's method with a preconditioned conjugate
+ * gradient inner solve over matrix-free Hessian-vector products (Sec. 4.1,
+ * Eq. 10); the backward pass is the adjoint of Eq. 9: one CG solve with the
+ * symmetric Hessian H(x1), followed by per-element vector-Jacobian products.
+ *
+ * Conventions shared by every call
+ *   - Vertex arrays are [n_v][dim] row-major FP64 (the n x d layout of Sec. 4.1);
+ *     element arrays are [n_e] or [n_e][dim]; y (axis 1) is "up"; dim is 2
+ *     (triangles) or 3 (tetrahedra).
+ *   - Pointers named "host" are CPU memory, copied before the call returns.
+ *     Every other array argument is device memory on the context's GPU, owned
+ *     by the caller; the library never keeps a caller pointer past the call.
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream). All device
+ *     work of a call is enqueued on it. A call that returns statistics to host
+ *     memory synchronises the stream; with stats == NULL and the graph-safe
+ *     option set, isb_step / isb_solve_adjoint / isb_vjp_params enqueue work
+ *     only (no host synchronisation, no allocation) and may be captured.
+ *   - Pinned (Dirichlet) DOFs keep their x0 value; the adjoint, x0_bar and
+ *     v0_bar are 0 on them (pins are boundary data, not differentiable state).
+ *   - Every call returns an isb_status; on failure isb_last_error() describes it.
+ *     The library owns the context and every workspace; isb_destroy frees them.
+ */
+#ifndef ISB_H
+#define ISB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct isb_ctx isb_ctx;   /* opaque, library-owned */
+typedef void* isb_stream;         /* a hipStream_t */
+
+typedef enum {
+  ISB_OK = 0,
+  ISB_E_ARG = 1,            /* bad argument: NULL pointer, size, a <= 0, unknown key */
+  ISB_E_MESH = 2,           /* invalid mesh: index out of body range, non-positive rest volume */
+  ISB_E_HIP = 3,            /* HIP runtime error */
+  ISB_E_NOT_CONVERGED = 4,  /* Newton or CG hit its iteration cap; outputs hold the last iterate */
+  ISB_E_NONFINITE = 5,      /* NaN or Inf in an energy, residual or input */
+  ISB_E_STATE = 6           /* call order: e.g. step before mesh and material upload */
+} isb_status;
+
+typedef enum { ISB_FP64 = 0, ISB_MIXED = 1 } isb_precision;
+typedef enum { ISB_QUASISTATIC = 0, ISB_BACKWARD_EULER = 1 } isb_integrator;
+
+/* Option keys for isb_set_option / isb_get_option. */
+typedef enum {
+  ISB_OPT_SOLVER = 0,       /* 0 = plain: host-driven Newton-PCG, one body at a time, grid-wide kernels;
+                               1 = batched: one persistent launch, one workgroup per body (default 0) */
+  ISB_OPT_SCATTER = 1,      /* plain solver scatter: 0 = FP64 atomics (default), 1 = graph colouring
+                               (deterministic, bitwise reproducible) */
+  ISB_OPT_GRAPH_SAFE = 2,   /* 1 = no host synchronisation inside step/adjoint/vjp (batched solver only) */
+  ISB_OPT_BLOCK = 3,        /* batched solver workgroup size: 256, 512 or 1024 (default 1024) */
+  ISB_OPT_CG_CHECK = 4,     /* plain solver: read the CG convergence flag every k iterations (default 4) */
+  ISB_OPT_PRECISION = 5     /* isb_precision; equals the value given to isb_create */
+} isb_option;
+
+/* Read-only context facts for isb_get_option. */
+#define ISB_INFO_N_VERTICES 100
+#define ISB_INFO_N_ELEMENTS 101
+#define ISB_INFO_N_BODIES 102
+#define ISB_INFO_DIM 103
+#define ISB_INFO_N_COLOURS 104    /* colours of the element colouring (max over bodies) */
+#define ISB_INFO_LDS_BYTES 105    /* LDS bytes per workgroup of the batched solver for the largest body */
+
+/* Per-body solver statistics (host memory). */
+typedef struct {
+  int32_t newton_iters;     /* Newton iterations taken */
+  int32_t cg_iters;         /* CG iterations summed over the Newton iterations */
+  int32_t adj_cg_iters;     /* CG iterations of the last adjoint solve */
+  int32_t ls_backtracks;    /* line-search halvings */
+  int32_t negcurv_exits;    /* CG solves cut short by non-positive curvature */
+  int32_t flags;            /* bit 0 converged, bit 1 stagnated (rounding floor), bit 2 non-finite,
+                               bit 3 adjoint converged */
+  double res0;              /* |grad g(x_init)|_2 over free DOFs */
+  double res_final;         /* |grad g(x1)|_2 over free DOFs */
+  double adj_res_final;     /* |H w - xbar|_2 / |xbar|_2 (CG recursive residual) of the last adjoint */
+  double energy;            /* g(x1) */
+  double min_J, max_J;      /* extreme element volume ratios det F at x1 */
+} isb_stats;
+
+#define ISB_FLAG_CONVERGED 1
+#define ISB_FLAG_STAGNATED 2
+#define ISB_FLAG_NONFINITE 4
+#define ISB_FLAG_ADJ_CONVERGED 8
+
+/* Scene constants (one set for every body of the context). */
+typedef struct {
+  int32_t integrator;       /* isb_integrator */
+  int32_t max_newton;       /* Newton iteration cap (e.g. 50) */
+  int32_t max_cg;           /* CG iteration cap per solve (e.g. 1000) */
+  int32_t pad_;
+  double h;                 /* time step (backward Euler; also the friction velocity scale) */
+  double gravity;           /* g >= 0, acting along -y */
+  double k_contact;         /* ground penalty stiffness k_c (Eq. 15), ground at y = 0 */
+  double k_friction;        /* friction stiffness k_fr (Eq. 17) */
+  double eps_friction;      /* friction contact tolerance eps (Eq. 17) */
+  double tol_rel;           /* Newton stop: |grad g| <= tol_rel |grad g(x_init)| */
+  double adj_tol_rel;       /* adjoint CG stop: |H w - xbar| <= adj_tol_rel |xbar| */
+} isb_scene;
+
+/* ---- lifetime ---------------------------------------------------------------------------- */
+
+/* Create a context on HIP device `device` computing in `precision` (ISB_FP64: every element
+ * kernel in FP64; ISB_MIXED: Hessian-vector products and the preconditioner diagonal in FP32
+ * element arithmetic, while gradients, energies, CG vectors, dot products, norms and the state
+ * stay FP64). The boundary is FP64 in both modes. */
+isb_status isb_create(int device, int precision, isb_ctx** out);
+isb_status isb_destroy(isb_ctx* ctx);
+/* Thread-local description of the last failure on this thread; valid until the next isb_ call. */
+const char* isb_last_error(void);
+/* Library version string. */
+const char* isb_version(void);
+
+/* ---- host-only helpers (no GPU needed) ---------------------------------------------------- */
+
+/* Check a mesh: dim in {2,3}; offsets monotone with body_v_off[0] = body_e_off[0] = 0 and
+ * body_v_off[n_bodies] = n_v, body_e_off[n_bodies] = n_e; each element's vertices distinct and
+ * inside its body's vertex range; every rest volume det(Dm)/dim! > 0 (Sec. 3: F = Ds Dm^-1).
+ * X host [n_v][dim], T host [n_e][dim+1] int32 (global vertex ids). Returns ISB_OK or ISB_E_MESH. */
+isb_status isb_validate_mesh(int dim, int64_t n_v, const double* X, int64_t n_e, const int32_t* T,
+                             int32_t n_bodies, const int64_t* body_v_off, const int64_t* body_e_off);
+
+/* Greedy element colouring: no two elements of one colour share a vertex. colour_out host [n_e]
+ * receives each element's colour; *n_colours_out the number of colours used. Deterministic. */
+isb_status isb_colour_elements(int dim, int64_t n_v, int64_t n_e, const int32_t* T,
+                               int32_t* colour_out, int32_t* n_colours_out);
+
+/* ---- upload ------------------------------------------------------------------------------- */
+
+/* Copy a mesh of n_bodies independent bodies to the device and precompute Dm^-1 and W per element.
+ * body_v_off / body_e_off host [n_bodies+1]; X_rest host [n_v][dim]; T host [n_e][dim+1]
+ * (positively oriented); dof_pinned host [n_v][dim], 1 = Dirichlet. Validates first (ISB_E_MESH).
+ * Replaces any previous mesh (the material must then be uploaded again). */
+isb_status isb_mesh_upload(isb_ctx* ctx, int dim, int32_t n_bodies, const int64_t* body_v_off,
+                           const int64_t* body_e_off, const double* X_rest, const int32_t* T,
+                           const uint8_t* dof_pinned);
+
+/* Per-element material, all host [n_e] except fibre_dir host [n_e][dim] (unit material-space
+ * direction d of the fibre, Eq. 2) and the scene. mu, lam: Lame pair of Eq. 3; k_fibre: k of
+ * Eq. 2 per unit rest volume; density: rho, giving the lumped mass m_v = sum rho W / (dim+1)
+ * (the M of Eq. 14). Requires a mesh. */
+isb_status isb_material_upload(isb_ctx* ctx, const double* mu, const double* lam, const double* k_fibre,
+                               const double* fibre_dir, const double* density, const isb_scene* scene);
+
+/* Replace the scene constants (tolerances, stiffnesses, h) without re-uploading the material. */
+isb_status isb_set_scene(isb_ctx* ctx, const isb_scene* scene);
+
+isb_status isb_set_option(isb_ctx* ctx, int key, int64_t value);
+isb_status isb_get_option(isb_ctx* ctx, int key, int64_t* value);
+
+/* Lumped vertex masses, device out [n_v] (FP64). */
+isb_status isb_get_mass(isb_ctx* ctx, isb_stream stream, double* mass_out);
+
+/* ---- the step and its adjoint ------------------------------------------------------------- */
+
+/* One implicit step (Eq. 1 or Eq. 14) of every body. x0, v0: device [n_v][dim] (v0 ignored and
+ * may be NULL in quasistatic mode); a: device [n_e], actuation of Eq. 2 (1 = relaxed, < 1
+ * contracts; must be > 0); x1, v1: device out [n_v][dim] (v1 may be NULL; it is not written in
+ * quasistatic mode). per_body: host [n_bodies] stats or NULL. Returns ISB_E_NOT_CONVERGED if
+ * any body hit max_newton (x1, v1 then hold the last iterate), ISB_E_NONFINITE on NaN/Inf. */
+isb_status isb_step(isb_ctx* ctx, isb_stream stream, const double* x0, const double* v0,
+                    const double* a, double* x1, double* v1, isb_stats* per_body);
+
+/* Adjoint solve of Eq. 9: w = H(x1)^-1 (x1_bar + v1_bar / h) over the free DOFs (the v1_bar term
+ * only in backward Euler; v1_bar may be NULL), w = 0 on pinned DOFs. H is the unprojected
+ * Hessian of the step objective at x1, symmetric and positive definite at a minimiser (Sec. 4),
+ * so CG needs no transpose. x1, x0: device [n_v][dim]; a: device [n_e]; w: device out. */
+isb_status isb_solve_adjoint(isb_ctx* ctx, isb_stream stream, const double* x1, const double* x0,
+                             const double* a, const double* x1_bar, const double* v1_bar, double* w,
+                             isb_stats* per_body);
+
+/* Vector-Jacobian products given the adjoint w: theta_bar = -w^T dG/dtheta with G = grad_x g
+ * (Eq. 9 and the remark after Eq. 10), evaluated at x1. Outputs (device, any may be NULL):
+ *   a_bar, mu_bar, lam_bar, kf_bar [n_e]   per-element actuation and material cotangents
+ *   x0_bar, v0_bar [n_v][dim]              previous-state cotangents, including the explicit
+ *                                          v1 = (x1 - x0)/h path (-v1_bar / h) in backward Euler */
+isb_status isb_vjp_params(isb_ctx* ctx, isb_stream stream, const double* w, const double* x1,
+                          const double* x0, const double* a, const double* v1_bar, double* a_bar,
+                          double* x0_bar, double* v0_bar, double* mu_bar, double* lam_bar,
+                          double* kf_bar);
+
+/* ---- single evaluations of the step objective (the kernels of the solver, exposed) --------- */
+
+/* g(x) per body, device out energy [n_bodies]; v0 may be NULL in quasistatic mode. */
+isb_status isb_energy(isb_ctx* ctx, isb_stream stream, const double* x, const double* x0,
+                      const double* v0, const double* a, double* energy);
+/* grad_x g(x), device out g [n_v][dim], 0 on pinned DOFs. */
+isb_status isb_gradient(isb_ctx* ctx, isb_stream stream, const double* x, const double* x0,
+                        const double* v0, const double* a, double* g);
+/* Hessian-vector product hp = P H(x) P p with P the projection onto free DOFs (Eq. 10);
+ * FP32 element arithmetic in ISB_MIXED. device [n_v][dim] in/out. */
+isb_status isb_hessvec(isb_ctx* ctx, isb_stream stream, const double* x, const double* x0,
+                       const double* a, const double* p, double* hp);
+/* Diagonal of H(x) over free DOFs (1 on pinned DOFs), device out [n_v][dim]. */
+isb_status isb_hessdiag(isb_ctx* ctx, isb_stream stream, const double* x, const double* x0,
+                        const double* a, double* diag);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ISB_H */

@@ -1,0 +1,810 @@
+// C-ABI implementation: context lifetime, upload, and the plain host-driven Newton-PCG solver.
+//
+// The plain solver handles one body at a time with grid-wide kernels. Per Newton iteration
+// (Sec. 3 and 5: x1 is the minimiser of the step objective; the paper leaves the minimiser free):
+//   gradient -> |G| (host read) -> Jacobi diagonal -> PCG on H dx = -G with device-resident
+//   scalars (host polls the stop flag every cg_check iterations) -> Armijo backtracking on
+//   element-wise energy differences (host read per trial) -> x += alpha dx.
+// The adjoint (Eq. 9) is one PCG solve with the same Hessian-vector kernel at x1.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "isb_ctx.hpp"
+
+using namespace isb;
+
+static constexpr double kArmijoC1 = 1e-4;
+static constexpr int kMaxBacktracks = 30;
+static constexpr double kEps = 2.220446049250313e-16;
+
+void isb_ctx::free_list(std::vector<void*>& v) {
+  for (void* p : v) (void)hipFree(p);
+  v.clear();
+}
+
+isb_ctx::~isb_ctx() {
+  (void)hipSetDevice(device);
+  batched_release(this);
+  free_list(work_allocs);
+  free_list(mesh_allocs);
+  if (hscal) (void)hipHostFree(hscal);
+  if (hcg) (void)hipHostFree(hcg);
+}
+
+namespace isb {
+
+DevMesh devmesh(const isb_ctx* c) {
+  DevMesh m;
+  m.dim = c->dim;
+  m.n_v = c->n_v;
+  m.n_e = c->n_e;
+  m.conn = c->conn;
+  m.Dinv = c->Dinv;
+  m.gf = c->gf;
+  m.W = c->W;
+  m.wmu = c->wmu;
+  m.wlam = c->wlam;
+  m.wkf = c->wkf;
+  m.Dinv32 = c->Dinv32;
+  m.gf32 = c->gf32;
+  m.wmu32 = c->wmu32;
+  m.wlam32 = c->wlam32;
+  m.wkf32 = c->wkf32;
+  m.mass = c->mass;
+  m.pinned = c->pinned;
+  return m;
+}
+
+DevScene devscene(const isb_ctx* c) {
+  DevScene s;
+  s.be = c->scene.integrator == ISB_BACKWARD_EULER;
+  s.h = c->scene.h;
+  s.s_pot = s.be ? c->scene.h * c->scene.h : 1.0;
+  s.grav = c->scene.gravity;
+  s.kc = c->scene.k_contact;
+  s.kfr = c->scene.k_friction;
+  s.eps = c->scene.eps_friction;
+  return s;
+}
+
+}  // namespace isb
+
+template <typename T>
+static isb_status dalloc(std::vector<void*>& list, T** p, size_t count) {
+  void* q = nullptr;
+  if (count == 0) count = 1;
+  ISB_HIP(hipMalloc(&q, count * sizeof(T)));
+  list.push_back(q);
+  *p = static_cast<T*>(q);
+  return ISB_OK;
+}
+
+#define ISB_TRY(expr)                 \
+  do {                                \
+    isb_status st_ = (expr);          \
+    if (st_ != ISB_OK) return st_;    \
+  } while (0)
+
+static isb_status check_ctx(isb_ctx* c, bool need_material) {
+  if (!c) return fail(ISB_E_ARG, "NULL context");
+  if (!c->have_mesh) return fail(ISB_E_STATE, "no mesh uploaded");
+  if (need_material && !c->have_material) return fail(ISB_E_STATE, "no material uploaded");
+  ISB_HIP(hipSetDevice(c->device));
+  return ISB_OK;
+}
+
+static isb_status check_scene(const isb_scene* s) {
+  if (!s) return fail(ISB_E_ARG, "NULL scene");
+  if (s->integrator != ISB_QUASISTATIC && s->integrator != ISB_BACKWARD_EULER)
+    return fail(ISB_E_ARG, "unknown integrator");
+  if (!(s->h > 0.0)) return fail(ISB_E_ARG, "h must be > 0");
+  if (s->max_newton < 0 || s->max_cg < 1) return fail(ISB_E_ARG, "iteration caps must be >= 0 / >= 1");
+  if (!(s->tol_rel >= 0.0) || !(s->adj_tol_rel >= 0.0)) return fail(ISB_E_ARG, "tolerances must be >= 0");
+  if (!std::isfinite(s->gravity) || !std::isfinite(s->k_contact) || !std::isfinite(s->k_friction) ||
+      !std::isfinite(s->eps_friction))
+    return fail(ISB_E_ARG, "non-finite scene constant");
+  return ISB_OK;
+}
+
+// read n doubles of dscal into hscal (synchronises the stream)
+static isb_status read_scal(isb_ctx* c, hipStream_t s, int n) {
+  ISB_HIP(hipMemcpyAsync(c->hscal, c->dscal, n * sizeof(double), hipMemcpyDeviceToHost, s));
+  ISB_HIP(hipStreamSynchronize(s));
+  return ISB_OK;
+}
+
+static isb_status read_cg(isb_ctx* c, hipStream_t s) {
+  ISB_HIP(hipMemcpyAsync(c->hcg, c->scal, sizeof(CgScal), hipMemcpyDeviceToHost, s));
+  ISB_HIP(hipStreamSynchronize(s));
+  return ISB_OK;
+}
+
+// run fn(ERange, atomic) over the elements of body b (all bodies when b < 0)
+template <class Fn>
+static void elem_ranges(const isb_ctx* c, int b, Fn fn) {
+  const int b0 = b < 0 ? 0 : b, b1 = b < 0 ? c->n_bodies : b + 1;
+  if (c->scatter == 0) {
+    fn(ERange{(int)c->eoff[b0], (int)c->eoff[b1], nullptr}, true);
+    return;
+  }
+  const int nc1 = c->n_colours + 1;
+  for (int bb = b0; bb < b1; ++bb)
+    for (int k = 0; k < c->n_colours; ++k) {
+      const int s = c->col_off[bb * nc1 + k], e = c->col_off[bb * nc1 + k + 1];
+      if (e > s) fn(ERange{s, e, c->clist}, false);
+    }
+}
+
+struct BodyRange {
+  int v0, v1, e0, e1, n, off;
+};
+
+static BodyRange body_range(const isb_ctx* c, int b) {
+  BodyRange r;
+  if (b < 0) {
+    r.v0 = 0;
+    r.v1 = c->n_v;
+    r.e0 = 0;
+    r.e1 = c->n_e;
+  } else {
+    r.v0 = (int)c->voff[b];
+    r.v1 = (int)c->voff[b + 1];
+    r.e0 = (int)c->eoff[b];
+    r.e1 = (int)c->eoff[b + 1];
+  }
+  r.n = (r.v1 - r.v0) * c->dim;
+  r.off = r.v0 * c->dim;
+  return r;
+}
+
+// ---------------------------------------------------------------------------------------------
+// building blocks of the plain solver (body b, or all bodies with b < 0)
+// ---------------------------------------------------------------------------------------------
+static void eval_grad(isb_ctx* c, int b, const double* x, const double* x0, const double* a, double* G,
+                      hipStream_t s) {
+  const DevMesh m = devmesh(c);
+  const DevScene sc = devscene(c);
+  const BodyRange br = body_range(c, b);
+  launch_vertex_grad(m, sc, br.v0, br.v1, x, x0, c->w_xhat, c->w_cv, G, s);
+  elem_ranges(c, b, [&](ERange r, bool atomic) { launch_elem_grad(m, sc, r, atomic, x, a, G, s); });
+  launch_mask(m, br.v0, br.v1, G, s);
+}
+
+// |v|_2 over body b's DOFs into dscal[slot]
+static void enqueue_norm2(isb_ctx* c, int b, const double* v, int slot, hipStream_t s) {
+  const BodyRange br = body_range(c, b);
+  int nb = 0;
+  launch_dot(br.n, v + br.off, v + br.off, c->partials, s, &nb);
+  launch_finalize(c->partials, nb, 1, c->dscal + slot, s);
+}
+
+static void eval_precond(isb_ctx* c, int b, const double* x, const double* a, hipStream_t s) {
+  const DevMesh m = devmesh(c);
+  const DevScene sc = devscene(c);
+  const BodyRange br = body_range(c, b);
+  launch_vertex_hdiag(m, sc, br.v0, br.v1, x, c->w_cv, c->w_vdiag, s);
+  launch_copy(br.n, c->w_vdiag + br.off, c->w_diag + br.off, s);
+  elem_ranges(c, b, [&](ERange r, bool atomic) {
+    launch_elem_diag(m, sc, r, atomic, c->precision, x, a, c->w_a32, c->w_diag, s);
+  });
+  launch_finish_diag(m, br.v0, br.v1, c->w_diag, c->w_Dinvp, s);
+}
+
+// energy change along dx at step alpha: dscal[0..3) = (sum dE, sum |E(x)|, E(x + alpha dx));
+// dx == nullptr gives the energy at x in dscal[2]
+static void enqueue_energy(isb_ctx* c, int b, const double* x, const double* dx, double alpha, const double* x0,
+                           const double* a, double* out, hipStream_t s) {
+  const DevMesh m = devmesh(c);
+  const DevScene sc = devscene(c);
+  const BodyRange br = body_range(c, b);
+  int nbe = 0, nbv = 0;
+  launch_elem_energy(m, sc, ERange{br.e0, br.e1, nullptr}, x, dx, alpha, a, c->partials, 0, s, &nbe);
+  launch_vertex_energy(m, sc, br.v0, br.v1, x, dx, alpha, x0, c->w_xhat, c->w_cv, c->partials, nbe, s, &nbv);
+  launch_finalize(c->partials, nbe + nbv, 3, out, s);
+}
+
+// PCG on H(x) xs = sign * rhs over body b; returns iterations, sets negcurv and the final r.r
+static isb_status run_cg(isb_ctx* c, int b, const double* x, const double* a, const double* rhs, double sign,
+                         double tol, int max_cg, hipStream_t s, int* iters, bool* negcurv, double* rr) {
+  const DevMesh m = devmesh(c);
+  const DevScene sc = devscene(c);
+  const BodyRange br = body_range(c, b);
+  const double tol2 = tol * tol;
+  const int o = br.off;
+  launch_cg_start(br.n, rhs + o, sign, c->w_Dinvp + o, c->w_vdiag + o, c->w_r + o, c->w_p + o, c->w_xs + o,
+                  c->w_Hp + o, c->partials, c->scal, tol2, s);
+  const int check = std::max(1, c->cg_check);
+  for (int it = 0; it < max_cg; ++it) {
+    elem_ranges(c, b, [&](ERange r, bool atomic) {
+      launch_elem_hv(m, sc, r, atomic, c->precision, x, a, c->w_a32, c->w_p, c->w_Hp, &c->scal->done, s);
+    });
+    launch_cg_dot(br.n, c->w_p + o, c->w_Hp + o, c->partials, c->scal, s);
+    launch_cg_update(br.n, it, c->w_p + o, c->w_Hp + o, c->w_Dinvp + o, c->w_r + o, c->w_xs + o, c->partials,
+                     c->scal, s);
+    launch_cg_p(br.n, it, c->w_r + o, c->w_Dinvp + o, c->w_vdiag + o, c->w_p + o, c->w_Hp + o, c->partials,
+                c->scal, tol2, s);
+    if (it == 0 || (it + 1) % check == 0 || it + 1 == max_cg) {
+      ISB_TRY(read_cg(c, s));
+      if (c->hcg->done) break;
+    }
+  }
+  ISB_TRY(read_cg(c, s));
+  *iters = c->hcg->iters;
+  *negcurv = c->hcg->negcurv != 0;
+  *rr = c->hcg->rr;
+  return ISB_OK;
+}
+
+// one Newton-PCG solve of body b; x is the iterate (workspace), G its gradient
+static isb_status plain_newton(isb_ctx* c, int b, hipStream_t s, const double* x0, const double* a, double** px,
+                               double** pxt, double** pG, double** pGt, isb_stats* st) {
+  const BodyRange br = body_range(c, b);
+  const isb_scene& sc = c->scene;
+  double *x = *px, *xt = *pxt, *G = *pG, *Gt = *pGt;
+  eval_grad(c, b, x, x0, a, G, s);
+  enqueue_norm2(c, b, G, 0, s);
+  ISB_TRY(read_scal(c, s, 1));
+  const double res0 = std::sqrt(c->hscal[0]);
+  double res = res0;
+  st->res0 = res0;
+  isb_status status = ISB_OK;
+  if (!std::isfinite(res0)) {
+    st->flags |= ISB_FLAG_NONFINITE;
+    status = fail(ISB_E_NONFINITE, "non-finite gradient at the initial guess");
+  }
+  while (status == ISB_OK) {
+    if (res <= sc.tol_rel * res0 || res == 0.0) {
+      st->flags |= ISB_FLAG_CONVERGED;
+      break;
+    }
+    if (st->newton_iters >= sc.max_newton) {
+      status = fail(ISB_E_NOT_CONVERGED, "Newton iteration cap reached");
+      break;
+    }
+    eval_precond(c, b, x, a, s);
+    // inexact Newton forcing term: the CG tolerance tightens as the gradient falls
+    const double eta = std::min(0.5, std::sqrt(res / res0));
+    int cg_it = 0;
+    bool neg = false;
+    double rr = 0.0;
+    ISB_TRY(run_cg(c, b, x, a, G, -1.0, eta * res, sc.max_cg, s, &cg_it, &neg, &rr));
+    st->cg_iters += cg_it;
+    st->negcurv_exits += neg ? 1 : 0;
+    double* dx = c->w_xs;
+    int nb = 0;
+    launch_dot(br.n, G + br.off, dx + br.off, c->partials, s, &nb);
+    launch_finalize(c->partials, nb, 1, c->dscal, s);
+    ISB_TRY(read_scal(c, s, 1));
+    double gTd = c->hscal[0];
+    if (!(gTd < 0.0)) {
+      // not a descent direction (CG stopped before any progress): preconditioned steepest descent
+      launch_neg_precond(br.n, c->w_Dinvp + br.off, G + br.off, dx + br.off, s);
+      launch_dot(br.n, G + br.off, dx + br.off, c->partials, s, &nb);
+      launch_finalize(c->partials, nb, 1, c->dscal, s);
+      ISB_TRY(read_scal(c, s, 1));
+      gTd = c->hscal[0];
+      if (!(gTd < 0.0)) {
+        st->flags |= ISB_FLAG_STAGNATED;
+        break;
+      }
+    }
+    // Armijo backtracking on sum_e [g_e(x + alpha dx) - g_e(x)]; below the FP64 resolution of g
+    // the decrease of |grad g| decides instead
+    double alpha = 1.0;
+    bool accepted = false, via_grad = false;
+    for (int ls = 0; ls <= kMaxBacktracks; ++ls) {
+      enqueue_energy(c, b, x, dx, alpha, x0, a, c->dscal, s);
+      ISB_TRY(read_scal(c, s, 3));
+      const double dg = c->hscal[0], gabs = c->hscal[1];
+      if (!std::isfinite(dg)) {
+        // overflow or an invalid trial point: backtrack
+      } else if (dg <= kArmijoC1 * alpha * gTd) {
+        accepted = true;
+      } else if (std::fabs(dg) <= 1e3 * kEps * gabs) {
+        launch_copy(br.n, x + br.off, xt + br.off, s);
+        launch_axpy(br.n, xt + br.off, alpha, dx + br.off, s);
+        eval_grad(c, b, xt, x0, a, Gt, s);
+        enqueue_norm2(c, b, Gt, 0, s);
+        ISB_TRY(read_scal(c, s, 1));
+        const double rt = std::sqrt(c->hscal[0]);
+        if (rt < res) {
+          accepted = via_grad = true;
+          std::swap(x, xt);
+          std::swap(G, Gt);
+          res = rt;
+        }
+      }
+      if (accepted) break;
+      alpha *= 0.5;
+      st->ls_backtracks += 1;
+    }
+    if (!accepted) {
+      st->flags |= ISB_FLAG_STAGNATED;
+      break;
+    }
+    if (!via_grad) {
+      launch_axpy(br.n, x + br.off, alpha, dx + br.off, s);
+      eval_grad(c, b, x, x0, a, G, s);
+      enqueue_norm2(c, b, G, 0, s);
+      ISB_TRY(read_scal(c, s, 1));
+      res = std::sqrt(c->hscal[0]);
+    }
+    st->newton_iters += 1;
+    if (!std::isfinite(res)) {
+      st->flags |= ISB_FLAG_NONFINITE;
+      status = fail(ISB_E_NONFINITE, "non-finite gradient");
+    }
+  }
+  st->res_final = res;
+  if (res <= sc.tol_rel * res0) st->flags |= ISB_FLAG_CONVERGED;
+  *px = x;
+  *pxt = xt;
+  *pG = G;
+  *pGt = Gt;
+  return status;
+}
+
+static isb_status fill_stats_tail(isb_ctx* c, int b, hipStream_t s, const double* x, const double* x0,
+                                  const double* a, isb_stats* st) {
+  const BodyRange br = body_range(c, b);
+  const DevMesh m = devmesh(c);
+  enqueue_energy(c, b, x, nullptr, 0.0, x0, a, c->dscal, s);
+  int nb = 0;
+  launch_elem_minmax_J(m, ERange{br.e0, br.e1, nullptr}, x, c->partials + 6 * kMaxRedBlocks, s, &nb);
+  launch_finalize_minmax(c->partials + 6 * kMaxRedBlocks, nb, c->dscal + 3, s);
+  ISB_TRY(read_scal(c, s, 5));
+  st->energy = c->hscal[2];
+  st->min_J = c->hscal[3];
+  st->max_J = c->hscal[4];
+  return ISB_OK;
+}
+
+// check a > 0 and finite (one reduction, host read)
+static isb_status check_actuation(isb_ctx* c, hipStream_t s, const double* a) {
+  launch_min_count(c->n_e, a, c->partials, c->dscal, s);
+  ISB_TRY(read_scal(c, s, 2));
+  if (c->hscal[1] != 0.0) return fail(ISB_E_NONFINITE, "non-finite actuation");
+  if (!(c->hscal[0] > 0.0)) return fail(ISB_E_ARG, "actuation a must be > 0");
+  return ISB_OK;
+}
+
+static isb_status plain_step(isb_ctx* c, hipStream_t s, const double* x0, const double* v0, const double* a,
+                             double* x1, double* v1, isb_stats* per_body) {
+  const DevMesh m = devmesh(c);
+  const DevScene dsc = devscene(c);
+  if (c->precision == ISB_MIXED) launch_to_f32(c->n_e, a, c->w_a32, s);
+  isb_status worst = ISB_OK;
+  for (int b = 0; b < c->n_bodies; ++b) {
+    const BodyRange br = body_range(c, b);
+    isb_stats st;
+    std::memset(&st, 0, sizeof(st));
+    double *x = c->w_x, *xt = c->w_xt, *G = c->w_G, *Gt = c->w_Gt;
+    launch_setup(m, dsc, br.v0, br.v1, x0, dsc.be ? v0 : nullptr, x, c->w_xhat, c->w_cv, s);
+    isb_status r = plain_newton(c, b, s, x0, a, &x, &xt, &G, &Gt, &st);
+    if (r == ISB_E_HIP) return r;
+    launch_copy(br.n, x + br.off, x1 + br.off, s);
+    if (dsc.be && v1) launch_velocity(br.n, x1 + br.off, x0 + br.off, 1.0 / dsc.h, v1 + br.off, s);
+    if (per_body) {
+      ISB_TRY(fill_stats_tail(c, b, s, x, x0, a, &st));
+      per_body[b] = st;
+    }
+    if (r != ISB_OK && worst == ISB_OK) worst = r;
+  }
+  if (worst != ISB_OK) return worst;
+  ISB_HIP(hipGetLastError());
+  return ISB_OK;
+}
+
+static isb_status plain_adjoint(isb_ctx* c, hipStream_t s, const double* x1, const double* x0, const double* a,
+                                const double* x1_bar, const double* v1_bar, double* w, isb_stats* per_body) {
+  const DevMesh m = devmesh(c);
+  const DevScene dsc = devscene(c);
+  if (c->precision == ISB_MIXED) launch_to_f32(c->n_e, a, c->w_a32, s);
+  isb_status worst = ISB_OK;
+  for (int b = 0; b < c->n_bodies; ++b) {
+    const BodyRange br = body_range(c, b);
+    launch_setup(m, dsc, br.v0, br.v1, x0, nullptr, c->w_x, c->w_xhat, c->w_cv, s);
+    launch_adjoint_rhs(m, dsc, br.v0, br.v1, x1_bar, dsc.be ? v1_bar : nullptr, c->w_G, s);
+    enqueue_norm2(c, b, c->w_G, 0, s);
+    ISB_TRY(read_scal(c, s, 1));
+    const double bnorm = std::sqrt(c->hscal[0]);
+    int iters = 0;
+    bool neg = false;
+    double rr = 0.0;
+    if (!std::isfinite(bnorm)) return fail(ISB_E_NONFINITE, "non-finite adjoint right-hand side");
+    if (bnorm == 0.0) {
+      launch_fill(br.n, 0.0, w + br.off, s);
+    } else {
+      eval_precond(c, b, x1, a, s);
+      ISB_TRY(run_cg(c, b, x1, a, c->w_G, 1.0, c->scene.adj_tol_rel * bnorm, c->scene.max_cg, s, &iters, &neg, &rr));
+      launch_copy(br.n, c->w_xs + br.off, w + br.off, s);
+    }
+    const double rel = bnorm > 0.0 ? std::sqrt(rr) / bnorm : 0.0;
+    const bool ok = rel <= c->scene.adj_tol_rel && !neg;
+    if (per_body) {
+      per_body[b].adj_cg_iters = iters;
+      per_body[b].adj_res_final = rel;
+      if (ok)
+        per_body[b].flags |= ISB_FLAG_ADJ_CONVERGED;
+      else
+        per_body[b].flags &= ~ISB_FLAG_ADJ_CONVERGED;
+    }
+    if (neg && worst == ISB_OK) worst = fail(ISB_E_NOT_CONVERGED, "adjoint CG met non-positive curvature");
+    if (!ok && !neg && worst == ISB_OK) worst = fail(ISB_E_NOT_CONVERGED, "adjoint CG iteration cap reached");
+  }
+  ISB_HIP(hipGetLastError());
+  return worst;
+}
+
+// ---------------------------------------------------------------------------------------------
+// workspace allocation
+// ---------------------------------------------------------------------------------------------
+static isb_status alloc_workspaces(isb_ctx* c) {
+  c->free_list(c->work_allocs);
+  const size_t nd = (size_t)c->n_v * c->dim;
+  auto& L = c->work_allocs;
+  for (double** p : {&c->w_x, &c->w_xt, &c->w_xhat, &c->w_G, &c->w_Gt, &c->w_xs, &c->w_r, &c->w_p, &c->w_Hp,
+                     &c->w_Dinvp, &c->w_vdiag, &c->w_diag})
+    ISB_TRY(dalloc(L, p, nd));
+  ISB_TRY(dalloc(L, &c->w_cv, (size_t)c->n_v));
+  ISB_TRY(dalloc(L, &c->w_a32, (size_t)c->n_e));
+  ISB_TRY(dalloc(L, &c->partials, (size_t)8 * kMaxRedBlocks));
+  ISB_TRY(dalloc(L, &c->dscal, (size_t)64));
+  ISB_TRY(dalloc(L, &c->ebuf, (size_t)3 * c->n_bodies));
+  ISB_TRY(dalloc(L, &c->scal, (size_t)1));
+  // zero the vectors once so that the Hessian-vector kernel never reads uninitialised memory
+  for (double* p : {c->w_x, c->w_xt, c->w_xhat, c->w_G, c->w_Gt, c->w_xs, c->w_r, c->w_p, c->w_Hp, c->w_Dinvp,
+                    c->w_vdiag, c->w_diag})
+    ISB_HIP(hipMemset(p, 0, nd * sizeof(double)));
+  ISB_HIP(hipMemset(c->scal, 0, sizeof(CgScal)));
+  return ISB_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------------------------
+extern "C" {
+
+isb_status isb_create(int device, int precision, isb_ctx** out) {
+  clear_error();
+  if (!out) return fail(ISB_E_ARG, "NULL out pointer");
+  *out = nullptr;
+  if (precision != ISB_FP64 && precision != ISB_MIXED) return fail(ISB_E_ARG, "unknown precision");
+  int n = 0;
+  ISB_HIP(hipGetDeviceCount(&n));
+  if (device < 0 || device >= n) return fail(ISB_E_ARG, "device index out of range");
+  ISB_HIP(hipSetDevice(device));
+  isb_ctx* c = new isb_ctx();
+  c->device = device;
+  c->precision = precision;
+  if (hipHostMalloc((void**)&c->hscal, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&c->hcg, sizeof(CgScal), hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    return fail(ISB_E_HIP, "pinned host allocation failed");
+  }
+  *out = c;
+  return ISB_OK;
+}
+
+isb_status isb_destroy(isb_ctx* ctx) {
+  clear_error();
+  if (!ctx) return ISB_OK;
+  delete ctx;
+  return ISB_OK;
+}
+
+isb_status isb_mesh_upload(isb_ctx* c, int dim, int32_t n_bodies, const int64_t* body_v_off,
+                           const int64_t* body_e_off, const double* X_rest, const int32_t* T,
+                           const uint8_t* dof_pinned) {
+  clear_error();
+  if (!c) return fail(ISB_E_ARG, "NULL context");
+  if (!body_v_off || !body_e_off || !X_rest || !T || !dof_pinned || n_bodies <= 0)
+    return fail(ISB_E_ARG, "NULL mesh argument");
+  const int64_t n_v = body_v_off[n_bodies], n_e = body_e_off[n_bodies];
+  ISB_TRY(validate_mesh(dim, n_v, X_rest, n_e, T, n_bodies, body_v_off, body_e_off));
+  ISB_HIP(hipSetDevice(c->device));
+  batched_release(c);
+  c->free_list(c->work_allocs);
+  c->free_list(c->mesh_allocs);
+  c->have_mesh = c->have_material = false;
+  c->dim = dim;
+  c->n_bodies = n_bodies;
+  c->n_v = (int)n_v;
+  c->n_e = (int)n_e;
+  c->voff.assign(body_v_off, body_v_off + n_bodies + 1);
+  c->eoff.assign(body_e_off, body_e_off + n_bodies + 1);
+
+  // colouring, then per-(body, colour) element lists
+  std::vector<int32_t> colour((size_t)n_e);
+  int32_t nc = 0;
+  ISB_TRY(colour_elements(dim, n_v, n_e, T, colour.data(), &nc));
+  c->n_colours = nc;
+  const int nc1 = nc + 1;
+  c->col_off.assign((size_t)n_bodies * nc1, 0);
+  std::vector<int32_t> clist((size_t)n_e);
+  {
+    int32_t pos = 0;
+    for (int b = 0; b < n_bodies; ++b) {
+      std::vector<int32_t> count(nc, 0);
+      for (int64_t e = body_e_off[b]; e < body_e_off[b + 1]; ++e) count[colour[e]]++;
+      std::vector<int32_t> start(nc, 0);
+      for (int k = 0; k < nc; ++k) {
+        c->col_off[b * nc1 + k] = pos;
+        start[k] = pos;
+        pos += count[k];
+      }
+      c->col_off[b * nc1 + nc] = pos;
+      for (int64_t e = body_e_off[b]; e < body_e_off[b + 1]; ++e) clist[start[colour[e]]++] = (int32_t)e;
+    }
+  }
+
+  // SoA connectivity
+  std::vector<int32_t> connh((size_t)(dim + 1) * n_e);
+  for (int64_t e = 0; e < n_e; ++e)
+    for (int k = 0; k <= dim; ++k) connh[(size_t)k * n_e + e] = T[e * (dim + 1) + k];
+
+  auto& L = c->mesh_allocs;
+  const size_t ne = (size_t)n_e, nd = (size_t)n_v * dim;
+  ISB_TRY(dalloc(L, &c->conn, (size_t)(dim + 1) * ne));
+  ISB_TRY(dalloc(L, &c->X, nd));
+  ISB_TRY(dalloc(L, &c->Dinv, (size_t)dim * dim * ne));
+  ISB_TRY(dalloc(L, &c->W, ne));
+  ISB_TRY(dalloc(L, &c->gf, (size_t)dim * ne));
+  ISB_TRY(dalloc(L, &c->wmu, ne));
+  ISB_TRY(dalloc(L, &c->wlam, ne));
+  ISB_TRY(dalloc(L, &c->wkf, ne));
+  ISB_TRY(dalloc(L, &c->rho, ne));
+  ISB_TRY(dalloc(L, &c->mass, (size_t)n_v));
+  ISB_TRY(dalloc(L, &c->pinned, nd));
+  ISB_TRY(dalloc(L, &c->clist, ne));
+  if (c->precision == ISB_MIXED) {
+    ISB_TRY(dalloc(L, &c->Dinv32, (size_t)dim * dim * ne));
+    ISB_TRY(dalloc(L, &c->gf32, (size_t)dim * ne));
+    ISB_TRY(dalloc(L, &c->wmu32, ne));
+    ISB_TRY(dalloc(L, &c->wlam32, ne));
+    ISB_TRY(dalloc(L, &c->wkf32, ne));
+  }
+  ISB_HIP(hipMemcpy(c->conn, connh.data(), connh.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  ISB_HIP(hipMemcpy(c->X, X_rest, nd * sizeof(double), hipMemcpyHostToDevice));
+  ISB_HIP(hipMemcpy(c->pinned, dof_pinned, nd, hipMemcpyHostToDevice));
+  ISB_HIP(hipMemcpy(c->clist, clist.data(), ne * sizeof(int32_t), hipMemcpyHostToDevice));
+  launch_precompute_geom(dim, (int)n_e, c->X, c->conn, c->Dinv, c->W, nullptr);
+  ISB_HIP(hipGetLastError());
+  ISB_HIP(hipDeviceSynchronize());
+  ISB_TRY(alloc_workspaces(c));
+  c->have_mesh = true;
+  return ISB_OK;
+}
+
+isb_status isb_material_upload(isb_ctx* c, const double* mu, const double* lam, const double* k_fibre,
+                               const double* fibre_dir, const double* density, const isb_scene* scene) {
+  clear_error();
+  ISB_TRY(check_ctx(c, false));
+  if (!mu || !lam || !k_fibre || !fibre_dir || !density) return fail(ISB_E_ARG, "NULL material array");
+  ISB_TRY(check_scene(scene));
+  const size_t ne = (size_t)c->n_e;
+  for (size_t e = 0; e < ne; ++e) {
+    if (!std::isfinite(mu[e]) || !std::isfinite(lam[e]) || !std::isfinite(k_fibre[e]) || !(density[e] > 0.0) ||
+        !std::isfinite(density[e]))
+      return fail(ISB_E_ARG, "material entry " + std::to_string(e) + " invalid (density must be > 0)");
+    double n2 = 0.0;
+    for (int c2 = 0; c2 < c->dim; ++c2) n2 += fibre_dir[e * c->dim + c2] * fibre_dir[e * c->dim + c2];
+    if (!(std::fabs(n2 - 1.0) < 1e-6)) return fail(ISB_E_ARG, "fibre_dir must be unit vectors");
+  }
+  std::vector<void*> tmp;
+  double *dmu, *dlam, *dkf, *dfd;
+  ISB_TRY(dalloc(tmp, &dmu, ne));
+  ISB_TRY(dalloc(tmp, &dlam, ne));
+  ISB_TRY(dalloc(tmp, &dkf, ne));
+  ISB_TRY(dalloc(tmp, &dfd, ne * c->dim));
+  isb_status st = ISB_OK;
+  auto copy_all = [&]() -> isb_status {
+    ISB_HIP(hipMemcpy(dmu, mu, ne * 8, hipMemcpyHostToDevice));
+    ISB_HIP(hipMemcpy(dlam, lam, ne * 8, hipMemcpyHostToDevice));
+    ISB_HIP(hipMemcpy(dkf, k_fibre, ne * 8, hipMemcpyHostToDevice));
+    ISB_HIP(hipMemcpy(dfd, fibre_dir, ne * c->dim * 8, hipMemcpyHostToDevice));
+    ISB_HIP(hipMemcpy(c->rho, density, ne * 8, hipMemcpyHostToDevice));
+    launch_precompute_material(c->dim, c->n_e, c->Dinv, c->W, dfd, dmu, dlam, dkf, c->gf, c->wmu, c->wlam, c->wkf,
+                               c->Dinv32, c->gf32, c->wmu32, c->wlam32, c->wkf32, nullptr);
+    // lumped mass, one colour at a time so that the sum order is fixed
+    ISB_HIP(hipMemset(c->mass, 0, (size_t)c->n_v * 8));
+    const int nc1 = c->n_colours + 1;
+    for (int b = 0; b < c->n_bodies; ++b)
+      for (int k = 0; k < c->n_colours; ++k) {
+        ERange r{c->col_off[b * nc1 + k], c->col_off[b * nc1 + k + 1], c->clist};
+        launch_mass_colour(c->dim, r, c->conn, c->n_e, c->W, c->rho, c->mass, nullptr);
+      }
+    ISB_HIP(hipGetLastError());
+    ISB_HIP(hipDeviceSynchronize());
+    return ISB_OK;
+  };
+  st = copy_all();
+  c->free_list(tmp);
+  if (st != ISB_OK) return st;
+  c->scene = *scene;
+  c->have_material = true;
+  batched_release(c);
+  return ISB_OK;
+}
+
+isb_status isb_set_scene(isb_ctx* c, const isb_scene* scene) {
+  clear_error();
+  if (!c) return fail(ISB_E_ARG, "NULL context");
+  ISB_TRY(check_scene(scene));
+  c->scene = *scene;
+  return ISB_OK;
+}
+
+isb_status isb_set_option(isb_ctx* c, int key, int64_t value) {
+  clear_error();
+  if (!c) return fail(ISB_E_ARG, "NULL context");
+  switch (key) {
+    case ISB_OPT_SOLVER:
+      if (value != 0 && value != 1) return fail(ISB_E_ARG, "solver must be 0 or 1");
+      c->solver = (int)value;
+      return ISB_OK;
+    case ISB_OPT_SCATTER:
+      if (value != 0 && value != 1) return fail(ISB_E_ARG, "scatter must be 0 or 1");
+      c->scatter = (int)value;
+      return ISB_OK;
+    case ISB_OPT_GRAPH_SAFE:
+      c->graph_safe = value != 0;
+      return ISB_OK;
+    case ISB_OPT_BLOCK:
+      if (value != 256 && value != 512 && value != 1024) return fail(ISB_E_ARG, "block must be 256, 512 or 1024");
+      c->block = (int)value;
+      return ISB_OK;
+    case ISB_OPT_CG_CHECK:
+      if (value < 1 || value > 1000) return fail(ISB_E_ARG, "cg_check must be in [1, 1000]");
+      c->cg_check = (int)value;
+      return ISB_OK;
+    default:
+      return fail(ISB_E_ARG, "unknown or read-only option key " + std::to_string(key));
+  }
+}
+
+isb_status isb_get_option(isb_ctx* c, int key, int64_t* value) {
+  clear_error();
+  if (!c || !value) return fail(ISB_E_ARG, "NULL argument");
+  switch (key) {
+    case ISB_OPT_SOLVER: *value = c->solver; return ISB_OK;
+    case ISB_OPT_SCATTER: *value = c->scatter; return ISB_OK;
+    case ISB_OPT_GRAPH_SAFE: *value = c->graph_safe; return ISB_OK;
+    case ISB_OPT_BLOCK: *value = c->block; return ISB_OK;
+    case ISB_OPT_CG_CHECK: *value = c->cg_check; return ISB_OK;
+    case ISB_OPT_PRECISION: *value = c->precision; return ISB_OK;
+    case ISB_INFO_N_VERTICES: *value = c->n_v; return ISB_OK;
+    case ISB_INFO_N_ELEMENTS: *value = c->n_e; return ISB_OK;
+    case ISB_INFO_N_BODIES: *value = c->n_bodies; return ISB_OK;
+    case ISB_INFO_DIM: *value = c->dim; return ISB_OK;
+    case ISB_INFO_N_COLOURS: *value = c->n_colours; return ISB_OK;
+    case ISB_INFO_LDS_BYTES: *value = c->have_mesh ? batched_lds_bytes(c) : 0; return ISB_OK;
+    default: return fail(ISB_E_ARG, "unknown option key " + std::to_string(key));
+  }
+}
+
+isb_status isb_get_mass(isb_ctx* c, isb_stream stream, double* mass_out) {
+  clear_error();
+  ISB_TRY(check_ctx(c, true));
+  if (!mass_out) return fail(ISB_E_ARG, "NULL output");
+  ISB_HIP(hipMemcpyAsync(mass_out, c->mass, (size_t)c->n_v * 8, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return ISB_OK;
+}
+
+isb_status isb_step(isb_ctx* c, isb_stream stream, const double* x0, const double* v0, const double* a, double* x1,
+                    double* v1, isb_stats* per_body) {
+  clear_error();
+  ISB_TRY(check_ctx(c, true));
+  const bool be = c->scene.integrator == ISB_BACKWARD_EULER;
+  if (!x0 || !a || !x1 || (be && !v0)) return fail(ISB_E_ARG, "NULL state argument");
+  hipStream_t s = (hipStream_t)stream;
+  if (per_body) std::memset(per_body, 0, sizeof(isb_stats) * c->n_bodies);
+  if (c->solver == 1) return batched_step(c, s, x0, be ? v0 : nullptr, a, x1, be ? v1 : nullptr, per_body);
+  ISB_TRY(check_actuation(c, s, a));
+  return plain_step(c, s, x0, v0, a, x1, v1, per_body);
+}
+
+isb_status isb_solve_adjoint(isb_ctx* c, isb_stream stream, const double* x1, const double* x0, const double* a,
+                             const double* x1_bar, const double* v1_bar, double* w, isb_stats* per_body) {
+  clear_error();
+  ISB_TRY(check_ctx(c, true));
+  if (!x1 || !x0 || !a || !x1_bar || !w) return fail(ISB_E_ARG, "NULL adjoint argument");
+  hipStream_t s = (hipStream_t)stream;
+  if (c->solver == 1) return batched_adjoint(c, s, x1, x0, a, x1_bar, v1_bar, w, per_body);
+  ISB_TRY(check_actuation(c, s, a));
+  return plain_adjoint(c, s, x1, x0, a, x1_bar, v1_bar, w, per_body);
+}
+
+isb_status isb_vjp_params(isb_ctx* c, isb_stream stream, const double* w, const double* x1, const double* x0,
+                          const double* a, const double* v1_bar, double* a_bar, double* x0_bar, double* v0_bar,
+                          double* mu_bar, double* lam_bar, double* kf_bar) {
+  clear_error();
+  ISB_TRY(check_ctx(c, true));
+  if (!w || !x1 || !x0 || !a) return fail(ISB_E_ARG, "NULL vjp argument");
+  hipStream_t s = (hipStream_t)stream;
+  const DevMesh m = devmesh(c);
+  const DevScene dsc = devscene(c);
+  if (a_bar || mu_bar || lam_bar || kf_bar)
+    launch_elem_vjp(m, dsc, ERange{0, c->n_e, nullptr}, w, x1, a, a_bar, mu_bar, lam_bar, kf_bar, s);
+  launch_vertex_vjp(m, dsc, 0, c->n_v, w, x1, x0, dsc.be ? v1_bar : nullptr, x0_bar, v0_bar, s);
+  ISB_HIP(hipGetLastError());
+  return ISB_OK;
+}
+
+isb_status isb_energy(isb_ctx* c, isb_stream stream, const double* x, const double* x0, const double* v0,
+                      const double* a, double* energy) {
+  clear_error();
+  ISB_TRY(check_ctx(c, true));
+  const DevScene dsc = devscene(c);
+  if (!x || !x0 || !a || !energy || (dsc.be && !v0)) return fail(ISB_E_ARG, "NULL argument");
+  hipStream_t s = (hipStream_t)stream;
+  const DevMesh m = devmesh(c);
+  launch_setup(m, dsc, 0, c->n_v, x0, dsc.be ? v0 : nullptr, c->w_xt, c->w_xhat, c->w_cv, s);
+  for (int b = 0; b < c->n_bodies; ++b) enqueue_energy(c, b, x, nullptr, 0.0, x0, a, c->ebuf + 3 * b, s);
+  ISB_HIP(hipMemcpy2DAsync(energy, sizeof(double), c->ebuf + 2, 3 * sizeof(double), sizeof(double), c->n_bodies,
+                           hipMemcpyDeviceToDevice, s));
+  ISB_HIP(hipGetLastError());
+  return ISB_OK;
+}
+
+isb_status isb_gradient(isb_ctx* c, isb_stream stream, const double* x, const double* x0, const double* v0,
+                        const double* a, double* g) {
+  clear_error();
+  ISB_TRY(check_ctx(c, true));
+  const DevScene dsc = devscene(c);
+  if (!x || !x0 || !a || !g || (dsc.be && !v0)) return fail(ISB_E_ARG, "NULL argument");
+  hipStream_t s = (hipStream_t)stream;
+  launch_setup(devmesh(c), dsc, 0, c->n_v, x0, dsc.be ? v0 : nullptr, c->w_xt, c->w_xhat, c->w_cv, s);
+  eval_grad(c, -1, x, x0, a, g, s);
+  ISB_HIP(hipGetLastError());
+  return ISB_OK;
+}
+
+isb_status isb_hessvec(isb_ctx* c, isb_stream stream, const double* x, const double* x0, const double* a,
+                       const double* p, double* hp) {
+  clear_error();
+  ISB_TRY(check_ctx(c, true));
+  if (!x || !x0 || !a || !p || !hp) return fail(ISB_E_ARG, "NULL argument");
+  hipStream_t s = (hipStream_t)stream;
+  const DevMesh m = devmesh(c);
+  const DevScene dsc = devscene(c);
+  const int n = c->n_v * c->dim;
+  if (c->precision == ISB_MIXED) launch_to_f32(c->n_e, a, c->w_a32, s);
+  launch_setup(m, dsc, 0, c->n_v, x0, nullptr, c->w_xt, c->w_xhat, c->w_cv, s);
+  launch_vertex_hdiag(m, dsc, 0, c->n_v, x, c->w_cv, c->w_vdiag, s);
+  launch_copy(n, p, c->w_p, s);
+  launch_mask(m, 0, c->n_v, c->w_p, s);
+  launch_mul(n, c->w_vdiag, c->w_p, hp, s);
+  elem_ranges(c, -1, [&](ERange r, bool atomic) {
+    launch_elem_hv(m, dsc, r, atomic, c->precision, x, a, c->w_a32, c->w_p, hp, nullptr, s);
+  });
+  launch_mask(m, 0, c->n_v, hp, s);
+  ISB_HIP(hipGetLastError());
+  return ISB_OK;
+}
+
+isb_status isb_hessdiag(isb_ctx* c, isb_stream stream, const double* x, const double* x0, const double* a,
+                        double* diag) {
+  clear_error();
+  ISB_TRY(check_ctx(c, true));
+  if (!x || !x0 || !a || !diag) return fail(ISB_E_ARG, "NULL argument");
+  hipStream_t s = (hipStream_t)stream;
+  const DevMesh m = devmesh(c);
+  const DevScene dsc = devscene(c);
+  if (c->precision == ISB_MIXED) launch_to_f32(c->n_e, a, c->w_a32, s);
+  launch_setup(m, dsc, 0, c->n_v, x0, nullptr, c->w_xt, c->w_xhat, c->w_cv, s);
+  launch_vertex_hdiag(m, dsc, 0, c->n_v, x, c->w_cv, diag, s);
+  elem_ranges(c, -1, [&](ERange r, bool atomic) {
+    launch_elem_diag(m, dsc, r, atomic, c->precision, x, a, c->w_a32, diag, s);
+  });
+  launch_set_pinned(m, 0, c->n_v, 1.0, diag, s);
+  ISB_HIP(hipGetLastError());
+  return ISB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,78 @@
+// The library context: uploaded mesh and material, options, and every device workspace.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/isb.h"
+#include "isb_host.hpp"
+#include "isb_internal.hpp"
+
+#define ISB_HIP(expr)                                                                                  \
+  do {                                                                                                 \
+    hipError_t e_ = (expr);                                                                            \
+    if (e_ != hipSuccess) return ::isb::fail(ISB_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+struct isb_ctx {
+  int device = 0;
+  int precision = ISB_FP64;
+
+  // mesh
+  int dim = 0, n_bodies = 0, n_v = 0, n_e = 0;
+  std::vector<int64_t> voff, eoff;
+  bool have_mesh = false, have_material = false;
+  std::vector<void*> mesh_allocs, work_allocs;  // freed on re-upload / destroy
+  int32_t* conn = nullptr;
+  double *X = nullptr, *Dinv = nullptr, *W = nullptr, *gf = nullptr, *wmu = nullptr, *wlam = nullptr,
+         *wkf = nullptr, *mass = nullptr, *rho = nullptr;
+  float *Dinv32 = nullptr, *gf32 = nullptr, *wmu32 = nullptr, *wlam32 = nullptr, *wkf32 = nullptr;
+  uint8_t* pinned = nullptr;
+
+  // element colouring: elements of body b and colour k are clist[col_off[b*(nc+1)+k] .. +1)
+  int n_colours = 0;
+  std::vector<int32_t> col_off;
+  int32_t* clist = nullptr;
+
+  isb_scene scene{};
+
+  // options
+  int solver = 0, scatter = 0, graph_safe = 0, block = 1024, cg_check = 4;
+
+  // plain-solver workspaces, [n_v*dim] unless noted
+  double *w_x = nullptr, *w_xt = nullptr, *w_xhat = nullptr, *w_cv = nullptr /*[n_v]*/, *w_G = nullptr,
+         *w_Gt = nullptr, *w_xs = nullptr, *w_r = nullptr, *w_p = nullptr, *w_Hp = nullptr, *w_Dinvp = nullptr,
+         *w_vdiag = nullptr, *w_diag = nullptr;
+  float* w_a32 = nullptr;           // [n_e]
+  double* partials = nullptr;       // reduction partials
+  double* dscal = nullptr;          // small device results (finalize outputs)
+  double* ebuf = nullptr;           // [3*n_bodies] per-body energy comps
+  isb::CgScal* scal = nullptr;      // device CG scalars
+  double* hscal = nullptr;          // pinned host mirror of dscal
+  isb::CgScal* hcg = nullptr;       // pinned host mirror of scal
+
+  // batched-solver state (owned by the batched solver)
+  void* batched = nullptr;
+
+  ~isb_ctx();
+  void free_list(std::vector<void*>& v);
+};
+
+namespace isb {
+
+DevMesh devmesh(const isb_ctx* c);
+DevScene devscene(const isb_ctx* c);
+
+// batched persistent solver (isb_batched.hip)
+isb_status batched_prepare(isb_ctx* c);
+void batched_release(isb_ctx* c);
+isb_status batched_step(isb_ctx* c, hipStream_t s, const double* x0, const double* v0, const double* a, double* x1,
+                        double* v1, isb_stats* stats);
+isb_status batched_adjoint(isb_ctx* c, hipStream_t s, const double* x1, const double* x0, const double* a,
+                           const double* x1_bar, const double* v1_bar, double* w, isb_stats* stats);
+int64_t batched_lds_bytes(const isb_ctx* c);
+
+}  // namespace isb

@@ -1,0 +1,114 @@
+// Host-only parts of libisb: mesh validation, element colouring, error reporting.
+// Nothing here touches the GPU, so these entry points work on a machine without one.
+#include <stdint.h>
+
+#include <cmath>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/isb.h"
+#include "isb_host.hpp"
+
+namespace isb {
+
+static thread_local std::string g_last_error;
+
+isb_status fail(isb_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+void clear_error() { g_last_error.clear(); }
+
+const char* last_error() { return g_last_error.c_str(); }
+
+// det of the edge matrix [x_1 - x_0, ..., x_d - x_0]
+static double edge_det(int dim, const double* X, const int32_t* t) {
+  double e[3][3];
+  for (int j = 0; j < dim; ++j)
+    for (int c = 0; c < dim; ++c) e[c][j] = X[(int64_t)t[j + 1] * dim + c] - X[(int64_t)t[0] * dim + c];
+  if (dim == 2) return e[0][0] * e[1][1] - e[0][1] * e[1][0];
+  return e[0][0] * (e[1][1] * e[2][2] - e[1][2] * e[2][1]) - e[0][1] * (e[1][0] * e[2][2] - e[1][2] * e[2][0]) +
+         e[0][2] * (e[1][0] * e[2][1] - e[1][1] * e[2][0]);
+}
+
+isb_status validate_mesh(int dim, int64_t n_v, const double* X, int64_t n_e, const int32_t* T, int32_t n_bodies,
+                         const int64_t* voff, const int64_t* eoff) {
+  if (dim != 2 && dim != 3) return fail(ISB_E_ARG, "dim must be 2 or 3");
+  if (n_v <= 0 || n_e <= 0 || n_bodies <= 0) return fail(ISB_E_ARG, "empty mesh");
+  if (!X || !T || !voff || !eoff) return fail(ISB_E_ARG, "NULL mesh array");
+  if (n_v > INT32_MAX / 4 || n_e > INT32_MAX / 16) return fail(ISB_E_ARG, "mesh too large for 32-bit indexing");
+  if (voff[0] != 0 || eoff[0] != 0 || voff[n_bodies] != n_v || eoff[n_bodies] != n_e)
+    return fail(ISB_E_MESH, "body offsets must start at 0 and end at n_v / n_e");
+  for (int32_t b = 0; b < n_bodies; ++b) {
+    if (voff[b + 1] <= voff[b] || eoff[b + 1] <= eoff[b])
+      return fail(ISB_E_MESH, "body " + std::to_string(b) + " has no vertices or no elements");
+  }
+  for (int64_t i = 0; i < n_v * dim; ++i)
+    if (!std::isfinite(X[i])) return fail(ISB_E_MESH, "non-finite rest position");
+  for (int32_t b = 0; b < n_bodies; ++b) {
+    for (int64_t e = eoff[b]; e < eoff[b + 1]; ++e) {
+      const int32_t* t = T + e * (dim + 1);
+      for (int k = 0; k <= dim; ++k) {
+        if (t[k] < voff[b] || t[k] >= voff[b + 1])
+          return fail(ISB_E_MESH, "element " + std::to_string(e) + " references vertex " + std::to_string(t[k]) +
+                                      " outside body " + std::to_string(b));
+        for (int j = 0; j < k; ++j)
+          if (t[j] == t[k]) return fail(ISB_E_MESH, "element " + std::to_string(e) + " repeats a vertex");
+      }
+      const double det = edge_det(dim, X, t);
+      if (!(det > 0.0))
+        return fail(ISB_E_MESH, "element " + std::to_string(e) + " has non-positive rest volume (det " +
+                                    std::to_string(det) + ")");
+    }
+  }
+  return ISB_OK;
+}
+
+isb_status colour_elements(int dim, int64_t n_v, int64_t n_e, const int32_t* T, int32_t* colour,
+                           int32_t* n_colours) {
+  // greedy first-fit in element order; a 64-bit mask per vertex holds the colours of its elements
+  std::vector<uint64_t> used((size_t)n_v, 0);
+  int32_t nc = 0;
+  for (int64_t e = 0; e < n_e; ++e) {
+    const int32_t* t = T + e * (dim + 1);
+    uint64_t m = 0;
+    for (int k = 0; k <= dim; ++k) {
+      if (t[k] < 0 || t[k] >= n_v) return fail(ISB_E_MESH, "vertex index out of range in colouring");
+      m |= used[t[k]];
+    }
+    if (m == ~0ull) return fail(ISB_E_MESH, "element colouring needs more than 64 colours");
+    int c = 0;
+    while (m & (1ull << c)) ++c;
+    colour[e] = c;
+    for (int k = 0; k <= dim; ++k) used[t[k]] |= (1ull << c);
+    if (c + 1 > nc) nc = c + 1;
+  }
+  *n_colours = nc;
+  return ISB_OK;
+}
+
+}  // namespace isb
+
+extern "C" {
+
+const char* isb_last_error(void) { return isb::last_error(); }
+
+const char* isb_version(void) { return "isb 0.1 (gfx950)"; }
+
+isb_status isb_validate_mesh(int dim, int64_t n_v, const double* X, int64_t n_e, const int32_t* T,
+                             int32_t n_bodies, const int64_t* body_v_off, const int64_t* body_e_off) {
+  isb::clear_error();
+  return isb::validate_mesh(dim, n_v, X, n_e, T, n_bodies, body_v_off, body_e_off);
+}
+
+isb_status isb_colour_elements(int dim, int64_t n_v, int64_t n_e, const int32_t* T, int32_t* colour_out,
+                               int32_t* n_colours_out) {
+  isb::clear_error();
+  if ((dim != 2 && dim != 3) || n_v <= 0 || n_e <= 0 || !T || !colour_out || !n_colours_out)
+    return isb::fail(ISB_E_ARG, "isb_colour_elements: bad argument");
+  return isb::colour_elements(dim, n_v, n_e, T, colour_out, n_colours_out);
+}
+
+}  // extern "C"

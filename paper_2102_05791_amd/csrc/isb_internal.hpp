@@ -1,0 +1,128 @@
+// Internal device data layout and kernel launchers of libisb (not part of the C ABI).
+//
+// HBM layout (all SoA, indexed by element or vertex id in the caller's order):
+//   conn  [D+1][n_e] int32      vertex ids of each simplex (global ids)
+//   Dinv  [D*D][n_e] f64        Dm^-1, entry (j, c) at plane j*D + c
+//   gf    [D][n_e]   f64        Dm^-1 d (fibre direction pulled back, so F d = Ds gf)
+//   W, wmu, wlam, wkf [n_e] f64 rest volume and W mu, W lam, W k_f
+//   *32 copies of Dinv, gf, wmu, wlam, wkf in f32 (mixed precision only)
+//   mass  [n_v] f64, pinned [n_v*D] u8
+// Vertex vectors (positions, gradients, CG vectors) are [n_v][D] f64, the boundary layout:
+// one vertex is one contiguous 16 B (2D) / 24 B (3D) record, which is what a simplex gathers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace isb {
+
+constexpr int kBlock = 256;        // threads per block of the grid-wide kernels
+constexpr int kMaxRedBlocks = 512; // cap on blocks of any kernel that writes reduction partials
+
+struct DevMesh {
+  int dim;
+  int n_v, n_e;
+  const int32_t* conn;
+  const double *Dinv, *gf, *W, *wmu, *wlam, *wkf;
+  const float *Dinv32, *gf32, *wmu32, *wlam32, *wkf32;
+  const double* mass;
+  const uint8_t* pinned;
+};
+
+struct DevScene {
+  int be;          // 1 = backward Euler, 0 = quasistatic
+  double h;        // time step
+  double s_pot;    // h^2 (backward Euler) or 1 (quasistatic): scale of the potential energy
+  double grav;     // gravity along -y
+  double kc;       // contact stiffness
+  double kfr;      // friction stiffness
+  double eps;      // friction contact tolerance
+};
+
+// Element index range: element k of [begin, end) is list[k] when list != nullptr, else k.
+struct ERange {
+  int begin, end;
+  const int32_t* list;
+};
+
+// Device-resident CG scalars of the plain solver (one solve at a time).
+struct CgScal {
+  double rz[2];    // r.z of the current iterate, double-buffered by iteration parity
+  double rr;       // r.r
+  double pHp;
+  double rr0;      // r.r at the start
+  int done;        // converged or stopped by curvature
+  int negcurv;     // non-positive curvature met
+  int iters;       // completed iterations
+  int pad;
+};
+
+// ---- precompute ----
+void launch_precompute_geom(int D, int n_e, const double* X, const int32_t* conn, double* Dinv, double* W,
+                            hipStream_t s);
+void launch_precompute_material(int D, int n_e, const double* Dinv, const double* W, const double* fdir,
+                                const double* mu, const double* lam, const double* kf, double* gf, double* wmu,
+                                double* wlam, double* wkf, float* Dinv32, float* gf32, float* wmu32, float* wlam32,
+                                float* wkf32, hipStream_t s);
+void launch_mass_colour(int D, ERange r, const int32_t* conn, int n_e, const double* W, const double* rho,
+                        double* mass, hipStream_t s);
+
+// ---- vertex kernels (range of vertices [v0, v1)) ----
+void launch_setup(const DevMesh& m, const DevScene& sc, int v0, int v1, const double* x0, const double* v0p,
+                  double* x, double* xhat, double* cv, hipStream_t s);
+void launch_vertex_grad(const DevMesh& m, const DevScene& sc, int v0, int v1, const double* x, const double* x0,
+                        const double* xhat, const double* cv, double* G, hipStream_t s);
+void launch_vertex_hdiag(const DevMesh& m, const DevScene& sc, int v0, int v1, const double* x, const double* cv,
+                         double* vdiag, hipStream_t s);
+void launch_mask(const DevMesh& m, int v0, int v1, double* vec, hipStream_t s);
+void launch_finish_diag(const DevMesh& m, int v0, int v1, const double* diag, double* Dinvp, hipStream_t s);
+void launch_vertex_energy(const DevMesh& m, const DevScene& sc, int v0, int v1, const double* x, const double* dx,
+                          double alpha, const double* x0, const double* xhat, const double* cv, double* partials,
+                          int part_off, hipStream_t s, int* nblocks_out);
+void launch_velocity(int n, const double* x1, const double* x0, double inv_h, double* v1, hipStream_t s);
+void launch_vertex_vjp(const DevMesh& m, const DevScene& sc, int v0, int v1, const double* w, const double* x1,
+                       const double* x0, const double* v1_bar, double* x0_bar, double* v0_bar, hipStream_t s);
+void launch_adjoint_rhs(const DevMesh& m, const DevScene& sc, int v0, int v1, const double* x1_bar,
+                        const double* v1_bar, double* b, hipStream_t s);
+
+// ---- element kernels ----
+// precision: 0 = f64 element math, 1 = f32 element math (Hessian-vector product and diagonal)
+void launch_elem_grad(const DevMesh& m, const DevScene& sc, ERange r, bool atomic, const double* x, const double* a,
+                      double* G, hipStream_t s);
+void launch_elem_hv(const DevMesh& m, const DevScene& sc, ERange r, bool atomic, int precision, const double* x,
+                    const double* a, const float* a32, const double* p, double* Hp, const int* done, hipStream_t s);
+void launch_elem_diag(const DevMesh& m, const DevScene& sc, ERange r, bool atomic, int precision, const double* x,
+                      const double* a, const float* a32, double* diag, hipStream_t s);
+void launch_elem_energy(const DevMesh& m, const DevScene& sc, ERange r, const double* x, const double* dx,
+                        double alpha, const double* a, double* partials, int part_off, hipStream_t s,
+                        int* nblocks_out);
+void launch_elem_vjp(const DevMesh& m, const DevScene& sc, ERange r, const double* w, const double* x1,
+                     const double* a, double* a_bar, double* mu_bar, double* lam_bar, double* kf_bar, hipStream_t s);
+void launch_elem_minmax_J(const DevMesh& m, ERange r, const double* x, double* partials, hipStream_t s,
+                          int* nblocks_out);
+void launch_to_f32(int n, const double* src, float* dst, hipStream_t s);
+
+// ---- reductions and CG vector kernels (vectors of length n, pointers already offset) ----
+// partial sums of ncomp products per block; finalize into out[0..ncomp)
+void launch_dot(int n, const double* a, const double* b, double* partials, hipStream_t s, int* nblocks_out);
+void launch_finalize(const double* partials, int nblocks, int ncomp, double* out, hipStream_t s);
+void launch_finalize_minmax(const double* partials, int nblocks, double* out, hipStream_t s);
+void launch_axpy(int n, double* x, double alpha, const double* dx, hipStream_t s);
+void launch_copy(int n, const double* src, double* dst, hipStream_t s);
+
+// CG on H xs = sign * b (b is masked to the free DOFs, where D^-1 != 0)
+void launch_cg_start(int n, const double* b, double sign, const double* Dinvp, const double* vdiag, double* r,
+                     double* p, double* xs, double* Hp, double* partials, CgScal* scal, double tol2, hipStream_t s);
+void launch_cg_dot(int n, const double* p, const double* Hp, double* partials, const CgScal* scal, hipStream_t s);
+void launch_cg_update(int n, int it, const double* p, const double* Hp, const double* Dinvp, double* r, double* xs,
+                      double* partials, CgScal* scal, hipStream_t s);
+void launch_cg_p(int n, int it, const double* r, const double* Dinvp, const double* vdiag, double* p, double* Hp,
+                 const double* partials, CgScal* scal, double tol2, hipStream_t s);
+int red_blocks(int n);
+void launch_fill(int n, double value, double* out, hipStream_t s);
+void launch_mul(int n, const double* a, const double* b, double* out, hipStream_t s);
+void launch_neg_precond(int n, const double* Dinvp, const double* g, double* out, hipStream_t s);
+void launch_set_pinned(const DevMesh& m, int v0, int v1, double value, double* vec, hipStream_t s);
+void launch_min_count(int n, const double* a, double* partials, double* out, hipStream_t s);
+
+}  // namespace isb

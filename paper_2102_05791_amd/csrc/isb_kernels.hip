@@ -1,0 +1,1044 @@
+// Grid-wide kernels of the plain (host-driven) solver and the one-off precompute.
+//
+// Element kernels run one simplex per thread over an element range and scatter their
+// per-vertex results either with FP64 global atomics or, when the range is one colour of a
+// graph colouring (no two elements share a vertex), with plain read-modify-writes, which is
+// race free and bitwise reproducible. Reductions write one partial per block (wavefront
+// shuffles, then LDS across the block's waves) and are finished by one block in a fixed
+// order, so every sum is deterministic.
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "isb_elem.hpp"
+#include "isb_internal.hpp"
+
+namespace isb {
+
+// ---------------------------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+
+// sum over the block (blockDim.x == kBlock); result valid in thread 0
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < kBlock / 64; ++w) r += sh[w];
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ double block_min(double v, double* sh) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_down(v, o, 64));
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double r = v;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < kBlock / 64; ++w) r = fmin(r, sh[w]);
+  __syncthreads();
+  return r;
+}
+
+int red_blocks(int n) {
+  int b = (n + kBlock - 1) / kBlock;
+  if (b < 1) b = 1;
+  return b > kMaxRedBlocks ? kMaxRedBlocks : b;
+}
+
+static int grid_for(int n) {
+  int b = (n + kBlock - 1) / kBlock;
+  if (b < 1) b = 1;
+  return b > 65535 ? 65535 : b;
+}
+
+__device__ __forceinline__ int elem_id(const ERange& r, int k) { return r.list ? r.list[k] : k; }
+
+template <int D>
+__device__ __forceinline__ void load_conn(const DevMesh& m, int e, int v[D + 1]) {
+#pragma unroll
+  for (int k = 0; k <= D; ++k) v[k] = m.conn[(size_t)k * m.n_e + e];
+}
+
+template <int D, typename T>
+__device__ __forceinline__ void load_rest(const DevMesh& m, int e, ElemRest<D, T>& R) {
+  const size_t ne = (size_t)m.n_e;
+  if constexpr (std::is_same<T, double>::value) {
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+#pragma unroll
+      for (int c = 0; c < D; ++c) R.Dinv[j][c] = m.Dinv[(size_t)(j * D + c) * ne + e];
+      R.gf[j] = m.gf[(size_t)j * ne + e];
+    }
+    R.wmu = m.wmu[e];
+    R.wlam = m.wlam[e];
+    R.wkf = m.wkf[e];
+  } else {
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+#pragma unroll
+      for (int c = 0; c < D; ++c) R.Dinv[j][c] = m.Dinv32[(size_t)(j * D + c) * ne + e];
+      R.gf[j] = m.gf32[(size_t)j * ne + e];
+    }
+    R.wmu = m.wmu32[e];
+    R.wlam = m.wlam32[e];
+    R.wkf = m.wkf32[e];
+  }
+}
+
+// Ds[c][j] = x_{v[j+1]} - x_{v[0]}, differences taken in f64 before rounding to T
+template <int D, typename T>
+__device__ __forceinline__ void gather_edges(const double* __restrict__ x, const int v[D + 1], T Ds[D][D]) {
+  double b[D];
+#pragma unroll
+  for (int c = 0; c < D; ++c) b[c] = x[(size_t)v[0] * D + c];
+#pragma unroll
+  for (int j = 0; j < D; ++j)
+#pragma unroll
+    for (int c = 0; c < D; ++c) Ds[c][j] = T(x[(size_t)v[j + 1] * D + c] - b[c]);
+}
+
+// edges of x + alpha dx
+template <int D>
+__device__ __forceinline__ void gather_edges_step(const double* __restrict__ x, const double* __restrict__ dx,
+                                                  double alpha, const int v[D + 1], double Ds[D][D]) {
+  double b[D];
+#pragma unroll
+  for (int c = 0; c < D; ++c) b[c] = x[(size_t)v[0] * D + c] + alpha * dx[(size_t)v[0] * D + c];
+#pragma unroll
+  for (int j = 0; j < D; ++j)
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      const size_t i = (size_t)v[j + 1] * D + c;
+      Ds[c][j] = (x[i] + alpha * dx[i]) - b[c];
+    }
+}
+
+template <bool ATOMIC>
+__device__ __forceinline__ void scatter_add(double* dst, size_t i, double val) {
+  if constexpr (ATOMIC)
+    unsafeAtomicAdd(dst + i, val);
+  else
+    dst[i] += val;
+}
+
+template <int D, bool ATOMIC, typename T>
+__device__ __forceinline__ void scatter_vertices(double* dst, const int v[D + 1], const T out[D + 1][D], double scale) {
+#pragma unroll
+  for (int k = 0; k <= D; ++k)
+#pragma unroll
+    for (int c = 0; c < D; ++c) scatter_add<ATOMIC>(dst, (size_t)v[k] * D + c, scale * double(out[k][c]));
+}
+
+// ---------------------------------------------------------------------------------------------
+// precompute
+// ---------------------------------------------------------------------------------------------
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_precompute_geom(int n_e, const double* __restrict__ X,
+                                                            const int32_t* __restrict__ conn, double* Dinv, double* W) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n_e; e += gridDim.x * blockDim.x) {
+    int v[D + 1];
+#pragma unroll
+    for (int k = 0; k <= D; ++k) v[k] = conn[(size_t)k * n_e + e];
+    double Dm[D][D];
+    gather_edges<D, double>(X, v, Dm);
+    double C[D][D];
+    cofactor<D, double>(Dm, C);
+    double det = 0.0;
+#pragma unroll
+    for (int r = 0; r < D; ++r) det += Dm[r][0] * C[r][0];
+    // Dm^-1 = cof(Dm)^T / det
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+#pragma unroll
+      for (int c = 0; c < D; ++c) Dinv[(size_t)(j * D + c) * n_e + e] = C[c][j] / det;
+    W[e] = det / (D == 2 ? 2.0 : 6.0);
+  }
+}
+
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_precompute_material(int n_e, const double* __restrict__ Dinv,
+                                                                const double* __restrict__ W,
+                                                                const double* __restrict__ fdir,
+                                                                const double* __restrict__ mu,
+                                                                const double* __restrict__ lam,
+                                                                const double* __restrict__ kf, double* gf, double* wmu,
+                                                                double* wlam, double* wkf, float* Dinv32, float* gf32,
+                                                                float* wmu32, float* wlam32, float* wkf32) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n_e; e += gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      double acc = 0.0;
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        const double di = Dinv[(size_t)(j * D + c) * n_e + e];
+        acc += di * fdir[(size_t)e * D + c];
+        if (Dinv32) Dinv32[(size_t)(j * D + c) * n_e + e] = float(di);
+      }
+      gf[(size_t)j * n_e + e] = acc;
+      if (gf32) gf32[(size_t)j * n_e + e] = float(acc);
+    }
+    const double w = W[e];
+    const double a = w * mu[e], b = w * lam[e], c = w * kf[e];
+    wmu[e] = a;
+    wlam[e] = b;
+    wkf[e] = c;
+    if (wmu32) {
+      wmu32[e] = float(a);
+      wlam32[e] = float(b);
+      wkf32[e] = float(c);
+    }
+  }
+}
+
+// one colour of elements: every element adds rho W / (D+1) to each of its vertices
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_mass_colour(ERange r, const int32_t* __restrict__ conn, int n_e,
+                                                        const double* __restrict__ W, const double* __restrict__ rho,
+                                                        double* mass) {
+  for (int k = r.begin + blockIdx.x * blockDim.x + threadIdx.x; k < r.end; k += gridDim.x * blockDim.x) {
+    const int e = elem_id(r, k);
+    const double q = rho[e] * W[e] / double(D + 1);
+#pragma unroll
+    for (int i = 0; i <= D; ++i) mass[conn[(size_t)i * n_e + e]] += q;
+  }
+}
+
+void launch_precompute_geom(int D, int n_e, const double* X, const int32_t* conn, double* Dinv, double* W,
+                            hipStream_t s) {
+  if (n_e <= 0) return;
+  if (D == 2)
+    k_precompute_geom<2><<<grid_for(n_e), kBlock, 0, s>>>(n_e, X, conn, Dinv, W);
+  else
+    k_precompute_geom<3><<<grid_for(n_e), kBlock, 0, s>>>(n_e, X, conn, Dinv, W);
+}
+
+void launch_precompute_material(int D, int n_e, const double* Dinv, const double* W, const double* fdir,
+                                const double* mu, const double* lam, const double* kf, double* gf, double* wmu,
+                                double* wlam, double* wkf, float* Dinv32, float* gf32, float* wmu32, float* wlam32,
+                                float* wkf32, hipStream_t s) {
+  if (n_e <= 0) return;
+  if (D == 2)
+    k_precompute_material<2><<<grid_for(n_e), kBlock, 0, s>>>(n_e, Dinv, W, fdir, mu, lam, kf, gf, wmu, wlam, wkf,
+                                                              Dinv32, gf32, wmu32, wlam32, wkf32);
+  else
+    k_precompute_material<3><<<grid_for(n_e), kBlock, 0, s>>>(n_e, Dinv, W, fdir, mu, lam, kf, gf, wmu, wlam, wkf,
+                                                              Dinv32, gf32, wmu32, wlam32, wkf32);
+}
+
+void launch_mass_colour(int D, ERange r, const int32_t* conn, int n_e, const double* W, const double* rho,
+                        double* mass, hipStream_t s) {
+  const int n = r.end - r.begin;
+  if (n <= 0) return;
+  if (D == 2)
+    k_mass_colour<2><<<grid_for(n), kBlock, 0, s>>>(r, conn, n_e, W, rho, mass);
+  else
+    k_mass_colour<3><<<grid_for(n), kBlock, 0, s>>>(r, conn, n_e, W, rho, mass);
+}
+
+// ---------------------------------------------------------------------------------------------
+// vertex kernels
+// ---------------------------------------------------------------------------------------------
+// tangential axes: x in 2D, x and z in 3D
+template <int D>
+__device__ __forceinline__ bool tangential(int c) {
+  return c != 1;
+}
+
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_setup(DevMesh m, DevScene sc, int v0, int v1,
+                                                  const double* __restrict__ x0, const double* __restrict__ vel0,
+                                                  double* x, double* xhat, double* cv) {
+  for (int v = v0 + blockIdx.x * blockDim.x + threadIdx.x; v < v1; v += gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      const size_t i = (size_t)v * D + c;
+      const double xh = (sc.be && vel0) ? x0[i] + sc.h * vel0[i] : x0[i];
+      xhat[i] = xh;
+      x[i] = m.pinned[i] ? x0[i] : xh;
+    }
+    cv[v] = fmax(-x0[(size_t)v * D + 1] + sc.eps, 0.0);
+  }
+}
+
+// gradient of the vertex terms: s_pot (m g e_y - 2 k_c ReLU(-y) e_y + 2 k_fr cv (x_t - x0_t)/h^2) + m (x - xhat)
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_vertex_grad(DevMesh m, DevScene sc, int v0, int v1,
+                                                        const double* __restrict__ x, const double* __restrict__ x0,
+                                                        const double* __restrict__ xhat, const double* __restrict__ cv,
+                                                        double* G) {
+  const double ih2 = 1.0 / (sc.h * sc.h);
+  for (int v = v0 + blockIdx.x * blockDim.x + threadIdx.x; v < v1; v += gridDim.x * blockDim.x) {
+    const double mv = m.mass[v];
+    const double cfr = 2.0 * sc.kfr * cv[v] * ih2;
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      const size_t i = (size_t)v * D + c;
+      double g = 0.0;
+      if (c == 1)
+        g = mv * sc.grav - 2.0 * sc.kc * fmax(-x[i], 0.0);
+      else
+        g = cfr * (x[i] - x0[i]);
+      g *= sc.s_pot;
+      if (sc.be) g += mv * (x[i] - xhat[i]);
+      G[i] = g;
+    }
+  }
+}
+
+// diagonal Hessian of the vertex terms (inertia, contact indicator [y < 0], friction); 0 on pinned DOFs
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_vertex_hdiag(DevMesh m, DevScene sc, int v0, int v1,
+                                                         const double* __restrict__ x, const double* __restrict__ cv,
+                                                         double* vdiag) {
+  const double ih2 = 1.0 / (sc.h * sc.h);
+  for (int v = v0 + blockIdx.x * blockDim.x + threadIdx.x; v < v1; v += gridDim.x * blockDim.x) {
+    const double mv = m.mass[v];
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      const size_t i = (size_t)v * D + c;
+      double hd = (c == 1) ? (x[i] < 0.0 ? 2.0 * sc.kc : 0.0) : 2.0 * sc.kfr * cv[v] * ih2;
+      hd *= sc.s_pot;
+      if (sc.be) hd += mv;
+      vdiag[i] = m.pinned[i] ? 0.0 : hd;
+    }
+  }
+}
+
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_mask(DevMesh m, int v0, int v1, double* vec) {
+  for (int i = v0 * D + blockIdx.x * blockDim.x + threadIdx.x; i < v1 * D; i += gridDim.x * blockDim.x)
+    if (m.pinned[i]) vec[i] = 0.0;
+}
+
+// Jacobi preconditioner 1/|diag H| (1 where the diagonal vanishes), 0 on pinned DOFs
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_finish_diag(DevMesh m, int v0, int v1, const double* __restrict__ diag,
+                                                        double* Dinvp) {
+  for (int i = v0 * D + blockIdx.x * blockDim.x + threadIdx.x; i < v1 * D; i += gridDim.x * blockDim.x) {
+    const double d = fabs(diag[i]);
+    Dinvp[i] = m.pinned[i] ? 0.0 : (d > 0.0 ? 1.0 / d : 1.0);
+  }
+}
+
+// vertex part of the energy: comps (sum of g_v(x + alpha dx) - g_v(x), sum |g_v(x)|, sum g_v(x + alpha dx))
+template <int D>
+__device__ __forceinline__ double vertex_energy(const DevMesh& m, const DevScene& sc, int v, const double* xv,
+                                                const double* x0, const double* xhat, const double* cv) {
+  const double mv = m.mass[v];
+  const double y = xv[1];
+  double e = mv * sc.grav * y;
+  const double pen = fmax(-y, 0.0);
+  e += sc.kc * pen * pen;
+  if (sc.kfr != 0.0) {
+    double vt2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < D; ++c)
+      if (c != 1) {
+        const double vt = (xv[c] - x0[(size_t)v * D + c]) / sc.h;
+        vt2 += vt * vt;
+      }
+    e += sc.kfr * cv[v] * vt2;
+  }
+  e *= sc.s_pot;
+  if (sc.be) {
+    double d2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      const double d = xv[c] - xhat[(size_t)v * D + c];
+      d2 += d * d;
+    }
+    e += 0.5 * mv * d2;
+  }
+  return e;
+}
+
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_vertex_energy(DevMesh m, DevScene sc, int v0, int v1,
+                                                          const double* __restrict__ x, const double* __restrict__ dx,
+                                                          double alpha, const double* __restrict__ x0,
+                                                          const double* __restrict__ xhat,
+                                                          const double* __restrict__ cv, double* partials) {
+  __shared__ double sh[kBlock / 64];
+  double sd = 0.0, sa = 0.0, st = 0.0;
+  for (int v = v0 + blockIdx.x * blockDim.x + threadIdx.x; v < v1; v += gridDim.x * blockDim.x) {
+    double xa[D], xb[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      const size_t i = (size_t)v * D + c;
+      xa[c] = x[i];
+      xb[c] = dx ? x[i] + alpha * dx[i] : x[i];
+    }
+    const double ea = vertex_energy<D>(m, sc, v, xa, x0, xhat, cv);
+    const double eb = vertex_energy<D>(m, sc, v, xb, x0, xhat, cv);
+    sd += eb - ea;
+    sa += fabs(ea);
+    st += eb;
+  }
+  sd = block_sum(sd, sh);
+  sa = block_sum(sa, sh);
+  st = block_sum(st, sh);
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x * 3 + 0] = sd;
+    partials[blockIdx.x * 3 + 1] = sa;
+    partials[blockIdx.x * 3 + 2] = st;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_velocity(int n, const double* __restrict__ x1,
+                                                     const double* __restrict__ x0, double inv_h, double* v1) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) v1[i] = (x1[i] - x0[i]) * inv_h;
+}
+
+// b = x1_bar + v1_bar / h (backward Euler), 0 on pinned DOFs
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_adjoint_rhs(DevMesh m, DevScene sc, int v0, int v1,
+                                                        const double* __restrict__ x1_bar,
+                                                        const double* __restrict__ v1_bar, double* b) {
+  for (int i = v0 * D + blockIdx.x * blockDim.x + threadIdx.x; i < v1 * D; i += gridDim.x * blockDim.x) {
+    double r = x1_bar[i];
+    if (sc.be && v1_bar) r += v1_bar[i] / sc.h;
+    b[i] = m.pinned[i] ? 0.0 : r;
+  }
+}
+
+// x0_bar = M w - s_pot (d^2 E_fr / dx dx0)^T w - v1_bar / h ; v0_bar = h M w (backward Euler)
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_vertex_vjp(DevMesh m, DevScene sc, int v0, int v1,
+                                                       const double* __restrict__ w, const double* __restrict__ x1,
+                                                       const double* __restrict__ x0,
+                                                       const double* __restrict__ v1_bar, double* x0_bar,
+                                                       double* v0_bar) {
+  const double ih2 = 1.0 / (sc.h * sc.h);
+  for (int v = v0 + blockIdx.x * blockDim.x + threadIdx.x; v < v1; v += gridDim.x * blockDim.x) {
+    const double mv = m.mass[v];
+    const size_t b = (size_t)v * D;
+    const double y0 = x0[b + 1];
+    const double cvv = fmax(-y0 + sc.eps, 0.0);
+    const double dcv = (-y0 + sc.eps > 0.0) ? -1.0 : 0.0;
+    double xb[D], vb[D];
+    double ycross = 0.0;
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      xb[c] = sc.be ? mv * w[b + c] : 0.0;
+      vb[c] = sc.be ? sc.h * mv * w[b + c] : 0.0;
+      if (sc.be && v1_bar) xb[c] -= v1_bar[b + c] / sc.h;
+      if (c != 1 && sc.kfr != 0.0) {
+        xb[c] -= sc.s_pot * (-2.0 * sc.kfr * cvv * ih2) * w[b + c];
+        ycross += 2.0 * sc.kfr * ih2 * (x1[b + c] - x0[b + c]) * w[b + c];
+      }
+    }
+    xb[1] -= sc.s_pot * ycross * dcv;
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      const bool pin = m.pinned[b + c];
+      if (x0_bar) x0_bar[b + c] = pin ? 0.0 : xb[c];
+      if (v0_bar) v0_bar[b + c] = pin ? 0.0 : vb[c];
+    }
+  }
+}
+
+#define DISPATCH_D(D_, KERNEL, GRID, ...)                                 \
+  do {                                                                    \
+    if ((D_) == 2)                                                        \
+      KERNEL<2><<<(GRID), kBlock, 0, s>>>(__VA_ARGS__);                   \
+    else                                                                  \
+      KERNEL<3><<<(GRID), kBlock, 0, s>>>(__VA_ARGS__);                   \
+  } while (0)
+
+void launch_setup(const DevMesh& m, const DevScene& sc, int v0, int v1, const double* x0, const double* v0p,
+                  double* x, double* xhat, double* cv, hipStream_t s) {
+  if (v1 <= v0) return;
+  DISPATCH_D(m.dim, k_setup, grid_for(v1 - v0), m, sc, v0, v1, x0, v0p, x, xhat, cv);
+}
+void launch_vertex_grad(const DevMesh& m, const DevScene& sc, int v0, int v1, const double* x, const double* x0,
+                        const double* xhat, const double* cv, double* G, hipStream_t s) {
+  if (v1 <= v0) return;
+  DISPATCH_D(m.dim, k_vertex_grad, grid_for(v1 - v0), m, sc, v0, v1, x, x0, xhat, cv, G);
+}
+void launch_vertex_hdiag(const DevMesh& m, const DevScene& sc, int v0, int v1, const double* x, const double* cv,
+                         double* vdiag, hipStream_t s) {
+  if (v1 <= v0) return;
+  DISPATCH_D(m.dim, k_vertex_hdiag, grid_for(v1 - v0), m, sc, v0, v1, x, cv, vdiag);
+}
+void launch_mask(const DevMesh& m, int v0, int v1, double* vec, hipStream_t s) {
+  if (v1 <= v0) return;
+  DISPATCH_D(m.dim, k_mask, grid_for((v1 - v0) * m.dim), m, v0, v1, vec);
+}
+void launch_finish_diag(const DevMesh& m, int v0, int v1, const double* diag, double* Dinvp, hipStream_t s) {
+  if (v1 <= v0) return;
+  DISPATCH_D(m.dim, k_finish_diag, grid_for((v1 - v0) * m.dim), m, v0, v1, diag, Dinvp);
+}
+void launch_vertex_energy(const DevMesh& m, const DevScene& sc, int v0, int v1, const double* x, const double* dx,
+                          double alpha, const double* x0, const double* xhat, const double* cv, double* partials,
+                          int part_off, hipStream_t s, int* nblocks_out) {
+  const int nb = red_blocks(v1 - v0);
+  DISPATCH_D(m.dim, k_vertex_energy, nb, m, sc, v0, v1, x, dx, alpha, x0, xhat, cv, partials + 3 * part_off);
+  *nblocks_out = nb;
+}
+void launch_velocity(int n, const double* x1, const double* x0, double inv_h, double* v1, hipStream_t s) {
+  if (n <= 0) return;
+  k_velocity<<<grid_for(n), kBlock, 0, s>>>(n, x1, x0, inv_h, v1);
+}
+void launch_vertex_vjp(const DevMesh& m, const DevScene& sc, int v0, int v1, const double* w, const double* x1,
+                       const double* x0, const double* v1_bar, double* x0_bar, double* v0_bar, hipStream_t s) {
+  if (v1 <= v0 || (!x0_bar && !v0_bar)) return;
+  DISPATCH_D(m.dim, k_vertex_vjp, grid_for(v1 - v0), m, sc, v0, v1, w, x1, x0, v1_bar, x0_bar, v0_bar);
+}
+void launch_adjoint_rhs(const DevMesh& m, const DevScene& sc, int v0, int v1, const double* x1_bar,
+                        const double* v1_bar, double* b, hipStream_t s) {
+  if (v1 <= v0) return;
+  DISPATCH_D(m.dim, k_adjoint_rhs, grid_for((v1 - v0) * m.dim), m, sc, v0, v1, x1_bar, v1_bar, b);
+}
+
+// ---------------------------------------------------------------------------------------------
+// element kernels
+// ---------------------------------------------------------------------------------------------
+template <int D, bool ATOMIC>
+__global__ void __launch_bounds__(kBlock) k_elem_grad(DevMesh m, DevScene sc, ERange r, const double* __restrict__ x,
+                                                      const double* __restrict__ a, double* G) {
+  for (int k = r.begin + blockIdx.x * blockDim.x + threadIdx.x; k < r.end; k += gridDim.x * blockDim.x) {
+    const int e = elem_id(r, k);
+    int v[D + 1];
+    load_conn<D>(m, e, v);
+    ElemRest<D, double> R;
+    load_rest<D, double>(m, e, R);
+    double Ds[D][D];
+    gather_edges<D, double>(x, v, Ds);
+    ElemState<D, double> S;
+    elem_state<D, double>(Ds, R, S);
+    double out[D + 1][D];
+    elem_grad<D, double>(R, S, a[e], out);
+    scatter_vertices<D, ATOMIC, double>(G, v, out, sc.s_pot);
+  }
+}
+
+template <int D, bool ATOMIC, typename T>
+__global__ void __launch_bounds__(kBlock) k_elem_hv(DevMesh m, DevScene sc, ERange r, const double* __restrict__ x,
+                                                    const double* __restrict__ a, const float* __restrict__ a32,
+                                                    const double* __restrict__ p, double* Hp, const int* done) {
+  if (done && *done) return;
+  for (int k = r.begin + blockIdx.x * blockDim.x + threadIdx.x; k < r.end; k += gridDim.x * blockDim.x) {
+    const int e = elem_id(r, k);
+    int v[D + 1];
+    load_conn<D>(m, e, v);
+    ElemRest<D, T> R;
+    load_rest<D, T>(m, e, R);
+    T Ds[D][D], dDs[D][D];
+    gather_edges<D, T>(x, v, Ds);
+    gather_edges<D, T>(p, v, dDs);
+    ElemState<D, T> S;
+    elem_state<D, T>(Ds, R, S);
+    const T ae = std::is_same<T, double>::value ? T(a[e]) : T(a32[e]);
+    T out[D + 1][D];
+    elem_hessvec<D, T>(R, S, ae, dDs, out);
+    scatter_vertices<D, ATOMIC, T>(Hp, v, out, sc.s_pot);
+  }
+}
+
+template <int D, bool ATOMIC, typename T>
+__global__ void __launch_bounds__(kBlock) k_elem_diag(DevMesh m, DevScene sc, ERange r, const double* __restrict__ x,
+                                                      const double* __restrict__ a, const float* __restrict__ a32,
+                                                      double* diag) {
+  for (int k = r.begin + blockIdx.x * blockDim.x + threadIdx.x; k < r.end; k += gridDim.x * blockDim.x) {
+    const int e = elem_id(r, k);
+    int v[D + 1];
+    load_conn<D>(m, e, v);
+    ElemRest<D, T> R;
+    load_rest<D, T>(m, e, R);
+    T Ds[D][D];
+    gather_edges<D, T>(x, v, Ds);
+    ElemState<D, T> S;
+    elem_state<D, T>(Ds, R, S);
+    const T ae = std::is_same<T, double>::value ? T(a[e]) : T(a32[e]);
+    T out[D + 1][D];
+    elem_hessdiag<D, T>(R, S, ae, out);
+    scatter_vertices<D, ATOMIC, T>(diag, v, out, sc.s_pot);
+  }
+}
+
+// comps per block: (sum s_pot [E_e(x + alpha dx) - E_e(x)], sum s_pot |E_e(x)|, sum s_pot E_e(x + alpha dx))
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_elem_energy(DevMesh m, DevScene sc, ERange r,
+                                                        const double* __restrict__ x, const double* __restrict__ dx,
+                                                        double alpha, const double* __restrict__ a, double* partials) {
+  __shared__ double sh[kBlock / 64];
+  double sd = 0.0, sa = 0.0, st = 0.0;
+  for (int k = r.begin + blockIdx.x * blockDim.x + threadIdx.x; k < r.end; k += gridDim.x * blockDim.x) {
+    const int e = elem_id(r, k);
+    int v[D + 1];
+    load_conn<D>(m, e, v);
+    ElemRest<D, double> R;
+    load_rest<D, double>(m, e, R);
+    double Ds[D][D];
+    gather_edges<D, double>(x, v, Ds);
+    ElemState<D, double> S;
+    elem_state<D, double>(Ds, R, S);
+    const double ea = sc.s_pot * elem_energy<D, double>(R, S, a[e]);
+    double eb = ea;
+    if (dx) {
+      gather_edges_step<D>(x, dx, alpha, v, Ds);
+      elem_state<D, double>(Ds, R, S);
+      eb = sc.s_pot * elem_energy<D, double>(R, S, a[e]);
+    }
+    sd += eb - ea;
+    sa += fabs(ea);
+    st += eb;
+  }
+  sd = block_sum(sd, sh);
+  sa = block_sum(sa, sh);
+  st = block_sum(st, sh);
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x * 3 + 0] = sd;
+    partials[blockIdx.x * 3 + 1] = sa;
+    partials[blockIdx.x * 3 + 2] = st;
+  }
+}
+
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_elem_vjp(DevMesh m, DevScene sc, ERange r, const double* __restrict__ w,
+                                                     const double* __restrict__ x1, const double* __restrict__ a,
+                                                     double* a_bar, double* mu_bar, double* lam_bar, double* kf_bar) {
+  for (int k = r.begin + blockIdx.x * blockDim.x + threadIdx.x; k < r.end; k += gridDim.x * blockDim.x) {
+    const int e = elem_id(r, k);
+    int v[D + 1];
+    load_conn<D>(m, e, v);
+    ElemRest<D, double> R;
+    load_rest<D, double>(m, e, R);
+    double Ds[D][D], dWs[D][D];
+    gather_edges<D, double>(x1, v, Ds);
+    gather_edges<D, double>(w, v, dWs);
+    ElemState<D, double> S;
+    elem_state<D, double>(Ds, R, S);
+    double out[4];
+    elem_vjp<D, double>(R, S, m.W[e], a[e], dWs, out);
+    if (a_bar) a_bar[e] = sc.s_pot * out[0];
+    if (mu_bar) mu_bar[e] = sc.s_pot * out[1];
+    if (lam_bar) lam_bar[e] = sc.s_pot * out[2];
+    if (kf_bar) kf_bar[e] = sc.s_pot * out[3];
+  }
+}
+
+// per block (min J, -max J) so that both finish with a min-reduction
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_elem_minmax_J(DevMesh m, ERange r, const double* __restrict__ x,
+                                                          double* partials) {
+  __shared__ double sh[kBlock / 64];
+  double lo = 1e300, nhi = 1e300;
+  for (int k = r.begin + blockIdx.x * blockDim.x + threadIdx.x; k < r.end; k += gridDim.x * blockDim.x) {
+    const int e = elem_id(r, k);
+    int v[D + 1];
+    load_conn<D>(m, e, v);
+    ElemRest<D, double> R;
+    load_rest<D, double>(m, e, R);
+    double Ds[D][D];
+    gather_edges<D, double>(x, v, Ds);
+    ElemState<D, double> S;
+    elem_state<D, double>(Ds, R, S);
+    lo = fmin(lo, S.J);
+    nhi = fmin(nhi, -S.J);
+  }
+  lo = block_min(lo, sh);
+  nhi = block_min(nhi, sh);
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x * 2 + 0] = lo;
+    partials[blockIdx.x * 2 + 1] = nhi;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_to_f32(int n, const double* __restrict__ src, float* dst) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) dst[i] = float(src[i]);
+}
+
+template <int D>
+static void elem_grad_d(const DevMesh& m, const DevScene& sc, ERange r, bool atomic, const double* x, const double* a,
+                        double* G, hipStream_t s) {
+  const int g = grid_for(r.end - r.begin);
+  if (atomic)
+    k_elem_grad<D, true><<<g, kBlock, 0, s>>>(m, sc, r, x, a, G);
+  else
+    k_elem_grad<D, false><<<g, kBlock, 0, s>>>(m, sc, r, x, a, G);
+}
+
+void launch_elem_grad(const DevMesh& m, const DevScene& sc, ERange r, bool atomic, const double* x, const double* a,
+                      double* G, hipStream_t s) {
+  if (r.end <= r.begin) return;
+  if (m.dim == 2)
+    elem_grad_d<2>(m, sc, r, atomic, x, a, G, s);
+  else
+    elem_grad_d<3>(m, sc, r, atomic, x, a, G, s);
+}
+
+template <int D, typename T>
+static void elem_hv_dt(const DevMesh& m, const DevScene& sc, ERange r, bool atomic, const double* x, const double* a,
+                       const float* a32, const double* p, double* Hp, const int* done, hipStream_t s) {
+  const int g = grid_for(r.end - r.begin);
+  if (atomic)
+    k_elem_hv<D, true, T><<<g, kBlock, 0, s>>>(m, sc, r, x, a, a32, p, Hp, done);
+  else
+    k_elem_hv<D, false, T><<<g, kBlock, 0, s>>>(m, sc, r, x, a, a32, p, Hp, done);
+}
+
+void launch_elem_hv(const DevMesh& m, const DevScene& sc, ERange r, bool atomic, int precision, const double* x,
+                    const double* a, const float* a32, const double* p, double* Hp, const int* done, hipStream_t s) {
+  if (r.end <= r.begin) return;
+  if (m.dim == 2) {
+    if (precision)
+      elem_hv_dt<2, float>(m, sc, r, atomic, x, a, a32, p, Hp, done, s);
+    else
+      elem_hv_dt<2, double>(m, sc, r, atomic, x, a, a32, p, Hp, done, s);
+  } else {
+    if (precision)
+      elem_hv_dt<3, float>(m, sc, r, atomic, x, a, a32, p, Hp, done, s);
+    else
+      elem_hv_dt<3, double>(m, sc, r, atomic, x, a, a32, p, Hp, done, s);
+  }
+}
+
+template <int D, typename T>
+static void elem_diag_dt(const DevMesh& m, const DevScene& sc, ERange r, bool atomic, const double* x,
+                         const double* a, const float* a32, double* diag, hipStream_t s) {
+  const int g = grid_for(r.end - r.begin);
+  if (atomic)
+    k_elem_diag<D, true, T><<<g, kBlock, 0, s>>>(m, sc, r, x, a, a32, diag);
+  else
+    k_elem_diag<D, false, T><<<g, kBlock, 0, s>>>(m, sc, r, x, a, a32, diag);
+}
+
+void launch_elem_diag(const DevMesh& m, const DevScene& sc, ERange r, bool atomic, int precision, const double* x,
+                      const double* a, const float* a32, double* diag, hipStream_t s) {
+  if (r.end <= r.begin) return;
+  if (m.dim == 2) {
+    if (precision)
+      elem_diag_dt<2, float>(m, sc, r, atomic, x, a, a32, diag, s);
+    else
+      elem_diag_dt<2, double>(m, sc, r, atomic, x, a, a32, diag, s);
+  } else {
+    if (precision)
+      elem_diag_dt<3, float>(m, sc, r, atomic, x, a, a32, diag, s);
+    else
+      elem_diag_dt<3, double>(m, sc, r, atomic, x, a, a32, diag, s);
+  }
+}
+
+void launch_elem_energy(const DevMesh& m, const DevScene& sc, ERange r, const double* x, const double* dx,
+                        double alpha, const double* a, double* partials, int part_off, hipStream_t s,
+                        int* nblocks_out) {
+  const int nb = red_blocks(r.end - r.begin);
+  DISPATCH_D(m.dim, k_elem_energy, nb, m, sc, r, x, dx, alpha, a, partials + 3 * part_off);
+  *nblocks_out = nb;
+}
+
+void launch_elem_vjp(const DevMesh& m, const DevScene& sc, ERange r, const double* w, const double* x1,
+                     const double* a, double* a_bar, double* mu_bar, double* lam_bar, double* kf_bar, hipStream_t s) {
+  if (r.end <= r.begin) return;
+  DISPATCH_D(m.dim, k_elem_vjp, grid_for(r.end - r.begin), m, sc, r, w, x1, a, a_bar, mu_bar, lam_bar, kf_bar);
+}
+
+void launch_elem_minmax_J(const DevMesh& m, ERange r, const double* x, double* partials, hipStream_t s,
+                          int* nblocks_out) {
+  const int nb = red_blocks(r.end - r.begin);
+  DISPATCH_D(m.dim, k_elem_minmax_J, nb, m, r, x, partials);
+  *nblocks_out = nb;
+}
+
+void launch_to_f32(int n, const double* src, float* dst, hipStream_t s) {
+  if (n <= 0) return;
+  k_to_f32<<<grid_for(n), kBlock, 0, s>>>(n, src, dst);
+}
+
+// ---------------------------------------------------------------------------------------------
+// reductions and vector kernels
+// ---------------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) k_dot(int n, const double* __restrict__ a, const double* __restrict__ b,
+                                                double* partials) {
+  __shared__ double sh[kBlock / 64];
+  double acc = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) acc += a[i] * b[i];
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = acc;
+}
+
+// out[c] = sum_b partials[b * ncomp + c], in block order
+__global__ void __launch_bounds__(kBlock) k_finalize(const double* __restrict__ partials, int nblocks, int ncomp,
+                                                     double* out) {
+  __shared__ double sh[kBlock / 64];
+  for (int c = 0; c < ncomp; ++c) {
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) acc += partials[b * ncomp + c];
+    acc = block_sum(acc, sh);
+    if (threadIdx.x == 0) out[c] = acc;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_finalize_minmax(const double* __restrict__ partials, int nblocks,
+                                                            double* out) {
+  __shared__ double sh[kBlock / 64];
+  double lo = 1e300, nhi = 1e300;
+  for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
+    lo = fmin(lo, partials[2 * b]);
+    nhi = fmin(nhi, partials[2 * b + 1]);
+  }
+  lo = block_min(lo, sh);
+  nhi = block_min(nhi, sh);
+  if (threadIdx.x == 0) {
+    out[0] = lo;
+    out[1] = -nhi;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_axpy(int n, double* x, double alpha, const double* __restrict__ dx) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) x[i] += alpha * dx[i];
+}
+
+__global__ void __launch_bounds__(kBlock) k_copy(int n, const double* __restrict__ src, double* dst) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) dst[i] = src[i];
+}
+
+// sum of the first nb partials (two components interleaved when ncomp == 2), identical in every block
+__device__ __forceinline__ double all_blocks_sum(const double* partials, int nb, int ncomp, int c, double* sh) {
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) acc += partials[b * ncomp + c];
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) sh[kBlock / 64] = acc;
+  __syncthreads();
+  const double r = sh[kBlock / 64];
+  __syncthreads();
+  return r;
+}
+
+// r = b, x = 0, p = D^-1 r, Hp = vdiag p; partials (r.z, r.r); a single block then fills scal
+__global__ void __launch_bounds__(kBlock) k_cg_start(int n, const double* __restrict__ b, double sign,
+                                                     const double* __restrict__ Dinvp,
+                                                     const double* __restrict__ vdiag, double* r, double* p, double* xs,
+                                                     double* Hp, double* partials) {
+  __shared__ double sh[kBlock / 64];
+  double rz = 0.0, rr = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const double ri = Dinvp[i] != 0.0 ? sign * b[i] : 0.0;
+    const double zi = Dinvp[i] * ri;
+    r[i] = ri;
+    p[i] = zi;
+    xs[i] = 0.0;
+    Hp[i] = vdiag[i] * zi;
+    rz += ri * zi;
+    rr += ri * ri;
+  }
+  rz = block_sum(rz, sh);
+  rr = block_sum(rr, sh);
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x] = rz;
+    partials[2 * blockIdx.x + 1] = rr;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_cg_start_fin(const double* __restrict__ partials, int nb, CgScal* scal,
+                                                         double tol2) {
+  __shared__ double sh[kBlock / 64 + 1];
+  const double rz = all_blocks_sum(partials, nb, 2, 0, sh);
+  const double rr = all_blocks_sum(partials, nb, 2, 1, sh);
+  if (threadIdx.x == 0) {
+    scal->rz[0] = rz;
+    scal->rr = rr;
+    scal->rr0 = rr;
+    scal->pHp = 0.0;
+    scal->done = (rr <= tol2) ? 1 : 0;
+    scal->negcurv = 0;
+    scal->iters = 0;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_cg_dot(int n, const double* __restrict__ p, const double* __restrict__ Hp,
+                                                   double* partials, const CgScal* scal) {
+  if (scal->done) return;
+  __shared__ double sh[kBlock / 64];
+  double acc = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) acc += p[i] * Hp[i];
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = acc;
+}
+
+// alpha = rz / pHp; x += alpha p; r -= alpha Hp (masked by D^-1 != 0); partials (r.z, r.r)
+__global__ void __launch_bounds__(kBlock) k_cg_update(int n, int it, int nb, const double* __restrict__ p,
+                                                      const double* __restrict__ Hp, const double* __restrict__ Dinvp,
+                                                      double* r, double* xs, double* partials, CgScal* scal) {
+  if (scal->done) return;
+  __shared__ double sh[kBlock / 64 + 1];
+  const double pHp = all_blocks_sum(partials, nb, 1, 0, sh);
+  __syncthreads();  // every block has read its partials before any overwrites them below
+  const double rz = scal->rz[it & 1];
+  if (!(pHp > 0.0)) {
+    // non-positive curvature: stop; on the first iteration return the preconditioned
+    // steepest-descent direction p0 = D^-1 b (Nocedal & Wright, Alg. 7.1)
+    if (it == 0)
+      for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) xs[i] = p[i];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      scal->negcurv = 1;
+      scal->done = 1;
+      scal->pHp = pHp;
+      scal->iters = it;
+    }
+    return;
+  }
+  const double alpha = rz / pHp;
+  double rz1 = 0.0, rr = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const double di = Dinvp[i];
+    xs[i] += alpha * p[i];
+    const double ri = di != 0.0 ? r[i] - alpha * Hp[i] : 0.0;
+    r[i] = ri;
+    rz1 += ri * di * ri;
+    rr += ri * ri;
+  }
+  // the partials buffer is reused: this kernel reads nb single partials, then writes 2 per block
+  rz1 = block_sum(rz1, sh);
+  rr = block_sum(rr, sh);
+  if (threadIdx.x == 0) {
+    partials[kMaxRedBlocks + 2 * blockIdx.x] = rz1;
+    partials[kMaxRedBlocks + 2 * blockIdx.x + 1] = rr;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) scal->pHp = pHp;
+}
+
+// beta = rz_new / rz; p = D^-1 r + beta p; Hp = vdiag p (the start of the next product)
+__global__ void __launch_bounds__(kBlock) k_cg_p(int n, int it, int nb, const double* __restrict__ r,
+                                                 const double* __restrict__ Dinvp, const double* __restrict__ vdiag,
+                                                 double* p, double* Hp, const double* __restrict__ partials,
+                                                 CgScal* scal, double tol2) {
+  if (scal->done) return;
+  __shared__ double sh[kBlock / 64 + 1];
+  const double rz1 = all_blocks_sum(partials + kMaxRedBlocks, nb, 2, 0, sh);
+  const double rr = all_blocks_sum(partials + kMaxRedBlocks, nb, 2, 1, sh);
+  if (rr <= tol2) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      scal->done = 1;
+      scal->rr = rr;
+      scal->iters = it + 1;
+    }
+    return;
+  }
+  const double beta = rz1 / scal->rz[it & 1];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const double pi = Dinvp[i] * r[i] + beta * p[i];
+    p[i] = pi;
+    Hp[i] = vdiag[i] * pi;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    scal->rz[(it + 1) & 1] = rz1;
+    scal->rr = rr;
+    scal->iters = it + 1;
+  }
+}
+
+void launch_dot(int n, const double* a, const double* b, double* partials, hipStream_t s, int* nblocks_out) {
+  const int nb = red_blocks(n);
+  k_dot<<<nb, kBlock, 0, s>>>(n, a, b, partials);
+  *nblocks_out = nb;
+}
+void launch_finalize(const double* partials, int nblocks, int ncomp, double* out, hipStream_t s) {
+  k_finalize<<<1, kBlock, 0, s>>>(partials, nblocks, ncomp, out);
+}
+void launch_finalize_minmax(const double* partials, int nblocks, double* out, hipStream_t s) {
+  k_finalize_minmax<<<1, kBlock, 0, s>>>(partials, nblocks, out);
+}
+void launch_axpy(int n, double* x, double alpha, const double* dx, hipStream_t s) {
+  if (n <= 0) return;
+  k_axpy<<<grid_for(n), kBlock, 0, s>>>(n, x, alpha, dx);
+}
+void launch_copy(int n, const double* src, double* dst, hipStream_t s) {
+  if (n <= 0) return;
+  k_copy<<<grid_for(n), kBlock, 0, s>>>(n, src, dst);
+}
+void launch_cg_start(int n, const double* b, double sign, const double* Dinvp, const double* vdiag, double* r,
+                     double* p, double* xs, double* Hp, double* partials, CgScal* scal, double tol2, hipStream_t s) {
+  const int nb = red_blocks(n);
+  k_cg_start<<<nb, kBlock, 0, s>>>(n, b, sign, Dinvp, vdiag, r, p, xs, Hp, partials);
+  k_cg_start_fin<<<1, kBlock, 0, s>>>(partials, nb, scal, tol2);
+}
+void launch_cg_dot(int n, const double* p, const double* Hp, double* partials, const CgScal* scal, hipStream_t s) {
+  k_cg_dot<<<red_blocks(n), kBlock, 0, s>>>(n, p, Hp, partials, scal);
+}
+void launch_cg_update(int n, int it, const double* p, const double* Hp, const double* Dinvp, double* r, double* xs,
+                      double* partials, CgScal* scal, hipStream_t s) {
+  const int nb = red_blocks(n);
+  k_cg_update<<<nb, kBlock, 0, s>>>(n, it, nb, p, Hp, Dinvp, r, xs, partials, scal);
+}
+void launch_cg_p(int n, int it, const double* r, const double* Dinvp, const double* vdiag, double* p, double* Hp,
+                 const double* partials, CgScal* scal, double tol2, hipStream_t s) {
+  const int nb = red_blocks(n);
+  k_cg_p<<<nb, kBlock, 0, s>>>(n, it, nb, r, Dinvp, vdiag, p, Hp, partials, scal, tol2);
+}
+
+__global__ void __launch_bounds__(kBlock) k_mul(int n, const double* __restrict__ a, const double* __restrict__ b,
+                                                double* out) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) out[i] = a[i] * b[i];
+}
+
+// out = -Dinv g: the preconditioned steepest-descent direction
+__global__ void __launch_bounds__(kBlock) k_neg_precond(int n, const double* __restrict__ Dinvp,
+                                                        const double* __restrict__ g, double* out) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) out[i] = -Dinvp[i] * g[i];
+}
+
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_set_pinned(DevMesh m, int v0, int v1, double value, double* vec) {
+  for (int i = v0 * D + blockIdx.x * blockDim.x + threadIdx.x; i < v1 * D; i += gridDim.x * blockDim.x)
+    if (m.pinned[i]) vec[i] = value;
+}
+
+// per block (min of a, count of non-finite entries)
+__global__ void __launch_bounds__(kBlock) k_min_count(int n, const double* __restrict__ a, double* partials) {
+  __shared__ double sh[kBlock / 64];
+  double lo = 1e300, bad = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const double v = a[i];
+    if (isfinite(v))
+      lo = fmin(lo, v);
+    else
+      bad += 1.0;
+  }
+  lo = block_min(lo, sh);
+  bad = block_sum(bad, sh);
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x] = lo;
+    partials[2 * blockIdx.x + 1] = -bad;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_fill(int n, double value, double* out) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) out[i] = value;
+}
+void launch_fill(int n, double value, double* out, hipStream_t s) {
+  if (n <= 0) return;
+  k_fill<<<grid_for(n), kBlock, 0, s>>>(n, value, out);
+}
+void launch_mul(int n, const double* a, const double* b, double* out, hipStream_t s) {
+  if (n <= 0) return;
+  k_mul<<<grid_for(n), kBlock, 0, s>>>(n, a, b, out);
+}
+void launch_neg_precond(int n, const double* Dinvp, const double* g, double* out, hipStream_t s) {
+  if (n <= 0) return;
+  k_neg_precond<<<grid_for(n), kBlock, 0, s>>>(n, Dinvp, g, out);
+}
+void launch_set_pinned(const DevMesh& m, int v0, int v1, double value, double* vec, hipStream_t s) {
+  if (v1 <= v0) return;
+  DISPATCH_D(m.dim, k_set_pinned, grid_for((v1 - v0) * m.dim), m, v0, v1, value, vec);
+}
+// out[0] = min a, out[1] = -(number of non-finite entries)
+void launch_min_count(int n, const double* a, double* partials, double* out, hipStream_t s) {
+  const int nb = red_blocks(n);
+  k_min_count<<<nb, kBlock, 0, s>>>(n, a, partials);
+  k_finalize_minmax<<<1, kBlock, 0, s>>>(partials, nb, out);
+}
+
+}  // namespace isb

@@ -1,0 +1,298 @@
+"""ctypes binding of libisb.so (the C ABI in include/isb.h).
+
+Argument marshalling only: every computation runs in the HIP library. Methods of `Context`
+carry the C names without the `isb_` prefix (isb_step -> Context.step, ...). Device arrays
+are torch CUDA tensors (float64, contiguous, on the context's device); PyTorch supplies
+device memory and the current stream, nothing else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libisb.so")
+
+ISB_OK, ISB_E_ARG, ISB_E_MESH, ISB_E_HIP, ISB_E_NOT_CONVERGED, ISB_E_NONFINITE, ISB_E_STATE = range(7)
+STATUS_NAMES = {0: "ISB_OK", 1: "ISB_E_ARG", 2: "ISB_E_MESH", 3: "ISB_E_HIP", 4: "ISB_E_NOT_CONVERGED",
+                5: "ISB_E_NONFINITE", 6: "ISB_E_STATE"}
+ISB_FP64, ISB_MIXED = 0, 1
+ISB_QUASISTATIC, ISB_BACKWARD_EULER = 0, 1
+OPT_SOLVER, OPT_SCATTER, OPT_GRAPH_SAFE, OPT_BLOCK, OPT_CG_CHECK, OPT_PRECISION = range(6)
+INFO_N_VERTICES, INFO_N_ELEMENTS, INFO_N_BODIES, INFO_DIM, INFO_N_COLOURS, INFO_LDS_BYTES = range(100, 106)
+FLAG_CONVERGED, FLAG_STAGNATED, FLAG_NONFINITE, FLAG_ADJ_CONVERGED = 1, 2, 4, 8
+
+EXPORTED = ("isb_create", "isb_destroy", "isb_last_error", "isb_version", "isb_validate_mesh",
+            "isb_colour_elements", "isb_mesh_upload", "isb_material_upload", "isb_set_scene",
+            "isb_set_option", "isb_get_option", "isb_get_mass", "isb_step", "isb_solve_adjoint",
+            "isb_vjp_params", "isb_energy", "isb_gradient", "isb_hessvec", "isb_hessdiag")
+
+
+class IsbError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("newton_iters", ctypes.c_int32), ("cg_iters", ctypes.c_int32),
+                ("adj_cg_iters", ctypes.c_int32), ("ls_backtracks", ctypes.c_int32),
+                ("negcurv_exits", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("res0", ctypes.c_double), ("res_final", ctypes.c_double),
+                ("adj_res_final", ctypes.c_double), ("energy", ctypes.c_double),
+                ("min_J", ctypes.c_double), ("max_J", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Scene(ctypes.Structure):
+    _fields_ = [("integrator", ctypes.c_int32), ("max_newton", ctypes.c_int32),
+                ("max_cg", ctypes.c_int32), ("pad_", ctypes.c_int32), ("h", ctypes.c_double),
+                ("gravity", ctypes.c_double), ("k_contact", ctypes.c_double),
+                ("k_friction", ctypes.c_double), ("eps_friction", ctypes.c_double),
+                ("tol_rel", ctypes.c_double), ("adj_tol_rel", ctypes.c_double)]
+
+    @classmethod
+    def from_dict(cls, d: dict) -> "Scene":
+        integ = d["integrator"]
+        if isinstance(integ, str):
+            integ = {"qs": ISB_QUASISTATIC, "be": ISB_BACKWARD_EULER}[integ]
+        return cls(int(integ), int(d["max_newton"]), int(d["max_cg"]), 0, float(d["h"]),
+                   float(d["gravity"]), float(d["k_contact"]), float(d["k_friction"]),
+                   float(d["eps_friction"]), float(d["tol_rel"]), float(d["adj_tol_rel"]))
+
+
+_lib = None
+
+
+def load_library(path: str | None = None) -> ctypes.CDLL:
+    """Load libisb.so; raises ImportError when it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    # torch ships its own HIP runtime under the same soname; loading torch first makes the library
+    # bind to that one copy, so that both share one runtime, one device context and its streams
+    import torch  # noqa: F401
+    if not os.path.exists(p):
+        raise ImportError(f"libisb.so not found at {p}; build it with "
+                          "`python -m paper_2102_05791_amd.build_lib`")
+    lib = ctypes.CDLL(p)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    P = ctypes.POINTER
+    sigs = {
+        "isb_create": [ctypes.c_int, ctypes.c_int, P(vp)],
+        "isb_destroy": [vp],
+        "isb_validate_mesh": [ctypes.c_int, i64, vp, i64, vp, i32, vp, vp],
+        "isb_colour_elements": [ctypes.c_int, i64, i64, vp, vp, P(i32)],
+        "isb_mesh_upload": [vp, ctypes.c_int, i32, vp, vp, vp, vp, vp],
+        "isb_material_upload": [vp, vp, vp, vp, vp, vp, P(Scene)],
+        "isb_set_scene": [vp, P(Scene)],
+        "isb_set_option": [vp, ctypes.c_int, i64],
+        "isb_get_option": [vp, ctypes.c_int, P(i64)],
+        "isb_get_mass": [vp, vp, vp],
+        "isb_step": [vp, vp, vp, vp, vp, vp, vp, vp],
+        "isb_solve_adjoint": [vp, vp, vp, vp, vp, vp, vp, vp, vp],
+        "isb_vjp_params": [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp],
+        "isb_energy": [vp, vp, vp, vp, vp, vp, vp],
+        "isb_gradient": [vp, vp, vp, vp, vp, vp, vp],
+        "isb_hessvec": [vp, vp, vp, vp, vp, vp, vp],
+        "isb_hessdiag": [vp, vp, vp, vp, vp, vp],
+    }
+    for name, argtypes in sigs.items():
+        f = getattr(lib, name)
+        f.argtypes = argtypes
+        f.restype = ctypes.c_int
+    lib.isb_last_error.restype = ctypes.c_char_p
+    lib.isb_last_error.argtypes = []
+    lib.isb_version.restype = ctypes.c_char_p
+    lib.isb_version.argtypes = []
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def _check(lib, status: int, allow=()):
+    if status != ISB_OK and status not in allow:
+        raise IsbError(status, lib.isb_last_error().decode())
+    return status
+
+
+def _host(a, dtype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data_as(ctypes.c_void_p)
+
+
+def validate_mesh(dim, X, T, body_v_off=None, body_e_off=None):
+    """isb_validate_mesh on host arrays; returns (status, message)."""
+    lib = load_library()
+    X, pX = _host(X, np.float64)
+    T, pT = _host(T, np.int32)
+    vo = np.array([0, X.shape[0]] if body_v_off is None else body_v_off, dtype=np.int64)
+    eo = np.array([0, T.shape[0]] if body_e_off is None else body_e_off, dtype=np.int64)
+    vo, pvo = _host(vo, np.int64)
+    eo, peo = _host(eo, np.int64)
+    st = lib.isb_validate_mesh(dim, X.shape[0], pX, T.shape[0], pT, len(vo) - 1, pvo, peo)
+    return st, lib.isb_last_error().decode()
+
+
+def colour_elements(dim, n_v, T):
+    """isb_colour_elements: (colour per element, number of colours)."""
+    lib = load_library()
+    T, pT = _host(T, np.int32)
+    col = np.zeros(T.shape[0], dtype=np.int32)
+    nc = ctypes.c_int32(0)
+    _check(lib, lib.isb_colour_elements(dim, n_v, T.shape[0], pT, col.ctypes.data_as(ctypes.c_void_p),
+                                        ctypes.byref(nc)))
+    return col, nc.value
+
+
+def _dev(t, name="tensor"):
+    if t is None:
+        return None
+    if not (t.is_cuda and t.dtype.is_floating_point and t.element_size() == 8 and t.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous float64 CUDA tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Context:
+    """One isb_ctx: a mesh of independent bodies on one GPU, plus material and scene."""
+
+    def __init__(self, device: int = 0, precision: str | int = "fp64"):
+        self.lib = load_library()
+        prec = {"fp64": ISB_FP64, "mixed": ISB_MIXED}.get(precision, precision)
+        h = ctypes.c_void_p()
+        _check(self.lib, self.lib.isb_create(int(device), int(prec), ctypes.byref(h)))
+        self.h = h
+        self.device = device
+        self.precision = prec
+        self.dim = self.n_v = self.n_e = self.n_bodies = 0
+        self.scene = None
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            self.lib.isb_destroy(h)
+            self.h = None
+
+    def close(self):
+        self.__del__()
+
+    # ---- upload ----
+    def mesh_upload(self, dim, X, T, pinned=None, body_v_off=None, body_e_off=None):
+        X, pX = _host(X, np.float64)
+        T, pT = _host(T, np.int32)
+        P = np.zeros(X.shape, np.uint8) if pinned is None else pinned
+        P, pP = _host(P, np.uint8)
+        vo, pvo = _host([0, X.shape[0]] if body_v_off is None else body_v_off, np.int64)
+        eo, peo = _host([0, T.shape[0]] if body_e_off is None else body_e_off, np.int64)
+        _check(self.lib, self.lib.isb_mesh_upload(self.h, int(dim), len(vo) - 1, pvo, peo, pX, pT, pP))
+        self.dim, self.n_v, self.n_e, self.n_bodies = int(dim), X.shape[0], T.shape[0], len(vo) - 1
+        self.body_v_off, self.body_e_off = vo.copy(), eo.copy()
+
+    def material_upload(self, mu, lam, kf, fdir, rho, scene: dict):
+        arrs = [_host(a, np.float64) for a in (mu, lam, kf, fdir, rho)]
+        sc = Scene.from_dict(scene)
+        _check(self.lib, self.lib.isb_material_upload(self.h, *[p for _, p in arrs], ctypes.byref(sc)))
+        self.scene = dict(scene)
+
+    def set_scene(self, scene: dict):
+        sc = Scene.from_dict(scene)
+        _check(self.lib, self.lib.isb_set_scene(self.h, ctypes.byref(sc)))
+        self.scene = dict(scene)
+
+    def set_option(self, key: int, value: int):
+        _check(self.lib, self.lib.isb_set_option(self.h, int(key), int(value)))
+
+    def get_option(self, key: int) -> int:
+        v = ctypes.c_int64(0)
+        _check(self.lib, self.lib.isb_get_option(self.h, int(key), ctypes.byref(v)))
+        return v.value
+
+    @classmethod
+    def from_workload(cls, w, device=0, precision="fp64", solver=0, scatter=0):
+        ctx = cls(device, precision)
+        ctx.set_option(OPT_SCATTER, scatter)
+        ctx.mesh_upload(w.dim, w.X, w.T, w.pinned, w.body_v_off, w.body_e_off)
+        ctx.material_upload(w.mu, w.lam, w.kf, w.fdir, w.rho, w.scene)
+        ctx.set_option(OPT_SOLVER, solver)
+        return ctx
+
+    # ---- device helpers ----
+    def _empty(self, *shape):
+        import torch
+        return torch.empty(*shape, dtype=torch.float64, device=f"cuda:{self.device}")
+
+    def _stats_buf(self, want):
+        return (Stats * self.n_bodies)() if want else None
+
+    def mass(self):
+        m = self._empty(self.n_v)
+        _check(self.lib, self.lib.isb_get_mass(self.h, _stream(), _dev(m)))
+        return m
+
+    # ---- the step and its adjoint ----
+    def step(self, x0, v0, a, x1=None, v1=None, stats=True, allow_not_converged=False):
+        """isb_step. Returns (x1, v1, [per-body stats dicts] or None, status)."""
+        be = self.scene["integrator"] in ("be", ISB_BACKWARD_EULER)
+        x1 = self._empty(self.n_v, self.dim) if x1 is None else x1
+        if be and v1 is None:
+            v1 = self._empty(self.n_v, self.dim)
+        sb = self._stats_buf(stats)
+        allow = (ISB_E_NOT_CONVERGED,) if allow_not_converged else ()
+        st = _check(self.lib, self.lib.isb_step(self.h, _stream(), _dev(x0, "x0"), _dev(v0, "v0"), _dev(a, "a"),
+                                                _dev(x1, "x1"), _dev(v1, "v1") if be else None, sb), allow)
+        return x1, (v1 if be else None), ([s.as_dict() for s in sb] if sb is not None else None), st
+
+    def solve_adjoint(self, x1, x0, a, x1_bar, v1_bar=None, w=None, stats=True, allow_not_converged=False):
+        """isb_solve_adjoint. Returns (w, per-body stats or None, status)."""
+        w = self._empty(self.n_v, self.dim) if w is None else w
+        sb = self._stats_buf(stats)
+        allow = (ISB_E_NOT_CONVERGED,) if allow_not_converged else ()
+        st = _check(self.lib, self.lib.isb_solve_adjoint(self.h, _stream(), _dev(x1, "x1"), _dev(x0, "x0"),
+                                                         _dev(a, "a"), _dev(x1_bar, "x1_bar"),
+                                                         _dev(v1_bar, "v1_bar"), _dev(w, "w"), sb), allow)
+        return w, ([s.as_dict() for s in sb] if sb is not None else None), st
+
+    def vjp_params(self, w, x1, x0, a, v1_bar=None, want=("a_bar", "x0_bar", "v0_bar", "mu_bar", "lam_bar",
+                                                          "kf_bar")):
+        """isb_vjp_params. Returns a dict of the requested cotangents."""
+        out = {}
+        for k in ("a_bar", "mu_bar", "lam_bar", "kf_bar"):
+            out[k] = self._empty(self.n_e) if k in want else None
+        for k in ("x0_bar", "v0_bar"):
+            out[k] = self._empty(self.n_v, self.dim) if k in want else None
+        _check(self.lib, self.lib.isb_vjp_params(
+            self.h, _stream(), _dev(w), _dev(x1), _dev(x0), _dev(a), _dev(v1_bar), _dev(out["a_bar"]),
+            _dev(out["x0_bar"]), _dev(out["v0_bar"]), _dev(out["mu_bar"]), _dev(out["lam_bar"]),
+            _dev(out["kf_bar"])))
+        return {k: v for k, v in out.items() if v is not None}
+
+    # ---- single evaluations ----
+    def energy(self, x, x0, v0, a):
+        e = self._empty(self.n_bodies)
+        _check(self.lib, self.lib.isb_energy(self.h, _stream(), _dev(x), _dev(x0), _dev(v0), _dev(a), _dev(e)))
+        return e
+
+    def gradient(self, x, x0, v0, a):
+        g = self._empty(self.n_v, self.dim)
+        _check(self.lib, self.lib.isb_gradient(self.h, _stream(), _dev(x), _dev(x0), _dev(v0), _dev(a), _dev(g)))
+        return g
+
+    def hessvec(self, x, x0, a, p):
+        hp = self._empty(self.n_v, self.dim)
+        _check(self.lib, self.lib.isb_hessvec(self.h, _stream(), _dev(x), _dev(x0), _dev(a), _dev(p), _dev(hp)))
+        return hp
+
+    def hessdiag(self, x, x0, a):
+        d = self._empty(self.n_v, self.dim)
+        _check(self.lib, self.lib.isb_hessdiag(self.h, _stream(), _dev(x), _dev(x0), _dev(a), _dev(d)))
+        return d

@@ -1,0 +1,127 @@
+"""GPU parity of the implicit step and the adjoint against the FP64 oracle (both solved tight),
+through the C ABI, plus error paths and determinism."""
+import numpy as np
+import pytest
+
+from oracle import solve
+from synth import scenes
+from tests.gpu_util import problems, rand_workload, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda:0")
+
+
+def _ctx(w, precision="fp64", scatter=0, solver=0):
+    from paper_2102_05791_amd import Context
+    return Context.from_workload(w, precision=precision, scatter=scatter, solver=solver)
+
+
+def _tight(w, tol=1e-13):
+    w.scene.update(tol_rel=tol, adj_tol_rel=1e-13, max_newton=60, max_cg=4000)
+    return w
+
+
+def test_cantilever_quasistatic_parity():
+    w = _tight(scenes.qs_cantilever())
+    p = problems(w)[0]
+    x_ref, _, st_ref = solve.step(p, w.x0, None, w.actions[0], tol=1e-13)
+    ctx = _ctx(w)
+    x1, v1, st, _ = ctx.step(_dev(w.x0), None, _dev(w.actions[0]))
+    x1 = x1.cpu().numpy()
+    print("oracle", st_ref["newton_iters"], "gpu", st[0])
+    assert v1 is None
+    assert st[0]["flags"] & 1 or st[0]["flags"] & 2
+    assert rel(x1, x_ref) <= 1e-10
+    assert rel(x1 - w.x0, x_ref - w.x0) <= 1e-10
+    # the minimiser at the 1e-10 tolerance of the cantilever workload
+    w.scene["tol_rel"] = 1e-10
+    ctx.set_scene(w.scene)
+    x1b, _, st, _ = ctx.step(_dev(w.x0), None, _dev(w.actions[0]))
+    assert st[0]["res_final"] <= 1e-10 * st[0]["res0"]
+    assert rel(x1b.cpu().numpy() - w.x0, x_ref - w.x0) <= 1e-8
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 1e-5)])
+def test_backward_euler_steps_parity(dim, precision, tol):
+    w, rng = rand_workload(dim, seed=7)
+    w = _tight(w)
+    p = problems(w)[0]
+    ctx = _ctx(w, precision=precision)
+    x, v = w.x0, w.v0
+    xg, vg = _dev(w.x0), _dev(w.v0)
+    for t in range(2):
+        x, v, st_ref = solve.step(p, x, v, w.actions[t], tol=1e-13)
+        xg, vg, st, _ = ctx.step(xg, vg, _dev(w.actions[t]))
+        print(t, "oracle iters", st_ref["newton_iters"], "gpu", st[0])
+        assert rel(xg.cpu().numpy() - w.x0, x - w.x0) <= tol
+        assert rel(vg.cpu().numpy(), v) <= tol
+        # continue both from the oracle state so that the steps are compared one by one
+        xg, vg = _dev(x), _dev(v)
+
+
+@pytest.mark.parametrize("dim,integ", [(2, "be"), (2, "qs"), (3, "be")])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 1e-5)])
+def test_adjoint_and_vjp_parity(dim, integ, precision, tol):
+    w, rng = rand_workload(dim, seed=8, integrator=integ, pinned_left=(integ == "qs"))
+    w = _tight(w)
+    p = problems(w)[0]
+    a = w.actions[0]
+    x1, v1, _ = solve.step(p, w.x0, w.v0, a, tol=1e-13)
+    xbar = rng.normal(size=x1.shape)
+    vbar = rng.normal(size=x1.shape) if integ == "be" else None
+    wref = solve.adjoint(p, x1, w.x0, a, xbar, vbar)
+    ref = solve.vjp_params(p, wref, x1, w.x0, a, v1_bar=vbar)
+    ctx = _ctx(w, precision=precision)
+    wg, st, _ = ctx.solve_adjoint(_dev(x1), _dev(w.x0), _dev(a), _dev(xbar), None if vbar is None else _dev(vbar))
+    print("adjoint", st[0])
+    assert rel(wg.cpu().numpy(), wref) <= tol
+    out = ctx.vjp_params(wg, _dev(x1), _dev(w.x0), _dev(a), None if vbar is None else _dev(vbar))
+    for k in ("a_bar", "mu_bar", "lam_bar", "kf_bar", "x0_bar"):
+        assert rel(out[k].cpu().numpy(), ref[k]) <= tol, k
+
+
+def test_colour_scatter_is_bitwise_reproducible():
+    w, _ = rand_workload(2, seed=9)
+    ctx = _ctx(w, scatter=1)
+    outs = []
+    for _ in range(2):
+        x1, v1, st, _ = ctx.step(_dev(w.x0), _dev(w.v0), _dev(w.actions[0]))
+        outs.append((x1.cpu().numpy(), v1.cpu().numpy(), st[0]["newton_iters"], st[0]["cg_iters"]))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    assert outs[0][2:] == outs[1][2:]
+
+
+def test_error_paths():
+    from paper_2102_05791_amd import IsbError, isb
+    w, _ = rand_workload(2, seed=10, shape=(8, 3))
+    ctx = _ctx(w)
+    a = w.actions[0].copy()
+    a[3] = 0.0
+    with pytest.raises(IsbError) as e:
+        ctx.step(_dev(w.x0), _dev(w.v0), _dev(a))
+    assert e.value.status == isb.ISB_E_ARG
+    a[3] = np.nan
+    with pytest.raises(IsbError) as e:
+        ctx.step(_dev(w.x0), _dev(w.v0), _dev(a))
+    assert e.value.status == isb.ISB_E_NONFINITE
+    x0 = w.x0.copy()
+    x0[2, 0] = np.inf
+    with pytest.raises(IsbError) as e:
+        ctx.step(_dev(x0), _dev(w.v0), _dev(w.actions[0]))
+    assert e.value.status == isb.ISB_E_NONFINITE
+    w.scene["max_newton"] = 1
+    w.scene["tol_rel"] = 1e-14
+    ctx.set_scene(w.scene)
+    x1, v1, st, status = ctx.step(_dev(w.x0), _dev(w.v0), _dev(w.actions[0]), allow_not_converged=True)
+    assert status == isb.ISB_E_NOT_CONVERGED and st[0]["newton_iters"] == 1
+    assert np.isfinite(x1.cpu().numpy()).all()
+    from paper_2102_05791_amd import Context
+    fresh = Context(0, "fp64")
+    with pytest.raises(IsbError) as e:
+        fresh.set_option(isb.OPT_BLOCK, 100)
+    assert e.value.status == isb.ISB_E_ARG
