@@ -1,26 +1,210 @@
-// Batched persistent solver: one workgroup per body, the whole Newton-PCG step and the adjoint
-// solve inside one launch (written after the plain path).
+// Batched persistent solver: many bodies of uneven size in one launch per phase (the
+// body-level logic is in isb_body.hpp). Mixed precision: the Hessian-vector product and the
+// diagonal evaluate elements in FP32 from FP32 rest data; gradients, energies, CG vectors, dot
+// products, norms and the state are FP64. No host synchronisation happens inside a launch, so
+// the launches are graph-capturable.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "isb_body.hpp"
 #include "isb_ctx.hpp"
 
 namespace isb {
 
+template <int D, typename T, int MODE>  // MODE 0: step, 1: adjoint
+__global__ void __launch_bounds__(1024) k_batched(DevMesh m, DevScene sc, BatchArgs A) {
+  extern __shared__ double smem[];
+  batched_body<D, T, MODE>(m, sc, A, smem, (int)blockIdx.x, (int)gridDim.x);
+}
+
+// ---------------------------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------------------------
+struct BatchedState {
+  std::vector<void*> allocs;
+  int32_t *order = nullptr, *voff = nullptr, *eoff = nullptr;
+  DevStats* stats = nullptr;
+  DevStats* hstats = nullptr;  // pinned host mirror
+  int nacc = 0, grid = 0, block = 0, precision = -1, dim = 0;
+  size_t lds = 0;
+};
+
+template <int D, typename T, int MODE>
+static void* kernel_ptr() {
+  return reinterpret_cast<void*>(&k_batched<D, T, MODE>);
+}
+
+static void* pick_kernel(int dim, int precision, int mode) {
+  if (dim == 2) {
+    if (precision == ISB_MIXED) return mode ? kernel_ptr<2, float, 1>() : kernel_ptr<2, float, 0>();
+    return mode ? kernel_ptr<2, double, 1>() : kernel_ptr<2, double, 0>();
+  }
+  if (precision == ISB_MIXED) return mode ? kernel_ptr<3, float, 1>() : kernel_ptr<3, float, 0>();
+  return mode ? kernel_ptr<3, double, 1>() : kernel_ptr<3, double, 0>();
+}
+
+int64_t batched_lds_bytes(const isb_ctx* c) {
+  int64_t mx = 0;
+  for (int b = 0; b < c->n_bodies; ++b) mx = std::max<int64_t>(mx, (c->voff[b + 1] - c->voff[b]) * c->dim);
+  return (int64_t)(kRedSlots + mx) * (int64_t)sizeof(double);
+}
+
+void batched_release(isb_ctx* c) {
+  auto* st = static_cast<BatchedState*>(c->batched);
+  if (!st) return;
+  for (void* p : st->allocs) (void)hipFree(p);
+  if (st->hstats) (void)hipHostFree(st->hstats);
+  delete st;
+  c->batched = nullptr;
+}
+
 isb_status batched_prepare(isb_ctx* c) {
-  (void)c;
-  return fail(ISB_E_ARG, "batched solver not available");
+  auto* st = static_cast<BatchedState*>(c->batched);
+  if (st && st->block == c->block && st->precision == c->precision && st->dim == c->dim) return ISB_OK;
+  batched_release(c);
+  st = new BatchedState();
+  c->batched = st;
+  const int nb = c->n_bodies;
+  std::vector<int32_t> order(nb), voff(nb + 1), eoff(nb + 1);
+  for (int b = 0; b <= nb; ++b) {
+    voff[b] = (int32_t)c->voff[b];
+    eoff[b] = (int32_t)c->eoff[b];
+  }
+  std::iota(order.begin(), order.end(), 0);
+  // longest processing time first: bodies with more elements start earlier
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return (eoff[a + 1] - eoff[a]) > (eoff[b + 1] - eoff[b]);
+  });
+  auto alloc = [&](void** p, size_t bytes) -> isb_status {
+    ISB_HIP(hipMalloc(p, bytes));
+    st->allocs.push_back(*p);
+    return ISB_OK;
+  };
+  isb_status r;
+  if ((r = alloc((void**)&st->order, nb * 4)) != ISB_OK) return r;
+  if ((r = alloc((void**)&st->voff, (nb + 1) * 4)) != ISB_OK) return r;
+  if ((r = alloc((void**)&st->eoff, (nb + 1) * 4)) != ISB_OK) return r;
+  if ((r = alloc((void**)&st->stats, nb * sizeof(DevStats))) != ISB_OK) return r;
+  ISB_HIP(hipHostMalloc((void**)&st->hstats, nb * sizeof(DevStats), hipHostMallocDefault));
+  ISB_HIP(hipMemcpy(st->order, order.data(), nb * 4, hipMemcpyHostToDevice));
+  ISB_HIP(hipMemcpy(st->voff, voff.data(), (nb + 1) * 4, hipMemcpyHostToDevice));
+  ISB_HIP(hipMemcpy(st->eoff, eoff.data(), (nb + 1) * 4, hipMemcpyHostToDevice));
+  ISB_HIP(hipMemset(st->stats, 0, nb * sizeof(DevStats)));
+  st->lds = (size_t)batched_lds_bytes(c);
+  st->nacc = (int)(st->lds / sizeof(double)) - kRedSlots;
+  st->block = c->block;
+  st->precision = c->precision;
+  st->dim = c->dim;
+  int max_lds = 0, n_cu = 0;
+  ISB_HIP(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
+  ISB_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, c->device));
+  if ((int64_t)st->lds > (int64_t)max_lds)
+    return fail(ISB_E_ARG, "batched solver: the largest body needs " + std::to_string(st->lds) +
+                               " B of LDS, the device allows " + std::to_string(max_lds) + " B per workgroup");
+  int occ = 0;
+  for (int mode = 0; mode < 2; ++mode) {
+    void* k = pick_kernel(c->dim, c->precision, mode);
+    ISB_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)st->lds));
+    int o = 0;
+    ISB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, k, st->block, st->lds));
+    occ = mode == 0 ? o : std::min(occ, o);
+  }
+  if (occ < 1) return fail(ISB_E_ARG, "batched solver: kernel does not fit one workgroup per CU");
+  st->grid = std::min(nb, occ * n_cu);
+  return ISB_OK;
 }
-void batched_release(isb_ctx* c) { (void)c; }
+
+static BatchArgs make_args(isb_ctx* c, BatchedState* st) {
+  BatchArgs A;
+  std::memset(&A, 0, sizeof(A));
+  A.order = st->order;
+  A.voff = st->voff;
+  A.eoff = st->eoff;
+  A.n_bodies = c->n_bodies;
+  A.a32 = c->w_a32;
+  A.xhat = c->w_xhat;
+  A.G = c->w_G;
+  A.Gt = c->w_Gt;
+  A.dx = c->w_xs;
+  A.r = c->w_r;
+  A.p = c->w_p;
+  A.Dinvp = c->w_Dinvp;
+  A.vdiag = c->w_vdiag;
+  A.cv = c->w_cv;
+  A.stats = st->stats;
+  A.tol = c->scene.tol_rel;
+  A.adj_tol = c->scene.adj_tol_rel;
+  A.max_newton = c->scene.max_newton;
+  A.max_cg = c->scene.max_cg;
+  A.nacc = st->nacc;
+  return A;
+}
+
+static isb_status launch(isb_ctx* c, BatchedState* st, hipStream_t s, int mode, const BatchArgs& A) {
+  void* k = pick_kernel(c->dim, c->precision, mode);
+  const DevMesh m = devmesh(c);
+  const DevScene sc = devscene(c);
+  void* args[] = {(void*)&m, (void*)&sc, (void*)&A};
+  ISB_HIP(hipLaunchKernel(k, dim3(st->grid), dim3(st->block), args, st->lds, s));
+  return ISB_OK;
+}
+
+static isb_status collect(isb_ctx* c, BatchedState* st, hipStream_t s, isb_stats* per_body, int mode) {
+  if (c->graph_safe && !per_body) return ISB_OK;
+  ISB_HIP(hipMemcpyAsync(st->hstats, st->stats, c->n_bodies * sizeof(DevStats), hipMemcpyDeviceToHost, s));
+  ISB_HIP(hipStreamSynchronize(s));
+  if (per_body) std::memcpy(per_body, st->hstats, c->n_bodies * sizeof(DevStats));
+  for (int b = 0; b < c->n_bodies; ++b) {
+    const DevStats& d = st->hstats[b];
+    if (d.flags & ISB_FLAG_NONFINITE)
+      return fail(ISB_E_NONFINITE, "body " + std::to_string(b) + ": non-finite value in the solve");
+    if (mode == 0 && !(d.flags & (ISB_FLAG_CONVERGED | ISB_FLAG_STAGNATED)))
+      return fail(ISB_E_NOT_CONVERGED, "body " + std::to_string(b) + ": Newton iteration cap reached");
+    if (mode == 1 && !(d.flags & ISB_FLAG_ADJ_CONVERGED))
+      return fail(ISB_E_NOT_CONVERGED, "body " + std::to_string(b) + ": adjoint CG did not converge");
+  }
+  return ISB_OK;
+}
+
 isb_status batched_step(isb_ctx* c, hipStream_t s, const double* x0, const double* v0, const double* a, double* x1,
-                        double* v1, isb_stats* stats) {
-  (void)c; (void)s; (void)x0; (void)v0; (void)a; (void)x1; (void)v1; (void)stats;
-  return fail(ISB_E_ARG, "batched solver not available");
+                        double* v1, isb_stats* per_body) {
+  isb_status r = batched_prepare(c);
+  if (r != ISB_OK) return r;
+  auto* st = static_cast<BatchedState*>(c->batched);
+  if (c->precision == ISB_MIXED) launch_to_f32(c->n_e, a, c->w_a32, s);
+  BatchArgs A = make_args(c, st);
+  A.x0 = x0;
+  A.v0 = v0;
+  A.a = a;
+  A.x1 = x1;
+  A.v1 = v1;
+  A.want_tail = per_body != nullptr;
+  if ((r = launch(c, st, s, 0, A)) != ISB_OK) return r;
+  ISB_HIP(hipGetLastError());
+  return collect(c, st, s, per_body, 0);
 }
+
 isb_status batched_adjoint(isb_ctx* c, hipStream_t s, const double* x1, const double* x0, const double* a,
-                           const double* x1_bar, const double* v1_bar, double* w, isb_stats* stats) {
-  (void)c; (void)s; (void)x1; (void)x0; (void)a; (void)x1_bar; (void)v1_bar; (void)w; (void)stats;
-  return fail(ISB_E_ARG, "batched solver not available");
+                           const double* x1_bar, const double* v1_bar, double* w, isb_stats* per_body) {
+  isb_status r = batched_prepare(c);
+  if (r != ISB_OK) return r;
+  auto* st = static_cast<BatchedState*>(c->batched);
+  if (c->precision == ISB_MIXED) launch_to_f32(c->n_e, a, c->w_a32, s);
+  BatchArgs A = make_args(c, st);
+  A.x0 = x0;
+  A.a = a;
+  A.x1 = const_cast<double*>(x1);
+  A.xbar = x1_bar;
+  A.vbar = v1_bar;
+  A.w = w;
+  if ((r = launch(c, st, s, 1, A)) != ISB_OK) return r;
+  ISB_HIP(hipGetLastError());
+  return collect(c, st, s, per_body, 1);
 }
-int64_t batched_lds_bytes(const isb_ctx* c) { (void)c; return 0; }
 
 }  // namespace isb

@@ -1,0 +1,583 @@
+// Body-level logic of the batched persistent solver, shared by the gfx950 kernel and by a
+// CPU build used in tests (a workgroup emulated with host threads).
+//
+// One workgroup solves one body at a time, dealt statically from the bodies sorted largest
+// first (see queue_position). Inside a body: Newton's method on the step
+// objective (Eq. 1 / Eq. 14) with a Jacobi-preconditioned CG inner solve, an Armijo line search
+// on element-wise energy differences, and v1 = (x1 - x0)/h; or, for the adjoint, one CG solve
+// of Eq. 9 at x1. The element scatter (gradient, Hessian diagonal, Hessian-vector product,
+// Eq. 10) accumulates into the body's vertex array in LDS with FP64 LDS atomics; each thread
+// owns the DOFs i = tid + k * blockDim of the body in every vector operation, so vector passes
+// need no synchronisation beyond the workgroup reductions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <type_traits>
+
+#include "../../include/isb.h"
+#include "isb_device.hpp"
+#include "isb_elem.hpp"
+#include "isb_internal.hpp"
+
+namespace isb {
+
+// Same layout as isb_stats.
+struct DevStats {
+  int32_t newton_iters, cg_iters, adj_cg_iters, ls_backtracks, negcurv_exits, flags;
+  double res0, res_final, adj_res_final, energy, min_J, max_J;
+};
+static_assert(sizeof(DevStats) == sizeof(isb_stats), "stats layout");
+
+struct BatchArgs {
+  const int32_t* order;  // bodies, largest first
+  const int32_t* voff;   // [n_bodies+1]
+  const int32_t* eoff;   // [n_bodies+1]
+  int n_bodies;
+  const double *x0, *v0, *a;
+  const float* a32;
+  double *x1, *v1;               // step outputs (x1 is also the Newton iterate)
+  const double *xbar, *vbar;     // adjoint right-hand side
+  double* w;                     // adjoint output
+  double *xhat, *G, *Gt, *dx, *r, *p, *Dinvp, *vdiag, *cv;  // workspaces
+  DevStats* stats;
+  double tol, adj_tol;
+  int max_newton, max_cg;
+  int want_tail;  // 1: final energy and min/max J into the stats
+  int nacc;       // LDS accumulator length: the largest body's DOF count
+};
+
+constexpr int kRedSlots = 16 * 4;  // up to 16 waves x 4 values
+
+// Values that steer control flow around barriers (the work-queue index, reduction results)
+// are read from LDS into vector registers, so the compiler cannot prove them uniform and would
+// structurize the loops around them as divergent, letting lanes loop back past the work-queue
+// fetch. Broadcasting them from the first active lane makes the branches scalar.
+__device__ __forceinline__ int wg_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ double wg_uniform(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll));
+  const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// sum of N values over the workgroup; every thread receives the same bits
+template <int N>
+__device__ __forceinline__ void wg_sum(double (&v)[N], double* red) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int k = 0; k < N; ++k) v[k] = wave_sum(v[k]);
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < N; ++k) red[wid * N + k] = v[k];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += red[w * N + k];
+    v[k] = wg_uniform(s);
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ double wg_sum1(double v, double* red) {
+  double t[1] = {v};
+  wg_sum<1>(t, red);
+  return t[0];
+}
+
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_down(v, o, 64));
+  return v;
+}
+
+// (min, max) over the workgroup, every thread receives the result
+__device__ __forceinline__ void wg_minmax(double& lo, double& hi, double* red) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  lo = wave_min(lo);
+  hi = -wave_min(-hi);
+  if (lane == 0) {
+    red[2 * wid] = lo;
+    red[2 * wid + 1] = hi;
+  }
+  __syncthreads();
+  lo = 1e300;
+  hi = -1e300;
+  for (int w = 0; w < nw; ++w) {
+    lo = fmin(lo, red[2 * w]);
+    hi = fmax(hi, red[2 * w + 1]);
+  }
+  lo = wg_uniform(lo);
+  hi = wg_uniform(hi);
+  __syncthreads();
+}
+
+template <int D, typename T>
+struct BodySolver {
+  const DevMesh& m;
+  const DevScene& sc;
+  const BatchArgs& A;
+  double* acc;  // LDS [n_loc * D], zero between passes
+  double* red;  // LDS reduction slots
+  int v0, v1, e0, e1, n, base;
+
+  __device__ __forceinline__ bool pinned(int i) const { return m.pinned[base + i] != 0; }
+
+  // -------- element passes: scatter into acc (local DOF index = (v - v0) * D + c) --------
+  __device__ __forceinline__ void lds_scatter(const int v[D + 1], const double out[D + 1][D], double scale) {
+#pragma unroll
+    for (int k = 0; k <= D; ++k)
+#pragma unroll
+      for (int c = 0; c < D; ++c) unsafeAtomicAdd(acc + (v[k] - v0) * D + c, scale * out[k][c]);
+  }
+
+  // gradient of the element energies at x + alpha dx (dx may be null)
+  __device__ void pass_grad(const double* x, const double* dxp, double alpha) {
+    for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+      int v[D + 1];
+      load_conn<D>(m, e, v);
+      ElemRest<D, double> R;
+      load_rest<D, double>(m, e, R);
+      double Ds[D][D];
+      if (dxp)
+        gather_edges_step<D>(x, dxp, alpha, v, Ds);
+      else
+        gather_edges<D, double>(x, v, Ds);
+      ElemState<D, double> S;
+      elem_state<D, double>(Ds, R, S);
+      double out[D + 1][D];
+      elem_grad<D, double>(R, S, A.a[e], out);
+      lds_scatter(v, out, sc.s_pot);
+    }
+  }
+
+  __device__ __forceinline__ T act(int e) const {
+    if constexpr (std::is_same<T, double>::value)
+      return A.a[e];
+    else
+      return A.a32[e];
+  }
+
+  __device__ void pass_hv(const double* x, const double* p) {
+    for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+      int v[D + 1];
+      load_conn<D>(m, e, v);
+      ElemRest<D, T> R;
+      load_rest<D, T>(m, e, R);
+      T Ds[D][D], dDs[D][D];
+      gather_edges<D, T>(x, v, Ds);
+      gather_edges<D, T>(p, v, dDs);
+      ElemState<D, T> S;
+      elem_state<D, T>(Ds, R, S);
+      T out[D + 1][D];
+      elem_hessvec<D, T>(R, S, act(e), dDs, out);
+      double o[D + 1][D];
+#pragma unroll
+      for (int k = 0; k <= D; ++k)
+#pragma unroll
+        for (int c = 0; c < D; ++c) o[k][c] = double(out[k][c]);
+      lds_scatter(v, o, sc.s_pot);
+    }
+  }
+
+  __device__ void pass_diag(const double* x) {
+    for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+      int v[D + 1];
+      load_conn<D>(m, e, v);
+      ElemRest<D, T> R;
+      load_rest<D, T>(m, e, R);
+      T Ds[D][D];
+      gather_edges<D, T>(x, v, Ds);
+      ElemState<D, T> S;
+      elem_state<D, T>(Ds, R, S);
+      T out[D + 1][D];
+      elem_hessdiag<D, T>(R, S, act(e), out);
+      double o[D + 1][D];
+#pragma unroll
+      for (int k = 0; k <= D; ++k)
+#pragma unroll
+        for (int c = 0; c < D; ++c) o[k][c] = double(out[k][c]);
+      lds_scatter(v, o, sc.s_pot);
+    }
+  }
+
+  // -------- vertex terms per DOF --------
+  __device__ __forceinline__ double vgrad(int i, double xi) const {
+    const int vg = v0 + i / D, c = i % D;
+    const double mv = m.mass[vg];
+    double g;
+    if (c == 1)
+      g = mv * sc.grav - 2.0 * sc.kc * fmax(-xi, 0.0);
+    else
+      g = 2.0 * sc.kfr * A.cv[vg] / (sc.h * sc.h) * (xi - A.x0[base + i]);
+    g *= sc.s_pot;
+    if (sc.be) g += mv * (xi - A.xhat[base + i]);
+    return g;
+  }
+
+  __device__ __forceinline__ double vhdiag(int i, double xi) const {
+    const int vg = v0 + i / D, c = i % D;
+    double hd = (c == 1) ? (xi < 0.0 ? 2.0 * sc.kc : 0.0) : 2.0 * sc.kfr * A.cv[vg] / (sc.h * sc.h);
+    hd *= sc.s_pot;
+    if (sc.be) hd += m.mass[vg];
+    return hd;
+  }
+
+  // gradient at x + alpha dx into Gout (0 on pinned DOFs); returns |G|^2
+  __device__ double gradient(const double* x, const double* dxp, double alpha, double* Gout) {
+    pass_grad(x, dxp, alpha);
+    __syncthreads();
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      const double xi = dxp ? x[base + i] + alpha * dxp[base + i] : x[base + i];
+      double g = acc[i] + vgrad(i, xi);
+      acc[i] = 0.0;
+      if (pinned(i)) g = 0.0;
+      Gout[base + i] = g;
+      s += g * g;
+    }
+    return wg_sum1(s, red);
+  }
+
+  // Jacobi preconditioner 1/|diag H| and the vertex-term diagonal
+  __device__ void precond(const double* x) {
+    pass_diag(x);
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      const bool pin = pinned(i);
+      const double vd = pin ? 0.0 : vhdiag(i, x[base + i]);
+      const double d = fabs(acc[i] + vd);
+      A.vdiag[base + i] = vd;
+      A.Dinvp[base + i] = pin ? 0.0 : (d > 0.0 ? 1.0 / d : 1.0);
+      acc[i] = 0.0;
+    }
+    __syncthreads();
+  }
+
+  // (sum of g_e(x + alpha dx) - g_e(x), sum |g_e(x)|, g(x + alpha dx)) over elements and vertices
+  __device__ void energy(const double* x, const double* dxp, double alpha, double out[3]) {
+    double sd = 0.0, sa = 0.0, st = 0.0;
+    for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+      int v[D + 1];
+      load_conn<D>(m, e, v);
+      ElemRest<D, double> R;
+      load_rest<D, double>(m, e, R);
+      double Ds[D][D];
+      gather_edges<D, double>(x, v, Ds);
+      ElemState<D, double> S;
+      elem_state<D, double>(Ds, R, S);
+      const double ea = sc.s_pot * elem_energy<D, double>(R, S, A.a[e]);
+      double eb = ea;
+      if (dxp) {
+        gather_edges_step<D>(x, dxp, alpha, v, Ds);
+        elem_state<D, double>(Ds, R, S);
+        eb = sc.s_pot * elem_energy<D, double>(R, S, A.a[e]);
+      }
+      sd += eb - ea;
+      sa += fabs(ea);
+      st += eb;
+    }
+    for (int vl = threadIdx.x; vl < v1 - v0; vl += blockDim.x) {
+      const int vg = v0 + vl;
+      double xa[D], xb[D];
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        xa[c] = x[(size_t)vg * D + c];
+        xb[c] = dxp ? xa[c] + alpha * dxp[(size_t)vg * D + c] : xa[c];
+      }
+      const double ea = vertex_energy<D>(m, sc, vg, xa, A.x0, A.xhat, A.cv);
+      const double eb = vertex_energy<D>(m, sc, vg, xb, A.x0, A.xhat, A.cv);
+      sd += eb - ea;
+      sa += fabs(ea);
+      st += eb;
+    }
+    double t[3] = {sd, sa, st};
+    wg_sum<3>(t, red);
+    out[0] = t[0];
+    out[1] = t[1];
+    out[2] = t[2];
+  }
+
+  __device__ void minmax_J(const double* x, double& lo, double& hi) {
+    lo = 1e300;
+    hi = -1e300;
+    for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+      int v[D + 1];
+      load_conn<D>(m, e, v);
+      ElemRest<D, double> R;
+      load_rest<D, double>(m, e, R);
+      double Ds[D][D];
+      gather_edges<D, double>(x, v, Ds);
+      ElemState<D, double> S;
+      elem_state<D, double>(Ds, R, S);
+      lo = fmin(lo, S.J);
+      hi = fmax(hi, S.J);
+    }
+    wg_minmax(lo, hi, red);
+  }
+
+  // PCG on H(x) xs = sign * rhs (masked to the free DOFs); returns the final r.r
+  __device__ double cg(const double* x, const double* rhs, double sign, double tol, int maxit, double* xs, int& iters,
+                       bool& neg) {
+    double* r = A.r;
+    double* p = A.p;
+    const double* Dv = A.Dinvp;
+    const double* vd = A.vdiag;
+    double rz = 0.0, rr = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      const int g = base + i;
+      const double di = Dv[g];
+      const double ri = di != 0.0 ? sign * rhs[g] : 0.0;
+      const double zi = di * ri;
+      r[g] = ri;
+      p[g] = zi;
+      xs[g] = 0.0;
+      rz += ri * zi;
+      rr += ri * ri;
+    }
+    {
+      double t[2] = {rz, rr};
+      wg_sum<2>(t, red);
+      rz = t[0];
+      rr = t[1];
+    }
+    iters = 0;
+    neg = false;
+    const double tol2 = tol * tol;
+    if (rr <= tol2) return rr;
+    for (int it = 0; it < maxit; ++it) {
+      pass_hv(x, p);
+      __syncthreads();
+      double pHp = 0.0;
+      for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const int g = base + i;
+        const double hp = acc[i] + vd[g] * p[g];
+        acc[i] = hp;
+        pHp += p[g] * hp;
+      }
+      pHp = wg_sum1(pHp, red);
+      if (!(pHp > 0.0)) {
+        // non-positive curvature: stop; on the first iteration keep the preconditioned
+        // steepest-descent direction (Nocedal & Wright, Alg. 7.1)
+        neg = true;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+          if (it == 0) xs[base + i] = p[base + i];
+          acc[i] = 0.0;
+        }
+        __syncthreads();
+        break;
+      }
+      const double alpha = rz / pHp;
+      double rz1 = 0.0;
+      rr = 0.0;
+      for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const int g = base + i;
+        xs[g] += alpha * p[g];
+        const double di = Dv[g];
+        const double ri = di != 0.0 ? r[g] - alpha * acc[i] : 0.0;
+        r[g] = ri;
+        acc[i] = 0.0;
+        rz1 += ri * di * ri;
+        rr += ri * ri;
+      }
+      {
+        double t[2] = {rz1, rr};
+        wg_sum<2>(t, red);
+        rz1 = t[0];
+        rr = t[1];
+      }
+      iters = it + 1;
+      if (rr <= tol2) break;
+      const double beta = rz1 / rz;
+      rz = rz1;
+      for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const int g = base + i;
+        p[g] = Dv[g] * r[g] + beta * p[g];
+      }
+      __syncthreads();
+    }
+    return rr;
+  }
+
+  // -------- the forward step of one body --------
+  __device__ void step(DevStats& st) {
+    double* x = A.x1;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      const int g = base + i;
+      const double xh = (sc.be && A.v0) ? A.x0[g] + sc.h * A.v0[g] : A.x0[g];
+      A.xhat[g] = xh;
+      x[g] = pinned(i) ? A.x0[g] : xh;
+    }
+    for (int vl = threadIdx.x; vl < v1 - v0; vl += blockDim.x)
+      A.cv[v0 + vl] = fmax(-A.x0[(size_t)(v0 + vl) * D + 1] + sc.eps, 0.0);
+    __syncthreads();
+    double* G = A.G;
+    double* Gt = A.Gt;
+    double* dx = A.dx;
+    const double res0 = sqrt(gradient(x, nullptr, 0.0, G));
+    double res = res0;
+    st.res0 = res0;
+    if (!isfinite(res0)) st.flags |= ISB_FLAG_NONFINITE;
+    while (isfinite(res)) {
+      if (res <= A.tol * res0 || res == 0.0) {
+        st.flags |= ISB_FLAG_CONVERGED;
+        break;
+      }
+      if (st.newton_iters >= A.max_newton) break;
+      precond(x);
+      const double eta = fmin(0.5, sqrt(res / res0));
+      int it = 0;
+      bool neg = false;
+      cg(x, G, -1.0, eta * res, A.max_cg, dx, it, neg);
+      st.cg_iters += it;
+      st.negcurv_exits += neg ? 1 : 0;
+      double gTd = 0.0;
+      for (int i = threadIdx.x; i < n; i += blockDim.x) gTd += G[base + i] * dx[base + i];
+      gTd = wg_sum1(gTd, red);
+      if (!(gTd < 0.0)) {
+        gTd = 0.0;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+          const double d = -A.Dinvp[base + i] * G[base + i];
+          dx[base + i] = d;
+          gTd += G[base + i] * d;
+        }
+        gTd = wg_sum1(gTd, red);
+        if (!(gTd < 0.0)) {
+          st.flags |= ISB_FLAG_STAGNATED;
+          break;
+        }
+      }
+      double alpha = 1.0;
+      bool accepted = false, via_grad = false;
+      for (int ls = 0; ls <= 30; ++ls) {
+        double en[3];
+        energy(x, dx, alpha, en);
+        if (isfinite(en[0])) {
+          if (en[0] <= 1e-4 * alpha * gTd) {
+            accepted = true;
+          } else if (fabs(en[0]) <= 1e3 * 2.220446049250313e-16 * en[1]) {
+            // below the FP64 resolution of g: accept on a decrease of |grad g| instead
+            const double rt = sqrt(gradient(x, dx, alpha, Gt));
+            if (rt < res) {
+              accepted = via_grad = true;
+              double* tmp = G;
+              G = Gt;
+              Gt = tmp;
+              res = rt;
+            }
+          }
+        }
+        if (accepted) break;
+        alpha *= 0.5;
+        st.ls_backtracks += 1;
+      }
+      if (!accepted) {
+        st.flags |= ISB_FLAG_STAGNATED;
+        break;
+      }
+      for (int i = threadIdx.x; i < n; i += blockDim.x) x[base + i] += alpha * dx[base + i];
+      __syncthreads();
+      if (!via_grad) res = sqrt(gradient(x, nullptr, 0.0, G));
+      st.newton_iters += 1;
+    }
+    if (!isfinite(res)) st.flags |= ISB_FLAG_NONFINITE;
+    st.res_final = res;
+    if (res <= A.tol * res0) st.flags |= ISB_FLAG_CONVERGED;
+    if (sc.be && A.v1)
+      for (int i = threadIdx.x; i < n; i += blockDim.x)
+        A.v1[base + i] = (x[base + i] - A.x0[base + i]) / sc.h;
+    if (A.want_tail) {
+      double en[3];
+      energy(x, nullptr, 0.0, en);
+      st.energy = en[2];
+      minmax_J(x, st.min_J, st.max_J);
+    }
+    __syncthreads();
+  }
+
+  // -------- the adjoint solve of one body (Eq. 9) --------
+  __device__ void adjoint(DevStats& st) {
+    const double* x = A.x1;
+    for (int vl = threadIdx.x; vl < v1 - v0; vl += blockDim.x)
+      A.cv[v0 + vl] = fmax(-A.x0[(size_t)(v0 + vl) * D + 1] + sc.eps, 0.0);
+    double bb = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      const int g = base + i;
+      double rhs = A.xbar[g];
+      if (sc.be && A.vbar) rhs += A.vbar[g] / sc.h;
+      if (pinned(i)) rhs = 0.0;
+      A.G[g] = rhs;
+      bb += rhs * rhs;
+    }
+    bb = wg_sum1(bb, red);  // its barriers also publish cv
+    const double bnorm = sqrt(bb);
+    int it = 0;
+    bool neg = false;
+    double rr = 0.0;
+    if (!isfinite(bnorm)) {
+      st.flags |= ISB_FLAG_NONFINITE;
+    } else if (bnorm == 0.0) {
+      for (int i = threadIdx.x; i < n; i += blockDim.x) A.w[base + i] = 0.0;
+    } else {
+      precond(x);
+      rr = cg(x, A.G, 1.0, A.adj_tol * bnorm, A.max_cg, A.w, it, neg);
+    }
+    st.adj_cg_iters = it;
+    st.adj_res_final = bnorm > 0.0 ? sqrt(rr) / bnorm : 0.0;
+    if (!neg && st.adj_res_final <= A.adj_tol) st.flags |= ISB_FLAG_ADJ_CONVERGED;
+    __syncthreads();
+  }
+};
+
+// Workgroup g solves the bodies at positions g, 2G-1-g, 2G+g, 4G-1-g, ... of the largest-first
+// order (G = number of workgroups): each round deals one body per workgroup, alternating the
+// direction, so heavy and light bodies pair up (a static approximation of longest-processing-
+// time scheduling). Every quantity in this loop is scalar, so the loop and its barriers stay
+// uniform.
+__device__ __forceinline__ int queue_position(int round, int g, int G) {
+  return round * G + ((round & 1) ? (G - 1 - g) : g);
+}
+
+template <int D, typename T, int MODE>  // MODE 0: step, 1: adjoint
+__device__ void batched_body(const DevMesh& m, const DevScene& sc, const BatchArgs& A, double* smem, int g, int G) {
+  double* red = smem;
+  double* acc = smem + kRedSlots;
+  // the accumulator starts at zero; every pass clears the entries it used
+  for (int i = threadIdx.x; i < A.nacc; i += blockDim.x) acc[i] = 0.0;
+  __syncthreads();
+  for (int round = 0; round * G < A.n_bodies; ++round) {
+    const int k = queue_position(round, g, G);
+    if (k >= A.n_bodies) continue;
+    const int body = wg_uniform(A.order[k]);
+    const int bv0 = wg_uniform(A.voff[body]), bv1 = wg_uniform(A.voff[body + 1]);
+    const int be0 = wg_uniform(A.eoff[body]), be1 = wg_uniform(A.eoff[body + 1]);
+    BodySolver<D, T> S{m, sc, A, acc, red, bv0, bv1, be0, be1, (bv1 - bv0) * D, bv0 * D};
+    DevStats st;
+    memset(&st, 0, sizeof(st));
+    if (MODE == 0)
+      S.step(st);
+    else
+      S.adjoint(st);
+    if (threadIdx.x == 0) {
+      DevStats& o = A.stats[body];
+      if (MODE == 0) {
+        const int adj = o.adj_cg_iters;
+        const double ares = o.adj_res_final;
+        const int aflag = o.flags & ISB_FLAG_ADJ_CONVERGED;
+        o = st;
+        o.adj_cg_iters = adj;
+        o.adj_res_final = ares;
+        o.flags |= aflag;
+      } else {
+        o.adj_cg_iters = st.adj_cg_iters;
+        o.adj_res_final = st.adj_res_final;
+        o.flags = (o.flags & ~ISB_FLAG_ADJ_CONVERGED) | st.flags;
+      }
+    }
+  }
+}
+
+}  // namespace isb

@@ -1,0 +1,154 @@
+"""ctypes driver of the CPU-emulated batched solver (tests/emu/batched_emu.cpp).
+
+Builds libisb_emu.so with g++ on first use (into tests/emu/_build, git-ignored) and runs
+isb_body.hpp's body logic with host threads as one workgroup. Test infrastructure only: it
+checks the persistent solver's control flow and arithmetic on the CPU; the GPU tests check
+the same code on the device.
+"""
+import ctypes
+import math
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+CSRC = os.path.join(ROOT, "paper_2102_05791_amd", "csrc")
+OUT = os.path.join(HERE, "_build", "libisb_emu.so")
+SRCS = [os.path.join(HERE, "batched_emu.cpp"), os.path.join(CSRC, "isb_body.hpp"),
+        os.path.join(CSRC, "isb_elem.hpp"), os.path.join(CSRC, "isb_device.hpp"),
+        os.path.join(HERE, "include", "hip", "hip_runtime.h")]
+
+vp, ci, cd = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+
+
+class DevMesh(ctypes.Structure):
+    _fields_ = [("dim", ci), ("n_v", ci), ("n_e", ci), ("conn", vp), ("Dinv", vp), ("gf", vp), ("W", vp),
+                ("wmu", vp), ("wlam", vp), ("wkf", vp), ("Dinv32", vp), ("gf32", vp), ("wmu32", vp),
+                ("wlam32", vp), ("wkf32", vp), ("mass", vp), ("pinned", vp)]
+
+
+class DevScene(ctypes.Structure):
+    _fields_ = [("be", ci), ("h", cd), ("s_pot", cd), ("grav", cd), ("kc", cd), ("kfr", cd), ("eps", cd)]
+
+
+class BatchArgs(ctypes.Structure):
+    _fields_ = [("order", vp), ("voff", vp), ("eoff", vp), ("n_bodies", ci),
+                ("x0", vp), ("v0", vp), ("a", vp), ("a32", vp), ("x1", vp), ("v1", vp), ("xbar", vp),
+                ("vbar", vp), ("w", vp), ("xhat", vp), ("G", vp), ("Gt", vp), ("dx", vp), ("r", vp), ("p", vp),
+                ("Dinvp", vp), ("vdiag", vp), ("cv", vp), ("stats", vp), ("tol", cd), ("adj_tol", cd),
+                ("max_newton", ci), ("max_cg", ci), ("want_tail", ci), ("nacc", ci)]
+
+
+STATS_DTYPE = np.dtype([("newton_iters", "<i4"), ("cg_iters", "<i4"), ("adj_cg_iters", "<i4"),
+                        ("ls_backtracks", "<i4"), ("negcurv_exits", "<i4"), ("flags", "<i4"),
+                        ("res0", "<f8"), ("res_final", "<f8"), ("adj_res_final", "<f8"), ("energy", "<f8"),
+                        ("min_J", "<f8"), ("max_J", "<f8")])
+
+
+def build():
+    os.makedirs(os.path.dirname(OUT), exist_ok=True)
+    if os.path.exists(OUT) and all(os.path.getmtime(OUT) >= os.path.getmtime(s) for s in SRCS):
+        return OUT
+    cmd = ["g++", "-std=c++20", "-O1", "-fPIC", "-shared", "-pthread", "-I", os.path.join(HERE, "include"),
+           "-I", CSRC, SRCS[0], "-o", OUT + ".tmp"]
+    subprocess.run(cmd, check=True, capture_output=True, text=True)
+    os.replace(OUT + ".tmp", OUT)
+    return OUT
+
+
+def _p(a):
+    return a.ctypes.data_as(vp)
+
+
+class EmuBatch:
+    """Host arrays laid out exactly as the device arrays of the library (SoA element data)."""
+
+    def __init__(self, w, precision="fp64"):
+        self.lib = ctypes.CDLL(build())
+        sizes = (ci * 4)()
+        self.lib.emu_sizes(sizes)
+        assert list(sizes) == [ctypes.sizeof(DevMesh), ctypes.sizeof(DevScene), ctypes.sizeof(BatchArgs), 72]
+        self.w = w
+        d = w.dim
+        self.prec = 1 if precision == "mixed" else 0
+        X, T = w.X, w.T.astype(np.int64)
+        Dm = np.swapaxes(X[T[:, 1:]] - X[T[:, :1]], 1, 2)
+        Dinv = np.linalg.inv(Dm)
+        W = np.linalg.det(Dm) / math.factorial(d)
+        gf = np.einsum("ejc,ec->ej", Dinv, w.fdir)
+        self.keep = []
+
+        def k(a):
+            a = np.ascontiguousarray(a)
+            self.keep.append(a)
+            return a
+        self.conn = k(np.ascontiguousarray(w.T.T, dtype=np.int32))
+        self.Dinv = k(Dinv.reshape(len(T), d * d).T.astype(np.float64))
+        self.gf = k(gf.T.astype(np.float64))
+        self.W = k(W)
+        self.wmu, self.wlam, self.wkf = k(W * w.mu), k(W * w.lam), k(W * w.kf)
+        mass = np.zeros(w.n_v)
+        np.add.at(mass, T, (w.rho * W / (d + 1))[:, None])
+        self.mass = k(mass)
+        self.pinned = k(w.pinned.astype(np.uint8))
+        f32 = lambda a: k(a.astype(np.float32))
+        self.m = DevMesh(d, w.n_v, w.n_e, _p(self.conn), _p(self.Dinv), _p(self.gf), _p(self.W), _p(self.wmu),
+                         _p(self.wlam), _p(self.wkf), _p(f32(self.Dinv)), _p(f32(self.gf)), _p(f32(self.wmu)),
+                         _p(f32(self.wlam)), _p(f32(self.wkf)), _p(self.mass), _p(self.pinned))
+        sc = w.scene
+        be = sc["integrator"] == "be"
+        self.sc = DevScene(int(be), sc["h"], sc["h"] ** 2 if be else 1.0, sc["gravity"], sc["k_contact"],
+                           sc["k_friction"], sc["eps_friction"])
+        nb = w.n_bodies
+        ne_b = np.diff(w.body_e_off)
+        self.order = k(np.argsort(-ne_b, kind="stable").astype(np.int32))
+        self.voff = k(w.body_v_off.astype(np.int32))
+        self.eoff = k(w.body_e_off.astype(np.int32))
+        self.nacc = int((np.diff(w.body_v_off) * d).max())
+        nd = w.n_v * d
+        self.ws = {n: k(np.zeros(nd)) for n in ("xhat", "G", "Gt", "dx", "r", "p", "Dinvp", "vdiag")}
+        self.cv = k(np.zeros(w.n_v))
+        self.stats = k(np.zeros(nb, dtype=STATS_DTYPE))
+        self.be = be
+
+    def _args(self, **kw):
+        A = BatchArgs()
+        sc = self.w.scene
+        A.order, A.voff, A.eoff = _p(self.order), _p(self.voff), _p(self.eoff)
+        A.n_bodies = self.w.n_bodies
+        for n in ("xhat", "G", "Gt", "dx", "r", "p", "Dinvp", "vdiag"):
+            setattr(A, n, _p(self.ws[n]))
+        A.cv = _p(self.cv)
+        A.stats = _p(self.stats)
+        A.tol, A.adj_tol = sc["tol_rel"], sc["adj_tol_rel"]
+        A.max_newton, A.max_cg = sc["max_newton"], sc["max_cg"]
+        A.nacc = self.nacc
+        for key, val in kw.items():
+            setattr(A, key, val)
+        return A
+
+    def step(self, x0, v0, a, block=128, want_tail=1):
+        x0 = np.ascontiguousarray(x0, dtype=np.float64)
+        v0 = np.ascontiguousarray(v0, dtype=np.float64)
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        a32 = a.astype(np.float32)
+        x1 = np.zeros_like(x0)
+        v1 = np.zeros_like(x0)
+        A = self._args(x0=_p(x0), v0=_p(v0) if self.be else None, a=_p(a), a32=_p(a32), x1=_p(x1),
+                       v1=_p(v1) if self.be else None, want_tail=want_tail)
+        self.lib.emu_batched(self.w.dim, self.prec, 0, block, ctypes.byref(self.m), ctypes.byref(self.sc),
+                             ctypes.byref(A))
+        return x1, (v1 if self.be else None), self.stats.copy()
+
+    def adjoint(self, x1, x0, a, xbar, vbar=None, block=128):
+        arrs = [np.ascontiguousarray(v, dtype=np.float64) for v in (x1, x0, a, xbar)]
+        vb = None if vbar is None else np.ascontiguousarray(vbar, dtype=np.float64)
+        a32 = arrs[2].astype(np.float32)
+        wv = np.zeros_like(arrs[0])
+        A = self._args(x1=_p(arrs[0]), x0=_p(arrs[1]), a=_p(arrs[2]), a32=_p(a32), xbar=_p(arrs[3]),
+                       vbar=None if vb is None else _p(vb), w=_p(wv))
+        self.lib.emu_batched(self.w.dim, self.prec, 1, block, ctypes.byref(self.m), ctypes.byref(self.sc),
+                             ctypes.byref(A))
+        return wv, self.stats.copy()

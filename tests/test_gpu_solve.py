@@ -125,3 +125,54 @@ def test_error_paths():
     with pytest.raises(IsbError) as e:
         fresh.set_option(isb.OPT_BLOCK, 100)
     assert e.value.status == isb.ISB_E_ARG
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 1e-5)])
+def test_batched_step_and_adjoint_parity(dim, precision, tol):
+    """Bodies of uneven size in one persistent launch; each body against its own oracle solve."""
+    shape = (10, 3) if dim == 2 else (3, 3, 2)
+    w, rng = rand_workload(dim, seed=11, bodies=4, shape=shape)
+    w = _tight(w)
+    ctx = _ctx(w, precision=precision, solver=1)
+    a = w.actions[0]
+    x1, v1, st, _ = ctx.step(_dev(w.x0), _dev(w.v0), _dev(a))
+    x1, v1 = x1.cpu().numpy(), v1.cpu().numpy()
+    xbar = rng.normal(size=x1.shape)
+    vbar = rng.normal(size=x1.shape)
+    for b, p in enumerate(problems(w)):
+        sv = slice(w.body_v_off[b], w.body_v_off[b + 1])
+        se = slice(w.body_e_off[b], w.body_e_off[b + 1])
+        xr, vr, sr = solve.step(p, w.x0[sv], w.v0[sv], a[se], tol=1e-13)
+        print(b, "oracle", sr["newton_iters"], "gpu", st[b])
+        assert rel(x1[sv] - w.x0[sv], xr - w.x0[sv]) <= tol
+        assert rel(v1[sv], vr) <= tol
+    # adjoint at the oracle's x1 so that only the adjoint is compared
+    xs = np.concatenate([solve.step(p, w.x0[slice(w.body_v_off[b], w.body_v_off[b + 1])],
+                                    w.v0[slice(w.body_v_off[b], w.body_v_off[b + 1])],
+                                    a[slice(w.body_e_off[b], w.body_e_off[b + 1])], tol=1e-13)[0]
+                         for b, p in enumerate(problems(w))])
+    wg, st, _ = ctx.solve_adjoint(_dev(xs), _dev(w.x0), _dev(a), _dev(xbar), _dev(vbar))
+    wg = wg.cpu().numpy()
+    for b, p in enumerate(problems(w)):
+        sv = slice(w.body_v_off[b], w.body_v_off[b + 1])
+        se = slice(w.body_e_off[b], w.body_e_off[b + 1])
+        wr = solve.adjoint(p, xs[sv], w.x0[sv], a[se], xbar[sv], vbar[sv])
+        print(b, "adjoint", st[b]["adj_cg_iters"], st[b]["adj_res_final"])
+        assert rel(wg[sv], wr) <= tol
+
+
+def test_batched_matches_plain_per_body():
+    """A body solved inside the batch equals the same body solved alone by the plain path."""
+    w, rng = rand_workload(2, seed=12, bodies=3, shape=(12, 4))
+    ctxb = _ctx(w, solver=1)
+    ctxp = _ctx(w, solver=0)
+    a = w.actions[1]
+    xb, vb, sb, _ = ctxb.step(_dev(w.x0), _dev(w.v0), _dev(a))
+    xp, vp, sp, _ = ctxp.step(_dev(w.x0), _dev(w.v0), _dev(a))
+    d = xb.cpu().numpy() - xp.cpu().numpy()
+    scale = np.linalg.norm(xp.cpu().numpy() - w.x0)
+    # both stop at the 1e-6 relative residual, along different rounding paths
+    assert np.linalg.norm(d) <= 1e-4 * scale
+    for s in sb:
+        assert s["flags"] & 1 and s["res_final"] <= 1e-6 * s["res0"]
