@@ -1,0 +1,285 @@
+#!/usr/bin/env python
+"""Benchmark: Newton-CG body-steps/sec, forward step + adjoint, on the batched-strips workload.
+
+One bench step = one full backprop-through-time pass over the batch: 512 strips of uneven size
+(4s x s quads, s ~ U{4..32}, 128 to 8192 triangles), 50 backward-Euler steps forward
+(isb_step, Newton-PCG to 1e-6 relative residual), then 50 adjoint solves (isb_solve_adjoint,
+CG to 1e-6) and parameter VJPs (isb_vjp_params) backward, loss = -sum of the bodies' centre of
+mass x. value = bodies x steps / seconds for the batched mixed-precision persistent solver.
+Beside it: the plain single-body FP64 GPU path on a stratified body subset, the FP64 CPU
+oracle on a bounded sample, the error against the oracle on sampled bodies, and the roofline
+of the dominant kernel (the persistent step launch), timed with HIP events on the stream the
+library launches on.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+# the oracle leg is timed single-threaded
+for _v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+    os.environ.setdefault(_v, "1")
+
+import numpy as np  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "Newton-CG steps/sec fwd+adjoint, batched FP32/64 vs plain FP64, 1e-6 residual"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3, help="timed bench steps (full BPTT passes)")
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--bodies", type=int, default=512)
+    ap.add_argument("--rollout", type=int, default=50, help="time steps per BPTT pass")
+    ap.add_argument("--plain-bodies", type=int, default=32, help="stratified subset for the plain FP64 path")
+    ap.add_argument("--plain-steps", type=int, default=2)
+    ap.add_argument("--cpu-bodies", type=int, default=6)
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--block", type=int, default=0, help="batched workgroup size (0 = library default)")
+    ap.add_argument("--profile", action="store_true", help="one untimed pass only (for rocprofv3)")
+    return ap.parse_args()
+
+
+# ---------------------------------------------------------------------------------------------
+# algorithmic bytes (minimal traffic: every array element moved once per pass)
+# ---------------------------------------------------------------------------------------------
+def elem_bytes(dim, word):
+    """conn + Dm^-1 + fibre vector + W mu, W lam, W k_f + actuation, per element."""
+    return 4 * (dim + 1) + word * (dim * dim + dim + 3 + 1)
+
+
+def step_launch_bytes(dim, ne, nv, st, word_hv):
+    """Algorithmic bytes of one body in one step launch, from its solver statistics."""
+    dof = nv * dim
+    eh, e64 = elem_bytes(dim, word_hv), elem_bytes(dim, 8)
+    cg = eh * ne + 72 * dof                     # Hv pass + p, r, dx, D^-1, vdiag, x vector traffic
+    newton = 2 * e64 * ne + eh * ne + 128 * dof  # gradient, preconditioner, energy + vector passes
+    ls = e64 * ne + 32 * dof                     # each extra line-search trial
+    setup = 56 * dof + 16 * nv
+    return (st["cg_iters"] * cg + st["newton_iters"] * newton + st["ls_backtracks"] * ls + setup
+            + e64 * ne + 32 * dof)             # initial gradient
+
+
+def adjoint_launch_bytes(dim, ne, nv, st, word_hv):
+    dof = nv * dim
+    eh = elem_bytes(dim, word_hv)
+    return st["adj_cg_iters"] * (eh * ne + 72 * dof) + eh * ne + 48 * dof
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}). "
+              "Bodies are independent, so a multi-GPU run would shard them across processes; "
+              "see the sharding note in DESIGN.md.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2102_05791_amd import Context, isb
+    from synth import scenes
+    from synth.meshes import concat_bodies
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    T = args.rollout
+    w = scenes.batched_strips(args.bodies, steps=T)
+    nb = w.n_bodies
+    ctx = Context.from_workload(w, precision="mixed", solver=1)
+    if args.block:
+        ctx.set_option(isb.OPT_BLOCK, args.block)
+    ctx.set_option(isb.OPT_GRAPH_SAFE, 1)
+    x0 = torch.tensor(w.x0, dtype=torch.float64, device=dev)
+    v0 = torch.tensor(w.v0, dtype=torch.float64, device=dev)
+    acts = torch.tensor(w.actions, dtype=torch.float64, device=dev)
+    mass = ctx.mass()
+    body_of_v = torch.tensor(np.repeat(np.arange(nb), np.diff(w.body_v_off)), device=dev)
+    msum = torch.zeros(nb, dtype=torch.float64, device=dev).index_add_(0, body_of_v, mass)
+    xbar_T = torch.zeros_like(x0)
+    xbar_T[:, 0] = -mass / msum[body_of_v]      # L = -sum_b COM_x(body b)
+
+    step_ev, adj_ev = [], []
+
+    def bptt(record=False, stats=False):
+        xs, vs = [x0], [v0]
+        st_f, st_a = [], []
+        for t in range(T):
+            if record:
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+            x1, v1, s, _ = ctx.step(xs[-1], vs[-1], acts[t], stats=stats)
+            if record:
+                e1.record()
+                step_ev.append((e0, e1))
+            xs.append(x1)
+            vs.append(v1)
+            st_f.append(s)
+        xb, vb = xbar_T, torch.zeros_like(x0)
+        a_bar = torch.empty_like(acts)
+        for t in range(T - 1, -1, -1):
+            if record:
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+            wv, s, _ = ctx.solve_adjoint(xs[t + 1], xs[t], acts[t], xb, vb, stats=stats)
+            if record:
+                e1.record()
+                adj_ev.append((e0, e1))
+            out = ctx.vjp_params(wv, xs[t + 1], xs[t], acts[t], vb, want=("a_bar", "x0_bar", "v0_bar"))
+            a_bar[t] = out["a_bar"]
+            xb, vb = out["x0_bar"], out["v0_bar"]
+            st_a.append(s)
+        return xs, a_bar, st_f, st_a
+
+    if args.profile:
+        bptt()
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_pass": "done", "bodies": nb, "rollout": T}))
+        return
+
+    for _ in range(args.warmup):
+        bptt()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        xs, a_bar, _, _ = bptt(record=True)
+        print(f"# timed step {k + 1}/{args.steps} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = 1e3 * wall / args.steps
+    body_steps = nb * T * args.steps
+    value = body_steps / wall
+    step_ms = float(np.mean([a.elapsed_time(b) for a, b in step_ev]))
+    adj_ms = float(np.mean([a.elapsed_time(b) for a, b in adj_ev]))
+
+    # solver statistics of one pass (untimed: statistics force a host read per launch)
+    _, _, st_f, st_a = bptt(stats=True)
+    print("# statistics pass done", file=sys.stderr, flush=True)
+    ne_b, nv_b = np.diff(w.body_e_off), np.diff(w.body_v_off)
+    fb = [sum(step_launch_bytes(2, ne_b[b], nv_b[b], s[b], 4) for b in range(nb)) for s in st_f]
+    ab = [sum(adjoint_launch_bytes(2, ne_b[b], nv_b[b], s[b], 4) for b in range(nb)) for s in st_a]
+    it = {"newton_per_step": float(np.mean([[s["newton_iters"] for s in S] for S in st_f])),
+          "cg_per_step": float(np.mean([[s["cg_iters"] for s in S] for S in st_f])),
+          "adj_cg_per_step": float(np.mean([[s["adj_cg_iters"] for s in S] for S in st_a])),
+          "max_newton": int(np.max([[s["newton_iters"] for s in S] for S in st_f])),
+          "not_converged_steps": int(sum(1 for S in st_f for s in S if not (s["flags"] & 1))),
+          "adj_not_converged": int(sum(1 for S in st_a for s in S if not (s["flags"] & 8)))}
+    dominant = "step" if step_ms >= adj_ms else "adjoint"
+    dom_ms = step_ms if dominant == "step" else adj_ms
+    dom_bytes = float(np.mean(fb if dominant == "step" else ab))
+    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": f"k_batched<2,float,{0 if dominant == 'step' else 1}> ({dominant} launch)",
+                "launch_ms": round(dom_ms, 4), "algorithmic_bytes_per_launch": int(dom_bytes),
+                "step_launch_ms": round(step_ms, 4), "adjoint_launch_ms": round(adj_ms, 4)}
+
+    # error against the oracle on sampled bodies, first step, at the metric's tolerance
+    parity = None
+    try:
+        from oracle import solve as osolve
+        from oracle.fem import Problem
+        x1 = xs[1].cpu().numpy()
+        errs = []
+        for b in (0, nb // 2, nb - 1):
+            wb = w.body(b)
+            p = Problem.from_workload(wb)
+            xr, _, _ = osolve.step(p, wb.x0, wb.v0, wb.actions[0], tol=1e-13)
+            sv = slice(w.body_v_off[b], w.body_v_off[b + 1])
+            errs.append(float(np.linalg.norm(x1[sv] - xr) / np.linalg.norm(xr - wb.x0)))
+        parity = {"bodies": [0, nb // 2, nb - 1], "x1_rel_err_vs_oracle_displacement": errs,
+                  "note": "batched mixed step at tol 1e-6 vs oracle at 1e-13"}
+    except Exception as e:  # report, never fail the bench line on the check
+        parity = {"error": repr(e)}
+
+    # plain single-body FP64 GPU path on a stratified subset (same bodies, one at a time)
+    plain = None
+    if not args.no_plain and args.plain_bodies > 0:
+        order = np.argsort(ne_b, kind="stable")
+        pick = order[np.linspace(0, nb - 1, args.plain_bodies).round().astype(int)]
+        parts = [(w.body(int(b)).X, w.body(int(b)).T, w.body(int(b)).pinned) for b in pick]
+        X, Tm, P, vo, eo = concat_bodies(parts)
+        sub = scenes.Workload("plain_subset", 2, X, Tm, P, np.concatenate([w.body(int(b)).mu for b in pick]),
+                              np.concatenate([w.body(int(b)).lam for b in pick]),
+                              np.concatenate([w.body(int(b)).kf for b in pick]),
+                              np.concatenate([w.body(int(b)).fdir for b in pick]),
+                              np.concatenate([w.body(int(b)).rho for b in pick]), dict(w.scene), X.copy(),
+                              np.zeros_like(X), np.concatenate([w.body(int(b)).actions for b in pick], axis=1),
+                              vo, eo)
+        pctx = Context.from_workload(sub, precision="fp64", solver=0)
+        px0 = torch.tensor(sub.x0, dtype=torch.float64, device=dev)
+        pv0 = torch.zeros_like(px0)
+        pa = torch.tensor(sub.actions, dtype=torch.float64, device=dev)
+        pm = pctx.mass()
+
+        def plain_pass(S):
+            xs_, vs_ = [px0], [pv0]
+            for t in range(S):
+                x1_, v1_, _, _ = pctx.step(xs_[-1], vs_[-1], pa[t], stats=False)
+                xs_.append(x1_)
+                vs_.append(v1_)
+            xb_, vb_ = torch.zeros_like(px0), torch.zeros_like(px0)
+            xb_[:, 0] = -pm / pm.sum()
+            for t in range(S - 1, -1, -1):
+                wv_, _, _ = pctx.solve_adjoint(xs_[t + 1], xs_[t], pa[t], xb_, vb_, stats=False)
+                out_ = pctx.vjp_params(wv_, xs_[t + 1], xs_[t], pa[t], vb_, want=("a_bar", "x0_bar", "v0_bar"))
+                xb_, vb_ = out_["x0_bar"], out_["v0_bar"]
+
+        plain_pass(1)
+        torch.cuda.synchronize()
+        print("# plain FP64 warm-up pass done", file=sys.stderr, flush=True)
+        tp = time.perf_counter()
+        plain_pass(args.plain_steps)
+        torch.cuda.synchronize()
+        tpl = time.perf_counter() - tp
+        pv = len(pick) * args.plain_steps / tpl
+        plain = {"value": round(pv, 2), "unit": "body-steps/s", "bodies": int(len(pick)),
+                 "steps": args.plain_steps, "sample": "stratified by size (evenly spaced in size order)",
+                 "dtype": "f64", "solver": "plain host-driven Newton-PCG, grid-wide kernels",
+                 "batched_over_plain": round(value / pv, 1)}
+
+    # FP64 CPU oracle on a bounded sample of the same workload
+    cpu = None
+    if not args.no_cpu:
+        from oracle import solve as osolve
+        from oracle.fem import Problem
+        tc = time.perf_counter()
+        n_done = 0
+        for b in range(args.cpu_bodies):
+            wb = w.body(b)
+            wb.scene.update(tol_rel=1e-6)
+            p = Problem.from_workload(wb)
+            states, _ = osolve.rollout(p, wb.x0, wb.v0, wb.actions[:args.cpu_steps], tol=1e-6)
+            osolve.rollout_grad(p, states, wb.actions[:args.cpu_steps], osolve.com_x_loss_grad(p, states[-1][0]))
+            n_done += args.cpu_steps
+            print(f"# oracle body {b} ({wb.n_e} triangles) done, {time.perf_counter() - tc:.1f} s", file=sys.stderr,
+                  flush=True)
+        tcpu = time.perf_counter() - tc
+        cpu = {"value": round(n_done / tcpu, 3), "unit": "body-steps/s", "cores": 1, "kind": "oracle",
+               "sample": f"bodies 0..{args.cpu_bodies - 1} of the batch x {args.cpu_steps} steps, forward "
+                         f"Newton (SuperLU) to 1e-6 + adjoint + VJP, {tcpu:.1f} s",
+               "host_cpus": os.cpu_count()}
+
+    line = {"metric": METRIC, "value": round(value, 1), "unit": "body-steps/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+            "data": "synthetic",
+            "config": {"workload": f"batched_strips: {nb} bodies (4s x s quads, s~U{{4..32}}, "
+                                   f"{w.n_e} triangles, {w.n_v} vertices), {T} backward-Euler steps "
+                                   "fwd + adjoint + VJP per bench step",
+                       "solver": "batched persistent, mixed FP32 element Hv / FP64 vectors",
+                       "tol_rel": w.scene["tol_rel"], "adj_tol_rel": w.scene["adj_tol_rel"],
+                       "block": ctx.get_option(isb.OPT_BLOCK)},
+            "iterations": it, "plain_fp64": plain, "parity": parity, "roofline": roofline,
+            "cpu_baseline": cpu}
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()
