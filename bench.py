@@ -46,6 +46,10 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--block", type=int, default=0, help="batched workgroup size (0 = library default)")
     ap.add_argument("--profile", action="store_true", help="one untimed pass only (for rocprofv3)")
+    ap.add_argument("--no-tet", action="store_true", help="skip the 3D tet-block leg")
+    ap.add_argument("--tet-steps", type=int, default=20)
+    ap.add_argument("--no-elem-roofline", action="store_true", help="skip the size-R element roofline leg")
+    ap.add_argument("--elem-grid", type=str, default="192x128x64", help="Kuhn-tet grid of the size-R leg")
     return ap.parse_args()
 
 
@@ -266,6 +270,9 @@ def main():
                          f"Newton (SuperLU) to 1e-6 + adjoint + VJP, {tcpu:.1f} s",
                "host_cpus": os.cpu_count()}
 
+    tet = None if args.no_tet else tet_leg(args, torch, Context, isb, scenes)
+    elem = None if args.no_elem_roofline else element_roofline_leg(args, torch, Context, isb, scenes)
+
     line = {"metric": METRIC, "value": round(value, 1), "unit": "body-steps/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
@@ -277,8 +284,97 @@ def main():
                        "tol_rel": w.scene["tol_rel"], "adj_tol_rel": w.scene["adj_tol_rel"],
                        "block": ctx.get_option(isb.OPT_BLOCK)},
             "iterations": it, "plain_fp64": plain, "parity": parity, "roofline": roofline,
-            "cpu_baseline": cpu}
+            "cpu_baseline": cpu, "tet_block": tet, "element_roofline": elem}
     print(json.dumps(line))
+
+
+def tet_leg(args, torch, Context, isb, scenes):
+    """3D tet block (393,216 tets): plain grid-wide path, mixed, T steps forward + T adjoints."""
+    dev = torch.device("cuda:0")
+    w = scenes.tet_block(steps=args.tet_steps)
+    ctx = Context.from_workload(w, precision="mixed", solver=0)
+    x0 = torch.tensor(w.x0, device=dev)
+    v0 = torch.tensor(w.v0, device=dev)
+    acts = torch.tensor(w.actions, device=dev)
+    m = ctx.mass()
+
+    def run(S, stats):
+        xs, vs, st = [x0], [v0], []
+        for t in range(S):
+            x1, v1, s, _ = ctx.step(xs[-1], vs[-1], acts[t], stats=stats)
+            xs.append(x1)
+            vs.append(v1)
+            st.append(s)
+        xb = torch.zeros_like(x0)
+        xb[:, 0] = -m / m.sum()
+        vb = torch.zeros_like(x0)
+        sa = []
+        for t in range(S - 1, -1, -1):
+            wv, s, _ = ctx.solve_adjoint(xs[t + 1], xs[t], acts[t], xb, vb, stats=stats)
+            out = ctx.vjp_params(wv, xs[t + 1], xs[t], acts[t], vb, want=("a_bar", "x0_bar", "v0_bar"))
+            xb, vb = out["x0_bar"], out["v0_bar"]
+            sa.append(s)
+        return st, sa
+
+    run(1, False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run(args.tet_steps, False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st, sa = run(2, True)
+    print("# tet-block leg done", file=sys.stderr, flush=True)
+    return {"workload": f"tet_block 64x32x32 Kuhn tets ({w.n_e} tets, {w.n_v} vertices), {args.tet_steps} "
+                        "backward-Euler steps fwd + adjoint + VJP",
+            "solver": "plain grid-wide Newton-PCG, mixed", "value": round(args.tet_steps / dt, 3),
+            "unit": "steps/s", "seconds": round(dt, 3),
+            "newton_per_step": float(np.mean([s[0]["newton_iters"] for s in st])),
+            "cg_per_step": float(np.mean([s[0]["cg_iters"] for s in st])),
+            "adj_cg_per_step": float(np.mean([s[0]["adj_cg_iters"] for s in sa]))}
+
+
+def element_roofline_leg(args, torch, Context, isb, scenes):
+    """Element Hessian-vector kernel alone (isb_hessvec_elements) on a mesh whose element data
+    exceeds the 256 MB last-level cache; algorithmic bytes / HIP-event time, FP64 and mixed."""
+    from synth import meshes
+    dev = torch.device("cuda:0")
+    nx, ny, nz = (int(v) for v in args.elem_grid.split("x"))
+    X, Tm = meshes.tet_grid(nx, ny, nz)
+    n_e, n_v = Tm.shape[0], X.shape[0]
+    mu, lam = scenes.lame(1e5, 0.45)
+    rng = np.random.default_rng([210205791, 6])
+    x = torch.tensor(X + 0.01 * rng.standard_normal(X.shape), device=dev)
+    p = torch.tensor(rng.standard_normal(X.shape), device=dev)
+    a = torch.tensor(meshes.contraction_actuation(rng, n_e), device=dev)
+    out = {"mesh": f"tet_grid {nx}x{ny}x{nz}: {n_e} tets, {n_v} vertices"}
+    for prec, word in (("fp64", 8), ("mixed", 4)):
+        ctx = Context(0, prec)
+        ctx.mesh_upload(3, X, Tm, None)
+        ctx.material_upload(np.full(n_e, mu), np.full(n_e, lam), np.full(n_e, 1e5), meshes.x_fibres(n_e, 3),
+                            np.ones(n_e), scenes.scene("be", h=1.0 / 30.0))
+        hp = torch.zeros_like(x)
+        for _ in range(3):
+            ctx.hessvec_elements(x, a, p, hp)
+        torch.cuda.synchronize()
+        evs = []
+        for _ in range(20):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            ctx.hessvec_elements(x, a, p, hp)
+            e1.record()
+            evs.append((e0, e1))
+        torch.cuda.synchronize()
+        ms = float(np.median([e0.elapsed_time(e1) for e0, e1 in evs]))
+        # the mixed launch also converts a to FP32: one read of n_e doubles, one write of n_e floats
+        elem_b = elem_bytes(3, word)
+        byt = n_e * elem_b + n_v * 3 * (8 + 8 + 16) + (12 * n_e if prec == "mixed" else 0)
+        gbs = byt / (ms * 1e-3) / 1e9
+        out[prec] = {"launch_ms": round(ms, 4), "algorithmic_bytes": int(byt), "achieved_GBs": round(gbs, 1),
+                     "frac_of_8TBs": round(gbs / HBM_PEAK_GBS, 4), "element_bytes": elem_b}
+        del ctx
+        torch.cuda.empty_cache()
+    print("# element roofline leg done", file=sys.stderr, flush=True)
+    return out
 
 
 if __name__ == "__main__":

@@ -208,6 +208,12 @@ isb_status isb_gradient(isb_ctx* ctx, isb_stream stream, const double* x, const 
  * FP32 element arithmetic in ISB_MIXED. device [n_v][dim] in/out. */
 isb_status isb_hessvec(isb_ctx* ctx, isb_stream stream, const double* x, const double* x0,
                        const double* a, const double* p, double* hp);
+/* Element part of the Hessian-vector product only, added into hp: hp += sum_e W_e dP(F_e; dF_e(p)) Dm^-T
+ * scattered to the element's vertices (Eq. 10 without the vertex terms and without the projection
+ * onto free DOFs), scaled by h^2 in backward Euler. This is the hot kernel of the CG iteration on
+ * its own, for callers that add their own vertex terms and for timing. device [n_v][dim] in/in-out. */
+isb_status isb_hessvec_elements(isb_ctx* ctx, isb_stream stream, const double* x, const double* a,
+                                const double* p, double* hp);
 /* Diagonal of H(x) over free DOFs (1 on pinned DOFs), device out [n_v][dim]. */
 isb_status isb_hessdiag(isb_ctx* ctx, isb_stream stream, const double* x, const double* x0,
                         const double* a, double* diag);

@@ -25,6 +25,11 @@ from .fem import Problem, cofactor, det, edge_matrix, logq, logq_d
 ARMIJO_C1 = 1e-4
 LS_MAX = 30
 EPS = np.finfo(np.float64).eps
+# Above this many free DOFs the sparse direct factorisation of a 3D mesh fills in too much; the
+# linear solves then use SciPy's conjugate gradient on the assembled matrix (a library routine,
+# Jacobi-preconditioned, relative tolerance 1e-14) instead.
+DIRECT_MAX_DOFS = 60000
+ITER_RTOL = 1e-14
 
 
 def _factor_pd(H: sp.csr_matrix):
@@ -36,8 +41,20 @@ def _factor_pd(H: sp.csr_matrix):
     return lu, is_pd
 
 
-def newton_direction(H: sp.csr_matrix, rhs: np.ndarray):
+def _cg_solve(A: sp.csr_matrix, rhs: np.ndarray):
+    """SciPy CG on the assembled matrix with a Jacobi preconditioner; (x, ok) where ok means
+    converged with positive curvature along the solution."""
+    d = np.abs(A.diagonal())
+    d[d == 0] = 1.0
+    M = spla.LinearOperator(A.shape, matvec=lambda v: v / d, dtype=np.float64)
+    x, info = spla.cg(A, rhs, rtol=ITER_RTOL, atol=0.0, maxiter=50000, M=M)
+    ok = info == 0 and float(x @ (A @ x)) > 0.0
+    return x, ok
+
+
+def newton_direction(H: sp.csr_matrix, rhs: np.ndarray, direct_max: int | None = None):
     """Solve (H + tau I) dx = rhs with the smallest tau >= 0 of the doubling sequence that is PD."""
+    direct_max = DIRECT_MAX_DOFS if direct_max is None else direct_max
     diag = H.diagonal()
     scale = np.mean(np.abs(diag))
     beta = 1e-3 * scale if scale > 0 else 1e-3
@@ -45,17 +62,22 @@ def newton_direction(H: sp.csr_matrix, rhs: np.ndarray):
     n = H.shape[0]
     for _ in range(80):
         A = H if tau == 0.0 else (H + tau * sp.identity(n, format="csr"))
-        try:
-            lu, ok = _factor_pd(A)
-        except RuntimeError:
-            ok = False
-        if ok:
-            return lu.solve(rhs), tau
+        if n <= direct_max:
+            try:
+                lu, ok = _factor_pd(A)
+            except RuntimeError:
+                ok = False
+            if ok:
+                return lu.solve(rhs), tau
+        else:
+            x, ok = _cg_solve(A.tocsr(), rhs)
+            if ok:
+                return x, tau
         tau = max(2.0 * tau, beta)
     raise RuntimeError("no positive-definite shift found")
 
 
-def step(prob: Problem, x0, v0, a, tol=1e-13, max_iter=50):
+def step(prob: Problem, x0, v0, a, tol=1e-13, max_iter=50, direct_max=None):
     """One implicit step: x1 = argmin g(x; x0, v0, a); v1 = (x1 - x0)/h in backward Euler.
 
     Stops at |G_free| <= tol |G_free(x_init)|, or when the line search can no longer make
@@ -83,7 +105,7 @@ def step(prob: Problem, x0, v0, a, tol=1e-13, max_iter=50):
             stats["converged"] = True
             break
         H = prob.hessian(x, x0, a)[free][:, free]
-        dx, tau = newton_direction(H, -G)
+        dx, tau = newton_direction(H, -G, direct_max)
         stats["shifts"] += int(tau > 0)
         gTd = float(G @ dx)
         ee0, ev0 = prob.energy_terms(x, x0, v0, a)
@@ -94,13 +116,16 @@ def step(prob: Problem, x0, v0, a, tol=1e-13, max_iter=50):
             xt.reshape(-1)[free] += alpha * dx
             ee1, ev1 = prob.energy_terms(xt, x0, v0, a)
             dg = float(np.sum(ee1 - ee0) + np.sum(ev1 - ev0))
-            if dg <= ARMIJO_C1 * alpha * gTd:
-                accepted = True
-            elif abs(dg) <= 1e3 * EPS * scale:
-                # energy change below FP64 resolution: fall back to a decrease of |G|
+            if abs(dg) <= 1e3 * EPS * scale:
+                # energy change below FP64 resolution, where the Armijo test only sees rounding:
+                # accept only if |G| at least halves (a smaller decrease is noise; stagnation)
                 Gt = grad_free(xt)
-                if np.linalg.norm(Gt) < res:
+                if np.linalg.norm(Gt) <= 0.5 * res:
                     accepted, G_new = True, Gt
+                else:
+                    break                       # shorter steps cannot do better at the floor
+            elif dg <= ARMIJO_C1 * alpha * gTd:
+                accepted = True
             if accepted:
                 break
             alpha *= 0.5
@@ -122,15 +147,22 @@ def _velocity(prob: Problem, x1, x0):
     return (x1 - x0) / prob.h if prob.be else None
 
 
-def adjoint(prob: Problem, x1, x0, a, x1_bar, v1_bar=None):
+def adjoint(prob: Problem, x1, x0, a, x1_bar, v1_bar=None, direct_max=None):
     """w = H(x1)^-1 (x1_bar + v1_bar/h) over the free DOFs; w = 0 on pinned DOFs (Eq. 9)."""
+    direct_max = DIRECT_MAX_DOFS if direct_max is None else direct_max
     rhs = np.asarray(x1_bar, dtype=np.float64).copy()
     if prob.be and v1_bar is not None:
         rhs = rhs + np.asarray(v1_bar, dtype=np.float64) / prob.h
     free = prob.free
     H = prob.hessian(x1, x0, a)[free][:, free]
     w = np.zeros(prob.mesh.n_v * prob.mesh.d)
-    w[free] = spla.spsolve(H.tocsc(), rhs.ravel()[free])
+    if H.shape[0] <= direct_max:
+        w[free] = spla.spsolve(H.tocsc(), rhs.ravel()[free])
+    else:
+        sol, ok = _cg_solve(H.tocsr(), rhs.ravel()[free])
+        if not ok:
+            raise RuntimeError("adjoint CG did not converge (Hessian not positive definite?)")
+        w[free] = sol
     return w.reshape(x1.shape)
 
 

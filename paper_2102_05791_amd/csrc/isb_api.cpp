@@ -21,6 +21,9 @@ using namespace isb;
 static constexpr double kArmijoC1 = 1e-4;
 static constexpr int kMaxBacktracks = 30;
 static constexpr double kEps = 2.220446049250313e-16;
+// Below the FP64 resolution of g the line search accepts a step only if it at least halves
+// |grad g|; a smaller decrease is rounding noise, and the solve stops there as stagnated.
+static constexpr double kFloorDecrease = 0.5;
 
 void isb_ctx::free_list(std::vector<void*>& v) {
   for (void* p : v) (void)hipFree(p);
@@ -303,20 +306,23 @@ static isb_status plain_newton(isb_ctx* c, int b, hipStream_t s, const double* x
       const double dg = c->hscal[0], gabs = c->hscal[1];
       if (!std::isfinite(dg)) {
         // overflow or an invalid trial point: backtrack
-      } else if (dg <= kArmijoC1 * alpha * gTd) {
-        accepted = true;
-      } else if (std::fabs(dg) <= 1e3 * kEps * gabs) {
+      } else if (std::fabs(dg) > 1e3 * kEps * gabs) {
+        accepted = dg <= kArmijoC1 * alpha * gTd;
+      } else {
+        // below the resolution of g the Armijo test only sees rounding
         launch_copy(br.n, x + br.off, xt + br.off, s);
         launch_axpy(br.n, xt + br.off, alpha, dx + br.off, s);
         eval_grad(c, b, xt, x0, a, Gt, s);
         enqueue_norm2(c, b, Gt, 0, s);
         ISB_TRY(read_scal(c, s, 1));
         const double rt = std::sqrt(c->hscal[0]);
-        if (rt < res) {
+        if (rt <= kFloorDecrease * res) {
           accepted = via_grad = true;
           std::swap(x, xt);
           std::swap(G, Gt);
           res = rt;
+        } else {
+          break;  // shorter steps cannot do better at the rounding floor
         }
       }
       if (accepted) break;
@@ -784,6 +790,22 @@ isb_status isb_hessvec(isb_ctx* c, isb_stream stream, const double* x, const dou
     launch_elem_hv(m, dsc, r, atomic, c->precision, x, a, c->w_a32, c->w_p, hp, nullptr, s);
   });
   launch_mask(m, 0, c->n_v, hp, s);
+  ISB_HIP(hipGetLastError());
+  return ISB_OK;
+}
+
+isb_status isb_hessvec_elements(isb_ctx* c, isb_stream stream, const double* x, const double* a,
+                                const double* p, double* hp) {
+  clear_error();
+  ISB_TRY(check_ctx(c, true));
+  if (!x || !a || !p || !hp) return fail(ISB_E_ARG, "NULL argument");
+  hipStream_t s = (hipStream_t)stream;
+  const DevMesh m = devmesh(c);
+  const DevScene dsc = devscene(c);
+  if (c->precision == ISB_MIXED) launch_to_f32(c->n_e, a, c->w_a32, s);
+  elem_ranges(c, -1, [&](ERange r, bool atomic) {
+    launch_elem_hv(m, dsc, r, atomic, c->precision, x, a, c->w_a32, p, hp, nullptr, s);
+  });
   ISB_HIP(hipGetLastError());
   return ISB_OK;
 }

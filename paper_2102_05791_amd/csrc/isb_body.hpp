@@ -456,17 +456,20 @@ struct BodySolver {
         double en[3];
         energy(x, dx, alpha, en);
         if (isfinite(en[0])) {
-          if (en[0] <= 1e-4 * alpha * gTd) {
-            accepted = true;
-          } else if (fabs(en[0]) <= 1e3 * 2.220446049250313e-16 * en[1]) {
-            // below the FP64 resolution of g: accept on a decrease of |grad g| instead
+          if (fabs(en[0]) > 1e3 * 2.220446049250313e-16 * en[1]) {
+            accepted = en[0] <= 1e-4 * alpha * gTd;
+          } else {
+            // below the FP64 resolution of g the Armijo test only sees rounding: accept only if
+            // |grad g| at least halves
             const double rt = sqrt(gradient(x, dx, alpha, Gt));
-            if (rt < res) {
+            if (rt <= 0.5 * res) {
               accepted = via_grad = true;
               double* tmp = G;
               G = Gt;
               Gt = tmp;
               res = rt;
+            } else {
+              break;  // shorter steps cannot do better at the rounding floor
             }
           }
         }

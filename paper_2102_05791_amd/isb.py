@@ -27,7 +27,8 @@ FLAG_CONVERGED, FLAG_STAGNATED, FLAG_NONFINITE, FLAG_ADJ_CONVERGED = 1, 2, 4, 8
 EXPORTED = ("isb_create", "isb_destroy", "isb_last_error", "isb_version", "isb_validate_mesh",
             "isb_colour_elements", "isb_mesh_upload", "isb_material_upload", "isb_set_scene",
             "isb_set_option", "isb_get_option", "isb_get_mass", "isb_step", "isb_solve_adjoint",
-            "isb_vjp_params", "isb_energy", "isb_gradient", "isb_hessvec", "isb_hessdiag")
+            "isb_vjp_params", "isb_energy", "isb_gradient", "isb_hessvec", "isb_hessvec_elements",
+            "isb_hessdiag")
 
 
 class IsbError(RuntimeError):
@@ -100,6 +101,7 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
         "isb_energy": [vp, vp, vp, vp, vp, vp, vp],
         "isb_gradient": [vp, vp, vp, vp, vp, vp, vp],
         "isb_hessvec": [vp, vp, vp, vp, vp, vp, vp],
+        "isb_hessvec_elements": [vp, vp, vp, vp, vp, vp],
         "isb_hessdiag": [vp, vp, vp, vp, vp, vp],
     }
     for name, argtypes in sigs.items():
@@ -290,6 +292,11 @@ class Context:
     def hessvec(self, x, x0, a, p):
         hp = self._empty(self.n_v, self.dim)
         _check(self.lib, self.lib.isb_hessvec(self.h, _stream(), _dev(x), _dev(x0), _dev(a), _dev(p), _dev(hp)))
+        return hp
+
+    def hessvec_elements(self, x, a, p, hp):
+        """isb_hessvec_elements: hp += element part of H(x) p (no vertex terms, no projection)."""
+        _check(self.lib, self.lib.isb_hessvec_elements(self.h, _stream(), _dev(x), _dev(a), _dev(p), _dev(hp)))
         return hp
 
     def hessdiag(self, x, x0, a):

@@ -1,0 +1,121 @@
+"""Backpropagation through time on the GPU: ImplicitStep and the checkpointed rollout against the
+FP64 oracle, and the full 100-step, 2048-triangle strip against central differences of whole
+rollouts (Sec. 5.1: the reward is the horizontal displacement at the horizon)."""
+import numpy as np
+import pytest
+
+from oracle import solve
+from oracle.fem import Problem
+from synth import meshes, scenes
+from synth.scenes import Workload
+
+pytestmark = pytest.mark.gpu
+
+SEED_ROOT = 210205791
+
+
+def _dev(a, requires_grad=False):
+    import torch
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda:0", requires_grad=requires_grad)
+
+
+def _tight(w):
+    w.scene.update(tol_rel=1e-13, adj_tol_rel=1e-13, max_newton=80, max_cg=4000)
+    return w
+
+
+def _com_loss(torch, mass, x):
+    return -(mass * x[:, 0]).sum() / mass.sum()
+
+
+def test_implicit_step_autograd_matches_oracle():
+    import torch
+    from paper_2102_05791_amd import Context
+    from paper_2102_05791_amd.autograd import implicit_step
+    w = _tight(scenes.be_strip(nx=12, ny=4, steps=2))
+    p = Problem.from_workload(w)
+    ctx = Context.from_workload(w, precision="fp64", solver=0)
+    x0 = _dev(w.x0, requires_grad=True)
+    v0 = _dev(w.v0, requires_grad=True)
+    a = _dev(w.actions[0], requires_grad=True)
+    x1, v1 = implicit_step(ctx, x0, v0, a)
+    c1 = np.random.default_rng(3).normal(size=w.x0.shape)
+    c2 = np.random.default_rng(4).normal(size=w.x0.shape)
+    L = (x1 * _dev(c1)).sum() + (v1 * _dev(c2)).sum()
+    L.backward()
+    xr, _, _ = solve.step(p, w.x0, w.v0, w.actions[0], tol=1e-13)
+    wv = solve.adjoint(p, xr, w.x0, w.actions[0], c1, c2)
+    ref = solve.vjp_params(p, wv, xr, w.x0, w.actions[0], v1_bar=c2)
+    for got, key in ((a.grad, "a_bar"), (x0.grad, "x0_bar"), (v0.grad, "v0_bar")):
+        g = got.cpu().numpy()
+        err = np.linalg.norm(g - ref[key]) / np.linalg.norm(ref[key])
+        print(key, err)
+        assert err <= 1e-10, key
+
+
+def _replicate(w, actions_per_body):
+    """One batched workload holding copies of body w, body b driven by actions_per_body[b]."""
+    nb = len(actions_per_body)
+    X, T, P, vo, eo = meshes.concat_bodies([(w.X, w.T, w.pinned)] * nb)
+    tile = lambda v: np.concatenate([v] * nb)
+    acts = np.concatenate(actions_per_body, axis=1)
+    return Workload("replicas", w.dim, X, T, P, tile(w.mu), tile(w.lam), tile(w.kf), tile(w.fdir), tile(w.rho),
+                    dict(w.scene), tile(w.x0), tile(w.v0), acts, vo, eo)
+
+
+def test_bptt_strip_100_steps_checkpointed_vs_oracle_and_fd():
+    """The 64x16 strip, 100 steps, L = -COM_x(x_100), gradient w.r.t. all 204,800 actuations."""
+    import torch
+    from paper_2102_05791_amd import Context
+    from paper_2102_05791_amd.autograd import rollout
+    w = _tight(scenes.be_strip())
+    n_e, T = w.n_e, w.actions.shape[0]
+    # AD: checkpointed rollout (every 10 steps) through the batched FP64 solver
+    ctx = Context.from_workload(w, precision="fp64", solver=1)
+    acts = _dev(w.actions, requires_grad=True)
+    xT, vT = rollout(ctx, _dev(w.x0), _dev(w.v0), acts, checkpoint_every=10)
+    mass = ctx.mass()
+    L = _com_loss(torch, mass, xT)
+    L.backward()
+    g = acts.grad.cpu().numpy()
+    Lv = float(L.detach())
+    # oracle BPTT storing every state
+    p = Problem.from_workload(w)
+    states, _ = solve.rollout(p, w.x0, w.v0, w.actions, tol=1e-13)
+    L_ref = solve.com_x_loss(p, states[-1][0])
+    g_ref, _, _ = solve.rollout_grad(p, states, w.actions, solve.com_x_loss_grad(p, states[-1][0]))
+    gerr = np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref)
+    print("loss", Lv, L_ref, "grad rel err vs oracle", gerr, "|g|", np.linalg.norm(g_ref))
+    assert abs(Lv - L_ref) <= 1e-10 * abs(L_ref)
+    assert gerr <= 1e-9
+    # central differences on 32 Rademacher directions: 64 perturbed rollouts as 64 bodies
+    eps = 1e-6
+    dirs = [meshes.rng(3, k).choice([-1.0, 1.0], size=(T, n_e)) for k in range(32)]
+    per_body = []
+    for r in dirs:
+        per_body += [w.actions + eps * r, w.actions - eps * r]
+    wb = _replicate(w, per_body)
+    bctx = Context.from_workload(wb, precision="fp64", solver=1)
+    x, v = _dev(wb.x0), _dev(wb.v0)
+    a_all = _dev(wb.actions)
+    contact = []
+    for t in range(T):
+        x, v, st, _ = bctx.step(x, v, a_all[t].contiguous())
+        contact.append((x[:, 1] < 0).reshape(64, -1).cpu().numpy())
+    contact = np.stack(contact, axis=1)                       # [64, T, n_v]
+    bm = bctx.mass().reshape(64, -1)
+    Lb = (-(bm * x[:, 0].reshape(64, -1)).sum(dim=1) / bm.sum(dim=1)).cpu().numpy()
+    n_flag, n_ok = 0, 0
+    for k, r in enumerate(dirs):
+        fd = (Lb[2 * k] - Lb[2 * k + 1]) / (2 * eps)
+        ad = float(np.sum(g * r))
+        flagged = not np.array_equal(contact[2 * k], contact[2 * k + 1])
+        ok = abs(fd - ad) <= 1e-5 * max(abs(fd), abs(ad)) + 1e-10 * abs(Lv)
+        print(f"dir {k}: fd {fd:.10e} ad {ad:.10e} rel {abs(fd - ad) / max(abs(fd), 1e-300):.2e}"
+              f"{' contact-set changed' if flagged else ''}")
+        if flagged:
+            n_flag += 1
+            continue
+        assert ok, (k, fd, ad)
+        n_ok += 1
+    assert n_ok >= 24, (n_ok, n_flag)

@@ -1,0 +1,46 @@
+"""The 3D workload at full size (64x32x32 Kuhn tets: 393,216 tets, 70,785 vertices) on the plain
+grid-wide path, against the oracle's sampled outputs stored by tests/golden/make_tet_block_golden.py
+(one backward-Euler step and the adjoint of L = -COM_x(x1), both solved by the oracle at 1e-12)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from synth import scenes
+
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "tet_block_step.json")
+
+
+def _dev(a):
+    import torch
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda:0")
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("mixed", 1e-5)])
+def test_tet_block_step_and_adjoint_vs_oracle_samples(precision, tol):
+    from paper_2102_05791_amd import Context
+    g = json.load(open(GOLD))
+    w = scenes.tet_block()
+    assert (w.n_v, w.n_e) == (g["n_v"], g["n_e"])
+    w.scene.update(tol_rel=g["tol_rel"], adj_tol_rel=1e-12, max_newton=60, max_cg=20000)
+    ctx = Context.from_workload(w, precision=precision, solver=0)
+    x1, v1, st, _ = ctx.step(_dev(w.x0), _dev(w.v0), _dev(w.actions[0]))
+    vs = np.array(g["vertices"])
+    x1s = x1.cpu().numpy()[vs]
+    gx = np.array(g["x1"])
+    ex = np.linalg.norm(x1s - gx) / np.linalg.norm(gx - w.x0[vs])
+    ev = np.linalg.norm(v1.cpu().numpy()[vs] - np.array(g["v1"])) / np.linalg.norm(np.array(g["v1"]))
+    m = ctx.mass()
+    xbar = _dev(np.zeros_like(w.x0))
+    xbar[:, 0] = -m / m.sum()
+    wv, sa, _ = ctx.solve_adjoint(x1, _dev(w.x0), _dev(w.actions[0]), xbar)
+    out = ctx.vjp_params(wv, x1, _dev(w.x0), _dev(w.actions[0]))
+    ew = np.linalg.norm(wv.cpu().numpy()[vs] - np.array(g["w"])) / np.linalg.norm(np.array(g["w"]))
+    es = np.array(g["elements"])
+    ea = np.linalg.norm(out["a_bar"].cpu().numpy()[es] - np.array(g["a_bar"])) / np.linalg.norm(np.array(g["a_bar"]))
+    print(f"{precision}: newton {st[0]['newton_iters']} cg {st[0]['cg_iters']} adj_cg {sa[0]['adj_cg_iters']} "
+          f"min_J {st[0]['min_J']:.3f} max_J {st[0]['max_J']:.3f} | x1 {ex:.2e} v1 {ev:.2e} w {ew:.2e} a_bar {ea:.2e}")
+    assert ex <= tol and ev <= tol and ew <= tol and ea <= tol

@@ -373,7 +373,7 @@ def test_lumped_mass_total_is_area():
 def test_newton_converges_quadratically():
     w = scenes.qs_cantilever()
     p = Problem.from_workload(w)
-    _, _, st = solve.step(p, w.x0, None, w.actions[0], tol=1e-14)
+    _, _, st = solve.step(p, w.x0, None, w.actions[0], tol=1e-13)
     r = np.array(st["res_hist"]) / st["res0"]
     assert st["converged"]
     tail = [(r[k], r[k + 1]) for k in range(len(r) - 1) if 1e-12 < r[k + 1] and r[k] < 1e-2]
@@ -515,3 +515,18 @@ def test_tet_grid_is_conforming_and_positive():
     assert set(counts.tolist()) <= {1, 2}
     n_boundary = 2 * 2 * (3 * 2 + 3 * 2 + 2 * 2)
     assert int((counts == 1).sum()) == n_boundary
+
+
+def test_iterative_linear_solves_match_direct():
+    """The large-system path (SciPy CG on the assembled matrix) agrees with the direct solves."""
+    from tests.gpu_util import rand_workload
+    w, rng = rand_workload(3, seed=5, shape=(4, 3, 3))
+    p = Problem.from_workload(w)
+    a = w.actions[0]
+    xd, _, sd = solve.step(p, w.x0, w.v0, a, tol=1e-12, direct_max=10 ** 9)
+    xi, _, si = solve.step(p, w.x0, w.v0, a, tol=1e-12, direct_max=0)
+    assert np.linalg.norm(xi - xd) <= 1e-11 * np.linalg.norm(xd - w.x0)
+    xbar = rng.normal(size=xd.shape)
+    wd = solve.adjoint(p, xd, w.x0, a, xbar, direct_max=10 ** 9)
+    wi = solve.adjoint(p, xd, w.x0, a, xbar, direct_max=0)
+    assert np.linalg.norm(wi - wd) <= 1e-11 * np.linalg.norm(wd)
