@@ -63,10 +63,14 @@ typedef enum { ISB_QUASISTATIC = 0, ISB_BACKWARD_EULER = 1 } isb_integrator;
 typedef enum {
   ISB_OPT_SOLVER = 0,       /* 0 = plain: host-driven Newton-PCG, one body at a time, grid-wide kernels;
                                1 = batched: one persistent launch, one workgroup per body (default 0) */
-  ISB_OPT_SCATTER = 1,      /* plain solver scatter: 0 = FP64 atomics (default), 1 = graph colouring
-                               (deterministic, bitwise reproducible) */
+  ISB_OPT_SCATTER = 1,      /* plain solver scatter: 0 = FP64 global atomics per element corner,
+                               1 = graph colouring (deterministic, bitwise reproducible),
+                               2 = LDS-staged element patches (default): one workgroup per patch of
+                               consecutive elements accumulates in LDS and adds each distinct vertex DOF
+                               to global memory once */
   ISB_OPT_GRAPH_SAFE = 2,   /* 1 = no host synchronisation inside step/adjoint/vjp (batched solver only) */
-  ISB_OPT_BLOCK = 3,        /* batched solver workgroup size: 256, 512 or 1024 (default 1024) */
+  ISB_OPT_BLOCK = 3,        /* batched solver workgroup size: 256, 512 or 1024; 0 (default) = 1024 for
+                               triangles, 512 for tetrahedra */
   ISB_OPT_CG_CHECK = 4,     /* plain solver: read the CG convergence flag every k iterations (default 4) */
   ISB_OPT_PRECISION = 5     /* isb_precision; equals the value given to isb_create */
 } isb_option;

@@ -131,7 +131,7 @@ static isb_status read_cg(isb_ctx* c, hipStream_t s) {
 template <class Fn>
 static void elem_ranges(const isb_ctx* c, int b, Fn fn) {
   const int b0 = b < 0 ? 0 : b, b1 = b < 0 ? c->n_bodies : b + 1;
-  if (c->scatter == 0) {
+  if (c->scatter != 1) {
     fn(ERange{(int)c->eoff[b0], (int)c->eoff[b1], nullptr}, true);
     return;
   }
@@ -141,6 +141,35 @@ static void elem_ranges(const isb_ctx* c, int b, Fn fn) {
       const int s = c->col_off[bb * nc1 + k], e = c->col_off[bb * nc1 + k + 1];
       if (e > s) fn(ERange{s, e, c->clist}, false);
     }
+}
+
+// Bodies below this many elements keep the per-corner atomic scatter in patch mode: a launch over
+// them is latency bound and patches of a small body cannot fill the GPU.
+static constexpr int64_t kPatchMinElems = 16384;
+
+// element scatter of op (PATCH_GRAD / PATCH_HV / PATCH_DIAG) over body b (all bodies when b < 0),
+// in the context's scatter mode: FP64 global atomics, colour passes, or LDS-staged patches
+static void elem_scatter(isb_ctx* c, int b, int op, const double* x, const double* a, const double* p, double* out,
+                         const int* done, hipStream_t s, bool a32_copy = true) {
+  const float* a32 = a32_copy ? c->w_a32 : nullptr;
+  const DevMesh m = devmesh(c);
+  const DevScene sc = devscene(c);
+  const int64_t ne_scope = b < 0 ? c->n_e : c->eoff[b + 1] - c->eoff[b];
+  if (c->scatter == 2 && ne_scope >= kPatchMinElems) {
+    const int p0 = b < 0 ? 0 : c->body_patch_off[b];
+    const int p1 = b < 0 ? c->n_patches : c->body_patch_off[b + 1];
+    launch_elem_patch(m, sc, c->plan, p0, p1, op, op == PATCH_GRAD ? 0 : c->precision, x, a, a32, p, out, done,
+                      s);
+    return;
+  }
+  elem_ranges(c, b, [&](ERange r, bool atomic) {
+    if (op == PATCH_GRAD)
+      launch_elem_grad(m, sc, r, atomic, x, a, out, s);
+    else if (op == PATCH_HV)
+      launch_elem_hv(m, sc, r, atomic, c->precision, x, a, a32, p, out, done, s);
+    else
+      launch_elem_diag(m, sc, r, atomic, c->precision, x, a, a32, out, s);
+  });
 }
 
 struct BodyRange {
@@ -174,7 +203,7 @@ static void eval_grad(isb_ctx* c, int b, const double* x, const double* x0, cons
   const DevScene sc = devscene(c);
   const BodyRange br = body_range(c, b);
   launch_vertex_grad(m, sc, br.v0, br.v1, x, x0, c->w_xhat, c->w_cv, G, s);
-  elem_ranges(c, b, [&](ERange r, bool atomic) { launch_elem_grad(m, sc, r, atomic, x, a, G, s); });
+  elem_scatter(c, b, PATCH_GRAD, x, a, nullptr, G, nullptr, s);
   launch_mask(m, br.v0, br.v1, G, s);
 }
 
@@ -192,9 +221,7 @@ static void eval_precond(isb_ctx* c, int b, const double* x, const double* a, hi
   const BodyRange br = body_range(c, b);
   launch_vertex_hdiag(m, sc, br.v0, br.v1, x, c->w_cv, c->w_vdiag, s);
   launch_copy(br.n, c->w_vdiag + br.off, c->w_diag + br.off, s);
-  elem_ranges(c, b, [&](ERange r, bool atomic) {
-    launch_elem_diag(m, sc, r, atomic, c->precision, x, a, c->w_a32, c->w_diag, s);
-  });
+  elem_scatter(c, b, PATCH_DIAG, x, a, nullptr, c->w_diag, nullptr, s);
   launch_finish_diag(m, br.v0, br.v1, c->w_diag, c->w_Dinvp, s);
 }
 
@@ -223,9 +250,7 @@ static isb_status run_cg(isb_ctx* c, int b, const double* x, const double* a, co
                   c->w_Hp + o, c->partials, c->scal, tol2, s);
   const int check = std::max(1, c->cg_check);
   for (int it = 0; it < max_cg; ++it) {
-    elem_ranges(c, b, [&](ERange r, bool atomic) {
-      launch_elem_hv(m, sc, r, atomic, c->precision, x, a, c->w_a32, c->w_p, c->w_Hp, &c->scal->done, s);
-    });
+    elem_scatter(c, b, PATCH_HV, x, a, c->w_p, c->w_Hp, &c->scal->done, s);
     launch_cg_dot(br.n, c->w_p + o, c->w_Hp + o, c->partials, c->scal, s);
     launch_cg_update(br.n, it, c->w_p + o, c->w_Hp + o, c->w_Dinvp + o, c->w_r + o, c->w_xs + o, c->partials,
                      c->scal, s);
@@ -549,6 +574,20 @@ isb_status isb_mesh_upload(isb_ctx* c, int dim, int32_t n_bodies, const int64_t*
     }
   }
 
+  // element patches for the LDS-staged scatter, sized to the patch workgroup's LDS budget
+  Patches pt;
+  {
+    const int per_vertex = 3 * dim * (int)sizeof(double);  // x, p and the accumulator, FP64
+    ISB_TRY(build_patches(dim, n_v, n_bodies, body_e_off, T, 2048, kPatchLdsBytes / per_vertex, &pt));
+    c->n_patches = (int)pt.eoff.size() - 1;
+    c->body_patch_off.assign(n_bodies + 1, 0);
+    int k = 0;
+    for (int b = 0; b <= n_bodies; ++b) {
+      while (k < c->n_patches && pt.eoff[k] < body_e_off[b]) ++k;
+      c->body_patch_off[b] = k;
+    }
+  }
+
   // SoA connectivity
   std::vector<int32_t> connh((size_t)(dim + 1) * n_e);
   for (int64_t e = 0; e < n_e; ++e)
@@ -568,6 +607,17 @@ isb_status isb_mesh_upload(isb_ctx* c, int dim, int32_t n_bodies, const int64_t*
   ISB_TRY(dalloc(L, &c->mass, (size_t)n_v));
   ISB_TRY(dalloc(L, &c->pinned, nd));
   ISB_TRY(dalloc(L, &c->clist, ne));
+  int32_t *p_eoff, *p_voff, *p_verts;
+  uint16_t* p_lconn;
+  ISB_TRY(dalloc(L, &p_eoff, pt.eoff.size()));
+  ISB_TRY(dalloc(L, &p_voff, pt.voff.size()));
+  ISB_TRY(dalloc(L, &p_verts, pt.verts.size()));
+  ISB_TRY(dalloc(L, &p_lconn, pt.lconn.size()));
+  ISB_HIP(hipMemcpy(p_eoff, pt.eoff.data(), pt.eoff.size() * 4, hipMemcpyHostToDevice));
+  ISB_HIP(hipMemcpy(p_voff, pt.voff.data(), pt.voff.size() * 4, hipMemcpyHostToDevice));
+  ISB_HIP(hipMemcpy(p_verts, pt.verts.data(), pt.verts.size() * 4, hipMemcpyHostToDevice));
+  ISB_HIP(hipMemcpy(p_lconn, pt.lconn.data(), pt.lconn.size() * 2, hipMemcpyHostToDevice));
+  c->plan = PatchPlan{p_eoff, p_voff, p_verts, p_lconn, pt.max_nv};
   if (c->precision == ISB_MIXED) {
     ISB_TRY(dalloc(L, &c->Dinv32, (size_t)dim * dim * ne));
     ISB_TRY(dalloc(L, &c->gf32, (size_t)dim * ne));
@@ -655,14 +705,15 @@ isb_status isb_set_option(isb_ctx* c, int key, int64_t value) {
       c->solver = (int)value;
       return ISB_OK;
     case ISB_OPT_SCATTER:
-      if (value != 0 && value != 1) return fail(ISB_E_ARG, "scatter must be 0 or 1");
+      if (value < 0 || value > 2) return fail(ISB_E_ARG, "scatter must be 0, 1 or 2");
       c->scatter = (int)value;
       return ISB_OK;
     case ISB_OPT_GRAPH_SAFE:
       c->graph_safe = value != 0;
       return ISB_OK;
     case ISB_OPT_BLOCK:
-      if (value != 256 && value != 512 && value != 1024) return fail(ISB_E_ARG, "block must be 256, 512 or 1024");
+      if (value != 0 && value != 256 && value != 512 && value != 1024)
+        return fail(ISB_E_ARG, "block must be 0 (automatic), 256, 512 or 1024");
       c->block = (int)value;
       return ISB_OK;
     case ISB_OPT_CG_CHECK:
@@ -681,7 +732,7 @@ isb_status isb_get_option(isb_ctx* c, int key, int64_t* value) {
     case ISB_OPT_SOLVER: *value = c->solver; return ISB_OK;
     case ISB_OPT_SCATTER: *value = c->scatter; return ISB_OK;
     case ISB_OPT_GRAPH_SAFE: *value = c->graph_safe; return ISB_OK;
-    case ISB_OPT_BLOCK: *value = c->block; return ISB_OK;
+    case ISB_OPT_BLOCK: *value = c->block > 0 ? c->block : (c->dim == 3 ? 512 : 1024); return ISB_OK;
     case ISB_OPT_CG_CHECK: *value = c->cg_check; return ISB_OK;
     case ISB_OPT_PRECISION: *value = c->precision; return ISB_OK;
     case ISB_INFO_N_VERTICES: *value = c->n_v; return ISB_OK;
@@ -786,9 +837,7 @@ isb_status isb_hessvec(isb_ctx* c, isb_stream stream, const double* x, const dou
   launch_copy(n, p, c->w_p, s);
   launch_mask(m, 0, c->n_v, c->w_p, s);
   launch_mul(n, c->w_vdiag, c->w_p, hp, s);
-  elem_ranges(c, -1, [&](ERange r, bool atomic) {
-    launch_elem_hv(m, dsc, r, atomic, c->precision, x, a, c->w_a32, c->w_p, hp, nullptr, s);
-  });
+  elem_scatter(c, -1, PATCH_HV, x, a, c->w_p, hp, nullptr, s);
   launch_mask(m, 0, c->n_v, hp, s);
   ISB_HIP(hipGetLastError());
   return ISB_OK;
@@ -802,10 +851,8 @@ isb_status isb_hessvec_elements(isb_ctx* c, isb_stream stream, const double* x, 
   hipStream_t s = (hipStream_t)stream;
   const DevMesh m = devmesh(c);
   const DevScene dsc = devscene(c);
-  if (c->precision == ISB_MIXED) launch_to_f32(c->n_e, a, c->w_a32, s);
-  elem_ranges(c, -1, [&](ERange r, bool atomic) {
-    launch_elem_hv(m, dsc, r, atomic, c->precision, x, a, c->w_a32, p, hp, nullptr, s);
-  });
+  // one pass: the element kernels read the FP64 actuation directly (no FP32 copy)
+  elem_scatter(c, -1, PATCH_HV, x, a, p, hp, nullptr, s, /*a32_copy=*/false);
   ISB_HIP(hipGetLastError());
   return ISB_OK;
 }
@@ -821,9 +868,7 @@ isb_status isb_hessdiag(isb_ctx* c, isb_stream stream, const double* x, const do
   if (c->precision == ISB_MIXED) launch_to_f32(c->n_e, a, c->w_a32, s);
   launch_setup(m, dsc, 0, c->n_v, x0, nullptr, c->w_xt, c->w_xhat, c->w_cv, s);
   launch_vertex_hdiag(m, dsc, 0, c->n_v, x, c->w_cv, diag, s);
-  elem_ranges(c, -1, [&](ERange r, bool atomic) {
-    launch_elem_diag(m, dsc, r, atomic, c->precision, x, a, c->w_a32, diag, s);
-  });
+  elem_scatter(c, -1, PATCH_DIAG, x, a, nullptr, diag, nullptr, s);
   launch_set_pinned(m, 0, c->n_v, 1.0, diag, s);
   ISB_HIP(hipGetLastError());
   return ISB_OK;

@@ -16,8 +16,10 @@
 
 namespace isb {
 
-template <int D, typename T, int MODE>  // MODE 0: step, 1: adjoint
-__global__ void __launch_bounds__(1024) k_batched(DevMesh m, DevScene sc, BatchArgs A) {
+// MODE 0: step, 1: adjoint. LB is the launch bound: 1024-thread workgroups get at most 128 VGPRs,
+// 512-thread ones 256, which the 3D and FP64 variants need to stay clear of spills.
+template <int D, typename T, int MODE, int LB>
+__global__ void __launch_bounds__(LB) k_batched(DevMesh m, DevScene sc, BatchArgs A) {
   extern __shared__ double smem[];
   batched_body<D, T, MODE>(m, sc, A, smem, (int)blockIdx.x, (int)gridDim.x);
 }
@@ -30,28 +32,42 @@ struct BatchedState {
   int32_t *order = nullptr, *voff = nullptr, *eoff = nullptr;
   DevStats* stats = nullptr;
   DevStats* hstats = nullptr;  // pinned host mirror
+  void* Fbuf = nullptr;        // per-element F and F d in the element precision
   int nacc = 0, grid = 0, block = 0, precision = -1, dim = 0;
   size_t lds = 0;
 };
 
-template <int D, typename T, int MODE>
+template <int D, typename T, int MODE, int LB>
 static void* kernel_ptr() {
-  return reinterpret_cast<void*>(&k_batched<D, T, MODE>);
+  return reinterpret_cast<void*>(&k_batched<D, T, MODE, LB>);
 }
 
-static void* pick_kernel(int dim, int precision, int mode) {
+template <int LB>
+static void* pick_lb(int dim, int precision, int mode) {
   if (dim == 2) {
-    if (precision == ISB_MIXED) return mode ? kernel_ptr<2, float, 1>() : kernel_ptr<2, float, 0>();
-    return mode ? kernel_ptr<2, double, 1>() : kernel_ptr<2, double, 0>();
+    if (precision == ISB_MIXED) return mode ? kernel_ptr<2, float, 1, LB>() : kernel_ptr<2, float, 0, LB>();
+    return mode ? kernel_ptr<2, double, 1, LB>() : kernel_ptr<2, double, 0, LB>();
   }
-  if (precision == ISB_MIXED) return mode ? kernel_ptr<3, float, 1>() : kernel_ptr<3, float, 0>();
-  return mode ? kernel_ptr<3, double, 1>() : kernel_ptr<3, double, 0>();
+  if (precision == ISB_MIXED) return mode ? kernel_ptr<3, float, 1, LB>() : kernel_ptr<3, float, 0, LB>();
+  return mode ? kernel_ptr<3, double, 1, LB>() : kernel_ptr<3, double, 0, LB>();
 }
 
+static void* pick_kernel(int dim, int precision, int mode, int block) {
+  return block > 512 ? pick_lb<1024>(dim, precision, mode) : pick_lb<512>(dim, precision, mode);
+}
+
+// LDS of one workgroup: reduction slots, the FP64 accumulator and the FP64 CG direction, sized for
+// the body with the most DOFs
 int64_t batched_lds_bytes(const isb_ctx* c) {
   int64_t mx = 0;
   for (int b = 0; b < c->n_bodies; ++b) mx = std::max<int64_t>(mx, (c->voff[b + 1] - c->voff[b]) * c->dim);
-  return (int64_t)(kRedSlots + mx) * (int64_t)sizeof(double);
+  return (int64_t)(kRedSlots + 2 * mx) * (int64_t)sizeof(double);
+}
+
+static int64_t batched_max_dof(const isb_ctx* c) {
+  int64_t mx = 0;
+  for (int b = 0; b < c->n_bodies; ++b) mx = std::max<int64_t>(mx, (c->voff[b + 1] - c->voff[b]) * c->dim);
+  return mx;
 }
 
 void batched_release(isb_ctx* c) {
@@ -65,7 +81,8 @@ void batched_release(isb_ctx* c) {
 
 isb_status batched_prepare(isb_ctx* c) {
   auto* st = static_cast<BatchedState*>(c->batched);
-  if (st && st->block == c->block && st->precision == c->precision && st->dim == c->dim) return ISB_OK;
+  const int want_block = c->block > 0 ? c->block : (c->dim == 2 ? 1024 : 512);
+  if (st && st->block == want_block && st->precision == c->precision && st->dim == c->dim) return ISB_OK;
   batched_release(c);
   st = new BatchedState();
   c->batched = st;
@@ -90,14 +107,16 @@ isb_status batched_prepare(isb_ctx* c) {
   if ((r = alloc((void**)&st->voff, (nb + 1) * 4)) != ISB_OK) return r;
   if ((r = alloc((void**)&st->eoff, (nb + 1) * 4)) != ISB_OK) return r;
   if ((r = alloc((void**)&st->stats, nb * sizeof(DevStats))) != ISB_OK) return r;
+  const size_t fwords = (size_t)(c->dim * c->dim + c->dim) * (size_t)c->n_e;
+  if ((r = alloc(&st->Fbuf, fwords * (c->precision == ISB_MIXED ? 4 : 8))) != ISB_OK) return r;
   ISB_HIP(hipHostMalloc((void**)&st->hstats, nb * sizeof(DevStats), hipHostMallocDefault));
   ISB_HIP(hipMemcpy(st->order, order.data(), nb * 4, hipMemcpyHostToDevice));
   ISB_HIP(hipMemcpy(st->voff, voff.data(), (nb + 1) * 4, hipMemcpyHostToDevice));
   ISB_HIP(hipMemcpy(st->eoff, eoff.data(), (nb + 1) * 4, hipMemcpyHostToDevice));
   ISB_HIP(hipMemset(st->stats, 0, nb * sizeof(DevStats)));
   st->lds = (size_t)batched_lds_bytes(c);
-  st->nacc = (int)(st->lds / sizeof(double)) - kRedSlots;
-  st->block = c->block;
+  st->nacc = (int)batched_max_dof(c);
+  st->block = c->block > 0 ? c->block : (c->dim == 2 ? 1024 : 512);
   st->precision = c->precision;
   st->dim = c->dim;
   int max_lds = 0, n_cu = 0;
@@ -108,7 +127,7 @@ isb_status batched_prepare(isb_ctx* c) {
                                " B of LDS, the device allows " + std::to_string(max_lds) + " B per workgroup");
   int occ = 0;
   for (int mode = 0; mode < 2; ++mode) {
-    void* k = pick_kernel(c->dim, c->precision, mode);
+    void* k = pick_kernel(c->dim, c->precision, mode, st->block);
     ISB_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)st->lds));
     int o = 0;
     ISB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, k, st->block, st->lds));
@@ -142,11 +161,12 @@ static BatchArgs make_args(isb_ctx* c, BatchedState* st) {
   A.max_newton = c->scene.max_newton;
   A.max_cg = c->scene.max_cg;
   A.nacc = st->nacc;
+  A.Fbuf = st->Fbuf;
   return A;
 }
 
 static isb_status launch(isb_ctx* c, BatchedState* st, hipStream_t s, int mode, const BatchArgs& A) {
-  void* k = pick_kernel(c->dim, c->precision, mode);
+  void* k = pick_kernel(c->dim, c->precision, mode, st->block);
   const DevMesh m = devmesh(c);
   const DevScene sc = devscene(c);
   void* args[] = {(void*)&m, (void*)&sc, (void*)&A};

@@ -46,6 +46,7 @@ struct BatchArgs {
   int max_newton, max_cg;
   int want_tail;  // 1: final energy and min/max J into the stats
   int nacc;       // LDS accumulator length: the largest body's DOF count
+  void* Fbuf;     // [(D*D + D)][n_e] per-element F and F d at the current Newton iterate (element precision)
 };
 
 constexpr int kRedSlots = 16 * 4;  // up to 16 waves x 4 values
@@ -122,7 +123,10 @@ struct BodySolver {
   const BatchArgs& A;
   double* acc;  // LDS [n_loc * D], zero between passes
   double* red;  // LDS reduction slots
+  double* ps;   // LDS [n_loc * D]: the CG direction p (FP64: the Hv pass takes differences of it)
   int v0, v1, e0, e1, n, base;
+
+  __device__ __forceinline__ T* Fb() const { return reinterpret_cast<T*>(A.Fbuf); }
 
   __device__ __forceinline__ bool pinned(int i) const { return m.pinned[base + i] != 0; }
 
@@ -161,19 +165,32 @@ struct BodySolver {
       return A.a32[e];
   }
 
-  __device__ void pass_hv(const double* x, const double* p) {
+  // Hessian-vector pass: element data and the stored F stream in coalesced; p comes from LDS
+  __device__ void pass_hv() {
+    const size_t ne = (size_t)m.n_e;
     for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
       int v[D + 1];
       load_conn<D>(m, e, v);
       ElemRest<D, T> R;
       load_rest<D, T>(m, e, R);
-      T Ds[D][D], dDs[D][D];
-      gather_edges<D, T>(x, v, Ds);
-      gather_edges<D, T>(p, v, dDs);
+      T F[D][D], Fd[D];
+#pragma unroll
+      for (int r = 0; r < D; ++r) {
+#pragma unroll
+        for (int c = 0; c < D; ++c) F[r][c] = Fb()[(size_t)(r * D + c) * ne + e];
+        Fd[r] = Fb()[(size_t)(D * D + r) * ne + e];
+      }
+      const T ae = act(e);
+      T dDs[D][D];
+      const int l0 = (v[0] - v0) * D;
+#pragma unroll
+      for (int j = 0; j < D; ++j)
+#pragma unroll
+        for (int c = 0; c < D; ++c) dDs[c][j] = T(ps[(v[j + 1] - v0) * D + c] - ps[l0 + c]);
       ElemState<D, T> S;
-      elem_state<D, T>(Ds, R, S);
+      elem_state_from_F<D, T>(F, Fd, S);
       T out[D + 1][D];
-      elem_hessvec<D, T>(R, S, act(e), dDs, out);
+      elem_hessvec<D, T>(R, S, ae, dDs, out);
       double o[D + 1][D];
 #pragma unroll
       for (int k = 0; k <= D; ++k)
@@ -183,16 +200,37 @@ struct BodySolver {
     }
   }
 
+  // diagonal pass; also stores F and F d of every element for the Hessian-vector passes that follow
   __device__ void pass_diag(const double* x) {
+    const size_t ne = (size_t)m.n_e;
     for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
       int v[D + 1];
       load_conn<D>(m, e, v);
+      ElemRest<D, double> R64;
+      load_rest<D, double>(m, e, R64);
+      double Ds[D][D];
+      gather_edges<D, double>(x, v, Ds);
+      double F64[D][D], Fd64[D];
+      mul_dinv<D, double>(Ds, R64.Dinv, F64);
+      T F[D][D], Fd[D];
+#pragma unroll
+      for (int r = 0; r < D; ++r) {
+        double acc_fd = 0.0;
+#pragma unroll
+        for (int j = 0; j < D; ++j) acc_fd += Ds[r][j] * R64.gf[j];
+        Fd64[r] = acc_fd;
+        Fd[r] = T(Fd64[r]);
+        Fb()[(size_t)(D * D + r) * ne + e] = Fd[r];
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+          F[r][c] = T(F64[r][c]);
+          Fb()[(size_t)(r * D + c) * ne + e] = F[r][c];
+        }
+      }
       ElemRest<D, T> R;
       load_rest<D, T>(m, e, R);
-      T Ds[D][D];
-      gather_edges<D, T>(x, v, Ds);
       ElemState<D, T> S;
-      elem_state<D, T>(Ds, R, S);
+      elem_state_from_F<D, T>(F, Fd, S);
       T out[D + 1][D];
       elem_hessdiag<D, T>(R, S, act(e), out);
       double o[D + 1][D];
@@ -319,21 +357,26 @@ struct BodySolver {
     wg_minmax(lo, hi, red);
   }
 
-  // PCG on H(x) xs = sign * rhs (masked to the free DOFs); returns the final r.r
-  __device__ double cg(const double* x, const double* rhs, double sign, double tol, int maxit, double* xs, int& iters,
-                       bool& neg) {
+  // PCG on H(x) xs = sign * rhs (masked to the free DOFs); returns the final r.r. The element
+  // state (F, F d) must have been stored by precond(x). Vector passes take kU owned DOFs per thread
+  // at a time and issue all their loads before any arithmetic.
+  static constexpr int kU = 2;
+
+  __device__ double cg(const double* rhs, double sign, double tol, int maxit, double* xs, int& iters, bool& neg) {
     double* r = A.r;
     double* p = A.p;
     const double* Dv = A.Dinvp;
     const double* vd = A.vdiag;
+    const int B = blockDim.x;
     double rz = 0.0, rr = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    for (int i = threadIdx.x; i < n; i += B) {
       const int g = base + i;
       const double di = Dv[g];
       const double ri = di != 0.0 ? sign * rhs[g] : 0.0;
       const double zi = di * ri;
       r[g] = ri;
       p[g] = zi;
+      ps[i] = zi;
       xs[g] = 0.0;
       rz += ri * zi;
       rr += ri * ri;
@@ -349,21 +392,36 @@ struct BodySolver {
     const double tol2 = tol * tol;
     if (rr <= tol2) return rr;
     for (int it = 0; it < maxit; ++it) {
-      pass_hv(x, p);
+      pass_hv();
       __syncthreads();
       double pHp = 0.0;
-      for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        const int g = base + i;
-        const double hp = acc[i] + vd[g] * p[g];
-        acc[i] = hp;
-        pHp += p[g] * hp;
+      for (int i0 = threadIdx.x; i0 < n; i0 += kU * B) {
+        double pv[kU], dv[kU], av[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const int i = i0 + u * B;
+          if (i < n) {
+            pv[u] = p[base + i];
+            dv[u] = vd[base + i];
+            av[u] = acc[i];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const int i = i0 + u * B;
+          if (i < n) {
+            const double hp = av[u] + dv[u] * pv[u];
+            acc[i] = hp;
+            pHp += pv[u] * hp;
+          }
+        }
       }
       pHp = wg_sum1(pHp, red);
       if (!(pHp > 0.0)) {
         // non-positive curvature: stop; on the first iteration keep the preconditioned
         // steepest-descent direction (Nocedal & Wright, Alg. 7.1)
         neg = true;
-        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        for (int i = threadIdx.x; i < n; i += B) {
           if (it == 0) xs[base + i] = p[base + i];
           acc[i] = 0.0;
         }
@@ -373,15 +431,33 @@ struct BodySolver {
       const double alpha = rz / pHp;
       double rz1 = 0.0;
       rr = 0.0;
-      for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        const int g = base + i;
-        xs[g] += alpha * p[g];
-        const double di = Dv[g];
-        const double ri = di != 0.0 ? r[g] - alpha * acc[i] : 0.0;
-        r[g] = ri;
-        acc[i] = 0.0;
-        rz1 += ri * di * ri;
-        rr += ri * ri;
+      for (int i0 = threadIdx.x; i0 < n; i0 += kU * B) {
+        double xv[kU], pv[kU], dv[kU], rv[kU], hv[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const int i = i0 + u * B;
+          if (i < n) {
+            const int g = base + i;
+            xv[u] = xs[g];
+            pv[u] = p[g];
+            dv[u] = Dv[g];
+            rv[u] = r[g];
+            hv[u] = acc[i];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const int i = i0 + u * B;
+          if (i < n) {
+            const int g = base + i;
+            xs[g] = xv[u] + alpha * pv[u];
+            const double ri = dv[u] != 0.0 ? rv[u] - alpha * hv[u] : 0.0;
+            r[g] = ri;
+            acc[i] = 0.0;
+            rz1 += ri * dv[u] * ri;
+            rr += ri * ri;
+          }
+        }
       }
       {
         double t[2] = {rz1, rr};
@@ -393,9 +469,27 @@ struct BodySolver {
       if (rr <= tol2) break;
       const double beta = rz1 / rz;
       rz = rz1;
-      for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        const int g = base + i;
-        p[g] = Dv[g] * r[g] + beta * p[g];
+      for (int i0 = threadIdx.x; i0 < n; i0 += kU * B) {
+        double pv[kU], dv[kU], rv[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const int i = i0 + u * B;
+          if (i < n) {
+            const int g = base + i;
+            pv[u] = p[g];
+            dv[u] = Dv[g];
+            rv[u] = r[g];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const int i = i0 + u * B;
+          if (i < n) {
+            const double pn = dv[u] * rv[u] + beta * pv[u];
+            p[base + i] = pn;
+            ps[i] = pn;
+          }
+        }
       }
       __syncthreads();
     }
@@ -431,7 +525,7 @@ struct BodySolver {
       const double eta = fmin(0.5, sqrt(res / res0));
       int it = 0;
       bool neg = false;
-      cg(x, G, -1.0, eta * res, A.max_cg, dx, it, neg);
+      cg(G, -1.0, eta * res, A.max_cg, dx, it, neg);
       st.cg_iters += it;
       st.negcurv_exits += neg ? 1 : 0;
       double gTd = 0.0;
@@ -526,7 +620,7 @@ struct BodySolver {
       for (int i = threadIdx.x; i < n; i += blockDim.x) A.w[base + i] = 0.0;
     } else {
       precond(x);
-      rr = cg(x, A.G, 1.0, A.adj_tol * bnorm, A.max_cg, A.w, it, neg);
+      rr = cg(A.G, 1.0, A.adj_tol * bnorm, A.max_cg, A.w, it, neg);
     }
     st.adj_cg_iters = it;
     st.adj_res_final = bnorm > 0.0 ? sqrt(rr) / bnorm : 0.0;
@@ -548,6 +642,7 @@ template <int D, typename T, int MODE>  // MODE 0: step, 1: adjoint
 __device__ void batched_body(const DevMesh& m, const DevScene& sc, const BatchArgs& A, double* smem, int g, int G) {
   double* red = smem;
   double* acc = smem + kRedSlots;
+  double* ps = acc + A.nacc;
   // the accumulator starts at zero; every pass clears the entries it used
   for (int i = threadIdx.x; i < A.nacc; i += blockDim.x) acc[i] = 0.0;
   __syncthreads();
@@ -557,7 +652,7 @@ __device__ void batched_body(const DevMesh& m, const DevScene& sc, const BatchAr
     const int body = wg_uniform(A.order[k]);
     const int bv0 = wg_uniform(A.voff[body]), bv1 = wg_uniform(A.voff[body + 1]);
     const int be0 = wg_uniform(A.eoff[body]), be1 = wg_uniform(A.eoff[body + 1]);
-    BodySolver<D, T> S{m, sc, A, acc, red, bv0, bv1, be0, be1, (bv1 - bv0) * D, bv0 * D};
+    BodySolver<D, T> S{m, sc, A, acc, red, ps, bv0, bv1, be0, be1, (bv1 - bv0) * D, bv0 * D};
     DevStats st;
     memset(&st, 0, sizeof(st));
     if (MODE == 0)

@@ -37,10 +37,15 @@ struct isb_ctx {
   std::vector<int32_t> col_off;
   int32_t* clist = nullptr;
 
+  // element patches of the LDS-staged scatter; body b owns patches [body_patch_off[b], body_patch_off[b+1])
+  int n_patches = 0;
+  std::vector<int32_t> body_patch_off;
+  isb::PatchPlan plan{};
+
   isb_scene scene{};
 
   // options
-  int solver = 0, scatter = 0, graph_safe = 0, block = 1024, cg_check = 4;
+  int solver = 0, scatter = 2, graph_safe = 0, block = 0 /* 0: 1024 in 2D, 512 in 3D */, cg_check = 4;
 
   // plain-solver workspaces, [n_v*dim] unless noted
   double *w_x = nullptr, *w_xt = nullptr, *w_xhat = nullptr, *w_cv = nullptr /*[n_v]*/, *w_G = nullptr,

@@ -115,6 +115,30 @@ __device__ __forceinline__ void elem_state(const T Ds[D][D], const ElemRest<D, T
   for (int r = 0; r < D; ++r) S.n[r] *= S.sinv;
 }
 
+// the same state from a stored F and F d (no vertex gather)
+template <int D, typename T>
+__device__ __forceinline__ void elem_state_from_F(const T F[D][D], const T Fd[D], ElemState<D, T>& S) {
+#pragma unroll
+  for (int r = 0; r < D; ++r)
+#pragma unroll
+    for (int c = 0; c < D; ++c) S.F[r][c] = F[r][c];
+  cofactor<D, T>(S.F, S.C);
+  T J = T(0);
+#pragma unroll
+  for (int r = 0; r < D; ++r) J += S.F[r][0] * S.C[r][0];
+  S.J = J;
+  const T jm1 = J - T(1);
+  S.l = jm1 - T(0.5) * jm1 * jm1;
+  S.dl = T(2) - J;
+  T ss = T(0);
+#pragma unroll
+  for (int r = 0; r < D; ++r) ss += Fd[r] * Fd[r];
+  S.s = sqrt(ss);
+  S.sinv = S.s > T(0) ? T(1) / S.s : T(0);
+#pragma unroll
+  for (int r = 0; r < D; ++r) S.n[r] = Fd[r] * S.sinv;
+}
+
 // W psi(F)
 template <int D, typename T>
 __device__ __forceinline__ T elem_energy(const ElemRest<D, T>& R, const ElemState<D, T>& S, T a) {

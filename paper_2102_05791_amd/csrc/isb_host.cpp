@@ -2,6 +2,7 @@
 // Nothing here touches the GPU, so these entry points work on a machine without one.
 #include <stdint.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <string>
@@ -86,6 +87,55 @@ isb_status colour_elements(int dim, int64_t n_v, int64_t n_e, const int32_t* T, 
     if (c + 1 > nc) nc = c + 1;
   }
   *n_colours = nc;
+  return ISB_OK;
+}
+
+isb_status build_patches(int dim, int64_t n_v, int n_bodies, const int64_t* eoff, const int32_t* T,
+                         int max_elems, int max_verts, Patches* out) {
+  const int64_t n_e = eoff[n_bodies];
+  out->eoff.assign(1, 0);
+  out->voff.assign(1, 0);
+  out->verts.clear();
+  out->lconn.assign((size_t)(dim + 1) * (size_t)n_e, 0);
+  out->max_nv = 0;
+  // mark[v] = last patch that took vertex v, so that each corner is counted in O(1)
+  std::vector<int32_t> mark((size_t)n_v, -1);
+  std::vector<int32_t> ids;
+  int32_t patch = 0;
+  for (int b = 0; b < n_bodies; ++b) {
+    // about a thousand patches per body when it is large enough, so that the launch fills the GPU
+    const int64_t me = std::min<int64_t>(max_elems, std::max<int64_t>(256, (eoff[b + 1] - eoff[b]) / 1024));
+    int64_t e = eoff[b];
+    while (e < eoff[b + 1]) {
+      const int64_t start = e;
+      ids.clear();
+      while (e < eoff[b + 1] && e - start < me) {
+        const int32_t* t = T + e * (dim + 1);
+        int fresh = 0;
+        for (int k = 0; k <= dim; ++k) fresh += mark[t[k]] != patch;
+        if ((int64_t)ids.size() + fresh > max_verts) break;
+        for (int k = 0; k <= dim; ++k)
+          if (mark[t[k]] != patch) {
+            mark[t[k]] = patch;
+            ids.push_back(t[k]);
+          }
+        ++e;
+      }
+      if (e == start) return fail(ISB_E_MESH, "patch builder: one element exceeds the vertex budget");
+      std::sort(ids.begin(), ids.end());
+      for (int64_t f = start; f < e; ++f)
+        for (int k = 0; k <= dim; ++k) {
+          const int32_t g = T[f * (dim + 1) + k];
+          const auto it = std::lower_bound(ids.begin(), ids.end(), g);
+          out->lconn[(size_t)k * n_e + f] = (uint16_t)(it - ids.begin());
+        }
+      out->verts.insert(out->verts.end(), ids.begin(), ids.end());
+      out->eoff.push_back((int32_t)e);
+      out->voff.push_back((int32_t)out->verts.size());
+      out->max_nv = std::max<int>(out->max_nv, (int)ids.size());
+      ++patch;
+    }
+  }
   return ISB_OK;
 }
 

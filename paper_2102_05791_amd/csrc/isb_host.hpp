@@ -4,6 +4,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/isb.h"
 
@@ -15,5 +16,16 @@ const char* last_error();
 isb_status validate_mesh(int dim, int64_t n_v, const double* X, int64_t n_e, const int32_t* T, int32_t n_bodies,
                          const int64_t* voff, const int64_t* eoff);
 isb_status colour_elements(int dim, int64_t n_v, int64_t n_e, const int32_t* T, int32_t* colour, int32_t* n_colours);
+
+// Element patches for the LDS-staged scatter: patch k holds the consecutive elements
+// [eoff[k], eoff[k+1]) of one body and the sorted distinct vertices verts[voff[k] .. voff[k+1]);
+// lconn[(d+1)][n_e] gives each element corner's index into its patch's vertex list.
+struct Patches {
+  std::vector<int32_t> eoff, voff, verts;
+  std::vector<uint16_t> lconn;
+  int max_nv = 0;
+};
+isb_status build_patches(int dim, int64_t n_v, int n_bodies, const int64_t* eoff, const int32_t* T,
+                         int max_elems, int max_verts, Patches* out);
 
 }  // namespace isb

@@ -45,6 +45,20 @@ struct ERange {
   const int32_t* list;
 };
 
+// Element patches of the LDS-staged scatter (see Patches in isb_host.hpp), on the device.
+struct PatchPlan {
+  const int32_t* eoff;    // [n_patch+1] element range of each patch
+  const int32_t* voff;    // [n_patch+1] range of each patch's vertex list
+  const int32_t* verts;   // distinct vertices of each patch, sorted
+  const uint16_t* lconn;  // [(D+1)][n_e] corner index into the patch's vertex list
+  int max_nv;             // largest vertex list
+};
+
+constexpr int kPatchBlock = 512;        // threads per patch workgroup
+constexpr int kPatchLdsBytes = 64 * 1024;  // LDS per patch workgroup (two workgroups per CU)
+
+enum PatchOp { PATCH_GRAD = 0, PATCH_HV = 1, PATCH_DIAG = 2 };
+
 // Device-resident CG scalars of the plain solver (one solve at a time).
 struct CgScal {
   double rz[2];    // r.z of the current iterate, double-buffered by iteration parity
@@ -101,6 +115,11 @@ void launch_elem_vjp(const DevMesh& m, const DevScene& sc, ERange r, const doubl
 void launch_elem_minmax_J(const DevMesh& m, ERange r, const double* x, double* partials, hipStream_t s,
                           int* nblocks_out);
 void launch_to_f32(int n, const double* src, float* dst, hipStream_t s);
+// LDS-staged scatter over patches [p0, p1): op = PatchOp; p is the Hessian-vector operand (HV only);
+// out receives one global atomic add per distinct vertex DOF of each patch
+void launch_elem_patch(const DevMesh& m, const DevScene& sc, const PatchPlan& P, int p0, int p1, int op,
+                       int precision, const double* x, const double* a, const float* a32, const double* p,
+                       double* out, const int* done, hipStream_t s);
 
 // ---- reductions and CG vector kernels (vectors of length n, pointers already offset) ----
 // partial sums of ncomp products per block; finalize into out[0..ncomp)

@@ -398,7 +398,7 @@ __global__ void __launch_bounds__(kBlock) k_elem_hv(DevMesh m, DevScene sc, ERan
     gather_edges<D, T>(p, v, dDs);
     ElemState<D, T> S;
     elem_state<D, T>(Ds, R, S);
-    const T ae = std::is_same<T, double>::value ? T(a[e]) : T(a32[e]);
+    const T ae = (std::is_same<T, float>::value && a32) ? T(a32[e]) : T(a[e]);
     T out[D + 1][D];
     elem_hessvec<D, T>(R, S, ae, dDs, out);
     scatter_vertices<D, ATOMIC, T>(Hp, v, out, sc.s_pot);
@@ -419,7 +419,7 @@ __global__ void __launch_bounds__(kBlock) k_elem_diag(DevMesh m, DevScene sc, ER
     gather_edges<D, T>(x, v, Ds);
     ElemState<D, T> S;
     elem_state<D, T>(Ds, R, S);
-    const T ae = std::is_same<T, double>::value ? T(a[e]) : T(a32[e]);
+    const T ae = (std::is_same<T, float>::value && a32) ? T(a32[e]) : T(a[e]);
     T out[D + 1][D];
     elem_hessdiag<D, T>(R, S, ae, out);
     scatter_vertices<D, ATOMIC, T>(diag, v, out, sc.s_pot);
@@ -898,6 +898,114 @@ void launch_min_count(int n, const double* a, double* partials, double* out, hip
   const int nb = red_blocks(n);
   k_min_count<<<nb, kBlock, 0, s>>>(n, a, partials);
   k_finalize_minmax<<<1, kBlock, 0, s>>>(partials, nb, out);
+}
+
+// ---------------------------------------------------------------------------------------------
+// LDS-staged scatter over element patches
+// ---------------------------------------------------------------------------------------------
+// One workgroup per patch (grid-stride over patches): stage x (and p) of the patch's distinct
+// vertices in LDS, evaluate the elements with LDS gathers and accumulate with LDS atomics, then
+// add each distinct vertex DOF to the global output once. Global atomics drop from d(d+1) per
+// element to the patch's distinct DOFs, and they no longer collide inside a wavefront.
+template <int D, typename T, int OP>
+__global__ void __launch_bounds__(kPatchBlock) k_elem_patch(DevMesh m, DevScene sc, PatchPlan P, int p0, int p1,
+                                                            const double* __restrict__ x,
+                                                            const double* __restrict__ a,
+                                                            const float* __restrict__ a32,
+                                                            const double* __restrict__ pv, double* out,
+                                                            const int* done) {
+  // LDS: x, the accumulator and the Hessian-vector operand p per patch DOF, all FP64: the element
+  // takes differences of x and of p, which must be formed before any rounding to T
+  extern __shared__ double lds[];
+  if (OP == PATCH_HV && done && *done) return;
+  const int nmax = P.max_nv * D;
+  double* xs = lds;
+  double* acc = lds + nmax;
+  double* ps = lds + 2 * nmax;
+  for (int pk = p0 + blockIdx.x; pk < p1; pk += gridDim.x) {
+    const int vb = P.voff[pk], nv = P.voff[pk + 1] - vb;
+    const int eb = P.eoff[pk], ee = P.eoff[pk + 1];
+    for (int i = threadIdx.x; i < nv * D; i += blockDim.x) {
+      const int vl = i / D, c = i - vl * D;
+      const size_t g = (size_t)P.verts[vb + vl] * D + c;
+      xs[i] = x[g];
+      if (OP == PATCH_HV) ps[i] = pv[g];
+      acc[i] = 0.0;
+    }
+    __syncthreads();
+    for (int e = eb + threadIdx.x; e < ee; e += blockDim.x) {
+      int l[D + 1];
+#pragma unroll
+      for (int k = 0; k <= D; ++k) l[k] = P.lconn[(size_t)k * m.n_e + e];
+      ElemRest<D, T> R;
+      load_rest<D, T>(m, e, R);
+      T Ds[D][D];
+#pragma unroll
+      for (int j = 0; j < D; ++j)
+#pragma unroll
+        for (int c = 0; c < D; ++c) Ds[c][j] = T(xs[l[j + 1] * D + c] - xs[l[0] * D + c]);
+      ElemState<D, T> S;
+      elem_state<D, T>(Ds, R, S);
+      // actuation in the element precision: the FP32 copy when the caller made one
+      const T ae = (std::is_same<T, float>::value && a32) ? T(a32[e]) : T(a[e]);
+      T o[D + 1][D];
+      if constexpr (OP == PATCH_GRAD) {
+        elem_grad<D, T>(R, S, ae, o);
+      } else if constexpr (OP == PATCH_HV) {
+        T dDs[D][D];
+#pragma unroll
+        for (int j = 0; j < D; ++j)
+#pragma unroll
+          for (int c = 0; c < D; ++c) dDs[c][j] = T(ps[l[j + 1] * D + c] - ps[l[0] * D + c]);
+        elem_hessvec<D, T>(R, S, ae, dDs, o);
+      } else {
+        elem_hessdiag<D, T>(R, S, ae, o);
+      }
+#pragma unroll
+      for (int k = 0; k <= D; ++k)
+#pragma unroll
+        for (int c = 0; c < D; ++c) unsafeAtomicAdd(acc + l[k] * D + c, sc.s_pot * double(o[k][c]));
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nv * D; i += blockDim.x) {
+      const int vl = i / D, c = i - vl * D;
+      unsafeAtomicAdd(out + (size_t)P.verts[vb + vl] * D + c, acc[i]);
+    }
+    __syncthreads();
+  }
+}
+
+template <int D, typename T, int OP>
+static void patch_launch(const DevMesh& m, const DevScene& sc, const PatchPlan& P, int p0, int p1, const double* x,
+                         const double* a, const float* a32, const double* p, double* out, const int* done,
+                         hipStream_t s) {
+  const size_t lds = (size_t)P.max_nv * D * sizeof(double) * (OP == PATCH_HV ? 3 : 2);
+  int grid = p1 - p0;
+  if (grid > 65535) grid = 65535;
+  k_elem_patch<D, T, OP><<<grid, kPatchBlock, lds, s>>>(m, sc, P, p0, p1, x, a, a32, p, out, done);
+}
+
+void launch_elem_patch(const DevMesh& m, const DevScene& sc, const PatchPlan& P, int p0, int p1, int op,
+                       int precision, const double* x, const double* a, const float* a32, const double* p,
+                       double* out, const int* done, hipStream_t s) {
+  if (p1 <= p0) return;
+#define ISB_PATCH_CASE(D_)                                                                          \
+  if (op == PATCH_GRAD)                                                                             \
+    patch_launch<D_, double, PATCH_GRAD>(m, sc, P, p0, p1, x, a, a32, p, out, done, s);             \
+  else if (op == PATCH_HV && precision)                                                             \
+    patch_launch<D_, float, PATCH_HV>(m, sc, P, p0, p1, x, a, a32, p, out, done, s);                \
+  else if (op == PATCH_HV)                                                                          \
+    patch_launch<D_, double, PATCH_HV>(m, sc, P, p0, p1, x, a, a32, p, out, done, s);               \
+  else if (precision)                                                                               \
+    patch_launch<D_, float, PATCH_DIAG>(m, sc, P, p0, p1, x, a, a32, p, out, done, s);              \
+  else                                                                                              \
+    patch_launch<D_, double, PATCH_DIAG>(m, sc, P, p0, p1, x, a, a32, p, out, done, s);
+  if (m.dim == 2) {
+    ISB_PATCH_CASE(2)
+  } else {
+    ISB_PATCH_CASE(3)
+  }
+#undef ISB_PATCH_CASE
 }
 
 }  // namespace isb

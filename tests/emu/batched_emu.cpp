@@ -22,7 +22,7 @@ static void run(int block, const isb::DevMesh* m, const isb::DevScene* sc, const
   isb_emu::g_wg = &wg;
   blockDim.x = block;
   gridDim.x = 1;
-  std::vector<double> smem(isb::kRedSlots + A->nacc, -12345.0);
+  std::vector<double> smem(isb::kRedSlots + 2 * (size_t)A->nacc, -12345.0);
   std::vector<std::thread> th;
   for (int t = 0; t < block; ++t)
     th.emplace_back([&, t]() {

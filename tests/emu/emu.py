@@ -38,7 +38,7 @@ class BatchArgs(ctypes.Structure):
                 ("x0", vp), ("v0", vp), ("a", vp), ("a32", vp), ("x1", vp), ("v1", vp), ("xbar", vp),
                 ("vbar", vp), ("w", vp), ("xhat", vp), ("G", vp), ("Gt", vp), ("dx", vp), ("r", vp), ("p", vp),
                 ("Dinvp", vp), ("vdiag", vp), ("cv", vp), ("stats", vp), ("tol", cd), ("adj_tol", cd),
-                ("max_newton", ci), ("max_cg", ci), ("want_tail", ci), ("nacc", ci)]
+                ("max_newton", ci), ("max_cg", ci), ("want_tail", ci), ("nacc", ci), ("Fbuf", vp)]
 
 
 STATS_DTYPE = np.dtype([("newton_iters", "<i4"), ("cg_iters", "<i4"), ("adj_cg_iters", "<i4"),
@@ -111,6 +111,7 @@ class EmuBatch:
         self.ws = {n: k(np.zeros(nd)) for n in ("xhat", "G", "Gt", "dx", "r", "p", "Dinvp", "vdiag")}
         self.cv = k(np.zeros(w.n_v))
         self.stats = k(np.zeros(nb, dtype=STATS_DTYPE))
+        self.Fbuf = k(np.zeros((d * d + d) * w.n_e, dtype=np.float64))
         self.be = be
 
     def _args(self, **kw):
@@ -125,6 +126,7 @@ class EmuBatch:
         A.tol, A.adj_tol = sc["tol_rel"], sc["adj_tol_rel"]
         A.max_newton, A.max_cg = sc["max_newton"], sc["max_cg"]
         A.nacc = self.nacc
+        A.Fbuf = _p(self.Fbuf)
         for key, val in kw.items():
             setattr(A, key, val)
         return A

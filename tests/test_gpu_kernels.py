@@ -29,7 +29,7 @@ def _state(w, rng):
 
 
 @pytest.mark.parametrize("case", CASES, ids=IDS)
-@pytest.mark.parametrize("scatter", [0, 1], ids=["atomic", "colour"])
+@pytest.mark.parametrize("scatter", [0, 1, 2], ids=["atomic", "colour", "patch"])
 def test_gradient_energy_parity_fp64(case, scatter):
     dim, integ, pin, nb = case
     w, rng = rand_workload(dim, seed=1, integrator=integ, pinned_left=pin, bodies=nb)
@@ -52,7 +52,7 @@ def test_gradient_energy_parity_fp64(case, scatter):
 
 @pytest.mark.parametrize("case", CASES, ids=IDS)
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 2e-6)])
-@pytest.mark.parametrize("scatter", [0, 1], ids=["atomic", "colour"])
+@pytest.mark.parametrize("scatter", [0, 1, 2], ids=["atomic", "colour", "patch"])
 def test_hessvec_hessdiag_parity(case, precision, tol, scatter):
     dim, integ, pin, nb = case
     w, rng = rand_workload(dim, seed=2, integrator=integ, pinned_left=pin, bodies=nb)
@@ -106,3 +106,57 @@ def test_mass_matches_oracle():
     m = ctx.mass().cpu().numpy()
     ref = problems(w)[0].mesh.mass
     assert rel(m, ref) <= 1e-15
+
+
+@pytest.mark.parametrize("dim,shape", [(2, (130, 65)), (3, (16, 16, 11))], ids=["2d-16900", "3d-16896"])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 2e-6)])
+def test_patch_scatter_large_mesh(dim, shape, precision, tol):
+    """Meshes above the patch threshold take the LDS-staged patch scatter (isb scatter mode 2)."""
+    w, rng = rand_workload(dim, seed=6, shape=shape)
+    assert w.n_e >= 16384
+    ctx = _ctx(w, precision=precision, scatter=2)
+    x = _state(w, rng)
+    a = w.actions[0]
+    pv = rng.normal(size=x.shape)
+    p = problems(w)[0]
+    G = ctx.gradient(_dev(x), _dev(w.x0), _dev(w.v0), _dev(a)).cpu().numpy()
+    Gref = p.grad(x, w.x0, w.v0, a)
+    assert rel(G, Gref, abs_assembly(p, x, w.x0, w.v0, a)) <= 1e-13
+    H = p.hessian(x, w.x0, a)
+    Hp = ctx.hessvec(_dev(x), _dev(w.x0), _dev(a), _dev(pv)).cpu().numpy().ravel()
+    assert rel(Hp, H @ pv.ravel(), abs(H) @ np.abs(pv.ravel())) <= tol
+    Hd = ctx.hessdiag(_dev(x), _dev(w.x0), _dev(a)).cpu().numpy().ravel()
+    assert rel(Hd, H.diagonal()) <= tol
+    he = ctx.hessvec_elements(_dev(x), _dev(a), _dev(pv), _dev(np.zeros_like(x))).cpu().numpy().ravel()
+    Hv_vertex = _elem_free_hessian(p, x, w.x0, a) @ pv.ravel()
+    assert rel(he, H @ pv.ravel() - Hv_vertex, abs(H) @ np.abs(pv.ravel())) <= tol
+
+
+def _elem_free_hessian(p, x, x0, a):
+    """The assembled Hessian with the element terms removed (vertex terms only)."""
+    import scipy.sparse as sp
+    from oracle import fem
+    K = p.s_pot * fem.element_hessians(p.mesh, x, p.mu, p.lam, p.kf, a, p.fd)
+    d = p.mesh.d
+    dofs = (p.mesh.T[:, :, None] * d + np.arange(d)[None, None, :]).reshape(p.mesh.n_e, -1)
+    rows = np.repeat(dofs, dofs.shape[1], axis=1).ravel()
+    cols = np.tile(dofs, (1, dofs.shape[1])).ravel()
+    n = p.mesh.n_v * d
+    return p.hessian(x, x0, a) - sp.coo_matrix((K.ravel(), (rows, cols)), shape=(n, n)).tocsr()
+
+
+@pytest.mark.parametrize("scatter", [0, 2], ids=["atomic", "patch"])
+@pytest.mark.parametrize("dim,shape", [(2, (130, 65)), (3, (16, 16, 11))], ids=["2d", "3d"])
+def test_mixed_hessvec_smooth_operand(dim, shape, scatter):
+    """p = large constant + small smooth field: the element sees only differences of p, which must
+    be formed in FP64 before rounding to the FP32 element precision (cancellation otherwise)."""
+    w, rng = rand_workload(dim, seed=7, shape=shape)
+    ctx = _ctx(w, precision="mixed", scatter=scatter)
+    x = _state(w, rng)
+    a = w.actions[0]
+    pv = 1e3 + 1e-2 * np.sin(w.X @ np.arange(1, dim + 1) * 0.1)[:, None] * np.ones((1, dim))
+    he = ctx.hessvec_elements(_dev(x), _dev(a), _dev(pv), _dev(np.zeros_like(x))).cpu().numpy().ravel()
+    p = problems(w)[0]
+    Hp = (p.hessian(x, w.x0, a) - _elem_free_hessian(p, x, w.x0, a)) @ pv.ravel()
+    scale = abs(p.hessian(x, w.x0, a) - _elem_free_hessian(p, x, w.x0, a)) @ np.abs(pv - pv.mean()).ravel()
+    assert rel(he, Hp, scale) <= 1e-5
