@@ -33,6 +33,7 @@ struct BatchedState {
   DevStats* stats = nullptr;
   DevStats* hstats = nullptr;  // pinned host mirror
   void* Fbuf = nullptr;        // per-element F and F d in the element precision
+  double *E0 = nullptr, *E1 = nullptr;  // per-element energies (iterate, trial)
   int nacc = 0, grid = 0, block = 0, precision = -1, dim = 0;
   size_t lds = 0;
 };
@@ -109,6 +110,8 @@ isb_status batched_prepare(isb_ctx* c) {
   if ((r = alloc((void**)&st->stats, nb * sizeof(DevStats))) != ISB_OK) return r;
   const size_t fwords = (size_t)(c->dim * c->dim + c->dim) * (size_t)c->n_e;
   if ((r = alloc(&st->Fbuf, fwords * (c->precision == ISB_MIXED ? 4 : 8))) != ISB_OK) return r;
+  if ((r = alloc((void**)&st->E0, (size_t)c->n_e * sizeof(double))) != ISB_OK) return r;
+  if ((r = alloc((void**)&st->E1, (size_t)c->n_e * sizeof(double))) != ISB_OK) return r;
   ISB_HIP(hipHostMalloc((void**)&st->hstats, nb * sizeof(DevStats), hipHostMallocDefault));
   ISB_HIP(hipMemcpy(st->order, order.data(), nb * 4, hipMemcpyHostToDevice));
   ISB_HIP(hipMemcpy(st->voff, voff.data(), (nb + 1) * 4, hipMemcpyHostToDevice));
@@ -162,6 +165,8 @@ static BatchArgs make_args(isb_ctx* c, BatchedState* st) {
   A.max_cg = c->scene.max_cg;
   A.nacc = st->nacc;
   A.Fbuf = st->Fbuf;
+  A.E0 = st->E0;
+  A.E1 = st->E1;
   return A;
 }
 

@@ -47,6 +47,7 @@ struct BatchArgs {
   int want_tail;  // 1: final energy and min/max J into the stats
   int nacc;       // LDS accumulator length: the largest body's DOF count
   void* Fbuf;     // [(D*D + D)][n_e] per-element F and F d at the current Newton iterate (element precision)
+  double *E0, *E1;  // [n_e] per-element energies at the iterate and at the line-search trial
 };
 
 constexpr int kRedSlots = 16 * 4;  // up to 16 waves x 4 values
@@ -136,26 +137,6 @@ struct BodySolver {
     for (int k = 0; k <= D; ++k)
 #pragma unroll
       for (int c = 0; c < D; ++c) unsafeAtomicAdd(acc + (v[k] - v0) * D + c, scale * out[k][c]);
-  }
-
-  // gradient of the element energies at x + alpha dx (dx may be null)
-  __device__ void pass_grad(const double* x, const double* dxp, double alpha) {
-    for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-      int v[D + 1];
-      load_conn<D>(m, e, v);
-      ElemRest<D, double> R;
-      load_rest<D, double>(m, e, R);
-      double Ds[D][D];
-      if (dxp)
-        gather_edges_step<D>(x, dxp, alpha, v, Ds);
-      else
-        gather_edges<D, double>(x, v, Ds);
-      ElemState<D, double> S;
-      elem_state<D, double>(Ds, R, S);
-      double out[D + 1][D];
-      elem_grad<D, double>(R, S, A.a[e], out);
-      lds_scatter(v, out, sc.s_pot);
-    }
   }
 
   __device__ __forceinline__ T act(int e) const {
@@ -264,22 +245,6 @@ struct BodySolver {
     return hd;
   }
 
-  // gradient at x + alpha dx into Gout (0 on pinned DOFs); returns |G|^2
-  __device__ double gradient(const double* x, const double* dxp, double alpha, double* Gout) {
-    pass_grad(x, dxp, alpha);
-    __syncthreads();
-    double s = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-      const double xi = dxp ? x[base + i] + alpha * dxp[base + i] : x[base + i];
-      double g = acc[i] + vgrad(i, xi);
-      acc[i] = 0.0;
-      if (pinned(i)) g = 0.0;
-      Gout[base + i] = g;
-      s += g * g;
-    }
-    return wg_sum1(s, red);
-  }
-
   // Jacobi preconditioner 1/|diag H| and the vertex-term diagonal
   __device__ void precond(const double* x) {
     pass_diag(x);
@@ -295,28 +260,59 @@ struct BodySolver {
     __syncthreads();
   }
 
-  // (sum of g_e(x + alpha dx) - g_e(x), sum |g_e(x)|, g(x + alpha dx)) over elements and vertices
-  __device__ void energy(const double* x, const double* dxp, double alpha, double out[3]) {
+  // One element pass at the trial point xt = x + alpha dx (x itself when dx is null). It returns
+  // out = (sum of g_e(xt) - g_e(x) over elements and vertices, sum |g_e(x)|, g(xt), |grad g(xt)|^2)
+  // -- the element differences use the stored energies Ecur of x, the new ones go to Enew -- and
+  // leaves behind the gradient at xt in Gout, the Jacobi preconditioner and vertex-term diagonal,
+  // and F, F d per element: everything the next Newton iteration needs if the trial is accepted.
+  __device__ void trial(const double* x, const double* dxp, double alpha, double* Gout, const double* Ecur,
+                        double* Enew, double out[4]) {
+    double* acc2 = ps;  // the CG direction's LDS is free outside CG: it takes the diagonal
+    const size_t ne = (size_t)m.n_e;
     double sd = 0.0, sa = 0.0, st = 0.0;
     for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
       int v[D + 1];
       load_conn<D>(m, e, v);
-      ElemRest<D, double> R;
-      load_rest<D, double>(m, e, R);
+      ElemRest<D, double> R64;
+      load_rest<D, double>(m, e, R64);
       double Ds[D][D];
-      gather_edges<D, double>(x, v, Ds);
-      ElemState<D, double> S;
-      elem_state<D, double>(Ds, R, S);
-      const double ea = sc.s_pot * elem_energy<D, double>(R, S, A.a[e]);
-      double eb = ea;
-      if (dxp) {
+      if (dxp)
         gather_edges_step<D>(x, dxp, alpha, v, Ds);
-        elem_state<D, double>(Ds, R, S);
-        eb = sc.s_pot * elem_energy<D, double>(R, S, A.a[e]);
-      }
+      else
+        gather_edges<D, double>(x, v, Ds);
+      ElemState<D, double> S64;
+      elem_state<D, double>(Ds, R64, S64);
+      const double eb = sc.s_pot * elem_energy<D, double>(R64, S64, A.a[e]);
+      const double ea = Ecur ? Ecur[e] : eb;
+      Enew[e] = eb;
       sd += eb - ea;
       sa += fabs(ea);
       st += eb;
+      double o[D + 1][D];
+      elem_grad<D, double>(R64, S64, A.a[e], o);
+      lds_scatter(v, o, sc.s_pot);
+      // F and F d for the Hessian-vector passes, rounded once to the element precision
+      T F[D][D], Fd[D];
+#pragma unroll
+      for (int r = 0; r < D; ++r) {
+        Fd[r] = T(S64.n[r] * S64.s);
+        Fb()[(size_t)(D * D + r) * ne + e] = Fd[r];
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+          F[r][c] = T(S64.F[r][c]);
+          Fb()[(size_t)(r * D + c) * ne + e] = F[r][c];
+        }
+      }
+      ElemRest<D, T> R;
+      load_rest<D, T>(m, e, R);
+      ElemState<D, T> S;
+      elem_state_from_F<D, T>(F, Fd, S);
+      T od[D + 1][D];
+      elem_hessdiag<D, T>(R, S, act(e), od);
+#pragma unroll
+      for (int k = 0; k <= D; ++k)
+#pragma unroll
+        for (int c = 0; c < D; ++c) unsafeAtomicAdd(acc2 + (v[k] - v0) * D + c, sc.s_pot * double(od[k][c]));
     }
     for (int vl = threadIdx.x; vl < v1 - v0; vl += blockDim.x) {
       const int vg = v0 + vl;
@@ -332,11 +328,28 @@ struct BodySolver {
       sa += fabs(ea);
       st += eb;
     }
-    double t[3] = {sd, sa, st};
-    wg_sum<3>(t, red);
+    __syncthreads();
+    double gg = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      const int g = base + i;
+      const bool pin = pinned(i);
+      const double xt = dxp ? x[g] + alpha * dxp[g] : x[g];
+      const double gi = pin ? 0.0 : acc[i] + vgrad(i, xt);
+      Gout[g] = gi;
+      gg += gi * gi;
+      const double vd = pin ? 0.0 : vhdiag(i, xt);
+      const double d = fabs(acc2[i] + vd);
+      A.vdiag[g] = vd;
+      A.Dinvp[g] = pin ? 0.0 : (d > 0.0 ? 1.0 / d : 1.0);
+      acc[i] = 0.0;
+      acc2[i] = 0.0;
+    }
+    double t[4] = {sd, sa, st, gg};
+    wg_sum<4>(t, red);
     out[0] = t[0];
     out[1] = t[1];
     out[2] = t[2];
+    out[3] = t[3];
   }
 
   __device__ void minmax_J(const double* x, double& lo, double& hi) {
@@ -511,8 +524,12 @@ struct BodySolver {
     double* G = A.G;
     double* Gt = A.Gt;
     double* dx = A.dx;
-    const double res0 = sqrt(gradient(x, nullptr, 0.0, G));
-    double res = res0;
+    double* Ecur = A.E0;
+    double* Enew = A.E1;
+    double tr[4];
+    trial(x, nullptr, 0.0, G, nullptr, Ecur, tr);
+    const double res0 = sqrt(tr[3]);
+    double res = res0, gcur = tr[2];
     st.res0 = res0;
     if (!isfinite(res0)) st.flags |= ISB_FLAG_NONFINITE;
     while (isfinite(res)) {
@@ -521,7 +538,6 @@ struct BodySolver {
         break;
       }
       if (st.newton_iters >= A.max_newton) break;
-      precond(x);
       const double eta = fmin(0.5, sqrt(res / res0));
       int it = 0;
       bool neg = false;
@@ -544,27 +560,20 @@ struct BodySolver {
           break;
         }
       }
-      double alpha = 1.0;
-      bool accepted = false, via_grad = false;
+      double alpha = 1.0, rt = res;
+      bool accepted = false;
       for (int ls = 0; ls <= 30; ++ls) {
-        double en[3];
-        energy(x, dx, alpha, en);
-        if (isfinite(en[0])) {
-          if (fabs(en[0]) > 1e3 * 2.220446049250313e-16 * en[1]) {
-            accepted = en[0] <= 1e-4 * alpha * gTd;
+        trial(x, dx, alpha, Gt, Ecur, Enew, tr);
+        rt = sqrt(tr[3]);
+        if (isfinite(tr[0]) && isfinite(rt)) {
+          if (fabs(tr[0]) > 1e3 * 2.220446049250313e-16 * tr[1]) {
+            accepted = tr[0] <= 1e-4 * alpha * gTd;
+          } else if (rt <= 0.5 * res) {
+            // below the FP64 resolution of g the Armijo test only sees rounding: a step that at
+            // least halves |grad g| is accepted instead
+            accepted = true;
           } else {
-            // below the FP64 resolution of g the Armijo test only sees rounding: accept only if
-            // |grad g| at least halves
-            const double rt = sqrt(gradient(x, dx, alpha, Gt));
-            if (rt <= 0.5 * res) {
-              accepted = via_grad = true;
-              double* tmp = G;
-              G = Gt;
-              Gt = tmp;
-              res = rt;
-            } else {
-              break;  // shorter steps cannot do better at the rounding floor
-            }
+            break;  // shorter steps cannot do better at the rounding floor
           }
         }
         if (accepted) break;
@@ -572,12 +581,20 @@ struct BodySolver {
         st.ls_backtracks += 1;
       }
       if (!accepted) {
+        // the preconditioner and the stored F now belong to the last rejected trial; the solve ends here
         st.flags |= ISB_FLAG_STAGNATED;
         break;
       }
       for (int i = threadIdx.x; i < n; i += blockDim.x) x[base + i] += alpha * dx[base + i];
       __syncthreads();
-      if (!via_grad) res = sqrt(gradient(x, nullptr, 0.0, G));
+      double* tmp = G;
+      G = Gt;
+      Gt = tmp;
+      tmp = Ecur;
+      Ecur = Enew;
+      Enew = tmp;
+      res = rt;
+      gcur = tr[2];
       st.newton_iters += 1;
     }
     if (!isfinite(res)) st.flags |= ISB_FLAG_NONFINITE;
@@ -586,12 +603,8 @@ struct BodySolver {
     if (sc.be && A.v1)
       for (int i = threadIdx.x; i < n; i += blockDim.x)
         A.v1[base + i] = (x[base + i] - A.x0[base + i]) / sc.h;
-    if (A.want_tail) {
-      double en[3];
-      energy(x, nullptr, 0.0, en);
-      st.energy = en[2];
-      minmax_J(x, st.min_J, st.max_J);
-    }
+    st.energy = gcur;
+    if (A.want_tail) minmax_J(x, st.min_J, st.max_J);
     __syncthreads();
   }
 

@@ -38,7 +38,7 @@ class BatchArgs(ctypes.Structure):
                 ("x0", vp), ("v0", vp), ("a", vp), ("a32", vp), ("x1", vp), ("v1", vp), ("xbar", vp),
                 ("vbar", vp), ("w", vp), ("xhat", vp), ("G", vp), ("Gt", vp), ("dx", vp), ("r", vp), ("p", vp),
                 ("Dinvp", vp), ("vdiag", vp), ("cv", vp), ("stats", vp), ("tol", cd), ("adj_tol", cd),
-                ("max_newton", ci), ("max_cg", ci), ("want_tail", ci), ("nacc", ci), ("Fbuf", vp)]
+                ("max_newton", ci), ("max_cg", ci), ("want_tail", ci), ("nacc", ci), ("Fbuf", vp), ("E0", vp), ("E1", vp)]
 
 
 STATS_DTYPE = np.dtype([("newton_iters", "<i4"), ("cg_iters", "<i4"), ("adj_cg_iters", "<i4"),
@@ -112,6 +112,8 @@ class EmuBatch:
         self.cv = k(np.zeros(w.n_v))
         self.stats = k(np.zeros(nb, dtype=STATS_DTYPE))
         self.Fbuf = k(np.zeros((d * d + d) * w.n_e, dtype=np.float64))
+        self.E0 = k(np.zeros(w.n_e))
+        self.E1 = k(np.zeros(w.n_e))
         self.be = be
 
     def _args(self, **kw):
@@ -127,6 +129,7 @@ class EmuBatch:
         A.max_newton, A.max_cg = sc["max_newton"], sc["max_cg"]
         A.nacc = self.nacc
         A.Fbuf = _p(self.Fbuf)
+        A.E0, A.E1 = _p(self.E0), _p(self.E1)
         for key, val in kw.items():
             setattr(A, key, val)
         return A
