@@ -61,22 +61,41 @@ def elem_bytes(dim, word):
     return 4 * (dim + 1) + word * (dim * dim + dim + 3 + 1)
 
 
+def fstate_bytes(dim, word):
+    """F and F d stored per element at the Newton iterate."""
+    return word * (dim * dim + dim)
+
+
+def cg_iter_bytes(dim, ne, nv, word_hv):
+    """One batched CG iteration: the Hessian-vector element pass (rest data + stored F; p is in
+    LDS), the x/r update pass (xs, r read and written, D^-1 and vdiag read) and the p pass
+    (vdiag read)."""
+    return (elem_bytes(dim, word_hv) + fstate_bytes(dim, word_hv)) * ne + 56 * nv * dim
+
+
+def trial_bytes(dim, ne, nv, word_hv):
+    """One fused line-search trial: FP64 rest data, E(x) read, E(x_t) written, F stored per element;
+    x, dx, x0, xhat, pinned read and G, vdiag, D^-1 written per DOF; mass and c_v per vertex."""
+    return (elem_bytes(dim, 8) + 16 + fstate_bytes(dim, word_hv)) * ne + 57 * nv * dim + 16 * nv
+
+
 def step_launch_bytes(dim, ne, nv, st, word_hv):
     """Algorithmic bytes of one body in one step launch, from its solver statistics."""
     dof = nv * dim
-    eh, e64 = elem_bytes(dim, word_hv), elem_bytes(dim, 8)
-    cg = eh * ne + 72 * dof                     # Hv pass + p, r, dx, D^-1, vdiag, x vector traffic
-    newton = 2 * e64 * ne + eh * ne + 128 * dof  # gradient, preconditioner, energy + vector passes
-    ls = e64 * ne + 32 * dof                     # each extra line-search trial
-    setup = 56 * dof + 16 * nv
-    return (st["cg_iters"] * cg + st["newton_iters"] * newton + st["ls_backtracks"] * ls + setup
-            + e64 * ne + 32 * dof)             # initial gradient
+    trials = 1 + st["newton_iters"] + st["ls_backtracks"]
+    setup = 57 * dof + 16 * nv                 # x0, v0, pinned -> xhat, x; c_v; v1 at the end
+    per_newton = 40 * dof + 16 * dof + 24 * dof  # CG start; g.dx; x += alpha dx
+    return (setup + trials * trial_bytes(dim, ne, nv, word_hv) - 8 * ne
+            + st["newton_iters"] * per_newton + st["cg_iters"] * cg_iter_bytes(dim, ne, nv, word_hv))
 
 
 def adjoint_launch_bytes(dim, ne, nv, st, word_hv):
+    """Right-hand side (xbar, vbar, pinned -> G; c_v), the FP64 diagonal pass that also stores F,
+    the CG start and the CG iterations."""
     dof = nv * dim
-    eh = elem_bytes(dim, word_hv)
-    return st["adj_cg_iters"] * (eh * ne + 72 * dof) + eh * ne + 48 * dof
+    rhs = 25 * dof + 16 * nv
+    diag = (elem_bytes(dim, 8) + fstate_bytes(dim, word_hv)) * ne + 25 * dof + 16 * nv
+    return rhs + diag + 40 * dof + st["adj_cg_iters"] * cg_iter_bytes(dim, ne, nv, word_hv)
 
 
 def main():

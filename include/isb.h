@@ -122,9 +122,9 @@ typedef struct {
 /* ---- lifetime ---------------------------------------------------------------------------- */
 
 /* Create a context on HIP device `device` computing in `precision` (ISB_FP64: every element
- * kernel in FP64; ISB_MIXED: Hessian-vector products and the preconditioner diagonal in FP32
- * element arithmetic, while gradients, energies, CG vectors, dot products, norms and the state
- * stay FP64). The boundary is FP64 in both modes. */
+ * kernel in FP64; ISB_MIXED: Hessian-vector products in FP32 element arithmetic, while
+ * gradients, energies, the preconditioner diagonal, CG vectors, dot products, norms and the
+ * state stay FP64). The boundary is FP64 in both modes. */
 isb_status isb_create(int device, int precision, isb_ctx** out);
 isb_status isb_destroy(isb_ctx* ctx);
 /* Thread-local description of the last failure on this thread; valid until the next isb_ call. */
@@ -218,7 +218,7 @@ isb_status isb_hessvec(isb_ctx* ctx, isb_stream stream, const double* x, const d
  * its own, for callers that add their own vertex terms and for timing. device [n_v][dim] in/in-out. */
 isb_status isb_hessvec_elements(isb_ctx* ctx, isb_stream stream, const double* x, const double* a,
                                 const double* p, double* hp);
-/* Diagonal of H(x) over free DOFs (1 on pinned DOFs), device out [n_v][dim]. */
+/* Diagonal of H(x) over free DOFs (1 on pinned DOFs), FP64 in both precisions, device out [n_v][dim]. */
 isb_status isb_hessdiag(isb_ctx* ctx, isb_stream stream, const double* x, const double* x0,
                         const double* a, double* diag);
 

@@ -148,7 +148,8 @@ static void elem_ranges(const isb_ctx* c, int b, Fn fn) {
 static constexpr int64_t kPatchMinElems = 16384;
 
 // element scatter of op (PATCH_GRAD / PATCH_HV / PATCH_DIAG) over body b (all bodies when b < 0),
-// in the context's scatter mode: FP64 global atomics, colour passes, or LDS-staged patches
+// in the context's scatter mode: FP64 global atomics, colour passes, or LDS-staged patches. Only
+// the Hessian-vector product takes the context's precision; gradient and diagonal are FP64.
 static void elem_scatter(isb_ctx* c, int b, int op, const double* x, const double* a, const double* p, double* out,
                          const int* done, hipStream_t s, bool a32_copy = true) {
   const float* a32 = a32_copy ? c->w_a32 : nullptr;
@@ -158,8 +159,7 @@ static void elem_scatter(isb_ctx* c, int b, int op, const double* x, const doubl
   if (c->scatter == 2 && ne_scope >= kPatchMinElems) {
     const int p0 = b < 0 ? 0 : c->body_patch_off[b];
     const int p1 = b < 0 ? c->n_patches : c->body_patch_off[b + 1];
-    launch_elem_patch(m, sc, c->plan, p0, p1, op, op == PATCH_GRAD ? 0 : c->precision, x, a, a32, p, out, done,
-                      s);
+    launch_elem_patch(m, sc, c->plan, p0, p1, op, op == PATCH_HV ? c->precision : 0, x, a, a32, p, out, done, s);
     return;
   }
   elem_ranges(c, b, [&](ERange r, bool atomic) {
@@ -168,7 +168,7 @@ static void elem_scatter(isb_ctx* c, int b, int op, const double* x, const doubl
     else if (op == PATCH_HV)
       launch_elem_hv(m, sc, r, atomic, c->precision, x, a, a32, p, out, done, s);
     else
-      launch_elem_diag(m, sc, r, atomic, c->precision, x, a, a32, out, s);
+      launch_elem_diag(m, sc, r, atomic, x, a, out, s);
   });
 }
 
@@ -865,7 +865,6 @@ isb_status isb_hessdiag(isb_ctx* c, isb_stream stream, const double* x, const do
   hipStream_t s = (hipStream_t)stream;
   const DevMesh m = devmesh(c);
   const DevScene dsc = devscene(c);
-  if (c->precision == ISB_MIXED) launch_to_f32(c->n_e, a, c->w_a32, s);
   launch_setup(m, dsc, 0, c->n_v, x0, nullptr, c->w_xt, c->w_xhat, c->w_cv, s);
   launch_vertex_hdiag(m, dsc, 0, c->n_v, x, c->w_cv, diag, s);
   elem_scatter(c, -1, PATCH_DIAG, x, a, nullptr, diag, nullptr, s);

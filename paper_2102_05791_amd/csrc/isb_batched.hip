@@ -154,7 +154,6 @@ static BatchArgs make_args(isb_ctx* c, BatchedState* st) {
   A.Gt = c->w_Gt;
   A.dx = c->w_xs;
   A.r = c->w_r;
-  A.p = c->w_p;
   A.Dinvp = c->w_Dinvp;
   A.vdiag = c->w_vdiag;
   A.cv = c->w_cv;

@@ -40,7 +40,7 @@ struct BatchArgs {
   double *x1, *v1;               // step outputs (x1 is also the Newton iterate)
   const double *xbar, *vbar;     // adjoint right-hand side
   double* w;                     // adjoint output
-  double *xhat, *G, *Gt, *dx, *r, *p, *Dinvp, *vdiag, *cv;  // workspaces
+  double *xhat, *G, *Gt, *dx, *r, *Dinvp, *vdiag, *cv;  // workspaces
   DevStats* stats;
   double tol, adj_tol;
   int max_newton, max_cg;
@@ -146,9 +146,12 @@ struct BodySolver {
       return A.a32[e];
   }
 
-  // Hessian-vector pass: element data and the stored F stream in coalesced; p comes from LDS
-  __device__ void pass_hv() {
+  // Hessian-vector pass: element data and the stored F stream in coalesced; p comes from LDS.
+  // Returns this thread's share of p^T H_elem p = sum over elements of p_e . (H_e p_e), so the
+  // CG curvature needs no separate pass over the scattered product.
+  __device__ double pass_hv() {
     const size_t ne = (size_t)m.n_e;
+    double php = 0.0;
     for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
       int v[D + 1];
       load_conn<D>(m, e, v);
@@ -162,12 +165,16 @@ struct BodySolver {
         Fd[r] = Fb()[(size_t)(D * D + r) * ne + e];
       }
       const T ae = act(e);
+      double pv[D + 1][D];
+#pragma unroll
+      for (int k = 0; k <= D; ++k)
+#pragma unroll
+        for (int c = 0; c < D; ++c) pv[k][c] = ps[(v[k] - v0) * D + c];
       T dDs[D][D];
-      const int l0 = (v[0] - v0) * D;
 #pragma unroll
       for (int j = 0; j < D; ++j)
 #pragma unroll
-        for (int c = 0; c < D; ++c) dDs[c][j] = T(ps[(v[j + 1] - v0) * D + c] - ps[l0 + c]);
+        for (int c = 0; c < D; ++c) dDs[c][j] = T(pv[j + 1][c] - pv[0][c]);
       ElemState<D, T> S;
       elem_state_from_F<D, T>(F, Fd, S);
       T out[D + 1][D];
@@ -176,12 +183,17 @@ struct BodySolver {
 #pragma unroll
       for (int k = 0; k <= D; ++k)
 #pragma unroll
-        for (int c = 0; c < D; ++c) o[k][c] = double(out[k][c]);
+        for (int c = 0; c < D; ++c) {
+          o[k][c] = double(out[k][c]);
+          php += o[k][c] * pv[k][c];
+        }
       lds_scatter(v, o, sc.s_pot);
     }
+    return sc.s_pot * php;
   }
 
-  // diagonal pass; also stores F and F d of every element for the Hessian-vector passes that follow
+  // diagonal pass (FP64); also stores F and F d of every element, rounded once to the element
+  // precision, for the Hessian-vector passes that follow
   __device__ void pass_diag(const double* x) {
     const size_t ne = (size_t)m.n_e;
     for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
@@ -191,35 +203,17 @@ struct BodySolver {
       load_rest<D, double>(m, e, R64);
       double Ds[D][D];
       gather_edges<D, double>(x, v, Ds);
-      double F64[D][D], Fd64[D];
-      mul_dinv<D, double>(Ds, R64.Dinv, F64);
-      T F[D][D], Fd[D];
+      ElemState<D, double> S64;
+      elem_state<D, double>(Ds, R64, S64);
 #pragma unroll
       for (int r = 0; r < D; ++r) {
-        double acc_fd = 0.0;
+        Fb()[(size_t)(D * D + r) * ne + e] = T(S64.n[r] * S64.s);
 #pragma unroll
-        for (int j = 0; j < D; ++j) acc_fd += Ds[r][j] * R64.gf[j];
-        Fd64[r] = acc_fd;
-        Fd[r] = T(Fd64[r]);
-        Fb()[(size_t)(D * D + r) * ne + e] = Fd[r];
-#pragma unroll
-        for (int c = 0; c < D; ++c) {
-          F[r][c] = T(F64[r][c]);
-          Fb()[(size_t)(r * D + c) * ne + e] = F[r][c];
-        }
+        for (int c = 0; c < D; ++c) Fb()[(size_t)(r * D + c) * ne + e] = T(S64.F[r][c]);
       }
-      ElemRest<D, T> R;
-      load_rest<D, T>(m, e, R);
-      ElemState<D, T> S;
-      elem_state_from_F<D, T>(F, Fd, S);
-      T out[D + 1][D];
-      elem_hessdiag<D, T>(R, S, act(e), out);
-      double o[D + 1][D];
-#pragma unroll
-      for (int k = 0; k <= D; ++k)
-#pragma unroll
-        for (int c = 0; c < D; ++c) o[k][c] = double(out[k][c]);
-      lds_scatter(v, o, sc.s_pot);
+      double od[D + 1][D];
+      elem_hessdiag<D, double>(R64, S64, A.a[e], od);
+      lds_scatter(v, od, sc.s_pot);
     }
   }
 
@@ -292,27 +286,19 @@ struct BodySolver {
       elem_grad<D, double>(R64, S64, A.a[e], o);
       lds_scatter(v, o, sc.s_pot);
       // F and F d for the Hessian-vector passes, rounded once to the element precision
-      T F[D][D], Fd[D];
 #pragma unroll
       for (int r = 0; r < D; ++r) {
-        Fd[r] = T(S64.n[r] * S64.s);
-        Fb()[(size_t)(D * D + r) * ne + e] = Fd[r];
+        Fb()[(size_t)(D * D + r) * ne + e] = T(S64.n[r] * S64.s);
 #pragma unroll
-        for (int c = 0; c < D; ++c) {
-          F[r][c] = T(S64.F[r][c]);
-          Fb()[(size_t)(r * D + c) * ne + e] = F[r][c];
-        }
+        for (int c = 0; c < D; ++c) Fb()[(size_t)(r * D + c) * ne + e] = T(S64.F[r][c]);
       }
-      ElemRest<D, T> R;
-      load_rest<D, T>(m, e, R);
-      ElemState<D, T> S;
-      elem_state_from_F<D, T>(F, Fd, S);
-      T od[D + 1][D];
-      elem_hessdiag<D, T>(R, S, act(e), od);
+      // the Jacobi diagonal in FP64 from the state already at hand, whatever the element precision
+      double od[D + 1][D];
+      elem_hessdiag<D, double>(R64, S64, A.a[e], od);
 #pragma unroll
       for (int k = 0; k <= D; ++k)
 #pragma unroll
-        for (int c = 0; c < D; ++c) unsafeAtomicAdd(acc2 + (v[k] - v0) * D + c, sc.s_pot * double(od[k][c]));
+        for (int c = 0; c < D; ++c) unsafeAtomicAdd(acc2 + (v[k] - v0) * D + c, sc.s_pot * od[k][c]);
     }
     for (int vl = threadIdx.x; vl < v1 - v0; vl += blockDim.x) {
       const int vg = v0 + vl;
@@ -371,28 +357,30 @@ struct BodySolver {
   }
 
   // PCG on H(x) xs = sign * rhs (masked to the free DOFs); returns the final r.r. The element
-  // state (F, F d) must have been stored by precond(x). Vector passes take kU owned DOFs per thread
-  // at a time and issue all their loads before any arithmetic.
+  // state (F, F d) must have been stored by precond(x) or trial(). The direction p lives only in
+  // LDS. Per iteration: the Hv pass, which also sums the element part of p^T H p; one vector pass
+  // that updates xs and r and leaves z = M r in the accumulator; one LDS-only pass that forms the
+  // next p and the vertex part of its curvature. Vector passes take kU owned DOFs per thread at a
+  // time and issue all their loads before any arithmetic.
   static constexpr int kU = 2;
 
   __device__ double cg(const double* rhs, double sign, double tol, int maxit, double* xs, int& iters, bool& neg) {
     double* r = A.r;
-    double* p = A.p;
     const double* Dv = A.Dinvp;
     const double* vd = A.vdiag;
     const int B = blockDim.x;
-    double rz = 0.0, rr = 0.0;
+    double rz = 0.0, rr = 0.0, pvp = 0.0;  // pvp: this thread's share of sum vd p^2
     for (int i = threadIdx.x; i < n; i += B) {
       const int g = base + i;
       const double di = Dv[g];
       const double ri = di != 0.0 ? sign * rhs[g] : 0.0;
       const double zi = di * ri;
       r[g] = ri;
-      p[g] = zi;
       ps[i] = zi;
       xs[g] = 0.0;
       rz += ri * zi;
       rr += ri * ri;
+      pvp += vd[g] * zi * zi;
     }
     {
       double t[2] = {rz, rr};
@@ -405,37 +393,14 @@ struct BodySolver {
     const double tol2 = tol * tol;
     if (rr <= tol2) return rr;
     for (int it = 0; it < maxit; ++it) {
-      pass_hv();
-      __syncthreads();
-      double pHp = 0.0;
-      for (int i0 = threadIdx.x; i0 < n; i0 += kU * B) {
-        double pv[kU], dv[kU], av[kU];
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-          const int i = i0 + u * B;
-          if (i < n) {
-            pv[u] = p[base + i];
-            dv[u] = vd[base + i];
-            av[u] = acc[i];
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-          const int i = i0 + u * B;
-          if (i < n) {
-            const double hp = av[u] + dv[u] * pv[u];
-            acc[i] = hp;
-            pHp += pv[u] * hp;
-          }
-        }
-      }
-      pHp = wg_sum1(pHp, red);
+      // the reduction's barriers also complete the scatter into acc
+      const double pHp = wg_sum1(pass_hv() + pvp, red);
       if (!(pHp > 0.0)) {
         // non-positive curvature: stop; on the first iteration keep the preconditioned
         // steepest-descent direction (Nocedal & Wright, Alg. 7.1)
         neg = true;
         for (int i = threadIdx.x; i < n; i += B) {
-          if (it == 0) xs[base + i] = p[base + i];
+          if (it == 0) xs[base + i] = ps[i];
           acc[i] = 0.0;
         }
         __syncthreads();
@@ -445,17 +410,16 @@ struct BodySolver {
       double rz1 = 0.0;
       rr = 0.0;
       for (int i0 = threadIdx.x; i0 < n; i0 += kU * B) {
-        double xv[kU], pv[kU], dv[kU], rv[kU], hv[kU];
+        double xv[kU], dv[kU], rv[kU], vv[kU];
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
           const int i = i0 + u * B;
           if (i < n) {
             const int g = base + i;
             xv[u] = xs[g];
-            pv[u] = p[g];
             dv[u] = Dv[g];
             rv[u] = r[g];
-            hv[u] = acc[i];
+            vv[u] = vd[g];
           }
         }
 #pragma unroll
@@ -463,11 +427,14 @@ struct BodySolver {
           const int i = i0 + u * B;
           if (i < n) {
             const int g = base + i;
-            xs[g] = xv[u] + alpha * pv[u];
-            const double ri = dv[u] != 0.0 ? rv[u] - alpha * hv[u] : 0.0;
+            const double pi = ps[i];
+            const double hp = acc[i] + vv[u] * pi;
+            xs[g] = xv[u] + alpha * pi;
+            const double ri = dv[u] != 0.0 ? rv[u] - alpha * hp : 0.0;
+            const double zi = dv[u] * ri;
             r[g] = ri;
-            acc[i] = 0.0;
-            rz1 += ri * dv[u] * ri;
+            acc[i] = zi;
+            rz1 += ri * zi;
             rr += ri * ri;
           }
         }
@@ -479,30 +446,19 @@ struct BodySolver {
         rr = t[1];
       }
       iters = it + 1;
-      if (rr <= tol2) break;
+      if (rr <= tol2) {
+        for (int i = threadIdx.x; i < n; i += B) acc[i] = 0.0;
+        __syncthreads();
+        break;
+      }
       const double beta = rz1 / rz;
       rz = rz1;
-      for (int i0 = threadIdx.x; i0 < n; i0 += kU * B) {
-        double pv[kU], dv[kU], rv[kU];
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-          const int i = i0 + u * B;
-          if (i < n) {
-            const int g = base + i;
-            pv[u] = p[g];
-            dv[u] = Dv[g];
-            rv[u] = r[g];
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-          const int i = i0 + u * B;
-          if (i < n) {
-            const double pn = dv[u] * rv[u] + beta * pv[u];
-            p[base + i] = pn;
-            ps[i] = pn;
-          }
-        }
+      pvp = 0.0;
+      for (int i = threadIdx.x; i < n; i += B) {
+        const double pn = acc[i] + beta * ps[i];
+        ps[i] = pn;
+        acc[i] = 0.0;
+        pvp += vd[base + i] * pn * pn;
       }
       __syncthreads();
     }

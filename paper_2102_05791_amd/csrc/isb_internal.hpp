@@ -105,8 +105,8 @@ void launch_elem_grad(const DevMesh& m, const DevScene& sc, ERange r, bool atomi
                       double* G, hipStream_t s);
 void launch_elem_hv(const DevMesh& m, const DevScene& sc, ERange r, bool atomic, int precision, const double* x,
                     const double* a, const float* a32, const double* p, double* Hp, const int* done, hipStream_t s);
-void launch_elem_diag(const DevMesh& m, const DevScene& sc, ERange r, bool atomic, int precision, const double* x,
-                      const double* a, const float* a32, double* diag, hipStream_t s);
+void launch_elem_diag(const DevMesh& m, const DevScene& sc, ERange r, bool atomic, const double* x, const double* a,
+                      double* diag, hipStream_t s);
 void launch_elem_energy(const DevMesh& m, const DevScene& sc, ERange r, const double* x, const double* dx,
                         double alpha, const double* a, double* partials, int part_off, hipStream_t s,
                         int* nblocks_out);

@@ -405,24 +405,23 @@ __global__ void __launch_bounds__(kBlock) k_elem_hv(DevMesh m, DevScene sc, ERan
   }
 }
 
-template <int D, bool ATOMIC, typename T>
+// Hessian diagonal, FP64 in both precisions (the Jacobi preconditioner and isb_hessdiag)
+template <int D, bool ATOMIC>
 __global__ void __launch_bounds__(kBlock) k_elem_diag(DevMesh m, DevScene sc, ERange r, const double* __restrict__ x,
-                                                      const double* __restrict__ a, const float* __restrict__ a32,
-                                                      double* diag) {
+                                                      const double* __restrict__ a, double* diag) {
   for (int k = r.begin + blockIdx.x * blockDim.x + threadIdx.x; k < r.end; k += gridDim.x * blockDim.x) {
     const int e = elem_id(r, k);
     int v[D + 1];
     load_conn<D>(m, e, v);
-    ElemRest<D, T> R;
-    load_rest<D, T>(m, e, R);
-    T Ds[D][D];
-    gather_edges<D, T>(x, v, Ds);
-    ElemState<D, T> S;
-    elem_state<D, T>(Ds, R, S);
-    const T ae = (std::is_same<T, float>::value && a32) ? T(a32[e]) : T(a[e]);
-    T out[D + 1][D];
-    elem_hessdiag<D, T>(R, S, ae, out);
-    scatter_vertices<D, ATOMIC, T>(diag, v, out, sc.s_pot);
+    ElemRest<D, double> R;
+    load_rest<D, double>(m, e, R);
+    double Ds[D][D];
+    gather_edges<D, double>(x, v, Ds);
+    ElemState<D, double> S;
+    elem_state<D, double>(Ds, R, S);
+    double out[D + 1][D];
+    elem_hessdiag<D, double>(R, S, a[e], out);
+    scatter_vertices<D, ATOMIC, double>(diag, v, out, sc.s_pot);
   }
 }
 
@@ -564,30 +563,23 @@ void launch_elem_hv(const DevMesh& m, const DevScene& sc, ERange r, bool atomic,
   }
 }
 
-template <int D, typename T>
-static void elem_diag_dt(const DevMesh& m, const DevScene& sc, ERange r, bool atomic, const double* x,
-                         const double* a, const float* a32, double* diag, hipStream_t s) {
+template <int D>
+static void elem_diag_d(const DevMesh& m, const DevScene& sc, ERange r, bool atomic, const double* x,
+                        const double* a, double* diag, hipStream_t s) {
   const int g = grid_for(r.end - r.begin);
   if (atomic)
-    k_elem_diag<D, true, T><<<g, kBlock, 0, s>>>(m, sc, r, x, a, a32, diag);
+    k_elem_diag<D, true><<<g, kBlock, 0, s>>>(m, sc, r, x, a, diag);
   else
-    k_elem_diag<D, false, T><<<g, kBlock, 0, s>>>(m, sc, r, x, a, a32, diag);
+    k_elem_diag<D, false><<<g, kBlock, 0, s>>>(m, sc, r, x, a, diag);
 }
 
-void launch_elem_diag(const DevMesh& m, const DevScene& sc, ERange r, bool atomic, int precision, const double* x,
-                      const double* a, const float* a32, double* diag, hipStream_t s) {
+void launch_elem_diag(const DevMesh& m, const DevScene& sc, ERange r, bool atomic, const double* x, const double* a,
+                      double* diag, hipStream_t s) {
   if (r.end <= r.begin) return;
-  if (m.dim == 2) {
-    if (precision)
-      elem_diag_dt<2, float>(m, sc, r, atomic, x, a, a32, diag, s);
-    else
-      elem_diag_dt<2, double>(m, sc, r, atomic, x, a, a32, diag, s);
-  } else {
-    if (precision)
-      elem_diag_dt<3, float>(m, sc, r, atomic, x, a, a32, diag, s);
-    else
-      elem_diag_dt<3, double>(m, sc, r, atomic, x, a, a32, diag, s);
-  }
+  if (m.dim == 2)
+    elem_diag_d<2>(m, sc, r, atomic, x, a, diag, s);
+  else
+    elem_diag_d<3>(m, sc, r, atomic, x, a, diag, s);
 }
 
 void launch_elem_energy(const DevMesh& m, const DevScene& sc, ERange r, const double* x, const double* dx,
@@ -996,8 +988,6 @@ void launch_elem_patch(const DevMesh& m, const DevScene& sc, const PatchPlan& P,
     patch_launch<D_, float, PATCH_HV>(m, sc, P, p0, p1, x, a, a32, p, out, done, s);                \
   else if (op == PATCH_HV)                                                                          \
     patch_launch<D_, double, PATCH_HV>(m, sc, P, p0, p1, x, a, a32, p, out, done, s);               \
-  else if (precision)                                                                               \
-    patch_launch<D_, float, PATCH_DIAG>(m, sc, P, p0, p1, x, a, a32, p, out, done, s);              \
   else                                                                                              \
     patch_launch<D_, double, PATCH_DIAG>(m, sc, P, p0, p1, x, a, a32, p, out, done, s);
   if (m.dim == 2) {

@@ -36,7 +36,7 @@ class DevScene(ctypes.Structure):
 class BatchArgs(ctypes.Structure):
     _fields_ = [("order", vp), ("voff", vp), ("eoff", vp), ("n_bodies", ci),
                 ("x0", vp), ("v0", vp), ("a", vp), ("a32", vp), ("x1", vp), ("v1", vp), ("xbar", vp),
-                ("vbar", vp), ("w", vp), ("xhat", vp), ("G", vp), ("Gt", vp), ("dx", vp), ("r", vp), ("p", vp),
+                ("vbar", vp), ("w", vp), ("xhat", vp), ("G", vp), ("Gt", vp), ("dx", vp), ("r", vp),
                 ("Dinvp", vp), ("vdiag", vp), ("cv", vp), ("stats", vp), ("tol", cd), ("adj_tol", cd),
                 ("max_newton", ci), ("max_cg", ci), ("want_tail", ci), ("nacc", ci), ("Fbuf", vp), ("E0", vp), ("E1", vp)]
 
@@ -108,7 +108,7 @@ class EmuBatch:
         self.eoff = k(w.body_e_off.astype(np.int32))
         self.nacc = int((np.diff(w.body_v_off) * d).max())
         nd = w.n_v * d
-        self.ws = {n: k(np.zeros(nd)) for n in ("xhat", "G", "Gt", "dx", "r", "p", "Dinvp", "vdiag")}
+        self.ws = {n: k(np.zeros(nd)) for n in ("xhat", "G", "Gt", "dx", "r", "Dinvp", "vdiag")}
         self.cv = k(np.zeros(w.n_v))
         self.stats = k(np.zeros(nb, dtype=STATS_DTYPE))
         self.Fbuf = k(np.zeros((d * d + d) * w.n_e, dtype=np.float64))
@@ -121,7 +121,7 @@ class EmuBatch:
         sc = self.w.scene
         A.order, A.voff, A.eoff = _p(self.order), _p(self.voff), _p(self.eoff)
         A.n_bodies = self.w.n_bodies
-        for n in ("xhat", "G", "Gt", "dx", "r", "p", "Dinvp", "vdiag"):
+        for n in ("xhat", "G", "Gt", "dx", "r", "Dinvp", "vdiag"):
             setattr(A, n, _p(self.ws[n]))
         A.cv = _p(self.cv)
         A.stats = _p(self.stats)
