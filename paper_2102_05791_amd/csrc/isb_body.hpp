@@ -124,7 +124,8 @@ struct BodySolver {
   const BatchArgs& A;
   double* acc;  // LDS [n_loc * D], zero between passes
   double* red;  // LDS reduction slots
-  double* ps;   // LDS [n_loc * D]: the CG direction p (FP64: the Hv pass takes differences of it)
+  double* ps;   // LDS [n_loc * D]: the CG direction p inside cg() (FP64: the Hv pass takes
+                // differences of it), the diagonal accumulator of trial(); zero outside both
   int v0, v1, e0, e1, n, base;
 
   __device__ __forceinline__ T* Fb() const { return reinterpret_cast<T*>(A.Fbuf); }
@@ -391,8 +392,7 @@ struct BodySolver {
     iters = 0;
     neg = false;
     const double tol2 = tol * tol;
-    if (rr <= tol2) return rr;
-    for (int it = 0; it < maxit; ++it) {
+    for (int it = 0; it < maxit && rr > tol2; ++it) {
       // the reduction's barriers also complete the scatter into acc
       const double pHp = wg_sum1(pass_hv() + pvp, red);
       if (!(pHp > 0.0)) {
@@ -403,7 +403,6 @@ struct BodySolver {
           if (it == 0) xs[base + i] = ps[i];
           acc[i] = 0.0;
         }
-        __syncthreads();
         break;
       }
       const double alpha = rz / pHp;
@@ -448,7 +447,6 @@ struct BodySolver {
       iters = it + 1;
       if (rr <= tol2) {
         for (int i = threadIdx.x; i < n; i += B) acc[i] = 0.0;
-        __syncthreads();
         break;
       }
       const double beta = rz1 / rz;
@@ -462,6 +460,9 @@ struct BodySolver {
       }
       __syncthreads();
     }
+    // every exit leaves p behind in LDS: clear it for the trial pass, which accumulates there
+    for (int i = threadIdx.x; i < n; i += B) ps[i] = 0.0;
+    __syncthreads();
     return rr;
   }
 
@@ -612,8 +613,9 @@ __device__ void batched_body(const DevMesh& m, const DevScene& sc, const BatchAr
   double* red = smem;
   double* acc = smem + kRedSlots;
   double* ps = acc + A.nacc;
-  // the accumulator starts at zero; every pass clears the entries it used
-  for (int i = threadIdx.x; i < A.nacc; i += blockDim.x) acc[i] = 0.0;
+  // LDS holds whatever the last kernel left: both accumulators start at zero, and every pass
+  // clears the entries it used
+  for (int i = threadIdx.x; i < 2 * A.nacc; i += blockDim.x) acc[i] = 0.0;
   __syncthreads();
   for (int round = 0; round * G < A.n_bodies; ++round) {
     const int k = queue_position(round, g, G);

@@ -1,7 +1,11 @@
 // Runs the batched solver's body logic (isb_body.hpp) on the CPU: one workgroup of `block`
-// host threads pulls every body from the work queue. Test infrastructure only.
+// host threads pulls every body from the work queue. The emulated LDS starts filled with
+// `lds_fill`, standing in for whatever an earlier kernel left there; the largest |value| left in
+// its two accumulators afterwards is returned in *lds_left. Test infrastructure only.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
 #include <thread>
 
 #include "isb_body.hpp"
@@ -11,7 +15,8 @@ isb_emu_dim3 blockDim, blockIdx, gridDim;
 isb_emu::Workgroup* isb_emu::g_wg = nullptr;
 
 template <int D, typename T, int MODE>
-static void run(int block, const isb::DevMesh* m, const isb::DevScene* sc, const isb::BatchArgs* A) {
+static void run(int block, const isb::DevMesh* m, const isb::DevScene* sc, const isb::BatchArgs* A, double lds_fill,
+                double* lds_left) {
   isb_emu::Workgroup wg;
   std::barrier<> all(block);
   std::vector<std::barrier<>*> waves;
@@ -22,7 +27,7 @@ static void run(int block, const isb::DevMesh* m, const isb::DevScene* sc, const
   isb_emu::g_wg = &wg;
   blockDim.x = block;
   gridDim.x = 1;
-  std::vector<double> smem(isb::kRedSlots + 2 * (size_t)A->nacc, -12345.0);
+  std::vector<double> smem(isb::kRedSlots + 2 * (size_t)A->nacc, lds_fill);
   std::vector<std::thread> th;
   for (int t = 0; t < block; ++t)
     th.emplace_back([&, t]() {
@@ -31,21 +36,25 @@ static void run(int block, const isb::DevMesh* m, const isb::DevScene* sc, const
     });
   for (auto& x : th) x.join();
   for (auto* b : waves) delete b;
+  double left = 0.0;
+  for (size_t i = isb::kRedSlots; i < smem.size(); ++i) left = std::max(left, std::fabs(smem[i]));
+  *lds_left = left;
 }
 
 extern "C" int emu_batched(int dim, int precision, int mode, int block, const isb::DevMesh* m,
-                           const isb::DevScene* sc, const isb::BatchArgs* A) {
+                           const isb::DevScene* sc, const isb::BatchArgs* A, double lds_fill,
+                           double* lds_left) {
   if (block % 64 || block < 64 || block > 1024) return 1;
   if (dim == 2) {
     if (precision)
-      mode ? run<2, float, 1>(block, m, sc, A) : run<2, float, 0>(block, m, sc, A);
+      mode ? run<2, float, 1>(block, m, sc, A, lds_fill, lds_left) : run<2, float, 0>(block, m, sc, A, lds_fill, lds_left);
     else
-      mode ? run<2, double, 1>(block, m, sc, A) : run<2, double, 0>(block, m, sc, A);
+      mode ? run<2, double, 1>(block, m, sc, A, lds_fill, lds_left) : run<2, double, 0>(block, m, sc, A, lds_fill, lds_left);
   } else {
     if (precision)
-      mode ? run<3, float, 1>(block, m, sc, A) : run<3, float, 0>(block, m, sc, A);
+      mode ? run<3, float, 1>(block, m, sc, A, lds_fill, lds_left) : run<3, float, 0>(block, m, sc, A, lds_fill, lds_left);
     else
-      mode ? run<3, double, 1>(block, m, sc, A) : run<3, double, 0>(block, m, sc, A);
+      mode ? run<3, double, 1>(block, m, sc, A, lds_fill, lds_left) : run<3, double, 0>(block, m, sc, A, lds_fill, lds_left);
   }
   return 0;
 }

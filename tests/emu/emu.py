@@ -67,6 +67,8 @@ class EmuBatch:
 
     def __init__(self, w, precision="fp64"):
         self.lib = ctypes.CDLL(build())
+        self._left = ctypes.c_double(0.0)
+        self.lds_left = None
         sizes = (ci * 4)()
         self.lib.emu_sizes(sizes)
         assert list(sizes) == [ctypes.sizeof(DevMesh), ctypes.sizeof(DevScene), ctypes.sizeof(BatchArgs), 72]
@@ -134,7 +136,7 @@ class EmuBatch:
             setattr(A, key, val)
         return A
 
-    def step(self, x0, v0, a, block=128, want_tail=1):
+    def step(self, x0, v0, a, block=128, want_tail=1, lds_fill=-12345.0):
         x0 = np.ascontiguousarray(x0, dtype=np.float64)
         v0 = np.ascontiguousarray(v0, dtype=np.float64)
         a = np.ascontiguousarray(a, dtype=np.float64)
@@ -144,10 +146,11 @@ class EmuBatch:
         A = self._args(x0=_p(x0), v0=_p(v0) if self.be else None, a=_p(a), a32=_p(a32), x1=_p(x1),
                        v1=_p(v1) if self.be else None, want_tail=want_tail)
         self.lib.emu_batched(self.w.dim, self.prec, 0, block, ctypes.byref(self.m), ctypes.byref(self.sc),
-                             ctypes.byref(A))
+                             ctypes.byref(A), ctypes.c_double(lds_fill), ctypes.byref(self._left))
+        self.lds_left = self._left.value
         return x1, (v1 if self.be else None), self.stats.copy()
 
-    def adjoint(self, x1, x0, a, xbar, vbar=None, block=128):
+    def adjoint(self, x1, x0, a, xbar, vbar=None, block=128, lds_fill=-12345.0):
         arrs = [np.ascontiguousarray(v, dtype=np.float64) for v in (x1, x0, a, xbar)]
         vb = None if vbar is None else np.ascontiguousarray(vbar, dtype=np.float64)
         a32 = arrs[2].astype(np.float32)
@@ -155,5 +158,6 @@ class EmuBatch:
         A = self._args(x1=_p(arrs[0]), x0=_p(arrs[1]), a=_p(arrs[2]), a32=_p(a32), xbar=_p(arrs[3]),
                        vbar=None if vb is None else _p(vb), w=_p(wv))
         self.lib.emu_batched(self.w.dim, self.prec, 1, block, ctypes.byref(self.m), ctypes.byref(self.sc),
-                             ctypes.byref(A))
+                             ctypes.byref(A), ctypes.c_double(lds_fill), ctypes.byref(self._left))
+        self.lds_left = self._left.value
         return wv, self.stats.copy()

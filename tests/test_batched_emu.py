@@ -58,3 +58,37 @@ def test_emulated_static_assignment_covers_every_body_once(emu_mod):
     x1, v1, st = eb.step(w.x0, w.v0, w.actions[0], block=64)
     assert np.all(st["newton_iters"] > 0) and np.all(st["flags"] & 1)
     assert np.all(x1 != 0.0)
+
+
+@pytest.mark.parametrize("lds_fill", [0.0, -12345.0, 1e30])
+def test_emulated_first_preconditioner_ignores_stale_lds(emu_mod, lds_fill):
+    """With no Newton iteration allowed, the Jacobi preconditioner left behind is the one of the
+    first trial pass: 1/|diag H| at the initial iterate (x0 + h v0, pinned DOFs at x0) on free DOFs,
+    whatever the LDS held when the launch began."""
+    w, _ = rand_workload(2, seed=23, bodies=2, shape=(6, 3))
+    w.scene.update(max_newton=0)
+    eb = emu_mod.EmuBatch(w, "mixed")
+    a = w.actions[0]
+    eb.step(w.x0, w.v0, a, block=64, lds_fill=lds_fill)
+    dinv = eb.ws["Dinvp"].reshape(w.x0.shape)
+    for b, p in enumerate(problems(w)):
+        sv = slice(w.body_v_off[b], w.body_v_off[b + 1])
+        se = slice(w.body_e_off[b], w.body_e_off[b + 1])
+        xi = np.where(p.pinned, w.x0[sv], p.x_hat(w.x0[sv], w.v0[sv]))
+        d = np.abs(p.hessian(xi, w.x0[sv], a[se]).diagonal())
+        ref = np.where(p.free, 1.0 / d, 0.0).reshape(xi.shape)
+        assert rel(dinv[sv], ref) <= 1e-12
+
+
+@pytest.mark.parametrize("mode", ["step", "adjoint"])
+def test_emulated_launch_leaves_lds_accumulators_zero(emu_mod, mode):
+    """Both LDS accumulators are zero outside the passes that use them: each pass clears what it
+    used, and CG clears its direction on every exit (the trial pass accumulates there next)."""
+    w, rng = rand_workload(2, seed=24, bodies=3, shape=(6, 3))
+    eb = emu_mod.EmuBatch(w, "mixed")
+    a = w.actions[0]
+    x1, _, st = eb.step(w.x0, w.v0, a, block=64, lds_fill=0.0)
+    assert np.all(st["flags"] & 1)
+    if mode == "adjoint":
+        eb.adjoint(x1, w.x0, a, rng.normal(size=x1.shape), rng.normal(size=x1.shape), block=64, lds_fill=0.0)
+    assert eb.lds_left == 0.0
