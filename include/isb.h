@@ -69,7 +69,7 @@ typedef enum {
                                consecutive elements accumulates in LDS and adds each distinct vertex DOF
                                to global memory once */
   ISB_OPT_GRAPH_SAFE = 2,   /* 1 = no host synchronisation inside step/adjoint/vjp (batched solver only) */
-  ISB_OPT_BLOCK = 3,        /* batched solver workgroup size: 256, 512 or 1024; 0 (default) = 1024 for
+  ISB_OPT_BLOCK = 3,        /* batched solver workgroup size: 256, 512, 768 or 1024; 0 (default) = 768 for
                                triangles, 512 for tetrahedra */
   ISB_OPT_CG_CHECK = 4,     /* plain solver: read the CG convergence flag every k iterations (default 4) */
   ISB_OPT_PRECISION = 5     /* isb_precision; equals the value given to isb_create */

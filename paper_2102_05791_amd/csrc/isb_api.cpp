@@ -72,6 +72,7 @@ DevScene devscene(const isb_ctx* c) {
   s.kc = c->scene.k_contact;
   s.kfr = c->scene.k_friction;
   s.eps = c->scene.eps_friction;
+  s.ih2 = 1.0 / (s.h * s.h);
   return s;
 }
 
@@ -712,8 +713,8 @@ isb_status isb_set_option(isb_ctx* c, int key, int64_t value) {
       c->graph_safe = value != 0;
       return ISB_OK;
     case ISB_OPT_BLOCK:
-      if (value != 0 && value != 256 && value != 512 && value != 1024)
-        return fail(ISB_E_ARG, "block must be 0 (automatic), 256, 512 or 1024");
+      if (value != 0 && value != 256 && value != 512 && value != 768 && value != 1024)
+        return fail(ISB_E_ARG, "block must be 0 (automatic), 256, 512, 768 or 1024");
       c->block = (int)value;
       return ISB_OK;
     case ISB_OPT_CG_CHECK:
@@ -732,7 +733,7 @@ isb_status isb_get_option(isb_ctx* c, int key, int64_t* value) {
     case ISB_OPT_SOLVER: *value = c->solver; return ISB_OK;
     case ISB_OPT_SCATTER: *value = c->scatter; return ISB_OK;
     case ISB_OPT_GRAPH_SAFE: *value = c->graph_safe; return ISB_OK;
-    case ISB_OPT_BLOCK: *value = c->block > 0 ? c->block : (c->dim == 3 ? 512 : 1024); return ISB_OK;
+    case ISB_OPT_BLOCK: *value = c->block > 0 ? c->block : (c->dim == 3 ? 512 : 768); return ISB_OK;
     case ISB_OPT_CG_CHECK: *value = c->cg_check; return ISB_OK;
     case ISB_OPT_PRECISION: *value = c->precision; return ISB_OK;
     case ISB_INFO_N_VERTICES: *value = c->n_v; return ISB_OK;

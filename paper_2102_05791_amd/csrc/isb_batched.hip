@@ -17,7 +17,7 @@
 namespace isb {
 
 // MODE 0: step, 1: adjoint. LB is the launch bound: 1024-thread workgroups get at most 128 VGPRs,
-// 512-thread ones 256, which the 3D and FP64 variants need to stay clear of spills.
+// 768-thread ones 168 and 512-thread ones 256 (one workgroup per CU in every case).
 template <int D, typename T, int MODE, int LB>
 __global__ void __launch_bounds__(LB) k_batched(DevMesh m, DevScene sc, BatchArgs A) {
   extern __shared__ double smem[];
@@ -54,7 +54,9 @@ static void* pick_lb(int dim, int precision, int mode) {
 }
 
 static void* pick_kernel(int dim, int precision, int mode, int block) {
-  return block > 512 ? pick_lb<1024>(dim, precision, mode) : pick_lb<512>(dim, precision, mode);
+  if (block > 768) return pick_lb<1024>(dim, precision, mode);
+  if (block > 512) return pick_lb<768>(dim, precision, mode);
+  return pick_lb<512>(dim, precision, mode);
 }
 
 // LDS of one workgroup: reduction slots, the FP64 accumulator and the FP64 CG direction, sized for
@@ -82,7 +84,7 @@ void batched_release(isb_ctx* c) {
 
 isb_status batched_prepare(isb_ctx* c) {
   auto* st = static_cast<BatchedState*>(c->batched);
-  const int want_block = c->block > 0 ? c->block : (c->dim == 2 ? 1024 : 512);
+  const int want_block = c->block > 0 ? c->block : (c->dim == 2 ? 768 : 512);
   if (st && st->block == want_block && st->precision == c->precision && st->dim == c->dim) return ISB_OK;
   batched_release(c);
   st = new BatchedState();

@@ -218,25 +218,24 @@ struct BodySolver {
     }
   }
 
-  // -------- vertex terms per DOF --------
-  __device__ __forceinline__ double vgrad(int i, double xi) const {
-    const int vg = v0 + i / D, c = i % D;
-    const double mv = m.mass[vg];
+  // -------- vertex terms per DOF, from values already in registers --------
+  // gradient of the vertex part along axis c: gravity / contact on y, friction on the others
+  // (Eq. 15-17), inertia in backward Euler
+  __device__ __forceinline__ double vgrad(int c, double xi, double mv, double cvv, double x0i, double xhi) const {
     double g;
     if (c == 1)
       g = mv * sc.grav - 2.0 * sc.kc * fmax(-xi, 0.0);
     else
-      g = 2.0 * sc.kfr * A.cv[vg] / (sc.h * sc.h) * (xi - A.x0[base + i]);
+      g = 2.0 * sc.kfr * cvv * sc.ih2 * (xi - x0i);
     g *= sc.s_pot;
-    if (sc.be) g += mv * (xi - A.xhat[base + i]);
+    if (sc.be) g += mv * (xi - xhi);
     return g;
   }
 
-  __device__ __forceinline__ double vhdiag(int i, double xi) const {
-    const int vg = v0 + i / D, c = i % D;
-    double hd = (c == 1) ? (xi < 0.0 ? 2.0 * sc.kc : 0.0) : 2.0 * sc.kfr * A.cv[vg] / (sc.h * sc.h);
+  __device__ __forceinline__ double vhdiag(int c, double xi, double mv, double cvv) const {
+    double hd = (c == 1) ? (xi < 0.0 ? 2.0 * sc.kc : 0.0) : 2.0 * sc.kfr * cvv * sc.ih2;
     hd *= sc.s_pot;
-    if (sc.be) hd += m.mass[vg];
+    if (sc.be) hd += mv;
     return hd;
   }
 
@@ -245,8 +244,9 @@ struct BodySolver {
     pass_diag(x);
     __syncthreads();
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      const int vg = v0 + i / D, c = i % D;
       const bool pin = pinned(i);
-      const double vd = pin ? 0.0 : vhdiag(i, x[base + i]);
+      const double vd = pin ? 0.0 : vhdiag(c, x[base + i], m.mass[vg], A.cv[vg]);
       const double d = fabs(acc[i] + vd);
       A.vdiag[base + i] = vd;
       A.Dinvp[base + i] = pin ? 0.0 : (d > 0.0 ? 1.0 / d : 1.0);
@@ -260,6 +260,10 @@ struct BodySolver {
   // -- the element differences use the stored energies Ecur of x, the new ones go to Enew -- and
   // leaves behind the gradient at xt in Gout, the Jacobi preconditioner and vertex-term diagonal,
   // and F, F d per element: everything the next Newton iteration needs if the trial is accepted.
+  // Each loop issues every global load of an iteration before its first global store: stores
+  // count against the same wait counter as loads, and a load placed after a store waits for it.
+  static constexpr int kV = 3;  // vertices per thread per chunk of the vertex loop
+
   __device__ void trial(const double* x, const double* dxp, double alpha, double* Gout, const double* Ecur,
                         double* Enew, double out[4]) {
     double* acc2 = ps;  // the CG direction's LDS is free outside CG: it takes the diagonal
@@ -270,6 +274,8 @@ struct BodySolver {
       load_conn<D>(m, e, v);
       ElemRest<D, double> R64;
       load_rest<D, double>(m, e, R64);
+      const double ae = A.a[e];
+      const double estored = Ecur ? Ecur[e] : 0.0;
       double Ds[D][D];
       if (dxp)
         gather_edges_step<D>(x, dxp, alpha, v, Ds);
@@ -277,59 +283,84 @@ struct BodySolver {
         gather_edges<D, double>(x, v, Ds);
       ElemState<D, double> S64;
       elem_state<D, double>(Ds, R64, S64);
-      const double eb = sc.s_pot * elem_energy<D, double>(R64, S64, A.a[e]);
-      const double ea = Ecur ? Ecur[e] : eb;
-      Enew[e] = eb;
+      const double eb = sc.s_pot * elem_energy<D, double>(R64, S64, ae);
+      const double ea = Ecur ? estored : eb;
       sd += eb - ea;
       sa += fabs(ea);
       st += eb;
       double o[D + 1][D];
-      elem_grad<D, double>(R64, S64, A.a[e], o);
-      lds_scatter(v, o, sc.s_pot);
-      // F and F d for the Hessian-vector passes, rounded once to the element precision
+      elem_grad<D, double>(R64, S64, ae, o);
+      // global stores once every load of the iteration has been issued: the energy, and F, F d
+      // rounded once to the element precision (F itself is not needed past this point)
+      Enew[e] = eb;
 #pragma unroll
       for (int r = 0; r < D; ++r) {
         Fb()[(size_t)(D * D + r) * ne + e] = T(S64.n[r] * S64.s);
 #pragma unroll
         for (int c = 0; c < D; ++c) Fb()[(size_t)(r * D + c) * ne + e] = T(S64.F[r][c]);
       }
+      lds_scatter(v, o, sc.s_pot);
       // the Jacobi diagonal in FP64 from the state already at hand, whatever the element precision
-      double od[D + 1][D];
-      elem_hessdiag<D, double>(R64, S64, A.a[e], od);
+      elem_hessdiag<D, double>(R64, S64, ae, o);
 #pragma unroll
       for (int k = 0; k <= D; ++k)
 #pragma unroll
-        for (int c = 0; c < D; ++c) unsafeAtomicAdd(acc2 + (v[k] - v0) * D + c, sc.s_pot * od[k][c]);
-    }
-    for (int vl = threadIdx.x; vl < v1 - v0; vl += blockDim.x) {
-      const int vg = v0 + vl;
-      double xa[D], xb[D];
-#pragma unroll
-      for (int c = 0; c < D; ++c) {
-        xa[c] = x[(size_t)vg * D + c];
-        xb[c] = dxp ? xa[c] + alpha * dxp[(size_t)vg * D + c] : xa[c];
-      }
-      const double ea = vertex_energy<D>(m, sc, vg, xa, A.x0, A.xhat, A.cv);
-      const double eb = vertex_energy<D>(m, sc, vg, xb, A.x0, A.xhat, A.cv);
-      sd += eb - ea;
-      sa += fabs(ea);
-      st += eb;
+        for (int c = 0; c < D; ++c) unsafeAtomicAdd(acc2 + (v[k] - v0) * D + c, sc.s_pot * o[k][c]);
     }
     __syncthreads();
+    // vertex terms, kV vertices per thread at a time: energies at x and xt, then per DOF the
+    // gradient, the vertex diagonal and the preconditioner
     double gg = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-      const int g = base + i;
-      const bool pin = pinned(i);
-      const double xt = dxp ? x[g] + alpha * dxp[g] : x[g];
-      const double gi = pin ? 0.0 : acc[i] + vgrad(i, xt);
-      Gout[g] = gi;
-      gg += gi * gi;
-      const double vd = pin ? 0.0 : vhdiag(i, xt);
-      const double d = fabs(acc2[i] + vd);
-      A.vdiag[g] = vd;
-      A.Dinvp[g] = pin ? 0.0 : (d > 0.0 ? 1.0 / d : 1.0);
-      acc[i] = 0.0;
-      acc2[i] = 0.0;
+    const int nv = v1 - v0, B = blockDim.x;
+    for (int vl0 = threadIdx.x; vl0 < nv; vl0 += kV * B) {
+      double xa[kV][D], dd[kV][D], x0v[kV][D], xhv[kV][D], mv[kV], cvv[kV];
+      bool pin[kV][D];
+#pragma unroll
+      for (int u = 0; u < kV; ++u) {
+        const int vl = vl0 + u * B;
+        if (vl < nv) {
+          const int vg = v0 + vl;
+          mv[u] = m.mass[vg];
+          cvv[u] = A.cv[vg];
+#pragma unroll
+          for (int c = 0; c < D; ++c) {
+            const size_t g = (size_t)vg * D + c;
+            xa[u][c] = x[g];
+            dd[u][c] = dxp ? dxp[g] : 0.0;
+            x0v[u][c] = A.x0[g];
+            xhv[u][c] = sc.be ? A.xhat[g] : 0.0;
+            pin[u][c] = m.pinned[g] != 0;
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kV; ++u) {
+        const int vl = vl0 + u * B;
+        if (vl < nv) {
+          double xb[D];
+#pragma unroll
+          for (int c = 0; c < D; ++c) xb[c] = xa[u][c] + alpha * dd[u][c];
+          const double ea = vertex_energy_vals<D>(sc, mv[u], cvv[u], xa[u], x0v[u], xhv[u]);
+          const double eb = vertex_energy_vals<D>(sc, mv[u], cvv[u], xb, x0v[u], xhv[u]);
+          sd += eb - ea;
+          sa += fabs(ea);
+          st += eb;
+#pragma unroll
+          for (int c = 0; c < D; ++c) {
+            const int i = vl * D + c;
+            const size_t g = (size_t)(v0 + vl) * D + c;
+            const double gi = pin[u][c] ? 0.0 : acc[i] + vgrad(c, xb[c], mv[u], cvv[u], x0v[u][c], xhv[u][c]);
+            gg += gi * gi;
+            const double vd = pin[u][c] ? 0.0 : vhdiag(c, xb[c], mv[u], cvv[u]);
+            const double d = fabs(acc2[i] + vd);
+            Gout[g] = gi;
+            A.vdiag[g] = vd;
+            A.Dinvp[g] = pin[u][c] ? 0.0 : (d > 0.0 ? 1.0 / d : 1.0);
+            acc[i] = 0.0;
+            acc2[i] = 0.0;
+          }
+        }
+      }
     }
     double t[4] = {sd, sa, st, gg};
     wg_sum<4>(t, red);
@@ -361,9 +392,24 @@ struct BodySolver {
   // state (F, F d) must have been stored by precond(x) or trial(). The direction p lives only in
   // LDS. Per iteration: the Hv pass, which also sums the element part of p^T H p; one vector pass
   // that updates xs and r and leaves z = M r in the accumulator; one LDS-only pass that forms the
-  // next p and the vertex part of its curvature. Vector passes take kU owned DOFs per thread at a
-  // time and issue all their loads before any arithmetic.
+  // next p.
   static constexpr int kU = 2;
+
+  // the kU owned DOFs from i0 on of xs, D^-1, r and vdiag. Indices past the body are clamped to
+  // its last DOF, so every lane loads unconditionally; the caller ignores those values.
+  __device__ __forceinline__ void cg_load(int i0, const double* xs, double (&x)[kU], double (&d)[kU],
+                                          double (&rv)[kU], double (&v)[kU]) const {
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int iu = i0 + u * (int)blockDim.x;
+      const int i = iu < n ? iu : n - 1;
+      const int g = base + i;
+      x[u] = xs[g];
+      d[u] = A.Dinvp[g];
+      rv[u] = A.r[g];
+      v[u] = A.vdiag[g];
+    }
+  }
 
   __device__ double cg(const double* rhs, double sign, double tol, int maxit, double* xs, int& iters, bool& neg) {
     double* r = A.r;
@@ -406,36 +452,42 @@ struct BodySolver {
         break;
       }
       const double alpha = rz / pHp;
-      double rz1 = 0.0;
+      // x/r update, kU owned DOFs per thread at a time and software-pipelined: the loads of the
+      // next chunk go out before the stores of this one. It also sums this thread's share of
+      // vd z^2, vd z p and vd p^2, from which the vertex part of the next direction's curvature
+      // follows once beta is known, so the direction pass below touches LDS only.
+      double rz1 = 0.0, zz = 0.0, zp = 0.0, pp = 0.0;
       rr = 0.0;
+      double cx[kU], cd[kU], cr[kU], cv[kU];
+      cg_load(threadIdx.x, xs, cx, cd, cr, cv);
       for (int i0 = threadIdx.x; i0 < n; i0 += kU * B) {
-        double xv[kU], dv[kU], rv[kU], vv[kU];
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-          const int i = i0 + u * B;
-          if (i < n) {
-            const int g = base + i;
-            xv[u] = xs[g];
-            dv[u] = Dv[g];
-            rv[u] = r[g];
-            vv[u] = vd[g];
-          }
-        }
+        double nx[kU], nd[kU], nr[kU], nv[kU];
+        cg_load(i0 + kU * B, xs, nx, nd, nr, nv);
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
           const int i = i0 + u * B;
           if (i < n) {
             const int g = base + i;
             const double pi = ps[i];
-            const double hp = acc[i] + vv[u] * pi;
-            xs[g] = xv[u] + alpha * pi;
-            const double ri = dv[u] != 0.0 ? rv[u] - alpha * hp : 0.0;
-            const double zi = dv[u] * ri;
+            const double hp = acc[i] + cv[u] * pi;
+            xs[g] = cx[u] + alpha * pi;
+            const double ri = cd[u] != 0.0 ? cr[u] - alpha * hp : 0.0;
+            const double zi = cd[u] * ri;
             r[g] = ri;
             acc[i] = zi;
             rz1 += ri * zi;
             rr += ri * ri;
+            zz += cv[u] * zi * zi;
+            zp += cv[u] * zi * pi;
+            pp += cv[u] * pi * pi;
           }
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          cx[u] = nx[u];
+          cd[u] = nd[u];
+          cr[u] = nr[u];
+          cv[u] = nv[u];
         }
       }
       {
@@ -451,12 +503,10 @@ struct BodySolver {
       }
       const double beta = rz1 / rz;
       rz = rz1;
-      pvp = 0.0;
+      pvp = zz + beta * (2.0 * zp + beta * pp);  // sum vd (z + beta p)^2 over this thread's DOFs
       for (int i = threadIdx.x; i < n; i += B) {
-        const double pn = acc[i] + beta * ps[i];
-        ps[i] = pn;
+        ps[i] = acc[i] + beta * ps[i];
         acc[i] = 0.0;
-        pvp += vd[base + i] * pn * pn;
       }
       __syncthreads();
     }

@@ -124,34 +124,45 @@ __device__ __forceinline__ void scatter_vertices(double* dst, const int v[D + 1]
 
 // per-vertex part of the step objective: s_pot (m g y + k_c ReLU(-y)^2 + k_fr cv |v_t|^2) + 1/2 m |x - xhat|^2
 template <int D>
-__device__ __forceinline__ double vertex_energy(const DevMesh& m, const DevScene& sc, int v, const double* xv,
-                                                const double* x0, const double* xhat, const double* cv) {
-  const double mv = m.mass[v];
+__device__ __forceinline__ double vertex_energy_vals(const DevScene& sc, double mv, double cv, const double* xv,
+                                                     const double* x0v, const double* xhv) {
   const double y = xv[1];
   double e = mv * sc.grav * y;
   const double pen = fmax(-y, 0.0);
   e += sc.kc * pen * pen;
   if (sc.kfr != 0.0) {
-    double vt2 = 0.0;
+    double dt2 = 0.0;  // |x_t - x0_t|^2 = h^2 |v_t|^2
 #pragma unroll
     for (int c = 0; c < D; ++c)
       if (c != 1) {
-        const double vt = (xv[c] - x0[(size_t)v * D + c]) / sc.h;
-        vt2 += vt * vt;
+        const double dt = xv[c] - x0v[c];
+        dt2 += dt * dt;
       }
-    e += sc.kfr * cv[v] * vt2;
+    e += sc.kfr * cv * dt2 * sc.ih2;
   }
   e *= sc.s_pot;
   if (sc.be) {
     double d2 = 0.0;
 #pragma unroll
     for (int c = 0; c < D; ++c) {
-      const double d = xv[c] - xhat[(size_t)v * D + c];
+      const double d = xv[c] - xhv[c];
       d2 += d * d;
     }
     e += 0.5 * mv * d2;
   }
   return e;
+}
+
+template <int D>
+__device__ __forceinline__ double vertex_energy(const DevMesh& m, const DevScene& sc, int v, const double* xv,
+                                                const double* x0, const double* xhat, const double* cv) {
+  double x0v[D], xhv[D];
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    x0v[c] = x0[(size_t)v * D + c];
+    xhv[c] = sc.be ? xhat[(size_t)v * D + c] : 0.0;
+  }
+  return vertex_energy_vals<D>(sc, m.mass[v], sc.kfr != 0.0 ? cv[v] : 0.0, xv, x0v, xhv);
 }
 
 }  // namespace isb

@@ -37,6 +37,7 @@ struct DevScene {
   double kc;       // contact stiffness
   double kfr;      // friction stiffness
   double eps;      // friction contact tolerance
+  double ih2;      // 1 / h^2
 };
 
 // Element index range: element k of [begin, end) is list[k] when list != nullptr, else k.

@@ -168,7 +168,7 @@ __global__ void __launch_bounds__(kBlock) k_vertex_grad(DevMesh m, DevScene sc, 
                                                         const double* __restrict__ x, const double* __restrict__ x0,
                                                         const double* __restrict__ xhat, const double* __restrict__ cv,
                                                         double* G) {
-  const double ih2 = 1.0 / (sc.h * sc.h);
+  const double ih2 = sc.ih2;
   for (int v = v0 + blockIdx.x * blockDim.x + threadIdx.x; v < v1; v += gridDim.x * blockDim.x) {
     const double mv = m.mass[v];
     const double cfr = 2.0 * sc.kfr * cv[v] * ih2;
@@ -192,7 +192,7 @@ template <int D>
 __global__ void __launch_bounds__(kBlock) k_vertex_hdiag(DevMesh m, DevScene sc, int v0, int v1,
                                                          const double* __restrict__ x, const double* __restrict__ cv,
                                                          double* vdiag) {
-  const double ih2 = 1.0 / (sc.h * sc.h);
+  const double ih2 = sc.ih2;
   for (int v = v0 + blockIdx.x * blockDim.x + threadIdx.x; v < v1; v += gridDim.x * blockDim.x) {
     const double mv = m.mass[v];
 #pragma unroll
@@ -278,7 +278,7 @@ __global__ void __launch_bounds__(kBlock) k_vertex_vjp(DevMesh m, DevScene sc, i
                                                        const double* __restrict__ x0,
                                                        const double* __restrict__ v1_bar, double* x0_bar,
                                                        double* v0_bar) {
-  const double ih2 = 1.0 / (sc.h * sc.h);
+  const double ih2 = sc.ih2;
   for (int v = v0 + blockIdx.x * blockDim.x + threadIdx.x; v < v1; v += gridDim.x * blockDim.x) {
     const double mv = m.mass[v];
     const size_t b = (size_t)v * D;

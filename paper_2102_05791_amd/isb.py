@@ -74,7 +74,8 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
     global _lib
     if _lib is not None and path is None:
         return _lib
-    p = path or LIB_PATH
+    # ISB_LIBRARY names another build of the same library (e.g. to compare two builds)
+    p = path or os.environ.get("ISB_LIBRARY") or LIB_PATH
     # torch ships its own HIP runtime under the same soname; loading torch first makes the library
     # bind to that one copy, so that both share one runtime, one device context and its streams
     import torch  # noqa: F401

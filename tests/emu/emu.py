@@ -30,7 +30,7 @@ class DevMesh(ctypes.Structure):
 
 
 class DevScene(ctypes.Structure):
-    _fields_ = [("be", ci), ("h", cd), ("s_pot", cd), ("grav", cd), ("kc", cd), ("kfr", cd), ("eps", cd)]
+    _fields_ = [("be", ci), ("h", cd), ("s_pot", cd), ("grav", cd), ("kc", cd), ("kfr", cd), ("eps", cd), ("ih2", cd)]
 
 
 class BatchArgs(ctypes.Structure):
@@ -102,7 +102,7 @@ class EmuBatch:
         sc = w.scene
         be = sc["integrator"] == "be"
         self.sc = DevScene(int(be), sc["h"], sc["h"] ** 2 if be else 1.0, sc["gravity"], sc["k_contact"],
-                           sc["k_friction"], sc["eps_friction"])
+                           sc["k_friction"], sc["eps_friction"], 1.0 / (sc["h"] * sc["h"]))
         nb = w.n_bodies
         ne_b = np.diff(w.body_e_off)
         self.order = k(np.argsort(-ne_b, kind="stable").astype(np.int32))
