@@ -9,6 +9,8 @@
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <queue>
+#include <utility>
 #include <vector>
 
 #include "isb_body.hpp"
@@ -21,7 +23,7 @@ namespace isb {
 template <int D, typename T, int MODE, int LB>
 __global__ void __launch_bounds__(LB) k_batched(DevMesh m, DevScene sc, BatchArgs A) {
   extern __shared__ double smem[];
-  batched_body<D, T, MODE>(m, sc, A, smem, (int)blockIdx.x, (int)gridDim.x);
+  batched_body<D, T, MODE>(m, sc, A, smem, (int)blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -29,7 +31,7 @@ __global__ void __launch_bounds__(LB) k_batched(DevMesh m, DevScene sc, BatchArg
 // ---------------------------------------------------------------------------------------------
 struct BatchedState {
   std::vector<void*> allocs;
-  int32_t *order = nullptr, *voff = nullptr, *eoff = nullptr;
+  int32_t *order = nullptr, *wg_off = nullptr, *voff = nullptr, *eoff = nullptr;
   DevStats* stats = nullptr;
   DevStats* hstats = nullptr;  // pinned host mirror
   void* Fbuf = nullptr;        // per-element F and F d in the element precision
@@ -82,6 +84,38 @@ void batched_release(isb_ctx* c) {
   c->batched = nullptr;
 }
 
+// Cost of a body in element-equivalents for the static schedule: a fixed part per body (the
+// vector passes, reductions and barriers of every CG iteration, which do not shrink with the
+// body) plus its elements.
+static constexpr double kBodyFixedCost = 1152.0;
+
+// Longest-processing-time schedule: bodies in decreasing cost go, one at a time, to the
+// workgroup with the least load so far (ties to the lowest index). Workgroup g solves
+// order[wg_off[g] .. wg_off[g+1]) in that order.
+static void lpt_schedule(const std::vector<int32_t>& eoff, int nb, int G, std::vector<int32_t>& order,
+                         std::vector<int32_t>& wg_off) {
+  std::vector<int32_t> byc(nb);
+  std::iota(byc.begin(), byc.end(), 0);
+  std::stable_sort(byc.begin(), byc.end(),
+                   [&](int a, int b) { return (eoff[a + 1] - eoff[a]) > (eoff[b + 1] - eoff[b]); });
+  using Load = std::pair<double, int>;
+  std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
+  for (int g = 0; g < G; ++g) heap.push({0.0, g});
+  std::vector<std::vector<int32_t>> lists(G);
+  for (int b : byc) {
+    Load l = heap.top();
+    heap.pop();
+    lists[l.second].push_back(b);
+    heap.push({l.first + kBodyFixedCost + (double)(eoff[b + 1] - eoff[b]), l.second});
+  }
+  order.clear();
+  wg_off.assign(1, 0);
+  for (int g = 0; g < G; ++g) {
+    order.insert(order.end(), lists[g].begin(), lists[g].end());
+    wg_off.push_back((int32_t)order.size());
+  }
+}
+
 isb_status batched_prepare(isb_ctx* c) {
   auto* st = static_cast<BatchedState*>(c->batched);
   const int want_block = c->block > 0 ? c->block : (c->dim == 2 ? 768 : 512);
@@ -90,38 +124,9 @@ isb_status batched_prepare(isb_ctx* c) {
   st = new BatchedState();
   c->batched = st;
   const int nb = c->n_bodies;
-  std::vector<int32_t> order(nb), voff(nb + 1), eoff(nb + 1);
-  for (int b = 0; b <= nb; ++b) {
-    voff[b] = (int32_t)c->voff[b];
-    eoff[b] = (int32_t)c->eoff[b];
-  }
-  std::iota(order.begin(), order.end(), 0);
-  // longest processing time first: bodies with more elements start earlier
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-    return (eoff[a + 1] - eoff[a]) > (eoff[b + 1] - eoff[b]);
-  });
-  auto alloc = [&](void** p, size_t bytes) -> isb_status {
-    ISB_HIP(hipMalloc(p, bytes));
-    st->allocs.push_back(*p);
-    return ISB_OK;
-  };
-  isb_status r;
-  if ((r = alloc((void**)&st->order, nb * 4)) != ISB_OK) return r;
-  if ((r = alloc((void**)&st->voff, (nb + 1) * 4)) != ISB_OK) return r;
-  if ((r = alloc((void**)&st->eoff, (nb + 1) * 4)) != ISB_OK) return r;
-  if ((r = alloc((void**)&st->stats, nb * sizeof(DevStats))) != ISB_OK) return r;
-  const size_t fwords = (size_t)(c->dim * c->dim + c->dim) * (size_t)c->n_e;
-  if ((r = alloc(&st->Fbuf, fwords * (c->precision == ISB_MIXED ? 4 : 8))) != ISB_OK) return r;
-  if ((r = alloc((void**)&st->E0, (size_t)c->n_e * sizeof(double))) != ISB_OK) return r;
-  if ((r = alloc((void**)&st->E1, (size_t)c->n_e * sizeof(double))) != ISB_OK) return r;
-  ISB_HIP(hipHostMalloc((void**)&st->hstats, nb * sizeof(DevStats), hipHostMallocDefault));
-  ISB_HIP(hipMemcpy(st->order, order.data(), nb * 4, hipMemcpyHostToDevice));
-  ISB_HIP(hipMemcpy(st->voff, voff.data(), (nb + 1) * 4, hipMemcpyHostToDevice));
-  ISB_HIP(hipMemcpy(st->eoff, eoff.data(), (nb + 1) * 4, hipMemcpyHostToDevice));
-  ISB_HIP(hipMemset(st->stats, 0, nb * sizeof(DevStats)));
   st->lds = (size_t)batched_lds_bytes(c);
   st->nacc = (int)batched_max_dof(c);
-  st->block = c->block > 0 ? c->block : (c->dim == 2 ? 1024 : 512);
+  st->block = want_block;
   st->precision = c->precision;
   st->dim = c->dim;
   int max_lds = 0, n_cu = 0;
@@ -140,6 +145,34 @@ isb_status batched_prepare(isb_ctx* c) {
   }
   if (occ < 1) return fail(ISB_E_ARG, "batched solver: kernel does not fit one workgroup per CU");
   st->grid = std::min(nb, occ * n_cu);
+
+  std::vector<int32_t> order, wg_off, voff(nb + 1), eoff(nb + 1);
+  for (int b = 0; b <= nb; ++b) {
+    voff[b] = (int32_t)c->voff[b];
+    eoff[b] = (int32_t)c->eoff[b];
+  }
+  lpt_schedule(eoff, nb, st->grid, order, wg_off);
+  auto alloc = [&](void** p, size_t bytes) -> isb_status {
+    ISB_HIP(hipMalloc(p, bytes));
+    st->allocs.push_back(*p);
+    return ISB_OK;
+  };
+  isb_status r;
+  if ((r = alloc((void**)&st->order, nb * 4)) != ISB_OK) return r;
+  if ((r = alloc((void**)&st->wg_off, (st->grid + 1) * 4)) != ISB_OK) return r;
+  if ((r = alloc((void**)&st->voff, (nb + 1) * 4)) != ISB_OK) return r;
+  if ((r = alloc((void**)&st->eoff, (nb + 1) * 4)) != ISB_OK) return r;
+  if ((r = alloc((void**)&st->stats, nb * sizeof(DevStats))) != ISB_OK) return r;
+  const size_t fwords = (size_t)(c->dim * c->dim + c->dim) * (size_t)c->n_e;
+  if ((r = alloc(&st->Fbuf, fwords * (c->precision == ISB_MIXED ? 4 : 8))) != ISB_OK) return r;
+  if ((r = alloc((void**)&st->E0, (size_t)c->n_e * sizeof(double))) != ISB_OK) return r;
+  if ((r = alloc((void**)&st->E1, (size_t)c->n_e * sizeof(double))) != ISB_OK) return r;
+  ISB_HIP(hipHostMalloc((void**)&st->hstats, nb * sizeof(DevStats), hipHostMallocDefault));
+  ISB_HIP(hipMemcpy(st->order, order.data(), nb * 4, hipMemcpyHostToDevice));
+  ISB_HIP(hipMemcpy(st->wg_off, wg_off.data(), (st->grid + 1) * 4, hipMemcpyHostToDevice));
+  ISB_HIP(hipMemcpy(st->voff, voff.data(), (nb + 1) * 4, hipMemcpyHostToDevice));
+  ISB_HIP(hipMemcpy(st->eoff, eoff.data(), (nb + 1) * 4, hipMemcpyHostToDevice));
+  ISB_HIP(hipMemset(st->stats, 0, nb * sizeof(DevStats)));
   return ISB_OK;
 }
 
@@ -147,6 +180,7 @@ static BatchArgs make_args(isb_ctx* c, BatchedState* st) {
   BatchArgs A;
   std::memset(&A, 0, sizeof(A));
   A.order = st->order;
+  A.wg_off = st->wg_off;
   A.voff = st->voff;
   A.eoff = st->eoff;
   A.n_bodies = c->n_bodies;

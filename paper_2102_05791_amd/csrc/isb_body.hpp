@@ -1,8 +1,8 @@
 // Body-level logic of the batched persistent solver, shared by the gfx950 kernel and by a
 // CPU build used in tests (a workgroup emulated with host threads).
 //
-// One workgroup solves one body at a time, dealt statically from the bodies sorted largest
-// first (see queue_position). Inside a body: Newton's method on the step
+// One workgroup solves one body at a time, from a list the host deals out ahead of the launch
+// (longest processing time first over a per-body cost model). Inside a body: Newton's method on the step
 // objective (Eq. 1 / Eq. 14) with a Jacobi-preconditioned CG inner solve, an Armijo line search
 // on element-wise energy differences, and v1 = (x1 - x0)/h; or, for the adjoint, one CG solve
 // of Eq. 9 at x1. The element scatter (gradient, Hessian diagonal, Hessian-vector product,
@@ -31,7 +31,8 @@ struct DevStats {
 static_assert(sizeof(DevStats) == sizeof(isb_stats), "stats layout");
 
 struct BatchArgs {
-  const int32_t* order;  // bodies, largest first
+  const int32_t* order;   // bodies of workgroup g: order[wg_off[g] .. wg_off[g+1])
+  const int32_t* wg_off;  // [grid+1]
   const int32_t* voff;   // [n_bodies+1]
   const int32_t* eoff;   // [n_bodies+1]
   int n_bodies;
@@ -52,10 +53,10 @@ struct BatchArgs {
 
 constexpr int kRedSlots = 16 * 4;  // up to 16 waves x 4 values
 
-// Values that steer control flow around barriers (the work-queue index, reduction results)
-// are read from LDS into vector registers, so the compiler cannot prove them uniform and would
-// structurize the loops around them as divergent, letting lanes loop back past the work-queue
-// fetch. Broadcasting them from the first active lane makes the branches scalar.
+// Values that steer control flow around barriers (the schedule's entries, reduction results)
+// are loaded into vector registers, so the compiler cannot prove them uniform and may structurize
+// the loops around them as divergent, letting some lanes loop back past a barrier the others have
+// not reached. Broadcasting them from the first active lane makes the branches scalar.
 __device__ __forceinline__ int wg_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 __device__ __forceinline__ double wg_uniform(double v) {
@@ -649,17 +650,8 @@ struct BodySolver {
   }
 };
 
-// Workgroup g solves the bodies at positions g, 2G-1-g, 2G+g, 4G-1-g, ... of the largest-first
-// order (G = number of workgroups): each round deals one body per workgroup, alternating the
-// direction, so heavy and light bodies pair up (a static approximation of longest-processing-
-// time scheduling). Every quantity in this loop is scalar, so the loop and its barriers stay
-// uniform.
-__device__ __forceinline__ int queue_position(int round, int g, int G) {
-  return round * G + ((round & 1) ? (G - 1 - g) : g);
-}
-
 template <int D, typename T, int MODE>  // MODE 0: step, 1: adjoint
-__device__ void batched_body(const DevMesh& m, const DevScene& sc, const BatchArgs& A, double* smem, int g, int G) {
+__device__ void batched_body(const DevMesh& m, const DevScene& sc, const BatchArgs& A, double* smem, int g) {
   double* red = smem;
   double* acc = smem + kRedSlots;
   double* ps = acc + A.nacc;
@@ -667,9 +659,10 @@ __device__ void batched_body(const DevMesh& m, const DevScene& sc, const BatchAr
   // clears the entries it used
   for (int i = threadIdx.x; i < 2 * A.nacc; i += blockDim.x) acc[i] = 0.0;
   __syncthreads();
-  for (int round = 0; round * G < A.n_bodies; ++round) {
-    const int k = queue_position(round, g, G);
-    if (k >= A.n_bodies) continue;
+  // the host's static schedule: every quantity in this loop is scalar, so the loop and its
+  // barriers stay uniform
+  const int k0 = wg_uniform(A.wg_off[g]), k1 = wg_uniform(A.wg_off[g + 1]);
+  for (int k = k0; k < k1; ++k) {
     const int body = wg_uniform(A.order[k]);
     const int bv0 = wg_uniform(A.voff[body]), bv1 = wg_uniform(A.voff[body + 1]);
     const int be0 = wg_uniform(A.eoff[body]), be1 = wg_uniform(A.eoff[body + 1]);

@@ -1,5 +1,5 @@
 // Runs the batched solver's body logic (isb_body.hpp) on the CPU: one workgroup of `block`
-// host threads pulls every body from the work queue. The emulated LDS starts filled with
+// host threads solves every body, largest first. The emulated LDS starts filled with
 // `lds_fill`, standing in for whatever an earlier kernel left there; the largest |value| left in
 // its two accumulators afterwards is returned in *lds_left. Test infrastructure only.
 #include <hip/hip_runtime.h>
@@ -32,7 +32,7 @@ static void run(int block, const isb::DevMesh* m, const isb::DevScene* sc, const
   for (int t = 0; t < block; ++t)
     th.emplace_back([&, t]() {
       threadIdx.x = t;
-      isb::batched_body<D, T, MODE>(*m, *sc, *A, smem.data(), 0, 1);
+      isb::batched_body<D, T, MODE>(*m, *sc, *A, smem.data(), 0);
     });
   for (auto& x : th) x.join();
   for (auto* b : waves) delete b;

@@ -34,7 +34,7 @@ class DevScene(ctypes.Structure):
 
 
 class BatchArgs(ctypes.Structure):
-    _fields_ = [("order", vp), ("voff", vp), ("eoff", vp), ("n_bodies", ci),
+    _fields_ = [("order", vp), ("wg_off", vp), ("voff", vp), ("eoff", vp), ("n_bodies", ci),
                 ("x0", vp), ("v0", vp), ("a", vp), ("a32", vp), ("x1", vp), ("v1", vp), ("xbar", vp),
                 ("vbar", vp), ("w", vp), ("xhat", vp), ("G", vp), ("Gt", vp), ("dx", vp), ("r", vp),
                 ("Dinvp", vp), ("vdiag", vp), ("cv", vp), ("stats", vp), ("tol", cd), ("adj_tol", cd),
@@ -106,6 +106,7 @@ class EmuBatch:
         nb = w.n_bodies
         ne_b = np.diff(w.body_e_off)
         self.order = k(np.argsort(-ne_b, kind="stable").astype(np.int32))
+        self.wg_off = k(np.array([0, nb], dtype=np.int32))  # one workgroup takes every body
         self.voff = k(w.body_v_off.astype(np.int32))
         self.eoff = k(w.body_e_off.astype(np.int32))
         self.nacc = int((np.diff(w.body_v_off) * d).max())
@@ -121,7 +122,7 @@ class EmuBatch:
     def _args(self, **kw):
         A = BatchArgs()
         sc = self.w.scene
-        A.order, A.voff, A.eoff = _p(self.order), _p(self.voff), _p(self.eoff)
+        A.order, A.wg_off, A.voff, A.eoff = _p(self.order), _p(self.wg_off), _p(self.voff), _p(self.eoff)
         A.n_bodies = self.w.n_bodies
         for n in ("xhat", "G", "Gt", "dx", "r", "Dinvp", "vdiag"):
             setattr(A, n, _p(self.ws[n]))
