@@ -61,22 +61,31 @@ def elem_bytes(dim, word):
     return 4 * (dim + 1) + word * (dim * dim + dim + 3 + 1)
 
 
-def fstate_bytes(dim, word):
-    """F and F d stored per element at the Newton iterate."""
-    return word * (dim * dim + dim)
+def hv_state_bytes(dim, word):
+    """Per-element state the Hessian-vector pass reads at a Newton iterate: the symmetric 4x4
+    Hessian with respect to the edge matrix for triangles (10 words), F and F d for tetrahedra."""
+    return word * (10 if dim == 2 else dim * dim + dim)
+
+
+def hv_elem_bytes(dim, word):
+    """Element bytes of one Hessian-vector pass: conn + the stored state (triangles), or conn +
+    rest data + actuation + the stored F, F d (tetrahedra)."""
+    if dim == 2:
+        return 4 * (dim + 1) + hv_state_bytes(dim, word)
+    return elem_bytes(dim, word) + hv_state_bytes(dim, word)
 
 
 def cg_iter_bytes(dim, ne, nv, word_hv):
-    """One batched CG iteration: the Hessian-vector element pass (rest data + stored F; p is in
-    LDS), the x/r update pass (xs, r read and written, D^-1 and vdiag read) and the p pass
-    (vdiag read)."""
-    return (elem_bytes(dim, word_hv) + fstate_bytes(dim, word_hv)) * ne + 56 * nv * dim
+    """One batched CG iteration: the Hessian-vector element pass (p is in LDS), and the x/r update
+    pass (xs, r read and written, D^-1 and vdiag read); the direction pass touches LDS only."""
+    return hv_elem_bytes(dim, word_hv) * ne + 48 * nv * dim
 
 
 def trial_bytes(dim, ne, nv, word_hv):
-    """One fused line-search trial: FP64 rest data, E(x) read, E(x_t) written, F stored per element;
-    x, dx, x0, xhat, pinned read and G, vdiag, D^-1 written per DOF; mass and c_v per vertex."""
-    return (elem_bytes(dim, 8) + 16 + fstate_bytes(dim, word_hv)) * ne + 57 * nv * dim + 16 * nv
+    """One fused line-search trial: FP64 rest data, E(x) read, E(x_t) written, the Hessian-vector
+    state stored per element; x, dx, x0, xhat, pinned read and G, vdiag, D^-1 written per DOF;
+    mass and c_v per vertex."""
+    return (elem_bytes(dim, 8) + 16 + hv_state_bytes(dim, word_hv)) * ne + 57 * nv * dim + 16 * nv
 
 
 def step_launch_bytes(dim, ne, nv, st, word_hv):
@@ -90,11 +99,11 @@ def step_launch_bytes(dim, ne, nv, st, word_hv):
 
 
 def adjoint_launch_bytes(dim, ne, nv, st, word_hv):
-    """Right-hand side (xbar, vbar, pinned -> G; c_v), the FP64 diagonal pass that also stores F,
-    the CG start and the CG iterations."""
+    """Right-hand side (xbar, vbar, pinned -> G; c_v), the FP64 diagonal pass that also stores the
+    Hessian-vector state, the CG start and the CG iterations."""
     dof = nv * dim
     rhs = 25 * dof + 16 * nv
-    diag = (elem_bytes(dim, 8) + fstate_bytes(dim, word_hv)) * ne + 25 * dof + 16 * nv
+    diag = (elem_bytes(dim, 8) + hv_state_bytes(dim, word_hv)) * ne + 25 * dof + 16 * nv
     return rhs + diag + 40 * dof + st["adj_cg_iters"] * cg_iter_bytes(dim, ne, nv, word_hv)
 
 

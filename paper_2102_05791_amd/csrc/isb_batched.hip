@@ -34,7 +34,7 @@ struct BatchedState {
   int32_t *order = nullptr, *wg_off = nullptr, *voff = nullptr, *eoff = nullptr;
   DevStats* stats = nullptr;
   DevStats* hstats = nullptr;  // pinned host mirror
-  void* Fbuf = nullptr;        // per-element F and F d in the element precision
+  void* Fbuf = nullptr;        // per-element Hessian-vector state in the element precision
   double *E0 = nullptr, *E1 = nullptr;  // per-element energies (iterate, trial)
   int nacc = 0, grid = 0, block = 0, precision = -1, dim = 0;
   size_t lds = 0;
@@ -163,7 +163,7 @@ isb_status batched_prepare(isb_ctx* c) {
   if ((r = alloc((void**)&st->voff, (nb + 1) * 4)) != ISB_OK) return r;
   if ((r = alloc((void**)&st->eoff, (nb + 1) * 4)) != ISB_OK) return r;
   if ((r = alloc((void**)&st->stats, nb * sizeof(DevStats))) != ISB_OK) return r;
-  const size_t fwords = (size_t)(c->dim * c->dim + c->dim) * (size_t)c->n_e;
+  const size_t fwords = (size_t)hv_state_words(c->dim) * (size_t)c->n_e;
   if ((r = alloc(&st->Fbuf, fwords * (c->precision == ISB_MIXED ? 4 : 8))) != ISB_OK) return r;
   if ((r = alloc((void**)&st->E0, (size_t)c->n_e * sizeof(double))) != ISB_OK) return r;
   if ((r = alloc((void**)&st->E1, (size_t)c->n_e * sizeof(double))) != ISB_OK) return r;

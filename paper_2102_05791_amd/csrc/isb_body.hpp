@@ -47,11 +47,17 @@ struct BatchArgs {
   int max_newton, max_cg;
   int want_tail;  // 1: final energy and min/max J into the stats
   int nacc;       // LDS accumulator length: the largest body's DOF count
-  void* Fbuf;     // [(D*D + D)][n_e] per-element F and F d at the current Newton iterate (element precision)
+  void* Fbuf;     // [hv_state_words(D)][n_e] per-element Hessian-vector state at the current Newton
+                  // iterate, in the element precision (see BodySolver::store_hv_state)
   double *E0, *E1;  // [n_e] per-element energies at the iterate and at the line-search trial
 };
 
 constexpr int kRedSlots = 16 * 4;  // up to 16 waves x 4 values
+
+// Words of per-element state the Hessian-vector pass reads: triangles keep the symmetric 4x4
+// Hessian of W psi with respect to the edge matrix (10 words); tetrahedra keep F and F d (12),
+// from which the product is formed matrix-free.
+__host__ __device__ constexpr int hv_state_words(int dim) { return dim == 2 ? 10 : dim * dim + dim; }
 
 // Values that steer control flow around barriers (the schedule's entries, reduction results)
 // are loaded into vector registers, so the compiler cannot prove them uniform and may structurize
@@ -148,73 +154,166 @@ struct BodySolver {
       return A.a32[e];
   }
 
-  // Hessian-vector pass: element data and the stored F stream in coalesced; p comes from LDS.
-  // Returns this thread's share of p^T H_elem p = sum over elements of p_e . (H_e p_e), so the
-  // CG curvature needs no separate pass over the scattered product.
+  // Hessian-vector pass: the per-element state streams in coalesced, p comes from LDS. Edge
+  // differences of p are formed in FP64 before any rounding to T. Returns this thread's share of
+  // p^T H_elem p = sum over elements of dDs(p) . (K_s dDs(p)), so the CG curvature needs no
+  // separate pass over the scattered product.
+  static constexpr bool kEdgeHessian = (D == 2);
+  static constexpr int kQ = D * D;  // entries of the edge matrix, q = j * D + r for Ds[r][j]
+
   __device__ double pass_hv() {
     const size_t ne = (size_t)m.n_e;
     double php = 0.0;
     for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
       int v[D + 1];
       load_conn<D>(m, e, v);
-      ElemRest<D, T> R;
-      load_rest<D, T>(m, e, R);
-      T F[D][D], Fd[D];
+      T out[D + 1][D];
+      double d64[kQ];  // edge differences of p, q = j * D + r
+      if constexpr (kEdgeHessian) {
+        T K[hv_state_words(D)];
 #pragma unroll
-      for (int r = 0; r < D; ++r) {
+        for (int w = 0; w < hv_state_words(D); ++w) K[w] = Fb()[(size_t)w * ne + e];
+        edge_diffs(v, d64);
+        T dd[kQ], y[kQ];
 #pragma unroll
-        for (int c = 0; c < D; ++c) F[r][c] = Fb()[(size_t)(r * D + c) * ne + e];
-        Fd[r] = Fb()[(size_t)(D * D + r) * ne + e];
+        for (int q = 0; q < kQ; ++q) dd[q] = T(d64[q]);
+        sym_apply(K, dd, y);
+#pragma unroll
+        for (int r = 0; r < D; ++r) out[0][r] = T(0);
+#pragma unroll
+        for (int j = 0; j < D; ++j)
+#pragma unroll
+          for (int r = 0; r < D; ++r) {
+            out[j + 1][r] = y[j * D + r];
+            out[0][r] -= y[j * D + r];
+          }
+      } else {
+        ElemRest<D, T> R;
+        load_rest<D, T>(m, e, R);
+        T F[D][D], Fd[D];
+#pragma unroll
+        for (int r = 0; r < D; ++r) {
+#pragma unroll
+          for (int c = 0; c < D; ++c) F[r][c] = Fb()[(size_t)(r * D + c) * ne + e];
+          Fd[r] = Fb()[(size_t)(D * D + r) * ne + e];
+        }
+        const T ae = act(e);
+        edge_diffs(v, d64);
+        T dDs[D][D];
+#pragma unroll
+        for (int j = 0; j < D; ++j)
+#pragma unroll
+          for (int r = 0; r < D; ++r) dDs[r][j] = T(d64[j * D + r]);
+        ElemState<D, T> S;
+        elem_state_from_F<D, T>(F, Fd, S);
+        elem_hessvec<D, T>(R, S, ae, dDs, out);
       }
-      const T ae = act(e);
-      double pv[D + 1][D];
-#pragma unroll
-      for (int k = 0; k <= D; ++k)
-#pragma unroll
-        for (int c = 0; c < D; ++c) pv[k][c] = ps[(v[k] - v0) * D + c];
-      T dDs[D][D];
+      // sum_k out_k . p_k = sum_j out_{j+1} . (p_{j+1} - p_0), since out_0 = -sum_j out_{j+1}
 #pragma unroll
       for (int j = 0; j < D; ++j)
 #pragma unroll
-        for (int c = 0; c < D; ++c) dDs[c][j] = T(pv[j + 1][c] - pv[0][c]);
-      ElemState<D, T> S;
-      elem_state_from_F<D, T>(F, Fd, S);
-      T out[D + 1][D];
-      elem_hessvec<D, T>(R, S, ae, dDs, out);
+        for (int r = 0; r < D; ++r) php += double(out[j + 1][r]) * d64[j * D + r];
       double o[D + 1][D];
 #pragma unroll
       for (int k = 0; k <= D; ++k)
 #pragma unroll
-        for (int c = 0; c < D; ++c) {
-          o[k][c] = double(out[k][c]);
-          php += o[k][c] * pv[k][c];
-        }
+        for (int c = 0; c < D; ++c) o[k][c] = double(out[k][c]);
       lds_scatter(v, o, sc.s_pot);
     }
     return sc.s_pot * php;
   }
 
-  // diagonal pass (FP64); also stores F and F d of every element, rounded once to the element
-  // precision, for the Hessian-vector passes that follow
-  __device__ void pass_diag(const double* x) {
+  // FP64 edge differences of the LDS direction p over one element, q = j * D + r
+  __device__ __forceinline__ void edge_diffs(const int v[D + 1], double d64[kQ]) const {
+    double p0[D];
+#pragma unroll
+    for (int r = 0; r < D; ++r) p0[r] = ps[(v[0] - v0) * D + r];
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+#pragma unroll
+      for (int r = 0; r < D; ++r) d64[j * D + r] = ps[(v[j + 1] - v0) * D + r] - p0[r];
+  }
+
+  // y = K x for the symmetric kQ x kQ matrix whose upper triangle K holds row by row
+  __device__ __forceinline__ static void sym_apply(const T* K, const T* x, T* y) {
+#pragma unroll
+    for (int a = 0; a < kQ; ++a) y[a] = T(0);
+    int w = 0;
+#pragma unroll
+    for (int a = 0; a < kQ; ++a)
+#pragma unroll
+      for (int b = a; b < kQ; ++b, ++w) {
+        y[a] += K[w] * x[b];
+        if (b != a) y[b] += K[w] * x[a];
+      }
+  }
+
+  // Stores what the Hessian-vector passes need at this iterate and returns the element's Hessian
+  // diagonal per vertex and axis (FP64, before the s_pot scale). Triangles: the Hessian of W psi
+  // with respect to the edge matrix, K_s[q][q'] = d^2 (W psi) / dDs_q dDs_q', built column by
+  // column from Hessian-vector products with unit edge displacements and rounded once to T; a unit
+  // move of vertex j+1 along r is the unit edge displacement q = j D + r, one of vertex 0 moves
+  // every edge by -e_r. Tetrahedra: F and F d, rounded once to T, and the closed-form diagonal.
+  __device__ __forceinline__ void store_hv_state(int e, const ElemRest<D, double>& R64,
+                                                 const ElemState<D, double>& S64, double ae,
+                                                 double diag[D + 1][D]) const {
     const size_t ne = (size_t)m.n_e;
-    for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-      int v[D + 1];
-      load_conn<D>(m, e, v);
-      ElemRest<D, double> R64;
-      load_rest<D, double>(m, e, R64);
-      double Ds[D][D];
-      gather_edges<D, double>(x, v, Ds);
-      ElemState<D, double> S64;
-      elem_state<D, double>(Ds, R64, S64);
+    if constexpr (kEdgeHessian) {
+      double K[kQ][kQ];
+#pragma unroll
+      for (int q = 0; q < kQ; ++q) {
+        double dDs[D][D], out[D + 1][D];
+#pragma unroll
+        for (int j = 0; j < D; ++j)
+#pragma unroll
+          for (int r = 0; r < D; ++r) dDs[r][j] = (j * D + r == q) ? 1.0 : 0.0;
+        elem_hessvec<D, double>(R64, S64, ae, dDs, out);
+#pragma unroll
+        for (int j = 0; j < D; ++j)
+#pragma unroll
+          for (int r = 0; r < D; ++r) K[j * D + r][q] = out[j + 1][r];
+      }
+      int w = 0;
+#pragma unroll
+      for (int a = 0; a < kQ; ++a)
+#pragma unroll
+        for (int b = a; b < kQ; ++b, ++w) Fb()[(size_t)w * ne + e] = T(K[a][b]);
+#pragma unroll
+      for (int r = 0; r < D; ++r) {
+        double d0 = 0.0;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+          diag[j + 1][r] = K[j * D + r][j * D + r];
+#pragma unroll
+          for (int jj = 0; jj < D; ++jj) d0 += K[j * D + r][jj * D + r];
+        }
+        diag[0][r] = d0;
+      }
+    } else {
 #pragma unroll
       for (int r = 0; r < D; ++r) {
         Fb()[(size_t)(D * D + r) * ne + e] = T(S64.n[r] * S64.s);
 #pragma unroll
         for (int c = 0; c < D; ++c) Fb()[(size_t)(r * D + c) * ne + e] = T(S64.F[r][c]);
       }
+      elem_hessdiag<D, double>(R64, S64, ae, diag);
+    }
+  }
+
+  // diagonal pass (FP64); also stores the Hessian-vector state of every element
+  __device__ void pass_diag(const double* x) {
+    for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+      int v[D + 1];
+      load_conn<D>(m, e, v);
+      ElemRest<D, double> R64;
+      load_rest<D, double>(m, e, R64);
+      const double ae = A.a[e];
+      double Ds[D][D];
+      gather_edges<D, double>(x, v, Ds);
+      ElemState<D, double> S64;
+      elem_state<D, double>(Ds, R64, S64);
       double od[D + 1][D];
-      elem_hessdiag<D, double>(R64, S64, A.a[e], od);
+      store_hv_state(e, R64, S64, ae, od);
       lds_scatter(v, od, sc.s_pot);
     }
   }
@@ -291,18 +390,11 @@ struct BodySolver {
       st += eb;
       double o[D + 1][D];
       elem_grad<D, double>(R64, S64, ae, o);
-      // global stores once every load of the iteration has been issued: the energy, and F, F d
-      // rounded once to the element precision (F itself is not needed past this point)
-      Enew[e] = eb;
-#pragma unroll
-      for (int r = 0; r < D; ++r) {
-        Fb()[(size_t)(D * D + r) * ne + e] = T(S64.n[r] * S64.s);
-#pragma unroll
-        for (int c = 0; c < D; ++c) Fb()[(size_t)(r * D + c) * ne + e] = T(S64.F[r][c]);
-      }
       lds_scatter(v, o, sc.s_pot);
-      // the Jacobi diagonal in FP64 from the state already at hand, whatever the element precision
-      elem_hessdiag<D, double>(R64, S64, ae, o);
+      // global stores once every load of the iteration has been issued: the energy, and the
+      // Hessian-vector state, whose computation also yields the Jacobi diagonal (FP64)
+      Enew[e] = eb;
+      store_hv_state(e, R64, S64, ae, o);
 #pragma unroll
       for (int k = 0; k <= D; ++k)
 #pragma unroll

@@ -114,7 +114,7 @@ class EmuBatch:
         self.ws = {n: k(np.zeros(nd)) for n in ("xhat", "G", "Gt", "dx", "r", "Dinvp", "vdiag")}
         self.cv = k(np.zeros(w.n_v))
         self.stats = k(np.zeros(nb, dtype=STATS_DTYPE))
-        self.Fbuf = k(np.zeros((d * d + d) * w.n_e, dtype=np.float64))
+        self.Fbuf = k(np.zeros((10 if d == 2 else d * d + d) * w.n_e, dtype=np.float64))  # hv_state_words
         self.E0 = k(np.zeros(w.n_e))
         self.E1 = k(np.zeros(w.n_e))
         self.be = be
