@@ -129,13 +129,19 @@ struct BodySolver {
   const DevMesh& m;
   const DevScene& sc;
   const BatchArgs& A;
-  double* acc;  // LDS [n_loc * D], zero between passes
+  double* acc;  // LDS, one value per body DOF (layout lv below), zero between passes
   double* red;  // LDS reduction slots
-  double* ps;   // LDS [n_loc * D]: the CG direction p inside cg() (FP64: the Hv pass takes
+  double* ps;   // LDS, same layout: the CG direction p inside cg() (FP64: the Hv pass takes
                 // differences of it), the diagonal accumulator of trial(); zero outside both
   int v0, v1, e0, e1, n, base;
 
   __device__ __forceinline__ T* Fb() const { return reinterpret_cast<T*>(A.Fbuf); }
+
+  // LDS arrays hold one component plane after the other (vertex vl, axis c at c * nvs + vl), so
+  // that the FP64 atomics of a wave, which touch runs of nearby vertices, spread over the banks;
+  // the interleaved layout of the global vectors would put vertices 8 apart on one bank.
+  __device__ __forceinline__ int lv(int vl, int c) const { return c * (A.nacc / D) + vl; }
+  __device__ __forceinline__ int ld(int i) const { return lv(i / D, i % D); }  // body DOF i = vl * D + c
 
   __device__ __forceinline__ bool pinned(int i) const { return m.pinned[base + i] != 0; }
 
@@ -144,7 +150,7 @@ struct BodySolver {
 #pragma unroll
     for (int k = 0; k <= D; ++k)
 #pragma unroll
-      for (int c = 0; c < D; ++c) unsafeAtomicAdd(acc + (v[k] - v0) * D + c, scale * out[k][c]);
+      for (int c = 0; c < D; ++c) unsafeAtomicAdd(acc + lv(v[k] - v0, c), scale * out[k][c]);
   }
 
   __device__ __forceinline__ T act(int e) const {
@@ -227,11 +233,11 @@ struct BodySolver {
   __device__ __forceinline__ void edge_diffs(const int v[D + 1], double d64[kQ]) const {
     double p0[D];
 #pragma unroll
-    for (int r = 0; r < D; ++r) p0[r] = ps[(v[0] - v0) * D + r];
+    for (int r = 0; r < D; ++r) p0[r] = ps[lv(v[0] - v0, r)];
 #pragma unroll
     for (int j = 0; j < D; ++j)
 #pragma unroll
-      for (int r = 0; r < D; ++r) d64[j * D + r] = ps[(v[j + 1] - v0) * D + r] - p0[r];
+      for (int r = 0; r < D; ++r) d64[j * D + r] = ps[lv(v[j + 1] - v0, r)] - p0[r];
   }
 
   // y = K x for the symmetric kQ x kQ matrix whose upper triangle K holds row by row
@@ -347,10 +353,10 @@ struct BodySolver {
       const int vg = v0 + i / D, c = i % D;
       const bool pin = pinned(i);
       const double vd = pin ? 0.0 : vhdiag(c, x[base + i], m.mass[vg], A.cv[vg]);
-      const double d = fabs(acc[i] + vd);
+      const double d = fabs(acc[ld(i)] + vd);
       A.vdiag[base + i] = vd;
       A.Dinvp[base + i] = pin ? 0.0 : (d > 0.0 ? 1.0 / d : 1.0);
-      acc[i] = 0.0;
+      acc[ld(i)] = 0.0;
     }
     __syncthreads();
   }
@@ -398,7 +404,7 @@ struct BodySolver {
 #pragma unroll
       for (int k = 0; k <= D; ++k)
 #pragma unroll
-        for (int c = 0; c < D; ++c) unsafeAtomicAdd(acc2 + (v[k] - v0) * D + c, sc.s_pot * o[k][c]);
+        for (int c = 0; c < D; ++c) unsafeAtomicAdd(acc2 + lv(v[k] - v0, c), sc.s_pot * o[k][c]);
     }
     __syncthreads();
     // vertex terms, kV vertices per thread at a time: energies at x and xt, then per DOF the
@@ -440,7 +446,7 @@ struct BodySolver {
           st += eb;
 #pragma unroll
           for (int c = 0; c < D; ++c) {
-            const int i = vl * D + c;
+            const int i = lv(vl, c);
             const size_t g = (size_t)(v0 + vl) * D + c;
             const double gi = pin[u][c] ? 0.0 : acc[i] + vgrad(c, xb[c], mv[u], cvv[u], x0v[u][c], xhv[u][c]);
             gg += gi * gi;
@@ -516,7 +522,7 @@ struct BodySolver {
       const double ri = di != 0.0 ? sign * rhs[g] : 0.0;
       const double zi = di * ri;
       r[g] = ri;
-      ps[i] = zi;
+      ps[ld(i)] = zi;
       xs[g] = 0.0;
       rz += ri * zi;
       rr += ri * ri;
@@ -539,8 +545,8 @@ struct BodySolver {
         // steepest-descent direction (Nocedal & Wright, Alg. 7.1)
         neg = true;
         for (int i = threadIdx.x; i < n; i += B) {
-          if (it == 0) xs[base + i] = ps[i];
-          acc[i] = 0.0;
+          if (it == 0) xs[base + i] = ps[ld(i)];
+          acc[ld(i)] = 0.0;
         }
         break;
       }
@@ -561,13 +567,14 @@ struct BodySolver {
           const int i = i0 + u * B;
           if (i < n) {
             const int g = base + i;
-            const double pi = ps[i];
-            const double hp = acc[i] + cv[u] * pi;
+            const int li = ld(i);
+            const double pi = ps[li];
+            const double hp = acc[li] + cv[u] * pi;
             xs[g] = cx[u] + alpha * pi;
             const double ri = cd[u] != 0.0 ? cr[u] - alpha * hp : 0.0;
             const double zi = cd[u] * ri;
             r[g] = ri;
-            acc[i] = zi;
+            acc[li] = zi;
             rz1 += ri * zi;
             rr += ri * ri;
             zz += cv[u] * zi * zi;
@@ -591,20 +598,21 @@ struct BodySolver {
       }
       iters = it + 1;
       if (rr <= tol2) {
-        for (int i = threadIdx.x; i < n; i += B) acc[i] = 0.0;
+        for (int i = threadIdx.x; i < n; i += B) acc[ld(i)] = 0.0;
         break;
       }
       const double beta = rz1 / rz;
       rz = rz1;
       pvp = zz + beta * (2.0 * zp + beta * pp);  // sum vd (z + beta p)^2 over this thread's DOFs
       for (int i = threadIdx.x; i < n; i += B) {
-        ps[i] = acc[i] + beta * ps[i];
-        acc[i] = 0.0;
+        const int li = ld(i);
+        ps[li] = acc[li] + beta * ps[li];
+        acc[li] = 0.0;
       }
       __syncthreads();
     }
     // every exit leaves p behind in LDS: clear it for the trial pass, which accumulates there
-    for (int i = threadIdx.x; i < n; i += B) ps[i] = 0.0;
+    for (int i = threadIdx.x; i < n; i += B) ps[ld(i)] = 0.0;
     __syncthreads();
     return rr;
   }
