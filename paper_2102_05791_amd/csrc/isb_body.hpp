@@ -52,7 +52,12 @@ struct BatchArgs {
   double *E0, *E1;  // [n_e] per-element energies at the iterate and at the line-search trial
 };
 
-constexpr int kRedSlots = 16 * 4;  // up to 16 waves x 4 values
+// Reduction slots: two banks of up to 16 waves x 4 values. Consecutive workgroup reductions use
+// alternate banks, so one barrier per reduction suffices: a wave writing a bank two reductions
+// later has passed the barrier of the reduction in between, which every reader of the bank's
+// previous contents reached only after reading them.
+constexpr int kRedBank = 16 * 4;
+constexpr int kRedSlots = 2 * kRedBank;
 
 // Words of per-element state the Hessian-vector pass reads: triangles keep the symmetric 4x4
 // Hessian of W psi with respect to the edge matrix (10 words); tetrahedra keep F and F d (12),
@@ -72,29 +77,50 @@ __device__ __forceinline__ double wg_uniform(double v) {
   return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 
-// sum of N values over the workgroup; every thread receives the same bits
+// A DPP cross-lane move of an FP64 value (both 32-bit halves take the same move); lanes in rows
+// outside ROWS receive 0.0.
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ double dpp_move(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, ROWS, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// Sum over the 64 lanes of a wave (all lanes active), returned to every lane. Within each row of
+// 16 lanes: quad_perm [1,0,3,2] and [2,3,0,1] sum the quads, row_ror 4 and 8 the row; then
+// row_bcast 15 adds row 0 into row 1 and row 2 into row 3, row_bcast 31 rows 0-1 into rows 2-3,
+// and lane 63 holds the total in a fixed order.
+__device__ __forceinline__ double wave_total(double v) {
+  v += dpp_move<0xB1>(v);
+  v += dpp_move<0x4E>(v);
+  v += dpp_move<0x124>(v);
+  v += dpp_move<0x128>(v);
+  v += dpp_move<0x142, 0xA>(v);
+  v += dpp_move<0x143, 0xC>(v);
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), 63);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// sum of N values over the workgroup into one bank of reduction slots; every thread receives the
+// same bits
 template <int N>
-__device__ __forceinline__ void wg_sum(double (&v)[N], double* red) {
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+__device__ __forceinline__ void wg_sum(double (&v)[N], double* bank) {
+  const int wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
 #pragma unroll
-  for (int k = 0; k < N; ++k) v[k] = wave_sum(v[k]);
-  if (lane == 0)
+  for (int k = 0; k < N; ++k) v[k] = wave_total(v[k]);
+  if ((threadIdx.x & 63) == 0)
 #pragma unroll
-    for (int k = 0; k < N; ++k) red[wid * N + k] = v[k];
+    for (int k = 0; k < N; ++k) bank[wid * N + k] = v[k];
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < N; ++k) {
     double s = 0.0;
-    for (int w = 0; w < nw; ++w) s += red[w * N + k];
+    for (int w = 0; w < nw; ++w) s += bank[w * N + k];
     v[k] = wg_uniform(s);
   }
-  __syncthreads();
-}
-
-__device__ __forceinline__ double wg_sum1(double v, double* red) {
-  double t[1] = {v};
-  wg_sum<1>(t, red);
-  return t[0];
 }
 
 __device__ __forceinline__ double wave_min(double v) {
@@ -103,25 +129,24 @@ __device__ __forceinline__ double wave_min(double v) {
   return v;
 }
 
-// (min, max) over the workgroup, every thread receives the result
-__device__ __forceinline__ void wg_minmax(double& lo, double& hi, double* red) {
+// (min, max) over the workgroup into one bank of reduction slots, every thread receives the result
+__device__ __forceinline__ void wg_minmax(double& lo, double& hi, double* bank) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
   lo = wave_min(lo);
   hi = -wave_min(-hi);
   if (lane == 0) {
-    red[2 * wid] = lo;
-    red[2 * wid + 1] = hi;
+    bank[2 * wid] = lo;
+    bank[2 * wid + 1] = hi;
   }
   __syncthreads();
   lo = 1e300;
   hi = -1e300;
   for (int w = 0; w < nw; ++w) {
-    lo = fmin(lo, red[2 * w]);
-    hi = fmax(hi, red[2 * w + 1]);
+    lo = fmin(lo, bank[2 * w]);
+    hi = fmax(hi, bank[2 * w + 1]);
   }
   lo = wg_uniform(lo);
   hi = wg_uniform(hi);
-  __syncthreads();
 }
 
 template <int D, typename T>
@@ -130,12 +155,26 @@ struct BodySolver {
   const DevScene& sc;
   const BatchArgs& A;
   double* acc;  // LDS, one value per body DOF (layout lv below), zero between passes
-  double* red;  // LDS reduction slots
+  double* red;  // LDS reduction slots, two banks (see kRedSlots)
   double* ps;   // LDS, same layout: the CG direction p inside cg() (FP64: the Hv pass takes
                 // differences of it), the diagonal accumulator of trial(); zero outside both
   int v0, v1, e0, e1, n, base;
 
+  int rbank = 0;  // bank of the last workgroup reduction
+
   __device__ __forceinline__ T* Fb() const { return reinterpret_cast<T*>(A.Fbuf); }
+
+  // workgroup reductions, alternating between the two banks of slots
+  template <int N>
+  __device__ __forceinline__ void sum(double (&v)[N]) {
+    rbank ^= 1;
+    wg_sum<N>(v, red + rbank * kRedBank);
+  }
+  __device__ __forceinline__ double sum1(double v) {
+    double t[1] = {v};
+    sum<1>(t);
+    return t[0];
+  }
 
   // LDS arrays hold one component plane after the other (vertex vl, axis c at c * nvs + vl), so
   // that the FP64 atomics of a wave, which touch runs of nearby vertices, spread over the banks;
@@ -462,7 +501,7 @@ struct BodySolver {
       }
     }
     double t[4] = {sd, sa, st, gg};
-    wg_sum<4>(t, red);
+    sum<4>(t);
     out[0] = t[0];
     out[1] = t[1];
     out[2] = t[2];
@@ -484,7 +523,8 @@ struct BodySolver {
       lo = fmin(lo, S.J);
       hi = fmax(hi, S.J);
     }
-    wg_minmax(lo, hi, red);
+    rbank ^= 1;
+    wg_minmax(lo, hi, red + rbank * kRedBank);
   }
 
   // PCG on H(x) xs = sign * rhs (masked to the free DOFs); returns the final r.r. The element
@@ -530,7 +570,7 @@ struct BodySolver {
     }
     {
       double t[2] = {rz, rr};
-      wg_sum<2>(t, red);
+      sum<2>(t);
       rz = t[0];
       rr = t[1];
     }
@@ -539,7 +579,7 @@ struct BodySolver {
     const double tol2 = tol * tol;
     for (int it = 0; it < maxit && rr > tol2; ++it) {
       // the reduction's barriers also complete the scatter into acc
-      const double pHp = wg_sum1(pass_hv() + pvp, red);
+      const double pHp = sum1(pass_hv() + pvp);
       if (!(pHp > 0.0)) {
         // non-positive curvature: stop; on the first iteration keep the preconditioned
         // steepest-descent direction (Nocedal & Wright, Alg. 7.1)
@@ -592,7 +632,7 @@ struct BodySolver {
       }
       {
         double t[2] = {rz1, rr};
-        wg_sum<2>(t, red);
+        sum<2>(t);
         rz1 = t[0];
         rr = t[1];
       }
@@ -654,7 +694,7 @@ struct BodySolver {
       st.negcurv_exits += neg ? 1 : 0;
       double gTd = 0.0;
       for (int i = threadIdx.x; i < n; i += blockDim.x) gTd += G[base + i] * dx[base + i];
-      gTd = wg_sum1(gTd, red);
+      gTd = sum1(gTd);
       if (!(gTd < 0.0)) {
         gTd = 0.0;
         for (int i = threadIdx.x; i < n; i += blockDim.x) {
@@ -662,7 +702,7 @@ struct BodySolver {
           dx[base + i] = d;
           gTd += G[base + i] * d;
         }
-        gTd = wg_sum1(gTd, red);
+        gTd = sum1(gTd);
         if (!(gTd < 0.0)) {
           st.flags |= ISB_FLAG_STAGNATED;
           break;
@@ -730,7 +770,7 @@ struct BodySolver {
       A.G[g] = rhs;
       bb += rhs * rhs;
     }
-    bb = wg_sum1(bb, red);  // its barriers also publish cv
+    bb = sum1(bb);  // its barriers also publish cv
     const double bnorm = sqrt(bb);
     int it = 0;
     bool neg = false;

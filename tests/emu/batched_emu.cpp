@@ -24,6 +24,7 @@ static void run(int block, const isb::DevMesh* m, const isb::DevScene* sc, const
   wg.all = &all;
   wg.waves = waves;
   wg.buf.assign(block, 0.0);
+  wg.ibuf.assign(block, 0);
   isb_emu::g_wg = &wg;
   blockDim.x = block;
   gridDim.x = 1;

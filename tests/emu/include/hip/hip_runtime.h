@@ -34,6 +34,7 @@ struct Workgroup {
   std::barrier<>* all = nullptr;
   std::vector<std::barrier<>*> waves;
   std::vector<double> buf;
+  std::vector<int> ibuf;
   std::mutex mu;
 };
 extern Workgroup* g_wg;
@@ -48,6 +49,46 @@ inline double __shfl_down(double v, int o, int width) {
   wg->buf[t] = v;
   wg->waves[wave]->arrive_and_wait();
   const double r = (lane + (unsigned)o < 64u) ? wg->buf[wave * 64 + lane + o] : v;
+  wg->waves[wave]->arrive_and_wait();
+  return r;
+}
+
+// DPP move within a wave of 64 (all lanes active): quad_perm (ctrl <= 0xFF), row_ror:n
+// (0x121..0x12F, lane i of a row takes lane i - n of the row), row_bcast:15 (0x142, the last lane
+// of the previous row) and row_bcast:31 (0x143, lane 31); lanes in rows outside row_mask keep old
+inline int __builtin_amdgcn_update_dpp(int old, int src, int ctrl, int row_mask, int bank_mask, bool bound_ctrl) {
+  (void)bank_mask;
+  (void)bound_ctrl;
+  const unsigned t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  auto* wg = isb_emu::g_wg;
+  wg->ibuf[t] = src;
+  wg->waves[wave]->arrive_and_wait();
+  int r = old;
+  const unsigned row = lane >> 4;
+  if ((row_mask >> row) & 1) {
+    unsigned sl;
+    if (ctrl <= 0xFF)
+      sl = (lane & ~3u) | ((unsigned)(ctrl >> (2 * (lane & 3))) & 3u);
+    else if (ctrl >= 0x121 && ctrl <= 0x12F)
+      sl = (lane & ~15u) | ((lane - (unsigned)(ctrl - 0x120)) & 15u);
+    else if (ctrl == 0x142)
+      sl = row * 16 - 1;
+    else if (ctrl == 0x143)
+      sl = 31;
+    else
+      sl = lane;  // not used by the solver
+    r = wg->ibuf[wave * 64 + sl];
+  }
+  wg->waves[wave]->arrive_and_wait();
+  return r;
+}
+
+inline int __builtin_amdgcn_readlane(int v, int l) {
+  const unsigned t = threadIdx.x, wave = t >> 6;
+  auto* wg = isb_emu::g_wg;
+  wg->ibuf[t] = v;
+  wg->waves[wave]->arrive_and_wait();
+  const int r = wg->ibuf[wave * 64 + l];
   wg->waves[wave]->arrive_and_wait();
   return r;
 }
