@@ -28,7 +28,36 @@ for _v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
 import numpy as np  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+HERE = os.path.dirname(os.path.abspath(__file__))
+TRAFFIC_PROFILE = os.path.join(HERE, "profiles", "batched_strips_512_hbm_counters.md")
 METRIC = "Newton-CG steps/sec fwd+adjoint, batched FP32/64 vs plain FP64, 1e-6 residual"
+
+
+def kernel_source_hash():
+    """sha256 over the library's sources (name and contents, sorted): the measured-traffic figure in
+    profiles/ applies only while this matches the hash recorded with it."""
+    import hashlib
+    h = hashlib.sha256()
+    src = os.path.join(HERE, "paper_2102_05791_amd", "csrc")
+    files = sorted(f for f in os.listdir(src) if f.endswith((".hpp", ".hip", ".cpp")))
+    for name, path in [(f, os.path.join(src, f)) for f in files] + [("isb.h", os.path.join(HERE, "include", "isb.h"))]:
+        h.update(name.encode() + b"\0")
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel_mode):
+    """HBM bytes per launch of the batched kernel (mode 0 step, 1 adjoint) from the committed
+    FETCH_SIZE / WRITE_SIZE summary, or None when the sources changed since it was taken."""
+    try:
+        with open(TRAFFIC_PROFILE) as fh:
+            rec = next(json.loads(l.split("traffic-record:", 1)[1]) for l in fh if "traffic-record:" in l)
+    except (OSError, StopIteration, ValueError):
+        return None
+    if rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch", {}).get(str(kernel_mode))
 
 
 def parse():
@@ -40,8 +69,8 @@ def parse():
     ap.add_argument("--rollout", type=int, default=50, help="time steps per BPTT pass")
     ap.add_argument("--plain-bodies", type=int, default=32, help="stratified subset for the plain FP64 path")
     ap.add_argument("--plain-steps", type=int, default=2)
-    ap.add_argument("--cpu-bodies", type=int, default=6)
-    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--cpu-bodies", type=int, default=32, help="stratified subset for the CPU oracle leg")
+    ap.add_argument("--cpu-steps", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--block", type=int, default=0, help="batched workgroup size (0 = library default)")
@@ -211,7 +240,8 @@ def main():
     dom_bytes = float(np.mean(fb if dominant == "step" else ab))
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(0 if dominant == "step" else 1),
                 "kernel": f"k_batched<2,float,{0 if dominant == 'step' else 1}> ({dominant} launch)",
                 "launch_ms": round(dom_ms, 4), "algorithmic_bytes_per_launch": int(dom_bytes),
                 "step_launch_ms": round(step_ms, 4), "adjoint_launch_ms": round(adj_ms, 4)}
@@ -285,10 +315,13 @@ def main():
     if not args.no_cpu:
         from oracle import solve as osolve
         from oracle.fem import Problem
+        # the same stratified pick as the plain leg: bodies evenly spaced in size order
+        by_size = np.argsort(np.diff(w.body_e_off), kind="stable")
+        cpick = by_size[np.linspace(0, nb - 1, min(args.cpu_bodies, nb)).round().astype(int)]
         tc = time.perf_counter()
         n_done = 0
-        for b in range(args.cpu_bodies):
-            wb = w.body(b)
+        for b in cpick:
+            wb = w.body(int(b))
             wb.scene.update(tol_rel=1e-6)
             p = Problem.from_workload(wb)
             states, _ = osolve.rollout(p, wb.x0, wb.v0, wb.actions[:args.cpu_steps], tol=1e-6)
@@ -298,8 +331,9 @@ def main():
                   flush=True)
         tcpu = time.perf_counter() - tc
         cpu = {"value": round(n_done / tcpu, 3), "unit": "body-steps/s", "cores": 1, "kind": "oracle",
-               "sample": f"bodies 0..{args.cpu_bodies - 1} of the batch x {args.cpu_steps} steps, forward "
-                         f"Newton (SuperLU) to 1e-6 + adjoint + VJP, {tcpu:.1f} s",
+               "sample": f"{len(cpick)} bodies stratified by size (evenly spaced in size order) x "
+                         f"{args.cpu_steps} steps, forward Newton (SuperLU) to 1e-6 + adjoint + VJP, "
+                         f"{tcpu:.1f} s",
                "host_cpus": os.cpu_count()}
 
     tet = None if args.no_tet else tet_leg(args, torch, Context, isb, scenes)
