@@ -336,8 +336,15 @@ def main():
                          f"{tcpu:.1f} s",
                "host_cpus": os.cpu_count()}
 
+    ceiling = copy_ceiling(torch, isb)
+    roofline["copy_ceiling"] = ceiling
+    roofline["frac_of_copy_ceiling"] = round(roofline["achieved"] / ceiling["GBs"], 4)
+    print("# copy ceiling done", file=sys.stderr, flush=True)
     tet = None if args.no_tet else tet_leg(args, torch, Context, isb, scenes)
     elem = None if args.no_elem_roofline else element_roofline_leg(args, torch, Context, isb, scenes)
+    if elem:
+        for prec in ("fp64", "mixed"):
+            elem[prec]["frac_of_copy_ceiling"] = round(elem[prec]["achieved_GBs"] / ceiling["GBs"], 4)
 
     line = {"metric": METRIC, "value": round(value, 1), "unit": "body-steps/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
@@ -352,6 +359,30 @@ def main():
             "iterations": it, "plain_fp64": plain, "parity": parity, "roofline": roofline,
             "cpu_baseline": cpu, "tet_block": tet, "element_roofline": elem}
     print(json.dumps(line))
+
+
+def copy_ceiling(torch, isb):
+    """HBM ceiling measured with the library's streaming copy kernel: 2 GiB copied, median of 10."""
+    n = 1 << 28
+    src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        isb.stream_copy(src, dst)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(10):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        isb.stream_copy(src, dst)
+        e1.record()
+        ts.append((e0, e1))
+    torch.cuda.synchronize()
+    ms = float(np.median([a.elapsed_time(b) for a, b in ts]))
+    gbs = 2 * 8 * n / (ms * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"kernel": "isb_stream_copy", "bytes_moved": 2 * 8 * n, "ms": round(ms, 4), "GBs": round(gbs, 1),
+            "frac_of_8TBs": round(gbs / HBM_PEAK_GBS, 4)}
 
 
 def tet_leg(args, torch, Context, isb, scenes):

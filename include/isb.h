@@ -222,6 +222,15 @@ isb_status isb_hessvec_elements(isb_ctx* ctx, isb_stream stream, const double* x
 isb_status isb_hessdiag(isb_ctx* ctx, isb_stream stream, const double* x, const double* x0,
                         const double* a, double* diag);
 
+/* ---- bandwidth probe ------------------------------------------------------------------------ */
+
+/* dst[i] = src[i] for i < n by a plain streaming copy kernel (16-byte loads and stores, enough
+ * workgroups to fill every CU), enqueued on `stream` on the current device: timed around a large n,
+ * it gives the HBM ceiling the element and solver kernels are compared with. Device buffers of n
+ * doubles owned by the caller, 16-byte aligned, not overlapping; n >= 0 (n == 0 does nothing).
+ * Returns ISB_E_ARG for NULL or misaligned pointers or negative n. Needs no context. */
+isb_status isb_stream_copy(isb_stream stream, const double* src, double* dst, int64_t n);
+
 #ifdef __cplusplus
 }
 #endif

@@ -579,7 +579,7 @@ isb_status isb_mesh_upload(isb_ctx* c, int dim, int32_t n_bodies, const int64_t*
   Patches pt;
   {
     const int per_vertex = 3 * dim * (int)sizeof(double);  // x, p and the accumulator, FP64
-    ISB_TRY(build_patches(dim, n_v, n_bodies, body_e_off, T, 2048, kPatchLdsBytes / per_vertex, &pt));
+    ISB_TRY(build_patches(dim, n_v, n_bodies, body_e_off, T, 1024, kPatchLdsBytes / per_vertex, &pt));
     c->n_patches = (int)pt.eoff.size() - 1;
     c->body_patch_off.assign(n_bodies + 1, 0);
     int k = 0;
@@ -870,6 +870,19 @@ isb_status isb_hessdiag(isb_ctx* c, isb_stream stream, const double* x, const do
   launch_vertex_hdiag(m, dsc, 0, c->n_v, x, c->w_cv, diag, s);
   elem_scatter(c, -1, PATCH_DIAG, x, a, nullptr, diag, nullptr, s);
   launch_set_pinned(m, 0, c->n_v, 1.0, diag, s);
+  ISB_HIP(hipGetLastError());
+  return ISB_OK;
+}
+
+isb_status isb_stream_copy(isb_stream stream, const double* src, double* dst, int64_t n) {
+  clear_error();
+  if (n < 0 || (n > 0 && (!src || !dst))) return fail(ISB_E_ARG, "isb_stream_copy: bad argument");
+  if (((uintptr_t)src | (uintptr_t)dst) & 15) return fail(ISB_E_ARG, "isb_stream_copy: buffers must be 16-byte aligned");
+  if (n > 0 && src < dst + n && dst < src + n) return fail(ISB_E_ARG, "isb_stream_copy: buffers overlap");
+  int dev = 0, n_cu = 0;
+  ISB_HIP(hipGetDevice(&dev));
+  ISB_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+  launch_stream_copy(n, n_cu, src, dst, (hipStream_t)stream);
   ISB_HIP(hipGetLastError());
   return ISB_OK;
 }

@@ -55,7 +55,7 @@ struct PatchPlan {
   int max_nv;             // largest vertex list
 };
 
-constexpr int kPatchBlock = 512;        // threads per patch workgroup
+constexpr int kPatchBlock = 512;        // threads per patch workgroup (FP32 element math; FP64 takes half)
 constexpr int kPatchLdsBytes = 64 * 1024;  // LDS per patch workgroup (two workgroups per CU)
 
 enum PatchOp { PATCH_GRAD = 0, PATCH_HV = 1, PATCH_DIAG = 2 };
@@ -129,6 +129,7 @@ void launch_finalize(const double* partials, int nblocks, int ncomp, double* out
 void launch_finalize_minmax(const double* partials, int nblocks, double* out, hipStream_t s);
 void launch_axpy(int n, double* x, double alpha, const double* dx, hipStream_t s);
 void launch_copy(int n, const double* src, double* dst, hipStream_t s);
+void launch_stream_copy(int64_t n, int n_cu, const double* src, double* dst, hipStream_t s);
 
 // CG on H xs = sign * b (b is masked to the free DOFs, where D^-1 != 0)
 void launch_cg_start(int n, const double* b, double sign, const double* Dinvp, const double* vdiag, double* r,

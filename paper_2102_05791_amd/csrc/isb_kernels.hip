@@ -806,6 +806,35 @@ void launch_axpy(int n, double* x, double alpha, const double* dx, hipStream_t s
   if (n <= 0) return;
   k_axpy<<<grid_for(n), kBlock, 0, s>>>(n, x, alpha, dx);
 }
+// Streaming copy for the bandwidth probe: each thread moves 4 x 16 bytes per trip, all four loads
+// issued before the stores, over a grid that fills the device several times.
+__global__ void __launch_bounds__(256) k_stream_copy(int64_t n2, const double2* __restrict__ src,
+                                                     double2* __restrict__ dst) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + 3 * stride < n2; i += 4 * stride) {
+    const double2 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+    dst[i] = a;
+    dst[i + stride] = b;
+    dst[i + 2 * stride] = c;
+    dst[i + 3 * stride] = d;
+  }
+  for (; i < n2; i += stride) dst[i] = src[i];
+}
+
+__global__ void k_copy_tail(const double* src, double* dst) { dst[0] = src[0]; }
+
+void launch_stream_copy(int64_t n, int n_cu, const double* src, double* dst, hipStream_t s) {
+  if (n <= 0) return;
+  const int64_t n2 = n / 2;
+  if (n2 > 0) {
+    const int64_t want = (n2 + 255) / 256;
+    const int grid = (int)std::min<int64_t>(want, (int64_t)n_cu * 16);
+    k_stream_copy<<<grid, 256, 0, s>>>(n2, reinterpret_cast<const double2*>(src), reinterpret_cast<double2*>(dst));
+  }
+  if (n & 1) k_copy_tail<<<1, 1, 0, s>>>(src + n - 1, dst + n - 1);
+}
+
 void launch_copy(int n, const double* src, double* dst, hipStream_t s) {
   if (n <= 0) return;
   k_copy<<<grid_for(n), kBlock, 0, s>>>(n, src, dst);
@@ -899,8 +928,8 @@ void launch_min_count(int n, const double* a, double* partials, double* out, hip
 // vertices in LDS, evaluate the elements with LDS gathers and accumulate with LDS atomics, then
 // add each distinct vertex DOF to the global output once. Global atomics drop from d(d+1) per
 // element to the patch's distinct DOFs, and they no longer collide inside a wavefront.
-template <int D, typename T, int OP>
-__global__ void __launch_bounds__(kPatchBlock) k_elem_patch(DevMesh m, DevScene sc, PatchPlan P, int p0, int p1,
+template <int D, typename T, int OP, int PB>
+__global__ void __launch_bounds__(PB) k_elem_patch(DevMesh m, DevScene sc, PatchPlan P, int p0, int p1,
                                                             const double* __restrict__ x,
                                                             const double* __restrict__ a,
                                                             const float* __restrict__ a32,
@@ -974,7 +1003,10 @@ static void patch_launch(const DevMesh& m, const DevScene& sc, const PatchPlan& 
   const size_t lds = (size_t)P.max_nv * D * sizeof(double) * (OP == PATCH_HV ? 3 : 2);
   int grid = p1 - p0;
   if (grid > 65535) grid = 65535;
-  k_elem_patch<D, T, OP><<<grid, kPatchBlock, lds, s>>>(m, sc, P, p0, p1, x, a, a32, p, out, done);
+  // FP64 element math needs about twice the registers of FP32: 256-thread workgroups keep more of
+  // them resident per CU than 512-thread ones would
+  constexpr int PB = std::is_same<T, float>::value ? kPatchBlock : kPatchBlock / 2;
+  k_elem_patch<D, T, OP, PB><<<grid, PB, lds, s>>>(m, sc, P, p0, p1, x, a, a32, p, out, done);
 }
 
 void launch_elem_patch(const DevMesh& m, const DevScene& sc, const PatchPlan& P, int p0, int p1, int op,

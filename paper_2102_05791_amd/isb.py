@@ -28,7 +28,7 @@ EXPORTED = ("isb_create", "isb_destroy", "isb_last_error", "isb_version", "isb_v
             "isb_colour_elements", "isb_mesh_upload", "isb_material_upload", "isb_set_scene",
             "isb_set_option", "isb_get_option", "isb_get_mass", "isb_step", "isb_solve_adjoint",
             "isb_vjp_params", "isb_energy", "isb_gradient", "isb_hessvec", "isb_hessvec_elements",
-            "isb_hessdiag")
+            "isb_hessdiag", "isb_stream_copy")
 
 
 class IsbError(RuntimeError):
@@ -104,6 +104,7 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
         "isb_hessvec": [vp, vp, vp, vp, vp, vp, vp],
         "isb_hessvec_elements": [vp, vp, vp, vp, vp, vp],
         "isb_hessdiag": [vp, vp, vp, vp, vp, vp],
+        "isb_stream_copy": [vp, vp, vp, i64],
     }
     for name, argtypes in sigs.items():
         f = getattr(lib, name)
@@ -164,6 +165,15 @@ def _dev(t, name="tensor"):
 def _stream():
     import torch
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def stream_copy(src, dst):
+    """isb_stream_copy: dst[:] = src[:] by the library's streaming copy kernel (bandwidth probe)."""
+    lib = load_library()
+    if src.numel() != dst.numel():
+        raise ValueError("stream_copy: sizes differ")
+    _check(lib, lib.isb_stream_copy(_stream(), _dev(src, "src"), _dev(dst, "dst"), src.numel()))
+    return dst
 
 
 class Context:

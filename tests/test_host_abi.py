@@ -108,3 +108,17 @@ def test_library_missing_raises(tmp_path):
     isb, _ = _lib()
     with pytest.raises(ImportError):
         isb.load_library(str(tmp_path / "nope.so"))
+
+
+def test_stream_copy_rejects_bad_arguments_before_any_gpu_call():
+    """isb_stream_copy checks its arguments on the host: negative n, NULL or misaligned buffers and
+    overlapping ranges fail with ISB_E_ARG without touching a device (pointer values only)."""
+    import ctypes
+    isb, _ = _lib()
+    lib = isb.load_library()
+    vp = ctypes.c_void_p
+    cases = [(vp(4096), vp(8192), -1), (None, vp(8192), 4), (vp(4096), None, 4),
+             (vp(4104), vp(8192), 4), (vp(4096), vp(4096 + 16), 8)]
+    for src, dst, n in cases:
+        assert lib.isb_stream_copy(None, src, dst, n) == isb.ISB_E_ARG
+        assert lib.isb_last_error()
