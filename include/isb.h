@@ -224,8 +224,8 @@ isb_status isb_hessdiag(isb_ctx* ctx, isb_stream stream, const double* x, const 
 
 /* ---- bandwidth probe ------------------------------------------------------------------------ */
 
-/* dst[i] = src[i] for i < n by a plain streaming copy kernel (16-byte loads and stores, enough
- * workgroups to fill every CU), enqueued on `stream` on the current device: timed around a large n,
+/* dst[i] = src[i] for i < n by a plain streaming copy kernel (one 16-byte load and store per
+ * thread), enqueued on `stream` on the current device: timed around a large n,
  * it gives the HBM ceiling the element and solver kernels are compared with. Device buffers of n
  * doubles owned by the caller, 16-byte aligned, not overlapping; n >= 0 (n == 0 does nothing).
  * Returns ISB_E_ARG for NULL or misaligned pointers or negative n. Needs no context. */

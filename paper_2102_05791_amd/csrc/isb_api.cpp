@@ -879,10 +879,7 @@ isb_status isb_stream_copy(isb_stream stream, const double* src, double* dst, in
   if (n < 0 || (n > 0 && (!src || !dst))) return fail(ISB_E_ARG, "isb_stream_copy: bad argument");
   if (((uintptr_t)src | (uintptr_t)dst) & 15) return fail(ISB_E_ARG, "isb_stream_copy: buffers must be 16-byte aligned");
   if (n > 0 && src < dst + n && dst < src + n) return fail(ISB_E_ARG, "isb_stream_copy: buffers overlap");
-  int dev = 0, n_cu = 0;
-  ISB_HIP(hipGetDevice(&dev));
-  ISB_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
-  launch_stream_copy(n, n_cu, src, dst, (hipStream_t)stream);
+  launch_stream_copy(n, src, dst, (hipStream_t)stream);
   ISB_HIP(hipGetLastError());
   return ISB_OK;
 }

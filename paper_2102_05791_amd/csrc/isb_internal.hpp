@@ -129,7 +129,7 @@ void launch_finalize(const double* partials, int nblocks, int ncomp, double* out
 void launch_finalize_minmax(const double* partials, int nblocks, double* out, hipStream_t s);
 void launch_axpy(int n, double* x, double alpha, const double* dx, hipStream_t s);
 void launch_copy(int n, const double* src, double* dst, hipStream_t s);
-void launch_stream_copy(int64_t n, int n_cu, const double* src, double* dst, hipStream_t s);
+void launch_stream_copy(int64_t n, const double* src, double* dst, hipStream_t s);
 
 // CG on H xs = sign * b (b is masked to the free DOFs, where D^-1 != 0)
 void launch_cg_start(int n, const double* b, double sign, const double* Dinvp, const double* vdiag, double* r,

@@ -806,30 +806,22 @@ void launch_axpy(int n, double* x, double alpha, const double* dx, hipStream_t s
   if (n <= 0) return;
   k_axpy<<<grid_for(n), kBlock, 0, s>>>(n, x, alpha, dx);
 }
-// Streaming copy for the bandwidth probe: each thread moves 4 x 16 bytes per trip, all four loads
-// issued before the stores, over a grid that fills the device several times.
+// Streaming copy for the bandwidth probe: one 16-byte element per thread over as many workgroups as
+// the data needs (up to 2^30, then each thread takes further elements a grid apart). On gfx950 this
+// short-lived-workgroup form streams faster than a persistent grid-stride loop.
 __global__ void __launch_bounds__(256) k_stream_copy(int64_t n2, const double2* __restrict__ src,
                                                      double2* __restrict__ dst) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  for (; i + 3 * stride < n2; i += 4 * stride) {
-    const double2 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
-    dst[i] = a;
-    dst[i + stride] = b;
-    dst[i + 2 * stride] = c;
-    dst[i + 3 * stride] = d;
-  }
-  for (; i < n2; i += stride) dst[i] = src[i];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += stride) dst[i] = src[i];
 }
 
 __global__ void k_copy_tail(const double* src, double* dst) { dst[0] = src[0]; }
 
-void launch_stream_copy(int64_t n, int n_cu, const double* src, double* dst, hipStream_t s) {
+void launch_stream_copy(int64_t n, const double* src, double* dst, hipStream_t s) {
   if (n <= 0) return;
   const int64_t n2 = n / 2;
   if (n2 > 0) {
-    const int64_t want = (n2 + 255) / 256;
-    const int grid = (int)std::min<int64_t>(want, (int64_t)n_cu * 16);
+    const int grid = (int)std::min<int64_t>((n2 + 255) / 256, (int64_t)1 << 30);
     k_stream_copy<<<grid, 256, 0, s>>>(n2, reinterpret_cast<const double2*>(src), reinterpret_cast<double2*>(dst));
   }
   if (n & 1) k_copy_tail<<<1, 1, 0, s>>>(src + n - 1, dst + n - 1);
