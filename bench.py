@@ -76,6 +76,7 @@ def parse():
     ap.add_argument("--block", type=int, default=0, help="batched workgroup size (0 = library default)")
     ap.add_argument("--profile", action="store_true", help="one untimed pass only (for rocprofv3)")
     ap.add_argument("--no-tet", action="store_true", help="skip the 3D tet-block leg")
+    ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay leg")
     ap.add_argument("--tet-steps", type=int, default=20)
     ap.add_argument("--no-elem-roofline", action="store_true", help="skip the size-R element roofline leg")
     ap.add_argument("--elem-grid", type=str, default="192x128x64", help="Kuhn-tet grid of the size-R leg")
@@ -340,6 +341,28 @@ def main():
     roofline["copy_ceiling"] = ceiling
     roofline["frac_of_copy_ceiling"] = round(roofline["achieved"] / ceiling["GBs"], 4)
     print("# copy ceiling done", file=sys.stderr, flush=True)
+    # the same BPTT pass captured once as a HIP graph (graph-safe mode, no statistics) and replayed
+    graph = None
+    if not args.no_graph:
+        g = torch.cuda.CUDAGraph()
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g):
+            gxs, ga_bar, _, _ = bptt()
+        g.replay()
+        torch.cuda.synchronize()
+        tg = time.perf_counter()
+        for _ in range(args.steps):
+            g.replay()
+        torch.cuda.synchronize()
+        tgw = time.perf_counter() - tg
+        gdiff = float((ga_bar - a_bar).abs().max() / a_bar.abs().max())
+        graph = {"value": round(nb * T * args.steps / tgw, 1), "unit": "body-steps/s",
+                 "ms_per_step": round(1e3 * tgw / args.steps, 3), "replays": args.steps,
+                 "a_bar_max_rel_diff_vs_eager": gdiff,
+                 "note": "whole BPTT pass (50 step launches, 50 adjoint launches, VJPs) captured once and replayed"}
+        del g
+        print("# graph replay leg done", file=sys.stderr, flush=True)
+
     tet = None if args.no_tet else tet_leg(args, torch, Context, isb, scenes)
     elem = None if args.no_elem_roofline else element_roofline_leg(args, torch, Context, isb, scenes)
     if elem:
@@ -357,7 +380,7 @@ def main():
                        "tol_rel": w.scene["tol_rel"], "adj_tol_rel": w.scene["adj_tol_rel"],
                        "block": ctx.get_option(isb.OPT_BLOCK)},
             "iterations": it, "plain_fp64": plain, "parity": parity, "roofline": roofline,
-            "cpu_baseline": cpu, "tet_block": tet, "element_roofline": elem}
+            "cpu_baseline": cpu, "graph_replay": graph, "tet_block": tet, "element_roofline": elem}
     print(json.dumps(line))
 
 

@@ -1,0 +1,65 @@
+"""The batched solver under HIP graph capture: a forward step and its adjoint solve, captured once
+in graph-safe mode, replayed several times with the program's own eager work and synchronisations
+between the replays; every replay must match the eager calls on the same inputs, including
+replays whose inputs were overwritten in place (the pattern of a captured BPTT step)."""
+import numpy as np
+import pytest
+
+from tests.gpu_util import rand_workload, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda:0")
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("mixed", 1e-6)])
+def test_batched_step_and_adjoint_replay_from_graph(precision, tol):
+    import torch
+    from paper_2102_05791_amd import Context, isb
+    w, rng = rand_workload(2, seed=31, bodies=4, shape=(8, 3))
+    # tight stops, so that a different order of LDS atomic additions cannot move a stopping decision
+    # by more than the comparison tolerance
+    w.scene.update(tol_rel=1e-12, adj_tol_rel=1e-12, max_newton=60, max_cg=4000)
+    ctx = Context.from_workload(w, precision=precision, solver=1)
+    ctx.set_option(isb.OPT_GRAPH_SAFE, 1)
+    inputs = []
+    for k in range(3):
+        x0 = w.x0 + (0.0 if k == 0 else 1e-3 * rng.normal(size=w.x0.shape))
+        x0[w.pinned.astype(bool)] = w.x0[w.pinned.astype(bool)]
+        inputs.append((x0, w.v0 + 0.1 * k, w.actions[k], rng.normal(size=w.x0.shape), rng.normal(size=w.x0.shape)))
+
+    def eager(x0, v0, a, xb, vb):
+        x1, v1, _, _ = ctx.step(_dev(x0), _dev(v0), _dev(a), stats=False)
+        wv, _, _ = ctx.solve_adjoint(x1, _dev(x0), _dev(a), _dev(xb), _dev(vb), stats=False)
+        torch.cuda.synchronize()
+        return x1.cpu().numpy(), v1.cpu().numpy(), wv.cpu().numpy()
+
+    ref = [eager(*inp) for inp in inputs]  # also prepares the batched state before the capture
+
+    # static buffers of the captured step and adjoint
+    sx0, sv0, sa, sxb, svb = (_dev(v) for v in inputs[0])
+    sx1, sv1, sw = torch.empty_like(sx0), torch.empty_like(sx0), torch.empty_like(sx0)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        ctx.step(sx0, sv0, sa, x1=sx1, v1=sv1, stats=False)
+        ctx.solve_adjoint(sx1, sx0, sa, sxb, svb, w=sw, stats=False)
+
+    order = [0, 1, 2, 0, 2]
+    for k in order:
+        x0, v0, a, xb, vb = inputs[k]
+        for dst, src in ((sx0, x0), (sv0, v0), (sa, a), (sxb, xb), (svb, vb)):
+            dst.copy_(_dev(src))
+        g.replay()
+        torch.cuda.synchronize()
+        x1, v1, wv = sx1.cpu().numpy(), sv1.cpu().numpy(), sw.cpu().numpy()
+        rx, rv, rw = ref[k]
+        # same arithmetic as the eager call; only the order of LDS atomic additions may differ
+        assert rel(x1 - x0, rx - x0) <= tol
+        assert rel(v1, rv) <= tol
+        assert rel(wv, rw) <= tol
+        # eager work of the program between replays
+        eager(*inputs[(k + 1) % 3])
