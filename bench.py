@@ -98,24 +98,27 @@ def hv_state_bytes(dim, word):
 
 
 def hv_elem_bytes(dim, word):
-    """Element bytes of one Hessian-vector pass: conn + the stored state (triangles), or conn +
-    rest data + actuation + the stored F, F d (tetrahedra)."""
+    """Element bytes of one batched Hessian-vector pass: 16-bit body-local connectivity + the
+    stored state (triangles), or + rest data + actuation + the stored F, F d (tetrahedra)."""
     if dim == 2:
-        return 4 * (dim + 1) + hv_state_bytes(dim, word)
-    return elem_bytes(dim, word) + hv_state_bytes(dim, word)
+        return 2 * (dim + 1) + hv_state_bytes(dim, word)
+    return elem_bytes(dim, word) - 2 * (dim + 1) + hv_state_bytes(dim, word)
 
 
 def cg_iter_bytes(dim, ne, nv, word_hv):
     """One batched CG iteration: the Hessian-vector element pass (p is in LDS), and the x/r update
-    pass (xs, r read and written, D^-1 and vdiag read); the direction pass touches LDS only."""
-    return hv_elem_bytes(dim, word_hv) * ne + 48 * nv * dim
+    pass (xs, r read and written, the FP32 preconditioner and the vertex diagonal in the element
+    precision read); the direction pass touches LDS only."""
+    return hv_elem_bytes(dim, word_hv) * ne + (32 + 4 + word_hv) * nv * dim
 
 
 def trial_bytes(dim, ne, nv, word_hv):
-    """One fused line-search trial: FP64 rest data, E(x) read, E(x_t) written, the Hessian-vector
-    state stored per element; x, dx, x0, xhat, pinned read and G, vdiag, D^-1 written per DOF;
+    """One fused line-search trial: 16-bit connectivity, FP64 rest data and actuation, E(x) read,
+    E(x_t) written, the Hessian-vector state stored per element; x, dx, x0, xhat, pinned read and G
+    (FP64), the vertex diagonal (element precision) and the FP32 preconditioner written per DOF;
     mass and c_v per vertex."""
-    return (elem_bytes(dim, 8) + 16 + hv_state_bytes(dim, word_hv)) * ne + 57 * nv * dim + 16 * nv
+    return ((elem_bytes(dim, 8) - 2 * (dim + 1) + 16 + hv_state_bytes(dim, word_hv)) * ne
+            + (41 + 8 + 4 + word_hv) * nv * dim + 16 * nv)
 
 
 def step_launch_bytes(dim, ne, nv, st, word_hv):
@@ -123,7 +126,7 @@ def step_launch_bytes(dim, ne, nv, st, word_hv):
     dof = nv * dim
     trials = 1 + st["newton_iters"] + st["ls_backtracks"]
     setup = 57 * dof + 16 * nv                 # x0, v0, pinned -> xhat, x; c_v; v1 at the end
-    per_newton = 40 * dof + 16 * dof + 24 * dof  # CG start; g.dx; x += alpha dx
+    per_newton = (8 + 4 + word_hv + 24) * dof + 16 * dof + 24 * dof  # CG start; g.dx; x += alpha dx
     return (setup + trials * trial_bytes(dim, ne, nv, word_hv) - 8 * ne
             + st["newton_iters"] * per_newton + st["cg_iters"] * cg_iter_bytes(dim, ne, nv, word_hv))
 
@@ -133,8 +136,8 @@ def adjoint_launch_bytes(dim, ne, nv, st, word_hv):
     Hessian-vector state, the CG start and the CG iterations."""
     dof = nv * dim
     rhs = 25 * dof + 16 * nv
-    diag = (elem_bytes(dim, 8) + hv_state_bytes(dim, word_hv)) * ne + 25 * dof + 16 * nv
-    return rhs + diag + 40 * dof + st["adj_cg_iters"] * cg_iter_bytes(dim, ne, nv, word_hv)
+    diag = (elem_bytes(dim, 8) - 2 * (dim + 1) + hv_state_bytes(dim, word_hv)) * ne + (9 + 4 + word_hv) * dof + 16 * nv
+    return rhs + diag + (36 + 4 + word_hv) * dof + st["adj_cg_iters"] * cg_iter_bytes(dim, ne, nv, word_hv)
 
 
 def main():

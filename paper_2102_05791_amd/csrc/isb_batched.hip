@@ -36,6 +36,9 @@ struct BatchedState {
   DevStats* hstats = nullptr;  // pinned host mirror
   void* Fbuf = nullptr;        // per-element Hessian-vector state in the element precision
   double *E0 = nullptr, *E1 = nullptr;  // per-element energies (iterate, trial)
+  float* Dv = nullptr;                  // FP32 Jacobi preconditioner
+  void* vdT = nullptr;                  // vertex-term diagonal, element precision
+  uint16_t* lconn = nullptr;            // body-local connectivity
   int nacc = 0, grid = 0, block = 0, precision = -1, dim = 0;
   size_t lds = 0;
 };
@@ -167,6 +170,25 @@ isb_status batched_prepare(isb_ctx* c) {
   if ((r = alloc(&st->Fbuf, fwords * (c->precision == ISB_MIXED ? 4 : 8))) != ISB_OK) return r;
   if ((r = alloc((void**)&st->E0, (size_t)c->n_e * sizeof(double))) != ISB_OK) return r;
   if ((r = alloc((void**)&st->E1, (size_t)c->n_e * sizeof(double))) != ISB_OK) return r;
+  const size_t ndof = (size_t)c->n_v * c->dim;
+  if ((r = alloc((void**)&st->Dv, ndof * sizeof(float))) != ISB_OK) return r;
+  if ((r = alloc(&st->vdT, ndof * (c->precision == ISB_MIXED ? 4 : 8))) != ISB_OK) return r;
+  // 16-bit body-local connectivity: every body passed the LDS check, so it has fewer than 65536
+  // vertices (2 x 8 bytes of LDS per DOF)
+  {
+    const size_t nk = (size_t)(c->dim + 1) * (size_t)c->n_e;
+    std::vector<int32_t> conn(nk);
+    ISB_HIP(hipMemcpy(conn.data(), c->conn, nk * sizeof(int32_t), hipMemcpyDeviceToHost));
+    std::vector<uint16_t> loc(nk);
+    for (int b = 0; b < nb; ++b) {
+      if (voff[b + 1] - voff[b] > 65536) return fail(ISB_E_ARG, "batched solver: body with more than 65536 vertices");
+      for (int k = 0; k <= c->dim; ++k)
+        for (int64_t e = eoff[b]; e < eoff[b + 1]; ++e)
+          loc[(size_t)k * c->n_e + e] = (uint16_t)(conn[(size_t)k * c->n_e + e] - voff[b]);
+    }
+    if ((r = alloc((void**)&st->lconn, nk * sizeof(uint16_t))) != ISB_OK) return r;
+    ISB_HIP(hipMemcpy(st->lconn, loc.data(), nk * sizeof(uint16_t), hipMemcpyHostToDevice));
+  }
   ISB_HIP(hipHostMalloc((void**)&st->hstats, nb * sizeof(DevStats), hipHostMallocDefault));
   ISB_HIP(hipMemcpy(st->order, order.data(), nb * 4, hipMemcpyHostToDevice));
   ISB_HIP(hipMemcpy(st->wg_off, wg_off.data(), (st->grid + 1) * 4, hipMemcpyHostToDevice));
@@ -190,8 +212,9 @@ static BatchArgs make_args(isb_ctx* c, BatchedState* st) {
   A.Gt = c->w_Gt;
   A.dx = c->w_xs;
   A.r = c->w_r;
-  A.Dinvp = c->w_Dinvp;
-  A.vdiag = c->w_vdiag;
+  A.Dv = st->Dv;
+  A.vdT = st->vdT;
+  A.lconn = st->lconn;
   A.cv = c->w_cv;
   A.stats = st->stats;
   A.tol = c->scene.tol_rel;

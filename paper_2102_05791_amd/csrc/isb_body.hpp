@@ -41,7 +41,10 @@ struct BatchArgs {
   double *x1, *v1;               // step outputs (x1 is also the Newton iterate)
   const double *xbar, *vbar;     // adjoint right-hand side
   double* w;                     // adjoint output
-  double *xhat, *G, *Gt, *dx, *r, *Dinvp, *vdiag, *cv;  // workspaces
+  double *xhat, *G, *Gt, *dx, *r, *cv;  // workspaces
+  float* Dv;          // [n_v*D] Jacobi preconditioner 1/|diag H| (FP32: it only steers convergence)
+  void* vdT;          // [n_v*D] vertex-term Hessian diagonal in the element precision
+  const uint16_t* lconn;  // [D+1][n_e] body-local vertex ids (a body that fits in LDS has < 65536 vertices)
   DevStats* stats;
   double tol, adj_tol;
   int max_newton, max_cg;
@@ -183,6 +186,19 @@ struct BodySolver {
   __device__ __forceinline__ int ld(int i) const { return lv(i / D, i % D); }  // body DOF i = vl * D + c
 
   __device__ __forceinline__ bool pinned(int i) const { return m.pinned[base + i] != 0; }
+  __device__ __forceinline__ T* vdp() const { return reinterpret_cast<T*>(A.vdT); }
+
+  // the element's vertices (global ids) from the 16-bit body-local connectivity
+  __device__ __forceinline__ void load_lconn(int e, int v[D + 1]) const {
+    const size_t ne = (size_t)m.n_e;
+#pragma unroll
+    for (int k = 0; k <= D; ++k) v[k] = v0 + (int)A.lconn[(size_t)k * ne + e];
+  }
+
+  // preconditioner entry of a free DOF with Hessian diagonal d (1 where d is 0), as stored
+  __device__ __forceinline__ static float precond_entry(double d) {
+    return d > 0.0 ? (float)fmin(1.0 / d, 3.0e38) : 1.0f;
+  }
 
   // -------- element passes: scatter into acc (local DOF index = (v - v0) * D + c) --------
   __device__ __forceinline__ void lds_scatter(const int v[D + 1], const double out[D + 1][D], double scale) {
@@ -211,7 +227,7 @@ struct BodySolver {
     double php = 0.0;
     for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
       int v[D + 1];
-      load_conn<D>(m, e, v);
+      load_lconn(e, v);
       T out[D + 1][D];
       double d64[kQ];  // edge differences of p, q = j * D + r
       if constexpr (kEdgeHessian) {
@@ -349,7 +365,7 @@ struct BodySolver {
   __device__ void pass_diag(const double* x) {
     for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
       int v[D + 1];
-      load_conn<D>(m, e, v);
+      load_lconn(e, v);
       ElemRest<D, double> R64;
       load_rest<D, double>(m, e, R64);
       const double ae = A.a[e];
@@ -393,8 +409,8 @@ struct BodySolver {
       const bool pin = pinned(i);
       const double vd = pin ? 0.0 : vhdiag(c, x[base + i], m.mass[vg], A.cv[vg]);
       const double d = fabs(acc[ld(i)] + vd);
-      A.vdiag[base + i] = vd;
-      A.Dinvp[base + i] = pin ? 0.0 : (d > 0.0 ? 1.0 / d : 1.0);
+      vdp()[base + i] = T(vd);
+      A.Dv[base + i] = pin ? 0.0f : precond_entry(d);
       acc[ld(i)] = 0.0;
     }
     __syncthreads();
@@ -416,7 +432,7 @@ struct BodySolver {
     double sd = 0.0, sa = 0.0, st = 0.0;
     for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
       int v[D + 1];
-      load_conn<D>(m, e, v);
+      load_lconn(e, v);
       ElemRest<D, double> R64;
       load_rest<D, double>(m, e, R64);
       const double ae = A.a[e];
@@ -492,8 +508,8 @@ struct BodySolver {
             const double vd = pin[u][c] ? 0.0 : vhdiag(c, xb[c], mv[u], cvv[u]);
             const double d = fabs(acc2[i] + vd);
             Gout[g] = gi;
-            A.vdiag[g] = vd;
-            A.Dinvp[g] = pin[u][c] ? 0.0 : (d > 0.0 ? 1.0 / d : 1.0);
+            vdp()[g] = T(vd);
+            A.Dv[g] = pin[u][c] ? 0.0f : precond_entry(d);
             acc[i] = 0.0;
             acc2[i] = 0.0;
           }
@@ -513,7 +529,7 @@ struct BodySolver {
     hi = -1e300;
     for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
       int v[D + 1];
-      load_conn<D>(m, e, v);
+      load_lconn(e, v);
       ElemRest<D, double> R;
       load_rest<D, double>(m, e, R);
       double Ds[D][D];
@@ -544,16 +560,16 @@ struct BodySolver {
       const int i = iu < n ? iu : n - 1;
       const int g = base + i;
       x[u] = xs[g];
-      d[u] = A.Dinvp[g];
+      d[u] = A.Dv[g];
       rv[u] = A.r[g];
-      v[u] = A.vdiag[g];
+      v[u] = vdp()[g];
     }
   }
 
   __device__ double cg(const double* rhs, double sign, double tol, int maxit, double* xs, int& iters, bool& neg) {
     double* r = A.r;
-    const double* Dv = A.Dinvp;
-    const double* vd = A.vdiag;
+    const float* Dv = A.Dv;
+    const T* vd = vdp();
     const int B = blockDim.x;
     double rz = 0.0, rr = 0.0, pvp = 0.0;  // pvp: this thread's share of sum vd p^2
     for (int i = threadIdx.x; i < n; i += B) {
@@ -698,7 +714,7 @@ struct BodySolver {
       if (!(gTd < 0.0)) {
         gTd = 0.0;
         for (int i = threadIdx.x; i < n; i += blockDim.x) {
-          const double d = -A.Dinvp[base + i] * G[base + i];
+          const double d = -(double)A.Dv[base + i] * G[base + i];
           dx[base + i] = d;
           gTd += G[base + i] * d;
         }

@@ -37,7 +37,7 @@ class BatchArgs(ctypes.Structure):
     _fields_ = [("order", vp), ("wg_off", vp), ("voff", vp), ("eoff", vp), ("n_bodies", ci),
                 ("x0", vp), ("v0", vp), ("a", vp), ("a32", vp), ("x1", vp), ("v1", vp), ("xbar", vp),
                 ("vbar", vp), ("w", vp), ("xhat", vp), ("G", vp), ("Gt", vp), ("dx", vp), ("r", vp),
-                ("Dinvp", vp), ("vdiag", vp), ("cv", vp), ("stats", vp), ("tol", cd), ("adj_tol", cd),
+                ("cv", vp), ("Dv", vp), ("vdT", vp), ("lconn", vp), ("stats", vp), ("tol", cd), ("adj_tol", cd),
                 ("max_newton", ci), ("max_cg", ci), ("want_tail", ci), ("nacc", ci), ("Fbuf", vp), ("E0", vp), ("E1", vp)]
 
 
@@ -111,7 +111,11 @@ class EmuBatch:
         self.eoff = k(w.body_e_off.astype(np.int32))
         self.nacc = int((np.diff(w.body_v_off) * d).max())
         nd = w.n_v * d
-        self.ws = {n: k(np.zeros(nd)) for n in ("xhat", "G", "Gt", "dx", "r", "Dinvp", "vdiag")}
+        self.ws = {n: k(np.zeros(nd)) for n in ("xhat", "G", "Gt", "dx", "r")}
+        self.Dv = k(np.zeros(nd, dtype=np.float32))  # FP32 preconditioner
+        self.vdT = k(np.zeros(nd, dtype=np.float64))  # element precision (FP32 uses the first half)
+        body = np.repeat(np.arange(nb), ne_b)
+        self.lconn = k((self.conn - w.body_v_off[body][None, :]).astype(np.uint16))
         self.cv = k(np.zeros(w.n_v))
         self.stats = k(np.zeros(nb, dtype=STATS_DTYPE))
         self.Fbuf = k(np.zeros((10 if d == 2 else d * d + d) * w.n_e, dtype=np.float64))  # hv_state_words
@@ -124,9 +128,10 @@ class EmuBatch:
         sc = self.w.scene
         A.order, A.wg_off, A.voff, A.eoff = _p(self.order), _p(self.wg_off), _p(self.voff), _p(self.eoff)
         A.n_bodies = self.w.n_bodies
-        for n in ("xhat", "G", "Gt", "dx", "r", "Dinvp", "vdiag"):
+        for n in ("xhat", "G", "Gt", "dx", "r"):
             setattr(A, n, _p(self.ws[n]))
         A.cv = _p(self.cv)
+        A.Dv, A.vdT, A.lconn = _p(self.Dv), _p(self.vdT), _p(self.lconn)
         A.stats = _p(self.stats)
         A.tol, A.adj_tol = sc["tol_rel"], sc["adj_tol_rel"]
         A.max_newton, A.max_cg = sc["max_newton"], sc["max_cg"]

@@ -64,20 +64,20 @@ def test_emulated_static_assignment_covers_every_body_once(emu_mod):
 def test_emulated_first_preconditioner_ignores_stale_lds(emu_mod, lds_fill):
     """With no Newton iteration allowed, the Jacobi preconditioner left behind is the one of the
     first trial pass: 1/|diag H| at the initial iterate (x0 + h v0, pinned DOFs at x0) on free DOFs,
-    whatever the LDS held when the launch began."""
+    rounded to FP32, whatever the LDS held when the launch began."""
     w, _ = rand_workload(2, seed=23, bodies=2, shape=(6, 3))
     w.scene.update(max_newton=0)
     eb = emu_mod.EmuBatch(w, "mixed")
     a = w.actions[0]
     eb.step(w.x0, w.v0, a, block=64, lds_fill=lds_fill)
-    dinv = eb.ws["Dinvp"].reshape(w.x0.shape)
+    dinv = eb.Dv.astype(np.float64).reshape(w.x0.shape)  # stored in FP32
     for b, p in enumerate(problems(w)):
         sv = slice(w.body_v_off[b], w.body_v_off[b + 1])
         se = slice(w.body_e_off[b], w.body_e_off[b + 1])
         xi = np.where(p.pinned, w.x0[sv], p.x_hat(w.x0[sv], w.v0[sv]))
         d = np.abs(p.hessian(xi, w.x0[sv], a[se]).diagonal())
         ref = np.where(p.free, 1.0 / d, 0.0).reshape(xi.shape)
-        assert rel(dinv[sv], ref) <= 1e-12
+        assert rel(dinv[sv], ref) <= 1e-7
 
 
 @pytest.mark.parametrize("mode", ["step", "adjoint"])
