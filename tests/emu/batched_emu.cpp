@@ -13,6 +13,7 @@
 thread_local isb_emu_dim3 threadIdx;
 isb_emu_dim3 blockDim, blockIdx, gridDim;
 isb_emu::Workgroup* isb_emu::g_wg = nullptr;
+thread_local unsigned isb_emu::wave_phase = 0;
 
 template <int D, typename T, int MODE>
 static void run(int block, const isb::DevMesh* m, const isb::DevScene* sc, const isb::BatchArgs* A, double lds_fill,
@@ -23,8 +24,8 @@ static void run(int block, const isb::DevMesh* m, const isb::DevScene* sc, const
   for (int w = 0; w < block / 64; ++w) waves.push_back(new std::barrier<>(64));
   wg.all = &all;
   wg.waves = waves;
-  wg.buf.assign(block, 0.0);
-  wg.ibuf.assign(block, 0);
+  wg.buf.assign(2 * block, 0.0);
+  wg.ibuf.assign(2 * block, 0);
   isb_emu::g_wg = &wg;
   blockDim.x = block;
   gridDim.x = 1;
@@ -33,6 +34,7 @@ static void run(int block, const isb::DevMesh* m, const isb::DevScene* sc, const
   for (int t = 0; t < block; ++t)
     th.emplace_back([&, t]() {
       threadIdx.x = t;
+      isb_emu::wave_phase = 0;
       isb::batched_body<D, T, MODE>(*m, *sc, *A, smem.data(), 0);
     });
   for (auto& x : th) x.join();

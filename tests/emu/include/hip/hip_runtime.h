@@ -1,7 +1,9 @@
 // CPU stand-in for the few HIP device facilities that the batched solver's body logic uses,
 // so that isb_body.hpp can be compiled with g++ and run by host threads as one workgroup.
 // Test infrastructure only: __syncthreads is a barrier over the workgroup's threads, wavefront
-// shuffles go through a per-wave buffer and barrier, and atomics take a mutex.
+// shuffles and DPP moves go through per-wave buffers and one wave barrier each (two buffers used
+// alternately: a lane can only overwrite a buffer after every lane has passed the barrier of the
+// operation in between, so after every lane has read it), and atomics take a mutex.
 #pragma once
 
 #include <barrier>
@@ -38,6 +40,7 @@ struct Workgroup {
   std::mutex mu;
 };
 extern Workgroup* g_wg;
+extern thread_local unsigned wave_phase;  // wave operations done by this thread (selects the buffer)
 }  // namespace isb_emu
 
 inline void __syncthreads() { isb_emu::g_wg->all->arrive_and_wait(); }
@@ -46,11 +49,10 @@ inline double __shfl_down(double v, int o, int width) {
   (void)width;
   const unsigned t = threadIdx.x, lane = t & 63, wave = t >> 6;
   auto* wg = isb_emu::g_wg;
-  wg->buf[t] = v;
+  double* b = wg->buf.data() + (isb_emu::wave_phase++ & 1) * blockDim.x;
+  b[t] = v;
   wg->waves[wave]->arrive_and_wait();
-  const double r = (lane + (unsigned)o < 64u) ? wg->buf[wave * 64 + lane + o] : v;
-  wg->waves[wave]->arrive_and_wait();
-  return r;
+  return (lane + (unsigned)o < 64u) ? b[wave * 64 + lane + o] : v;
 }
 
 // DPP move within a wave of 64 (all lanes active): quad_perm (ctrl <= 0xFF), row_ror:n
@@ -61,7 +63,8 @@ inline int __builtin_amdgcn_update_dpp(int old, int src, int ctrl, int row_mask,
   (void)bound_ctrl;
   const unsigned t = threadIdx.x, lane = t & 63, wave = t >> 6;
   auto* wg = isb_emu::g_wg;
-  wg->ibuf[t] = src;
+  int* buf = wg->ibuf.data() + (isb_emu::wave_phase++ & 1) * blockDim.x;
+  buf[t] = src;
   wg->waves[wave]->arrive_and_wait();
   int r = old;
   const unsigned row = lane >> 4;
@@ -77,20 +80,18 @@ inline int __builtin_amdgcn_update_dpp(int old, int src, int ctrl, int row_mask,
       sl = 31;
     else
       sl = lane;  // not used by the solver
-    r = wg->ibuf[wave * 64 + sl];
+    r = buf[wave * 64 + sl];
   }
-  wg->waves[wave]->arrive_and_wait();
   return r;
 }
 
 inline int __builtin_amdgcn_readlane(int v, int l) {
   const unsigned t = threadIdx.x, wave = t >> 6;
   auto* wg = isb_emu::g_wg;
-  wg->ibuf[t] = v;
+  int* buf = wg->ibuf.data() + (isb_emu::wave_phase++ & 1) * blockDim.x;
+  buf[t] = v;
   wg->waves[wave]->arrive_and_wait();
-  const int r = wg->ibuf[wave * 64 + l];
-  wg->waves[wave]->arrive_and_wait();
-  return r;
+  return buf[wave * 64 + l];
 }
 
 inline void unsafeAtomicAdd(double* p, double v) {
