@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <thread>
 
 #include "isb_body.hpp"
@@ -68,4 +69,19 @@ extern "C" int emu_sizes(int* out) {
   out[2] = (int)sizeof(isb::BatchArgs);
   out[3] = (int)sizeof(isb::DevStats);
   return 0;
+}
+
+// byte offsets of BatchArgs' fields in declaration order, checked against the ctypes mirror
+extern "C" int emu_batchargs_offsets(int* out) {
+  int k = 0;
+#define ISB_EMU_OFF(f) out[k++] = (int)offsetof(isb::BatchArgs, f)
+  ISB_EMU_OFF(order); ISB_EMU_OFF(wg_off); ISB_EMU_OFF(voff); ISB_EMU_OFF(eoff); ISB_EMU_OFF(n_bodies);
+  ISB_EMU_OFF(x0); ISB_EMU_OFF(v0); ISB_EMU_OFF(a); ISB_EMU_OFF(a32); ISB_EMU_OFF(x1); ISB_EMU_OFF(v1);
+  ISB_EMU_OFF(xbar); ISB_EMU_OFF(vbar); ISB_EMU_OFF(w); ISB_EMU_OFF(xhat); ISB_EMU_OFF(G); ISB_EMU_OFF(Gt);
+  ISB_EMU_OFF(dx); ISB_EMU_OFF(r); ISB_EMU_OFF(cv); ISB_EMU_OFF(xt); ISB_EMU_OFF(Dv); ISB_EMU_OFF(vdT);
+  ISB_EMU_OFF(lconn); ISB_EMU_OFF(stats); ISB_EMU_OFF(tol); ISB_EMU_OFF(adj_tol); ISB_EMU_OFF(max_newton);
+  ISB_EMU_OFF(max_cg); ISB_EMU_OFF(want_tail); ISB_EMU_OFF(nacc); ISB_EMU_OFF(Fbuf); ISB_EMU_OFF(E0);
+  ISB_EMU_OFF(E1);
+#undef ISB_EMU_OFF
+  return k;
 }

@@ -36,8 +36,8 @@ class DevScene(ctypes.Structure):
 class BatchArgs(ctypes.Structure):
     _fields_ = [("order", vp), ("wg_off", vp), ("voff", vp), ("eoff", vp), ("n_bodies", ci),
                 ("x0", vp), ("v0", vp), ("a", vp), ("a32", vp), ("x1", vp), ("v1", vp), ("xbar", vp),
-                ("vbar", vp), ("w", vp), ("xhat", vp), ("G", vp), ("Gt", vp), ("dx", vp), ("r", vp),
-                ("cv", vp), ("Dv", vp), ("vdT", vp), ("lconn", vp), ("stats", vp), ("tol", cd), ("adj_tol", cd),
+                ("vbar", vp), ("w", vp), ("xhat", vp), ("G", vp), ("Gt", vp), ("dx", vp), ("r", vp), ("cv", vp),
+                ("xt", vp), ("Dv", vp), ("vdT", vp), ("lconn", vp), ("stats", vp), ("tol", cd), ("adj_tol", cd),
                 ("max_newton", ci), ("max_cg", ci), ("want_tail", ci), ("nacc", ci), ("Fbuf", vp), ("E0", vp), ("E1", vp)]
 
 
@@ -72,6 +72,9 @@ class EmuBatch:
         sizes = (ci * 4)()
         self.lib.emu_sizes(sizes)
         assert list(sizes) == [ctypes.sizeof(DevMesh), ctypes.sizeof(DevScene), ctypes.sizeof(BatchArgs), 72]
+        offs = (ci * len(BatchArgs._fields_))()
+        assert self.lib.emu_batchargs_offsets(offs) == len(BatchArgs._fields_)
+        assert list(offs) == [getattr(BatchArgs, f).offset for f, _ in BatchArgs._fields_], "BatchArgs layout"
         self.w = w
         d = w.dim
         self.prec = 1 if precision == "mixed" else 0
@@ -111,7 +114,7 @@ class EmuBatch:
         self.eoff = k(w.body_e_off.astype(np.int32))
         self.nacc = int((np.diff(w.body_v_off) * d).max())
         nd = w.n_v * d
-        self.ws = {n: k(np.zeros(nd)) for n in ("xhat", "G", "Gt", "dx", "r")}
+        self.ws = {n: k(np.zeros(nd)) for n in ("xhat", "G", "Gt", "dx", "r", "xt")}
         self.Dv = k(np.zeros(nd, dtype=np.float32))  # FP32 preconditioner
         self.vdT = k(np.zeros(nd, dtype=np.float64))  # element precision (FP32 uses the first half)
         body = np.repeat(np.arange(nb), ne_b)
@@ -128,7 +131,7 @@ class EmuBatch:
         sc = self.w.scene
         A.order, A.wg_off, A.voff, A.eoff = _p(self.order), _p(self.wg_off), _p(self.voff), _p(self.eoff)
         A.n_bodies = self.w.n_bodies
-        for n in ("xhat", "G", "Gt", "dx", "r"):
+        for n in ("xhat", "G", "Gt", "dx", "r", "xt"):
             setattr(A, n, _p(self.ws[n]))
         A.cv = _p(self.cv)
         A.Dv, A.vdT, A.lconn = _p(self.Dv), _p(self.vdT), _p(self.lconn)
