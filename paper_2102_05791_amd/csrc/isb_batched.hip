@@ -210,6 +210,7 @@ static BatchArgs make_args(isb_ctx* c, BatchedState* st) {
   A.xhat = c->w_xhat;
   A.G = c->w_G;
   A.Gt = c->w_Gt;
+  A.xt = c->w_xt;
   A.dx = c->w_xs;
   A.r = c->w_r;
   A.Dv = st->Dv;

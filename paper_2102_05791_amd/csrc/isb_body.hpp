@@ -42,6 +42,7 @@ struct BatchArgs {
   const double *xbar, *vbar;     // adjoint right-hand side
   double* w;                     // adjoint output
   double *xhat, *G, *Gt, *dx, *r, *cv;  // workspaces
+  double* xt;         // [n_v*D] trial point of the line search; swaps with the iterate on acceptance
   float* Dv;          // [n_v*D] Jacobi preconditioner 1/|diag H| (FP32: it only steers convergence)
   void* vdT;          // [n_v*D] vertex-term Hessian diagonal in the element precision
   const uint16_t* lconn;  // [D+1][n_e] body-local vertex ids (a body that fits in LDS has < 65536 vertices)
@@ -420,13 +421,14 @@ struct BodySolver {
   // out = (sum of g_e(xt) - g_e(x) over elements and vertices, sum |g_e(x)|, g(xt), |grad g(xt)|^2)
   // -- the element differences use the stored energies Ecur of x, the new ones go to Enew -- and
   // leaves behind the gradient at xt in Gout, the Jacobi preconditioner and vertex-term diagonal,
-  // and F, F d per element: everything the next Newton iteration needs if the trial is accepted.
+  // the Hessian-vector state per element, and xt itself in xt_out (when given): everything the next
+  // Newton iteration needs if the trial is accepted.
   // Each loop issues every global load of an iteration before its first global store: stores
   // count against the same wait counter as loads, and a load placed after a store waits for it.
   static constexpr int kV = 3;  // vertices per thread per chunk of the vertex loop
 
   __device__ void trial(const double* x, const double* dxp, double alpha, double* Gout, const double* Ecur,
-                        double* Enew, double out[4]) {
+                        double* Enew, double out[4], double* xt_out = nullptr) {
     double* acc2 = ps;  // the CG direction's LDS is free outside CG: it takes the diagonal
     const size_t ne = (size_t)m.n_e;
     double sd = 0.0, sa = 0.0, st = 0.0;
@@ -508,6 +510,7 @@ struct BodySolver {
             const double vd = pin[u][c] ? 0.0 : vhdiag(c, xb[c], mv[u], cvv[u]);
             const double d = fabs(acc2[i] + vd);
             Gout[g] = gi;
+            if (xt_out) xt_out[g] = xb[c];
             vdp()[g] = T(vd);
             A.Dv[g] = pin[u][c] ? 0.0f : precond_entry(d);
             acc[i] = 0.0;
@@ -572,17 +575,30 @@ struct BodySolver {
     const T* vd = vdp();
     const int B = blockDim.x;
     double rz = 0.0, rr = 0.0, pvp = 0.0;  // pvp: this thread's share of sum vd p^2
-    for (int i = threadIdx.x; i < n; i += B) {
-      const int g = base + i;
-      const double di = Dv[g];
-      const double ri = di != 0.0 ? sign * rhs[g] : 0.0;
-      const double zi = di * ri;
-      r[g] = ri;
-      ps[ld(i)] = zi;
-      xs[g] = 0.0;
-      rz += ri * zi;
-      rr += ri * ri;
-      pvp += vd[g] * zi * zi;
+    for (int i0 = threadIdx.x; i0 < n; i0 += kC * B) {
+      double dv[kC], bv[kC], vv[kC];
+#pragma unroll
+      for (int u = 0; u < kC; ++u) {
+        const int g = base + (i0 + u * B < n ? i0 + u * B : n - 1);
+        dv[u] = Dv[g];
+        bv[u] = rhs[g];
+        vv[u] = vd[g];
+      }
+#pragma unroll
+      for (int u = 0; u < kC; ++u) {
+        const int i = i0 + u * B;
+        if (i < n) {
+          const int g = base + i;
+          const double ri = dv[u] != 0.0 ? sign * bv[u] : 0.0;
+          const double zi = dv[u] * ri;
+          r[g] = ri;
+          ps[ld(i)] = zi;
+          xs[g] = 0.0;
+          rz += ri * zi;
+          rr += ri * ri;
+          pvp += vv[u] * zi * zi;
+        }
+      }
     }
     {
       double t[2] = {rz, rr};
@@ -674,13 +690,32 @@ struct BodySolver {
   }
 
   // -------- the forward step of one body --------
+  // per-DOF loops outside CG take kC owned DOFs per thread at a time, all loads first (indices
+  // past the body clamped to its last DOF)
+  static constexpr int kC = 4;
+
   __device__ void step(DevStats& st) {
     double* x = A.x1;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-      const int g = base + i;
-      const double xh = (sc.be && A.v0) ? A.x0[g] + sc.h * A.v0[g] : A.x0[g];
-      A.xhat[g] = xh;
-      x[g] = pinned(i) ? A.x0[g] : xh;
+    double* xt = A.xt;
+    const int B = blockDim.x;
+    for (int i0 = threadIdx.x; i0 < n; i0 += kC * B) {
+      double x0v[kC], v0v[kC];
+      bool pin[kC];
+#pragma unroll
+      for (int u = 0; u < kC; ++u) {
+        const int g = base + (i0 + u * B < n ? i0 + u * B : n - 1);
+        x0v[u] = A.x0[g];
+        v0v[u] = (sc.be && A.v0) ? A.v0[g] : 0.0;
+        pin[u] = m.pinned[g] != 0;
+      }
+#pragma unroll
+      for (int u = 0; u < kC; ++u)
+        if (i0 + u * B < n) {
+          const int g = base + i0 + u * B;
+          const double xh = (sc.be && A.v0) ? x0v[u] + sc.h * v0v[u] : x0v[u];
+          A.xhat[g] = xh;
+          x[g] = pin[u] ? x0v[u] : xh;
+        }
     }
     for (int vl = threadIdx.x; vl < v1 - v0; vl += blockDim.x)
       A.cv[v0 + vl] = fmax(-A.x0[(size_t)(v0 + vl) * D + 1] + sc.eps, 0.0);
@@ -709,7 +744,18 @@ struct BodySolver {
       st.cg_iters += it;
       st.negcurv_exits += neg ? 1 : 0;
       double gTd = 0.0;
-      for (int i = threadIdx.x; i < n; i += blockDim.x) gTd += G[base + i] * dx[base + i];
+      for (int i0 = threadIdx.x; i0 < n; i0 += kC * B) {
+        double gv[kC], dv[kC];
+#pragma unroll
+        for (int u = 0; u < kC; ++u) {
+          const int g = base + (i0 + u * B < n ? i0 + u * B : n - 1);
+          gv[u] = G[g];
+          dv[u] = dx[g];
+        }
+#pragma unroll
+        for (int u = 0; u < kC; ++u)
+          if (i0 + u * B < n) gTd += gv[u] * dv[u];
+      }
       gTd = sum1(gTd);
       if (!(gTd < 0.0)) {
         gTd = 0.0;
@@ -727,7 +773,7 @@ struct BodySolver {
       double alpha = 1.0, rt = res;
       bool accepted = false;
       for (int ls = 0; ls <= 30; ++ls) {
-        trial(x, dx, alpha, Gt, Ecur, Enew, tr);
+        trial(x, dx, alpha, Gt, Ecur, Enew, tr, xt);
         rt = sqrt(tr[3]);
         if (isfinite(tr[0]) && isfinite(rt)) {
           if (fabs(tr[0]) > 1e3 * 2.220446049250313e-16 * tr[1]) {
@@ -749,9 +795,11 @@ struct BodySolver {
         st.flags |= ISB_FLAG_STAGNATED;
         break;
       }
-      for (int i = threadIdx.x; i < n; i += blockDim.x) x[base + i] += alpha * dx[base + i];
-      __syncthreads();
-      double* tmp = G;
+      // the accepted trial point becomes the iterate (the trial's reduction published it)
+      double* tmp = x;
+      x = xt;
+      xt = tmp;
+      tmp = G;
       G = Gt;
       Gt = tmp;
       tmp = Ecur;
@@ -764,9 +812,25 @@ struct BodySolver {
     if (!isfinite(res)) st.flags |= ISB_FLAG_NONFINITE;
     st.res_final = res;
     if (res <= A.tol * res0) st.flags |= ISB_FLAG_CONVERGED;
-    if (sc.be && A.v1)
-      for (int i = threadIdx.x; i < n; i += blockDim.x)
-        A.v1[base + i] = (x[base + i] - A.x0[base + i]) / sc.h;
+    // x1 (when the iterate ended in the trial buffer) and v1 = (x1 - x0) / h
+    const bool copy_x = x != A.x1, want_v = sc.be && A.v1;
+    if (copy_x || want_v)
+      for (int i0 = threadIdx.x; i0 < n; i0 += kC * B) {
+        double xv[kC], x0v[kC];
+#pragma unroll
+        for (int u = 0; u < kC; ++u) {
+          const int g = base + (i0 + u * B < n ? i0 + u * B : n - 1);
+          xv[u] = x[g];
+          x0v[u] = want_v ? A.x0[g] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kC; ++u)
+          if (i0 + u * B < n) {
+            const int g = base + i0 + u * B;
+            if (copy_x) A.x1[g] = xv[u];
+            if (want_v) A.v1[g] = (xv[u] - x0v[u]) / sc.h;
+          }
+      }
     st.energy = gcur;
     if (A.want_tail) minmax_J(x, st.min_J, st.max_J);
     __syncthreads();
