@@ -312,29 +312,17 @@ struct BodySolver {
 
   // Stores what the Hessian-vector passes need at this iterate and returns the element's Hessian
   // diagonal per vertex and axis (FP64, before the s_pot scale). Triangles: the Hessian of W psi
-  // with respect to the edge matrix, K_s[q][q'] = d^2 (W psi) / dDs_q dDs_q', built column by
-  // column from Hessian-vector products with unit edge displacements and rounded once to T; a unit
-  // move of vertex j+1 along r is the unit edge displacement q = j D + r, one of vertex 0 moves
-  // every edge by -e_r. Tetrahedra: F and F d, rounded once to T, and the closed-form diagonal.
+  // with respect to the edge matrix, K_s[q][q'] = d^2 (W psi) / dDs_q dDs_q', in closed form
+  // (edge_hessian_2d) and rounded once to T; a unit move of vertex j+1 along r is the unit edge
+  // displacement q = j D + r, one of vertex 0 moves every edge by -e_r. Tetrahedra: F and F d,
+  // rounded once to T, and the closed-form diagonal.
   __device__ __forceinline__ void store_hv_state(int e, const ElemRest<D, double>& R64,
                                                  const ElemState<D, double>& S64, double ae,
                                                  double diag[D + 1][D]) const {
     const size_t ne = (size_t)m.n_e;
     if constexpr (kEdgeHessian) {
       double K[kQ][kQ];
-#pragma unroll
-      for (int q = 0; q < kQ; ++q) {
-        double dDs[D][D], out[D + 1][D];
-#pragma unroll
-        for (int j = 0; j < D; ++j)
-#pragma unroll
-          for (int r = 0; r < D; ++r) dDs[r][j] = (j * D + r == q) ? 1.0 : 0.0;
-        elem_hessvec<D, double>(R64, S64, ae, dDs, out);
-#pragma unroll
-        for (int j = 0; j < D; ++j)
-#pragma unroll
-          for (int r = 0; r < D; ++r) K[j * D + r][q] = out[j + 1][r];
-      }
+      edge_hessian_2d<double>(R64, S64, ae, K);
       int w = 0;
 #pragma unroll
       for (int a = 0; a < kQ; ++a)

@@ -260,6 +260,50 @@ __device__ __forceinline__ void elem_hessdiag(const ElemRest<D, T>& R, const Ele
   }
 }
 
+// Hessian of W psi of a triangle with respect to its edge matrix Ds, K[q][q'] with q = j*2 + r for
+// Ds[r][j], in closed form (the second derivative of Eq. 3 and Eq. 2 through F = Ds Dm^-1):
+//   K[(r,j),(r',j')] = [r == r'] (W mu M[j][j'] + k2 gf[j] gf[j'])
+//                    + [r != r'] c1 det(Dm^-1) s_r e(j,j')          (the cofactor term)
+//                    + c2 g[r][j] g[r'][j']                          (the log term, rank one)
+//                    + (k1 - k2) gf[j] gf[j'] n[r] n[r']             (the fibre's stretch direction)
+// with M = Dm^-1 Dm^-T, g = cof F Dm^-T, s_0 = 1, s_1 = -1, e(0,1) = 1, e(1,0) = -1, e(j,j) = 0,
+// c1 = (W lam l - W mu) l', c2 = W lam l'^2 - (W lam l - W mu) (l'' = -1), k1 = W k_f / a^2 and
+// k2 = (W k_f / a)(s/a - 1)/s: the same terms elem_hessvec applies to a direction.
+template <typename T>
+__device__ __forceinline__ void edge_hessian_2d(const ElemRest<2, T>& R, const ElemState<2, T>& S, T a,
+                                                T K[4][4]) {
+  const T c1 = (R.wlam * S.l - R.wmu) * S.dl;
+  const T c2 = R.wlam * S.dl * S.dl - (R.wlam * S.l - R.wmu);
+  const T ia = T(1) / a;
+  const T k1 = R.wkf * ia * ia;
+  const T k2 = R.wkf * ia * (S.s * ia - T(1)) * S.sinv;
+  const T detDinv = R.Dinv[0][0] * R.Dinv[1][1] - R.Dinv[0][1] * R.Dinv[1][0];
+  T M[2][2], g[2][2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j)
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      M[j][k] = R.Dinv[j][0] * R.Dinv[k][0] + R.Dinv[j][1] * R.Dinv[k][1];
+      g[j][k] = S.C[j][0] * R.Dinv[k][0] + S.C[j][1] * R.Dinv[k][1];  // g[r][j]
+    }
+#pragma unroll
+  for (int j = 0; j < 2; ++j)
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+        for (int rr = 0; rr < 2; ++rr) {
+          const T ff = R.gf[j] * R.gf[jj];
+          T v = c2 * g[r][j] * g[rr][jj] + (k1 - k2) * ff * S.n[r] * S.n[rr];
+          if (r == rr)
+            v += R.wmu * M[j][jj] + k2 * ff;
+          else if (j != jj)
+            v += c1 * detDinv * T(r == 0 ? 1 : -1) * T(j == 0 ? 1 : -1);
+          K[j * 2 + r][jj * 2 + rr] = v;
+        }
+}
+
 // Cotangents -w^T dG/dtheta of one element (G = d(W psi)/dx), before the s_pot scale:
 // returns {a_bar, mu_bar, lam_bar, kf_bar} for the edge matrix dWs of the adjoint vector w.
 template <int D, typename T>
