@@ -77,6 +77,8 @@ def parse():
     ap.add_argument("--profile", action="store_true", help="one untimed pass only (for rocprofv3)")
     ap.add_argument("--no-tet", action="store_true", help="skip the 3D tet-block leg")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay leg")
+    ap.add_argument("--no-policy", action="store_true", help="skip the policy-training leg")
+    ap.add_argument("--policy-iters", type=int, default=4)
     ap.add_argument("--tet-steps", type=int, default=20)
     ap.add_argument("--no-elem-roofline", action="store_true", help="skip the size-R element roofline leg")
     ap.add_argument("--elem-grid", type=str, default="192x128x64", help="Kuhn-tet grid of the size-R leg")
@@ -143,9 +145,10 @@ def adjoint_launch_bytes(dim, ne, nv, st, word_hv):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}). "
-              "Bodies are independent, so a multi-GPU run would shard them across processes; "
-              "see the sharding note in DESIGN.md.", file=sys.stderr)
+        print(f"bench.py measures one GPU: there is no multi-GPU path (asked for --gpus {args.gpus}). "
+              "Bodies are independent, so a multi-GPU run would give each process (one per GPU) a "
+              "slice of the bodies balanced by elements and iterations, with no exchange during a "
+              "solve.", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2102_05791_amd import Context, isb
@@ -366,6 +369,7 @@ def main():
         del g
         print("# graph replay leg done", file=sys.stderr, flush=True)
 
+    policy = None if args.no_policy else policy_leg(args, torch, Context, isb, scenes)
     tet = None if args.no_tet else tet_leg(args, torch, Context, isb, scenes)
     elem = None if args.no_elem_roofline else element_roofline_leg(args, torch, Context, isb, scenes)
     if elem:
@@ -383,7 +387,7 @@ def main():
                        "tol_rel": w.scene["tol_rel"], "adj_tol_rel": w.scene["adj_tol_rel"],
                        "block": ctx.get_option(isb.OPT_BLOCK)},
             "iterations": it, "plain_fp64": plain, "parity": parity, "roofline": roofline,
-            "cpu_baseline": cpu, "graph_replay": graph, "tet_block": tet, "element_roofline": elem}
+            "cpu_baseline": cpu, "graph_replay": graph, "policy_training": policy, "tet_block": tet, "element_roofline": elem}
     print(json.dumps(line))
 
 
@@ -409,6 +413,31 @@ def copy_ceiling(torch, isb):
     torch.cuda.empty_cache()
     return {"kernel": "isb_stream_copy", "bytes_moved": 2 * 8 * n, "ms": round(ms, 4), "GBs": round(gbs, 1),
             "frac_of_8TBs": round(gbs / HBM_PEAK_GBS, 4)}
+
+
+def policy_leg(args, torch, Context, isb, scenes):
+    """Policy-in-the-loop training (one Adam step per 100-step episode) on the 64x16 strip with the
+    batched mixed solver: training iterations per second and the rewards."""
+    from paper_2102_05791_amd.policy import FibrePolicy, train_locomotion
+    w = scenes.be_strip(64, 16, steps=1)
+    dev = torch.device("cuda:0")
+    ctx = Context.from_workload(w, precision="mixed", solver=1)
+    ctx.set_option(isb.OPT_GRAPH_SAFE, 1)
+    x0 = torch.tensor(w.x0, dtype=torch.float64, device=dev)
+    v0 = torch.zeros_like(x0)
+    pol = FibrePolicy(ctx.mass(), 2, w.n_e, seed=0)
+    H = 100
+    train_locomotion(ctx, pol, x0, v0, horizon=H, iterations=1)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rewards = train_locomotion(ctx, pol, x0, v0, horizon=H, iterations=args.policy_iters)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    print("# policy leg done", file=sys.stderr, flush=True)
+    return {"workload": f"be_strip 64x16 ({w.n_e} triangles), episode of {H} backward-Euler steps",
+            "policy": "32 ReLU units, FP64; Adam lr 1e-3, one step per episode",
+            "iterations_per_s": round(args.policy_iters / dt, 3), "iterations": args.policy_iters,
+            "rewards": [round(r, 6) for r in rewards], "solver": "batched mixed, graph-safe"}
 
 
 def tet_leg(args, torch, Context, isb, scenes):

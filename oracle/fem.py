@@ -13,7 +13,7 @@ products), so this module shares no algorithm with the GPU path.
   * Objectives: quasistatic E (Eq. 1) and backward Euler
     1/2 |x - (x0 + h v0)|_M^2 + h^2 E (Eq. 14).
 
-Readings where the paper is silent (all listed in the design doc):
+Readings where the paper is silent:
   log J is replaced by l(J) = (J-1) - (J-1)^2/2 for every J; I1 - d in 3D;
   one fibre per element with l/l0 = |F d|; lumped mass rho W / (d+1) per corner;
   contact has no 1/2 and an indicator [y < 0]; friction factor

@@ -5,8 +5,7 @@ holds none of the simulation's arithmetic (no energies, no derivatives, no
 solver), so that the oracle and the HIP path can both consume its output
 without sharing any of the method.
 
-Mesh conventions (the paper fixes none of them; they are readings documented in
-DESIGN.md):
+Mesh conventions (the paper fixes none of them; they are readings):
   * 2D: unit quads, vertex id = j*(nx+1) + i, position (i, j); each quad
     (v00, v10, v11, v01) is split into (v00, v10, v11) and (v00, v11, v01),
     both counter-clockwise, so every triangle has positive signed area.
