@@ -6,7 +6,7 @@ import torch
 
 from oracle.fem import Problem
 from synth import scenes
-from tests.test_gpu_policy import oracle_step
+from tests.oracle_layers import oracle_step
 
 
 def test_oracle_policy_gradient_matches_finite_differences():
