@@ -459,22 +459,21 @@ struct BodySolver {
     for (int vl0 = threadIdx.x; vl0 < nv; vl0 += kV * B) {
       double xa[kV][D], dd[kV][D], x0v[kV][D], xhv[kV][D], mv[kV], cvv[kV];
       bool pin[kV][D];
+      // loads for every lane (indices past the body clamped to its last vertex): loads inside a
+      // divergent branch are each waited for before the branch ends
 #pragma unroll
       for (int u = 0; u < kV; ++u) {
-        const int vl = vl0 + u * B;
-        if (vl < nv) {
-          const int vg = v0 + vl;
-          mv[u] = m.mass[vg];
-          cvv[u] = A.cv[vg];
+        const int vg = v0 + (vl0 + u * B < nv ? vl0 + u * B : nv - 1);
+        mv[u] = m.mass[vg];
+        cvv[u] = A.cv[vg];
 #pragma unroll
-          for (int c = 0; c < D; ++c) {
-            const size_t g = (size_t)vg * D + c;
-            xa[u][c] = x[g];
-            dd[u][c] = dxp ? dxp[g] : 0.0;
-            x0v[u][c] = A.x0[g];
-            xhv[u][c] = sc.be ? A.xhat[g] : 0.0;
-            pin[u][c] = m.pinned[g] != 0;
-          }
+        for (int c = 0; c < D; ++c) {
+          const size_t g = (size_t)vg * D + c;
+          xa[u][c] = x[g];
+          dd[u][c] = dxp ? dxp[g] : 0.0;
+          x0v[u][c] = A.x0[g];
+          xhv[u][c] = sc.be ? A.xhat[g] : 0.0;
+          pin[u][c] = m.pinned[g] != 0;
         }
       }
 #pragma unroll
