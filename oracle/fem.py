@@ -8,6 +8,9 @@ products), so this module shares no algorithm with the GPU path.
     stand-in for log J that the paper uses for inverted elements, plus the
     contractile fibre term (Eq. 2) written per element along a material
     direction; F is linear in x (Sec. 3).
+  * Spring energy: Eq. 2 as a literal spring between two vertices i, j with
+    l(x) = |x_j - x_i|, rest length l0 = |X_j - X_i| and its own action (Fig. 2's
+    reading of energies of d = x_j - x_i).
   * Vertex energies: ground contact (Sec. 5.2, Eq. 15), friction through the
     velocity v(x) = (x - x0)/h (Eq. 16-17), gravity.
   * Objectives: quasistatic E (Eq. 1) and backward Euler
@@ -17,7 +20,9 @@ Readings where the paper is silent:
   log J is replaced by l(J) = (J-1) - (J-1)^2/2 for every J; I1 - d in 3D;
   one fibre per element with l/l0 = |F d|; lumped mass rho W / (d+1) per corner;
   contact has no 1/2 and an indicator [y < 0]; friction factor
-  ReLU(-y0 + eps) on the tangential components; gravity lives inside E.
+  ReLU(-y0 + eps) on the tangential components; gravity lives inside E;
+  a spring's energy is k/2 (l/(a l0) - 1)^2 with no volume weight, and the action
+  vector lists the elements' actions first and then the springs'.
 """
 from __future__ import annotations
 
@@ -190,13 +195,65 @@ def element_hessians(mesh: Mesh, x, mu, lam, kf, a, fd):
 
 
 # --------------------------------------------------------------------------------------------
+# vertex-pair springs (Eq. 2 with d = x_j - x_i; Fig. 2)
+# --------------------------------------------------------------------------------------------
+def spring_energy(x, S, k, l0, a):
+    """k/2 (l/(a l0) - 1)^2 per spring, l = |x_j - x_i| for the pair (i, j) = S[s]."""
+    l = np.linalg.norm(x[S[:, 1]] - x[S[:, 0]], axis=-1)
+    return 0.5 * k * (l / (a * l0) - 1.0) ** 2
+
+
+def spring_force_terms(x, S, k, l0, a):
+    """(n, l, c, f) with n = d/l the spring's unit direction, c = 1/(a l0) and f = dE/dl = k c (c l - 1)."""
+    dvec = x[S[:, 1]] - x[S[:, 0]]
+    l = np.linalg.norm(dvec, axis=-1)
+    n = dvec / l[:, None]
+    c = 1.0 / (a * l0)
+    return n, l, c, k * c * (c * l - 1.0)
+
+
+def spring_grad(x, S, k, l0, a):
+    """Assembled gradient of the springs' energy [n_v, d]: +f n at j, -f n at i."""
+    n, _, _, f = spring_force_terms(x, S, k, l0, a)
+    G = np.zeros_like(x)
+    np.add.at(G, S[:, 1], f[:, None] * n)
+    np.add.at(G, S[:, 0], -f[:, None] * n)
+    return G
+
+
+def spring_hessians(x, S, k, l0, a):
+    """Dense spring Hessians [n_s, 2d, 2d], row/col index = end*d + axis with end 0 = i, 1 = j.
+
+    With K = d^2E/dd^2 = k c^2 n n^T + (f / l)(I - n n^T), the blocks are [[K, -K], [-K, K]]."""
+    n, l, c, f = spring_force_terms(x, S, k, l0, a)
+    d = x.shape[1]
+    nn = np.einsum("si,sj->sij", n, n)
+    K = (k * c * c)[:, None, None] * nn + (f / l)[:, None, None] * (np.eye(d)[None] - nn)
+    out = np.empty((S.shape[0], 2 * d, 2 * d))
+    out[:, :d, :d] = K
+    out[:, d:, d:] = K
+    out[:, :d, d:] = -K
+    out[:, d:, :d] = -K
+    return out
+
+
+# --------------------------------------------------------------------------------------------
 # the step objective g(x) (Eq. 1 quasistatic, Eq. 14 backward Euler) and its derivatives
 # --------------------------------------------------------------------------------------------
 class Problem:
     """One body: mesh, material, scene constants. All arrays FP64; x is [n_v, d]."""
 
-    def __init__(self, X, T, pinned, mu, lam, kf, fdir, rho, scene):
+    def __init__(self, X, T, pinned, mu, lam, kf, fdir, rho, scene, springs=None, k_spring=None):
         self.mesh = Mesh(X, T, rho)
+        # vertex-pair springs (i, j) with stiffness k and rest length |X_j - X_i|
+        self.S = np.zeros((0, 2), np.int64) if springs is None else np.asarray(springs, dtype=np.int64)
+        self.ks = np.zeros(0) if k_spring is None else np.asarray(k_spring, dtype=np.float64)
+        self.n_s = self.S.shape[0]
+        if self.ks.shape != (self.n_s,):
+            raise ValueError("one stiffness per spring")
+        self.l0 = np.linalg.norm(self.mesh.X[self.S[:, 1]] - self.mesh.X[self.S[:, 0]], axis=-1)
+        if np.any(self.l0 <= 0):
+            raise ValueError("a spring with zero rest length")
         self.pinned = np.asarray(pinned, dtype=bool)
         self.free = ~self.pinned.ravel()
         self.mu = np.asarray(mu, dtype=np.float64)
@@ -211,7 +268,15 @@ class Problem:
 
     @classmethod
     def from_workload(cls, w):
-        return cls(w.X, w.T, w.pinned, w.mu, w.lam, w.kf, w.fdir, w.rho, w.scene)
+        return cls(w.X, w.T, w.pinned, w.mu, w.lam, w.kf, w.fdir, w.rho, w.scene,
+                   getattr(w, "S", None), getattr(w, "ks", None))
+
+    def split(self, a):
+        """(element actions [n_e], spring actions [n_s]) of an action vector [n_e + n_s]."""
+        a = np.asarray(a, dtype=np.float64)
+        if a.shape != (self.mesh.n_e + self.n_s,):
+            raise ValueError("the action vector has one entry per element and then one per spring")
+        return a[:self.mesh.n_e], a[self.mesh.n_e:]
 
     # ---- vertex terms (Eq. 15-17 and gravity) ----
     def friction_factor(self, x0):
@@ -267,8 +332,10 @@ class Problem:
         return x0 + self.h * v0 if self.be else x0
 
     def energy_terms(self, x, x0, v0, a):
-        """(per-element terms, per-vertex terms) of g; their total sum is g(x)."""
-        ee = self.s_pot * self.element_energy(x, a)
+        """(per-element terms then per-spring terms, per-vertex terms) of g; their total sum is g(x)."""
+        ae, as_ = self.split(a)
+        ee = self.s_pot * np.concatenate([self.element_energy(x, ae),
+                                          spring_energy(x, self.S, self.ks, self.l0, as_)])
         ev = self.s_pot * self.vertex_energy(x, x0)
         if self.be:
             dx = x - self.x_hat(x0, v0)
@@ -281,7 +348,9 @@ class Problem:
 
     def grad(self, x, x0, v0, a):
         """dg/dx [n_v, d]; pinned DOFs are not masked here."""
-        G = self.s_pot * (self.element_grad(x, a) + self.vertex_grad(x, x0))
+        ae, as_ = self.split(a)
+        G = self.s_pot * (self.element_grad(x, ae) + spring_grad(x, self.S, self.ks, self.l0, as_)
+                          + self.vertex_grad(x, x0))
         if self.be:
             G += self.mesh.mass[:, None] * (x - self.x_hat(x0, v0))
         return G
@@ -289,12 +358,15 @@ class Problem:
     def hessian(self, x, x0, a) -> sp.csr_matrix:
         """Assembled d^2 g / dx^2 over all n_v*d DOFs (row-major DOF = v*d + axis)."""
         d = self.mesh.d
-        K = self.s_pot * element_hessians(self.mesh, x, self.mu, self.lam, self.kf, a, self.fd)
-        dofs = (self.mesh.T[:, :, None] * d + np.arange(d)[None, None, :]).reshape(self.mesh.n_e, -1)
-        rows = np.repeat(dofs, dofs.shape[1], axis=1).ravel()
-        cols = np.tile(dofs, (1, dofs.shape[1])).ravel()
+        ae, as_ = self.split(a)
         n = self.mesh.n_v * d
-        H = sp.coo_matrix((K.ravel(), (rows, cols)), shape=(n, n)).tocsr()
+        H = sp.csr_matrix((n, n))
+        for K, conn in ((element_hessians(self.mesh, x, self.mu, self.lam, self.kf, ae, self.fd), self.mesh.T),
+                        (spring_hessians(x, self.S, self.ks, self.l0, as_), self.S)):
+            dofs = (conn[:, :, None] * d + np.arange(d)[None, None, :]).reshape(conn.shape[0], conn.shape[1] * d)
+            rows = np.repeat(dofs, dofs.shape[1], axis=1).ravel()
+            cols = np.tile(dofs, (1, dofs.shape[1])).ravel()
+            H = H + sp.coo_matrix(((self.s_pot * K).ravel(), (rows, cols)), shape=(n, n)).tocsr()
         diag = self.s_pot * self.vertex_hess_diag(x, x0)
         if self.be:
             diag = diag + self.mesh.mass[:, None]

@@ -20,7 +20,7 @@ import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-from .fem import Problem, cofactor, det, edge_matrix, logq, logq_d
+from .fem import Problem, cofactor, det, edge_matrix, logq, logq_d, spring_force_terms
 
 ARMIJO_C1 = 1e-4
 LS_MAX = 30
@@ -167,12 +167,14 @@ def adjoint(prob: Problem, x1, x0, a, x1_bar, v1_bar=None, direct_max=None):
 
 
 def vjp_params(prob: Problem, w, x1, x0, a, v1_bar=None):
-    """Cotangents of (a, mu, lam, kf, x0, v0) given the adjoint vector w (Eq. 9, Eq. 14).
+    """Cotangents of (a, mu, lam, kf, k_spring, x0, v0) given the adjoint vector w (Eq. 9, Eq. 14).
 
-    Each is -w^T dG/dtheta evaluated at x1, where G = dg/dx, plus the explicit v1 path.
+    Each is -w^T dG/dtheta evaluated at x1, where G = dg/dx, plus the explicit v1 path. a_bar
+    lists the elements' entries and then the springs'.
     """
     m = prob.mesh
     s_pot = prob.s_pot
+    a, a_s = prob.split(a)
     F = m.F(x1)
     J = det(F)
     lJ, dl = logq(J), logq_d(J)
@@ -188,6 +190,13 @@ def vjp_params(prob: Problem, w, x1, x0, a, v1_bar=None):
     out["mu_bar"] = -s_pot * W * np.sum((F - dl[:, None, None] * C) * dFw, axis=(-2, -1))
     out["lam_bar"] = -s_pot * W * lJ * dl * np.sum(C * dFw, axis=(-2, -1))
     out["kf_bar"] = -s_pot * W * (1.0 / a) * (s / a - 1.0) * n_dFw_d
+    # springs: G = f n at j and -f n at i with f = k c (c l - 1), c = 1/(a l0); only f depends on
+    # a (dc/da = -c/a) and on k, so -w^T dG/dtheta = -(df/dtheta) n.(w_j - w_i)
+    n_s, l_s, c_s, _ = spring_force_terms(x1, prob.S, prob.ks, prob.l0, a_s)
+    n_dw = np.sum(n_s * (w[prob.S[:, 1]] - w[prob.S[:, 0]]), axis=-1)
+    df_da = -prob.ks * c_s * (2.0 * c_s * l_s - 1.0) / a_s
+    out["a_bar"] = np.concatenate([out["a_bar"], -s_pot * df_da * n_dw])
+    out["ks_bar"] = -s_pot * c_s * (c_s * l_s - 1.0) * n_dw
     # state cotangents: G depends on x0 through the inertia term and through friction
     x0_bar = np.zeros_like(x1)
     v0_bar = np.zeros_like(x1)
@@ -238,11 +247,11 @@ def rollout(prob: Problem, x0, v0, actions, tol=1e-13, max_iter=50):
 
 
 def rollout_grad(prob: Problem, states, actions, x_bar_T, v_bar_T=None):
-    """Backprop through time over a stored rollout: returns dL/da [T, n_e], dL/dx0, dL/dv0."""
+    """Backprop through time over a stored rollout: returns dL/da [T, n_e + n_s], dL/dx0, dL/dv0."""
     T = len(actions)
     x_bar = np.asarray(x_bar_T, dtype=np.float64)
     v_bar = np.zeros_like(x_bar) if v_bar_T is None else np.asarray(v_bar_T, dtype=np.float64)
-    a_bar = np.zeros((T, prob.mesh.n_e))
+    a_bar = np.zeros((T, prob.mesh.n_e + prob.n_s))
     for t in range(T - 1, -1, -1):
         x0, _ = states[t]
         x1, _ = states[t + 1]

@@ -98,6 +98,13 @@ def left_column_pins(X: np.ndarray) -> np.ndarray:
     return pinned
 
 
+def grid_springs(nx: int, ny: int) -> np.ndarray:
+    """The horizontal edges of tri_grid(nx, ny) as vertex pairs (left, right): int32 [nx (ny+1), 2]."""
+    j, i = np.meshgrid(np.arange(ny + 1), np.arange(nx), indexing="ij")
+    left = (j * (nx + 1) + i).ravel()
+    return np.stack([left, left + 1], axis=1).astype(np.int32)
+
+
 def contraction_actuation(gen: np.random.Generator, shape, umax: float = 0.3) -> np.ndarray:
     """Actuation a = 1 - u with u ~ U[0, umax): a = 1 relaxed, a < 1 contracts."""
     return 1.0 - gen.uniform(0.0, umax, size=shape)

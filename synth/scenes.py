@@ -10,6 +10,10 @@ Sizes:
   be_strip        64x16 quads, 2048 triangles, 1105 vertices, backward Euler, 100 steps
   batched_strips  512 bodies, s ~ U{4..32}, grid 4s x s, 50 steps
   tet_block       64x32x32 cubes, 393216 Kuhn tets, 70785 vertices, 20 steps
+  be_spring_strip, batched_spring_strips: the strips with the fibres as vertex-pair springs on
+                  the horizontal grid edges (k = E per unit quad) and passive triangles (k_f = 0)
+
+Action arrays hold, per step, the elements' actions and then the springs'.
 """
 from __future__ import annotations
 
@@ -53,15 +57,28 @@ class Workload:
     scene: dict
     x0: np.ndarray           # [n_v, d]
     v0: np.ndarray           # [n_v, d]
-    actions: np.ndarray      # [steps, n_e]
+    actions: np.ndarray      # [steps, n_e + n_s]
     body_v_off: np.ndarray = field(default=None)
     body_e_off: np.ndarray = field(default=None)
+    S: np.ndarray = field(default=None)           # [n_s, 2] int32 vertex pairs (global ids)
+    ks: np.ndarray = field(default=None)          # [n_s] spring stiffness
+    body_s_off: np.ndarray = field(default=None)  # [n_bodies + 1]
 
     def __post_init__(self):
         if self.body_v_off is None:
             self.body_v_off = np.array([0, self.X.shape[0]], dtype=np.int64)
         if self.body_e_off is None:
             self.body_e_off = np.array([0, self.T.shape[0]], dtype=np.int64)
+        if self.S is None:
+            self.S = np.zeros((0, 2), np.int32)
+            self.ks = np.zeros(0)
+        if self.body_s_off is None:
+            self.body_s_off = np.zeros(len(self.body_v_off), dtype=np.int64)
+            self.body_s_off[-1] = self.S.shape[0]
+
+    @property
+    def n_s(self):
+        return self.S.shape[0]
 
     @property
     def n_v(self):
@@ -79,12 +96,14 @@ class Workload:
         """The b-th body as a stand-alone single-body workload."""
         v0, v1 = int(self.body_v_off[b]), int(self.body_v_off[b + 1])
         e0, e1 = int(self.body_e_off[b]), int(self.body_e_off[b + 1])
+        s0, s1 = int(self.body_s_off[b]), int(self.body_s_off[b + 1])
+        acts = np.concatenate([self.actions[:, e0:e1], self.actions[:, self.n_e + s0:self.n_e + s1]], axis=1)
         return Workload(f"{self.name}[{b}]", self.dim, self.X[v0:v1].copy(),
                         (self.T[e0:e1] - v0).astype(np.int32), self.pinned[v0:v1].copy(),
                         self.mu[e0:e1].copy(), self.lam[e0:e1].copy(), self.kf[e0:e1].copy(),
                         self.fdir[e0:e1].copy(), self.rho[e0:e1].copy(), dict(self.scene),
-                        self.x0[v0:v1].copy(), self.v0[v0:v1].copy(),
-                        self.actions[:, e0:e1].copy())
+                        self.x0[v0:v1].copy(), self.v0[v0:v1].copy(), acts,
+                        S=(self.S[s0:s1] - v0).astype(np.int32), ks=self.ks[s0:s1].copy())
 
 
 def _material(n_e, dim, E, nu):
@@ -142,3 +161,37 @@ def tet_block(nx=64, ny=32, nz=32, steps=20, tol_rel=1e-6) -> Workload:
     sc = scene("be", h=1.0 / 30.0, tol_rel=tol_rel)
     return Workload(f"tet_block_{nx}x{ny}x{nz}", 3, X, T, np.zeros(X.shape, np.uint8), mu, lam,
                     kf, fd, rho, sc, X.copy(), np.zeros_like(X), acts)
+
+
+def be_spring_strip(nx=64, ny=16, steps=100, seed_cfg=6, tol_rel=1e-6) -> Workload:
+    """be_strip with the fibres moved to springs: passive triangles (k_f = 0) and one spring of
+    stiffness E on each horizontal grid edge (the fibre of one unit quad), actuated at random."""
+    w = be_strip(nx, ny, steps, tol_rel=tol_rel)
+    S = meshes.grid_springs(nx, ny)
+    E = float(w.kf[0])
+    acts = np.concatenate([np.ones((steps, w.n_e)),
+                           meshes.contraction_actuation(meshes.rng(seed_cfg), (steps, S.shape[0]))], axis=1)
+    return Workload(f"be_spring_strip_{nx}x{ny}", 2, w.X, w.T, w.pinned, w.mu, w.lam, np.zeros(w.n_e),
+                    w.fdir, w.rho, w.scene, w.x0, w.v0, acts, S=S, ks=np.full(S.shape[0], E))
+
+
+def batched_spring_strips(n_bodies=512, steps=50, tol_rel=1e-6, sizes=None) -> Workload:
+    """batched_strips with spring fibres: body b is a (4 s_b) x s_b strip, s_b ~ U{4..32}, with
+    passive triangles and a spring on each horizontal grid edge."""
+    if sizes is None:
+        sizes = batched_sizes(n_bodies)
+    bodies, springs, eacts, sacts = [], [], [], []
+    for b, s in enumerate(sizes):
+        X, T = meshes.tri_grid(4 * int(s), int(s))
+        bodies.append((X, T, np.zeros(X.shape, np.uint8)))
+        springs.append(meshes.grid_springs(4 * int(s), int(s)))
+        eacts.append(np.ones((steps, T.shape[0])))
+        sacts.append(meshes.contraction_actuation(meshes.rng(7, b), (steps, springs[-1].shape[0])))
+    X, T, P, voff, eoff = meshes.concat_bodies(bodies)
+    soff = np.concatenate([[0], np.cumsum([sp.shape[0] for sp in springs])]).astype(np.int64)
+    S = np.concatenate([sp + voff[b] for b, sp in enumerate(springs)]).astype(np.int32)
+    mu, lam, kf, fd, rho = _material(T.shape[0], 2, 1e4, 0.3)
+    sc = scene("be", h=1.0 / 60.0, tol_rel=tol_rel)
+    return Workload(f"batched_spring_strips_{len(sizes)}", 2, X, T, P, mu, lam, np.zeros_like(kf), fd, rho,
+                    sc, X.copy(), np.zeros_like(X), np.concatenate(eacts + sacts, axis=1), voff, eoff,
+                    S=S, ks=np.full(S.shape[0], 1e4), body_s_off=soff)
