@@ -78,6 +78,7 @@ def parse():
     ap.add_argument("--no-tet", action="store_true", help="skip the 3D tet-block leg")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay leg")
     ap.add_argument("--no-policy", action="store_true", help="skip the policy-training leg")
+    ap.add_argument("--no-springs", action="store_true", help="skip the vertex-pair spring leg")
     ap.add_argument("--policy-iters", type=int, default=4)
     ap.add_argument("--tet-steps", type=int, default=20)
     ap.add_argument("--no-elem-roofline", action="store_true", help="skip the size-R element roofline leg")
@@ -123,23 +124,38 @@ def trial_bytes(dim, ne, nv, word_hv):
             + (41 + 8 + 4 + word_hv) * nv * dim + 16 * nv)
 
 
-def step_launch_bytes(dim, ne, nv, st, word_hv):
-    """Algorithmic bytes of one body in one step launch, from its solver statistics."""
+def spring_hv_bytes(dim, word):
+    """One spring in a batched Hessian-vector pass: two 16-bit ends and the stored block K."""
+    return 4 + word * dim * (dim + 1) // 2
+
+
+def spring_trial_bytes(dim, word):
+    """One spring in a trial (or diagonal) pass: ends, stiffness, 1/l0 and action (FP64), its energy
+    read and written, the block K stored."""
+    return 4 + 24 + 16 + word * dim * (dim + 1) // 2
+
+
+def step_launch_bytes(dim, ne, nv, st, word_hv, ns=0):
+    """Algorithmic bytes of one body (ne elements, nv vertices, ns springs) in one step launch,
+    from its solver statistics."""
     dof = nv * dim
     trials = 1 + st["newton_iters"] + st["ls_backtracks"]
     setup = 57 * dof + 16 * nv                 # x0, v0, pinned -> xhat, x; c_v; v1 at the end
     per_newton = (8 + 4 + word_hv + 24) * dof + 16 * dof + 24 * dof  # CG start; g.dx; x += alpha dx
-    return (setup + trials * trial_bytes(dim, ne, nv, word_hv) - 8 * ne
-            + st["newton_iters"] * per_newton + st["cg_iters"] * cg_iter_bytes(dim, ne, nv, word_hv))
+    return (setup + trials * (trial_bytes(dim, ne, nv, word_hv) + ns * spring_trial_bytes(dim, word_hv))
+            - 8 * (ne + ns) + st["newton_iters"] * per_newton
+            + st["cg_iters"] * (cg_iter_bytes(dim, ne, nv, word_hv) + ns * spring_hv_bytes(dim, word_hv)))
 
 
-def adjoint_launch_bytes(dim, ne, nv, st, word_hv):
+def adjoint_launch_bytes(dim, ne, nv, st, word_hv, ns=0):
     """Right-hand side (xbar, vbar, pinned -> G; c_v), the FP64 diagonal pass that also stores the
     Hessian-vector state, the CG start and the CG iterations."""
     dof = nv * dim
     rhs = 25 * dof + 16 * nv
-    diag = (elem_bytes(dim, 8) - 2 * (dim + 1) + hv_state_bytes(dim, word_hv)) * ne + (9 + 4 + word_hv) * dof + 16 * nv
-    return rhs + diag + (36 + 4 + word_hv) * dof + st["adj_cg_iters"] * cg_iter_bytes(dim, ne, nv, word_hv)
+    diag = ((elem_bytes(dim, 8) - 2 * (dim + 1) + hv_state_bytes(dim, word_hv)) * ne + (9 + 4 + word_hv) * dof
+            + 16 * nv + ns * (spring_trial_bytes(dim, word_hv) - 16))
+    return (rhs + diag + (36 + 4 + word_hv) * dof
+            + st["adj_cg_iters"] * (cg_iter_bytes(dim, ne, nv, word_hv) + ns * spring_hv_bytes(dim, word_hv)))
 
 
 def main():
@@ -369,6 +385,7 @@ def main():
         del g
         print("# graph replay leg done", file=sys.stderr, flush=True)
 
+    springs = None if args.no_springs else spring_leg(args, torch, Context, isb, scenes)
     policy = None if args.no_policy else policy_leg(args, torch, Context, isb, scenes)
     tet = None if args.no_tet else tet_leg(args, torch, Context, isb, scenes)
     elem = None if args.no_elem_roofline else element_roofline_leg(args, torch, Context, isb, scenes)
@@ -387,7 +404,7 @@ def main():
                        "tol_rel": w.scene["tol_rel"], "adj_tol_rel": w.scene["adj_tol_rel"],
                        "block": ctx.get_option(isb.OPT_BLOCK)},
             "iterations": it, "plain_fp64": plain, "parity": parity, "roofline": roofline,
-            "cpu_baseline": cpu, "graph_replay": graph, "policy_training": policy, "tet_block": tet, "element_roofline": elem}
+            "cpu_baseline": cpu, "graph_replay": graph, "springs": springs, "policy_training": policy, "tet_block": tet, "element_roofline": elem}
     print(json.dumps(line))
 
 
@@ -413,6 +430,86 @@ def copy_ceiling(torch, isb):
     torch.cuda.empty_cache()
     return {"kernel": "isb_stream_copy", "bytes_moved": 2 * 8 * n, "ms": round(ms, 4), "GBs": round(gbs, 1),
             "frac_of_8TBs": round(gbs / HBM_PEAK_GBS, 4)}
+
+
+def spring_leg(args, torch, Context, isb, scenes):
+    """The batched workload with the fibres as vertex-pair springs (passive triangles, one spring per
+    horizontal grid edge): the same BPTT pass (T steps fwd + T adjoints + VJPs), batched mixed."""
+    dev = torch.device("cuda:0")
+    T = args.rollout
+    w = scenes.batched_spring_strips(args.bodies, steps=T)
+    nb = w.n_bodies
+    ctx = Context.from_workload(w, precision="mixed", solver=1)
+    ctx.set_option(isb.OPT_GRAPH_SAFE, 1)
+    x0 = torch.tensor(w.x0, dtype=torch.float64, device=dev)
+    v0 = torch.zeros_like(x0)
+    acts = torch.tensor(w.actions, dtype=torch.float64, device=dev)
+    mass = ctx.mass()
+    body_of_v = torch.tensor(np.repeat(np.arange(nb), np.diff(w.body_v_off)), device=dev)
+    msum = torch.zeros(nb, dtype=torch.float64, device=dev).index_add_(0, body_of_v, mass)
+    xbar_T = torch.zeros_like(x0)
+    xbar_T[:, 0] = -mass / msum[body_of_v]
+    step_ev = []
+
+    def bptt(record=False, stats=False):
+        xs, vs, st_f, st_a = [x0], [v0], [], []
+        for t in range(T):
+            if record:
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+            x1, v1, sf, _ = ctx.step(xs[-1], vs[-1], acts[t], stats=stats)
+            if record:
+                e1.record()
+                step_ev.append((e0, e1))
+            xs.append(x1)
+            vs.append(v1)
+            st_f.append(sf)
+        xb, vb = xbar_T, torch.zeros_like(x0)
+        for t in range(T - 1, -1, -1):
+            wv, sa, _ = ctx.solve_adjoint(xs[t + 1], xs[t], acts[t], xb, vb, stats=stats)
+            out = ctx.vjp_params(wv, xs[t + 1], xs[t], acts[t], vb, want=("a_bar", "x0_bar", "v0_bar"))
+            xb, vb = out["x0_bar"], out["v0_bar"]
+            st_a.append(sa)
+        return xs, st_f, st_a
+
+    bptt()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        xs, _, _ = bptt(record=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = float(np.mean([a.elapsed_time(b) for a, b in step_ev]))
+    _, st_f, st_a = bptt(stats=True)
+    ne_b, nv_b, ns_b = np.diff(w.body_e_off), np.diff(w.body_v_off), np.diff(w.body_s_off)
+    fb = float(np.mean([sum(step_launch_bytes(2, ne_b[b], nv_b[b], S[b], 4, ns_b[b]) for b in range(nb))
+                        for S in st_f]))
+    achieved = fb / (step_ms * 1e-3) / 1e9
+    errs = []
+    try:
+        from oracle import solve as osolve
+        from oracle.fem import Problem
+        x1 = xs[1].cpu().numpy()
+        for b in (0, nb - 1):
+            wb = w.body(b)
+            xr, _, _ = osolve.step(Problem.from_workload(wb), wb.x0, wb.v0, wb.actions[0], tol=1e-13)
+            sv = slice(w.body_v_off[b], w.body_v_off[b + 1])
+            errs.append(float(np.linalg.norm(x1[sv] - xr) / np.linalg.norm(xr - wb.x0)))
+    except Exception as e:  # report, never fail the bench line on the check
+        errs = [repr(e)]
+    print("# spring leg done", file=sys.stderr, flush=True)
+    return {"workload": f"batched_spring_strips: {nb} bodies, {w.n_e} passive triangles + {w.n_s} springs, "
+                        f"{w.n_v} vertices, {T} backward-Euler steps fwd + adjoint + VJP",
+            "value": round(nb * T * args.steps / wall, 1), "unit": "body-steps/s",
+            "ms_per_step": round(1e3 * wall / args.steps, 3), "solver": "batched mixed, graph-safe",
+            "step_launch_ms": round(step_ms, 4),
+            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(achieved / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_launch": int(fb)},
+            "newton_per_step": float(np.mean([[s["newton_iters"] for s in S] for S in st_f])),
+            "cg_per_step": float(np.mean([[s["cg_iters"] for s in S] for S in st_f])),
+            "adj_cg_per_step": float(np.mean([[s["adj_cg_iters"] for s in S] for S in st_a])),
+            "not_converged_steps": int(sum(1 for S in st_f for s in S if not (s["flags"] & 1))),
+            "x1_rel_err_vs_oracle_displacement": {"bodies": [0, nb - 1], "err": errs}}
 
 
 def policy_leg(args, torch, Context, isb, scenes):

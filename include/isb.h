@@ -11,7 +11,9 @@
  * plus the contractile fibre term of Eq. 2 taken along a per-element material
  * direction d (l / l0 = |F d|), scaled by the rest volume W; and, per vertex,
  * gravity m g y, ground contact k_c ReLU(-y)^2 (Eq. 15) and friction
- * k_fr ((x_t - x0_t)/h)^2 ReLU(-y0 + eps) on the tangential axes (Eq. 16-17).
+ * k_fr ((x_t - x0_t)/h)^2 ReLU(-y0 + eps) on the tangential axes (Eq. 16-17);
+ * and, per vertex-pair spring (optional, isb_spring_upload), Eq. 2 with l the
+ * distance between the spring's two vertices (Fig. 2's energies of d = x_j - x_i).
  * The minimiser is found by Newton's method with a preconditioned conjugate
  * gradient inner solve over matrix-free Hessian-vector products (Sec. 4.1,
  * Eq. 10); the backward pass is the adjoint of Eq. 9: one CG solve with the
@@ -21,6 +23,8 @@
  *   - Vertex arrays are [n_v][dim] row-major FP64 (the n x d layout of Sec. 4.1);
  *     element arrays are [n_e] or [n_e][dim]; y (axis 1) is "up"; dim is 2
  *     (triangles) or 3 (tetrahedra).
+ *   - The action vector a (and its cotangent a_bar) has n_e + n_s entries: one per
+ *     element's fibre, then one per spring (n_s = 0 without springs).
  *   - Pointers named "host" are CPU memory, copied before the call returns.
  *     Every other array argument is device memory on the context's GPU, owned
  *     by the caller; the library never keeps a caller pointer past the call.
@@ -163,6 +167,18 @@ isb_status isb_mesh_upload(isb_ctx* ctx, int dim, int32_t n_bodies, const int64_
 isb_status isb_material_upload(isb_ctx* ctx, const double* mu, const double* lam, const double* k_fibre,
                                const double* fibre_dir, const double* density, const isb_scene* scene);
 
+/* Vertex-pair springs of Eq. 2: spring s joins vertices i = pairs[2s] and j = pairs[2s+1] (global
+ * ids, both inside the body that owns s, i != j) with energy k[s]/2 (l / (a l0) - 1)^2, l = |x_j - x_i|,
+ * rest length l0 = |X_j - X_i| from the uploaded rest positions (must be > 0) and its own action
+ * a[n_e + s]. body_s_off host [n_bodies+1] (springs of body b are [body_s_off[b], body_s_off[b+1]);
+ * may be NULL for one body); pairs host [n_s][2] int32; k host [n_s], finite and >= 0 (no volume
+ * weight). Spring arithmetic is FP64, except that the batched solver in ISB_MIXED applies the
+ * FP64-formed spring block to the CG direction in FP32, as it does the element blocks. n_s = 0
+ * removes the springs. Requires a
+ * mesh; a new mesh upload removes them. ISB_E_MESH for a bad pair or rest length, ISB_E_ARG otherwise. */
+isb_status isb_spring_upload(isb_ctx* ctx, int64_t n_s, const int64_t* body_s_off, const int32_t* pairs,
+                             const double* k);
+
 /* Replace the scene constants (tolerances, stiffnesses, h) without re-uploading the material. */
 isb_status isb_set_scene(isb_ctx* ctx, const isb_scene* scene);
 
@@ -175,7 +191,7 @@ isb_status isb_get_mass(isb_ctx* ctx, isb_stream stream, double* mass_out);
 /* ---- the step and its adjoint ------------------------------------------------------------- */
 
 /* One implicit step (Eq. 1 or Eq. 14) of every body. x0, v0: device [n_v][dim] (v0 ignored and
- * may be NULL in quasistatic mode); a: device [n_e], actuation of Eq. 2 (1 = relaxed, < 1
+ * may be NULL in quasistatic mode); a: device [n_e + n_s], actuation of Eq. 2 (1 = relaxed, < 1
  * contracts; must be > 0); x1, v1: device out [n_v][dim] (v1 may be NULL; it is not written in
  * quasistatic mode). per_body: host [n_bodies] stats or NULL. Returns ISB_E_NOT_CONVERGED if
  * any body hit max_newton (x1, v1 then hold the last iterate), ISB_E_NONFINITE on NaN/Inf. */
@@ -185,20 +201,26 @@ isb_status isb_step(isb_ctx* ctx, isb_stream stream, const double* x0, const dou
 /* Adjoint solve of Eq. 9: w = H(x1)^-1 (x1_bar + v1_bar / h) over the free DOFs (the v1_bar term
  * only in backward Euler; v1_bar may be NULL), w = 0 on pinned DOFs. H is the unprojected
  * Hessian of the step objective at x1, symmetric and positive definite at a minimiser (Sec. 4),
- * so CG needs no transpose. x1, x0: device [n_v][dim]; a: device [n_e]; w: device out. */
+ * so CG needs no transpose. x1, x0: device [n_v][dim]; a: device [n_e + n_s]; w: device out. */
 isb_status isb_solve_adjoint(isb_ctx* ctx, isb_stream stream, const double* x1, const double* x0,
                              const double* a, const double* x1_bar, const double* v1_bar, double* w,
                              isb_stats* per_body);
 
 /* Vector-Jacobian products given the adjoint w: theta_bar = -w^T dG/dtheta with G = grad_x g
  * (Eq. 9 and the remark after Eq. 10), evaluated at x1. Outputs (device, any may be NULL):
- *   a_bar, mu_bar, lam_bar, kf_bar [n_e]   per-element actuation and material cotangents
+ *   a_bar [n_e + n_s]                      actuation cotangents (elements, then springs)
+ *   mu_bar, lam_bar, kf_bar [n_e]          per-element material cotangents
  *   x0_bar, v0_bar [n_v][dim]              previous-state cotangents, including the explicit
  *                                          v1 = (x1 - x0)/h path (-v1_bar / h) in backward Euler */
 isb_status isb_vjp_params(isb_ctx* ctx, isb_stream stream, const double* w, const double* x1,
                           const double* x0, const double* a, const double* v1_bar, double* a_bar,
                           double* x0_bar, double* v0_bar, double* mu_bar, double* lam_bar,
                           double* kf_bar);
+
+/* Spring stiffness cotangents k_bar = -w^T dG/dk (Eq. 9) at x1, device out [n_s]; a: device
+ * [n_e + n_s]. Nothing to do without springs. */
+isb_status isb_vjp_spring_stiffness(isb_ctx* ctx, isb_stream stream, const double* w, const double* x1,
+                                    const double* a, double* k_bar);
 
 /* ---- single evaluations of the step objective (the kernels of the solver, exposed) --------- */
 
@@ -213,8 +235,8 @@ isb_status isb_gradient(isb_ctx* ctx, isb_stream stream, const double* x, const 
 isb_status isb_hessvec(isb_ctx* ctx, isb_stream stream, const double* x, const double* x0,
                        const double* a, const double* p, double* hp);
 /* Element part of the Hessian-vector product only, added into hp: hp += sum_e W_e dP(F_e; dF_e(p)) Dm^-T
- * scattered to the element's vertices (Eq. 10 without the vertex terms and without the projection
- * onto free DOFs), scaled by h^2 in backward Euler. This is the hot kernel of the CG iteration on
+ * scattered to the element's vertices, plus the springs' K (p_j - p_i) (Eq. 10 without the vertex
+ * terms and without the projection onto free DOFs), scaled by h^2 in backward Euler. This is the hot kernel of the CG iteration on
  * its own, for callers that add their own vertex terms and for timing. device [n_v][dim] in/in-out. */
 isb_status isb_hessvec_elements(isb_ctx* ctx, isb_stream stream, const double* x, const double* a,
                                 const double* p, double* hp);

@@ -34,6 +34,7 @@ isb_ctx::~isb_ctx() {
   (void)hipSetDevice(device);
   batched_release(this);
   free_list(work_allocs);
+  free_list(spring_allocs);
   free_list(mesh_allocs);
   if (hscal) (void)hipHostFree(hscal);
   if (hcg) (void)hipHostFree(hcg);
@@ -62,6 +63,8 @@ DevMesh devmesh(const isb_ctx* c) {
   m.pinned = c->pinned;
   return m;
 }
+
+DevSprings devsprings(const isb_ctx* c) { return DevSprings{c->n_s, c->sconn, c->sk, c->sil0}; }
 
 DevScene devscene(const isb_ctx* c) {
   DevScene s;
@@ -148,6 +151,28 @@ static void elem_ranges(const isb_ctx* c, int b, Fn fn) {
 // them is latency bound and patches of a small body cannot fill the GPU.
 static constexpr int64_t kPatchMinElems = 16384;
 
+// spring scatter of op (PATCH_GRAD / PATCH_HV / PATCH_DIAG) over body b (all bodies when b < 0):
+// one pass per colour in colour mode (bitwise reproducible), FP64 global atomics otherwise
+static void spring_scatter(isb_ctx* c, int b, int op, const double* x, const double* a, const double* p,
+                           double* out, const int* done, hipStream_t s) {
+  if (c->n_s == 0) return;
+  const DevSprings sp = devsprings(c);
+  const DevScene sc = devscene(c);
+  const double* as = a + c->n_e;
+  const int b0 = b < 0 ? 0 : b, b1 = b < 0 ? c->n_bodies : b + 1;
+  if (c->scatter != 1) {
+    launch_spring_op(c->dim, sp, sc, ERange{(int)c->soff[b0], (int)c->soff[b1], nullptr}, true, op, x, as, p, out,
+                     done, s);
+    return;
+  }
+  const int nc1 = c->n_scolours + 1;
+  for (int bb = b0; bb < b1; ++bb)
+    for (int k = 0; k < c->n_scolours; ++k) {
+      const int s0 = c->scol_off[bb * nc1 + k], s1 = c->scol_off[bb * nc1 + k + 1];
+      if (s1 > s0) launch_spring_op(c->dim, sp, sc, ERange{s0, s1, c->sclist}, false, op, x, as, p, out, done, s);
+    }
+}
+
 // element scatter of op (PATCH_GRAD / PATCH_HV / PATCH_DIAG) over body b (all bodies when b < 0),
 // in the context's scatter mode: FP64 global atomics, colour passes, or LDS-staged patches. Only
 // the Hessian-vector product takes the context's precision; gradient and diagonal are FP64.
@@ -161,16 +186,17 @@ static void elem_scatter(isb_ctx* c, int b, int op, const double* x, const doubl
     const int p0 = b < 0 ? 0 : c->body_patch_off[b];
     const int p1 = b < 0 ? c->n_patches : c->body_patch_off[b + 1];
     launch_elem_patch(m, sc, c->plan, p0, p1, op, op == PATCH_HV ? c->precision : 0, x, a, a32, p, out, done, s);
-    return;
+  } else {
+    elem_ranges(c, b, [&](ERange r, bool atomic) {
+      if (op == PATCH_GRAD)
+        launch_elem_grad(m, sc, r, atomic, x, a, out, s);
+      else if (op == PATCH_HV)
+        launch_elem_hv(m, sc, r, atomic, c->precision, x, a, a32, p, out, done, s);
+      else
+        launch_elem_diag(m, sc, r, atomic, x, a, out, s);
+    });
   }
-  elem_ranges(c, b, [&](ERange r, bool atomic) {
-    if (op == PATCH_GRAD)
-      launch_elem_grad(m, sc, r, atomic, x, a, out, s);
-    else if (op == PATCH_HV)
-      launch_elem_hv(m, sc, r, atomic, c->precision, x, a, a32, p, out, done, s);
-    else
-      launch_elem_diag(m, sc, r, atomic, x, a, out, s);
-  });
+  spring_scatter(c, b, op, x, a, p, out, done, s);
 }
 
 struct BodyRange {
@@ -233,10 +259,15 @@ static void enqueue_energy(isb_ctx* c, int b, const double* x, const double* dx,
   const DevMesh m = devmesh(c);
   const DevScene sc = devscene(c);
   const BodyRange br = body_range(c, b);
-  int nbe = 0, nbv = 0;
+  int nbe = 0, nbs = 0, nbv = 0;
   launch_elem_energy(m, sc, ERange{br.e0, br.e1, nullptr}, x, dx, alpha, a, c->partials, 0, s, &nbe);
-  launch_vertex_energy(m, sc, br.v0, br.v1, x, dx, alpha, x0, c->w_xhat, c->w_cv, c->partials, nbe, s, &nbv);
-  launch_finalize(c->partials, nbe + nbv, 3, out, s);
+  if (c->n_s > 0) {
+    const int b0 = b < 0 ? 0 : b, b1 = b < 0 ? c->n_bodies : b + 1;
+    launch_spring_energy(c->dim, devsprings(c), sc, ERange{(int)c->soff[b0], (int)c->soff[b1], nullptr}, x, dx,
+                         alpha, a + c->n_e, c->partials, nbe, s, &nbs);
+  }
+  launch_vertex_energy(m, sc, br.v0, br.v1, x, dx, alpha, x0, c->w_xhat, c->w_cv, c->partials, nbe + nbs, s, &nbv);
+  launch_finalize(c->partials, nbe + nbs + nbv, 3, out, s);
 }
 
 // PCG on H(x) xs = sign * rhs over body b; returns iterations, sets negcurv and the final r.r
@@ -396,9 +427,9 @@ static isb_status fill_stats_tail(isb_ctx* c, int b, hipStream_t s, const double
   return ISB_OK;
 }
 
-// check a > 0 and finite (one reduction, host read)
+// check a > 0 and finite over the elements' and springs' actions (one reduction, host read)
 static isb_status check_actuation(isb_ctx* c, hipStream_t s, const double* a) {
-  launch_min_count(c->n_e, a, c->partials, c->dscal, s);
+  launch_min_count(c->n_e + c->n_s, a, c->partials, c->dscal, s);
   ISB_TRY(read_scal(c, s, 2));
   if (c->hscal[1] != 0.0) return fail(ISB_E_NONFINITE, "non-finite actuation");
   if (!(c->hscal[0] > 0.0)) return fail(ISB_E_ARG, "actuation a must be > 0");
@@ -485,7 +516,7 @@ static isb_status alloc_workspaces(isb_ctx* c) {
     ISB_TRY(dalloc(L, p, nd));
   ISB_TRY(dalloc(L, &c->w_cv, (size_t)c->n_v));
   ISB_TRY(dalloc(L, &c->w_a32, (size_t)c->n_e));
-  ISB_TRY(dalloc(L, &c->partials, (size_t)8 * kMaxRedBlocks));
+  ISB_TRY(dalloc(L, &c->partials, (size_t)12 * kMaxRedBlocks));
   ISB_TRY(dalloc(L, &c->dscal, (size_t)64));
   ISB_TRY(dalloc(L, &c->ebuf, (size_t)3 * c->n_bodies));
   ISB_TRY(dalloc(L, &c->scal, (size_t)1));
@@ -550,6 +581,13 @@ isb_status isb_mesh_upload(isb_ctx* c, int dim, int32_t n_bodies, const int64_t*
   c->n_e = (int)n_e;
   c->voff.assign(body_v_off, body_v_off + n_bodies + 1);
   c->eoff.assign(body_e_off, body_e_off + n_bodies + 1);
+  c->free_list(c->spring_allocs);
+  c->n_s = c->n_scolours = 0;
+  c->soff.assign(n_bodies + 1, 0);
+  c->scol_off.clear();
+  c->sconn = nullptr;
+  c->sk = c->sil0 = nullptr;
+  c->sclist = nullptr;
 
   // colouring, then per-(body, colour) element lists
   std::vector<int32_t> colour((size_t)n_e);
@@ -789,8 +827,110 @@ isb_status isb_vjp_params(isb_ctx* c, isb_stream stream, const double* w, const 
   const DevScene dsc = devscene(c);
   if (a_bar || mu_bar || lam_bar || kf_bar)
     launch_elem_vjp(m, dsc, ERange{0, c->n_e, nullptr}, w, x1, a, a_bar, mu_bar, lam_bar, kf_bar, s);
+  if (a_bar && c->n_s > 0)
+    launch_spring_vjp(c->dim, devsprings(c), dsc, ERange{0, c->n_s, nullptr}, w, x1, a + c->n_e, a_bar + c->n_e,
+                      nullptr, s);
   launch_vertex_vjp(m, dsc, 0, c->n_v, w, x1, x0, dsc.be ? v1_bar : nullptr, x0_bar, v0_bar, s);
   ISB_HIP(hipGetLastError());
+  return ISB_OK;
+}
+
+isb_status isb_vjp_spring_stiffness(isb_ctx* c, isb_stream stream, const double* w, const double* x1,
+                                    const double* a, double* k_bar) {
+  clear_error();
+  ISB_TRY(check_ctx(c, true));
+  if (!w || !x1 || !a || !k_bar) return fail(ISB_E_ARG, "NULL vjp argument");
+  launch_spring_vjp(c->dim, devsprings(c), devscene(c), ERange{0, c->n_s, nullptr}, w, x1, a + c->n_e, nullptr, k_bar,
+                    (hipStream_t)stream);
+  ISB_HIP(hipGetLastError());
+  return ISB_OK;
+}
+
+isb_status isb_spring_upload(isb_ctx* c, int64_t n_s, const int64_t* body_s_off, const int32_t* pairs,
+                             const double* k) {
+  clear_error();
+  if (!c) return fail(ISB_E_ARG, "NULL context");
+  if (!c->have_mesh) return fail(ISB_E_STATE, "isb_spring_upload needs the mesh first");
+  if (n_s < 0 || n_s > INT32_MAX / 2) return fail(ISB_E_ARG, "spring count out of range");
+  if (n_s > 0 && (!pairs || !k)) return fail(ISB_E_ARG, "NULL spring array");
+  const int nb = c->n_bodies;
+  std::vector<int64_t> soff(nb + 1, 0);
+  if (body_s_off) {
+    soff.assign(body_s_off, body_s_off + nb + 1);
+  } else if (nb == 1) {
+    soff[1] = n_s;
+  } else {
+    return fail(ISB_E_ARG, "body_s_off is required with several bodies");
+  }
+  if (soff[0] != 0 || soff[nb] != n_s) return fail(ISB_E_ARG, "body_s_off must run from 0 to n_s");
+  for (int b = 0; b < nb; ++b)
+    if (soff[b + 1] < soff[b]) return fail(ISB_E_ARG, "body_s_off must be non-decreasing");
+  // rest lengths from the uploaded rest positions
+  const int D = c->dim;
+  std::vector<double> X((size_t)c->n_v * D);
+  ISB_HIP(hipSetDevice(c->device));
+  ISB_HIP(hipMemcpy(X.data(), c->X, X.size() * sizeof(double), hipMemcpyDeviceToHost));
+  std::vector<int32_t> connh((size_t)2 * n_s);
+  std::vector<double> il0((size_t)n_s);
+  for (int b = 0; b < nb; ++b)
+    for (int64_t s = soff[b]; s < soff[b + 1]; ++s) {
+      const int32_t i = pairs[2 * s], j = pairs[2 * s + 1];
+      if (i < c->voff[b] || i >= c->voff[b + 1] || j < c->voff[b] || j >= c->voff[b + 1])
+        return fail(ISB_E_MESH, "spring " + std::to_string(s) + " joins vertices outside its body");
+      if (i == j) return fail(ISB_E_MESH, "spring " + std::to_string(s) + " joins a vertex to itself");
+      if (!std::isfinite(k[s]) || k[s] < 0.0)
+        return fail(ISB_E_ARG, "spring " + std::to_string(s) + " needs a finite stiffness >= 0");
+      double l2 = 0.0;
+      for (int r = 0; r < D; ++r) {
+        const double d = X[(size_t)j * D + r] - X[(size_t)i * D + r];
+        l2 += d * d;
+      }
+      if (!(l2 > 0.0)) return fail(ISB_E_MESH, "spring " + std::to_string(s) + " has zero rest length");
+      il0[s] = 1.0 / std::sqrt(l2);
+      connh[s] = i;
+      connh[(size_t)n_s + s] = j;
+    }
+  // colouring (pairs are elements of two vertices), then per-(body, colour) lists
+  std::vector<int32_t> colour((size_t)n_s);
+  int32_t nc = 0;
+  if (n_s > 0) ISB_TRY(colour_elements(1, c->n_v, n_s, pairs, colour.data(), &nc));
+  const int nc1 = nc + 1;
+  std::vector<int32_t> scol_off((size_t)nb * nc1, 0), sclist((size_t)n_s);
+  {
+    int32_t pos = 0;
+    for (int b = 0; b < nb; ++b) {
+      std::vector<int32_t> start(nc, 0), count(nc, 0);
+      for (int64_t s = soff[b]; s < soff[b + 1]; ++s) count[colour[s]]++;
+      for (int q = 0; q < nc; ++q) {
+        scol_off[b * nc1 + q] = pos;
+        start[q] = pos;
+        pos += count[q];
+      }
+      scol_off[b * nc1 + nc] = pos;
+      for (int64_t s = soff[b]; s < soff[b + 1]; ++s) sclist[start[colour[s]]++] = (int32_t)s;
+    }
+  }
+  batched_release(c);
+  c->free_list(c->spring_allocs);
+  c->sconn = nullptr;
+  c->sk = c->sil0 = nullptr;
+  c->sclist = nullptr;
+  c->n_s = 0;
+  if (n_s > 0) {
+    auto& L = c->spring_allocs;
+    ISB_TRY(dalloc(L, &c->sconn, (size_t)2 * n_s));
+    ISB_TRY(dalloc(L, &c->sk, (size_t)n_s));
+    ISB_TRY(dalloc(L, &c->sil0, (size_t)n_s));
+    ISB_TRY(dalloc(L, &c->sclist, (size_t)n_s));
+    ISB_HIP(hipMemcpy(c->sconn, connh.data(), connh.size() * 4, hipMemcpyHostToDevice));
+    ISB_HIP(hipMemcpy(c->sk, k, (size_t)n_s * 8, hipMemcpyHostToDevice));
+    ISB_HIP(hipMemcpy(c->sil0, il0.data(), (size_t)n_s * 8, hipMemcpyHostToDevice));
+    ISB_HIP(hipMemcpy(c->sclist, sclist.data(), (size_t)n_s * 4, hipMemcpyHostToDevice));
+  }
+  c->n_s = (int)n_s;
+  c->n_scolours = nc;
+  c->soff = soff;
+  c->scol_off = scol_off;
   return ISB_OK;
 }
 

@@ -39,6 +39,9 @@ struct BatchedState {
   float* Dv = nullptr;                  // FP32 Jacobi preconditioner
   void* vdT = nullptr;                  // vertex-term diagonal, element precision
   uint16_t* lconn = nullptr;            // body-local connectivity
+  int32_t* soff = nullptr;              // springs per body
+  uint16_t* slconn = nullptr;           // body-local spring ends
+  void* Sbuf = nullptr;                 // per-spring block K in the element precision
   int nacc = 0, grid = 0, block = 0, precision = -1, dim = 0;
   size_t lds = 0;
 };
@@ -94,7 +97,8 @@ static constexpr double kBodyFixedCost = 1152.0;
 
 // Longest-processing-time schedule: bodies in decreasing cost go, one at a time, to the
 // workgroup with the least load so far (ties to the lowest index). Workgroup g solves
-// order[wg_off[g] .. wg_off[g+1]) in that order.
+// order[wg_off[g] .. wg_off[g+1]) in that order. eoff: cumulative work items (elements and
+// springs) per body.
 static void lpt_schedule(const std::vector<int32_t>& eoff, int nb, int G, std::vector<int32_t>& order,
                          std::vector<int32_t>& wg_off) {
   std::vector<int32_t> byc(nb);
@@ -154,7 +158,11 @@ isb_status batched_prepare(isb_ctx* c) {
     voff[b] = (int32_t)c->voff[b];
     eoff[b] = (int32_t)c->eoff[b];
   }
-  lpt_schedule(eoff, nb, st->grid, order, wg_off);
+  {
+    std::vector<int32_t> work(nb + 1);
+    for (int b = 0; b <= nb; ++b) work[b] = eoff[b] + (int32_t)c->soff[b];
+    lpt_schedule(work, nb, st->grid, order, wg_off);
+  }
   auto alloc = [&](void** p, size_t bytes) -> isb_status {
     ISB_HIP(hipMalloc(p, bytes));
     st->allocs.push_back(*p);
@@ -168,8 +176,28 @@ isb_status batched_prepare(isb_ctx* c) {
   if ((r = alloc((void**)&st->stats, nb * sizeof(DevStats))) != ISB_OK) return r;
   const size_t fwords = (size_t)hv_state_words(c->dim) * (size_t)c->n_e;
   if ((r = alloc(&st->Fbuf, fwords * (c->precision == ISB_MIXED ? 4 : 8))) != ISB_OK) return r;
-  if ((r = alloc((void**)&st->E0, (size_t)c->n_e * sizeof(double))) != ISB_OK) return r;
-  if ((r = alloc((void**)&st->E1, (size_t)c->n_e * sizeof(double))) != ISB_OK) return r;
+  const size_t nterms = (size_t)c->n_e + (size_t)c->n_s;
+  if ((r = alloc((void**)&st->E0, nterms * sizeof(double))) != ISB_OK) return r;
+  if ((r = alloc((void**)&st->E1, nterms * sizeof(double))) != ISB_OK) return r;
+  if (c->n_s > 0) {
+    const size_t ns = (size_t)c->n_s;
+    if ((r = alloc(&st->Sbuf, (size_t)spring_state_words(c->dim) * ns * (c->precision == ISB_MIXED ? 4 : 8))) != ISB_OK)
+      return r;
+    if ((r = alloc((void**)&st->soff, (nb + 1) * 4)) != ISB_OK) return r;
+    if ((r = alloc((void**)&st->slconn, 2 * ns * sizeof(uint16_t))) != ISB_OK) return r;
+    std::vector<int32_t> sconn(2 * ns), soff(nb + 1);
+    ISB_HIP(hipMemcpy(sconn.data(), c->sconn, 2 * ns * sizeof(int32_t), hipMemcpyDeviceToHost));
+    std::vector<uint16_t> loc(2 * ns);
+    for (int b = 0; b < nb; ++b) {
+      soff[b] = (int32_t)c->soff[b];
+      for (int k = 0; k < 2; ++k)
+        for (int64_t q = c->soff[b]; q < c->soff[b + 1]; ++q)
+          loc[(size_t)k * ns + q] = (uint16_t)(sconn[(size_t)k * ns + q] - voff[b]);
+    }
+    soff[nb] = (int32_t)c->soff[nb];
+    ISB_HIP(hipMemcpy(st->slconn, loc.data(), 2 * ns * sizeof(uint16_t), hipMemcpyHostToDevice));
+    ISB_HIP(hipMemcpy(st->soff, soff.data(), (nb + 1) * 4, hipMemcpyHostToDevice));
+  }
   const size_t ndof = (size_t)c->n_v * c->dim;
   if ((r = alloc((void**)&st->Dv, ndof * sizeof(float))) != ISB_OK) return r;
   if ((r = alloc(&st->vdT, ndof * (c->precision == ISB_MIXED ? 4 : 8))) != ISB_OK) return r;
@@ -226,6 +254,12 @@ static BatchArgs make_args(isb_ctx* c, BatchedState* st) {
   A.Fbuf = st->Fbuf;
   A.E0 = st->E0;
   A.E1 = st->E1;
+  A.n_s = c->n_s;
+  A.soff = st->soff;
+  A.slconn = st->slconn;
+  A.sk = c->sk;
+  A.sil0 = c->sil0;
+  A.Sbuf = st->Sbuf;
   return A;
 }
 

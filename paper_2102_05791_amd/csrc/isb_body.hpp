@@ -20,6 +20,7 @@
 #include "isb_device.hpp"
 #include "isb_elem.hpp"
 #include "isb_internal.hpp"
+#include "isb_spring.hpp"
 
 namespace isb {
 
@@ -53,7 +54,14 @@ struct BatchArgs {
   int nacc;       // LDS accumulator length: the largest body's DOF count
   void* Fbuf;     // [hv_state_words(D)][n_e] per-element Hessian-vector state at the current Newton
                   // iterate, in the element precision (see BodySolver::store_hv_state)
-  double *E0, *E1;  // [n_e] per-element energies at the iterate and at the line-search trial
+  double *E0, *E1;  // [n_e + n_s] per-element, then per-spring, energies at the iterate and at the
+                    // line-search trial
+  // vertex-pair springs (Eq. 2 between two vertices); n_s = 0 without springs
+  const int32_t* soff;     // [n_bodies+1] springs of each body
+  const uint16_t* slconn;  // [2][n_s] body-local end vertices i, j
+  const double *sk, *sil0; // [n_s] stiffness, 1 / rest length
+  void* Sbuf;              // [spring_state_words(D)][n_s] spring block K at the iterate, element precision
+  int n_s;
 };
 
 // Reduction slots: two banks of up to 16 waves x 4 values. Consecutive workgroup reductions use
@@ -164,7 +172,8 @@ struct BodySolver {
                 // differences of it), the diagonal accumulator of trial(); zero outside both
   int v0, v1, e0, e1, n, base;
 
-  int rbank = 0;  // bank of the last workgroup reduction
+  int rbank = 0;       // bank of the last workgroup reduction
+  int s0 = 0, s1 = 0;  // the body's springs
 
   __device__ __forceinline__ T* Fb() const { return reinterpret_cast<T*>(A.Fbuf); }
 
@@ -214,6 +223,30 @@ struct BodySolver {
       return A.a[e];
     else
       return A.a32[e];
+  }
+
+  // -------- springs: FP64 terms (isb_spring.hpp); the block K is rounded once to T --------
+  static constexpr int kSW = spring_state_words(D);
+  __device__ __forceinline__ T* Sb() const { return reinterpret_cast<T*>(A.Sbuf); }
+  __device__ __forceinline__ void spring_ends(int s, int& i, int& j) const {
+    i = (int)A.slconn[s];
+    j = (int)A.slconn[(size_t)A.n_s + s];
+  }
+  // +y at vertex j and -y at vertex i (both_plus: +y at both) into the LDS array dst
+  __device__ __forceinline__ void spring_lds(double* dst, int i, int j, const double y[D], bool both_plus) const {
+#pragma unroll
+    for (int r = 0; r < D; ++r) {
+      unsafeAtomicAdd(dst + lv(j, r), sc.s_pot * y[r]);
+      unsafeAtomicAdd(dst + lv(i, r), both_plus ? sc.s_pot * y[r] : -sc.s_pot * y[r]);
+    }
+  }
+  // stores the block K of a spring and returns its diagonal (each end receives it)
+  __device__ __forceinline__ void store_spring_state(int s, const SpringTerms<D>& S, double dg[D]) const {
+    double K[kSW];
+    spring_block<D>(S, K);
+#pragma unroll
+    for (int w = 0; w < kSW; ++w) Sb()[(size_t)w * A.n_s + s] = T(K[w]);
+    spring_diag<D>(S, dg);
   }
 
   // Hessian-vector pass: the per-element state streams in coalesced, p comes from LDS. Edge
@@ -281,6 +314,27 @@ struct BodySolver {
 #pragma unroll
         for (int c = 0; c < D; ++c) o[k][c] = double(out[k][c]);
       lds_scatter(v, o, sc.s_pot);
+    }
+    for (int s = s0 + threadIdx.x; s < s1; s += blockDim.x) {
+      int i, j;
+      spring_ends(s, i, j);
+      T K[kSW];
+#pragma unroll
+      for (int w = 0; w < kSW; ++w) K[w] = Sb()[(size_t)w * A.n_s + s];
+      double u64[D], y64[D];
+      T u[D], y[D];
+#pragma unroll
+      for (int r = 0; r < D; ++r) {
+        u64[r] = ps[lv(j, r)] - ps[lv(i, r)];
+        u[r] = T(u64[r]);
+      }
+      spring_block_apply<D, T>(K, u, y);
+#pragma unroll
+      for (int r = 0; r < D; ++r) {
+        y64[r] = double(y[r]);
+        php += y64[r] * u64[r];
+      }
+      spring_lds(acc, i, j, y64, false);
     }
     return sc.s_pot * php;
   }
@@ -366,6 +420,18 @@ struct BodySolver {
       store_hv_state(e, R64, S64, ae, od);
       lds_scatter(v, od, sc.s_pot);
     }
+    for (int s = s0 + threadIdx.x; s < s1; s += blockDim.x) {
+      int i, j;
+      spring_ends(s, i, j);
+      double d[D];
+#pragma unroll
+      for (int r = 0; r < D; ++r) d[r] = x[(size_t)(v0 + j) * D + r] - x[(size_t)(v0 + i) * D + r];
+      SpringTerms<D> S;
+      spring_terms<D>(d, A.sk[s], A.sil0[s], A.a[m.n_e + s], S);
+      double dg[D];
+      store_spring_state(s, S, dg);
+      spring_lds(acc, i, j, dg, true);
+    }
   }
 
   // -------- vertex terms per DOF, from values already in registers --------
@@ -450,6 +516,36 @@ struct BodySolver {
       for (int k = 0; k <= D; ++k)
 #pragma unroll
         for (int c = 0; c < D; ++c) unsafeAtomicAdd(acc2 + lv(v[k] - v0, c), sc.s_pot * o[k][c]);
+    }
+    // springs: energy difference, gradient, block K and diagonal, as for the elements; the trial
+    // point of each end is formed per DOF exactly as the vertex loop below forms it
+    for (int s = s0 + threadIdx.x; s < s1; s += blockDim.x) {
+      int i, j;
+      spring_ends(s, i, j);
+      const double ks = A.sk[s], il0 = A.sil0[s], as = A.a[m.n_e + s];
+      const double estored = Ecur ? Ecur[m.n_e + s] : 0.0;
+      double d[D];
+#pragma unroll
+      for (int r = 0; r < D; ++r) {
+        const size_t gi = (size_t)(v0 + i) * D + r, gj = (size_t)(v0 + j) * D + r;
+        const double xi = dxp ? x[gi] + alpha * dxp[gi] : x[gi];
+        const double xj = dxp ? x[gj] + alpha * dxp[gj] : x[gj];
+        d[r] = xj - xi;
+      }
+      SpringTerms<D> S;
+      spring_terms<D>(d, ks, il0, as, S);
+      const double eb = sc.s_pot * spring_energy<D>(S, ks);
+      const double ea = Ecur ? estored : eb;
+      sd += eb - ea;
+      sa += fabs(ea);
+      st += eb;
+      double y[D];
+#pragma unroll
+      for (int r = 0; r < D; ++r) y[r] = S.f * S.n[r];
+      spring_lds(acc, i, j, y, false);
+      Enew[m.n_e + s] = eb;
+      store_spring_state(s, S, y);
+      spring_lds(acc2, i, j, y, true);
     }
     __syncthreads();
     // vertex terms, kV vertices per thread at a time: energies at x and xt, then per DOF the
@@ -874,6 +970,10 @@ __device__ void batched_body(const DevMesh& m, const DevScene& sc, const BatchAr
     const int bv0 = wg_uniform(A.voff[body]), bv1 = wg_uniform(A.voff[body + 1]);
     const int be0 = wg_uniform(A.eoff[body]), be1 = wg_uniform(A.eoff[body + 1]);
     BodySolver<D, T> S{m, sc, A, acc, red, ps, bv0, bv1, be0, be1, (bv1 - bv0) * D, bv0 * D};
+    if (A.n_s > 0) {
+      S.s0 = wg_uniform(A.soff[body]);
+      S.s1 = wg_uniform(A.soff[body + 1]);
+    }
     DevStats st;
     memset(&st, 0, sizeof(st));
     if (MODE == 0)

@@ -42,6 +42,16 @@ struct isb_ctx {
   std::vector<int32_t> body_patch_off;
   isb::PatchPlan plan{};
 
+  // vertex-pair springs (isb_spring_upload); body b owns springs [soff[b], soff[b+1]); colour k of
+  // body b is sclist[scol_off[b*(nsc+1)+k] .. +1) as for the elements
+  int n_s = 0, n_scolours = 0;
+  std::vector<int64_t> soff;
+  std::vector<int32_t> scol_off;
+  std::vector<void*> spring_allocs;  // freed on spring or mesh re-upload / destroy
+  int32_t* sconn = nullptr;          // [2][n_s]
+  double *sk = nullptr, *sil0 = nullptr;
+  int32_t* sclist = nullptr;
+
   isb_scene scene{};
 
   // options
@@ -70,6 +80,7 @@ namespace isb {
 
 DevMesh devmesh(const isb_ctx* c);
 DevScene devscene(const isb_ctx* c);
+DevSprings devsprings(const isb_ctx* c);
 
 // batched persistent solver (isb_batched.hip)
 isb_status batched_prepare(isb_ctx* c);

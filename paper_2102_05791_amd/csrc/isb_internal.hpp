@@ -29,6 +29,14 @@ struct DevMesh {
   const uint8_t* pinned;
 };
 
+// Vertex-pair springs, SoA over the caller's spring order:
+//   conn [2][n_s] int32 end vertices i, j (global ids), k [n_s] stiffness, il0 [n_s] 1 / rest length
+struct DevSprings {
+  int n_s;
+  const int32_t* conn;
+  const double *k, *il0;
+};
+
 struct DevScene {
   int be;          // 1 = backward Euler, 0 = quasistatic
   double h;        // time step
@@ -121,6 +129,17 @@ void launch_to_f32(int n, const double* src, float* dst, hipStream_t s);
 void launch_elem_patch(const DevMesh& m, const DevScene& sc, const PatchPlan& P, int p0, int p1, int op,
                        int precision, const double* x, const double* a, const float* a32, const double* p,
                        double* out, const int* done, hipStream_t s);
+
+// ---- spring kernels (isb_springs.hip): spring range r (ids through r.list when given); as = the
+// springs' actions (the action vector past the elements' entries); op = PatchOp; FP64 throughout ----
+void launch_spring_op(int dim, const DevSprings& sp, const DevScene& sc, ERange r, bool atomic, int op,
+                      const double* x, const double* as, const double* p, double* out, const int* done,
+                      hipStream_t s);
+void launch_spring_energy(int dim, const DevSprings& sp, const DevScene& sc, ERange r, const double* x,
+                          const double* dx, double alpha, const double* as, double* partials, int part_off,
+                          hipStream_t s, int* nblocks_out);
+void launch_spring_vjp(int dim, const DevSprings& sp, const DevScene& sc, ERange r, const double* w,
+                       const double* x1, const double* as, double* a_bar, double* k_bar, hipStream_t s);
 
 // ---- reductions and CG vector kernels (vectors of length n, pointers already offset) ----
 // partial sums of ncomp products per block; finalize into out[0..ncomp)

@@ -28,7 +28,7 @@ EXPORTED = ("isb_create", "isb_destroy", "isb_last_error", "isb_version", "isb_v
             "isb_colour_elements", "isb_mesh_upload", "isb_material_upload", "isb_set_scene",
             "isb_set_option", "isb_get_option", "isb_get_mass", "isb_step", "isb_solve_adjoint",
             "isb_vjp_params", "isb_energy", "isb_gradient", "isb_hessvec", "isb_hessvec_elements",
-            "isb_hessdiag", "isb_stream_copy")
+            "isb_hessdiag", "isb_stream_copy", "isb_spring_upload", "isb_vjp_spring_stiffness")
 
 
 class IsbError(RuntimeError):
@@ -105,6 +105,8 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
         "isb_hessvec_elements": [vp, vp, vp, vp, vp, vp],
         "isb_hessdiag": [vp, vp, vp, vp, vp, vp],
         "isb_stream_copy": [vp, vp, vp, i64],
+        "isb_spring_upload": [vp, i64, vp, vp, vp],
+        "isb_vjp_spring_stiffness": [vp, vp, vp, vp, vp, vp],
     }
     for name, argtypes in sigs.items():
         f = getattr(lib, name)
@@ -187,7 +189,7 @@ class Context:
         self.h = h
         self.device = device
         self.precision = prec
-        self.dim = self.n_v = self.n_e = self.n_bodies = 0
+        self.dim = self.n_v = self.n_e = self.n_bodies = self.n_s = 0
         self.scene = None
 
     def __del__(self):
@@ -210,6 +212,28 @@ class Context:
         _check(self.lib, self.lib.isb_mesh_upload(self.h, int(dim), len(vo) - 1, pvo, peo, pX, pT, pP))
         self.dim, self.n_v, self.n_e, self.n_bodies = int(dim), X.shape[0], T.shape[0], len(vo) - 1
         self.body_v_off, self.body_e_off = vo.copy(), eo.copy()
+        self.n_s = 0
+
+    def spring_upload(self, pairs, k, body_s_off=None):
+        """isb_spring_upload: vertex-pair springs (i, j) = pairs[s] with stiffness k[s]; their actions
+        follow the elements' in every action vector, which then has n_e + n_s entries."""
+        S, pS = _host(np.asarray(pairs).reshape(-1, 2), np.int32)
+        K, pK = _host(k, np.float64)
+        if K.shape != (S.shape[0],):
+            raise ValueError("one stiffness per spring")
+        so, pso = (None, None) if body_s_off is None else _host(body_s_off, np.int64)
+        _check(self.lib, self.lib.isb_spring_upload(self.h, S.shape[0], pso, pS, pK))
+        self.n_s = S.shape[0]
+
+    @property
+    def n_act(self):
+        """Length of an action vector: one per element, then one per spring."""
+        return self.n_e + self.n_s
+
+    def _a(self, a, name="a"):
+        if a.numel() != self.n_act:
+            raise ValueError(f"{name} must have n_e + n_s = {self.n_act} entries, got {a.numel()}")
+        return _dev(a, name)
 
     def material_upload(self, mu, lam, kf, fdir, rho, scene: dict):
         arrs = [_host(a, np.float64) for a in (mu, lam, kf, fdir, rho)]
@@ -236,6 +260,8 @@ class Context:
         ctx.set_option(OPT_SCATTER, scatter)
         ctx.mesh_upload(w.dim, w.X, w.T, w.pinned, w.body_v_off, w.body_e_off)
         ctx.material_upload(w.mu, w.lam, w.kf, w.fdir, w.rho, w.scene)
+        if getattr(w, "S", None) is not None and len(w.S) > 0:
+            ctx.spring_upload(w.S, w.ks, w.body_s_off)
         ctx.set_option(OPT_SOLVER, solver)
         return ctx
 
@@ -261,7 +287,7 @@ class Context:
             v1 = self._empty(self.n_v, self.dim)
         sb = self._stats_buf(stats)
         allow = (ISB_E_NOT_CONVERGED,) if allow_not_converged else ()
-        st = _check(self.lib, self.lib.isb_step(self.h, _stream(), _dev(x0, "x0"), _dev(v0, "v0"), _dev(a, "a"),
+        st = _check(self.lib, self.lib.isb_step(self.h, _stream(), _dev(x0, "x0"), _dev(v0, "v0"), self._a(a),
                                                 _dev(x1, "x1"), _dev(v1, "v1") if be else None, sb), allow)
         return x1, (v1 if be else None), ([s.as_dict() for s in sb] if sb is not None else None), st
 
@@ -271,46 +297,54 @@ class Context:
         sb = self._stats_buf(stats)
         allow = (ISB_E_NOT_CONVERGED,) if allow_not_converged else ()
         st = _check(self.lib, self.lib.isb_solve_adjoint(self.h, _stream(), _dev(x1, "x1"), _dev(x0, "x0"),
-                                                         _dev(a, "a"), _dev(x1_bar, "x1_bar"),
+                                                         self._a(a), _dev(x1_bar, "x1_bar"),
                                                          _dev(v1_bar, "v1_bar"), _dev(w, "w"), sb), allow)
         return w, ([s.as_dict() for s in sb] if sb is not None else None), st
 
     def vjp_params(self, w, x1, x0, a, v1_bar=None, want=("a_bar", "x0_bar", "v0_bar", "mu_bar", "lam_bar",
                                                           "kf_bar")):
         """isb_vjp_params. Returns a dict of the requested cotangents."""
-        out = {}
-        for k in ("a_bar", "mu_bar", "lam_bar", "kf_bar"):
+        out = {"a_bar": self._empty(self.n_act) if "a_bar" in want else None}
+        for k in ("mu_bar", "lam_bar", "kf_bar"):
             out[k] = self._empty(self.n_e) if k in want else None
         for k in ("x0_bar", "v0_bar"):
             out[k] = self._empty(self.n_v, self.dim) if k in want else None
         _check(self.lib, self.lib.isb_vjp_params(
-            self.h, _stream(), _dev(w), _dev(x1), _dev(x0), _dev(a), _dev(v1_bar), _dev(out["a_bar"]),
+            self.h, _stream(), _dev(w), _dev(x1), _dev(x0), self._a(a), _dev(v1_bar), _dev(out["a_bar"]),
             _dev(out["x0_bar"]), _dev(out["v0_bar"]), _dev(out["mu_bar"]), _dev(out["lam_bar"]),
             _dev(out["kf_bar"])))
         return {k: v for k, v in out.items() if v is not None}
 
+    def vjp_spring_stiffness(self, w, x1, a):
+        """isb_vjp_spring_stiffness: k_bar [n_s] = -w^T dG/dk at x1."""
+        kb = self._empty(self.n_s)
+        if self.n_s:
+            _check(self.lib, self.lib.isb_vjp_spring_stiffness(self.h, _stream(), _dev(w), _dev(x1), self._a(a),
+                                                               _dev(kb)))
+        return kb
+
     # ---- single evaluations ----
     def energy(self, x, x0, v0, a):
         e = self._empty(self.n_bodies)
-        _check(self.lib, self.lib.isb_energy(self.h, _stream(), _dev(x), _dev(x0), _dev(v0), _dev(a), _dev(e)))
+        _check(self.lib, self.lib.isb_energy(self.h, _stream(), _dev(x), _dev(x0), _dev(v0), self._a(a), _dev(e)))
         return e
 
     def gradient(self, x, x0, v0, a):
         g = self._empty(self.n_v, self.dim)
-        _check(self.lib, self.lib.isb_gradient(self.h, _stream(), _dev(x), _dev(x0), _dev(v0), _dev(a), _dev(g)))
+        _check(self.lib, self.lib.isb_gradient(self.h, _stream(), _dev(x), _dev(x0), _dev(v0), self._a(a), _dev(g)))
         return g
 
     def hessvec(self, x, x0, a, p):
         hp = self._empty(self.n_v, self.dim)
-        _check(self.lib, self.lib.isb_hessvec(self.h, _stream(), _dev(x), _dev(x0), _dev(a), _dev(p), _dev(hp)))
+        _check(self.lib, self.lib.isb_hessvec(self.h, _stream(), _dev(x), _dev(x0), self._a(a), _dev(p), _dev(hp)))
         return hp
 
     def hessvec_elements(self, x, a, p, hp):
         """isb_hessvec_elements: hp += element part of H(x) p (no vertex terms, no projection)."""
-        _check(self.lib, self.lib.isb_hessvec_elements(self.h, _stream(), _dev(x), _dev(a), _dev(p), _dev(hp)))
+        _check(self.lib, self.lib.isb_hessvec_elements(self.h, _stream(), _dev(x), self._a(a), _dev(p), _dev(hp)))
         return hp
 
     def hessdiag(self, x, x0, a):
         d = self._empty(self.n_v, self.dim)
-        _check(self.lib, self.lib.isb_hessdiag(self.h, _stream(), _dev(x), _dev(x0), _dev(a), _dev(d)))
+        _check(self.lib, self.lib.isb_hessdiag(self.h, _stream(), _dev(x), _dev(x0), self._a(a), _dev(d)))
         return d

@@ -17,7 +17,7 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 CSRC = os.path.join(ROOT, "paper_2102_05791_amd", "csrc")
 OUT = os.path.join(HERE, "_build", "libisb_emu.so")
 SRCS = [os.path.join(HERE, "batched_emu.cpp"), os.path.join(CSRC, "isb_body.hpp"),
-        os.path.join(CSRC, "isb_elem.hpp"), os.path.join(CSRC, "isb_device.hpp"),
+        os.path.join(CSRC, "isb_elem.hpp"), os.path.join(CSRC, "isb_device.hpp"), os.path.join(CSRC, "isb_spring.hpp"),
         os.path.join(HERE, "include", "hip", "hip_runtime.h")]
 
 vp, ci, cd = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
@@ -38,7 +38,8 @@ class BatchArgs(ctypes.Structure):
                 ("x0", vp), ("v0", vp), ("a", vp), ("a32", vp), ("x1", vp), ("v1", vp), ("xbar", vp),
                 ("vbar", vp), ("w", vp), ("xhat", vp), ("G", vp), ("Gt", vp), ("dx", vp), ("r", vp), ("cv", vp),
                 ("xt", vp), ("Dv", vp), ("vdT", vp), ("lconn", vp), ("stats", vp), ("tol", cd), ("adj_tol", cd),
-                ("max_newton", ci), ("max_cg", ci), ("want_tail", ci), ("nacc", ci), ("Fbuf", vp), ("E0", vp), ("E1", vp)]
+                ("max_newton", ci), ("max_cg", ci), ("want_tail", ci), ("nacc", ci), ("Fbuf", vp), ("E0", vp), ("E1", vp),
+                ("soff", vp), ("slconn", vp), ("sk", vp), ("sil0", vp), ("Sbuf", vp), ("n_s", ci)]
 
 
 STATS_DTYPE = np.dtype([("newton_iters", "<i4"), ("cg_iters", "<i4"), ("adj_cg_iters", "<i4"),
@@ -122,8 +123,18 @@ class EmuBatch:
         self.cv = k(np.zeros(w.n_v))
         self.stats = k(np.zeros(nb, dtype=STATS_DTYPE))
         self.Fbuf = k(np.zeros((10 if d == 2 else d * d + d) * w.n_e, dtype=np.float64))  # hv_state_words
-        self.E0 = k(np.zeros(w.n_e))
-        self.E1 = k(np.zeros(w.n_e))
+        n_s = getattr(w, "n_s", 0)
+        self.n_s = n_s
+        self.E0 = k(np.zeros(w.n_e + n_s))
+        self.E1 = k(np.zeros(w.n_e + n_s))
+        if n_s:
+            S = w.S.astype(np.int64)
+            sbody = np.repeat(np.arange(nb), np.diff(w.body_s_off))
+            self.soff = k(w.body_s_off.astype(np.int32))
+            self.slconn = k((S.T - w.body_v_off[sbody][None, :]).astype(np.uint16))
+            self.sk = k(w.ks.astype(np.float64))
+            self.sil0 = k(1.0 / np.linalg.norm(X[S[:, 1]] - X[S[:, 0]], axis=1))
+            self.Sbuf = k(np.zeros(d * (d + 1) // 2 * n_s, dtype=np.float64))  # spring_state_words
         self.be = be
 
     def _args(self, **kw):
@@ -141,6 +152,10 @@ class EmuBatch:
         A.nacc = self.nacc
         A.Fbuf = _p(self.Fbuf)
         A.E0, A.E1 = _p(self.E0), _p(self.E1)
+        A.n_s = self.n_s
+        if self.n_s:
+            A.soff, A.slconn, A.sk, A.sil0, A.Sbuf = (_p(self.soff), _p(self.slconn), _p(self.sk), _p(self.sil0),
+                                                      _p(self.Sbuf))
         for key, val in kw.items():
             setattr(A, key, val)
         return A

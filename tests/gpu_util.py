@@ -39,6 +39,33 @@ def rand_workload(dim, seed=0, integrator="be", pinned_left=False, bodies=1, sha
     return w, rng
 
 
+def with_springs(w, rng, frac=0.5, extra=4, ks_scale=1.0):
+    """The workload plus vertex-pair springs in every body: the first edge of a random `frac` of its
+    elements (distinct pairs) and `extra` random pairs of its vertices (longer reaches), stiffness
+    ~ U(0.5, 1.5) E (E = the elements' mean fibre stiffness), spring actions ~ U(0.7, 1) appended
+    to every step's actions."""
+    S, soff = [], [0]
+    E = float(np.mean(w.kf)) if np.mean(w.kf) > 0 else 1e4
+    for b in range(w.n_bodies):
+        v0, v1 = int(w.body_v_off[b]), int(w.body_v_off[b + 1])
+        e0, e1 = int(w.body_e_off[b]), int(w.body_e_off[b + 1])
+        pick = rng.choice(np.arange(e0, e1), size=max(1, int(frac * (e1 - e0))), replace=False)
+        pairs = {tuple(sorted((int(w.T[e, 0]), int(w.T[e, 1])))) for e in pick}
+        while len(pairs) < len(pick) + extra:
+            i, j = rng.integers(v0, v1, size=2)
+            if i != j:
+                pairs.add((int(i), int(j)))
+        pairs = sorted(pairs)
+        S.extend(pairs)
+        soff.append(len(S))
+    S = np.asarray(S, np.int32)
+    ks = ks_scale * E * rng.uniform(0.5, 1.5, size=S.shape[0])
+    acts = np.concatenate([w.actions, rng.uniform(0.7, 1.0, size=(w.actions.shape[0], S.shape[0]))], axis=1)
+    return Workload(w.name + "+springs", w.dim, w.X, w.T, w.pinned, w.mu, w.lam, w.kf, w.fdir, w.rho, w.scene,
+                    w.x0, w.v0, acts, w.body_v_off, w.body_e_off, S=S, ks=ks,
+                    body_s_off=np.asarray(soff, np.int64))
+
+
 def problems(w):
     """Oracle Problem per body."""
     return [Problem.from_workload(w.body(b)) for b in range(w.n_bodies)]
@@ -46,10 +73,15 @@ def problems(w):
 
 def abs_assembly(prob: Problem, x, x0, v0, a):
     """|contributions| assembled per DOF: the scale of the gradient's rounding (A17-style measure)."""
+    ae, as_ = prob.split(a)
     F = prob.mesh.F(x)
-    cg = np.abs(fem.corner_grads(prob.mesh, fem.stress(F, prob.mu, prob.lam, prob.kf, a, prob.fd)))
+    cg = np.abs(fem.corner_grads(prob.mesh, fem.stress(F, prob.mu, prob.lam, prob.kf, ae, prob.fd)))
     G = np.zeros_like(x)
     np.add.at(G, prob.mesh.T, cg)
+    if prob.n_s:
+        n, _, _, f = fem.spring_force_terms(x, prob.S, prob.ks, prob.l0, as_)
+        np.add.at(G, prob.S[:, 0], np.abs(f[:, None] * n))
+        np.add.at(G, prob.S[:, 1], np.abs(f[:, None] * n))
     G = prob.s_pot * (G + np.abs(prob.vertex_grad(x, x0)))
     if prob.be:
         G += np.abs(prob.mesh.mass[:, None] * (x - prob.x_hat(x0, v0)))

@@ -5,7 +5,8 @@ import numpy as np
 import pytest
 
 from oracle import solve
-from tests.gpu_util import problems, rand_workload, rel
+from oracle.fem import Problem
+from tests.gpu_util import problems, rand_workload, rel, with_springs
 
 
 @pytest.fixture(scope="module")
@@ -48,6 +49,40 @@ def test_emulated_batched_step_and_adjoint(emu_mod, precision, tol):
         sv = slice(w.body_v_off[b], w.body_v_off[b + 1])
         se = slice(w.body_e_off[b], w.body_e_off[b + 1])
         wr = solve.adjoint(p, xs[sv], w.x0[sv], a[se], xbar[sv], vbar[sv])
+        assert rel(wv[sv], wr) <= tol
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 1e-5)])
+def test_emulated_batched_springs_step_and_adjoint(emu_mod, precision, tol):
+    """Bodies with vertex-pair springs (Eq. 2 between two vertices) besides their element fibres."""
+    w, rng = rand_workload(2, seed=23, bodies=3, shape=(5, 2))
+    w = _tight(with_springs(w, rng))
+    eb = emu_mod.EmuBatch(w, precision)
+    a = w.actions[0]
+    x1, v1, st = eb.step(w.x0, w.v0, a, block=64)
+    assert np.all(st["flags"] & 1)
+    xs = []
+    for b in range(w.n_bodies):
+        wb = w.body(b)
+        p = Problem.from_workload(wb)
+        assert p.n_s > 0
+        sv = slice(w.body_v_off[b], w.body_v_off[b + 1])
+        xr, vr, _ = solve.step(p, wb.x0, wb.v0, wb.actions[0], tol=1e-13)
+        xs.append(xr)
+        assert rel(x1[sv] - w.x0[sv], xr - w.x0[sv]) <= tol
+        assert rel(v1[sv], vr) <= tol
+        # the final energy of the batched solve includes the springs' terms
+        assert st["energy"][b] == pytest.approx(p.energy(xr, wb.x0, wb.v0, wb.actions[0]), rel=1e-9)
+    xs = np.concatenate(xs)
+    xbar = rng.normal(size=xs.shape)
+    vbar = rng.normal(size=xs.shape)
+    wv, st = eb.adjoint(xs, w.x0, a, xbar, vbar, block=64)
+    assert np.all(st["flags"] & 8)
+    for b in range(w.n_bodies):
+        wb = w.body(b)
+        p = Problem.from_workload(wb)
+        sv = slice(w.body_v_off[b], w.body_v_off[b + 1])
+        wr = solve.adjoint(p, xs[sv], wb.x0, wb.actions[0], xbar[sv], vbar[sv])
         assert rel(wv[sv], wr) <= tol
 
 
