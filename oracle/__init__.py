@@ -8,7 +8,7 @@ Hessian are written out from the paper's definitions (fem.py), and the step and
 adjoint use direct sparse solves (solve.py), not CG.
 
 Parity status: every function here is pinned by the CPU tests in
-tests/test_oracle_pins.py and tests/test_oracle_springs.py (closed forms,
+tests/test_oracle_pins.py, tests/test_oracle_springs.py and tests/test_oracle_models.py (closed forms,
 invariants, finite differences, independent automatic differentiation and brute
 force); none is "parity unpinned".
 """

@@ -114,40 +114,152 @@ def logq_d(J):
 LOGQ_DD = -1.0
 
 
-def psi(F, mu, lam, kf, a, fd):
-    """Energy density: mu/2 (I1 - d) - mu l(J) + lam/2 l(J)^2 + kf/2 (|F fd| / a - 1)^2."""
+# Isotropic element energies (the neo-Hookean density of Eq. 3 and the alternatives Sec. 3 names;
+# all are functions of F alone) and the fibre term of Eq. 2 along a material direction.
+MODELS = ("nh", "stvk", "corot", "snh")
+
+
+def closest_rotation(F):
+    """R = argmax over rotations of tr(R^T F): U V^T from the SVD F = U S V^T, with the sign of the
+    last singular vector flipped when det(U V^T) < 0, so that det R = 1 also for inverted F."""
+    U, _, Vt = np.linalg.svd(F)
+    flip = np.where(det(U @ Vt) < 0.0, -1.0, 1.0)
+    U = U.copy()
+    U[..., :, -1] *= flip[..., None]
+    return U @ Vt
+
+
+def _corot_dR(R, S, dF):
+    """dR = R Omega for the polar pair F = R S (S symmetric): Omega is skew with
+    Omega S + S Omega = R^T dF - dF^T R."""
+    d = R.shape[-1]
+    K = np.swapaxes(R, -1, -2) @ dF
+    K = K - np.swapaxes(K, -1, -2)
+    trS = np.trace(S, axis1=-2, axis2=-1)
+    if d == 2:
+        om = K[:, 1, 0] / trS
+        Om = np.zeros_like(R)
+        Om[:, 1, 0] = om
+        Om[:, 0, 1] = -om
+    else:
+        # Omega = skew(w), Omega S + S Omega = skew((tr S I - S) w)
+        k = np.stack([K[:, 2, 1], K[:, 0, 2], K[:, 1, 0]], axis=-1)
+        w = np.linalg.solve(trS[:, None, None] * np.eye(3)[None] - S, k[..., None])[..., 0]
+        Om = np.zeros_like(R)
+        Om[:, 2, 1], Om[:, 1, 2] = w[:, 0], -w[:, 0]
+        Om[:, 0, 2], Om[:, 2, 0] = w[:, 1], -w[:, 1]
+        Om[:, 1, 0], Om[:, 0, 1] = w[:, 2], -w[:, 2]
+    return R @ Om
+
+
+def _polar(F):
+    R = closest_rotation(F)
+    S = np.swapaxes(R, -1, -2) @ F
+    return R, 0.5 * (S + np.swapaxes(S, -1, -2))
+
+
+def iso_param_parts(F, model="nh"):
+    """(psi_mu, psi_lam, P_mu, P_lam): the isotropic density and its first Piola stress are
+    mu psi_mu + lam psi_lam and mu P_mu + lam P_lam in every model (both linear in the Lame pair).
+
+      nh    Eq. 3 with log J replaced by l(J) = (J-1) - (J-1)^2/2:
+            mu/2 (I1 - d) - mu l(J) + lam/2 l(J)^2
+      stvk  St. Venant-Kirchhoff, E = (F^T F - I)/2:  mu E:E + lam/2 tr(E)^2
+      corot corotated, F = R S with R the closest rotation:  mu |F - R|^2 + lam/2 tr(S - I)^2
+      snh   stable neo-Hookean without its log barrier, Lame pair reparametrised (lam -> lam + mu,
+            rest stress zero) and shifted to zero rest energy:
+            mu/2 (I1 - d) - mu (J - 1) + (lam + mu)/2 (J - 1)^2
+    """
     d = F.shape[-1]
-    I1 = np.sum(F * F, axis=(-2, -1))
-    lJ = logq(det(F))
-    s = np.linalg.norm(np.einsum("eij,ej->ei", F, fd), axis=-1)
-    return 0.5 * mu * (I1 - d) - mu * lJ + 0.5 * lam * lJ ** 2 + 0.5 * kf * (s / a - 1.0) ** 2
+    eye = np.eye(d)[None]
+    if model == "nh":
+        J = det(F)
+        lJ, dl = logq(J), logq_d(J)
+        C = cofactor(F)
+        I1 = np.sum(F * F, axis=(-2, -1))
+        return (0.5 * (I1 - d) - lJ, 0.5 * lJ ** 2, F - dl[:, None, None] * C, (lJ * dl)[:, None, None] * C)
+    if model == "stvk":
+        E = 0.5 * (np.swapaxes(F, -1, -2) @ F - eye)
+        trE = np.trace(E, axis1=-2, axis2=-1)
+        return np.sum(E * E, axis=(-2, -1)), 0.5 * trE ** 2, 2.0 * F @ E, trE[:, None, None] * F
+    if model == "corot":
+        R, S = _polar(F)
+        t = np.trace(S, axis1=-2, axis2=-1) - d
+        return np.sum((F - R) ** 2, axis=(-2, -1)), 0.5 * t ** 2, 2.0 * (F - R), t[:, None, None] * R
+    if model == "snh":
+        J = det(F)
+        C = cofactor(F)
+        I1 = np.sum(F * F, axis=(-2, -1))
+        j1 = J - 1.0
+        return (0.5 * (I1 - d) - j1 + 0.5 * j1 ** 2, 0.5 * j1 ** 2, F + (j1 - 1.0)[:, None, None] * C,
+                j1[:, None, None] * C)
+    raise ValueError(f"unknown energy model {model!r}")
 
 
-def stress(F, mu, lam, kf, a, fd):
-    """First Piola stress P = d psi / dF."""
-    J = det(F)
-    lJ, dl = logq(J), logq_d(J)
-    C = cofactor(F)
-    P = mu[:, None, None] * F + ((lam * lJ - mu) * dl)[:, None, None] * C
+def iso_stress_diff(F, dF, mu, lam, model="nh"):
+    """d(P_iso) along dF."""
+    mu3, lam3 = mu[:, None, None], lam[:, None, None]
+    if model == "nh":
+        J = det(F)
+        lJ, dl = logq(J), logq_d(J)
+        C = cofactor(F)
+        dJ = np.sum(C * dF, axis=(-2, -1))
+        dP = mu3 * dF
+        dP += ((lam * lJ - mu) * dl)[:, None, None] * cofactor_diff(F, dF)
+        dP += ((lam * dl * dl + (lam * lJ - mu) * LOGQ_DD) * dJ)[:, None, None] * C
+        return dP
+    if model == "stvk":
+        d = F.shape[-1]
+        E = 0.5 * (np.swapaxes(F, -1, -2) @ F - np.eye(d)[None])
+        dE = 0.5 * (np.swapaxes(dF, -1, -2) @ F + np.swapaxes(F, -1, -2) @ dF)
+        trE = np.trace(E, axis1=-2, axis2=-1)[:, None, None]
+        trdE = np.trace(dE, axis1=-2, axis2=-1)[:, None, None]
+        return dF @ (2.0 * mu3 * E) + lam3 * trE * dF + F @ (2.0 * mu3 * dE) + lam3 * trdE * F
+    if model == "corot":
+        d = F.shape[-1]
+        R, S = _polar(F)
+        dR = _corot_dR(R, S, dF)
+        t = (np.trace(S, axis1=-2, axis2=-1) - d)[:, None, None]
+        trRdF = np.sum(R * dF, axis=(-2, -1))[:, None, None]     # tr(dS) = tr(R^T dF)
+        return 2.0 * mu3 * (dF - dR) + lam3 * trRdF * R + lam3 * t * dR
+    if model == "snh":
+        J = det(F)
+        C = cofactor(F)
+        dJ = np.sum(C * dF, axis=(-2, -1))
+        lp = lam + mu
+        dP = mu3 * dF + (lp * dJ)[:, None, None] * C
+        dP += (lp * (J - 1.0) - mu)[:, None, None] * cofactor_diff(F, dF)
+        return dP
+    raise ValueError(f"unknown energy model {model!r}")
+
+
+def fibre_terms(F, fd):
+    """(s, n): fibre stretch |F d| and unit direction F d / s."""
     Ffd = np.einsum("eij,ej->ei", F, fd)
     s = np.linalg.norm(Ffd, axis=-1)
-    n = Ffd / s[:, None]
+    return s, Ffd / s[:, None]
+
+
+def psi(F, mu, lam, kf, a, fd, model="nh"):
+    """Energy density: the isotropic model's density plus kf/2 (|F fd| / a - 1)^2 (Eq. 2)."""
+    pm, pl, _, _ = iso_param_parts(F, model)
+    s, _ = fibre_terms(F, fd)
+    return mu * pm + lam * pl + 0.5 * kf * (s / a - 1.0) ** 2
+
+
+def stress(F, mu, lam, kf, a, fd, model="nh"):
+    """First Piola stress P = d psi / dF."""
+    _, _, Pm, Pl = iso_param_parts(F, model)
+    P = mu[:, None, None] * Pm + lam[:, None, None] * Pl
+    s, n = fibre_terms(F, fd)
     P += ((kf / a) * (s / a - 1.0))[:, None, None] * np.einsum("ei,ej->eij", n, fd)
     return P
 
 
-def stress_diff(F, dF, mu, lam, kf, a, fd):
+def stress_diff(F, dF, mu, lam, kf, a, fd, model="nh"):
     """dP = (d^2 psi / dF^2) : dF."""
-    J = det(F)
-    lJ, dl = logq(J), logq_d(J)
-    C = cofactor(F)
-    dJ = np.sum(C * dF, axis=(-2, -1))
-    dP = mu[:, None, None] * dF
-    dP += ((lam * lJ - mu) * dl)[:, None, None] * cofactor_diff(F, dF)
-    dP += ((lam * dl * dl + (lam * lJ - mu) * LOGQ_DD) * dJ)[:, None, None] * C
-    Ffd = np.einsum("eij,ej->ei", F, fd)
-    s = np.linalg.norm(Ffd, axis=-1)
-    n = Ffd / s[:, None]
+    dP = iso_stress_diff(F, dF, mu, lam, model)
+    s, n = fibre_terms(F, fd)
     q = np.einsum("eij,ej->ei", dF, fd)                   # dF fd
     nq = np.sum(n * q, axis=-1)
     dn = (q - n * nq[:, None]) / s[:, None]               # d(n) = (I - n n^T) dF fd / s
@@ -182,14 +294,14 @@ def corner_dF(mesh: Mesh, j: int, c: int):
     return dDs @ mesh.DmInv
 
 
-def element_hessians(mesh: Mesh, x, mu, lam, kf, a, fd):
+def element_hessians(mesh: Mesh, x, mu, lam, kf, a, fd, model="nh"):
     """Dense element Hessians [n_e, (d+1)d, (d+1)d] of E_e = W psi(F), row/col index = corner*d + axis."""
     F = mesh.F(x)
     nd = (mesh.d + 1) * mesh.d
     K = np.empty((mesh.n_e, nd, nd))
     for j in range(mesh.d + 1):
         for c in range(mesh.d):
-            dP = stress_diff(F, corner_dF(mesh, j, c), mu, lam, kf, a, fd)
+            dP = stress_diff(F, corner_dF(mesh, j, c), mu, lam, kf, a, fd, model)
             K[:, :, j * mesh.d + c] = corner_grads(mesh, dP).reshape(mesh.n_e, nd)
     return K
 
@@ -243,8 +355,11 @@ def spring_hessians(x, S, k, l0, a):
 class Problem:
     """One body: mesh, material, scene constants. All arrays FP64; x is [n_v, d]."""
 
-    def __init__(self, X, T, pinned, mu, lam, kf, fdir, rho, scene, springs=None, k_spring=None):
+    def __init__(self, X, T, pinned, mu, lam, kf, fdir, rho, scene, springs=None, k_spring=None, model="nh"):
         self.mesh = Mesh(X, T, rho)
+        if model not in MODELS:
+            raise ValueError(f"unknown energy model {model!r}")
+        self.model = model
         # vertex-pair springs (i, j) with stiffness k and rest length |X_j - X_i|
         self.S = np.zeros((0, 2), np.int64) if springs is None else np.asarray(springs, dtype=np.int64)
         self.ks = np.zeros(0) if k_spring is None else np.asarray(k_spring, dtype=np.float64)
@@ -269,7 +384,7 @@ class Problem:
     @classmethod
     def from_workload(cls, w):
         return cls(w.X, w.T, w.pinned, w.mu, w.lam, w.kf, w.fdir, w.rho, w.scene,
-                   getattr(w, "S", None), getattr(w, "ks", None))
+                   getattr(w, "S", None), getattr(w, "ks", None), getattr(w, "model", "nh"))
 
     def split(self, a):
         """(element actions [n_e], spring actions [n_s]) of an action vector [n_e + n_s]."""
@@ -317,12 +432,12 @@ class Problem:
     # ---- element terms ----
     def element_energy(self, x, a):
         F = self.mesh.F(x)
-        return self.mesh.W * psi(F, self.mu, self.lam, self.kf, a, self.fd)
+        return self.mesh.W * psi(F, self.mu, self.lam, self.kf, a, self.fd, self.model)
 
     def element_grad(self, x, a):
         """Assembled gradient of sum_e E_e, [n_v, d]."""
         F = self.mesh.F(x)
-        cg = corner_grads(self.mesh, stress(F, self.mu, self.lam, self.kf, a, self.fd))
+        cg = corner_grads(self.mesh, stress(F, self.mu, self.lam, self.kf, a, self.fd, self.model))
         G = np.zeros_like(x)
         np.add.at(G, self.mesh.T, cg)
         return G
@@ -361,7 +476,8 @@ class Problem:
         ae, as_ = self.split(a)
         n = self.mesh.n_v * d
         H = sp.csr_matrix((n, n))
-        for K, conn in ((element_hessians(self.mesh, x, self.mu, self.lam, self.kf, ae, self.fd), self.mesh.T),
+        for K, conn in ((element_hessians(self.mesh, x, self.mu, self.lam, self.kf, ae, self.fd, self.model),
+                         self.mesh.T),
                         (spring_hessians(x, self.S, self.ks, self.l0, as_), self.S)):
             dofs = (conn[:, :, None] * d + np.arange(d)[None, None, :]).reshape(conn.shape[0], conn.shape[1] * d)
             rows = np.repeat(dofs, dofs.shape[1], axis=1).ravel()

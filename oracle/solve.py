@@ -20,7 +20,7 @@ import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-from .fem import Problem, cofactor, det, edge_matrix, logq, logq_d, spring_force_terms
+from .fem import Problem, edge_matrix, iso_param_parts, spring_force_terms
 
 ARMIJO_C1 = 1e-4
 LS_MAX = 30
@@ -176,9 +176,7 @@ def vjp_params(prob: Problem, w, x1, x0, a, v1_bar=None):
     s_pot = prob.s_pot
     a, a_s = prob.split(a)
     F = m.F(x1)
-    J = det(F)
-    lJ, dl = logq(J), logq_d(J)
-    C = cofactor(F)
+    _, _, P_mu, P_lam = iso_param_parts(F, prob.model)
     Ffd = np.einsum("eij,ej->ei", F, prob.fd)
     s = np.linalg.norm(Ffd, axis=-1)
     n = Ffd / s[:, None]
@@ -187,8 +185,8 @@ def vjp_params(prob: Problem, w, x1, x0, a, v1_bar=None):
     W = m.W
     out = {}
     out["a_bar"] = -s_pot * W * prob.kf * (1.0 / a ** 2 - 2.0 * s / a ** 3) * n_dFw_d
-    out["mu_bar"] = -s_pot * W * np.sum((F - dl[:, None, None] * C) * dFw, axis=(-2, -1))
-    out["lam_bar"] = -s_pot * W * lJ * dl * np.sum(C * dFw, axis=(-2, -1))
+    out["mu_bar"] = -s_pot * W * np.sum(P_mu * dFw, axis=(-2, -1))
+    out["lam_bar"] = -s_pot * W * np.sum(P_lam * dFw, axis=(-2, -1))
     out["kf_bar"] = -s_pot * W * (1.0 / a) * (s / a - 1.0) * n_dFw_d
     # springs: G = f n at j and -f n at i with f = k c (c l - 1), c = 1/(a l0); only f depends on
     # a (dc/da = -c/a) and on k, so -w^T dG/dtheta = -(df/dtheta) n.(w_j - w_i)

@@ -63,6 +63,7 @@ class Workload:
     S: np.ndarray = field(default=None)           # [n_s, 2] int32 vertex pairs (global ids)
     ks: np.ndarray = field(default=None)          # [n_s] spring stiffness
     body_s_off: np.ndarray = field(default=None)  # [n_bodies + 1]
+    model: str = "nh"  # isotropic element energy: nh (Eq. 3), stvk, corot, snh
 
     def __post_init__(self):
         if self.body_v_off is None:
@@ -103,7 +104,7 @@ class Workload:
                         self.mu[e0:e1].copy(), self.lam[e0:e1].copy(), self.kf[e0:e1].copy(),
                         self.fdir[e0:e1].copy(), self.rho[e0:e1].copy(), dict(self.scene),
                         self.x0[v0:v1].copy(), self.v0[v0:v1].copy(), acts,
-                        S=(self.S[s0:s1] - v0).astype(np.int32), ks=self.ks[s0:s1].copy())
+                        S=(self.S[s0:s1] - v0).astype(np.int32), ks=self.ks[s0:s1].copy(), model=self.model)
 
 
 def _material(n_e, dim, E, nu):
