@@ -79,6 +79,7 @@ def parse():
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay leg")
     ap.add_argument("--no-policy", action="store_true", help="skip the policy-training leg")
     ap.add_argument("--no-springs", action="store_true", help="skip the vertex-pair spring leg")
+    ap.add_argument("--no-energies", action="store_true", help="skip the alternative-energy legs")
     ap.add_argument("--policy-iters", type=int, default=4)
     ap.add_argument("--tet-steps", type=int, default=20)
     ap.add_argument("--no-elem-roofline", action="store_true", help="skip the size-R element roofline leg")
@@ -386,6 +387,7 @@ def main():
         print("# graph replay leg done", file=sys.stderr, flush=True)
 
     springs = None if args.no_springs else spring_leg(args, torch, Context, isb, scenes)
+    energies = None if args.no_energies else energy_leg(args, torch, Context, isb, scenes)
     policy = None if args.no_policy else policy_leg(args, torch, Context, isb, scenes)
     tet = None if args.no_tet else tet_leg(args, torch, Context, isb, scenes)
     elem = None if args.no_elem_roofline else element_roofline_leg(args, torch, Context, isb, scenes)
@@ -404,7 +406,7 @@ def main():
                        "tol_rel": w.scene["tol_rel"], "adj_tol_rel": w.scene["adj_tol_rel"],
                        "block": ctx.get_option(isb.OPT_BLOCK)},
             "iterations": it, "plain_fp64": plain, "parity": parity, "roofline": roofline,
-            "cpu_baseline": cpu, "graph_replay": graph, "springs": springs, "policy_training": policy, "tet_block": tet, "element_roofline": elem}
+            "cpu_baseline": cpu, "graph_replay": graph, "springs": springs, "energies": energies, "policy_training": policy, "tet_block": tet, "element_roofline": elem}
     print(json.dumps(line))
 
 
@@ -510,6 +512,76 @@ def spring_leg(args, torch, Context, isb, scenes):
             "adj_cg_per_step": float(np.mean([[s["adj_cg_iters"] for s in S] for S in st_a])),
             "not_converged_steps": int(sum(1 for S in st_f for s in S if not (s["flags"] & 1))),
             "x1_rel_err_vs_oracle_displacement": {"bodies": [0, nb - 1], "err": errs}}
+
+
+def energy_leg(args, torch, Context, isb, scenes):
+    """The batched workload with each alternative isotropic energy (Sec. 3): one warm-up and one
+    timed BPTT pass (T steps fwd + T adjoints + VJPs), batched mixed; error of body 0's first step
+    against the oracle."""
+    dev = torch.device("cuda:0")
+    T = args.rollout
+    out = {}
+    for model in ("stvk", "corot", "snh"):
+        w = scenes.batched_strips(args.bodies, steps=T)
+        w.model = model
+        nb = w.n_bodies
+        ctx = Context.from_workload(w, precision="mixed", solver=1)
+        ctx.set_option(isb.OPT_GRAPH_SAFE, 1)
+        x0 = torch.tensor(w.x0, dtype=torch.float64, device=dev)
+        v0 = torch.zeros_like(x0)
+        acts = torch.tensor(w.actions, dtype=torch.float64, device=dev)
+        xbar_T = torch.zeros_like(x0)
+        xbar_T[:, 0] = -1.0 / w.n_v
+        ev = []
+
+        def bptt(record=False, stats=False):
+            xs, vs, sts = [x0], [v0], []
+            for t in range(T):
+                if record:
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                x1, v1, sf, _ = ctx.step(xs[-1], vs[-1], acts[t], stats=stats)
+                if record:
+                    e1.record()
+                    ev.append((e0, e1))
+                xs.append(x1)
+                vs.append(v1)
+                sts.append(sf)
+            xb, vb = xbar_T, torch.zeros_like(x0)
+            for t in range(T - 1, -1, -1):
+                wv, _, _ = ctx.solve_adjoint(xs[t + 1], xs[t], acts[t], xb, vb, stats=False)
+                o = ctx.vjp_params(wv, xs[t + 1], xs[t], acts[t], vb, want=("a_bar", "x0_bar", "v0_bar"))
+                xb, vb = o["x0_bar"], o["v0_bar"]
+            return xs, sts
+
+        bptt()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xs, _ = bptt(record=True)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        _, sts = bptt(stats=True)
+        err = None
+        try:
+            from oracle import solve as osolve
+            from oracle.fem import Problem
+            wb = w.body(0)
+            xr, _, _ = osolve.step(Problem.from_workload(wb), wb.x0, wb.v0, wb.actions[0], tol=1e-13)
+            x1 = xs[1].cpu().numpy()[w.body_v_off[0]:w.body_v_off[1]]
+            err = float(np.linalg.norm(x1 - xr) / np.linalg.norm(xr - wb.x0))
+        except Exception as e:  # report, never fail the bench line on the check
+            err = repr(e)
+        out[model] = {"value": round(nb * T / wall, 1), "unit": "body-steps/s",
+                      "step_launch_ms": round(float(np.mean([a.elapsed_time(b) for a, b in ev])), 4),
+                      "newton_per_step": float(np.mean([[s["newton_iters"] for s in S] for S in sts])),
+                      "cg_per_step": float(np.mean([[s["cg_iters"] for s in S] for S in sts])),
+                      "not_converged_steps": int(sum(1 for S in sts for s in S if not (s["flags"] & 1))),
+                      "x1_rel_err_vs_oracle_body0": err}
+        del ctx
+        print(f"# energy leg {model} done", file=sys.stderr, flush=True)
+    out["workload"] = (f"batched_strips: {args.bodies} bodies, {T} backward-Euler steps fwd + adjoint + VJP, "
+                       "batched mixed, one timed pass per model")
+    return out
 
 
 def policy_leg(args, torch, Context, isb, scenes):

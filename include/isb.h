@@ -63,6 +63,23 @@ typedef enum {
 typedef enum { ISB_FP64 = 0, ISB_MIXED = 1 } isb_precision;
 typedef enum { ISB_QUASISTATIC = 0, ISB_BACKWARD_EULER = 1 } isb_integrator;
 
+/* Isotropic element energy (ISB_OPT_ENERGY). Each density is a function of F = Ds Dm^-1, linear in
+ * the Lame pair (mu, lam) of isb_material_upload, zero with zero stress at rest, and its Hessian at
+ * rest is the linear-elastic stiffness of that Lame pair; the fibre term of Eq. 2 is added in all.
+ *   NEOHOOKEAN         Eq. 3 with log J replaced by (J-1) - (J-1)^2/2 (Sec. 3)
+ *   STVK               St. Venant-Kirchhoff, E = (F^T F - I)/2: mu E:E + lam/2 tr(E)^2
+ *   COROTATED          mu |F - R|^2 + lam/2 tr(R^T F - I)^2, R the rotation closest to F
+ *                      (argmax of tr(R^T F) over rotations, so det R = 1 also for inverted F)
+ *   STABLE_NEOHOOKEAN  mu/2 (I1 - dim) - mu (J - 1) + (lam + mu)/2 (J - 1)^2: the stable neo-Hookean
+ *                      form without its log barrier, Lame pair reparametrised to rest stress zero
+ * Sec. 3 names these models as alternatives to Eq. 3. */
+typedef enum {
+  ISB_ENERGY_NEOHOOKEAN = 0,
+  ISB_ENERGY_STVK = 1,
+  ISB_ENERGY_COROTATED = 2,
+  ISB_ENERGY_STABLE_NEOHOOKEAN = 3
+} isb_energy_model;
+
 /* Option keys for isb_set_option / isb_get_option. */
 typedef enum {
   ISB_OPT_SOLVER = 0,       /* 0 = plain: host-driven Newton-PCG, one body at a time, grid-wide kernels;
@@ -76,7 +93,9 @@ typedef enum {
   ISB_OPT_BLOCK = 3,        /* batched solver workgroup size: 256, 512, 768 or 1024; 0 (default) = 768 for
                                triangles, 512 for tetrahedra */
   ISB_OPT_CG_CHECK = 4,     /* plain solver: read the CG convergence flag every k iterations (default 4) */
-  ISB_OPT_PRECISION = 5     /* isb_precision; equals the value given to isb_create */
+  ISB_OPT_PRECISION = 5,    /* isb_precision; equals the value given to isb_create */
+  ISB_OPT_ENERGY = 6        /* isotropic element energy, one of isb_energy_model (default neo-Hookean); the
+                             * batched solver runs the alternatives with the default workgroup size only */
 } isb_option;
 
 /* Read-only context facts for isb_get_option. */

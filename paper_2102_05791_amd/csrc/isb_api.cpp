@@ -61,6 +61,7 @@ DevMesh devmesh(const isb_ctx* c) {
   m.wkf32 = c->wkf32;
   m.mass = c->mass;
   m.pinned = c->pinned;
+  m.model = c->model;
   return m;
 }
 
@@ -759,6 +760,11 @@ isb_status isb_set_option(isb_ctx* c, int key, int64_t value) {
       if (value < 1 || value > 1000) return fail(ISB_E_ARG, "cg_check must be in [1, 1000]");
       c->cg_check = (int)value;
       return ISB_OK;
+    case ISB_OPT_ENERGY:
+      if (value < ISB_ENERGY_NEOHOOKEAN || value > ISB_ENERGY_STABLE_NEOHOOKEAN)
+        return fail(ISB_E_ARG, "energy must be one of ISB_ENERGY_*");
+      c->model = (int)value;
+      return ISB_OK;
     default:
       return fail(ISB_E_ARG, "unknown or read-only option key " + std::to_string(key));
   }
@@ -774,6 +780,7 @@ isb_status isb_get_option(isb_ctx* c, int key, int64_t* value) {
     case ISB_OPT_BLOCK: *value = c->block > 0 ? c->block : (c->dim == 3 ? 512 : 768); return ISB_OK;
     case ISB_OPT_CG_CHECK: *value = c->cg_check; return ISB_OK;
     case ISB_OPT_PRECISION: *value = c->precision; return ISB_OK;
+    case ISB_OPT_ENERGY: *value = c->model; return ISB_OK;
     case ISB_INFO_N_VERTICES: *value = c->n_v; return ISB_OK;
     case ISB_INFO_N_ELEMENTS: *value = c->n_e; return ISB_OK;
     case ISB_INFO_N_BODIES: *value = c->n_bodies; return ISB_OK;

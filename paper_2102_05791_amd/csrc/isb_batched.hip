@@ -20,10 +20,10 @@ namespace isb {
 
 // MODE 0: step, 1: adjoint. LB is the launch bound: 1024-thread workgroups get at most 128 VGPRs,
 // 768-thread ones 168 and 512-thread ones 256 (one workgroup per CU in every case).
-template <int D, typename T, int MODE, int LB>
+template <int D, typename T, int MODE, int LB, int EM = EM_NH>
 __global__ void __launch_bounds__(LB) k_batched(DevMesh m, DevScene sc, BatchArgs A) {
   extern __shared__ double smem[];
-  batched_body<D, T, MODE>(m, sc, A, smem, (int)blockIdx.x);
+  batched_body<D, T, MODE, EM>(m, sc, A, smem, (int)blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -42,13 +42,24 @@ struct BatchedState {
   int32_t* soff = nullptr;              // springs per body
   uint16_t* slconn = nullptr;           // body-local spring ends
   void* Sbuf = nullptr;                 // per-spring block K in the element precision
-  int nacc = 0, grid = 0, block = 0, precision = -1, dim = 0;
+  int nacc = 0, grid = 0, block = 0, precision = -1, dim = 0, model = 0;
   size_t lds = 0;
 };
 
-template <int D, typename T, int MODE, int LB>
+template <int D, typename T, int MODE, int LB, int EM = EM_NH>
 static void* kernel_ptr() {
-  return reinterpret_cast<void*>(&k_batched<D, T, MODE, LB>);
+  return reinterpret_cast<void*>(&k_batched<D, T, MODE, LB, EM>);
+}
+
+// the alternative energy models come in the default workgroup size of each dimension only
+template <int EM>
+static void* pick_model(int dim, int precision, int mode) {
+  if (dim == 2) {
+    if (precision == ISB_MIXED) return mode ? kernel_ptr<2, float, 1, 768, EM>() : kernel_ptr<2, float, 0, 768, EM>();
+    return mode ? kernel_ptr<2, double, 1, 768, EM>() : kernel_ptr<2, double, 0, 768, EM>();
+  }
+  if (precision == ISB_MIXED) return mode ? kernel_ptr<3, float, 1, 512, EM>() : kernel_ptr<3, float, 0, 512, EM>();
+  return mode ? kernel_ptr<3, double, 1, 512, EM>() : kernel_ptr<3, double, 0, 512, EM>();
 }
 
 template <int LB>
@@ -61,7 +72,16 @@ static void* pick_lb(int dim, int precision, int mode) {
   return mode ? kernel_ptr<3, double, 1, LB>() : kernel_ptr<3, double, 0, LB>();
 }
 
-static void* pick_kernel(int dim, int precision, int mode, int block) {
+static int default_block(int dim) { return dim == 2 ? 768 : 512; }
+
+// nullptr: no kernel of this configuration (an alternative energy model at another block size)
+static void* pick_kernel(int dim, int precision, int mode, int block, int model) {
+  if (model != EM_NH) {
+    if (block != default_block(dim)) return nullptr;
+    if (model == EM_STVK) return pick_model<EM_STVK>(dim, precision, mode);
+    if (model == EM_COROT) return pick_model<EM_COROT>(dim, precision, mode);
+    return pick_model<EM_SNH>(dim, precision, mode);
+  }
   if (block > 768) return pick_lb<1024>(dim, precision, mode);
   if (block > 512) return pick_lb<768>(dim, precision, mode);
   return pick_lb<512>(dim, precision, mode);
@@ -125,8 +145,11 @@ static void lpt_schedule(const std::vector<int32_t>& eoff, int nb, int G, std::v
 
 isb_status batched_prepare(isb_ctx* c) {
   auto* st = static_cast<BatchedState*>(c->batched);
-  const int want_block = c->block > 0 ? c->block : (c->dim == 2 ? 768 : 512);
-  if (st && st->block == want_block && st->precision == c->precision && st->dim == c->dim) return ISB_OK;
+  const int want_block = c->block > 0 ? c->block : default_block(c->dim);
+  if (st && st->block == want_block && st->precision == c->precision && st->dim == c->dim && st->model == c->model)
+    return ISB_OK;
+  if (!pick_kernel(c->dim, c->precision, 0, want_block, c->model))
+    return fail(ISB_E_ARG, "batched solver: the alternative energy models run with the default workgroup size only");
   batched_release(c);
   st = new BatchedState();
   c->batched = st;
@@ -136,6 +159,7 @@ isb_status batched_prepare(isb_ctx* c) {
   st->block = want_block;
   st->precision = c->precision;
   st->dim = c->dim;
+  st->model = c->model;
   int max_lds = 0, n_cu = 0;
   ISB_HIP(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
   ISB_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, c->device));
@@ -144,7 +168,7 @@ isb_status batched_prepare(isb_ctx* c) {
                                " B of LDS, the device allows " + std::to_string(max_lds) + " B per workgroup");
   int occ = 0;
   for (int mode = 0; mode < 2; ++mode) {
-    void* k = pick_kernel(c->dim, c->precision, mode, st->block);
+    void* k = pick_kernel(c->dim, c->precision, mode, st->block, c->model);
     ISB_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)st->lds));
     int o = 0;
     ISB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, k, st->block, st->lds));
@@ -264,7 +288,7 @@ static BatchArgs make_args(isb_ctx* c, BatchedState* st) {
 }
 
 static isb_status launch(isb_ctx* c, BatchedState* st, hipStream_t s, int mode, const BatchArgs& A) {
-  void* k = pick_kernel(c->dim, c->precision, mode, st->block);
+  void* k = pick_kernel(c->dim, c->precision, mode, st->block, c->model);
   const DevMesh m = devmesh(c);
   const DevScene sc = devscene(c);
   void* args[] = {(void*)&m, (void*)&sc, (void*)&A};

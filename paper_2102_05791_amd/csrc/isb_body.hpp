@@ -161,7 +161,7 @@ __device__ __forceinline__ void wg_minmax(double& lo, double& hi, double* bank) 
   hi = wg_uniform(hi);
 }
 
-template <int D, typename T>
+template <int D, typename T, int EM = EM_NH>
 struct BodySolver {
   const DevMesh& m;
   const DevScene& sc;
@@ -301,7 +301,7 @@ struct BodySolver {
           for (int r = 0; r < D; ++r) dDs[r][j] = T(d64[j * D + r]);
         ElemState<D, T> S;
         elem_state_from_F<D, T>(F, Fd, S);
-        elem_hessvec<D, T>(R, S, ae, dDs, out);
+        elem_hessvec<D, T, EM>(R, S, ae, dDs, out);
       }
       // sum_k out_k . p_k = sum_j out_{j+1} . (p_{j+1} - p_0), since out_0 = -sum_j out_{j+1}
 #pragma unroll
@@ -376,7 +376,7 @@ struct BodySolver {
     const size_t ne = (size_t)m.n_e;
     if constexpr (kEdgeHessian) {
       double K[kQ][kQ];
-      edge_hessian_2d<double>(R64, S64, ae, K);
+      edge_hessian_2d<double, EM>(R64, S64, ae, K);
       int w = 0;
 #pragma unroll
       for (int a = 0; a < kQ; ++a)
@@ -400,7 +400,7 @@ struct BodySolver {
 #pragma unroll
         for (int c = 0; c < D; ++c) Fb()[(size_t)(r * D + c) * ne + e] = T(S64.F[r][c]);
       }
-      elem_hessdiag<D, double>(R64, S64, ae, diag);
+      elem_hessdiag<D, double, EM>(R64, S64, ae, diag);
     }
   }
 
@@ -500,13 +500,13 @@ struct BodySolver {
         gather_edges<D, double>(x, v, Ds);
       ElemState<D, double> S64;
       elem_state<D, double>(Ds, R64, S64);
-      const double eb = sc.s_pot * elem_energy<D, double>(R64, S64, ae);
+      const double eb = sc.s_pot * elem_energy<D, double, EM>(R64, S64, ae);
       const double ea = Ecur ? estored : eb;
       sd += eb - ea;
       sa += fabs(ea);
       st += eb;
       double o[D + 1][D];
-      elem_grad<D, double>(R64, S64, ae, o);
+      elem_grad<D, double, EM>(R64, S64, ae, o);
       lds_scatter(v, o, sc.s_pot);
       // global stores once every load of the iteration has been issued: the energy, and the
       // Hessian-vector state, whose computation also yields the Jacobi diagonal (FP64)
@@ -953,7 +953,7 @@ struct BodySolver {
   }
 };
 
-template <int D, typename T, int MODE>  // MODE 0: step, 1: adjoint
+template <int D, typename T, int MODE, int EM = EM_NH>  // MODE 0: step, 1: adjoint
 __device__ void batched_body(const DevMesh& m, const DevScene& sc, const BatchArgs& A, double* smem, int g) {
   double* red = smem;
   double* acc = smem + kRedSlots;
@@ -969,7 +969,7 @@ __device__ void batched_body(const DevMesh& m, const DevScene& sc, const BatchAr
     const int body = wg_uniform(A.order[k]);
     const int bv0 = wg_uniform(A.voff[body]), bv1 = wg_uniform(A.voff[body + 1]);
     const int be0 = wg_uniform(A.eoff[body]), be1 = wg_uniform(A.eoff[body + 1]);
-    BodySolver<D, T> S{m, sc, A, acc, red, ps, bv0, bv1, be0, be1, (bv1 - bv0) * D, bv0 * D};
+    BodySolver<D, T, EM> S{m, sc, A, acc, red, ps, bv0, bv1, be0, be1, (bv1 - bv0) * D, bv0 * D};
     if (A.n_s > 0) {
       S.s0 = wg_uniform(A.soff[body]);
       S.s1 = wg_uniform(A.soff[body + 1]);

@@ -56,6 +56,7 @@ struct isb_ctx {
 
   // options
   int solver = 0, scatter = 2, graph_safe = 0, block = 0 /* 0: 768 in 2D, 512 in 3D */, cg_check = 4;
+  int model = 0;  // ISB_ENERGY_*
 
   // plain-solver workspaces, [n_v*dim] unless noted
   double *w_x = nullptr, *w_xt = nullptr, *w_xhat = nullptr, *w_cv = nullptr /*[n_v]*/, *w_G = nullptr,

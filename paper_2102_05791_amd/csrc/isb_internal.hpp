@@ -27,6 +27,7 @@ struct DevMesh {
   const float *Dinv32, *gf32, *wmu32, *wlam32, *wkf32;
   const double* mass;
   const uint8_t* pinned;
+  int model;  // isotropic energy model (EM_* of isb_elem.hpp, ISB_ENERGY_* of the C ABI)
 };
 
 // Vertex-pair springs, SoA over the caller's spring order:

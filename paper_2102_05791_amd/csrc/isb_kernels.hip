@@ -363,7 +363,7 @@ void launch_adjoint_rhs(const DevMesh& m, const DevScene& sc, int v0, int v1, co
 // ---------------------------------------------------------------------------------------------
 // element kernels
 // ---------------------------------------------------------------------------------------------
-template <int D, bool ATOMIC>
+template <int D, bool ATOMIC, int EM>
 __global__ void __launch_bounds__(kBlock) k_elem_grad(DevMesh m, DevScene sc, ERange r, const double* __restrict__ x,
                                                       const double* __restrict__ a, double* G) {
   for (int k = r.begin + blockIdx.x * blockDim.x + threadIdx.x; k < r.end; k += gridDim.x * blockDim.x) {
@@ -377,12 +377,12 @@ __global__ void __launch_bounds__(kBlock) k_elem_grad(DevMesh m, DevScene sc, ER
     ElemState<D, double> S;
     elem_state<D, double>(Ds, R, S);
     double out[D + 1][D];
-    elem_grad<D, double>(R, S, a[e], out);
+    elem_grad<D, double, EM>(R, S, a[e], out);
     scatter_vertices<D, ATOMIC, double>(G, v, out, sc.s_pot);
   }
 }
 
-template <int D, bool ATOMIC, typename T>
+template <int D, bool ATOMIC, typename T, int EM>
 __global__ void __launch_bounds__(kBlock) k_elem_hv(DevMesh m, DevScene sc, ERange r, const double* __restrict__ x,
                                                     const double* __restrict__ a, const float* __restrict__ a32,
                                                     const double* __restrict__ p, double* Hp, const int* done) {
@@ -400,13 +400,13 @@ __global__ void __launch_bounds__(kBlock) k_elem_hv(DevMesh m, DevScene sc, ERan
     elem_state<D, T>(Ds, R, S);
     const T ae = (std::is_same<T, float>::value && a32) ? T(a32[e]) : T(a[e]);
     T out[D + 1][D];
-    elem_hessvec<D, T>(R, S, ae, dDs, out);
+    elem_hessvec<D, T, EM>(R, S, ae, dDs, out);
     scatter_vertices<D, ATOMIC, T>(Hp, v, out, sc.s_pot);
   }
 }
 
 // Hessian diagonal, FP64 in both precisions (the Jacobi preconditioner and isb_hessdiag)
-template <int D, bool ATOMIC>
+template <int D, bool ATOMIC, int EM>
 __global__ void __launch_bounds__(kBlock) k_elem_diag(DevMesh m, DevScene sc, ERange r, const double* __restrict__ x,
                                                       const double* __restrict__ a, double* diag) {
   for (int k = r.begin + blockIdx.x * blockDim.x + threadIdx.x; k < r.end; k += gridDim.x * blockDim.x) {
@@ -420,13 +420,13 @@ __global__ void __launch_bounds__(kBlock) k_elem_diag(DevMesh m, DevScene sc, ER
     ElemState<D, double> S;
     elem_state<D, double>(Ds, R, S);
     double out[D + 1][D];
-    elem_hessdiag<D, double>(R, S, a[e], out);
+    elem_hessdiag<D, double, EM>(R, S, a[e], out);
     scatter_vertices<D, ATOMIC, double>(diag, v, out, sc.s_pot);
   }
 }
 
 // comps per block: (sum s_pot [E_e(x + alpha dx) - E_e(x)], sum s_pot |E_e(x)|, sum s_pot E_e(x + alpha dx))
-template <int D>
+template <int D, int EM>
 __global__ void __launch_bounds__(kBlock) k_elem_energy(DevMesh m, DevScene sc, ERange r,
                                                         const double* __restrict__ x, const double* __restrict__ dx,
                                                         double alpha, const double* __restrict__ a, double* partials) {
@@ -442,12 +442,12 @@ __global__ void __launch_bounds__(kBlock) k_elem_energy(DevMesh m, DevScene sc, 
     gather_edges<D, double>(x, v, Ds);
     ElemState<D, double> S;
     elem_state<D, double>(Ds, R, S);
-    const double ea = sc.s_pot * elem_energy<D, double>(R, S, a[e]);
+    const double ea = sc.s_pot * elem_energy<D, double, EM>(R, S, a[e]);
     double eb = ea;
     if (dx) {
       gather_edges_step<D>(x, dx, alpha, v, Ds);
       elem_state<D, double>(Ds, R, S);
-      eb = sc.s_pot * elem_energy<D, double>(R, S, a[e]);
+      eb = sc.s_pot * elem_energy<D, double, EM>(R, S, a[e]);
     }
     sd += eb - ea;
     sa += fabs(ea);
@@ -463,7 +463,7 @@ __global__ void __launch_bounds__(kBlock) k_elem_energy(DevMesh m, DevScene sc, 
   }
 }
 
-template <int D>
+template <int D, int EM>
 __global__ void __launch_bounds__(kBlock) k_elem_vjp(DevMesh m, DevScene sc, ERange r, const double* __restrict__ w,
                                                      const double* __restrict__ x1, const double* __restrict__ a,
                                                      double* a_bar, double* mu_bar, double* lam_bar, double* kf_bar) {
@@ -479,7 +479,7 @@ __global__ void __launch_bounds__(kBlock) k_elem_vjp(DevMesh m, DevScene sc, ERa
     ElemState<D, double> S;
     elem_state<D, double>(Ds, R, S);
     double out[4];
-    elem_vjp<D, double>(R, S, m.W[e], a[e], dWs, out);
+    elem_vjp<D, double, EM>(R, S, m.W[e], a[e], dWs, out);
     if (a_bar) a_bar[e] = sc.s_pot * out[0];
     if (mu_bar) mu_bar[e] = sc.s_pot * out[1];
     if (lam_bar) lam_bar[e] = sc.s_pot * out[2];
@@ -518,14 +518,28 @@ __global__ void __launch_bounds__(kBlock) k_to_f32(int n, const double* __restri
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) dst[i] = float(src[i]);
 }
 
+// calls fn(std::integral_constant<int, EM>) for the energy model of the mesh
+template <class Fn>
+static void with_model(int model, Fn&& fn) {
+  switch (model) {
+    case EM_STVK: fn(std::integral_constant<int, EM_STVK>{}); break;
+    case EM_COROT: fn(std::integral_constant<int, EM_COROT>{}); break;
+    case EM_SNH: fn(std::integral_constant<int, EM_SNH>{}); break;
+    default: fn(std::integral_constant<int, EM_NH>{}); break;
+  }
+}
+
 template <int D>
 static void elem_grad_d(const DevMesh& m, const DevScene& sc, ERange r, bool atomic, const double* x, const double* a,
                         double* G, hipStream_t s) {
   const int g = grid_for(r.end - r.begin);
-  if (atomic)
-    k_elem_grad<D, true><<<g, kBlock, 0, s>>>(m, sc, r, x, a, G);
-  else
-    k_elem_grad<D, false><<<g, kBlock, 0, s>>>(m, sc, r, x, a, G);
+  with_model(m.model, [&](auto em) {
+    constexpr int EM = decltype(em)::value;
+    if (atomic)
+      k_elem_grad<D, true, EM><<<g, kBlock, 0, s>>>(m, sc, r, x, a, G);
+    else
+      k_elem_grad<D, false, EM><<<g, kBlock, 0, s>>>(m, sc, r, x, a, G);
+  });
 }
 
 void launch_elem_grad(const DevMesh& m, const DevScene& sc, ERange r, bool atomic, const double* x, const double* a,
@@ -541,10 +555,13 @@ template <int D, typename T>
 static void elem_hv_dt(const DevMesh& m, const DevScene& sc, ERange r, bool atomic, const double* x, const double* a,
                        const float* a32, const double* p, double* Hp, const int* done, hipStream_t s) {
   const int g = grid_for(r.end - r.begin);
-  if (atomic)
-    k_elem_hv<D, true, T><<<g, kBlock, 0, s>>>(m, sc, r, x, a, a32, p, Hp, done);
-  else
-    k_elem_hv<D, false, T><<<g, kBlock, 0, s>>>(m, sc, r, x, a, a32, p, Hp, done);
+  with_model(m.model, [&](auto em) {
+    constexpr int EM = decltype(em)::value;
+    if (atomic)
+      k_elem_hv<D, true, T, EM><<<g, kBlock, 0, s>>>(m, sc, r, x, a, a32, p, Hp, done);
+    else
+      k_elem_hv<D, false, T, EM><<<g, kBlock, 0, s>>>(m, sc, r, x, a, a32, p, Hp, done);
+  });
 }
 
 void launch_elem_hv(const DevMesh& m, const DevScene& sc, ERange r, bool atomic, int precision, const double* x,
@@ -567,10 +584,13 @@ template <int D>
 static void elem_diag_d(const DevMesh& m, const DevScene& sc, ERange r, bool atomic, const double* x,
                         const double* a, double* diag, hipStream_t s) {
   const int g = grid_for(r.end - r.begin);
-  if (atomic)
-    k_elem_diag<D, true><<<g, kBlock, 0, s>>>(m, sc, r, x, a, diag);
-  else
-    k_elem_diag<D, false><<<g, kBlock, 0, s>>>(m, sc, r, x, a, diag);
+  with_model(m.model, [&](auto em) {
+    constexpr int EM = decltype(em)::value;
+    if (atomic)
+      k_elem_diag<D, true, EM><<<g, kBlock, 0, s>>>(m, sc, r, x, a, diag);
+    else
+      k_elem_diag<D, false, EM><<<g, kBlock, 0, s>>>(m, sc, r, x, a, diag);
+  });
 }
 
 void launch_elem_diag(const DevMesh& m, const DevScene& sc, ERange r, bool atomic, const double* x, const double* a,
@@ -586,14 +606,27 @@ void launch_elem_energy(const DevMesh& m, const DevScene& sc, ERange r, const do
                         double alpha, const double* a, double* partials, int part_off, hipStream_t s,
                         int* nblocks_out) {
   const int nb = red_blocks(r.end - r.begin);
-  DISPATCH_D(m.dim, k_elem_energy, nb, m, sc, r, x, dx, alpha, a, partials + 3 * part_off);
+  with_model(m.model, [&](auto em) {
+    constexpr int EM = decltype(em)::value;
+    if (m.dim == 2)
+      k_elem_energy<2, EM><<<nb, kBlock, 0, s>>>(m, sc, r, x, dx, alpha, a, partials + 3 * part_off);
+    else
+      k_elem_energy<3, EM><<<nb, kBlock, 0, s>>>(m, sc, r, x, dx, alpha, a, partials + 3 * part_off);
+  });
   *nblocks_out = nb;
 }
 
 void launch_elem_vjp(const DevMesh& m, const DevScene& sc, ERange r, const double* w, const double* x1,
                      const double* a, double* a_bar, double* mu_bar, double* lam_bar, double* kf_bar, hipStream_t s) {
   if (r.end <= r.begin) return;
-  DISPATCH_D(m.dim, k_elem_vjp, grid_for(r.end - r.begin), m, sc, r, w, x1, a, a_bar, mu_bar, lam_bar, kf_bar);
+  const int g = grid_for(r.end - r.begin);
+  with_model(m.model, [&](auto em) {
+    constexpr int EM = decltype(em)::value;
+    if (m.dim == 2)
+      k_elem_vjp<2, EM><<<g, kBlock, 0, s>>>(m, sc, r, w, x1, a, a_bar, mu_bar, lam_bar, kf_bar);
+    else
+      k_elem_vjp<3, EM><<<g, kBlock, 0, s>>>(m, sc, r, w, x1, a, a_bar, mu_bar, lam_bar, kf_bar);
+  });
 }
 
 void launch_elem_minmax_J(const DevMesh& m, ERange r, const double* x, double* partials, hipStream_t s,
@@ -920,7 +953,7 @@ void launch_min_count(int n, const double* a, double* partials, double* out, hip
 // vertices in LDS, evaluate the elements with LDS gathers and accumulate with LDS atomics, then
 // add each distinct vertex DOF to the global output once. Global atomics drop from d(d+1) per
 // element to the patch's distinct DOFs, and they no longer collide inside a wavefront.
-template <int D, typename T, int OP, int PB>
+template <int D, typename T, int OP, int PB, int EM>
 __global__ void __launch_bounds__(PB) k_elem_patch(DevMesh m, DevScene sc, PatchPlan P, int p0, int p1,
                                                             const double* __restrict__ x,
                                                             const double* __restrict__ a,
@@ -963,16 +996,16 @@ __global__ void __launch_bounds__(PB) k_elem_patch(DevMesh m, DevScene sc, Patch
       const T ae = (std::is_same<T, float>::value && a32) ? T(a32[e]) : T(a[e]);
       T o[D + 1][D];
       if constexpr (OP == PATCH_GRAD) {
-        elem_grad<D, T>(R, S, ae, o);
+        elem_grad<D, T, EM>(R, S, ae, o);
       } else if constexpr (OP == PATCH_HV) {
         T dDs[D][D];
 #pragma unroll
         for (int j = 0; j < D; ++j)
 #pragma unroll
           for (int c = 0; c < D; ++c) dDs[c][j] = T(ps[l[j + 1] * D + c] - ps[l[0] * D + c]);
-        elem_hessvec<D, T>(R, S, ae, dDs, o);
+        elem_hessvec<D, T, EM>(R, S, ae, dDs, o);
       } else {
-        elem_hessdiag<D, T>(R, S, ae, o);
+        elem_hessdiag<D, T, EM>(R, S, ae, o);
       }
 #pragma unroll
       for (int k = 0; k <= D; ++k)
@@ -998,7 +1031,10 @@ static void patch_launch(const DevMesh& m, const DevScene& sc, const PatchPlan& 
   // FP64 element math needs about twice the registers of FP32: 256-thread workgroups keep more of
   // them resident per CU than 512-thread ones would
   constexpr int PB = std::is_same<T, float>::value ? kPatchBlock : kPatchBlock / 2;
-  k_elem_patch<D, T, OP, PB><<<grid, PB, lds, s>>>(m, sc, P, p0, p1, x, a, a32, p, out, done);
+  with_model(m.model, [&](auto em) {
+    constexpr int EM = decltype(em)::value;
+    k_elem_patch<D, T, OP, PB, EM><<<grid, PB, lds, s>>>(m, sc, P, p0, p1, x, a, a32, p, out, done);
+  });
 }
 
 void launch_elem_patch(const DevMesh& m, const DevScene& sc, const PatchPlan& P, int p0, int p1, int op,

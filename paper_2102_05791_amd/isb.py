@@ -20,7 +20,9 @@ STATUS_NAMES = {0: "ISB_OK", 1: "ISB_E_ARG", 2: "ISB_E_MESH", 3: "ISB_E_HIP", 4:
                 5: "ISB_E_NONFINITE", 6: "ISB_E_STATE"}
 ISB_FP64, ISB_MIXED = 0, 1
 ISB_QUASISTATIC, ISB_BACKWARD_EULER = 0, 1
-OPT_SOLVER, OPT_SCATTER, OPT_GRAPH_SAFE, OPT_BLOCK, OPT_CG_CHECK, OPT_PRECISION = range(6)
+OPT_SOLVER, OPT_SCATTER, OPT_GRAPH_SAFE, OPT_BLOCK, OPT_CG_CHECK, OPT_PRECISION, OPT_ENERGY = range(7)
+# isotropic element energies (ISB_ENERGY_*), by the names the synthetic workloads use
+ENERGY = {"nh": 0, "stvk": 1, "corot": 2, "snh": 3}
 INFO_N_VERTICES, INFO_N_ELEMENTS, INFO_N_BODIES, INFO_DIM, INFO_N_COLOURS, INFO_LDS_BYTES = range(100, 106)
 FLAG_CONVERGED, FLAG_STAGNATED, FLAG_NONFINITE, FLAG_ADJ_CONVERGED = 1, 2, 4, 8
 
@@ -258,6 +260,7 @@ class Context:
     def from_workload(cls, w, device=0, precision="fp64", solver=0, scatter=0):
         ctx = cls(device, precision)
         ctx.set_option(OPT_SCATTER, scatter)
+        ctx.set_option(OPT_ENERGY, ENERGY[getattr(w, "model", "nh")])
         ctx.mesh_upload(w.dim, w.X, w.T, w.pinned, w.body_v_off, w.body_e_off)
         ctx.material_upload(w.mu, w.lam, w.kf, w.fdir, w.rho, w.scene)
         if getattr(w, "S", None) is not None and len(w.S) > 0:

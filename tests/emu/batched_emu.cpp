@@ -36,7 +36,12 @@ static void run(int block, const isb::DevMesh* m, const isb::DevScene* sc, const
     th.emplace_back([&, t]() {
       threadIdx.x = t;
       isb_emu::wave_phase = 0;
-      isb::batched_body<D, T, MODE>(*m, *sc, *A, smem.data(), 0);
+      switch (m->model) {
+        case isb::EM_STVK: isb::batched_body<D, T, MODE, isb::EM_STVK>(*m, *sc, *A, smem.data(), 0); break;
+        case isb::EM_COROT: isb::batched_body<D, T, MODE, isb::EM_COROT>(*m, *sc, *A, smem.data(), 0); break;
+        case isb::EM_SNH: isb::batched_body<D, T, MODE, isb::EM_SNH>(*m, *sc, *A, smem.data(), 0); break;
+        default: isb::batched_body<D, T, MODE>(*m, *sc, *A, smem.data(), 0); break;
+      }
     });
   for (auto& x : th) x.join();
   for (auto* b : waves) delete b;

@@ -26,7 +26,7 @@ vp, ci, cd = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
 class DevMesh(ctypes.Structure):
     _fields_ = [("dim", ci), ("n_v", ci), ("n_e", ci), ("conn", vp), ("Dinv", vp), ("gf", vp), ("W", vp),
                 ("wmu", vp), ("wlam", vp), ("wkf", vp), ("Dinv32", vp), ("gf32", vp), ("wmu32", vp),
-                ("wlam32", vp), ("wkf32", vp), ("mass", vp), ("pinned", vp)]
+                ("wlam32", vp), ("wkf32", vp), ("mass", vp), ("pinned", vp), ("model", ci)]
 
 
 class DevScene(ctypes.Structure):
@@ -102,7 +102,8 @@ class EmuBatch:
         f32 = lambda a: k(a.astype(np.float32))
         self.m = DevMesh(d, w.n_v, w.n_e, _p(self.conn), _p(self.Dinv), _p(self.gf), _p(self.W), _p(self.wmu),
                          _p(self.wlam), _p(self.wkf), _p(f32(self.Dinv)), _p(f32(self.gf)), _p(f32(self.wmu)),
-                         _p(f32(self.wlam)), _p(f32(self.wkf)), _p(self.mass), _p(self.pinned))
+                         _p(f32(self.wlam)), _p(f32(self.wkf)), _p(self.mass), _p(self.pinned),
+                         {"nh": 0, "stvk": 1, "corot": 2, "snh": 3}[getattr(w, "model", "nh")])
         sc = w.scene
         be = sc["integrator"] == "be"
         self.sc = DevScene(int(be), sc["h"], sc["h"] ** 2 if be else 1.0, sc["gravity"], sc["k_contact"],

@@ -86,6 +86,41 @@ def test_emulated_batched_springs_step_and_adjoint(emu_mod, precision, tol):
         assert rel(wv[sv], wr) <= tol
 
 
+@pytest.mark.parametrize("model", ["stvk", "corot", "snh"])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_emulated_batched_energy_models(emu_mod, model, dim):
+    """The alternative isotropic energies (Sec. 3) in the batched step and adjoint, FP64 and mixed.
+    The mixed adjoint solves with the FP32 operator; St. Venant-Kirchhoff forms E = (F^T F - I)/2
+    from an FP32 F, which cancels near rest and leaves E about 6e-8/|E| relative precision, so the
+    mixed adjoint bar of the alternative models is 3e-5 (the step stays at 1e-5)."""
+    shape = (5, 2) if dim == 2 else (2, 2, 1)
+    w, rng = rand_workload(dim, seed=24, bodies=2, shape=shape)
+    w = _tight(w)
+    w.model = model
+    probs = problems(w)
+    a = w.actions[0]
+    for precision, tol, adj_tol in (("fp64", 1e-10, 1e-10), ("mixed", 1e-5, 3e-5)):
+        eb = emu_mod.EmuBatch(w, precision)
+        x1, v1, st = eb.step(w.x0, w.v0, a, block=64)
+        assert np.all(st["flags"] & 1)
+        xs = []
+        for b, p in enumerate(probs):
+            sv = slice(w.body_v_off[b], w.body_v_off[b + 1])
+            se = slice(w.body_e_off[b], w.body_e_off[b + 1])
+            xr, vr, _ = solve.step(p, w.x0[sv], w.v0[sv], a[se], tol=1e-13)
+            xs.append(xr)
+            assert rel(x1[sv] - w.x0[sv], xr - w.x0[sv]) <= tol
+        xs = np.concatenate(xs)
+        xbar = rng.normal(size=xs.shape)
+        wv, st = eb.adjoint(xs, w.x0, a, xbar, None, block=64)
+        assert np.all(st["flags"] & 8)
+        for b, p in enumerate(probs):
+            sv = slice(w.body_v_off[b], w.body_v_off[b + 1])
+            se = slice(w.body_e_off[b], w.body_e_off[b + 1])
+            wr = solve.adjoint(p, xs[sv], w.x0[sv], a[se], xbar[sv])
+            assert rel(wv[sv], wr) <= adj_tol
+
+
 def test_emulated_static_assignment_covers_every_body_once(emu_mod):
     """With more bodies than rounds x workgroups boundaries, every body is solved exactly once."""
     w, _ = rand_workload(2, seed=22, bodies=5, shape=(3, 2))
