@@ -80,6 +80,8 @@ def parse():
     ap.add_argument("--no-policy", action="store_true", help="skip the policy-training leg")
     ap.add_argument("--no-springs", action="store_true", help="skip the vertex-pair spring leg")
     ap.add_argument("--no-energies", action="store_true", help="skip the alternative-energy legs")
+    ap.add_argument("--no-first-order", action="store_true", help="skip the Newton vs first-order leg")
+    ap.add_argument("--first-order-steps", type=int, default=5)
     ap.add_argument("--policy-iters", type=int, default=4)
     ap.add_argument("--tet-steps", type=int, default=20)
     ap.add_argument("--no-elem-roofline", action="store_true", help="skip the size-R element roofline leg")
@@ -388,6 +390,7 @@ def main():
 
     springs = None if args.no_springs else spring_leg(args, torch, Context, isb, scenes)
     energies = None if args.no_energies else energy_leg(args, torch, Context, isb, scenes)
+    first_order = None if args.no_first_order else first_order_leg(args, torch, Context, isb, scenes)
     policy = None if args.no_policy else policy_leg(args, torch, Context, isb, scenes)
     tet = None if args.no_tet else tet_leg(args, torch, Context, isb, scenes)
     elem = None if args.no_elem_roofline else element_roofline_leg(args, torch, Context, isb, scenes)
@@ -406,7 +409,7 @@ def main():
                        "tol_rel": w.scene["tol_rel"], "adj_tol_rel": w.scene["adj_tol_rel"],
                        "block": ctx.get_option(isb.OPT_BLOCK)},
             "iterations": it, "plain_fp64": plain, "parity": parity, "roofline": roofline,
-            "cpu_baseline": cpu, "graph_replay": graph, "springs": springs, "energies": energies, "policy_training": policy, "tet_block": tet, "element_roofline": elem}
+            "cpu_baseline": cpu, "graph_replay": graph, "springs": springs, "energies": energies, "first_order": first_order, "policy_training": policy, "tet_block": tet, "element_roofline": elem}
     print(json.dumps(line))
 
 
@@ -581,6 +584,48 @@ def energy_leg(args, torch, Context, isb, scenes):
         print(f"# energy leg {model} done", file=sys.stderr, flush=True)
     out["workload"] = (f"batched_strips: {args.bodies} bodies, {T} backward-Euler steps fwd + adjoint + VJP, "
                        "batched mixed, one timed pass per model")
+    return out
+
+
+def first_order_leg(args, torch, Context, isb, scenes):
+    """Newton-PCG against the first-order forward solver (L-BFGS with the same line search and stop,
+    the paper's kind of forward pass) on the 64x16 strip, plain FP64 path, at the same relative
+    residual: steps/s, iterations and gradient evaluations per step, and the gap between the two
+    trajectories."""
+    dev = torch.device("cuda:0")
+    S = args.first_order_steps
+    w = scenes.be_strip(64, 16, steps=S)
+    out = {"workload": f"be_strip 64x16 ({w.n_e} triangles), {S} backward-Euler steps, plain FP64, "
+                       f"tol_rel {w.scene['tol_rel']}"}
+    finals = {}
+    for name, fwd in (("newton_pcg", isb.FORWARD_NEWTON), ("lbfgs", isb.FORWARD_LBFGS)):
+        ctx = Context.from_workload(w, precision="fp64", solver=0)
+        ctx.set_option(isb.OPT_FORWARD, fwd)
+        acts = torch.tensor(w.actions, dtype=torch.float64, device=dev)
+        x = torch.tensor(w.x0, dtype=torch.float64, device=dev)
+        v = torch.zeros_like(x)
+        ctx.step(x, v, acts[0], stats=False)    # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its, cgs, lss = [], [], []
+        for t in range(S):
+            x, v, st, _ = ctx.step(x, v, acts[t])
+            its.append(st[0]["newton_iters"])
+            cgs.append(st[0]["cg_iters"])
+            lss.append(st[0]["ls_backtracks"])
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        finals[name] = x.cpu().numpy()
+        # gradient evaluations: one per accepted iterate plus the initial one; Newton adds one
+        # Hessian-vector product per CG iteration
+        out[name] = {"steps_per_s": round(S / dt, 3), "ms_per_step": round(1e3 * dt / S, 2),
+                     "iterations_per_step": float(np.mean(its)), "cg_per_step": float(np.mean(cgs)),
+                     "backtracks_per_step": float(np.mean(lss))}
+        del ctx
+    d = finals["lbfgs"] - finals["newton_pcg"]
+    out["x_rel_diff_after_steps"] = float(np.linalg.norm(d) / np.linalg.norm(finals["newton_pcg"] - w.x0))
+    out["newton_speedup"] = round(out["newton_pcg"]["steps_per_s"] / out["lbfgs"]["steps_per_s"], 1)
+    print("# first-order leg done", file=sys.stderr, flush=True)
     return out
 
 

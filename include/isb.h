@@ -80,6 +80,14 @@ typedef enum {
   ISB_ENERGY_STABLE_NEOHOOKEAN = 3
 } isb_energy_model;
 
+/* Forward minimiser of the step objective (ISB_OPT_FORWARD). The adjoint of Eq. 9 does not depend
+ * on it (Sec. 4: the rule differentiates the minimiser, not the iterations that found it).
+ *   NEWTON  inexact Newton with Jacobi-preconditioned CG over matrix-free Hessian-vector products
+ *   LBFGS   the paper's kind of forward pass: a descent method with line search that uses first
+ *           derivatives only (Sec. 6), here limited-memory BFGS (two-loop recursion, scaling
+ *           s^T y / y^T y); same Armijo line search and stopping rule as NEWTON; plain solver only */
+typedef enum { ISB_FORWARD_NEWTON = 0, ISB_FORWARD_LBFGS = 1 } isb_forward;
+
 /* Option keys for isb_set_option / isb_get_option. */
 typedef enum {
   ISB_OPT_SOLVER = 0,       /* 0 = plain: host-driven Newton-PCG, one body at a time, grid-wide kernels;
@@ -94,8 +102,12 @@ typedef enum {
                                triangles, 512 for tetrahedra */
   ISB_OPT_CG_CHECK = 4,     /* plain solver: read the CG convergence flag every k iterations (default 4) */
   ISB_OPT_PRECISION = 5,    /* isb_precision; equals the value given to isb_create */
-  ISB_OPT_ENERGY = 6        /* isotropic element energy, one of isb_energy_model (default neo-Hookean); the
+  ISB_OPT_ENERGY = 6,       /* isotropic element energy, one of isb_energy_model (default neo-Hookean); the
                              * batched solver runs the alternatives with the default workgroup size only */
+  ISB_OPT_FORWARD = 7,      /* forward minimiser of the plain solver, one of isb_forward (default Newton-PCG);
+                             * the batched solver takes ISB_FORWARD_NEWTON only (ISB_E_ARG otherwise) */
+  ISB_OPT_LBFGS_MEMORY = 8, /* pairs kept by ISB_FORWARD_LBFGS, 1..64 (default 8) */
+  ISB_OPT_LBFGS_MAX_ITERS = 9 /* iteration cap of ISB_FORWARD_LBFGS (default 20000; max_newton caps Newton) */
 } isb_option;
 
 /* Read-only context facts for isb_get_option. */

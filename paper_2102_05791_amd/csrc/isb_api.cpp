@@ -302,6 +302,75 @@ static isb_status run_cg(isb_ctx* c, int b, const double* x, const double* a, co
 }
 
 // one Newton-PCG solve of body b; x is the iterate (workspace), G its gradient
+// Armijo backtracking along dx from the iterate *px (gradient *pG, norm *res, g^T dx = gTd < 0) on
+// sum_e [g_e(x + alpha dx) - g_e(x)]. Below the FP64 resolution of g the gradient decides instead:
+// Newton takes the step if |grad g| at least halves and otherwise stops (shorter steps of a
+// quadratically convergent method cannot do better at the floor); a first-order method takes it if
+// the slope along dx has not turned past half its initial size, grad g(x + alpha dx) . dx <=
+// |gTd| / 2 (on a quadratic that holds up to 1.5 times the exact line minimiser, where g still
+// decreases), and otherwise halves alpha. On acceptance *px, *pG and *res hold the new iterate (the
+// buffers may swap with *pxt, *pGt) and *alpha_out the step taken.
+static isb_status line_search(isb_ctx* c, int b, hipStream_t s, const double* x0, const double* a, const double* dx,
+                              double gTd, bool first_order, double** px, double** pxt, double** pG,
+                              double** pGt, double* res, isb_stats* st, bool* accepted_out, double* alpha_out) {
+  const BodyRange br = body_range(c, b);
+  double *x = *px, *xt = *pxt, *G = *pG, *Gt = *pGt;
+  double alpha = 1.0;
+  bool accepted = false, via_grad = false;
+  for (int ls = 0; ls <= kMaxBacktracks; ++ls) {
+    enqueue_energy(c, b, x, dx, alpha, x0, a, c->dscal, s);
+    ISB_TRY(read_scal(c, s, 3));
+    const double dg = c->hscal[0], gabs = c->hscal[1];
+    if (!std::isfinite(dg)) {
+      // overflow or an invalid trial point: backtrack
+    } else if (std::fabs(dg) > 1e3 * kEps * gabs) {
+      accepted = dg <= kArmijoC1 * alpha * gTd;
+    } else {
+      // below the resolution of g the Armijo test only sees rounding
+      launch_copy(br.n, x + br.off, xt + br.off, s);
+      launch_axpy(br.n, xt + br.off, alpha, dx + br.off, s);
+      eval_grad(c, b, xt, x0, a, Gt, s);
+      enqueue_norm2(c, b, Gt, 0, s);
+      ISB_TRY(read_scal(c, s, 1));
+      const double rt = std::sqrt(c->hscal[0]);
+      bool take;
+      if (first_order) {
+        int nb = 0;
+        launch_dot(br.n, Gt + br.off, dx + br.off, c->partials, s, &nb);
+        launch_finalize(c->partials, nb, 1, c->dscal, s);
+        ISB_TRY(read_scal(c, s, 1));
+        take = c->hscal[0] <= 0.5 * std::fabs(gTd);
+      } else {
+        take = rt <= kFloorDecrease * *res;
+        if (!take) break;  // shorter steps cannot do better at the rounding floor
+      }
+      if (take) {
+        accepted = via_grad = true;
+        std::swap(x, xt);
+        std::swap(G, Gt);
+        *res = rt;
+      }
+    }
+    if (accepted) break;
+    alpha *= 0.5;
+    st->ls_backtracks += 1;
+  }
+  if (accepted && !via_grad) {
+    launch_axpy(br.n, x + br.off, alpha, dx + br.off, s);
+    eval_grad(c, b, x, x0, a, G, s);
+    enqueue_norm2(c, b, G, 0, s);
+    ISB_TRY(read_scal(c, s, 1));
+    *res = std::sqrt(c->hscal[0]);
+  }
+  *px = x;
+  *pxt = xt;
+  *pG = G;
+  *pGt = Gt;
+  *accepted_out = accepted;
+  *alpha_out = alpha;
+  return ISB_OK;
+}
+
 static isb_status plain_newton(isb_ctx* c, int b, hipStream_t s, const double* x0, const double* a, double** px,
                                double** pxt, double** pG, double** pGt, isb_stats* st) {
   const BodyRange br = body_range(c, b);
@@ -354,54 +423,146 @@ static isb_status plain_newton(isb_ctx* c, int b, hipStream_t s, const double* x
         break;
       }
     }
-    // Armijo backtracking on sum_e [g_e(x + alpha dx) - g_e(x)]; below the FP64 resolution of g
-    // the decrease of |grad g| decides instead
-    double alpha = 1.0;
-    bool accepted = false, via_grad = false;
-    for (int ls = 0; ls <= kMaxBacktracks; ++ls) {
-      enqueue_energy(c, b, x, dx, alpha, x0, a, c->dscal, s);
-      ISB_TRY(read_scal(c, s, 3));
-      const double dg = c->hscal[0], gabs = c->hscal[1];
-      if (!std::isfinite(dg)) {
-        // overflow or an invalid trial point: backtrack
-      } else if (std::fabs(dg) > 1e3 * kEps * gabs) {
-        accepted = dg <= kArmijoC1 * alpha * gTd;
-      } else {
-        // below the resolution of g the Armijo test only sees rounding
-        launch_copy(br.n, x + br.off, xt + br.off, s);
-        launch_axpy(br.n, xt + br.off, alpha, dx + br.off, s);
-        eval_grad(c, b, xt, x0, a, Gt, s);
-        enqueue_norm2(c, b, Gt, 0, s);
-        ISB_TRY(read_scal(c, s, 1));
-        const double rt = std::sqrt(c->hscal[0]);
-        if (rt <= kFloorDecrease * res) {
-          accepted = via_grad = true;
-          std::swap(x, xt);
-          std::swap(G, Gt);
-          res = rt;
-        } else {
-          break;  // shorter steps cannot do better at the rounding floor
-        }
-      }
-      if (accepted) break;
-      alpha *= 0.5;
-      st->ls_backtracks += 1;
-    }
+    bool accepted = false;
+    double alpha = 0.0;
+    ISB_TRY(line_search(c, b, s, x0, a, dx, gTd, false, &x, &xt, &G, &Gt, &res, st, &accepted, &alpha));
     if (!accepted) {
       st->flags |= ISB_FLAG_STAGNATED;
       break;
-    }
-    if (!via_grad) {
-      launch_axpy(br.n, x + br.off, alpha, dx + br.off, s);
-      eval_grad(c, b, x, x0, a, G, s);
-      enqueue_norm2(c, b, G, 0, s);
-      ISB_TRY(read_scal(c, s, 1));
-      res = std::sqrt(c->hscal[0]);
     }
     st->newton_iters += 1;
     if (!std::isfinite(res)) {
       st->flags |= ISB_FLAG_NONFINITE;
       status = fail(ISB_E_NONFINITE, "non-finite gradient");
+    }
+  }
+  st->res_final = res;
+  if (res <= sc.tol_rel * res0) st->flags |= ISB_FLAG_CONVERGED;
+  *px = x;
+  *pxt = xt;
+  *pG = G;
+  *pGt = Gt;
+  return status;
+}
+
+// dot product of two vectors over body b's DOFs, read back to the host
+static isb_status body_dot(isb_ctx* c, int b, const double* u, const double* v, hipStream_t s, double* out) {
+  const BodyRange br = body_range(c, b);
+  int nb = 0;
+  launch_dot(br.n, u + br.off, v + br.off, c->partials, s, &nb);
+  launch_finalize(c->partials, nb, 1, c->dscal, s);
+  ISB_TRY(read_scal(c, s, 1));
+  *out = c->hscal[0];
+  return ISB_OK;
+}
+
+// The first-order forward solver (ISB_FORWARD_LBFGS): limited-memory BFGS on the step objective,
+// which uses gradients only (Nocedal & Wright, Alg. 7.4 and 7.5, two-loop recursion with the
+// scaling s^T y / y^T y of the newest pair), the same Armijo line search and stopping rule as
+// Newton, and steepest descent of unit length as the first direction and whenever the recursion
+// does not give a descent direction. Pairs with s^T y <= 1e-12 |s| |y| are not stored. Iterations
+// are reported as newton_iters.
+static isb_status plain_lbfgs(isb_ctx* c, int b, hipStream_t s, const double* x0, const double* a, double** px,
+                              double** pxt, double** pG, double** pGt, isb_stats* st) {
+  const BodyRange br = body_range(c, b);
+  const isb_scene& sc = c->scene;
+  const int m = c->lbfgs_m, n = br.n, o = br.off;
+  const size_t nd = (size_t)c->n_v * c->dim;
+  double *x = *px, *xt = *pxt, *G = *pG, *Gt = *pGt;
+  double* q = c->w_p;      // the recursion's vector, then the direction's negative
+  double* Gold = c->w_r;   // gradient at the previous iterate
+  double* dx = c->w_xs;    // search direction
+  std::vector<double> rho(m), al(m);
+  std::vector<int> slot;   // history, oldest first; entries index the S and Y planes
+  int next = 0;
+  eval_grad(c, b, x, x0, a, G, s);
+  enqueue_norm2(c, b, G, 0, s);
+  ISB_TRY(read_scal(c, s, 1));
+  const double res0 = std::sqrt(c->hscal[0]);
+  double res = res0;
+  st->res0 = res0;
+  isb_status status = ISB_OK;
+  if (!std::isfinite(res0)) {
+    st->flags |= ISB_FLAG_NONFINITE;
+    status = fail(ISB_E_NONFINITE, "non-finite gradient at the initial guess");
+  }
+  while (status == ISB_OK) {
+    if (res <= sc.tol_rel * res0 || res == 0.0) {
+      st->flags |= ISB_FLAG_CONVERGED;
+      break;
+    }
+    if (st->newton_iters >= c->lbfgs_max_iters) {
+      status = fail(ISB_E_NOT_CONVERGED, "L-BFGS iteration cap reached");
+      break;
+    }
+    double gTd = 0.0;
+    if (!slot.empty()) {
+      // two-loop recursion: q = H_k G
+      launch_copy(n, G + o, q + o, s);
+      for (int k = (int)slot.size() - 1; k >= 0; --k) {
+        const int j = slot[k];
+        double sq = 0.0;
+        ISB_TRY(body_dot(c, b, c->w_lbS + (size_t)j * nd, q, s, &sq));
+        al[j] = rho[j] * sq;
+        launch_axpy(n, q + o, -al[j], c->w_lbY + (size_t)j * nd + o, s);
+      }
+      const int jn = slot.back();
+      double yy = 0.0;
+      ISB_TRY(body_dot(c, b, c->w_lbY + (size_t)jn * nd, c->w_lbY + (size_t)jn * nd, s, &yy));
+      const double gamma = 1.0 / (rho[jn] * yy);
+      launch_axpy(n, q + o, gamma - 1.0, q + o, s);
+      for (int k = 0; k < (int)slot.size(); ++k) {
+        const int j = slot[k];
+        double yq = 0.0;
+        ISB_TRY(body_dot(c, b, c->w_lbY + (size_t)j * nd, q, s, &yq));
+        launch_axpy(n, q + o, al[j] - rho[j] * yq, c->w_lbS + (size_t)j * nd + o, s);
+      }
+      launch_copy(n, q + o, dx + o, s);
+      launch_axpy(n, dx + o, -2.0, dx + o, s);  // dx = -q
+      ISB_TRY(body_dot(c, b, G, dx, s, &gTd));
+    }
+    if (!(gTd < 0.0)) {
+      // steepest descent of unit length; the history restarts
+      slot.clear();
+      launch_copy(n, G + o, dx + o, s);
+      launch_axpy(n, dx + o, -1.0 - 1.0 / res, dx + o, s);  // dx = -G / |G|
+      gTd = -res;
+    }
+    launch_copy(n, G + o, Gold + o, s);
+    bool accepted = false;
+    double alpha = 0.0;
+    ISB_TRY(line_search(c, b, s, x0, a, dx, gTd, true, &x, &xt, &G, &Gt, &res, st, &accepted, &alpha));
+    if (!accepted) {
+      st->flags |= ISB_FLAG_STAGNATED;
+      break;
+    }
+    st->newton_iters += 1;
+    if (!std::isfinite(res)) {
+      st->flags |= ISB_FLAG_NONFINITE;
+      status = fail(ISB_E_NONFINITE, "non-finite gradient");
+      break;
+    }
+    // the new pair s = alpha dx, y = G - G_old, written over the oldest pair when the history is full
+    const int j = next;
+    for (size_t k = 0; k < slot.size(); ++k)
+      if (slot[k] == j) {
+        slot.erase(slot.begin() + k);
+        break;
+      }
+    double* Sj = c->w_lbS + (size_t)j * nd;
+    double* Yj = c->w_lbY + (size_t)j * nd;
+    launch_copy(n, dx + o, Sj + o, s);
+    launch_axpy(n, Sj + o, alpha - 1.0, Sj + o, s);
+    launch_copy(n, G + o, Yj + o, s);
+    launch_axpy(n, Yj + o, -1.0, Gold + o, s);
+    double sy = 0.0, ss = 0.0, yy = 0.0;
+    ISB_TRY(body_dot(c, b, Sj, Yj, s, &sy));
+    ISB_TRY(body_dot(c, b, Sj, Sj, s, &ss));
+    ISB_TRY(body_dot(c, b, Yj, Yj, s, &yy));
+    if (sy > 1e-12 * std::sqrt(ss * yy)) {
+      slot.push_back(j);
+      rho[j] = 1.0 / sy;
+      next = (j + 1) % m;
     }
   }
   st->res_final = res;
@@ -442,6 +603,15 @@ static isb_status plain_step(isb_ctx* c, hipStream_t s, const double* x0, const 
   const DevMesh m = devmesh(c);
   const DevScene dsc = devscene(c);
   if (c->precision == ISB_MIXED) launch_to_f32(c->n_e, a, c->w_a32, s);
+  if (c->forward == ISB_FORWARD_LBFGS && c->lbfgs_alloc_m != c->lbfgs_m) {
+    // the first-order solver's history: lbfgs_m pairs (s, y) of full DOF vectors
+    const size_t nd = (size_t)c->n_v * c->dim * (size_t)c->lbfgs_m;
+    ISB_TRY(dalloc(c->work_allocs, &c->w_lbS, nd));
+    ISB_TRY(dalloc(c->work_allocs, &c->w_lbY, nd));
+    ISB_HIP(hipMemset(c->w_lbS, 0, nd * sizeof(double)));
+    ISB_HIP(hipMemset(c->w_lbY, 0, nd * sizeof(double)));
+    c->lbfgs_alloc_m = c->lbfgs_m;
+  }
   isb_status worst = ISB_OK;
   for (int b = 0; b < c->n_bodies; ++b) {
     const BodyRange br = body_range(c, b);
@@ -449,7 +619,8 @@ static isb_status plain_step(isb_ctx* c, hipStream_t s, const double* x0, const 
     std::memset(&st, 0, sizeof(st));
     double *x = c->w_x, *xt = c->w_xt, *G = c->w_G, *Gt = c->w_Gt;
     launch_setup(m, dsc, br.v0, br.v1, x0, dsc.be ? v0 : nullptr, x, c->w_xhat, c->w_cv, s);
-    isb_status r = plain_newton(c, b, s, x0, a, &x, &xt, &G, &Gt, &st);
+    isb_status r = c->forward == ISB_FORWARD_LBFGS ? plain_lbfgs(c, b, s, x0, a, &x, &xt, &G, &Gt, &st)
+                                                   : plain_newton(c, b, s, x0, a, &x, &xt, &G, &Gt, &st);
     if (r == ISB_E_HIP) return r;
     launch_copy(br.n, x + br.off, x1 + br.off, s);
     if (dsc.be && v1) launch_velocity(br.n, x1 + br.off, x0 + br.off, 1.0 / dsc.h, v1 + br.off, s);
@@ -510,6 +681,8 @@ static isb_status plain_adjoint(isb_ctx* c, hipStream_t s, const double* x1, con
 // ---------------------------------------------------------------------------------------------
 static isb_status alloc_workspaces(isb_ctx* c) {
   c->free_list(c->work_allocs);
+  c->w_lbS = c->w_lbY = nullptr;
+  c->lbfgs_alloc_m = 0;
   const size_t nd = (size_t)c->n_v * c->dim;
   auto& L = c->work_allocs;
   for (double** p : {&c->w_x, &c->w_xt, &c->w_xhat, &c->w_G, &c->w_Gt, &c->w_xs, &c->w_r, &c->w_p, &c->w_Hp,
@@ -765,6 +938,19 @@ isb_status isb_set_option(isb_ctx* c, int key, int64_t value) {
         return fail(ISB_E_ARG, "energy must be one of ISB_ENERGY_*");
       c->model = (int)value;
       return ISB_OK;
+    case ISB_OPT_FORWARD:
+      if (value != ISB_FORWARD_NEWTON && value != ISB_FORWARD_LBFGS)
+        return fail(ISB_E_ARG, "forward must be ISB_FORWARD_NEWTON or ISB_FORWARD_LBFGS");
+      c->forward = (int)value;
+      return ISB_OK;
+    case ISB_OPT_LBFGS_MEMORY:
+      if (value < 1 || value > 64) return fail(ISB_E_ARG, "lbfgs memory must be in [1, 64]");
+      c->lbfgs_m = (int)value;
+      return ISB_OK;
+    case ISB_OPT_LBFGS_MAX_ITERS:
+      if (value < 1 || value > 10000000) return fail(ISB_E_ARG, "lbfgs iteration cap must be in [1, 1e7]");
+      c->lbfgs_max_iters = (int)value;
+      return ISB_OK;
     default:
       return fail(ISB_E_ARG, "unknown or read-only option key " + std::to_string(key));
   }
@@ -781,6 +967,9 @@ isb_status isb_get_option(isb_ctx* c, int key, int64_t* value) {
     case ISB_OPT_CG_CHECK: *value = c->cg_check; return ISB_OK;
     case ISB_OPT_PRECISION: *value = c->precision; return ISB_OK;
     case ISB_OPT_ENERGY: *value = c->model; return ISB_OK;
+    case ISB_OPT_FORWARD: *value = c->forward; return ISB_OK;
+    case ISB_OPT_LBFGS_MEMORY: *value = c->lbfgs_m; return ISB_OK;
+    case ISB_OPT_LBFGS_MAX_ITERS: *value = c->lbfgs_max_iters; return ISB_OK;
     case ISB_INFO_N_VERTICES: *value = c->n_v; return ISB_OK;
     case ISB_INFO_N_ELEMENTS: *value = c->n_e; return ISB_OK;
     case ISB_INFO_N_BODIES: *value = c->n_bodies; return ISB_OK;
@@ -807,7 +996,11 @@ isb_status isb_step(isb_ctx* c, isb_stream stream, const double* x0, const doubl
   if (!x0 || !a || !x1 || (be && !v0)) return fail(ISB_E_ARG, "NULL state argument");
   hipStream_t s = (hipStream_t)stream;
   if (per_body) std::memset(per_body, 0, sizeof(isb_stats) * c->n_bodies);
-  if (c->solver == 1) return batched_step(c, s, x0, be ? v0 : nullptr, a, x1, be ? v1 : nullptr, per_body);
+  if (c->solver == 1) {
+    if (c->forward != ISB_FORWARD_NEWTON)
+      return fail(ISB_E_ARG, "the batched solver runs Newton-PCG only (ISB_OPT_FORWARD)");
+    return batched_step(c, s, x0, be ? v0 : nullptr, a, x1, be ? v1 : nullptr, per_body);
+  }
   ISB_TRY(check_actuation(c, s, a));
   return plain_step(c, s, x0, v0, a, x1, v1, per_body);
 }

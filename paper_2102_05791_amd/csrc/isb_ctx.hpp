@@ -57,12 +57,15 @@ struct isb_ctx {
   // options
   int solver = 0, scatter = 2, graph_safe = 0, block = 0 /* 0: 768 in 2D, 512 in 3D */, cg_check = 4;
   int model = 0;  // ISB_ENERGY_*
+  int forward = 0, lbfgs_m = 8, lbfgs_max_iters = 20000;  // ISB_OPT_FORWARD and the L-BFGS settings
 
   // plain-solver workspaces, [n_v*dim] unless noted
   double *w_x = nullptr, *w_xt = nullptr, *w_xhat = nullptr, *w_cv = nullptr /*[n_v]*/, *w_G = nullptr,
          *w_Gt = nullptr, *w_xs = nullptr, *w_r = nullptr, *w_p = nullptr, *w_Hp = nullptr, *w_Dinvp = nullptr,
          *w_vdiag = nullptr, *w_diag = nullptr;
   float* w_a32 = nullptr;           // [n_e]
+  double *w_lbS = nullptr, *w_lbY = nullptr;  // [lbfgs_m][n_v*dim] L-BFGS pairs (allocated on first use)
+  int lbfgs_alloc_m = 0;
   double* partials = nullptr;       // reduction partials
   double* dscal = nullptr;          // small device results (finalize outputs)
   double* ebuf = nullptr;           // [3*n_bodies] per-body energy comps

@@ -20,7 +20,9 @@ STATUS_NAMES = {0: "ISB_OK", 1: "ISB_E_ARG", 2: "ISB_E_MESH", 3: "ISB_E_HIP", 4:
                 5: "ISB_E_NONFINITE", 6: "ISB_E_STATE"}
 ISB_FP64, ISB_MIXED = 0, 1
 ISB_QUASISTATIC, ISB_BACKWARD_EULER = 0, 1
-OPT_SOLVER, OPT_SCATTER, OPT_GRAPH_SAFE, OPT_BLOCK, OPT_CG_CHECK, OPT_PRECISION, OPT_ENERGY = range(7)
+(OPT_SOLVER, OPT_SCATTER, OPT_GRAPH_SAFE, OPT_BLOCK, OPT_CG_CHECK, OPT_PRECISION, OPT_ENERGY, OPT_FORWARD,
+ OPT_LBFGS_MEMORY, OPT_LBFGS_MAX_ITERS) = range(10)
+FORWARD_NEWTON, FORWARD_LBFGS = 0, 1
 # isotropic element energies (ISB_ENERGY_*), by the names the synthetic workloads use
 ENERGY = {"nh": 0, "stvk": 1, "corot": 2, "snh": 3}
 INFO_N_VERTICES, INFO_N_ELEMENTS, INFO_N_BODIES, INFO_DIM, INFO_N_COLOURS, INFO_LDS_BYTES = range(100, 106)
