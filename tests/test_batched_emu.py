@@ -93,8 +93,10 @@ def test_emulated_batched_energy_models(emu_mod, model, dim):
     The mixed adjoint solves with the FP32 operator; St. Venant-Kirchhoff forms E = (F^T F - I)/2
     from an FP32 F, which cancels near rest and leaves E about 6e-8/|E| relative precision, so the
     mixed adjoint bar of the alternative models is 3e-5 (the step stays at 1e-5)."""
-    shape = (5, 2) if dim == 2 else (2, 2, 1)
-    w, rng = rand_workload(dim, seed=24, bodies=2, shape=shape)
+    # small bodies: the host-thread emulation pays a barrier per wave operation (the GPU tests
+    # cover the same paths at full size)
+    shape = (4, 2) if dim == 2 else (2, 1, 1)
+    w, rng = rand_workload(dim, seed=24, bodies=2 if dim == 2 else 1, shape=shape)
     w = _tight(w)
     w.model = model
     probs = problems(w)
