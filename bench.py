@@ -395,7 +395,7 @@ def main():
     tet = None if args.no_tet else tet_leg(args, torch, Context, isb, scenes)
     elem = None if args.no_elem_roofline else element_roofline_leg(args, torch, Context, isb, scenes)
     if elem:
-        for prec in ("fp64", "mixed"):
+        for prec in ("fp64", "mixed", "gradient_fp64"):
             elem[prec]["frac_of_copy_ceiling"] = round(elem[prec]["achieved_GBs"] / ceiling["GBs"], 4)
 
     line = {"metric": METRIC, "value": round(value, 1), "unit": "body-steps/s", "n_gpus": 1,
@@ -700,8 +700,9 @@ def tet_leg(args, torch, Context, isb, scenes):
 
 
 def element_roofline_leg(args, torch, Context, isb, scenes):
-    """Element Hessian-vector kernel alone (isb_hessvec_elements) on a mesh whose element data
-    exceeds the 256 MB last-level cache; algorithmic bytes / HIP-event time, FP64 and mixed."""
+    """Element Hessian-vector kernel alone (isb_hessvec_elements, FP64 and mixed) and the element
+    gradient kernel alone (isb_gradient_elements, FP64) on a mesh whose element data exceeds the
+    256 MB last-level cache; algorithmic bytes / HIP-event time."""
     from synth import meshes
     dev = torch.device("cuda:0")
     nx, ny, nz = (int(v) for v in args.elem_grid.split("x"))
@@ -737,6 +738,26 @@ def element_roofline_leg(args, torch, Context, isb, scenes):
         gbs = byt / (ms * 1e-3) / 1e9
         out[prec] = {"launch_ms": round(ms, 4), "algorithmic_bytes": int(byt), "achieved_GBs": round(gbs, 1),
                      "frac_of_8TBs": round(gbs / HBM_PEAK_GBS, 4), "element_bytes": elem_b}
+        if prec == "fp64":
+            # the element gradient (FP64 in both precisions): element data once, x read, g read and written
+            g = torch.zeros_like(x)
+            for _ in range(3):
+                ctx.gradient_elements(x, a, g)
+            torch.cuda.synchronize()
+            evs = []
+            for _ in range(20):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                ctx.gradient_elements(x, a, g)
+                e1.record()
+                evs.append((e0, e1))
+            torch.cuda.synchronize()
+            gms = float(np.median([e0.elapsed_time(e1) for e0, e1 in evs]))
+            gbyt = n_e * elem_bytes(3, 8) + n_v * 3 * (8 + 16)
+            ggbs = gbyt / (gms * 1e-3) / 1e9
+            out["gradient_fp64"] = {"launch_ms": round(gms, 4), "algorithmic_bytes": int(gbyt),
+                                    "achieved_GBs": round(ggbs, 1), "frac_of_8TBs": round(ggbs / HBM_PEAK_GBS, 4),
+                                    "element_bytes": elem_bytes(3, 8)}
         del ctx
         torch.cuda.empty_cache()
     print("# element roofline leg done", file=sys.stderr, flush=True)

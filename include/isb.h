@@ -271,6 +271,11 @@ isb_status isb_hessvec(isb_ctx* ctx, isb_stream stream, const double* x, const d
  * its own, for callers that add their own vertex terms and for timing. device [n_v][dim] in/in-out. */
 isb_status isb_hessvec_elements(isb_ctx* ctx, isb_stream stream, const double* x, const double* a,
                                 const double* p, double* hp);
+/* Element part of the gradient only, added into g: g += sum_e W_e P(F_e) Dm^-T scattered to the
+ * element's vertices (Eq. 4-5), plus the springs' forces (no vertex terms, no projection onto free
+ * DOFs), scaled by h^2 in backward Euler; FP64 in both precisions. The gradient kernel on its own,
+ * for callers that add their own vertex terms and for timing. device [n_v][dim] in/in-out. */
+isb_status isb_gradient_elements(isb_ctx* ctx, isb_stream stream, const double* x, const double* a, double* g);
 /* Diagonal of H(x) over free DOFs (1 on pinned DOFs), FP64 in both precisions, device out [n_v][dim]. */
 isb_status isb_hessdiag(isb_ctx* ctx, isb_stream stream, const double* x, const double* x0,
                         const double* a, double* diag);

@@ -1198,6 +1198,15 @@ isb_status isb_hessvec_elements(isb_ctx* c, isb_stream stream, const double* x, 
   return ISB_OK;
 }
 
+isb_status isb_gradient_elements(isb_ctx* c, isb_stream stream, const double* x, const double* a, double* g) {
+  clear_error();
+  ISB_TRY(check_ctx(c, true));
+  if (!x || !a || !g) return fail(ISB_E_ARG, "NULL argument");
+  elem_scatter(c, -1, PATCH_GRAD, x, a, nullptr, g, nullptr, (hipStream_t)stream);
+  ISB_HIP(hipGetLastError());
+  return ISB_OK;
+}
+
 isb_status isb_hessdiag(isb_ctx* c, isb_stream stream, const double* x, const double* x0, const double* a,
                         double* diag) {
   clear_error();

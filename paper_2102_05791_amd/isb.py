@@ -32,7 +32,8 @@ EXPORTED = ("isb_create", "isb_destroy", "isb_last_error", "isb_version", "isb_v
             "isb_colour_elements", "isb_mesh_upload", "isb_material_upload", "isb_set_scene",
             "isb_set_option", "isb_get_option", "isb_get_mass", "isb_step", "isb_solve_adjoint",
             "isb_vjp_params", "isb_energy", "isb_gradient", "isb_hessvec", "isb_hessvec_elements",
-            "isb_hessdiag", "isb_stream_copy", "isb_spring_upload", "isb_vjp_spring_stiffness")
+            "isb_hessdiag", "isb_stream_copy", "isb_spring_upload", "isb_vjp_spring_stiffness",
+            "isb_gradient_elements")
 
 
 class IsbError(RuntimeError):
@@ -108,6 +109,7 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
         "isb_hessvec": [vp, vp, vp, vp, vp, vp, vp],
         "isb_hessvec_elements": [vp, vp, vp, vp, vp, vp],
         "isb_hessdiag": [vp, vp, vp, vp, vp, vp],
+        "isb_gradient_elements": [vp, vp, vp, vp, vp],
         "isb_stream_copy": [vp, vp, vp, i64],
         "isb_spring_upload": [vp, i64, vp, vp, vp],
         "isb_vjp_spring_stiffness": [vp, vp, vp, vp, vp, vp],
@@ -348,6 +350,11 @@ class Context:
         """isb_hessvec_elements: hp += element part of H(x) p (no vertex terms, no projection)."""
         _check(self.lib, self.lib.isb_hessvec_elements(self.h, _stream(), _dev(x), self._a(a), _dev(p), _dev(hp)))
         return hp
+
+    def gradient_elements(self, x, a, g):
+        """isb_gradient_elements: g += element (and spring) part of grad g(x) (no vertex terms)."""
+        _check(self.lib, self.lib.isb_gradient_elements(self.h, _stream(), _dev(x), self._a(a), _dev(g)))
+        return g
 
     def hessdiag(self, x, x0, a):
         d = self._empty(self.n_v, self.dim)

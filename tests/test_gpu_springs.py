@@ -5,7 +5,7 @@ paths."""
 import numpy as np
 import pytest
 
-from oracle import solve
+from oracle import fem, solve
 from oracle.fem import Problem
 from synth import scenes
 from tests.gpu_util import abs_assembly, rand_workload, rel, with_springs
@@ -118,6 +118,12 @@ def test_spring_hessvec_elements_includes_springs():
                 w.S, w.ks)
     ref = p.s_pot * (q.hessian(x, w.x0, a) @ pv.ravel())
     assert rel(hp.cpu().numpy().ravel(), ref) <= 1e-12
+    # isb_gradient_elements: the element and spring forces alone, added into g
+    g = torch.ones(w.n_v, 2, dtype=torch.float64, device="cuda:0")
+    ctx.gradient_elements(_dev(x), _dev(a), g)
+    ae, as_ = p.split(a)
+    gref = 1.0 + p.s_pot * (p.element_grad(x, ae) + fem.spring_grad(x, p.S, p.ks, p.l0, as_))
+    assert rel(g.cpu().numpy(), gref) <= 1e-13
 
 
 @pytest.mark.parametrize("case", CASES, ids=IDS)
