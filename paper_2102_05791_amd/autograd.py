@@ -3,7 +3,8 @@
 ImplicitStep: one step as a differentiable layer (the integration cell of Sec. 5, Fig.
 dynamics-cell): the forward is isb_step; the backward is the adjoint solve of Eq. 9
 (isb_solve_adjoint) followed by isb_vjp_params, which also carries the explicit
-v1 = (x1 - x0)/h path of Eq. 14.
+v1 = (x1 - x0)/h path of Eq. 14, and, when the per-element Lame pair and fibre stiffness are
+passed as inputs, their cotangents.
 
 CheckpointedRollout: backpropagation through time over T steps (Sec. 5.1) storing only every
 K-th state; the backward recomputes one K-step segment at a time from its checkpoint, so
@@ -18,11 +19,14 @@ from .isb import Context
 
 class ImplicitStep(torch.autograd.Function):
     @staticmethod
-    def forward(fctx, ctx: Context, x0, v0, a):
+    def forward(fctx, ctx: Context, x0, v0, a, mu=None, lam=None, kf=None):
+        if mu is not None:
+            ctx.set_material_params(mu, lam, kf)
         x1, v1, _, _ = ctx.step(x0, v0, a, stats=False)
         if v1 is None:
             v1 = torch.zeros_like(x1)
         fctx.ctx = ctx
+        fctx.with_material = mu is not None
         fctx.save_for_backward(x0, a, x1)
         return x1, v1
 
@@ -33,12 +37,19 @@ class ImplicitStep(torch.autograd.Function):
         x1_bar = torch.zeros_like(x1) if x1_bar is None else x1_bar.contiguous()
         v1_bar = None if v1_bar is None else v1_bar.contiguous()
         w, _, _ = ctx.solve_adjoint(x1, x0, a, x1_bar, v1_bar, stats=False)
-        out = ctx.vjp_params(w, x1, x0, a, v1_bar, want=("a_bar", "x0_bar", "v0_bar"))
-        return None, out["x0_bar"], out["v0_bar"], out["a_bar"]
+        want = ("a_bar", "x0_bar", "v0_bar") + (("mu_bar", "lam_bar", "kf_bar") if fctx.with_material else ())
+        out = ctx.vjp_params(w, x1, x0, a, v1_bar, want=want)
+        mat = (out["mu_bar"], out["lam_bar"], out["kf_bar"]) if fctx.with_material else (None, None, None)
+        return (None, out["x0_bar"], out["v0_bar"], out["a_bar"]) + mat
 
 
-def implicit_step(ctx: Context, x0, v0, a):
-    return ImplicitStep.apply(ctx, x0, v0, a)
+def implicit_step(ctx: Context, x0, v0, a, mu=None, lam=None, kf=None):
+    """One differentiable step. With mu, lam, kf (device tensors [n_e], e.g. requiring grad) the
+    step runs with that Lame pair and fibre stiffness, uploaded when they differ from the context's
+    current ones (a host copy), and the backward also returns their cotangents (Eq. 9)."""
+    if (mu is None) != (lam is None) or (mu is None) != (kf is None):
+        raise ValueError("give all of mu, lam, kf or none of them")
+    return ImplicitStep.apply(ctx, x0, v0, a, mu, lam, kf)
 
 
 class CheckpointedRollout(torch.autograd.Function):

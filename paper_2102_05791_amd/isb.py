@@ -246,6 +246,19 @@ class Context:
         sc = Scene.from_dict(scene)
         _check(self.lib, self.lib.isb_material_upload(self.h, *[p for _, p in arrs], ctypes.byref(sc)))
         self.scene = dict(scene)
+        # host copies: the differentiable step re-uploads the Lame pair and k_f when they change
+        self.material = {k: a.copy() for k, (a, _) in zip(("mu", "lam", "kf", "fdir", "rho"), arrs)}
+
+    def set_material_params(self, mu, lam, kf):
+        """Upload a new Lame pair and fibre stiffness per element (host or device arrays [n_e]),
+        keeping the fibre directions, densities and scene; no-op when the values are unchanged."""
+        new = [np.ascontiguousarray(v.detach().cpu().numpy() if hasattr(v, "detach") else v, dtype=np.float64)
+               for v in (mu, lam, kf)]
+        old = self.material
+        if all(np.array_equal(n, old[k]) for n, k in zip(new, ("mu", "lam", "kf"))):
+            return False
+        self.material_upload(new[0], new[1], new[2], old["fdir"], old["rho"], self.scene)
+        return True
 
     def set_scene(self, scene: dict):
         sc = Scene.from_dict(scene)

@@ -25,7 +25,8 @@ class FibrePolicy(torch.nn.Module):
     """pi_theta(x, v) -> a, one actuation per element, a in (1 - max_contraction, 1).
 
     mass: lumped vertex masses [n_v] (isb_get_mass), which weight the centre; dim: 2 or 3; n_e:
-    elements of the body. Weights start uniform in +-1/sqrt(fan_in) from a seeded generator, so
+    actions per step, one per element (plus one per spring when the body has springs, whose
+    actions follow the elements'). Weights start uniform in +-1/sqrt(fan_in) from a seeded generator, so
     two policies built with the same arguments are identical (on any device)."""
 
     def __init__(self, mass, dim: int, n_e: int, hidden: int = 32, max_contraction: float = 0.3, seed: int = 0):

@@ -53,6 +53,34 @@ def test_implicit_step_autograd_matches_oracle():
         assert err <= 1e-10, key
 
 
+def test_implicit_step_material_gradients_and_reupload():
+    """The Lame pair and fibre stiffness as differentiable inputs: their cotangents match the oracle's
+    (Eq. 9), and new values take effect in the next step (re-uploaded)."""
+    import torch
+    from paper_2102_05791_amd import Context
+    from paper_2102_05791_amd.autograd import implicit_step
+    w = _tight(scenes.be_strip(nx=12, ny=4, steps=2))
+    ctx = Context.from_workload(w, precision="fp64", solver=0)
+    rng = np.random.default_rng(5)
+    for scale in (1.0, 1.1):
+        mu_np, lam_np, kf_np = w.mu * scale, w.lam * (2.0 - scale), w.kf * scale
+        mu, lam, kf = (_dev(v, requires_grad=True) for v in (mu_np, lam_np, kf_np))
+        x0, v0, a = _dev(w.x0), _dev(w.v0), _dev(w.actions[0])
+        x1, v1 = implicit_step(ctx, x0, v0, a, mu, lam, kf)
+        c1 = rng.normal(size=w.x0.shape)
+        ((x1 * _dev(c1)).sum()).backward()
+        wm = scenes.Workload(w.name, 2, w.X, w.T, w.pinned, mu_np, lam_np, kf_np, w.fdir, w.rho, w.scene,
+                             w.x0, w.v0, w.actions)
+        p = Problem.from_workload(wm)
+        xr, _, _ = solve.step(p, w.x0, w.v0, w.actions[0], tol=1e-13)
+        assert np.linalg.norm(x1.detach().cpu().numpy() - xr) <= 1e-10 * np.linalg.norm(xr - w.x0)
+        wv = solve.adjoint(p, xr, w.x0, w.actions[0], c1)
+        ref = solve.vjp_params(p, wv, xr, w.x0, w.actions[0])
+        for got, key in ((mu.grad, "mu_bar"), (lam.grad, "lam_bar"), (kf.grad, "kf_bar")):
+            g = got.cpu().numpy()
+            assert np.linalg.norm(g - ref[key]) <= 1e-9 * np.linalg.norm(ref[key]), key
+
+
 def _replicate(w, actions_per_body):
     """One batched workload holding copies of body w, body b driven by actions_per_body[b]."""
     nb = len(actions_per_body)
