@@ -38,6 +38,7 @@ isb_ctx::~isb_ctx() {
   free_list(mesh_allocs);
   if (hscal) (void)hipHostFree(hscal);
   if (hcg) (void)hipHostFree(hcg);
+  if (cap_stream) (void)hipStreamDestroy(cap_stream);
 }
 
 namespace isb {
@@ -271,27 +272,61 @@ static void enqueue_energy(isb_ctx* c, int b, const double* x, const double* dx,
   launch_finalize(c->partials, nbe + nbs + nbv, 3, out, s);
 }
 
-// PCG on H(x) xs = sign * rhs over body b; returns iterations, sets negcurv and the final r.r
+// one CG iteration over body b: the Hessian-vector product, then the three vector kernels (every
+// kernel returns at once when the device flag says the solve is done)
+static void cg_iteration(isb_ctx* c, int b, const double* x, const double* a, hipStream_t s) {
+  const BodyRange br = body_range(c, b);
+  const int o = br.off;
+  elem_scatter(c, b, PATCH_HV, x, a, c->w_p, c->w_Hp, &c->scal->done, s);
+  launch_cg_dot(br.n, c->w_p + o, c->w_Hp + o, c->partials, c->scal, s);
+  launch_cg_update(br.n, c->w_p + o, c->w_Hp + o, c->w_Dinvp + o, c->w_r + o, c->w_xs + o, c->partials, c->scal, s);
+  launch_cg_p(br.n, c->w_r + o, c->w_Dinvp + o, c->w_vdiag + o, c->w_p + o, c->w_Hp + o, c->partials, c->scal, s);
+}
+
+// Iterations per captured chunk of the graph mode: a chunk is replayed until the device flag says
+// the solve is done; the iterations of the last chunk past that point return at once.
+static constexpr int kCgChunk = 8;
+
+// PCG on H(x) xs = sign * rhs over body b; returns iterations, sets negcurv and the final r.r.
+// Graph mode (ISB_OPT_CG_GRAPH): a chunk of kCgChunk iterations is captured once per solve on an
+// internal stream and replayed on `s`, one launch and one host read per chunk instead of four
+// launches per iteration and a read every cg_check iterations.
 static isb_status run_cg(isb_ctx* c, int b, const double* x, const double* a, const double* rhs, double sign,
                          double tol, int max_cg, hipStream_t s, int* iters, bool* negcurv, double* rr) {
-  const DevMesh m = devmesh(c);
-  const DevScene sc = devscene(c);
   const BodyRange br = body_range(c, b);
-  const double tol2 = tol * tol;
   const int o = br.off;
   launch_cg_start(br.n, rhs + o, sign, c->w_Dinvp + o, c->w_vdiag + o, c->w_r + o, c->w_p + o, c->w_xs + o,
-                  c->w_Hp + o, c->partials, c->scal, tol2, s);
-  const int check = std::max(1, c->cg_check);
-  for (int it = 0; it < max_cg; ++it) {
-    elem_scatter(c, b, PATCH_HV, x, a, c->w_p, c->w_Hp, &c->scal->done, s);
-    launch_cg_dot(br.n, c->w_p + o, c->w_Hp + o, c->partials, c->scal, s);
-    launch_cg_update(br.n, it, c->w_p + o, c->w_Hp + o, c->w_Dinvp + o, c->w_r + o, c->w_xs + o, c->partials,
-                     c->scal, s);
-    launch_cg_p(br.n, it, c->w_r + o, c->w_Dinvp + o, c->w_vdiag + o, c->w_p + o, c->w_Hp + o, c->partials,
-                c->scal, tol2, s);
-    if (it == 0 || (it + 1) % check == 0 || it + 1 == max_cg) {
-      ISB_TRY(read_cg(c, s));
-      if (c->hcg->done) break;
+                  c->w_Hp + o, c->partials, c->scal, tol * tol, max_cg, s);
+  if (c->cg_graph && max_cg > kCgChunk) {
+    if (!c->cap_stream) ISB_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ISB_HIP(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < kCgChunk; ++k) cg_iteration(c, b, x, a, c->cap_stream);
+    const hipError_t ce = hipStreamEndCapture(c->cap_stream, &graph);
+    if (ce != hipSuccess) return fail(ISB_E_HIP, std::string("CG graph capture: ") + hipGetErrorString(ce));
+    const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) return fail(ISB_E_HIP, std::string("CG graph instantiation: ") + hipGetErrorString(ie));
+    isb_status st = ISB_OK;
+    for (int done_its = 0; done_its < max_cg; done_its += kCgChunk) {
+      const hipError_t le = hipGraphLaunch(exec, s);
+      if (le != hipSuccess) {
+        st = fail(ISB_E_HIP, std::string("CG graph launch: ") + hipGetErrorString(le));
+        break;
+      }
+      if ((st = read_cg(c, s)) != ISB_OK || c->hcg->done) break;
+    }
+    (void)hipGraphExecDestroy(exec);
+    if (st != ISB_OK) return st;
+  } else {
+    const int check = std::max(1, c->cg_check);
+    for (int it = 0; it < max_cg; ++it) {
+      cg_iteration(c, b, x, a, s);
+      if (it == 0 || (it + 1) % check == 0 || it + 1 == max_cg) {
+        ISB_TRY(read_cg(c, s));
+        if (c->hcg->done) break;
+      }
     }
   }
   ISB_TRY(read_cg(c, s));
@@ -938,6 +973,9 @@ isb_status isb_set_option(isb_ctx* c, int key, int64_t value) {
         return fail(ISB_E_ARG, "energy must be one of ISB_ENERGY_*");
       c->model = (int)value;
       return ISB_OK;
+    case ISB_OPT_CG_GRAPH:
+      c->cg_graph = value != 0;
+      return ISB_OK;
     case ISB_OPT_FORWARD:
       if (value != ISB_FORWARD_NEWTON && value != ISB_FORWARD_LBFGS)
         return fail(ISB_E_ARG, "forward must be ISB_FORWARD_NEWTON or ISB_FORWARD_LBFGS");
@@ -968,6 +1006,7 @@ isb_status isb_get_option(isb_ctx* c, int key, int64_t* value) {
     case ISB_OPT_PRECISION: *value = c->precision; return ISB_OK;
     case ISB_OPT_ENERGY: *value = c->model; return ISB_OK;
     case ISB_OPT_FORWARD: *value = c->forward; return ISB_OK;
+    case ISB_OPT_CG_GRAPH: *value = c->cg_graph; return ISB_OK;
     case ISB_OPT_LBFGS_MEMORY: *value = c->lbfgs_m; return ISB_OK;
     case ISB_OPT_LBFGS_MAX_ITERS: *value = c->lbfgs_max_iters; return ISB_OK;
     case ISB_INFO_N_VERTICES: *value = c->n_v; return ISB_OK;

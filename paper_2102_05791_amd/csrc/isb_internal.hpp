@@ -69,15 +69,21 @@ constexpr int kPatchLdsBytes = 64 * 1024;  // LDS per patch workgroup (two workg
 
 enum PatchOp { PATCH_GRAD = 0, PATCH_HV = 1, PATCH_DIAG = 2 };
 
-// Device-resident CG scalars of the plain solver (one solve at a time).
+// Device-resident CG scalars of the plain solver (one solve at a time). The iteration index lives
+// here too, so that a captured chunk of iterations can be replayed: k_cg_update reads the completed
+// count and publishes it in it_cur, k_cg_p reads it_cur and advances the count (each kernel only
+// reads what the previous one wrote).
 struct CgScal {
   double rz[2];    // r.z of the current iterate, double-buffered by iteration parity
   double rr;       // r.r
   double pHp;
   double rr0;      // r.r at the start
-  int done;        // converged or stopped by curvature
+  double tol2;     // stop when r.r <= tol2
+  int done;        // converged, stopped by curvature, or at the iteration cap
   int negcurv;     // non-positive curvature met
   int iters;       // completed iterations
+  int it_cur;      // the iteration in progress
+  int max_it;      // iteration cap
   int pad;
 };
 
@@ -153,12 +159,13 @@ void launch_stream_copy(int64_t n, const double* src, double* dst, hipStream_t s
 
 // CG on H xs = sign * b (b is masked to the free DOFs, where D^-1 != 0)
 void launch_cg_start(int n, const double* b, double sign, const double* Dinvp, const double* vdiag, double* r,
-                     double* p, double* xs, double* Hp, double* partials, CgScal* scal, double tol2, hipStream_t s);
+                     double* p, double* xs, double* Hp, double* partials, CgScal* scal, double tol2, int max_it,
+                     hipStream_t s);
 void launch_cg_dot(int n, const double* p, const double* Hp, double* partials, const CgScal* scal, hipStream_t s);
-void launch_cg_update(int n, int it, const double* p, const double* Hp, const double* Dinvp, double* r, double* xs,
+void launch_cg_update(int n, const double* p, const double* Hp, const double* Dinvp, double* r, double* xs,
                       double* partials, CgScal* scal, hipStream_t s);
-void launch_cg_p(int n, int it, const double* r, const double* Dinvp, const double* vdiag, double* p, double* Hp,
-                 const double* partials, CgScal* scal, double tol2, hipStream_t s);
+void launch_cg_p(int n, const double* r, const double* Dinvp, const double* vdiag, double* p, double* Hp,
+                 const double* partials, CgScal* scal, hipStream_t s);
 int red_blocks(int n);
 void launch_fill(int n, double value, double* out, hipStream_t s);
 void launch_mul(int n, const double* a, const double* b, double* out, hipStream_t s);

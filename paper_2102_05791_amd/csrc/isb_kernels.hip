@@ -727,7 +727,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_start(int n, const double* __rest
 }
 
 __global__ void __launch_bounds__(kBlock) k_cg_start_fin(const double* __restrict__ partials, int nb, CgScal* scal,
-                                                         double tol2) {
+                                                         double tol2, int max_it) {
   __shared__ double sh[kBlock / 64 + 1];
   const double rz = all_blocks_sum(partials, nb, 2, 0, sh);
   const double rr = all_blocks_sum(partials, nb, 2, 1, sh);
@@ -736,9 +736,12 @@ __global__ void __launch_bounds__(kBlock) k_cg_start_fin(const double* __restric
     scal->rr = rr;
     scal->rr0 = rr;
     scal->pHp = 0.0;
-    scal->done = (rr <= tol2) ? 1 : 0;
+    scal->tol2 = tol2;
+    scal->max_it = max_it;
+    scal->done = (rr <= tol2 || max_it <= 0) ? 1 : 0;
     scal->negcurv = 0;
     scal->iters = 0;
+    scal->it_cur = 0;
   }
 }
 
@@ -753,10 +756,11 @@ __global__ void __launch_bounds__(kBlock) k_cg_dot(int n, const double* __restri
 }
 
 // alpha = rz / pHp; x += alpha p; r -= alpha Hp (masked by D^-1 != 0); partials (r.z, r.r)
-__global__ void __launch_bounds__(kBlock) k_cg_update(int n, int it, int nb, const double* __restrict__ p,
+__global__ void __launch_bounds__(kBlock) k_cg_update(int n, int nb, const double* __restrict__ p,
                                                       const double* __restrict__ Hp, const double* __restrict__ Dinvp,
                                                       double* r, double* xs, double* partials, CgScal* scal) {
   if (scal->done) return;
+  const int it = scal->iters;
   __shared__ double sh[kBlock / 64 + 1];
   const double pHp = all_blocks_sum(partials, nb, 1, 0, sh);
   __syncthreads();  // every block has read its partials before any overwrites them below
@@ -791,15 +795,20 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(int n, int it, int nb, con
     partials[kMaxRedBlocks + 2 * blockIdx.x] = rz1;
     partials[kMaxRedBlocks + 2 * blockIdx.x + 1] = rr;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) scal->pHp = pHp;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    scal->pHp = pHp;
+    scal->it_cur = it;
+  }
 }
 
 // beta = rz_new / rz; p = D^-1 r + beta p; Hp = vdiag p (the start of the next product)
-__global__ void __launch_bounds__(kBlock) k_cg_p(int n, int it, int nb, const double* __restrict__ r,
+__global__ void __launch_bounds__(kBlock) k_cg_p(int n, int nb, const double* __restrict__ r,
                                                  const double* __restrict__ Dinvp, const double* __restrict__ vdiag,
                                                  double* p, double* Hp, const double* __restrict__ partials,
-                                                 CgScal* scal, double tol2) {
+                                                 CgScal* scal) {
   if (scal->done) return;
+  const int it = scal->it_cur;
+  const double tol2 = scal->tol2;
   __shared__ double sh[kBlock / 64 + 1];
   const double rz1 = all_blocks_sum(partials + kMaxRedBlocks, nb, 2, 0, sh);
   const double rr = all_blocks_sum(partials + kMaxRedBlocks, nb, 2, 1, sh);
@@ -821,6 +830,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_p(int n, int it, int nb, const do
     scal->rz[(it + 1) & 1] = rz1;
     scal->rr = rr;
     scal->iters = it + 1;
+    if (it + 1 >= scal->max_it) scal->done = 1;  // the cap: rr above tol2 tells the host it did not converge
   }
 }
 
@@ -865,23 +875,24 @@ void launch_copy(int n, const double* src, double* dst, hipStream_t s) {
   k_copy<<<grid_for(n), kBlock, 0, s>>>(n, src, dst);
 }
 void launch_cg_start(int n, const double* b, double sign, const double* Dinvp, const double* vdiag, double* r,
-                     double* p, double* xs, double* Hp, double* partials, CgScal* scal, double tol2, hipStream_t s) {
+                     double* p, double* xs, double* Hp, double* partials, CgScal* scal, double tol2, int max_it,
+                     hipStream_t s) {
   const int nb = red_blocks(n);
   k_cg_start<<<nb, kBlock, 0, s>>>(n, b, sign, Dinvp, vdiag, r, p, xs, Hp, partials);
-  k_cg_start_fin<<<1, kBlock, 0, s>>>(partials, nb, scal, tol2);
+  k_cg_start_fin<<<1, kBlock, 0, s>>>(partials, nb, scal, tol2, max_it);
 }
 void launch_cg_dot(int n, const double* p, const double* Hp, double* partials, const CgScal* scal, hipStream_t s) {
   k_cg_dot<<<red_blocks(n), kBlock, 0, s>>>(n, p, Hp, partials, scal);
 }
-void launch_cg_update(int n, int it, const double* p, const double* Hp, const double* Dinvp, double* r, double* xs,
+void launch_cg_update(int n, const double* p, const double* Hp, const double* Dinvp, double* r, double* xs,
                       double* partials, CgScal* scal, hipStream_t s) {
   const int nb = red_blocks(n);
-  k_cg_update<<<nb, kBlock, 0, s>>>(n, it, nb, p, Hp, Dinvp, r, xs, partials, scal);
+  k_cg_update<<<nb, kBlock, 0, s>>>(n, nb, p, Hp, Dinvp, r, xs, partials, scal);
 }
-void launch_cg_p(int n, int it, const double* r, const double* Dinvp, const double* vdiag, double* p, double* Hp,
-                 const double* partials, CgScal* scal, double tol2, hipStream_t s) {
+void launch_cg_p(int n, const double* r, const double* Dinvp, const double* vdiag, double* p, double* Hp,
+                 const double* partials, CgScal* scal, hipStream_t s) {
   const int nb = red_blocks(n);
-  k_cg_p<<<nb, kBlock, 0, s>>>(n, it, nb, r, Dinvp, vdiag, p, Hp, partials, scal, tol2);
+  k_cg_p<<<nb, kBlock, 0, s>>>(n, nb, r, Dinvp, vdiag, p, Hp, partials, scal);
 }
 
 __global__ void __launch_bounds__(kBlock) k_mul(int n, const double* __restrict__ a, const double* __restrict__ b,

@@ -21,7 +21,7 @@ STATUS_NAMES = {0: "ISB_OK", 1: "ISB_E_ARG", 2: "ISB_E_MESH", 3: "ISB_E_HIP", 4:
 ISB_FP64, ISB_MIXED = 0, 1
 ISB_QUASISTATIC, ISB_BACKWARD_EULER = 0, 1
 (OPT_SOLVER, OPT_SCATTER, OPT_GRAPH_SAFE, OPT_BLOCK, OPT_CG_CHECK, OPT_PRECISION, OPT_ENERGY, OPT_FORWARD,
- OPT_LBFGS_MEMORY, OPT_LBFGS_MAX_ITERS) = range(10)
+ OPT_LBFGS_MEMORY, OPT_LBFGS_MAX_ITERS, OPT_CG_GRAPH) = range(11)
 FORWARD_NEWTON, FORWARD_LBFGS = 0, 1
 # isotropic element energies (ISB_ENERGY_*), by the names the synthetic workloads use
 ENERGY = {"nh": 0, "stvk": 1, "corot": 2, "snh": 3}
@@ -274,7 +274,7 @@ class Context:
         return v.value
 
     @classmethod
-    def from_workload(cls, w, device=0, precision="fp64", solver=0, scatter=0):
+    def from_workload(cls, w, device=0, precision="fp64", solver=0, scatter=2):
         ctx = cls(device, precision)
         ctx.set_option(OPT_SCATTER, scatter)
         ctx.set_option(OPT_ENERGY, ENERGY[getattr(w, "model", "nh")])

@@ -176,3 +176,48 @@ def test_batched_matches_plain_per_body():
     assert np.linalg.norm(d) <= 1e-4 * scale
     for s in sb:
         assert s["flags"] & 1 and s["res_final"] <= 1e-6 * s["res0"]
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_cg_graph_chunks_match_eager_cg(dim):
+    """The plain solver's CG as replayed graph chunks of 8 iterations runs the same kernels in the
+    same order as one launch per kernel: in the colour scatter mode (no atomics) step, adjoint and
+    iteration counts agree bit for bit, over several solves with eager work in between."""
+    from paper_2102_05791_amd import isb
+    w, rng = rand_workload(dim, seed=71, bodies=2, shape=(10, 3) if dim == 2 else (3, 3, 2))
+    w = _tight(w)
+    outs = {}
+    for graph in (1, 0):
+        ctx = _ctx(w, scatter=1)
+        ctx.set_option(isb.OPT_CG_GRAPH, graph)
+        assert ctx.get_option(isb.OPT_CG_GRAPH) == graph
+        res = []
+        for k in range(3):
+            a = w.actions[k]
+            x1, v1, st, _ = ctx.step(_dev(w.x0), _dev(w.v0), _dev(a))
+            xbar = np.random.default_rng(k).normal(size=w.x0.shape)
+            wv, sa, _ = ctx.solve_adjoint(x1, _dev(w.x0), _dev(a), _dev(xbar))
+            res.append((x1.cpu().numpy(), v1.cpu().numpy(), wv.cpu().numpy(),
+                        [(s["newton_iters"], s["cg_iters"]) for s in st], [s["adj_cg_iters"] for s in sa]))
+        outs[graph] = res
+    for (x1g, v1g, wg, itg, ag), (x1e, v1e, we, ite, ae) in zip(outs[1], outs[0]):
+        assert np.array_equal(x1g, x1e) and np.array_equal(v1g, v1e) and np.array_equal(wg, we)
+        assert itg == ite and ag == ae
+
+
+def test_cg_graph_iteration_cap_inside_a_chunk():
+    """A CG cap that falls inside a chunk stops the solve there (the kernels check it on the device)."""
+    from paper_2102_05791_amd import isb
+    w, _ = rand_workload(2, seed=72, shape=(12, 4))
+    w.scene.update(tol_rel=1e-12, adj_tol_rel=1e-12, max_newton=60, max_cg=12)
+    counts = {}
+    for graph in (1, 0):
+        ctx = _ctx(w, scatter=1)
+        ctx.set_option(isb.OPT_CG_GRAPH, graph)
+        x1 = _dev(w.x0 + 0.01)
+        xbar = _dev(np.ones_like(w.x0))
+        wv, st, status = ctx.solve_adjoint(x1, _dev(w.x0), _dev(w.actions[0]), xbar, allow_not_converged=True)
+        assert status == isb.ISB_E_NOT_CONVERGED
+        counts[graph] = (st[0]["adj_cg_iters"], wv.cpu().numpy())
+    assert counts[1][0] == counts[0][0] == 12
+    assert np.array_equal(counts[1][1], counts[0][1])
