@@ -108,9 +108,10 @@ typedef enum {
                              * the batched solver takes ISB_FORWARD_NEWTON only (ISB_E_ARG otherwise) */
   ISB_OPT_LBFGS_MEMORY = 8, /* pairs kept by ISB_FORWARD_LBFGS, 1..64 (default 8) */
   ISB_OPT_LBFGS_MAX_ITERS = 9, /* iteration cap of ISB_FORWARD_LBFGS (default 20000; max_newton caps Newton) */
-  ISB_OPT_CG_GRAPH = 10     /* plain solver: 1 (default) = run CG as a captured graph of 8 iterations replayed
-                             * until converged (one launch and one host read per 8 iterations); 0 = one launch
-                             * per kernel and a read every ISB_OPT_CG_CHECK iterations. Same kernels either way */
+  ISB_OPT_CG_GRAPH = 10     /* plain solver: 1 = run CG as a graph of 8 iterations, captured once per solve and
+                             * replayed until converged (one launch and one host read per 8 iterations);
+                             * 0 (default) = one launch per kernel and a read every ISB_OPT_CG_CHECK iterations.
+                             * Same kernels in the same order either way */
 } isb_option;
 
 /* Read-only context facts for isb_get_option. */

@@ -58,7 +58,7 @@ struct isb_ctx {
   int solver = 0, scatter = 2, graph_safe = 0, block = 0 /* 0: 768 in 2D, 512 in 3D */, cg_check = 4;
   int model = 0;  // ISB_ENERGY_*
   int forward = 0, lbfgs_m = 8, lbfgs_max_iters = 20000;  // ISB_OPT_FORWARD and the L-BFGS settings
-  int cg_graph = 1;                    // ISB_OPT_CG_GRAPH
+  int cg_graph = 0;                    // ISB_OPT_CG_GRAPH
   hipStream_t cap_stream = nullptr;    // internal stream the CG chunk is captured on
 
   // plain-solver workspaces, [n_v*dim] unless noted
