@@ -63,8 +63,8 @@ def measured_traffic(kernel_mode):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3, help="timed bench steps (full BPTT passes)")
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5, help="timed bench steps (full BPTT passes)")
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--bodies", type=int, default=512)
     ap.add_argument("--rollout", type=int, default=50, help="time steps per BPTT pass")
     ap.add_argument("--plain-bodies", type=int, default=32, help="stratified subset for the plain FP64 path")
@@ -238,11 +238,17 @@ def main():
         bptt()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    pass_ev = []
     for k in range(args.steps):
+        p0, p1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        p0.record()
         xs, a_bar, _, _ = bptt(record=True)
+        p1.record()
+        pass_ev.append((p0, p1))
         print(f"# timed step {k + 1}/{args.steps} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    ms_median = float(np.median([a.elapsed_time(b) for a, b in pass_ev]))
     ms_per_step = 1e3 * wall / args.steps
     body_steps = nb * T * args.steps
     value = body_steps / wall
@@ -395,11 +401,13 @@ def main():
     tet = None if args.no_tet else tet_leg(args, torch, Context, isb, scenes)
     elem = None if args.no_elem_roofline else element_roofline_leg(args, torch, Context, isb, scenes)
     if elem:
-        for prec in ("fp64", "mixed", "gradient_fp64"):
-            elem[prec]["frac_of_copy_ceiling"] = round(elem[prec]["achieved_GBs"] / ceiling["GBs"], 4)
+        for part in (elem, elem["tet_block_64x32x32"]):
+            for prec in ("fp64", "mixed", "gradient_fp64"):
+                part[prec]["frac_of_copy_ceiling"] = round(part[prec]["achieved_GBs"] / ceiling["GBs"], 4)
 
     line = {"metric": METRIC, "value": round(value, 1), "unit": "body-steps/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+            "ms_per_step_median": round(ms_median, 3),
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
             "data": "synthetic",
             "config": {"workload": f"batched_strips: {nb} bodies (4s x s quads, s~U{{4..32}}, "
@@ -703,9 +711,17 @@ def element_roofline_leg(args, torch, Context, isb, scenes):
     """Element Hessian-vector kernel alone (isb_hessvec_elements, FP64 and mixed) and the element
     gradient kernel alone (isb_gradient_elements, FP64) on a mesh whose element data exceeds the
     256 MB last-level cache; algorithmic bytes / HIP-event time."""
+    out = element_roofline_mesh(args.elem_grid, torch, Context, isb, scenes)
+    # the same kernels on the 64x32x32 tet block (whose element data fits the last-level cache)
+    out["tet_block_64x32x32"] = element_roofline_mesh("64x32x32", torch, Context, isb, scenes)
+    print("# element roofline leg done", file=sys.stderr, flush=True)
+    return out
+
+
+def element_roofline_mesh(grid, torch, Context, isb, scenes):
     from synth import meshes
     dev = torch.device("cuda:0")
-    nx, ny, nz = (int(v) for v in args.elem_grid.split("x"))
+    nx, ny, nz = (int(v) for v in grid.split("x"))
     X, Tm = meshes.tet_grid(nx, ny, nz)
     n_e, n_v = Tm.shape[0], X.shape[0]
     mu, lam = scenes.lame(1e5, 0.45)
@@ -760,7 +776,6 @@ def element_roofline_leg(args, torch, Context, isb, scenes):
                                     "element_bytes": elem_bytes(3, 8)}
         del ctx
         torch.cuda.empty_cache()
-    print("# element roofline leg done", file=sys.stderr, flush=True)
     return out
 
 
