@@ -34,6 +34,7 @@ isb_ctx::~isb_ctx() {
   (void)hipSetDevice(device);
   batched_release(this);
   free_list(work_allocs);
+  free_list(lbfgs_allocs);
   free_list(spring_allocs);
   free_list(mesh_allocs);
   if (hscal) (void)hipHostFree(hscal);
@@ -640,9 +641,11 @@ static isb_status plain_step(isb_ctx* c, hipStream_t s, const double* x0, const 
   if (c->precision == ISB_MIXED) launch_to_f32(c->n_e, a, c->w_a32, s);
   if (c->forward == ISB_FORWARD_LBFGS && c->lbfgs_alloc_m != c->lbfgs_m) {
     // the first-order solver's history: lbfgs_m pairs (s, y) of full DOF vectors
+    c->free_list(c->lbfgs_allocs);
+    c->lbfgs_alloc_m = 0;
     const size_t nd = (size_t)c->n_v * c->dim * (size_t)c->lbfgs_m;
-    ISB_TRY(dalloc(c->work_allocs, &c->w_lbS, nd));
-    ISB_TRY(dalloc(c->work_allocs, &c->w_lbY, nd));
+    ISB_TRY(dalloc(c->lbfgs_allocs, &c->w_lbS, nd));
+    ISB_TRY(dalloc(c->lbfgs_allocs, &c->w_lbY, nd));
     ISB_HIP(hipMemset(c->w_lbS, 0, nd * sizeof(double)));
     ISB_HIP(hipMemset(c->w_lbY, 0, nd * sizeof(double)));
     c->lbfgs_alloc_m = c->lbfgs_m;
@@ -716,6 +719,7 @@ static isb_status plain_adjoint(isb_ctx* c, hipStream_t s, const double* x1, con
 // ---------------------------------------------------------------------------------------------
 static isb_status alloc_workspaces(isb_ctx* c) {
   c->free_list(c->work_allocs);
+  c->free_list(c->lbfgs_allocs);
   c->w_lbS = c->w_lbY = nullptr;
   c->lbfgs_alloc_m = 0;
   const size_t nd = (size_t)c->n_v * c->dim;
@@ -782,6 +786,9 @@ isb_status isb_mesh_upload(isb_ctx* c, int dim, int32_t n_bodies, const int64_t*
   ISB_HIP(hipSetDevice(c->device));
   batched_release(c);
   c->free_list(c->work_allocs);
+  c->free_list(c->lbfgs_allocs);
+  c->w_lbS = c->w_lbY = nullptr;
+  c->lbfgs_alloc_m = 0;
   c->free_list(c->mesh_allocs);
   c->have_mesh = c->have_material = false;
   c->dim = dim;

@@ -68,6 +68,7 @@ struct isb_ctx {
   float* w_a32 = nullptr;           // [n_e]
   double *w_lbS = nullptr, *w_lbY = nullptr;  // [lbfgs_m][n_v*dim] L-BFGS pairs (allocated on first use)
   int lbfgs_alloc_m = 0;
+  std::vector<void*> lbfgs_allocs;           // the two arrays above; freed when lbfgs_m changes
   double* partials = nullptr;       // reduction partials
   double* dscal = nullptr;          // small device results (finalize outputs)
   double* ebuf = nullptr;           // [3*n_bodies] per-body energy comps
