@@ -729,7 +729,7 @@ def element_roofline_mesh(grid, torch, Context, isb, scenes):
     x = torch.tensor(X + 0.01 * rng.standard_normal(X.shape), device=dev)
     p = torch.tensor(rng.standard_normal(X.shape), device=dev)
     a = torch.tensor(meshes.contraction_actuation(rng, n_e), device=dev)
-    out = {"mesh": f"tet_grid {nx}x{ny}x{nz}: {n_e} tets, {n_v} vertices"}
+    out = {"mesh": f"tet_grid {nx}x{ny}x{nz} (4x4x4-cube block element order): {n_e} tets, {n_v} vertices"}
     for prec, word in (("fp64", 8), ("mixed", 4)):
         ctx = Context(0, prec)
         ctx.mesh_upload(3, X, Tm, None)

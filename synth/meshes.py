@@ -68,22 +68,30 @@ def _kuhn_paths():
     return paths
 
 
-def tet_grid(nx: int, ny: int, nz: int, origin=(0.0, 0.0, 0.0)):
+def tet_grid(nx: int, ny: int, nz: int, origin=(0.0, 0.0, 0.0), block: int = 4):
     """Kuhn (Freudenthal) split of an nx-by-ny-by-nz block of unit cubes.
 
     Returns X (float64 [(nx+1)(ny+1)(nz+1), 3]) and T (int32 [6*nx*ny*nz, 4]),
-    every tetrahedron positively oriented.
+    every tetrahedron positively oriented. Vertices are numbered x fastest; the cubes (six
+    tetrahedra each, consecutive) come in block x block x block groups, the groups in x-fastest
+    order and the cubes x-fastest inside a group: a locality order, so that runs of consecutive
+    elements cover compact regions (block = 1 gives plain x-fastest cube order).
     """
     if min(nx, ny, nz) < 1:
         raise ValueError("tet_grid needs nx, ny, nz >= 1")
+    if block < 1:
+        raise ValueError("tet_grid needs block >= 1")
     k, j, i = np.meshgrid(np.arange(nz + 1), np.arange(ny + 1), np.arange(nx + 1), indexing="ij")
     X = np.stack([i.ravel(), j.ravel(), k.ravel()], axis=1).astype(np.float64)
     X += np.asarray(origin, dtype=np.float64)
     vid = lambda ii, jj, kk: (kk * (ny + 1) + jj) * (nx + 1) + ii
     ck, cj, ci = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
-    ci = ci.ravel()
-    cj = cj.ravel()
-    ck = ck.ravel()
+    B = int(block)
+    order = np.lexsort((ci.ravel() % B, cj.ravel() % B, ck.ravel() % B,
+                        ci.ravel() // B, cj.ravel() // B, ck.ravel() // B))
+    ci = ci.ravel()[order]
+    cj = cj.ravel()[order]
+    ck = ck.ravel()[order]
     tets = []
     for corners in _kuhn_paths():
         tets.append(np.stack([vid(ci + a, cj + b, ck + c) for (a, b, c) in corners], axis=1))
