@@ -185,6 +185,16 @@ isb_status isb_validate_mesh(int dim, int64_t n_v, const double* X, int64_t n_e,
 isb_status isb_colour_elements(int dim, int64_t n_v, int64_t n_e, const int32_t* T,
                                int32_t* colour_out, int32_t* n_colours_out);
 
+/* A locality order of the elements: perm_out host [n_e] receives, for each new position, the
+ * element that goes there, sorting each body's elements (body_e_off host [n_bodies+1], or NULL for
+ * one body) by the Morton key of their rest centroids (X host [n_v][dim]). The LDS-staged patch
+ * scatter takes consecutive elements, so a mesh whose elements come in such an order loads and
+ * flushes each vertex in fewer patches; a caller applies the permutation to T and to every
+ * per-element array once, before isb_mesh_upload. Deterministic; ISB_E_MESH for an out-of-range
+ * vertex, ISB_E_ARG otherwise. */
+isb_status isb_locality_order(int dim, int64_t n_v, const double* X, int64_t n_e, const int32_t* T,
+                              int32_t n_bodies, const int64_t* body_e_off, int64_t* perm_out);
+
 /* ---- upload ------------------------------------------------------------------------------- */
 
 /* Copy a mesh of n_bodies independent bodies to the device and precompute Dm^-1 and W per element.

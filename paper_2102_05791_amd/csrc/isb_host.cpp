@@ -153,6 +153,60 @@ isb_status isb_validate_mesh(int dim, int64_t n_v, const double* X, int64_t n_e,
   return isb::validate_mesh(dim, n_v, X, n_e, T, n_bodies, body_v_off, body_e_off);
 }
 
+isb_status isb_locality_order(int dim, int64_t n_v, const double* X, int64_t n_e, const int32_t* T,
+                              int32_t n_bodies, const int64_t* body_e_off, int64_t* perm_out) {
+  isb::clear_error();
+  if ((dim != 2 && dim != 3) || n_v <= 0 || n_e < 0 || !X || (n_e > 0 && !T) || !perm_out || n_bodies < 0)
+    return isb::fail(ISB_E_ARG, "isb_locality_order: bad argument");
+  std::vector<int64_t> eoff{0, n_e};
+  if (body_e_off) {
+    eoff.assign(body_e_off, body_e_off + n_bodies + 1);
+    if (eoff.front() != 0 || eoff.back() != n_e) return isb::fail(ISB_E_ARG, "isb_locality_order: bad body_e_off");
+    for (int32_t b = 0; b < n_bodies; ++b)
+      if (eoff[b + 1] < eoff[b]) return isb::fail(ISB_E_ARG, "isb_locality_order: bad body_e_off");
+  }
+  const int nk = dim + 1;
+  // bounding box of the rest positions
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  for (int64_t v = 0; v < n_v; ++v)
+    for (int c = 0; c < dim; ++c) {
+      lo[c] = std::min(lo[c], X[v * dim + c]);
+      hi[c] = std::max(hi[c], X[v * dim + c]);
+    }
+  // Morton key of each element's rest centroid on one cubic lattice over the bounding box (one
+  // scale for every axis, so that the key's cells stay cubic on elongated meshes): 21 bits per
+  // axis in 3D, 31 in 2D, bits interleaved
+  const int bits = dim == 3 ? 21 : 31;
+  double span = 0.0;
+  for (int c = 0; c < dim; ++c) span = std::max(span, hi[c] - lo[c]);
+  if (!(span > 0.0)) span = 1.0;
+  std::vector<uint64_t> key((size_t)n_e);
+  for (int64_t e = 0; e < n_e; ++e) {
+    uint64_t q[3] = {0, 0, 0};
+    for (int c = 0; c < dim; ++c) {
+      double m = 0.0;
+      for (int k = 0; k < nk; ++k) {
+        const int32_t v = T[e * nk + k];
+        if (v < 0 || v >= n_v) return isb::fail(ISB_E_MESH, "isb_locality_order: vertex index out of range");
+        m += X[(int64_t)v * dim + c];
+      }
+      m /= nk;
+      double t = (m - lo[c]) / span;
+      t = std::min(std::max(t, 0.0), 1.0);
+      q[c] = (uint64_t)(t * (double)((1ull << bits) - 1));
+    }
+    uint64_t k = 0;
+    for (int bit = bits - 1; bit >= 0; --bit)
+      for (int c = dim - 1; c >= 0; --c) k = (k << 1) | ((q[c] >> bit) & 1ull);
+    key[e] = k;
+  }
+  for (int64_t e = 0; e < n_e; ++e) perm_out[e] = e;
+  for (size_t b = 0; b + 1 < eoff.size(); ++b)
+    std::stable_sort(perm_out + eoff[b], perm_out + eoff[b + 1],
+                     [&](int64_t a, int64_t c) { return key[a] < key[c]; });
+  return ISB_OK;
+}
+
 isb_status isb_colour_elements(int dim, int64_t n_v, int64_t n_e, const int32_t* T, int32_t* colour_out,
                                int32_t* n_colours_out) {
   isb::clear_error();

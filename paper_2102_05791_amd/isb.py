@@ -33,7 +33,7 @@ EXPORTED = ("isb_create", "isb_destroy", "isb_last_error", "isb_version", "isb_v
             "isb_set_option", "isb_get_option", "isb_get_mass", "isb_step", "isb_solve_adjoint",
             "isb_vjp_params", "isb_energy", "isb_gradient", "isb_hessvec", "isb_hessvec_elements",
             "isb_hessdiag", "isb_stream_copy", "isb_spring_upload", "isb_vjp_spring_stiffness",
-            "isb_gradient_elements")
+            "isb_gradient_elements", "isb_locality_order")
 
 
 class IsbError(RuntimeError):
@@ -95,6 +95,7 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
         "isb_destroy": [vp],
         "isb_validate_mesh": [ctypes.c_int, i64, vp, i64, vp, i32, vp, vp],
         "isb_colour_elements": [ctypes.c_int, i64, i64, vp, vp, P(i32)],
+        "isb_locality_order": [ctypes.c_int, i64, vp, i64, vp, i32, vp, vp],
         "isb_mesh_upload": [vp, ctypes.c_int, i32, vp, vp, vp, vp, vp],
         "isb_material_upload": [vp, vp, vp, vp, vp, vp, P(Scene)],
         "isb_set_scene": [vp, P(Scene)],
@@ -160,6 +161,22 @@ def colour_elements(dim, n_v, T):
     _check(lib, lib.isb_colour_elements(dim, n_v, T.shape[0], pT, col.ctypes.data_as(ctypes.c_void_p),
                                         ctypes.byref(nc)))
     return col, nc.value
+
+
+def locality_order(dim, X, T, body_e_off=None):
+    """isb_locality_order: the element permutation (new position -> element) of a locality order."""
+    lib = load_library()
+    X, pX = _host(X, np.float64)
+    T, pT = _host(T, np.int32)
+    perm = np.zeros(T.shape[0], dtype=np.int64)
+    if body_e_off is None:
+        _check(lib, lib.isb_locality_order(dim, X.shape[0], pX, T.shape[0], pT, 1, None,
+                                           perm.ctypes.data_as(ctypes.c_void_p)))
+    else:
+        eo, peo = _host(body_e_off, np.int64)
+        _check(lib, lib.isb_locality_order(dim, X.shape[0], pX, T.shape[0], pT, len(eo) - 1, peo,
+                                           perm.ctypes.data_as(ctypes.c_void_p)))
+    return perm
 
 
 def _dev(t, name="tensor"):

@@ -122,3 +122,39 @@ def test_stream_copy_rejects_bad_arguments_before_any_gpu_call():
     for src, dst, n in cases:
         assert lib.isb_stream_copy(None, src, dst, n) == isb.ISB_E_ARG
         assert lib.isb_last_error()
+
+
+def _patch_duplication(T, n_v, size=1024):
+    """Sum over runs of `size` consecutive elements of their distinct vertices, over n_v."""
+    return sum(np.unique(T[s:s + size]).size for s in range(0, T.shape[0], size)) / n_v
+
+
+def test_locality_order_is_a_per_body_permutation_that_compacts_patches():
+    from paper_2102_05791_amd import isb
+    X, T = meshes.tet_grid(96, 8, 8, block=1)           # cubes x fastest: long thin runs
+    perm = isb.locality_order(3, X, T)
+    assert np.array_equal(np.sort(perm), np.arange(T.shape[0]))
+    assert np.array_equal(perm, isb.locality_order(3, X, T))          # deterministic
+    before, after = _patch_duplication(T, X.shape[0]), _patch_duplication(T[perm], X.shape[0])
+    assert after < 0.7 * before, (before, after)
+    # two bodies: every body's elements stay in its own range
+    X2, T2 = meshes.tri_grid(40, 30)
+    Xb = np.concatenate([X2, X2 + 100.0])
+    Tb = np.concatenate([T2, T2 + X2.shape[0]])
+    eoff = np.array([0, T2.shape[0], 2 * T2.shape[0]])
+    pb = isb.locality_order(2, Xb, Tb, eoff)
+    assert np.array_equal(np.sort(pb[:T2.shape[0]]), np.arange(T2.shape[0]))
+    assert np.array_equal(np.sort(pb[T2.shape[0]:]), np.arange(T2.shape[0], 2 * T2.shape[0]))
+
+
+def test_locality_order_rejects_bad_input():
+    from paper_2102_05791_amd import IsbError, isb
+    X, T = meshes.tri_grid(3, 2)
+    bad = T.copy()
+    bad[1, 2] = X.shape[0]
+    with pytest.raises(IsbError) as e:
+        isb.locality_order(2, X, bad)
+    assert e.value.status == isb.ISB_E_MESH
+    with pytest.raises(IsbError) as e:
+        isb.locality_order(2, X, T, np.array([0, 3, 2]))
+    assert e.value.status == isb.ISB_E_ARG
