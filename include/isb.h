@@ -233,6 +233,16 @@ isb_status isb_get_option(isb_ctx* ctx, int key, int64_t* value);
 /* Lumped vertex masses, device out [n_v] (FP64). */
 isb_status isb_get_mass(isb_ctx* ctx, isb_stream stream, double* mass_out);
 
+/* Pick the fastest launch configuration for this context on the caller's inputs: each candidate
+ * runs two steps from (x0, v0, a) (the first prepares and warms up; the second is timed with HIP
+ * events on `stream`) and the fastest is kept as the context's option. Candidates: the batched
+ * solver's workgroup size (ISB_OPT_BLOCK 512, 768, 1024; the alternative energies have one size),
+ * the plain solver's scatter (ISB_OPT_SCATTER 0 atomic or 2 patches). chosen_out host [2] or NULL
+ * receives (option key, value). Allocates two temporary state buffers; synchronises the stream.
+ * Candidates that cannot run on the context are skipped; ISB_E_ARG if none ran. */
+isb_status isb_autotune(isb_ctx* ctx, isb_stream stream, const double* x0, const double* v0,
+                        const double* a, int64_t* chosen_out);
+
 /* ---- the step and its adjoint ------------------------------------------------------------- */
 
 /* One implicit step (Eq. 1 or Eq. 14) of every body. x0, v0: device [n_v][dim] (v0 ignored and

@@ -1180,6 +1180,81 @@ isb_status isb_spring_upload(isb_ctx* c, int64_t n_s, const int64_t* body_s_off,
   return ISB_OK;
 }
 
+isb_status isb_autotune(isb_ctx* c, isb_stream stream, const double* x0, const double* v0, const double* a,
+                        int64_t* chosen_out) {
+  clear_error();
+  ISB_TRY(check_ctx(c, true));
+  const bool be = c->scene.integrator == ISB_BACKWARD_EULER;
+  if (!x0 || !a || (be && !v0)) return fail(ISB_E_ARG, "NULL state argument");
+  hipStream_t s = (hipStream_t)stream;
+  // candidates: the batched solver's workgroup size (the alternative energies have one size only),
+  // the plain solver's scatter (atomic or LDS-staged patches; the colour mode is for reproducibility)
+  const bool batched = c->solver == 1;
+  std::vector<int> cand;
+  if (batched)
+    cand = c->model == ISB_ENERGY_NEOHOOKEAN ? std::vector<int>{512, 768, 1024} : std::vector<int>{0};
+  else
+    cand = {0, 2};
+  const int keep_block = c->block, keep_scatter = c->scatter;
+  const size_t nd = (size_t)c->n_v * c->dim;
+  double *x1 = nullptr, *v1 = nullptr;
+  ISB_HIP(hipMalloc(&x1, nd * sizeof(double)));
+  if (hipMalloc(&v1, nd * sizeof(double)) != hipSuccess) {
+    (void)hipFree(x1);
+    return fail(ISB_E_HIP, "isb_autotune: out of device memory");
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  int best = -1;
+  float best_ms = 0.0f;
+  isb_status st = ISB_OK;
+  for (int v : cand) {
+    if (batched)
+      c->block = v;
+    else
+      c->scatter = v;
+    float ms = 0.0f;
+    bool ok = true;
+    for (int rep = 0; rep < 2 && ok; ++rep) {  // the first run prepares state and warms the caches
+      (void)hipEventRecord(e0, s);
+      const isb_status r = isb_step(c, stream, x0, v0, a, x1, be ? v1 : nullptr, nullptr);
+      (void)hipEventRecord(e1, s);
+      if (r != ISB_OK && r != ISB_E_NOT_CONVERGED) {
+        ok = false;  // this configuration cannot run on the context (e.g. too little LDS)
+        break;
+      }
+      if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        st = fail(ISB_E_HIP, "isb_autotune: event timing failed");
+        ok = false;
+      }
+    }
+    if (st != ISB_OK) break;
+    if (ok && (best < 0 || ms < best_ms)) {
+      best = v;
+      best_ms = ms;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(x1);
+  (void)hipFree(v1);
+  c->block = keep_block;
+  c->scatter = keep_scatter;
+  if (st != ISB_OK) return st;
+  if (best < 0) return fail(ISB_E_ARG, "isb_autotune: no candidate configuration ran");
+  if (batched)
+    c->block = best;
+  else
+    c->scatter = best;
+  clear_error();
+  if (chosen_out) {
+    chosen_out[0] = batched ? ISB_OPT_BLOCK : ISB_OPT_SCATTER;
+    chosen_out[1] = best;
+  }
+  return ISB_OK;
+}
+
 isb_status isb_energy(isb_ctx* c, isb_stream stream, const double* x, const double* x0, const double* v0,
                       const double* a, double* energy) {
   clear_error();

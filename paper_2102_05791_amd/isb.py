@@ -33,7 +33,7 @@ EXPORTED = ("isb_create", "isb_destroy", "isb_last_error", "isb_version", "isb_v
             "isb_set_option", "isb_get_option", "isb_get_mass", "isb_step", "isb_solve_adjoint",
             "isb_vjp_params", "isb_energy", "isb_gradient", "isb_hessvec", "isb_hessvec_elements",
             "isb_hessdiag", "isb_stream_copy", "isb_spring_upload", "isb_vjp_spring_stiffness",
-            "isb_gradient_elements", "isb_locality_order")
+            "isb_gradient_elements", "isb_locality_order", "isb_autotune")
 
 
 class IsbError(RuntimeError):
@@ -96,6 +96,7 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
         "isb_validate_mesh": [ctypes.c_int, i64, vp, i64, vp, i32, vp, vp],
         "isb_colour_elements": [ctypes.c_int, i64, i64, vp, vp, P(i32)],
         "isb_locality_order": [ctypes.c_int, i64, vp, i64, vp, i32, vp, vp],
+        "isb_autotune": [vp, vp, vp, vp, vp, vp],
         "isb_mesh_upload": [vp, ctypes.c_int, i32, vp, vp, vp, vp, vp],
         "isb_material_upload": [vp, vp, vp, vp, vp, vp, P(Scene)],
         "isb_set_scene": [vp, P(Scene)],
@@ -301,6 +302,41 @@ class Context:
             ctx.spring_upload(w.S, w.ks, w.body_s_off)
         ctx.set_option(OPT_SOLVER, solver)
         return ctx
+
+    # ---- launch configuration ----
+    def autotune(self, x0, v0, a, cache_path=None):
+        """isb_autotune on (x0, v0, a): keeps the fastest workgroup size (batched) or scatter (plain)
+        and returns {option key: value}. With cache_path, a JSON file keyed by device architecture,
+        dimension, precision, solver, energy model and element-count bucket (powers of two) answers
+        repeated questions without timing."""
+        import json
+        import math
+        import torch
+        key = None
+        if cache_path:
+            arch = getattr(torch.cuda.get_device_properties(self.device), "gcnArchName", "unknown")
+            bucket = int(math.log2(max(self.n_e, 1)))
+            key = (f"{arch}|dim{self.dim}|prec{self.precision}|solver{self.get_option(OPT_SOLVER)}|"
+                   f"energy{self.get_option(OPT_ENERGY)}|ne2^{bucket}")
+            try:
+                with open(cache_path) as fh:
+                    cache = json.load(fh)
+            except (OSError, ValueError):
+                cache = {}
+            if key in cache:
+                opt, val = cache[key]
+                self.set_option(int(opt), int(val))
+                return {int(opt): int(val)}
+        chosen = (ctypes.c_int64 * 2)()
+        _check(self.lib, self.lib.isb_autotune(self.h, _stream(), _dev(x0, "x0"), _dev(v0, "v0"), self._a(a),
+                                               chosen))
+        if key is not None:
+            cache[key] = [int(chosen[0]), int(chosen[1])]
+            tmp = cache_path + ".tmp"
+            with open(tmp, "w") as fh:
+                json.dump(cache, fh, indent=1, sort_keys=True)
+            os.replace(tmp, cache_path)
+        return {int(chosen[0]): int(chosen[1])}
 
     # ---- device helpers ----
     def _empty(self, *shape):
