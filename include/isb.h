@@ -108,6 +108,10 @@ typedef enum {
                              * the batched solver takes ISB_FORWARD_NEWTON only (ISB_E_ARG otherwise) */
   ISB_OPT_LBFGS_MEMORY = 8, /* pairs kept by ISB_FORWARD_LBFGS, 1..64 (default 8) */
   ISB_OPT_LBFGS_MAX_ITERS = 9, /* iteration cap of ISB_FORWARD_LBFGS (default 20000; max_newton caps Newton) */
+  ISB_OPT_FP64_FALLBACK = 11, /* batched solver in ISB_MIXED: 1 (default) = a body whose step or adjoint did not
+                             * converge is solved again from the same inputs in FP64 (its stats then carry
+                             * ISB_FLAG_FP64_FALLBACK); needs the host check, so not in graph-safe mode without
+                             * stats; 0 = off; 2 = re-solve every body in FP64 (exercises the fallback path) */
   ISB_OPT_CG_GRAPH = 10     /* plain solver: 1 = run CG as a graph of 8 iterations, captured once per solve and
                              * replayed until converged (one launch and one host read per 8 iterations);
                              * 0 (default) = one launch per kernel and a read every ISB_OPT_CG_CHECK iterations.
@@ -142,6 +146,7 @@ typedef struct {
 #define ISB_FLAG_STAGNATED 2
 #define ISB_FLAG_NONFINITE 4
 #define ISB_FLAG_ADJ_CONVERGED 8
+#define ISB_FLAG_FP64_FALLBACK 16 /* the mixed solve did not converge; these stats are the FP64 re-solve's */
 
 /* Scene constants (one set for every body of the context). */
 typedef struct {

@@ -983,6 +983,10 @@ isb_status isb_set_option(isb_ctx* c, int key, int64_t value) {
     case ISB_OPT_CG_GRAPH:
       c->cg_graph = value != 0;
       return ISB_OK;
+    case ISB_OPT_FP64_FALLBACK:
+      if (value < 0 || value > 2) return fail(ISB_E_ARG, "fp64 fallback must be 0, 1 or 2");
+      c->fp64_fallback = (int)value;
+      return ISB_OK;
     case ISB_OPT_FORWARD:
       if (value != ISB_FORWARD_NEWTON && value != ISB_FORWARD_LBFGS)
         return fail(ISB_E_ARG, "forward must be ISB_FORWARD_NEWTON or ISB_FORWARD_LBFGS");
@@ -1014,6 +1018,7 @@ isb_status isb_get_option(isb_ctx* c, int key, int64_t* value) {
     case ISB_OPT_ENERGY: *value = c->model; return ISB_OK;
     case ISB_OPT_FORWARD: *value = c->forward; return ISB_OK;
     case ISB_OPT_CG_GRAPH: *value = c->cg_graph; return ISB_OK;
+    case ISB_OPT_FP64_FALLBACK: *value = c->fp64_fallback; return ISB_OK;
     case ISB_OPT_LBFGS_MEMORY: *value = c->lbfgs_m; return ISB_OK;
     case ISB_OPT_LBFGS_MAX_ITERS: *value = c->lbfgs_max_iters; return ISB_OK;
     case ISB_INFO_N_VERTICES: *value = c->n_v; return ISB_OK;

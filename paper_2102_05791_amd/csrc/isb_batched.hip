@@ -42,6 +42,7 @@ struct BatchedState {
   int32_t* soff = nullptr;              // springs per body
   uint16_t* slconn = nullptr;           // body-local spring ends
   void* Sbuf = nullptr;                 // per-spring block K in the element precision
+  int32_t *fb_order = nullptr, *fb_wgoff = nullptr;  // schedule of a fallback launch (FP64 state only)
   int nacc = 0, grid = 0, block = 0, precision = -1, dim = 0, model = 0;
   size_t lds = 0;
 };
@@ -101,13 +102,18 @@ static int64_t batched_max_dof(const isb_ctx* c) {
   return mx;
 }
 
-void batched_release(isb_ctx* c) {
-  auto* st = static_cast<BatchedState*>(c->batched);
+static void release_state(void** slot) {
+  auto* st = static_cast<BatchedState*>(*slot);
   if (!st) return;
   for (void* p : st->allocs) (void)hipFree(p);
   if (st->hstats) (void)hipHostFree(st->hstats);
   delete st;
-  c->batched = nullptr;
+  *slot = nullptr;
+}
+
+void batched_release(isb_ctx* c) {
+  release_state(&c->batched);
+  release_state(&c->batched64);
 }
 
 // Cost of a body in element-equivalents for the static schedule: a fixed part per body (the
@@ -143,21 +149,22 @@ static void lpt_schedule(const std::vector<int32_t>& eoff, int nb, int G, std::v
   }
 }
 
-isb_status batched_prepare(isb_ctx* c) {
-  auto* st = static_cast<BatchedState*>(c->batched);
+// the batched state of one precision in *slot (the context's, or the FP64 fallback's)
+static isb_status prepare_state(isb_ctx* c, void** slot, int precision) {
+  auto* st = static_cast<BatchedState*>(*slot);
   const int want_block = c->block > 0 ? c->block : default_block(c->dim);
-  if (st && st->block == want_block && st->precision == c->precision && st->dim == c->dim && st->model == c->model)
+  if (st && st->block == want_block && st->precision == precision && st->dim == c->dim && st->model == c->model)
     return ISB_OK;
-  if (!pick_kernel(c->dim, c->precision, 0, want_block, c->model))
+  if (!pick_kernel(c->dim, precision, 0, want_block, c->model))
     return fail(ISB_E_ARG, "batched solver: the alternative energy models run with the default workgroup size only");
-  batched_release(c);
+  release_state(slot);
   st = new BatchedState();
-  c->batched = st;
+  *slot = st;
   const int nb = c->n_bodies;
   st->lds = (size_t)batched_lds_bytes(c);
   st->nacc = (int)batched_max_dof(c);
   st->block = want_block;
-  st->precision = c->precision;
+  st->precision = precision;
   st->dim = c->dim;
   st->model = c->model;
   int max_lds = 0, n_cu = 0;
@@ -168,7 +175,7 @@ isb_status batched_prepare(isb_ctx* c) {
                                " B of LDS, the device allows " + std::to_string(max_lds) + " B per workgroup");
   int occ = 0;
   for (int mode = 0; mode < 2; ++mode) {
-    void* k = pick_kernel(c->dim, c->precision, mode, st->block, c->model);
+    void* k = pick_kernel(c->dim, precision, mode, st->block, c->model);
     ISB_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)st->lds));
     int o = 0;
     ISB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, k, st->block, st->lds));
@@ -198,14 +205,16 @@ isb_status batched_prepare(isb_ctx* c) {
   if ((r = alloc((void**)&st->voff, (nb + 1) * 4)) != ISB_OK) return r;
   if ((r = alloc((void**)&st->eoff, (nb + 1) * 4)) != ISB_OK) return r;
   if ((r = alloc((void**)&st->stats, nb * sizeof(DevStats))) != ISB_OK) return r;
+  if ((r = alloc((void**)&st->fb_order, nb * 4)) != ISB_OK) return r;
+  if ((r = alloc((void**)&st->fb_wgoff, (st->grid + 1) * 4)) != ISB_OK) return r;
   const size_t fwords = (size_t)hv_state_words(c->dim) * (size_t)c->n_e;
-  if ((r = alloc(&st->Fbuf, fwords * (c->precision == ISB_MIXED ? 4 : 8))) != ISB_OK) return r;
+  if ((r = alloc(&st->Fbuf, fwords * (precision == ISB_MIXED ? 4 : 8))) != ISB_OK) return r;
   const size_t nterms = (size_t)c->n_e + (size_t)c->n_s;
   if ((r = alloc((void**)&st->E0, nterms * sizeof(double))) != ISB_OK) return r;
   if ((r = alloc((void**)&st->E1, nterms * sizeof(double))) != ISB_OK) return r;
   if (c->n_s > 0) {
     const size_t ns = (size_t)c->n_s;
-    if ((r = alloc(&st->Sbuf, (size_t)spring_state_words(c->dim) * ns * (c->precision == ISB_MIXED ? 4 : 8))) != ISB_OK)
+    if ((r = alloc(&st->Sbuf, (size_t)spring_state_words(c->dim) * ns * (precision == ISB_MIXED ? 4 : 8))) != ISB_OK)
       return r;
     if ((r = alloc((void**)&st->soff, (nb + 1) * 4)) != ISB_OK) return r;
     if ((r = alloc((void**)&st->slconn, 2 * ns * sizeof(uint16_t))) != ISB_OK) return r;
@@ -224,7 +233,7 @@ isb_status batched_prepare(isb_ctx* c) {
   }
   const size_t ndof = (size_t)c->n_v * c->dim;
   if ((r = alloc((void**)&st->Dv, ndof * sizeof(float))) != ISB_OK) return r;
-  if ((r = alloc(&st->vdT, ndof * (c->precision == ISB_MIXED ? 4 : 8))) != ISB_OK) return r;
+  if ((r = alloc(&st->vdT, ndof * (precision == ISB_MIXED ? 4 : 8))) != ISB_OK) return r;
   // 16-bit body-local connectivity: every body passed the LDS check, so it has fewer than 65536
   // vertices (2 x 8 bytes of LDS per DOF)
   {
@@ -249,6 +258,8 @@ isb_status batched_prepare(isb_ctx* c) {
   ISB_HIP(hipMemset(st->stats, 0, nb * sizeof(DevStats)));
   return ISB_OK;
 }
+
+isb_status batched_prepare(isb_ctx* c) { return prepare_state(c, &c->batched, c->precision); }
 
 static BatchArgs make_args(isb_ctx* c, BatchedState* st) {
   BatchArgs A;
@@ -287,19 +298,76 @@ static BatchArgs make_args(isb_ctx* c, BatchedState* st) {
   return A;
 }
 
-static isb_status launch(isb_ctx* c, BatchedState* st, hipStream_t s, int mode, const BatchArgs& A) {
-  void* k = pick_kernel(c->dim, c->precision, mode, st->block, c->model);
+static isb_status launch(isb_ctx* c, BatchedState* st, hipStream_t s, int mode, const BatchArgs& A, int grid = 0) {
+  void* k = pick_kernel(c->dim, st->precision, mode, st->block, c->model);
   const DevMesh m = devmesh(c);
   const DevScene sc = devscene(c);
   void* args[] = {(void*)&m, (void*)&sc, (void*)&A};
-  ISB_HIP(hipLaunchKernel(k, dim3(st->grid), dim3(st->block), args, st->lds, s));
+  ISB_HIP(hipLaunchKernel(k, dim3(grid > 0 ? grid : st->grid), dim3(st->block), args, st->lds, s));
   return ISB_OK;
 }
 
-static isb_status collect(isb_ctx* c, BatchedState* st, hipStream_t s, isb_stats* per_body, int mode) {
+// Mixed-precision recovery: the bodies whose solve did not converge are solved again from the same
+// inputs by the FP64 kernel (its own batched state), in one launch over just those bodies, which
+// overwrites their outputs; their stats come from that solve and carry ISB_FLAG_FP64_FALLBACK.
+static isb_status fp64_fallback(isb_ctx* c, BatchedState* st, hipStream_t s, int mode, const BatchArgs& A0,
+                                const std::vector<int32_t>& bodies) {
+  isb_status r = prepare_state(c, &c->batched64, ISB_FP64);
+  if (r != ISB_OK) return r;
+  auto* fb = static_cast<BatchedState*>(c->batched64);
+  const int n = (int)bodies.size(), grid = std::min(n, fb->grid);
+  std::vector<int32_t> order, wg_off(1, 0);
+  for (int g = 0; g < grid; ++g) {
+    for (int k = g; k < n; k += grid) order.push_back(bodies[k]);
+    wg_off.push_back((int32_t)order.size());
+  }
+  ISB_HIP(hipMemcpy(fb->fb_order, order.data(), order.size() * 4, hipMemcpyHostToDevice));
+  ISB_HIP(hipMemcpy(fb->fb_wgoff, wg_off.data(), wg_off.size() * 4, hipMemcpyHostToDevice));
+  ISB_HIP(hipMemcpy(fb->stats, st->hstats, c->n_bodies * sizeof(DevStats), hipMemcpyHostToDevice));
+  BatchArgs A = make_args(c, fb);
+  A.order = fb->fb_order;
+  A.wg_off = fb->fb_wgoff;
+  A.x0 = A0.x0;
+  A.v0 = A0.v0;
+  A.a = A0.a;
+  A.x1 = A0.x1;
+  A.v1 = A0.v1;
+  A.xbar = A0.xbar;
+  A.vbar = A0.vbar;
+  A.w = A0.w;
+  A.want_tail = A0.want_tail;
+  if ((r = launch(c, fb, s, mode, A, grid)) != ISB_OK) return r;
+  ISB_HIP(hipGetLastError());
+  ISB_HIP(hipMemcpyAsync(fb->hstats, fb->stats, c->n_bodies * sizeof(DevStats), hipMemcpyDeviceToHost, s));
+  ISB_HIP(hipStreamSynchronize(s));
+  for (int32_t b : bodies) {
+    st->hstats[b] = fb->hstats[b];
+    st->hstats[b].flags |= ISB_FLAG_FP64_FALLBACK;
+  }
+  // the context's stats keep the merged record (a later call merges its own phase into it)
+  ISB_HIP(hipMemcpy(st->stats, st->hstats, c->n_bodies * sizeof(DevStats), hipMemcpyHostToDevice));
+  return ISB_OK;
+}
+
+static bool body_failed(const DevStats& d, int mode) {
+  if (d.flags & ISB_FLAG_NONFINITE) return true;
+  return mode == 0 ? !(d.flags & ISB_FLAG_CONVERGED) : !(d.flags & ISB_FLAG_ADJ_CONVERGED);
+}
+
+static isb_status collect(isb_ctx* c, BatchedState* st, hipStream_t s, isb_stats* per_body, int mode,
+                          const BatchArgs& A) {
   if (c->graph_safe && !per_body) return ISB_OK;
   ISB_HIP(hipMemcpyAsync(st->hstats, st->stats, c->n_bodies * sizeof(DevStats), hipMemcpyDeviceToHost, s));
   ISB_HIP(hipStreamSynchronize(s));
+  if (c->precision == ISB_MIXED && c->fp64_fallback) {
+    std::vector<int32_t> failed;
+    for (int b = 0; b < c->n_bodies; ++b)
+      if (c->fp64_fallback == 2 || body_failed(st->hstats[b], mode)) failed.push_back(b);
+    if (!failed.empty()) {
+      const isb_status r = fp64_fallback(c, st, s, mode, A, failed);
+      if (r != ISB_OK) return r;
+    }
+  }
   if (per_body) std::memcpy(per_body, st->hstats, c->n_bodies * sizeof(DevStats));
   for (int b = 0; b < c->n_bodies; ++b) {
     const DevStats& d = st->hstats[b];
@@ -328,7 +396,7 @@ isb_status batched_step(isb_ctx* c, hipStream_t s, const double* x0, const doubl
   A.want_tail = per_body != nullptr;
   if ((r = launch(c, st, s, 0, A)) != ISB_OK) return r;
   ISB_HIP(hipGetLastError());
-  return collect(c, st, s, per_body, 0);
+  return collect(c, st, s, per_body, 0, A);
 }
 
 isb_status batched_adjoint(isb_ctx* c, hipStream_t s, const double* x1, const double* x0, const double* a,
@@ -346,7 +414,7 @@ isb_status batched_adjoint(isb_ctx* c, hipStream_t s, const double* x1, const do
   A.w = w;
   if ((r = launch(c, st, s, 1, A)) != ISB_OK) return r;
   ISB_HIP(hipGetLastError());
-  return collect(c, st, s, per_body, 1);
+  return collect(c, st, s, per_body, 1, A);
 }
 
 }  // namespace isb

@@ -59,6 +59,7 @@ struct isb_ctx {
   int model = 0;  // ISB_ENERGY_*
   int forward = 0, lbfgs_m = 8, lbfgs_max_iters = 20000;  // ISB_OPT_FORWARD and the L-BFGS settings
   int cg_graph = 0;                    // ISB_OPT_CG_GRAPH
+  int fp64_fallback = 1;               // ISB_OPT_FP64_FALLBACK
   hipStream_t cap_stream = nullptr;    // internal stream the CG chunk is captured on
 
   // plain-solver workspaces, [n_v*dim] unless noted
@@ -76,8 +77,10 @@ struct isb_ctx {
   double* hscal = nullptr;          // pinned host mirror of dscal
   isb::CgScal* hcg = nullptr;       // pinned host mirror of scal
 
-  // batched-solver state (owned by the batched solver)
+  // batched-solver state (owned by the batched solver); batched64: the FP64 state of the mixed
+  // solver's fallback, prepared on first use
   void* batched = nullptr;
+  void* batched64 = nullptr;
 
   ~isb_ctx();
   void free_list(std::vector<void*>& v);

@@ -21,7 +21,8 @@ STATUS_NAMES = {0: "ISB_OK", 1: "ISB_E_ARG", 2: "ISB_E_MESH", 3: "ISB_E_HIP", 4:
 ISB_FP64, ISB_MIXED = 0, 1
 ISB_QUASISTATIC, ISB_BACKWARD_EULER = 0, 1
 (OPT_SOLVER, OPT_SCATTER, OPT_GRAPH_SAFE, OPT_BLOCK, OPT_CG_CHECK, OPT_PRECISION, OPT_ENERGY, OPT_FORWARD,
- OPT_LBFGS_MEMORY, OPT_LBFGS_MAX_ITERS, OPT_CG_GRAPH) = range(11)
+ OPT_LBFGS_MEMORY, OPT_LBFGS_MAX_ITERS, OPT_CG_GRAPH, OPT_FP64_FALLBACK) = range(12)
+FLAG_CONVERGED, FLAG_STAGNATED, FLAG_NONFINITE, FLAG_ADJ_CONVERGED, FLAG_FP64_FALLBACK = 1, 2, 4, 8, 16
 FORWARD_NEWTON, FORWARD_LBFGS = 0, 1
 # isotropic element energies (ISB_ENERGY_*), by the names the synthetic workloads use
 ENERGY = {"nh": 0, "stvk": 1, "corot": 2, "snh": 3}

@@ -221,3 +221,34 @@ def test_cg_graph_iteration_cap_inside_a_chunk():
         counts[graph] = (st[0]["adj_cg_iters"], wv.cpu().numpy())
     assert counts[1][0] == counts[0][0] == 12
     assert np.array_equal(counts[1][1], counts[0][1])
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_mixed_fp64_fallback_path(dim):
+    """The mixed batched solver's FP64 recovery: forced for every body (option value 2), the step and
+    the adjoint come out as an FP64 context's, with the fallback flag set; in the default mode a
+    converged mixed solve takes no fallback."""
+    from paper_2102_05791_amd import isb
+    shape = (10, 3) if dim == 2 else (3, 3, 2)
+    w, rng = rand_workload(dim, seed=73, bodies=3, shape=shape)
+    w = _tight(w)
+    a = w.actions[0]
+    xbar = rng.normal(size=w.x0.shape)
+    ref = _ctx(w, precision="fp64", solver=1)
+    xr, vr, sr, _ = ref.step(_dev(w.x0), _dev(w.v0), _dev(a))
+    wr, _, _ = ref.solve_adjoint(xr, _dev(w.x0), _dev(a), _dev(xbar))
+    mixed = _ctx(w, precision="mixed", solver=1)
+    assert mixed.get_option(isb.OPT_FP64_FALLBACK) == 1
+    x1, v1, st, _ = mixed.step(_dev(w.x0), _dev(w.v0), _dev(a))
+    assert all(s["flags"] & isb.FLAG_CONVERGED and not s["flags"] & isb.FLAG_FP64_FALLBACK for s in st)
+    mixed.set_option(isb.OPT_FP64_FALLBACK, 2)
+    x1, v1, st, _ = mixed.step(_dev(w.x0), _dev(w.v0), _dev(a))
+    assert all(s["flags"] & isb.FLAG_FP64_FALLBACK and s["flags"] & isb.FLAG_CONVERGED for s in st)
+    d = w.x0
+    assert rel(x1.cpu().numpy() - d, xr.cpu().numpy() - d) <= 1e-12
+    assert rel(v1.cpu().numpy(), vr.cpu().numpy()) <= 1e-12
+    wv, sa, _ = mixed.solve_adjoint(xr, _dev(w.x0), _dev(a), _dev(xbar))
+    assert all(s["flags"] & isb.FLAG_FP64_FALLBACK and s["flags"] & isb.FLAG_ADJ_CONVERGED for s in sa)
+    assert rel(wv.cpu().numpy(), wr.cpu().numpy()) <= 1e-12
+    with pytest.raises(Exception):
+        mixed.set_option(isb.OPT_FP64_FALLBACK, 3)
