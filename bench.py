@@ -276,7 +276,11 @@ def main():
                 "traffic": measured_traffic(0 if dominant == "step" else 1),
                 "kernel": f"k_batched<2,float,{0 if dominant == 'step' else 1}> ({dominant} launch)",
                 "launch_ms": round(dom_ms, 4), "algorithmic_bytes_per_launch": int(dom_bytes),
-                "step_launch_ms": round(step_ms, 4), "adjoint_launch_ms": round(adj_ms, 4)}
+                "step_launch_ms": round(step_ms, 4), "adjoint_launch_ms": round(adj_ms, 4),
+                "adjoint_launch": {"algorithmic_bytes_per_launch": int(np.mean(ab)),
+                                   "achieved": round(float(np.mean(ab)) / (adj_ms * 1e-3) / 1e9, 1),
+                                   "frac": round(float(np.mean(ab)) / (adj_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                   "traffic": measured_traffic(1)}}
 
     # error against the oracle on sampled bodies, first step, at the metric's tolerance
     parity = None
