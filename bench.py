@@ -670,6 +670,7 @@ def tet_leg(args, torch, Context, isb, scenes):
     """3D tet block (393,216 tets): plain grid-wide path, mixed, T steps forward + T adjoints."""
     dev = torch.device("cuda:0")
     w = scenes.tet_block(steps=args.tet_steps)
+    w = w.permute_elements(isb.wave_order(3, w.n_v, w.T, w.body_e_off))
     ctx = Context.from_workload(w, precision="mixed", solver=0)
     x0 = torch.tensor(w.x0, device=dev)
     v0 = torch.tensor(w.v0, device=dev)
@@ -702,8 +703,8 @@ def tet_leg(args, torch, Context, isb, scenes):
     dt = time.perf_counter() - t0
     st, sa = run(2, True)
     print("# tet-block leg done", file=sys.stderr, flush=True)
-    return {"workload": f"tet_block 64x32x32 Kuhn tets ({w.n_e} tets, {w.n_v} vertices), {args.tet_steps} "
-                        "backward-Euler steps fwd + adjoint + VJP",
+    return {"workload": f"tet_block 64x32x32 Kuhn tets ({w.n_e} tets, {w.n_v} vertices; block order, then "
+                        f"isb_wave_order), {args.tet_steps} backward-Euler steps fwd + adjoint + VJP",
             "solver": "plain grid-wide Newton-PCG, mixed", "value": round(args.tet_steps / dt, 3),
             "unit": "steps/s", "seconds": round(dt, 3),
             "newton_per_step": float(np.mean([s[0]["newton_iters"] for s in st])),
@@ -723,35 +724,54 @@ def element_roofline_leg(args, torch, Context, isb, scenes):
 
 
 def element_roofline_mesh(grid, torch, Context, isb, scenes):
+    """The element kernels on one Kuhn-tet grid, with the elements in the order isb_wave_order gives
+    the 4x4x4-cube block order (the figures reported), and in the block order itself."""
     from synth import meshes
     dev = torch.device("cuda:0")
     nx, ny, nz = (int(v) for v in grid.split("x"))
     X, Tm = meshes.tet_grid(nx, ny, nz)
     n_e, n_v = Tm.shape[0], X.shape[0]
-    mu, lam = scenes.lame(1e5, 0.45)
     rng = np.random.default_rng([210205791, 6])
     x = torch.tensor(X + 0.01 * rng.standard_normal(X.shape), device=dev)
     p = torch.tensor(rng.standard_normal(X.shape), device=dev)
-    a = torch.tensor(meshes.contraction_actuation(rng, n_e), device=dev)
-    out = {"mesh": f"tet_grid {nx}x{ny}x{nz} (4x4x4-cube block element order): {n_e} tets, {n_v} vertices"}
+    a_np = meshes.contraction_actuation(rng, n_e)
+    perm = isb.wave_order(3, n_v, Tm)
+    out = {"mesh": f"tet_grid {nx}x{ny}x{nz}: {n_e} tets, {n_v} vertices; 4x4x4-cube block element order, "
+                   "then isb_wave_order inside each patch"}
+    out.update(element_times(X, np.ascontiguousarray(Tm[perm]), x, p, torch.tensor(a_np[perm], device=dev),
+                             torch, Context, scenes))
+    blk = element_times(X, Tm, x, p, torch.tensor(a_np, device=dev), torch, Context, scenes)
+    out["block_order"] = {k: {"launch_ms": v["launch_ms"], "frac_of_8TBs": v["frac_of_8TBs"]} for k, v in blk.items()}
+    return out
+
+
+def element_times(X, Tm, x, p, a, torch, Context, scenes):
+    from synth import meshes
+    n_e, n_v = Tm.shape[0], X.shape[0]
+    mu, lam = scenes.lame(1e5, 0.45)
+
+    def median_ms(fn):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        evs = []
+        for _ in range(20):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            evs.append((e0, e1))
+        torch.cuda.synchronize()
+        return float(np.median([e0.elapsed_time(e1) for e0, e1 in evs]))
+
+    out = {}
     for prec, word in (("fp64", 8), ("mixed", 4)):
         ctx = Context(0, prec)
         ctx.mesh_upload(3, X, Tm, None)
         ctx.material_upload(np.full(n_e, mu), np.full(n_e, lam), np.full(n_e, 1e5), meshes.x_fibres(n_e, 3),
                             np.ones(n_e), scenes.scene("be", h=1.0 / 30.0))
         hp = torch.zeros_like(x)
-        for _ in range(3):
-            ctx.hessvec_elements(x, a, p, hp)
-        torch.cuda.synchronize()
-        evs = []
-        for _ in range(20):
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            ctx.hessvec_elements(x, a, p, hp)
-            e1.record()
-            evs.append((e0, e1))
-        torch.cuda.synchronize()
-        ms = float(np.median([e0.elapsed_time(e1) for e0, e1 in evs]))
+        ms = median_ms(lambda: ctx.hessvec_elements(x, a, p, hp))
         # isb_hessvec_elements reads the FP64 actuation in both precisions
         elem_b = elem_bytes(3, word) + (4 if prec == "mixed" else 0)
         byt = n_e * elem_b + n_v * 3 * (8 + 8 + 16)
@@ -761,18 +781,7 @@ def element_roofline_mesh(grid, torch, Context, isb, scenes):
         if prec == "fp64":
             # the element gradient (FP64 in both precisions): element data once, x read, g read and written
             g = torch.zeros_like(x)
-            for _ in range(3):
-                ctx.gradient_elements(x, a, g)
-            torch.cuda.synchronize()
-            evs = []
-            for _ in range(20):
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e0.record()
-                ctx.gradient_elements(x, a, g)
-                e1.record()
-                evs.append((e0, e1))
-            torch.cuda.synchronize()
-            gms = float(np.median([e0.elapsed_time(e1) for e0, e1 in evs]))
+            gms = median_ms(lambda: ctx.gradient_elements(x, a, g))
             gbyt = n_e * elem_bytes(3, 8) + n_v * 3 * (8 + 16)
             ggbs = gbyt / (gms * 1e-3) / 1e9
             out["gradient_fp64"] = {"launch_ms": round(gms, 4), "algorithmic_bytes": int(gbyt),

@@ -200,6 +200,20 @@ isb_status isb_colour_elements(int dim, int64_t n_v, int64_t n_e, const int32_t*
 isb_status isb_locality_order(int dim, int64_t n_v, const double* X, int64_t n_e, const int32_t* T,
                               int32_t n_bodies, const int64_t* body_e_off, int64_t* perm_out);
 
+/* An order of the elements for the patch scatter's wavefronts, applied after a locality order:
+ * perm_out host [n_e] receives, for each new position, the element that goes there. It only
+ * permutes elements inside each patch of the plan isb_mesh_upload builds for this T (n_v
+ * vertices, T host [n_e][dim+1] int32, body_e_off host [n_bodies+1] or NULL for one body): the
+ * patches, their vertex sets and the plan's boundaries are unchanged. Inside a patch, each group of
+ * 64 consecutive elements from the patch's first (one wavefront of the patch kernels) receives
+ * elements with distinct vertices in each corner slot where a greedy placement finds them, so that
+ * the lanes of one LDS atomic add address distinct vertices. A caller applies the permutation to T
+ * and to every per-element array once, before isb_mesh_upload; results change only by the
+ * rounding of the summation order. Deterministic; ISB_E_MESH for an out-of-range vertex,
+ * ISB_E_ARG otherwise. */
+isb_status isb_wave_order(int dim, int64_t n_v, int64_t n_e, const int32_t* T, int32_t n_bodies,
+                          const int64_t* body_e_off, int64_t* perm_out);
+
 /* ---- upload ------------------------------------------------------------------------------- */
 
 /* Copy a mesh of n_bodies independent bodies to the device and precompute Dm^-1 and W per element.

@@ -832,8 +832,7 @@ isb_status isb_mesh_upload(isb_ctx* c, int dim, int32_t n_bodies, const int64_t*
   // element patches for the LDS-staged scatter, sized to the patch workgroup's LDS budget
   Patches pt;
   {
-    const int per_vertex = 3 * dim * (int)sizeof(double);  // x, p and the accumulator, FP64
-    ISB_TRY(build_patches(dim, n_v, n_bodies, body_e_off, T, 1024, kPatchLdsBytes / per_vertex, &pt));
+    ISB_TRY(build_patches(dim, n_v, n_bodies, body_e_off, T, kPatchMaxElems, patch_max_verts(dim), &pt));
     c->n_patches = (int)pt.eoff.size() - 1;
     c->body_patch_off.assign(n_bodies + 1, 0);
     int k = 0;

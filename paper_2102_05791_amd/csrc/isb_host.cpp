@@ -103,8 +103,10 @@ isb_status build_patches(int dim, int64_t n_v, int n_bodies, const int64_t* eoff
   std::vector<int32_t> ids;
   int32_t patch = 0;
   for (int b = 0; b < n_bodies; ++b) {
-    // about a thousand patches per body when it is large enough, so that the launch fills the GPU
-    const int64_t me = std::min<int64_t>(max_elems, std::max<int64_t>(256, (eoff[b + 1] - eoff[b]) / 1024));
+    // about a thousand patches per body when it is large enough, so that the launch fills the GPU;
+    // a whole number of 64-element wavefronts, so that every wavefront of a full patch is full
+    const int64_t per = ((eoff[b + 1] - eoff[b]) / 1024 + 63) / 64 * 64;
+    const int64_t me = std::min<int64_t>(max_elems, std::max<int64_t>(256, per));
     int64_t e = eoff[b];
     while (e < eoff[b + 1]) {
       const int64_t start = e;
@@ -135,6 +137,60 @@ isb_status build_patches(int dim, int64_t n_v, int n_bodies, const int64_t* eoff
       out->max_nv = std::max<int>(out->max_nv, (int)ids.size());
       ++patch;
     }
+  }
+  return ISB_OK;
+}
+
+isb_status wave_order(int dim, int64_t n_v, int n_bodies, const int64_t* eoff, const int32_t* T, int64_t* perm) {
+  constexpr int kWave = 64;
+  const int nk = dim + 1;
+  Patches pt;
+  const isb_status st = build_patches(dim, n_v, n_bodies, eoff, T, kPatchMaxElems, patch_max_verts(dim), &pt);
+  if (st != ISB_OK) return st;
+  // bit w of mask[v * nk + k]: a wavefront group w of the current patch has vertex v in slot k
+  std::vector<uint32_t> mask((size_t)n_v * nk, 0);
+  std::vector<int> fill, cap;
+  std::vector<int64_t> slots;
+  static_assert(kPatchMaxElems / kWave <= 32, "groups of one patch must fit the 32-bit mask");
+  for (size_t q = 0; q + 1 < pt.eoff.size(); ++q) {
+    const int64_t s = pt.eoff[q], e1 = pt.eoff[q + 1];
+    const int len = (int)(e1 - s), nw = (len + kWave - 1) / kWave;
+    fill.assign(nw, 0);
+    cap.assign(nw, kWave);
+    cap[nw - 1] = len - (nw - 1) * kWave;  // groups full but the last, as the kernel's lanes take them
+    slots.assign((size_t)nw * kWave, 0);
+    for (int64_t e = s; e < e1; ++e)
+      for (int k = 0; k < nk; ++k) mask[(size_t)T[e * nk + k] * nk + k] = 0;
+    int start = 0;
+    for (int64_t e = s; e < e1; ++e) {
+      const int32_t* t = T + e * nk;
+      uint32_t used = 0;
+      for (int k = 0; k < nk; ++k) used |= mask[(size_t)t[k] * nk + k];
+      // the first group from a rotating start with room and no clash; else the fewest clashes
+      int pick = -1;
+      for (int j = 0; j < nw && pick < 0; ++j) {
+        const int w = (start + j) % nw;
+        if (fill[w] < cap[w] && !((used >> w) & 1u)) pick = w;
+      }
+      if (pick < 0) {
+        int best = nk + 1;
+        for (int w = 0; w < nw; ++w) {
+          if (fill[w] >= cap[w]) continue;
+          int c = 0;
+          for (int k = 0; k < nk; ++k) c += (mask[(size_t)t[k] * nk + k] >> w) & 1u;
+          if (c < best) {
+            best = c;
+            pick = w;
+          }
+        }
+      }
+      for (int k = 0; k < nk; ++k) mask[(size_t)t[k] * nk + k] |= 1u << pick;
+      slots[(size_t)pick * kWave + fill[pick]++] = e;
+      start = (pick + 1) % nw;
+    }
+    int64_t o = s;
+    for (int w = 0; w < nw; ++w)
+      for (int i = 0; i < fill[w]; ++i) perm[o++] = slots[(size_t)w * kWave + i];
   }
   return ISB_OK;
 }
@@ -205,6 +261,27 @@ isb_status isb_locality_order(int dim, int64_t n_v, const double* X, int64_t n_e
     std::stable_sort(perm_out + eoff[b], perm_out + eoff[b + 1],
                      [&](int64_t a, int64_t c) { return key[a] < key[c]; });
   return ISB_OK;
+}
+
+isb_status isb_wave_order(int dim, int64_t n_v, int64_t n_e, const int32_t* T, int32_t n_bodies,
+                          const int64_t* body_e_off, int64_t* perm_out) {
+  isb::clear_error();
+  if ((dim != 2 && dim != 3) || n_v <= 0 || n_e < 0 || (n_e > 0 && !T) || !perm_out || n_bodies < 0 ||
+      (body_e_off && n_bodies < 1))
+    return isb::fail(ISB_E_ARG, "isb_wave_order: bad argument");
+  std::vector<int64_t> eoff{0, n_e};
+  int32_t nb = 1;
+  if (body_e_off) {
+    eoff.assign(body_e_off, body_e_off + n_bodies + 1);
+    nb = n_bodies;
+    if (eoff.front() != 0 || eoff.back() != n_e) return isb::fail(ISB_E_ARG, "isb_wave_order: bad body_e_off");
+    for (int32_t b = 0; b < n_bodies; ++b)
+      if (eoff[b + 1] < eoff[b]) return isb::fail(ISB_E_ARG, "isb_wave_order: bad body_e_off");
+  }
+  for (int64_t i = 0; i < n_e * (dim + 1); ++i)
+    if (T[i] < 0 || T[i] >= n_v) return isb::fail(ISB_E_MESH, "isb_wave_order: vertex index out of range");
+  if (n_e == 0) return ISB_OK;
+  return isb::wave_order(dim, n_v, nb, eoff.data(), T, perm_out);
 }
 
 isb_status isb_colour_elements(int dim, int64_t n_v, int64_t n_e, const int32_t* T, int32_t* colour_out,

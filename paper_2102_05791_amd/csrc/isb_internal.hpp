@@ -65,7 +65,6 @@ struct PatchPlan {
 };
 
 constexpr int kPatchBlock = 512;        // threads per patch workgroup (FP32 element math; FP64 takes half)
-constexpr int kPatchLdsBytes = 64 * 1024;  // LDS per patch workgroup (two workgroups per CU)
 
 enum PatchOp { PATCH_GRAD = 0, PATCH_HV = 1, PATCH_DIAG = 2 };
 

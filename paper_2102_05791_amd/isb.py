@@ -27,14 +27,13 @@ FORWARD_NEWTON, FORWARD_LBFGS = 0, 1
 # isotropic element energies (ISB_ENERGY_*), by the names the synthetic workloads use
 ENERGY = {"nh": 0, "stvk": 1, "corot": 2, "snh": 3}
 INFO_N_VERTICES, INFO_N_ELEMENTS, INFO_N_BODIES, INFO_DIM, INFO_N_COLOURS, INFO_LDS_BYTES = range(100, 106)
-FLAG_CONVERGED, FLAG_STAGNATED, FLAG_NONFINITE, FLAG_ADJ_CONVERGED = 1, 2, 4, 8
 
 EXPORTED = ("isb_create", "isb_destroy", "isb_last_error", "isb_version", "isb_validate_mesh",
             "isb_colour_elements", "isb_mesh_upload", "isb_material_upload", "isb_set_scene",
             "isb_set_option", "isb_get_option", "isb_get_mass", "isb_step", "isb_solve_adjoint",
             "isb_vjp_params", "isb_energy", "isb_gradient", "isb_hessvec", "isb_hessvec_elements",
             "isb_hessdiag", "isb_stream_copy", "isb_spring_upload", "isb_vjp_spring_stiffness",
-            "isb_gradient_elements", "isb_locality_order", "isb_autotune")
+            "isb_gradient_elements", "isb_locality_order", "isb_wave_order", "isb_autotune")
 
 
 class IsbError(RuntimeError):
@@ -97,6 +96,7 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
         "isb_validate_mesh": [ctypes.c_int, i64, vp, i64, vp, i32, vp, vp],
         "isb_colour_elements": [ctypes.c_int, i64, i64, vp, vp, P(i32)],
         "isb_locality_order": [ctypes.c_int, i64, vp, i64, vp, i32, vp, vp],
+        "isb_wave_order": [ctypes.c_int, i64, i64, vp, i32, vp, vp],
         "isb_autotune": [vp, vp, vp, vp, vp, vp],
         "isb_mesh_upload": [vp, ctypes.c_int, i32, vp, vp, vp, vp, vp],
         "isb_material_upload": [vp, vp, vp, vp, vp, vp, P(Scene)],
@@ -178,6 +178,22 @@ def locality_order(dim, X, T, body_e_off=None):
         eo, peo = _host(body_e_off, np.int64)
         _check(lib, lib.isb_locality_order(dim, X.shape[0], pX, T.shape[0], pT, len(eo) - 1, peo,
                                            perm.ctypes.data_as(ctypes.c_void_p)))
+    return perm
+
+
+def wave_order(dim, n_v, T, body_e_off=None):
+    """isb_wave_order: the element permutation (new position -> element) that packs each patch's
+    wavefront groups with distinct vertices per corner slot; it keeps the patches."""
+    lib = load_library()
+    T, pT = _host(T, np.int32)
+    perm = np.zeros(T.shape[0], dtype=np.int64)
+    if body_e_off is None:
+        _check(lib, lib.isb_wave_order(dim, int(n_v), T.shape[0], pT, 1, None,
+                                       perm.ctypes.data_as(ctypes.c_void_p)))
+    else:
+        eo, peo = _host(body_e_off, np.int64)
+        _check(lib, lib.isb_wave_order(dim, int(n_v), T.shape[0], pT, len(eo) - 1, peo,
+                                       perm.ctypes.data_as(ctypes.c_void_p)))
     return perm
 
 

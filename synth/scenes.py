@@ -106,6 +106,25 @@ class Workload:
                         self.x0[v0:v1].copy(), self.v0[v0:v1].copy(), acts,
                         S=(self.S[s0:s1] - v0).astype(np.int32), ks=self.ks[s0:s1].copy(), model=self.model)
 
+    def permute_elements(self, perm) -> "Workload":
+        """The same workload with its elements in the order `perm` (new position -> element),
+        which must keep each body's elements in that body's range: connectivity, per-element
+        material and the elements' actions move together; vertices and springs stay."""
+        perm = np.asarray(perm, dtype=np.int64)
+        if perm.shape != (self.n_e,) or not np.array_equal(np.sort(perm), np.arange(self.n_e)):
+            raise ValueError("perm is not a permutation of the elements")
+        for b in range(self.n_bodies):
+            e0, e1 = int(self.body_e_off[b]), int(self.body_e_off[b + 1])
+            if e1 > e0 and (perm[e0:e1].min() < e0 or perm[e0:e1].max() >= e1):
+                raise ValueError(f"perm moves an element out of body {b}")
+        acts = self.actions.copy()
+        acts[:, :self.n_e] = self.actions[:, perm]
+        return Workload(self.name, self.dim, self.X, np.ascontiguousarray(self.T[perm]), self.pinned,
+                        self.mu[perm], self.lam[perm], self.kf[perm], np.ascontiguousarray(self.fdir[perm]),
+                        self.rho[perm], dict(self.scene), self.x0, self.v0, acts,
+                        body_v_off=self.body_v_off, body_e_off=self.body_e_off, S=self.S, ks=self.ks,
+                        body_s_off=self.body_s_off, model=self.model)
+
 
 def _material(n_e, dim, E, nu):
     mu, lam = lame(E, nu)

@@ -108,12 +108,17 @@ def test_mass_matches_oracle():
     assert rel(m, ref) <= 1e-15
 
 
+@pytest.mark.parametrize("order", ["given", "wave"])
 @pytest.mark.parametrize("dim,shape", [(2, (130, 65)), (3, (16, 16, 11))], ids=["2d-16900", "3d-16896"])
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 2e-6)])
-def test_patch_scatter_large_mesh(dim, shape, precision, tol):
-    """Meshes above the patch threshold take the LDS-staged patch scatter (isb scatter mode 2)."""
+def test_patch_scatter_large_mesh(dim, shape, precision, tol, order):
+    """Meshes above the patch threshold take the LDS-staged patch scatter (isb scatter mode 2), in
+    the elements' given order and in the order isb_wave_order gives them."""
+    from paper_2102_05791_amd import isb
     w, rng = rand_workload(dim, seed=6, shape=shape)
     assert w.n_e >= 16384
+    if order == "wave":
+        w = w.permute_elements(isb.wave_order(dim, w.n_v, w.T, w.body_e_off))
     ctx = _ctx(w, precision=precision, scatter=2)
     x = _state(w, rng)
     a = w.actions[0]
