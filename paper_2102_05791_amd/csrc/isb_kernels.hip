@@ -971,23 +971,30 @@ __global__ void __launch_bounds__(PB) k_elem_patch(DevMesh m, DevScene sc, Patch
                                                             const float* __restrict__ a32,
                                                             const double* __restrict__ pv, double* out,
                                                             const int* done) {
-  // LDS: x, the accumulator and the Hessian-vector operand p per patch DOF, all FP64: the element
-  // takes differences of x and of p, which must be formed before any rounding to T
+  // LDS: x, the accumulator and the Hessian-vector operand p per patch DOF, all FP64 (the element
+  // takes differences of x and of p, which must be formed before any rounding to T), then the
+  // global id of each patch vertex, so that the flush needs no second load of the vertex list
   extern __shared__ double lds[];
   if (OP == PATCH_HV && done && *done) return;
   const int nmax = P.max_nv * D;
   double* xs = lds;
   double* acc = lds + nmax;
   double* ps = lds + 2 * nmax;
+  int* vid = reinterpret_cast<int*>(lds + (OP == PATCH_HV ? 3 : 2) * nmax);
   for (int pk = p0 + blockIdx.x; pk < p1; pk += gridDim.x) {
     const int vb = P.voff[pk], nv = P.voff[pk + 1] - vb;
     const int eb = P.eoff[pk], ee = P.eoff[pk + 1];
-    for (int i = threadIdx.x; i < nv * D; i += blockDim.x) {
-      const int vl = i / D, c = i - vl * D;
-      const size_t g = (size_t)P.verts[vb + vl] * D + c;
-      xs[i] = x[g];
-      if (OP == PATCH_HV) ps[i] = pv[g];
-      acc[i] = 0.0;
+    // one vertex per thread: its id, then its D components of x (and p) in one round trip
+    for (int vl = threadIdx.x; vl < nv; vl += blockDim.x) {
+      const int gv = P.verts[vb + vl];
+      vid[vl] = gv;
+      const size_t g = (size_t)gv * D;
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        xs[vl * D + c] = x[g + c];
+        if (OP == PATCH_HV) ps[vl * D + c] = pv[g + c];
+        acc[vl * D + c] = 0.0;
+      }
     }
     __syncthreads();
     for (int e = eb + threadIdx.x; e < ee; e += blockDim.x) {
@@ -1026,7 +1033,7 @@ __global__ void __launch_bounds__(PB) k_elem_patch(DevMesh m, DevScene sc, Patch
     __syncthreads();
     for (int i = threadIdx.x; i < nv * D; i += blockDim.x) {
       const int vl = i / D, c = i - vl * D;
-      unsafeAtomicAdd(out + (size_t)P.verts[vb + vl] * D + c, acc[i]);
+      unsafeAtomicAdd(out + (size_t)vid[vl] * D + c, acc[i]);
     }
     __syncthreads();
   }
@@ -1036,7 +1043,7 @@ template <int D, typename T, int OP>
 static void patch_launch(const DevMesh& m, const DevScene& sc, const PatchPlan& P, int p0, int p1, const double* x,
                          const double* a, const float* a32, const double* p, double* out, const int* done,
                          hipStream_t s) {
-  const size_t lds = (size_t)P.max_nv * D * sizeof(double) * (OP == PATCH_HV ? 3 : 2);
+  const size_t lds = (size_t)P.max_nv * (D * sizeof(double) * (OP == PATCH_HV ? 3 : 2) + sizeof(int));
   int grid = p1 - p0;
   if (grid > 65535) grid = 65535;
   // FP64 element math needs about twice the registers of FP32: 256-thread workgroups keep more of
