@@ -30,7 +30,7 @@ isb_status build_patches(int dim, int64_t n_v, int n_bodies, const int64_t* eoff
 
 // The patch plan the context builds: at most kPatchMaxElems elements per patch, and as many
 // vertices as fit x, p, the FP64 accumulator and the vertex id in kPatchLdsBytes of LDS.
-constexpr int kPatchMaxElems = 1024;
+constexpr int kPatchMaxElems = 2048;
 constexpr int kPatchLdsBytes = 64 * 1024;  // LDS per patch workgroup (two workgroups per CU)
 constexpr int patch_max_verts(int dim) { return kPatchLdsBytes / (3 * dim * (int)sizeof(double) + 4); }
 

@@ -148,14 +148,14 @@ def test_locality_order_is_a_per_body_permutation_that_compacts_patches():
 
 
 def _patch_bounds(T, n_v, eoff, dim):
-    """Patch boundaries by the plan's rule: per body, runs of min(1024, max(256, n_b/1024 rounded
+    """Patch boundaries by the plan's rule: per body, runs of min(2048, max(256, n_b/1024 rounded
     up to a multiple of 64)) elements, cut early where the distinct vertices would exceed what
     three FP64 vectors and a 4-byte vertex id fit in 64 KB of LDS."""
     budget = 64 * 1024 // (3 * dim * 8 + 4)
     out = [0]
     for b in range(len(eoff) - 1):
         n_b = eoff[b + 1] - eoff[b]
-        me = min(1024, max(256, -(-(n_b // 1024) // 64) * 64))
+        me = min(2048, max(256, -(-(n_b // 1024) // 64) * 64))
         e = eoff[b]
         while e < eoff[b + 1]:
             seen, start = set(), e
