@@ -75,6 +75,8 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--block", type=int, default=0, help="batched workgroup size (0 = library default)")
     ap.add_argument("--profile", action="store_true", help="one untimed pass only (for rocprofv3)")
+    ap.add_argument("--profile-elements", action="store_true",
+                    help="the element kernels alone on the --elem-grid mesh in wave order (for rocprofv3)")
     ap.add_argument("--no-tet", action="store_true", help="skip the 3D tet-block leg")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay leg")
     ap.add_argument("--no-policy", action="store_true", help="skip the policy-training leg")
@@ -176,6 +178,14 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.profile_elements:
+        out = element_roofline_mesh(args.elem_grid, torch, Context, isb, scenes, block_order=False)
+        src = torch.ones(2 ** 27, dtype=torch.float64, device=dev)   # byte-counter calibration copy
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_pass": "elements", "copy_bytes_each_way": 2 ** 30, **out}))
+        return
     T = args.rollout
     w = scenes.batched_strips(args.bodies, steps=T)
     nb = w.n_bodies
@@ -723,7 +733,7 @@ def element_roofline_leg(args, torch, Context, isb, scenes):
     return out
 
 
-def element_roofline_mesh(grid, torch, Context, isb, scenes):
+def element_roofline_mesh(grid, torch, Context, isb, scenes, block_order=True):
     """The element kernels on one Kuhn-tet grid, with the elements in the order isb_wave_order gives
     the 4x4x4-cube block order (the figures reported), and in the block order itself."""
     from synth import meshes
@@ -740,8 +750,10 @@ def element_roofline_mesh(grid, torch, Context, isb, scenes):
                    "then isb_wave_order inside each patch"}
     out.update(element_times(X, np.ascontiguousarray(Tm[perm]), x, p, torch.tensor(a_np[perm], device=dev),
                              torch, Context, scenes))
-    blk = element_times(X, Tm, x, p, torch.tensor(a_np, device=dev), torch, Context, scenes)
-    out["block_order"] = {k: {"launch_ms": v["launch_ms"], "frac_of_8TBs": v["frac_of_8TBs"]} for k, v in blk.items()}
+    if block_order:
+        blk = element_times(X, Tm, x, p, torch.tensor(a_np, device=dev), torch, Context, scenes)
+        out["block_order"] = {k: {"launch_ms": v["launch_ms"], "frac_of_8TBs": v["frac_of_8TBs"]}
+                              for k, v in blk.items()}
     return out
 
 
