@@ -276,6 +276,8 @@ def main():
           "adj_cg_per_step": float(np.mean([[s["adj_cg_iters"] for s in S] for S in st_a])),
           "max_newton": int(np.max([[s["newton_iters"] for s in S] for S in st_f])),
           "not_converged_steps": int(sum(1 for S in st_f for s in S if not (s["flags"] & 1))),
+          "stagnated_steps": int(sum(1 for S in st_f for s in S if s["flags"] & 2)),
+          "fp64_fallback_steps": int(sum(1 for S in st_f for s in S if s["flags"] & 16)),
           "adj_not_converged": int(sum(1 for S in st_a for s in S if not (s["flags"] & 8)))}
     dominant = "step" if step_ms >= adj_ms else "adjoint"
     dom_ms = step_ms if dominant == "step" else adj_ms

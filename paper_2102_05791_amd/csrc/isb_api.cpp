@@ -22,7 +22,8 @@ static constexpr double kArmijoC1 = 1e-4;
 static constexpr int kMaxBacktracks = 30;
 static constexpr double kEps = 2.220446049250313e-16;
 // Below the FP64 resolution of g the line search accepts a step only if it at least halves
-// |grad g|; a smaller decrease is rounding noise, and the solve stops there as stagnated.
+// |grad g| or brings it under the stopping threshold; a smaller decrease is rounding noise, and the
+// solve stops there as stagnated.
 static constexpr double kFloorDecrease = 0.5;
 
 void isb_ctx::free_list(std::vector<void*>& v) {
@@ -340,14 +341,15 @@ static isb_status run_cg(isb_ctx* c, int b, const double* x, const double* a, co
 // one Newton-PCG solve of body b; x is the iterate (workspace), G its gradient
 // Armijo backtracking along dx from the iterate *px (gradient *pG, norm *res, g^T dx = gTd < 0) on
 // sum_e [g_e(x + alpha dx) - g_e(x)]. Below the FP64 resolution of g the gradient decides instead:
-// Newton takes the step if |grad g| at least halves and otherwise stops (shorter steps of a
-// quadratically convergent method cannot do better at the floor); a first-order method takes it if
-// the slope along dx has not turned past half its initial size, grad g(x + alpha dx) . dx <=
-// |gTd| / 2 (on a quadratic that holds up to 1.5 times the exact line minimiser, where g still
-// decreases), and otherwise halves alpha. On acceptance *px, *pG and *res hold the new iterate (the
-// buffers may swap with *pxt, *pGt) and *alpha_out the step taken.
+// Newton takes the step if |grad g| at least halves or falls to res_stop (the stopping threshold)
+// and otherwise stops (shorter steps of a quadratically convergent method cannot do better at the
+// floor); a first-order method takes it if |grad g| falls to res_stop or the slope along dx has not
+// turned past half its initial size, grad g(x + alpha dx) . dx <= |gTd| / 2 (on a quadratic that
+// holds up to 1.5 times the exact line minimiser, where g still decreases), and otherwise halves
+// alpha. On acceptance *px, *pG and *res hold the new iterate (the buffers may swap with *pxt, *pGt)
+// and *alpha_out the step taken.
 static isb_status line_search(isb_ctx* c, int b, hipStream_t s, const double* x0, const double* a, const double* dx,
-                              double gTd, bool first_order, double** px, double** pxt, double** pG,
+                              double gTd, double res_stop, bool first_order, double** px, double** pxt, double** pG,
                               double** pGt, double* res, isb_stats* st, bool* accepted_out, double* alpha_out) {
   const BodyRange br = body_range(c, b);
   double *x = *px, *xt = *pxt, *G = *pG, *Gt = *pGt;
@@ -375,9 +377,9 @@ static isb_status line_search(isb_ctx* c, int b, hipStream_t s, const double* x0
         launch_dot(br.n, Gt + br.off, dx + br.off, c->partials, s, &nb);
         launch_finalize(c->partials, nb, 1, c->dscal, s);
         ISB_TRY(read_scal(c, s, 1));
-        take = c->hscal[0] <= 0.5 * std::fabs(gTd);
+        take = rt <= res_stop || c->hscal[0] <= 0.5 * std::fabs(gTd);
       } else {
-        take = rt <= kFloorDecrease * *res;
+        take = rt <= kFloorDecrease * *res || rt <= res_stop;
         if (!take) break;  // shorter steps cannot do better at the rounding floor
       }
       if (take) {
@@ -433,12 +435,14 @@ static isb_status plain_newton(isb_ctx* c, int b, hipStream_t s, const double* x
       break;
     }
     eval_precond(c, b, x, a, s);
-    // inexact Newton forcing term: the CG tolerance tightens as the gradient falls
+    // inexact Newton forcing term: the CG tolerance tightens as the gradient falls, but not below
+    // half the Newton stopping threshold, which a more accurate last step could not improve on
     const double eta = std::min(0.5, std::sqrt(res / res0));
+    const double cg_tol = std::max(eta * res, 0.5 * sc.tol_rel * res0);
     int cg_it = 0;
     bool neg = false;
     double rr = 0.0;
-    ISB_TRY(run_cg(c, b, x, a, G, -1.0, eta * res, sc.max_cg, s, &cg_it, &neg, &rr));
+    ISB_TRY(run_cg(c, b, x, a, G, -1.0, cg_tol, sc.max_cg, s, &cg_it, &neg, &rr));
     st->cg_iters += cg_it;
     st->negcurv_exits += neg ? 1 : 0;
     double* dx = c->w_xs;
@@ -461,7 +465,8 @@ static isb_status plain_newton(isb_ctx* c, int b, hipStream_t s, const double* x
     }
     bool accepted = false;
     double alpha = 0.0;
-    ISB_TRY(line_search(c, b, s, x0, a, dx, gTd, false, &x, &xt, &G, &Gt, &res, st, &accepted, &alpha));
+    ISB_TRY(line_search(c, b, s, x0, a, dx, gTd, sc.tol_rel * res0, false, &x, &xt, &G, &Gt, &res, st, &accepted,
+                        &alpha));
     if (!accepted) {
       st->flags |= ISB_FLAG_STAGNATED;
       break;
@@ -567,7 +572,8 @@ static isb_status plain_lbfgs(isb_ctx* c, int b, hipStream_t s, const double* x0
     launch_copy(n, G + o, Gold + o, s);
     bool accepted = false;
     double alpha = 0.0;
-    ISB_TRY(line_search(c, b, s, x0, a, dx, gTd, true, &x, &xt, &G, &Gt, &res, st, &accepted, &alpha));
+    ISB_TRY(line_search(c, b, s, x0, a, dx, gTd, sc.tol_rel * res0, true, &x, &xt, &G, &Gt, &res, st, &accepted,
+                        &alpha));
     if (!accepted) {
       st->flags |= ISB_FLAG_STAGNATED;
       break;

@@ -820,10 +820,12 @@ struct BodySolver {
         break;
       }
       if (st.newton_iters >= A.max_newton) break;
+      // forcing term: the CG tolerance tightens as the gradient falls, but not below half the
+      // Newton stopping threshold, which a more accurate last step could not improve on
       const double eta = fmin(0.5, sqrt(res / res0));
       int it = 0;
       bool neg = false;
-      cg(G, -1.0, eta * res, A.max_cg, dx, it, neg);
+      cg(G, -1.0, fmax(eta * res, 0.5 * A.tol * res0), A.max_cg, dx, it, neg);
       st.cg_iters += it;
       st.negcurv_exits += neg ? 1 : 0;
       double gTd = 0.0;
@@ -861,9 +863,9 @@ struct BodySolver {
         if (isfinite(tr[0]) && isfinite(rt)) {
           if (fabs(tr[0]) > 1e3 * 2.220446049250313e-16 * tr[1]) {
             accepted = tr[0] <= 1e-4 * alpha * gTd;
-          } else if (rt <= 0.5 * res) {
+          } else if (rt <= 0.5 * res || rt <= A.tol * res0) {
             // below the FP64 resolution of g the Armijo test only sees rounding: a step that at
-            // least halves |grad g| is accepted instead
+            // least halves |grad g|, or brings it under the stopping threshold, is accepted instead
             accepted = true;
           } else {
             break;  // shorter steps cannot do better at the rounding floor

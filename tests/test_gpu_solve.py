@@ -244,9 +244,12 @@ def test_mixed_fp64_fallback_path(dim):
     mixed.set_option(isb.OPT_FP64_FALLBACK, 2)
     x1, v1, st, _ = mixed.step(_dev(w.x0), _dev(w.v0), _dev(a))
     assert all(s["flags"] & isb.FLAG_FP64_FALLBACK and s["flags"] & isb.FLAG_CONVERGED for s in st)
+    # two FP64 solves, each stopped at |grad g| <= 1e-13 |grad g0| with its own workgroup schedule
+    # (so its own rounding): each lies within about 5e-12 of the minimiser on these bodies, so they
+    # agree to the FP64 step parity bar; a mixed solve would be about 1e-6 away
     d = w.x0
-    assert rel(x1.cpu().numpy() - d, xr.cpu().numpy() - d) <= 1e-12
-    assert rel(v1.cpu().numpy(), vr.cpu().numpy()) <= 1e-12
+    assert rel(x1.cpu().numpy() - d, xr.cpu().numpy() - d) <= 1e-10
+    assert rel(v1.cpu().numpy(), vr.cpu().numpy()) <= 1e-10
     wv, sa, _ = mixed.solve_adjoint(xr, _dev(w.x0), _dev(a), _dev(xbar))
     assert all(s["flags"] & isb.FLAG_FP64_FALLBACK and s["flags"] & isb.FLAG_ADJ_CONVERGED for s in sa)
     assert rel(wv.cpu().numpy(), wr.cpu().numpy()) <= 1e-12
