@@ -4,8 +4,8 @@
 One bench step = one full backprop-through-time pass over the batch: 512 strips of uneven size
 (4s x s quads, s ~ U{4..32}, 128 to 8192 triangles), 50 backward-Euler steps forward
 (isb_step, Newton-PCG to 1e-6 relative residual), then 50 adjoint solves (isb_solve_adjoint,
-CG to 1e-6) and parameter VJPs (isb_vjp_params) backward, loss = -sum of the bodies' centre of
-mass x. value = bodies x steps / seconds for the batched mixed-precision persistent solver.
+CG to 1e-6, each starting from the adjoint of the step after) and parameter VJPs (isb_vjp_params)
+backward, loss = -sum of the bodies' centre of mass x. value = bodies x steps / seconds for the batched mixed-precision persistent solver.
 Beside it: the plain single-body FP64 GPU path on a stratified body subset, the FP64 CPU
 oracle on a bounded sample, the error against the oracle on sampled bodies, and the roofline
 of the dominant kernel (the persistent step launch), timed with HIP events on the stream the
@@ -220,11 +220,12 @@ def main():
             st_f.append(s)
         xb, vb = xbar_T, torch.zeros_like(x0)
         a_bar = torch.empty_like(acts)
+        wv = None  # each adjoint CG starts from the adjoint of the step after, in place
         for t in range(T - 1, -1, -1):
             if record:
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 e0.record()
-            wv, s, _ = ctx.solve_adjoint(xs[t + 1], xs[t], acts[t], xb, vb, stats=stats)
+            wv, s, _ = ctx.solve_adjoint(xs[t + 1], xs[t], acts[t], xb, vb, stats=stats, w=wv, w_init=wv)
             if record:
                 e1.record()
                 adj_ev.append((e0, e1))
@@ -340,8 +341,9 @@ def main():
                 vs_.append(v1_)
             xb_, vb_ = torch.zeros_like(px0), torch.zeros_like(px0)
             xb_[:, 0] = -pm / pm.sum()
+            wv_ = None
             for t in range(S - 1, -1, -1):
-                wv_, _, _ = pctx.solve_adjoint(xs_[t + 1], xs_[t], pa[t], xb_, vb_, stats=False)
+                wv_, _, _ = pctx.solve_adjoint(xs_[t + 1], xs_[t], pa[t], xb_, vb_, stats=False, w=wv_, w_init=wv_)
                 out_ = pctx.vjp_params(wv_, xs_[t + 1], xs_[t], pa[t], vb_, want=("a_bar", "x0_bar", "v0_bar"))
                 xb_, vb_ = out_["x0_bar"], out_["v0_bar"]
 
@@ -494,8 +496,9 @@ def spring_leg(args, torch, Context, isb, scenes):
             vs.append(v1)
             st_f.append(sf)
         xb, vb = xbar_T, torch.zeros_like(x0)
+        wv = None
         for t in range(T - 1, -1, -1):
-            wv, sa, _ = ctx.solve_adjoint(xs[t + 1], xs[t], acts[t], xb, vb, stats=stats)
+            wv, sa, _ = ctx.solve_adjoint(xs[t + 1], xs[t], acts[t], xb, vb, stats=stats, w=wv, w_init=wv)
             out = ctx.vjp_params(wv, xs[t + 1], xs[t], acts[t], vb, want=("a_bar", "x0_bar", "v0_bar"))
             xb, vb = out["x0_bar"], out["v0_bar"]
             st_a.append(sa)
@@ -575,8 +578,9 @@ def energy_leg(args, torch, Context, isb, scenes):
                 vs.append(v1)
                 sts.append(sf)
             xb, vb = xbar_T, torch.zeros_like(x0)
+            wv = None
             for t in range(T - 1, -1, -1):
-                wv, _, _ = ctx.solve_adjoint(xs[t + 1], xs[t], acts[t], xb, vb, stats=False)
+                wv, _, _ = ctx.solve_adjoint(xs[t + 1], xs[t], acts[t], xb, vb, stats=False, w=wv, w_init=wv)
                 o = ctx.vjp_params(wv, xs[t + 1], xs[t], acts[t], vb, want=("a_bar", "x0_bar", "v0_bar"))
                 xb, vb = o["x0_bar"], o["v0_bar"]
             return xs, sts
@@ -700,8 +704,9 @@ def tet_leg(args, torch, Context, isb, scenes):
         xb[:, 0] = -m / m.sum()
         vb = torch.zeros_like(x0)
         sa = []
+        wv = None
         for t in range(S - 1, -1, -1):
-            wv, s, _ = ctx.solve_adjoint(xs[t + 1], xs[t], acts[t], xb, vb, stats=stats)
+            wv, s, _ = ctx.solve_adjoint(xs[t + 1], xs[t], acts[t], xb, vb, stats=stats, w=wv, w_init=wv)
             out = ctx.vjp_params(wv, xs[t + 1], xs[t], acts[t], vb, want=("a_bar", "x0_bar", "v0_bar"))
             xb, vb = out["x0_bar"], out["v0_bar"]
             sa.append(s)

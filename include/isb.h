@@ -112,6 +112,12 @@ typedef enum {
                              * converge is solved again from the same inputs in FP64 (its stats then carry
                              * ISB_FLAG_FP64_FALLBACK); needs the host check, so not in graph-safe mode without
                              * stats; 0 = off; 2 = re-solve every body in FP64 (exercises the fallback path) */
+  ISB_OPT_ADJ_WARM_START = 12, /* 1 = isb_solve_adjoint reads w on entry as the starting point of its CG
+                             * (pinned DOFs ignored; e.g. the adjoint of the step after, in a backward pass
+                             * through time, whose solution is close) and solves H d = b - H w for the
+                             * correction, to the same tolerance on the residual of H w = b; 0 (default) =
+                             * w is output only and CG starts from zero. An FP64 re-solve (ISB_OPT_FP64_FALLBACK)
+                             * starts from the first attempt's w */
   ISB_OPT_CG_GRAPH = 10     /* plain solver: 1 = run CG as a graph of 8 iterations, captured once per solve and
                              * replayed until converged (one launch and one host read per 8 iterations);
                              * 0 (default) = one launch per kernel and a read every ISB_OPT_CG_CHECK iterations.
@@ -275,7 +281,8 @@ isb_status isb_step(isb_ctx* ctx, isb_stream stream, const double* x0, const dou
 /* Adjoint solve of Eq. 9: w = H(x1)^-1 (x1_bar + v1_bar / h) over the free DOFs (the v1_bar term
  * only in backward Euler; v1_bar may be NULL), w = 0 on pinned DOFs. H is the unprojected
  * Hessian of the step objective at x1, symmetric and positive definite at a minimiser (Sec. 4),
- * so CG needs no transpose. x1, x0: device [n_v][dim]; a: device [n_e + n_s]; w: device out. */
+ * so CG needs no transpose. x1, x0: device [n_v][dim]; a: device [n_e + n_s]; w: device out (also
+ * the starting point on entry with ISB_OPT_ADJ_WARM_START). */
 isb_status isb_solve_adjoint(isb_ctx* ctx, isb_stream stream, const double* x1, const double* x0,
                              const double* a, const double* x1_bar, const double* v1_bar, double* w,
                              isb_stats* per_body);

@@ -700,8 +700,21 @@ static isb_status plain_adjoint(isb_ctx* c, hipStream_t s, const double* x1, con
       launch_fill(br.n, 0.0, w + br.off, s);
     } else {
       eval_precond(c, b, x1, a, s);
+      if (c->adj_warm) {
+        // start from the caller's w: CG solves H d = b - H w for the correction d, whose residual is
+        // that of H (w + d) = b, so the tolerance stays relative to |b|
+        launch_mask(m, br.v0, br.v1, w, s);
+        launch_copy(br.n, w + br.off, c->w_p + br.off, s);
+        launch_mul(br.n, c->w_vdiag + br.off, c->w_p + br.off, c->w_Hp + br.off, s);
+        elem_scatter(c, b, PATCH_HV, x1, a, c->w_p, c->w_Hp, nullptr, s);
+        launch_mask(m, br.v0, br.v1, c->w_Hp, s);
+        launch_axpy(br.n, c->w_G + br.off, -1.0, c->w_Hp + br.off, s);
+      }
       ISB_TRY(run_cg(c, b, x1, a, c->w_G, 1.0, c->scene.adj_tol_rel * bnorm, c->scene.max_cg, s, &iters, &neg, &rr));
-      launch_copy(br.n, c->w_xs + br.off, w + br.off, s);
+      if (c->adj_warm)
+        launch_axpy(br.n, w + br.off, 1.0, c->w_xs + br.off, s);
+      else
+        launch_copy(br.n, c->w_xs + br.off, w + br.off, s);
     }
     const double rel = bnorm > 0.0 ? std::sqrt(rr) / bnorm : 0.0;
     const bool ok = rel <= c->scene.adj_tol_rel && !neg;
@@ -992,6 +1005,10 @@ isb_status isb_set_option(isb_ctx* c, int key, int64_t value) {
       if (value < 0 || value > 2) return fail(ISB_E_ARG, "fp64 fallback must be 0, 1 or 2");
       c->fp64_fallback = (int)value;
       return ISB_OK;
+    case ISB_OPT_ADJ_WARM_START:
+      if (value != 0 && value != 1) return fail(ISB_E_ARG, "adjoint warm start must be 0 or 1");
+      c->adj_warm = (int)value;
+      return ISB_OK;
     case ISB_OPT_FORWARD:
       if (value != ISB_FORWARD_NEWTON && value != ISB_FORWARD_LBFGS)
         return fail(ISB_E_ARG, "forward must be ISB_FORWARD_NEWTON or ISB_FORWARD_LBFGS");
@@ -1024,6 +1041,7 @@ isb_status isb_get_option(isb_ctx* c, int key, int64_t* value) {
     case ISB_OPT_FORWARD: *value = c->forward; return ISB_OK;
     case ISB_OPT_CG_GRAPH: *value = c->cg_graph; return ISB_OK;
     case ISB_OPT_FP64_FALLBACK: *value = c->fp64_fallback; return ISB_OK;
+    case ISB_OPT_ADJ_WARM_START: *value = c->adj_warm; return ISB_OK;
     case ISB_OPT_LBFGS_MEMORY: *value = c->lbfgs_m; return ISB_OK;
     case ISB_OPT_LBFGS_MAX_ITERS: *value = c->lbfgs_max_iters; return ISB_OK;
     case ISB_INFO_N_VERTICES: *value = c->n_v; return ISB_OK;

@@ -285,6 +285,7 @@ static BatchArgs make_args(isb_ctx* c, BatchedState* st) {
   A.adj_tol = c->scene.adj_tol_rel;
   A.max_newton = c->scene.max_newton;
   A.max_cg = c->scene.max_cg;
+  A.adj_warm = c->adj_warm;
   A.nacc = st->nacc;
   A.Fbuf = st->Fbuf;
   A.E0 = st->E0;

@@ -62,6 +62,7 @@ struct BatchArgs {
   const double *sk, *sil0; // [n_s] stiffness, 1 / rest length
   void* Sbuf;              // [spring_state_words(D)][n_s] spring block K at the iterate, element precision
   int n_s;
+  int adj_warm;            // 1: the adjoint starts its CG from the w it is given (ISB_OPT_ADJ_WARM_START)
 };
 
 // Reduction slots: two banks of up to 16 waves x 4 values. Consecutive workgroup reductions use
@@ -946,7 +947,26 @@ struct BodySolver {
       for (int i = threadIdx.x; i < n; i += blockDim.x) A.w[base + i] = 0.0;
     } else {
       precond(x);
+      if (A.adj_warm) {
+        // start from the given w: CG solves H d = b - H w for the correction d, whose residual is
+        // that of H (w + d) = b, so the tolerance stays relative to |b|; w waits in dx meanwhile
+        for (int i = threadIdx.x; i < n; i += blockDim.x) ps[ld(i)] = pinned(i) ? 0.0 : A.w[base + i];
+        __syncthreads();
+        pass_hv();
+        __syncthreads();
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+          const int g = base + i, li = ld(i);
+          const double wi = ps[li];
+          if (!pinned(i)) A.G[g] -= acc[li] + double(vdp()[g]) * wi;
+          A.dx[g] = wi;
+          acc[li] = 0.0;
+          ps[li] = 0.0;
+        }
+        __syncthreads();
+      }
       rr = cg(A.G, 1.0, A.adj_tol * bnorm, A.max_cg, A.w, it, neg);
+      if (A.adj_warm)
+        for (int i = threadIdx.x; i < n; i += blockDim.x) A.w[base + i] += A.dx[base + i];
     }
     st.adj_cg_iters = it;
     st.adj_res_final = bnorm > 0.0 ? sqrt(rr) / bnorm : 0.0;

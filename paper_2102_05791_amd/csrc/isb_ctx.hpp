@@ -60,6 +60,7 @@ struct isb_ctx {
   int forward = 0, lbfgs_m = 8, lbfgs_max_iters = 20000;  // ISB_OPT_FORWARD and the L-BFGS settings
   int cg_graph = 0;                    // ISB_OPT_CG_GRAPH
   int fp64_fallback = 1;               // ISB_OPT_FP64_FALLBACK
+  int adj_warm = 0;                    // ISB_OPT_ADJ_WARM_START
   hipStream_t cap_stream = nullptr;    // internal stream the CG chunk is captured on
 
   // plain-solver workspaces, [n_v*dim] unless noted

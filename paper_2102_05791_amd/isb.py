@@ -21,7 +21,7 @@ STATUS_NAMES = {0: "ISB_OK", 1: "ISB_E_ARG", 2: "ISB_E_MESH", 3: "ISB_E_HIP", 4:
 ISB_FP64, ISB_MIXED = 0, 1
 ISB_QUASISTATIC, ISB_BACKWARD_EULER = 0, 1
 (OPT_SOLVER, OPT_SCATTER, OPT_GRAPH_SAFE, OPT_BLOCK, OPT_CG_CHECK, OPT_PRECISION, OPT_ENERGY, OPT_FORWARD,
- OPT_LBFGS_MEMORY, OPT_LBFGS_MAX_ITERS, OPT_CG_GRAPH, OPT_FP64_FALLBACK) = range(12)
+ OPT_LBFGS_MEMORY, OPT_LBFGS_MAX_ITERS, OPT_CG_GRAPH, OPT_FP64_FALLBACK, OPT_ADJ_WARM_START) = range(13)
 FLAG_CONVERGED, FLAG_STAGNATED, FLAG_NONFINITE, FLAG_ADJ_CONVERGED, FLAG_FP64_FALLBACK = 1, 2, 4, 8, 16
 FORWARD_NEWTON, FORWARD_LBFGS = 0, 1
 # isotropic element energies (ISB_ENERGY_*), by the names the synthetic workloads use
@@ -381,14 +381,28 @@ class Context:
                                                 _dev(x1, "x1"), _dev(v1, "v1") if be else None, sb), allow)
         return x1, (v1 if be else None), ([s.as_dict() for s in sb] if sb is not None else None), st
 
-    def solve_adjoint(self, x1, x0, a, x1_bar, v1_bar=None, w=None, stats=True, allow_not_converged=False):
-        """isb_solve_adjoint. Returns (w, per-body stats or None, status)."""
+    def solve_adjoint(self, x1, x0, a, x1_bar, v1_bar=None, w=None, stats=True, allow_not_converged=False,
+                      w_init=None):
+        """isb_solve_adjoint. Returns (w, per-body stats or None, status). w_init (device [n_v][dim]):
+        the starting point of the adjoint CG for this call (ISB_OPT_ADJ_WARM_START), e.g. the adjoint
+        of the step after in a backward pass through time; None starts from zero."""
         w = self._empty(self.n_v, self.dim) if w is None else w
         sb = self._stats_buf(stats)
         allow = (ISB_E_NOT_CONVERGED,) if allow_not_converged else ()
-        st = _check(self.lib, self.lib.isb_solve_adjoint(self.h, _stream(), _dev(x1, "x1"), _dev(x0, "x0"),
-                                                         self._a(a), _dev(x1_bar, "x1_bar"),
-                                                         _dev(v1_bar, "v1_bar"), _dev(w, "w"), sb), allow)
+        prev = None
+        if w_init is not None:
+            _dev(w_init, "w_init")
+            if w_init.data_ptr() != w.data_ptr():
+                w.copy_(w_init)
+            prev = self.get_option(OPT_ADJ_WARM_START)
+            self.set_option(OPT_ADJ_WARM_START, 1)
+        try:
+            st = _check(self.lib, self.lib.isb_solve_adjoint(self.h, _stream(), _dev(x1, "x1"), _dev(x0, "x0"),
+                                                             self._a(a), _dev(x1_bar, "x1_bar"),
+                                                             _dev(v1_bar, "v1_bar"), _dev(w, "w"), sb), allow)
+        finally:
+            if prev is not None:
+                self.set_option(OPT_ADJ_WARM_START, prev)
         return w, ([s.as_dict() for s in sb] if sb is not None else None), st
 
     def vjp_params(self, w, x1, x0, a, v1_bar=None, want=("a_bar", "x0_bar", "v0_bar", "mu_bar", "lam_bar",

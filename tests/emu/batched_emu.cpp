@@ -87,7 +87,7 @@ extern "C" int emu_batchargs_offsets(int* out) {
   ISB_EMU_OFF(lconn); ISB_EMU_OFF(stats); ISB_EMU_OFF(tol); ISB_EMU_OFF(adj_tol); ISB_EMU_OFF(max_newton);
   ISB_EMU_OFF(max_cg); ISB_EMU_OFF(want_tail); ISB_EMU_OFF(nacc); ISB_EMU_OFF(Fbuf); ISB_EMU_OFF(E0);
   ISB_EMU_OFF(E1); ISB_EMU_OFF(soff); ISB_EMU_OFF(slconn); ISB_EMU_OFF(sk); ISB_EMU_OFF(sil0);
-  ISB_EMU_OFF(Sbuf); ISB_EMU_OFF(n_s);
+  ISB_EMU_OFF(Sbuf); ISB_EMU_OFF(n_s); ISB_EMU_OFF(adj_warm);
 #undef ISB_EMU_OFF
   return k;
 }

@@ -39,7 +39,8 @@ class BatchArgs(ctypes.Structure):
                 ("vbar", vp), ("w", vp), ("xhat", vp), ("G", vp), ("Gt", vp), ("dx", vp), ("r", vp), ("cv", vp),
                 ("xt", vp), ("Dv", vp), ("vdT", vp), ("lconn", vp), ("stats", vp), ("tol", cd), ("adj_tol", cd),
                 ("max_newton", ci), ("max_cg", ci), ("want_tail", ci), ("nacc", ci), ("Fbuf", vp), ("E0", vp), ("E1", vp),
-                ("soff", vp), ("slconn", vp), ("sk", vp), ("sil0", vp), ("Sbuf", vp), ("n_s", ci)]
+                ("soff", vp), ("slconn", vp), ("sk", vp), ("sil0", vp), ("Sbuf", vp), ("n_s", ci),
+                ("adj_warm", ci)]
 
 
 STATS_DTYPE = np.dtype([("newton_iters", "<i4"), ("cg_iters", "<i4"), ("adj_cg_iters", "<i4"),
@@ -175,13 +176,14 @@ class EmuBatch:
         self.lds_left = self._left.value
         return x1, (v1 if self.be else None), self.stats.copy()
 
-    def adjoint(self, x1, x0, a, xbar, vbar=None, block=128, lds_fill=-12345.0):
+    def adjoint(self, x1, x0, a, xbar, vbar=None, block=128, lds_fill=-12345.0, w_init=None):
+        """w_init: the starting point of the adjoint CG (ISB_OPT_ADJ_WARM_START), else zero."""
         arrs = [np.ascontiguousarray(v, dtype=np.float64) for v in (x1, x0, a, xbar)]
         vb = None if vbar is None else np.ascontiguousarray(vbar, dtype=np.float64)
         a32 = arrs[2].astype(np.float32)
-        wv = np.zeros_like(arrs[0])
+        wv = np.zeros_like(arrs[0]) if w_init is None else np.array(w_init, dtype=np.float64)
         A = self._args(x1=_p(arrs[0]), x0=_p(arrs[1]), a=_p(arrs[2]), a32=_p(a32), xbar=_p(arrs[3]),
-                       vbar=None if vb is None else _p(vb), w=_p(wv))
+                       vbar=None if vb is None else _p(vb), w=_p(wv), adj_warm=int(w_init is not None))
         self.lib.emu_batched(self.w.dim, self.prec, 1, block, ctypes.byref(self.m), ctypes.byref(self.sc),
                              ctypes.byref(A), ctypes.c_double(lds_fill), ctypes.byref(self._left))
         self.lds_left = self._left.value

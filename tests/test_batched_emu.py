@@ -164,3 +164,40 @@ def test_emulated_launch_leaves_lds_accumulators_zero(emu_mod, mode):
     if mode == "adjoint":
         eb.adjoint(x1, w.x0, a, rng.normal(size=x1.shape), rng.normal(size=x1.shape), block=64, lds_fill=0.0)
     assert eb.lds_left == 0.0
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 1e-5)])
+def test_emulated_adjoint_warm_start(emu_mod, precision, tol):
+    """ISB_OPT_ADJ_WARM_START: CG starts from the given w and solves for the correction. In FP64 a
+    restart from the cold solution has nothing left to do; with the FP32 operator the restart sees
+    the true residual b - H w, which at this 1e-13 tolerance lies well above CG's recurrence
+    residual (FP32 rounding of H w), so it only takes fewer iterations than the cold solve. From a
+    perturbed start it reaches the oracle's adjoint (Eq. 9) to the cold start's bar. Springs
+    included, pinned DOFs stay 0."""
+    w, rng = rand_workload(2, seed=24, bodies=3, shape=(6, 2), pinned_left=True)
+    w = _tight(with_springs(w, rng))
+    eb = emu_mod.EmuBatch(w, precision)
+    a = w.actions[0]
+    x1, _, st = eb.step(w.x0, w.v0, a, block=64)
+    assert np.all(st["flags"] & 1)
+    xbar = rng.normal(size=x1.shape)
+    vbar = rng.normal(size=x1.shape)
+    w_cold, st_c = eb.adjoint(x1, w.x0, a, xbar, vbar, block=64)
+    w_same, st_s = eb.adjoint(x1, w.x0, a, xbar, vbar, block=64, w_init=w_cold)
+    assert np.all(st_s["flags"] & 8)
+    if precision == "fp64":
+        assert np.all(st_s["adj_cg_iters"] == 0) and np.all(st_c["adj_cg_iters"] > 5)
+    else:
+        assert np.all(st_s["adj_cg_iters"] < st_c["adj_cg_iters"])
+    assert rel(w_same, w_cold) <= tol
+    start = w_cold + 0.1 * np.abs(w_cold).max() * rng.normal(size=w_cold.shape)
+    w_warm, st_w = eb.adjoint(x1, w.x0, a, xbar, vbar, block=64, w_init=start)
+    assert np.all(st_w["flags"] & 8)
+    pin = w.pinned.astype(bool)
+    assert np.all(w_warm[pin] == 0.0)
+    for b in range(w.n_bodies):
+        wb = w.body(b)
+        p = Problem.from_workload(wb)
+        sv = slice(w.body_v_off[b], w.body_v_off[b + 1])
+        wr = solve.adjoint(p, x1[sv], w.x0[sv], wb.actions[0], xbar[sv], vbar[sv])
+        assert rel(w_warm[sv], wr) <= tol
