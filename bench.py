@@ -152,14 +152,18 @@ def step_launch_bytes(dim, ne, nv, st, word_hv, ns=0):
             + st["cg_iters"] * (cg_iter_bytes(dim, ne, nv, word_hv) + ns * spring_hv_bytes(dim, word_hv)))
 
 
-def adjoint_launch_bytes(dim, ne, nv, st, word_hv, ns=0):
+def adjoint_launch_bytes(dim, ne, nv, st, word_hv, ns=0, warm=False):
     """Right-hand side (xbar, vbar, pinned -> G; c_v), the FP64 diagonal pass that also stores the
-    Hessian-vector state, the CG start and the CG iterations."""
+    Hessian-vector state, the warm start (one Hessian-vector pass over the given w; w read, G read
+    and written, the vertex diagonal read, w parked and added back), the CG start and the CG
+    iterations."""
     dof = nv * dim
     rhs = 25 * dof + 16 * nv
     diag = ((elem_bytes(dim, 8) - 2 * (dim + 1) + hv_state_bytes(dim, word_hv)) * ne + (9 + 4 + word_hv) * dof
             + 16 * nv + ns * (spring_trial_bytes(dim, word_hv) - 16))
-    return (rhs + diag + (36 + 4 + word_hv) * dof
+    start = (hv_elem_bytes(dim, word_hv) * ne + ns * spring_hv_bytes(dim, word_hv)
+             + (8 + 16 + word_hv + 8 + 24) * dof) if warm else 0
+    return (rhs + diag + start + (36 + 4 + word_hv) * dof
             + st["adj_cg_iters"] * (cg_iter_bytes(dim, ne, nv, word_hv) + ns * spring_hv_bytes(dim, word_hv)))
 
 
@@ -271,7 +275,9 @@ def main():
     print("# statistics pass done", file=sys.stderr, flush=True)
     ne_b, nv_b = np.diff(w.body_e_off), np.diff(w.body_v_off)
     fb = [sum(step_launch_bytes(2, ne_b[b], nv_b[b], s[b], 4) for b in range(nb)) for s in st_f]
-    ab = [sum(adjoint_launch_bytes(2, ne_b[b], nv_b[b], s[b], 4) for b in range(nb)) for s in st_a]
+    # st_a runs backward in time: the first adjoint starts from zero, every later one from the last w
+    ab = [sum(adjoint_launch_bytes(2, ne_b[b], nv_b[b], s[b], 4, warm=k > 0) for b in range(nb))
+          for k, s in enumerate(st_a)]
     it = {"newton_per_step": float(np.mean([[s["newton_iters"] for s in S] for S in st_f])),
           "cg_per_step": float(np.mean([[s["cg_iters"] for s in S] for S in st_f])),
           "adj_cg_per_step": float(np.mean([[s["adj_cg_iters"] for s in S] for S in st_a])),
