@@ -1,0 +1,49 @@
+"""CPU checks of bench.py's contract pieces: it refuses more than one GPU, its algorithmic byte
+model gives the per-element figures the roofline is quoted with, and measured traffic is only
+reported for the library sources it was taken on."""
+import json
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_element_byte_model():
+    # 3D element Hessian-vector product: connectivity 16 B, Dm^-1 (9), gf (3), W mu, W lam, W k_f,
+    # actuation: 144 B in FP64; 80 + the FP64 actuation's extra 4 B = 84 B mixed
+    assert bench.elem_bytes(3, 8) == 144
+    assert bench.elem_bytes(3, 4) + 4 == 84
+    assert bench.elem_bytes(2, 8) == 4 * 3 + 8 * (4 + 2 + 3 + 1)
+    # batched triangles: 16-bit body-local connectivity and the 10-word edge Hessian
+    assert bench.hv_elem_bytes(2, 4) == 2 * 3 + 40
+
+
+def test_adjoint_warm_start_adds_one_hessian_vector_pass():
+    st = {"adj_cg_iters": 40}
+    ne, nv = 1000, 550
+    cold = bench.adjoint_launch_bytes(2, ne, nv, st, 4)
+    warm = bench.adjoint_launch_bytes(2, ne, nv, st, 4, warm=True)
+    assert warm - cold == bench.hv_elem_bytes(2, 4) * ne + (8 + 16 + 4 + 8 + 24) * nv * 2
+    one_more = bench.adjoint_launch_bytes(2, ne, nv, {"adj_cg_iters": 41}, 4)
+    assert cold < warm < one_more + (8 + 16 + 4 + 8 + 24) * nv * 2
+
+
+def test_traffic_record_is_ignored_for_other_sources(tmp_path, monkeypatch):
+    rec = {"source_hash": bench.kernel_source_hash(), "bytes_per_launch": {"0": 123, "1": 45}}
+    f = tmp_path / "counters.md"
+    f.write_text("# counters\n\ntraffic-record: " + json.dumps(rec) + "\n")
+    monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(f))
+    assert bench.measured_traffic(0) == 123 and bench.measured_traffic(1) == 45
+    rec["source_hash"] = "0" * 64
+    f.write_text("traffic-record: " + json.dumps(rec) + "\n")
+    assert bench.measured_traffic(0) is None
