@@ -20,7 +20,7 @@ def _dev(a):
 
 
 @pytest.mark.parametrize("precision,tol,order", [("fp64", 1e-9, "given"), ("mixed", 1e-5, "given"),
-                                               ("mixed", 1e-5, "wave")])
+                                               ("fp64", 1e-9, "wave"), ("mixed", 1e-5, "wave")])
 def test_tet_block_step_and_adjoint_vs_oracle_samples(precision, tol, order):
     """order "wave": the elements permuted by isb_wave_order (as the benchmark runs the block); the
     sampled element outputs are read back at each element's new position."""
