@@ -77,7 +77,9 @@ class CheckpointedRollout(torch.autograd.Function):
         vb = vT_bar.contiguous() if vT_bar is not None else None
         if xb is None:
             xb = torch.zeros_like(cps[0][0])
-        w = None  # each adjoint CG starts from the one of the step after (ISB_OPT_ADJ_WARM_START)
+        # each adjoint CG starts from the one of the step after (ISB_OPT_ADJ_WARM_START), in place:
+        # that adjoint is no longer needed once its VJP is taken
+        w = None
         for seg in range((T - 1) // K, -1, -1):
             t0, t1 = seg * K, min(seg * K + K, T)
             states = [cps[seg]]
@@ -87,7 +89,7 @@ class CheckpointedRollout(torch.autograd.Function):
             for t in range(t1 - 1, t0 - 1, -1):
                 x_prev, x_next = states[t - t0][0], states[t - t0 + 1][0]
                 a_t = actions[t].contiguous()
-                w, _, _ = ctx.solve_adjoint(x_next, x_prev, a_t, xb, vb, stats=False, w_init=w)
+                w, _, _ = ctx.solve_adjoint(x_next, x_prev, a_t, xb, vb, stats=False, w=w, w_init=w)
                 out = ctx.vjp_params(w, x_next, x_prev, a_t, vb, want=("a_bar", "x0_bar", "v0_bar"))
                 a_bar[t] = out["a_bar"]
                 xb, vb = out["x0_bar"], out["v0_bar"]
