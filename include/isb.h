@@ -153,6 +153,9 @@ typedef struct {
 #define ISB_FLAG_NONFINITE 4
 #define ISB_FLAG_ADJ_CONVERGED 8
 #define ISB_FLAG_FP64_FALLBACK 16 /* the mixed solve did not converge; these stats are the FP64 re-solve's */
+#define ISB_FLAG_INVALID_ACTION 32 /* batched solver: an action of the body was <= 0 or non-finite (non-finite
+                                    * also sets ISB_FLAG_NONFINITE); the body was not solved: x1 = x_init,
+                                    * v1 = (x1 - x0) / h, or w = 0 for the adjoint */
 
 /* Scene constants (one set for every body of the context). */
 typedef struct {
@@ -171,7 +174,8 @@ typedef struct {
 
 /* ---- lifetime ---------------------------------------------------------------------------- */
 
-/* Create a context on HIP device `device` computing in `precision` (ISB_FP64: every element
+/* Create a context on HIP device `device` computing in `precision`: the holder of one simulated
+ * system, whose state transition s1 = sim(s0, a0) (Sec. 5, Eq. 12) isb_step evaluates (ISB_FP64: every element
  * kernel in FP64; ISB_MIXED: Hessian-vector products in FP32 element arithmetic, while
  * gradients, energies, the preconditioner diagonal, CG vectors, dot products, norms and the
  * state stay FP64). The boundary is FP64 in both modes. */
@@ -222,7 +226,9 @@ isb_status isb_wave_order(int dim, int64_t n_v, int64_t n_e, const int32_t* T, i
 
 /* ---- upload ------------------------------------------------------------------------------- */
 
-/* Copy a mesh of n_bodies independent bodies to the device and precompute Dm^-1 and W per element.
+/* Copy a mesh of n_bodies independent bodies to the device and precompute Dm^-1 and W per element:
+ * F = Ds Dm^-1 is linear in the vertex positions (Sec. 3, beside Eq. 3) and W = det(Dm) / dim! is the
+ * rest volume that scales each element's energy; the positions are the n x dim tensor of Sec. 4.1.
  * body_v_off / body_e_off host [n_bodies+1]; X_rest host [n_v][dim]; T host [n_e][dim+1]
  * (positively oriented); dof_pinned host [n_v][dim], 1 = Dirichlet. Validates first (ISB_E_MESH).
  * Replaces any previous mesh (the material must then be uploaded again). */
@@ -274,7 +280,10 @@ isb_status isb_autotune(isb_ctx* ctx, isb_stream stream, const double* x0, const
  * may be NULL in quasistatic mode); a: device [n_e + n_s], actuation of Eq. 2 (1 = relaxed, < 1
  * contracts; must be > 0); x1, v1: device out [n_v][dim] (v1 may be NULL; it is not written in
  * quasistatic mode). per_body: host [n_bodies] stats or NULL. Returns ISB_E_NOT_CONVERGED if
- * any body hit max_newton (x1, v1 then hold the last iterate), ISB_E_NONFINITE on NaN/Inf. */
+ * any body hit max_newton (x1, v1 then hold the last iterate), ISB_E_NONFINITE on NaN/Inf, ISB_E_ARG
+ * if an action is <= 0. The batched solver checks the actions on the device, per body
+ * (ISB_FLAG_INVALID_ACTION), and reports them with the other per-body failures when the call reads its
+ * stats back; a graph-safe call without stats reports no per-body failure. */
 isb_status isb_step(isb_ctx* ctx, isb_stream stream, const double* x0, const double* v0,
                     const double* a, double* x1, double* v1, isb_stats* per_body);
 

@@ -27,6 +27,8 @@ class ImplicitStep(torch.autograd.Function):
             v1 = torch.zeros_like(x1)
         fctx.ctx = ctx
         fctx.with_material = mu is not None
+        # the material this step ran with: the context may hold another one by the time backward runs
+        fctx.material = (mu.detach().clone(), lam.detach().clone(), kf.detach().clone()) if mu is not None else None
         fctx.save_for_backward(x0, a, x1)
         return x1, v1
 
@@ -34,6 +36,8 @@ class ImplicitStep(torch.autograd.Function):
     def backward(fctx, x1_bar, v1_bar):
         ctx = fctx.ctx
         x0, a, x1 = fctx.saved_tensors
+        if fctx.material is not None:
+            ctx.set_material_params(*fctx.material)   # a no-op when the context still holds it
         x1_bar = torch.zeros_like(x1) if x1_bar is None else x1_bar.contiguous()
         v1_bar = None if v1_bar is None else v1_bar.contiguous()
         w, _, _ = ctx.solve_adjoint(x1, x0, a, x1_bar, v1_bar, stats=False)

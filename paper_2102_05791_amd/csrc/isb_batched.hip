@@ -351,6 +351,7 @@ static isb_status fp64_fallback(isb_ctx* c, BatchedState* st, hipStream_t s, int
 }
 
 static bool body_failed(const DevStats& d, int mode) {
+  if (d.flags & ISB_FLAG_INVALID_ACTION) return false;  // an input error: a re-solve cannot help
   if (d.flags & ISB_FLAG_NONFINITE) return true;
   return mode == 0 ? !(d.flags & ISB_FLAG_CONVERGED) : !(d.flags & ISB_FLAG_ADJ_CONVERGED);
 }
@@ -374,6 +375,8 @@ static isb_status collect(isb_ctx* c, BatchedState* st, hipStream_t s, isb_stats
     const DevStats& d = st->hstats[b];
     if (d.flags & ISB_FLAG_NONFINITE)
       return fail(ISB_E_NONFINITE, "body " + std::to_string(b) + ": non-finite value in the solve");
+    if (d.flags & ISB_FLAG_INVALID_ACTION)
+      return fail(ISB_E_ARG, "body " + std::to_string(b) + ": actuation a must be > 0");
     if (mode == 0 && !(d.flags & (ISB_FLAG_CONVERGED | ISB_FLAG_STAGNATED)))
       return fail(ISB_E_NOT_CONVERGED, "body " + std::to_string(b) + ": Newton iteration cap reached");
     if (mode == 1 && !(d.flags & ISB_FLAG_ADJ_CONVERGED))

@@ -773,6 +773,28 @@ struct BodySolver {
     return rr;
   }
 
+  // ISB_FLAG_INVALID_ACTION when an action of the body's elements or springs is <= 0 or not finite
+  // (with ISB_FLAG_NONFINITE for the latter), else 0; every thread receives the same value
+  __device__ int check_actions() {
+    double t[2] = {0.0, 0.0};  // actions <= 0, non-finite actions
+    for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+      const double ae = A.a[e];
+      if (!isfinite(ae))
+        t[1] += 1.0;
+      else if (!(ae > 0.0))
+        t[0] += 1.0;
+    }
+    for (int s = s0 + threadIdx.x; s < s1; s += blockDim.x) {
+      const double as = A.a[m.n_e + s];
+      if (!isfinite(as))
+        t[1] += 1.0;
+      else if (!(as > 0.0))
+        t[0] += 1.0;
+    }
+    sum<2>(t);
+    return (t[0] > 0.0 || t[1] > 0.0 ? ISB_FLAG_INVALID_ACTION : 0) | (t[1] > 0.0 ? ISB_FLAG_NONFINITE : 0);
+  }
+
   // -------- the forward step of one body --------
   // per-DOF loops outside CG take kC owned DOFs per thread at a time, all loads first (indices
   // past the body clamped to its last DOF)
@@ -803,7 +825,14 @@ struct BodySolver {
     }
     for (int vl = threadIdx.x; vl < v1 - v0; vl += blockDim.x)
       A.cv[v0 + vl] = fmax(-A.x0[(size_t)(v0 + vl) * D + 1] + sc.eps, 0.0);
-    __syncthreads();
+    // invalid actions: no solve; x1 keeps x_init (each thread rereads the DOFs it wrote above)
+    if (const int bad = check_actions()) {
+      st.flags |= bad;
+      if (sc.be && A.v1)
+        for (int i = threadIdx.x; i < n; i += B) A.v1[base + i] = (x[base + i] - A.x0[base + i]) / sc.h;
+      __syncthreads();
+      return;
+    }
     double* G = A.G;
     double* Gt = A.Gt;
     double* dx = A.dx;
@@ -937,6 +966,12 @@ struct BodySolver {
       bb += rhs * rhs;
     }
     bb = sum1(bb);  // its barriers also publish cv
+    if (const int bad = check_actions()) {
+      st.flags |= bad;
+      for (int i = threadIdx.x; i < n; i += blockDim.x) A.w[base + i] = 0.0;
+      __syncthreads();
+      return;
+    }
     const double bnorm = sqrt(bb);
     int it = 0;
     bool neg = false;
@@ -1013,9 +1048,10 @@ __device__ void batched_body(const DevMesh& m, const DevScene& sc, const BatchAr
         o.adj_res_final = ares;
         o.flags |= aflag;
       } else {
+        // the step's outcome stays; every other flag is this adjoint's own
         o.adj_cg_iters = st.adj_cg_iters;
         o.adj_res_final = st.adj_res_final;
-        o.flags = (o.flags & ~ISB_FLAG_ADJ_CONVERGED) | st.flags;
+        o.flags = (o.flags & (ISB_FLAG_CONVERGED | ISB_FLAG_STAGNATED | ISB_FLAG_FP64_FALLBACK)) | st.flags;
       }
     }
   }

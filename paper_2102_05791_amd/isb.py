@@ -23,6 +23,7 @@ ISB_QUASISTATIC, ISB_BACKWARD_EULER = 0, 1
 (OPT_SOLVER, OPT_SCATTER, OPT_GRAPH_SAFE, OPT_BLOCK, OPT_CG_CHECK, OPT_PRECISION, OPT_ENERGY, OPT_FORWARD,
  OPT_LBFGS_MEMORY, OPT_LBFGS_MAX_ITERS, OPT_CG_GRAPH, OPT_FP64_FALLBACK, OPT_ADJ_WARM_START) = range(13)
 FLAG_CONVERGED, FLAG_STAGNATED, FLAG_NONFINITE, FLAG_ADJ_CONVERGED, FLAG_FP64_FALLBACK = 1, 2, 4, 8, 16
+FLAG_INVALID_ACTION = 32
 FORWARD_NEWTON, FORWARD_LBFGS = 0, 1
 # isotropic element energies (ISB_ENERGY_*), by the names the synthetic workloads use
 ENERGY = {"nh": 0, "stvk": 1, "corot": 2, "snh": 3}
@@ -75,12 +76,12 @@ _lib = None
 
 
 def load_library(path: str | None = None) -> ctypes.CDLL:
-    """Load libisb.so; raises ImportError when it has not been built (no fallback exists)."""
+    """Load the in-tree libisb.so (or the build at `path`, which is not cached); raises ImportError
+    when it has not been built (no fallback exists)."""
     global _lib
     if _lib is not None and path is None:
         return _lib
-    # ISB_LIBRARY names another build of the same library (e.g. to compare two builds)
-    p = path or os.environ.get("ISB_LIBRARY") or LIB_PATH
+    p = path or LIB_PATH
     # torch ships its own HIP runtime under the same soname; loading torch first makes the library
     # bind to that one copy, so that both share one runtime, one device context and its streams
     import torch  # noqa: F401

@@ -93,3 +93,13 @@ def rel(a, b, scale=None):
     b = np.asarray(b, dtype=np.float64)
     den = np.linalg.norm(b if scale is None else scale)
     return float(np.linalg.norm(a - b) / den) if den > 0 else float(np.linalg.norm(a - b))
+
+
+def rel_inf(a, b, scale=None):
+    """max |a - b| over max |b| (or over max |scale|): the worst entry, which a 2-norm measure can
+    hide when a handful of entries (a ragged tail, a patch boundary) are wrong."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    den = np.max(np.abs(b if scale is None else scale)) if b.size else 0.0
+    num = np.max(np.abs(a - b)) if a.size else 0.0
+    return float(num / den) if den > 0 else float(num)

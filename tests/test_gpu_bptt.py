@@ -91,12 +91,85 @@ def _replicate(w, actions_per_body):
                     dict(w.scene), tile(w.x0), tile(w.v0), acts, vo, eo)
 
 
-def test_bptt_strip_100_steps_checkpointed_vs_oracle_and_fd():
+@pytest.fixture(scope="module")
+def strip_oracle():
+    """The oracle's 100-step rollout of the 64x16 strip (every state stored) and its BPTT gradient
+    of L = -COM_x(x_100) with respect to all 204,800 actuations."""
+    w = _tight(scenes.be_strip())
+    p = Problem.from_workload(w)
+    states, _ = solve.rollout(p, w.x0, w.v0, w.actions, tol=1e-13)
+    L_ref = solve.com_x_loss(p, states[-1][0])
+    g_ref, _, _ = solve.rollout_grad(p, states, w.actions, solve.com_x_loss_grad(p, states[-1][0]))
+    return w, states, L_ref, g_ref
+
+
+def test_implicit_step_two_materials_then_one_backward():
+    """Two differentiable steps run with different Lame pairs and fibre stiffnesses before one
+    backward pass: each step's adjoint (Eq. 9) and cotangents use the material that step ran with,
+    not the one the context holds when the backward runs."""
+    import torch
+    from paper_2102_05791_amd import Context
+    from paper_2102_05791_amd.autograd import implicit_step
+    w = _tight(scenes.be_strip(nx=12, ny=4, steps=2))
+    ctx = Context.from_workload(w, precision="fp64", solver=0)
+    mats = [(w.mu, w.lam, w.kf), (1.3 * w.mu, 0.8 * w.lam, 0.7 * w.kf)]
+    leaves = [tuple(_dev(v, requires_grad=True) for v in m) for m in mats]
+    x, v = _dev(w.x0, requires_grad=True), _dev(w.v0)
+    acts = [_dev(w.actions[t], requires_grad=True) for t in range(2)]
+    x1, v1 = implicit_step(ctx, x, v, acts[0], *leaves[0])
+    x2, v2 = implicit_step(ctx, x1, v1, acts[1], *leaves[1])
+    c = np.random.default_rng(6).normal(size=w.x0.shape)
+    ((x2 * _dev(c)).sum()).backward()
+    # the oracle: step 1 with material 0, step 2 with material 1, then the two adjoints backwards
+    probs = [Problem.from_workload(Workload(w.name, 2, w.X, w.T, w.pinned, mu, lam, kf, w.fdir, w.rho, w.scene,
+                                            w.x0, w.v0, w.actions)) for mu, lam, kf in mats]
+    xa, va, _ = solve.step(probs[0], w.x0, w.v0, w.actions[0], tol=1e-13)
+    xb, vb, _ = solve.step(probs[1], xa, va, w.actions[1], tol=1e-13)
+    w2 = solve.adjoint(probs[1], xb, xa, w.actions[1], c)
+    r2 = solve.vjp_params(probs[1], w2, xb, xa, w.actions[1])
+    w1 = solve.adjoint(probs[0], xa, w.x0, w.actions[0], r2["x0_bar"], r2["v0_bar"])
+    r1 = solve.vjp_params(probs[0], w1, xa, w.x0, w.actions[0], v1_bar=r2["v0_bar"])
+    for (mu, lam, kf), ref in zip(leaves, (r1, r2)):
+        for got, key in ((mu.grad, "mu_bar"), (lam.grad, "lam_bar"), (kf.grad, "kf_bar")):
+            err = np.linalg.norm(got.cpu().numpy() - ref[key]) / np.linalg.norm(ref[key])
+            print(key, err)
+            assert err <= 1e-9, key
+    for got, ref in ((acts[0].grad, r1["a_bar"]), (acts[1].grad, r2["a_bar"]), (x.grad, r1["x0_bar"])):
+        assert np.linalg.norm(got.cpu().numpy() - ref) <= 1e-9 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("solver", [0, 1], ids=["plain", "batched"])
+def test_strip_100_steps_mixed_vs_oracle(strip_oracle, solver):
+    """The 64x16 strip over its full 100 backward-Euler steps (Eq. 14 with contact and friction,
+    Eq. 15-17) in mixed precision: x_100 and v_100 against the oracle's rollout, and the checkpointed
+    BPTT gradient of -COM_x(x_100) with respect to all 204,800 actuations against the oracle's, at
+    the mixed bar (both solved tight; the mixed adjoints solve with the FP32 operator)."""
+    import torch
+    from paper_2102_05791_amd import Context
+    from paper_2102_05791_amd.autograd import rollout
+    w, states, L_ref, g_ref = strip_oracle
+    ctx = Context.from_workload(w, precision="mixed", solver=solver)
+    acts = _dev(w.actions, requires_grad=True)
+    xT, vT = rollout(ctx, _dev(w.x0), _dev(w.v0), acts, checkpoint_every=10)
+    xr, vr = states[-1]
+    ex = np.linalg.norm(xT.detach().cpu().numpy() - xr) / np.linalg.norm(xr - w.x0)
+    ev = np.linalg.norm(vT.detach().cpu().numpy() - vr) / np.linalg.norm(vr)
+    L = _com_loss(torch, ctx.mass(), xT)
+    L.backward()
+    g = acts.grad.cpu().numpy()
+    eg = np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref)
+    egi = np.max(np.abs(g - g_ref)) / np.max(np.abs(g_ref))
+    print(f"mixed {solver}: x_100 err {ex:.2e} v_100 err {ev:.2e} grad err {eg:.2e} (worst entry {egi:.2e})")
+    assert ex <= 1e-5 and ev <= 1e-5
+    assert eg <= 1e-5 and egi <= 1e-5
+
+
+def test_bptt_strip_100_steps_checkpointed_vs_oracle_and_fd(strip_oracle):
     """The 64x16 strip, 100 steps, L = -COM_x(x_100), gradient w.r.t. all 204,800 actuations."""
     import torch
     from paper_2102_05791_amd import Context
     from paper_2102_05791_amd.autograd import rollout
-    w = _tight(scenes.be_strip())
+    w, states, L_ref, g_ref = strip_oracle
     n_e, T = w.n_e, w.actions.shape[0]
     # AD: checkpointed rollout (every 10 steps) through the batched FP64 solver
     ctx = Context.from_workload(w, precision="fp64", solver=1)
@@ -107,11 +180,7 @@ def test_bptt_strip_100_steps_checkpointed_vs_oracle_and_fd():
     L.backward()
     g = acts.grad.cpu().numpy()
     Lv = float(L.detach())
-    # oracle BPTT storing every state
-    p = Problem.from_workload(w)
-    states, _ = solve.rollout(p, w.x0, w.v0, w.actions, tol=1e-13)
-    L_ref = solve.com_x_loss(p, states[-1][0])
-    g_ref, _, _ = solve.rollout_grad(p, states, w.actions, solve.com_x_loss_grad(p, states[-1][0]))
+    # against the oracle's BPTT, which stores every state
     gerr = np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref)
     print("loss", Lv, L_ref, "grad rel err vs oracle", gerr, "|g|", np.linalg.norm(g_ref))
     assert abs(Lv - L_ref) <= 1e-10 * abs(L_ref)

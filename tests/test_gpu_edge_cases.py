@@ -1,0 +1,181 @@
+"""GPU parity at the method's edge cases, through the C ABI against the FP64 oracle:
+
+* single evaluations (gradient, Hessian-vector product, Hessian diagonal) at states with inverted
+  elements (J <= 0, where Sec. 3 replaces log J by its quadratic expansion so the energy stays
+  finite) and at J = 2, where that expansion's slope l'(J) = 2 - J vanishes, for every energy model;
+* a quasistatic solve from a strongly compressed state, whose Hessian has negative curvature (the
+  CG must stop early, Nocedal & Wright Alg. 7.1, and Newton still reaches the oracle's minimiser);
+* the corotated model's closest rotation at inverted F (the GPU's Horn quaternion / 2D angle against
+  the oracle's sign-corrected SVD), in single evaluations and in backward-Euler steps from an
+  inverted start, in both solvers."""
+import numpy as np
+import pytest
+
+from oracle import solve
+from oracle.fem import Problem
+from synth import meshes, scenes
+from synth.scenes import Workload
+from tests.gpu_util import abs_assembly, problems, rand_workload, rel, rel_inf
+
+pytestmark = pytest.mark.gpu
+
+MODELS = ["nh", "stvk", "corot", "snh"]
+
+
+def _dev(a):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda:0")
+
+
+def _ctx(w, precision="fp64", scatter=0, solver=0):
+    from paper_2102_05791_amd import Context
+    return Context.from_workload(w, precision=precision, scatter=scatter, solver=solver)
+
+
+def _inverted_state(w, rng, frac=0.25):
+    """x0 plus noise, then a quarter of the vertices pushed about one grid spacing through their
+    neighbours: 7-13% of the elements end up with J <= 0 (J from about -13 to 14)."""
+    x = w.x0 + 0.05 * rng.normal(size=w.x0.shape)
+    pick = rng.random(w.n_v) < frac
+    x[pick] += 0.7 * rng.normal(size=(int(pick.sum()), w.dim))
+    return x
+
+
+def _expanded_state(w, rng, J=2.0):
+    """Every element stretched to volume ratio J (uniform scaling of the rest shape), plus a small
+    perturbation so that J scatters around that value."""
+    x = w.X * J ** (1.0 / w.dim)
+    return x + 1e-3 * rng.normal(size=x.shape)
+
+
+def _jacobians(p, x):
+    from oracle import fem
+    return fem.det(p.mesh.F(x))
+
+
+@pytest.mark.parametrize("model", MODELS)
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("state", ["inverted", "J2"])
+@pytest.mark.parametrize("scatter", [0, 2], ids=["atomic", "patch"])
+def test_single_evaluations_at_inverted_and_J2_states(model, dim, state, scatter):
+    shape = (40, 13) if dim == 2 else (6, 5, 4)
+    if scatter == 2:   # bodies of >= 16,384 elements take the LDS-staged patches
+        shape = (130, 65) if dim == 2 else (16, 16, 11)
+    w, rng = rand_workload(dim, seed=81, shape=shape)
+    w.model = model
+    p = problems(w)[0]
+    x = _inverted_state(w, rng) if state == "inverted" else _expanded_state(w, rng)
+    J = _jacobians(p, x)
+    if state == "inverted":
+        assert (J <= 0).sum() >= 0.05 * J.size, (J <= 0).mean()
+    else:
+        assert np.all(np.abs(J - 2.0) < 0.05), (J.min(), J.max())
+    a = w.actions[0]
+    ctx = _ctx(w, scatter=scatter)
+    print(f"{model} dim{dim} {state}: J in [{J.min():.3f}, {J.max():.3f}], {int((J <= 0).sum())} inverted")
+    G = ctx.gradient(_dev(x), _dev(w.x0), _dev(w.v0), _dev(a)).cpu().numpy()
+    scale = abs_assembly(p, x, w.x0, w.v0, a)
+    Gref = p.grad(x, w.x0, w.v0, a)
+    assert rel(G, Gref, scale) <= 1e-12
+    assert np.all(np.isfinite(G))
+    pv = rng.normal(size=x.shape)
+    H = p.hessian(x, w.x0, a)
+    Hp = ctx.hessvec(_dev(x), _dev(w.x0), _dev(a), _dev(pv)).cpu().numpy()
+    assert rel(Hp.ravel(), H @ pv.ravel(), abs(H) @ np.abs(pv.ravel())) <= 1e-12
+    Hd = ctx.hessdiag(_dev(x), _dev(w.x0), _dev(a)).cpu().numpy()
+    free = ~w.pinned.ravel().astype(bool)
+    assert rel(Hd.ravel()[free], H.diagonal()[free], abs(H).diagonal()[free]) <= 1e-12
+    E = ctx.energy(_dev(x), _dev(w.x0), _dev(w.v0), _dev(a)).cpu().numpy()
+    ee, ev = p.energy_terms(x, w.x0, w.v0, a)
+    assert np.isfinite(E[0])
+    assert abs(E[0] - (ee.sum() + ev.sum())) <= 1e-13 * (np.abs(ee).sum() + np.abs(ev).sum())
+
+
+def _compressed_cantilever():
+    """The 10x4 quasistatic cantilever (left column pinned at rest) without gravity and with relaxed
+    fibres (a = 1), so that its minimiser is the rest shape X exactly, started from the free vertices
+    squeezed to 45% along x and 55% along y (J = 0.2475 in the interior): along an element's
+    infinitesimal rotations the Hessian is then mu + (lam l - mu) l' < 0, with l = l(0.2475)."""
+    w = scenes.qs_cantilever()
+    x0 = w.X * np.array([0.45, 0.55])
+    pin = w.pinned.any(axis=1)
+    x0[pin] = w.X[pin]
+    w.scene.update(gravity=0.0, tol_rel=1e-13, adj_tol_rel=1e-13, max_newton=80, max_cg=4000)
+    acts = np.ones_like(w.actions)
+    return Workload("compressed_cantilever", 2, w.X, w.T, w.pinned, w.mu, w.lam, w.kf, w.fdir, w.rho, w.scene,
+                    x0, np.zeros_like(x0), acts)
+
+
+@pytest.mark.parametrize("solver", [0, 1], ids=["plain", "batched"])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 1e-5)])
+def test_negative_curvature_exits_and_minimiser(solver, precision, tol):
+    w = _compressed_cantilever()
+    p = problems(w)[0]
+    a = w.actions[0]
+    H0 = p.hessian(w.x0, w.x0, a).toarray()
+    free = ~w.pinned.ravel().astype(bool)
+    assert np.linalg.eigvalsh(H0[np.ix_(free, free)])[0] < 0    # indefinite at the start
+    xr, _, sr = solve.step(p, w.x0, None, a, tol=1e-13)
+    ctx = _ctx(w, precision=precision, solver=solver)
+    x1, _, st, _ = ctx.step(_dev(w.x0), None, _dev(a))
+    print("oracle", sr, "gpu", st[0])
+    assert st[0]["negcurv_exits"] > 0
+    assert st[0]["flags"] & 1 or st[0]["flags"] & 2
+    x1 = x1.cpu().numpy()
+    Hf = p.hessian(xr, w.x0, a).toarray()
+    assert np.linalg.eigvalsh(Hf[np.ix_(free, free)])[0] > 0      # the oracle's end point is a minimum
+    assert rel(x1 - w.x0, xr - w.x0) <= tol
+    assert rel_inf(x1 - w.x0, xr - w.x0) <= tol
+    assert rel(xr - w.x0, w.X - w.x0) <= 1e-10       # the oracle found the rest shape
+
+
+def _corotated_from_inverted(dim, seed):
+    shape = (8, 3) if dim == 2 else (3, 3, 2)
+    w, rng = rand_workload(dim, seed=seed, bodies=2, shape=shape)
+    w.model = "corot"
+    x0 = w.X + 0.02 * rng.normal(size=w.X.shape)
+    # invert a few elements: move single interior vertices across an opposite edge
+    p = problems(w)[0]
+    J = _jacobians(p, x0[: w.body_v_off[1]])
+    tries = 0
+    while (J <= 0).sum() < 2 and tries < 50:
+        v = rng.integers(0, w.body_v_off[1])
+        x0[v] += 0.7 * rng.normal(size=dim)
+        J = _jacobians(p, x0[: w.body_v_off[1]])
+        tries += 1
+    x0[:, 1] += 0.05 - x0[:, 1].min()        # above the ground: contact stays out of it
+    w.x0 = x0
+    w.v0 = np.zeros_like(x0)
+    w.scene.update(tol_rel=1e-13, adj_tol_rel=1e-13, max_newton=80, max_cg=4000)
+    return w, rng, int((J <= 0).sum())
+
+
+@pytest.mark.parametrize("solver", [0, 1], ids=["plain", "batched"])
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 1e-5)])
+def test_corotated_step_and_adjoint_from_inverted_start(solver, dim, precision, tol):
+    w, rng, n_inv = _corotated_from_inverted(dim, 82)
+    assert n_inv >= 2
+    a = w.actions[0]
+    ctx = _ctx(w, precision=precision, solver=solver)
+    x1, v1, st, _ = ctx.step(_dev(w.x0), _dev(w.v0), _dev(a))
+    x1, v1 = x1.cpu().numpy(), v1.cpu().numpy()
+    xs = []
+    for b, p in enumerate(problems(w)):
+        sv = slice(w.body_v_off[b], w.body_v_off[b + 1])
+        se = slice(w.body_e_off[b], w.body_e_off[b + 1])
+        xr, vr, sr = solve.step(p, w.x0[sv], w.v0[sv], a[se], tol=1e-13)
+        print(b, "inverted at start", int((_jacobians(p, w.x0[sv]) <= 0).sum()), "oracle", sr["newton_iters"],
+              "gpu", st[b])
+        xs.append(xr)
+        assert rel(x1[sv] - w.x0[sv], xr - w.x0[sv]) <= tol
+        assert rel(v1[sv], vr) <= tol
+    xs = np.concatenate(xs)
+    xbar = rng.normal(size=xs.shape)
+    wg, st, _ = ctx.solve_adjoint(_dev(xs), _dev(w.x0), _dev(a), _dev(xbar))
+    wg = wg.cpu().numpy()
+    for b, p in enumerate(problems(w)):
+        sv = slice(w.body_v_off[b], w.body_v_off[b + 1])
+        se = slice(w.body_e_off[b], w.body_e_off[b + 1])
+        wr = solve.adjoint(p, xs[sv], w.x0[sv], a[se], xbar[sv])
+        assert rel(wg[sv], wr) <= tol

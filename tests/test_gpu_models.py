@@ -2,14 +2,14 @@
 stable neo-Hookean; Sec. 3) against the FP64 oracle through the C ABI: single evaluations in the
 atomic and patch scatter modes, the Lame-pair VJPs, and the plain and batched step and adjoint.
 
-The mixed adjoint solves with the FP32 operator. St. Venant-Kirchhoff and corotated form F^T F - I
-and F - R, which cancel near rest, from an FP32 F, so their mixed adjoint bar is 3e-5; the
-forward step converges to the FP64 gradient's zero and keeps 1e-5."""
+Mixed precision is held to the 1e-5 bar for the step and for the adjoint, which solves with the FP32
+operator (the error then follows the conditioning of H(x1): about 1e-7 on these triangles, 1e-6 on
+these tetrahedra, for every model), in the 2-norm and in the worst entry."""
 import numpy as np
 import pytest
 
 from oracle import fem, solve
-from tests.gpu_util import abs_assembly, problems, rand_workload, rel
+from tests.gpu_util import abs_assembly, problems, rand_workload, rel, rel_inf
 
 pytestmark = pytest.mark.gpu
 
@@ -102,9 +102,8 @@ def test_model_patch_scatter_large_mesh(model, dim, shape):
 @pytest.mark.parametrize("solver", [0, 1], ids=["plain", "batched"])
 @pytest.mark.parametrize("model", MODELS)
 @pytest.mark.parametrize("dim", [2, 3])
-@pytest.mark.parametrize("precision,tol,adj_tol", [("fp64", 1e-10, 1e-10), ("mixed", 1e-5, 3e-5)],
-                         ids=["fp64", "mixed"])
-def test_model_step_adjoint_parity(solver, model, dim, precision, tol, adj_tol):
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 1e-5)], ids=["fp64", "mixed"])
+def test_model_step_adjoint_parity(solver, model, dim, precision, tol):
     shape = (10, 3) if dim == 2 else (3, 3, 2)
     w, rng = _workload(dim, model, 54, bodies=3, shape=shape)
     w.scene.update(tol_rel=1e-13, adj_tol_rel=1e-13, max_newton=60, max_cg=4000)
@@ -120,6 +119,7 @@ def test_model_step_adjoint_parity(solver, model, dim, precision, tol, adj_tol):
         xs.append(xr)
         print(b, model, "gpu", st[b])
         assert rel(x1[sv] - w.x0[sv], xr - w.x0[sv]) <= tol
+        assert rel_inf(x1[sv] - w.x0[sv], xr - w.x0[sv]) <= tol
         assert rel(v1[sv], vr) <= tol
     xs = np.concatenate(xs)
     xbar = rng.normal(size=xs.shape)
@@ -130,7 +130,9 @@ def test_model_step_adjoint_parity(solver, model, dim, precision, tol, adj_tol):
         sv = slice(w.body_v_off[b], w.body_v_off[b + 1])
         se = slice(w.body_e_off[b], w.body_e_off[b + 1])
         wr = solve.adjoint(p, xs[sv], w.x0[sv], a[se], xbar[sv], vbar[sv])
-        assert rel(wg[sv], wr) <= adj_tol
+        print(b, model, "adjoint err", rel(wg[sv], wr), rel_inf(wg[sv], wr))
+        assert rel(wg[sv], wr) <= tol
+        assert rel_inf(wg[sv], wr) <= tol
 
 
 def test_model_option_errors():

@@ -6,7 +6,7 @@ import pytest
 from oracle import solve
 from oracle.fem import Problem
 from synth import scenes
-from tests.gpu_util import problems, rand_workload, rel, with_springs
+from tests.gpu_util import problems, rand_workload, rel, rel_inf, with_springs
 
 pytestmark = pytest.mark.gpu
 
@@ -60,7 +60,9 @@ def test_backward_euler_steps_parity(dim, precision, tol):
         xg, vg, st, _ = ctx.step(xg, vg, _dev(w.actions[t]))
         print(t, "oracle iters", st_ref["newton_iters"], "gpu", st[0])
         assert rel(xg.cpu().numpy() - w.x0, x - w.x0) <= tol
+        assert rel_inf(xg.cpu().numpy() - w.x0, x - w.x0) <= tol
         assert rel(vg.cpu().numpy(), v) <= tol
+        assert rel_inf(vg.cpu().numpy(), v) <= tol
         # continue both from the oracle state so that the steps are compared one by one
         xg, vg = _dev(x), _dev(v)
 
@@ -81,9 +83,12 @@ def test_adjoint_and_vjp_parity(dim, integ, precision, tol):
     wg, st, _ = ctx.solve_adjoint(_dev(x1), _dev(w.x0), _dev(a), _dev(xbar), None if vbar is None else _dev(vbar))
     print("adjoint", st[0])
     assert rel(wg.cpu().numpy(), wref) <= tol
+    assert rel_inf(wg.cpu().numpy(), wref) <= tol
     out = ctx.vjp_params(wg, _dev(x1), _dev(w.x0), _dev(a), None if vbar is None else _dev(vbar))
     for k in ("a_bar", "mu_bar", "lam_bar", "kf_bar", "x0_bar"):
+        print(k, rel(out[k].cpu().numpy(), ref[k]), rel_inf(out[k].cpu().numpy(), ref[k]))
         assert rel(out[k].cpu().numpy(), ref[k]) <= tol, k
+        assert rel_inf(out[k].cpu().numpy(), ref[k]) <= tol, k
 
 
 def test_colour_scatter_is_bitwise_reproducible():
@@ -97,19 +102,47 @@ def test_colour_scatter_is_bitwise_reproducible():
     assert outs[0][2:] == outs[1][2:]
 
 
-def test_error_paths():
+@pytest.mark.parametrize("solver", [0, 1], ids=["plain", "batched"])
+def test_error_paths(solver):
+    """Invalid actions (a <= 0, NaN), a non-finite state and the Newton cap, in both solvers; the
+    batched solver checks the actions on the device, per body, and its other bodies still solve."""
     from paper_2102_05791_amd import IsbError, isb
-    w, _ = rand_workload(2, seed=10, shape=(8, 3))
-    ctx = _ctx(w)
+    w, _ = rand_workload(2, seed=10, shape=(8, 3), bodies=2)
+    ctx = _ctx(w, solver=solver)
     a = w.actions[0].copy()
     a[3] = 0.0
     with pytest.raises(IsbError) as e:
         ctx.step(_dev(w.x0), _dev(w.v0), _dev(a))
     assert e.value.status == isb.ISB_E_ARG
+    with pytest.raises(IsbError) as e:
+        ctx.solve_adjoint(_dev(w.x0), _dev(w.x0), _dev(a), _dev(np.ones_like(w.x0)))
+    assert e.value.status == isb.ISB_E_ARG
+    if solver == 1:
+        # the per-body stats of the failed call: only body 0 holds the bad action
+        lib = ctx.lib
+        sb = (isb.Stats * w.n_bodies)()
+        x0d, v0d, ad = _dev(w.x0), _dev(w.v0), _dev(a)     # kept alive across the call
+        x1 = _dev(np.zeros_like(w.x0))
+        v1 = _dev(np.zeros_like(w.x0))
+        r = lib.isb_step(ctx.h, isb._stream(), isb._dev(x0d), isb._dev(v0d), isb._dev(ad), isb._dev(x1),
+                         isb._dev(v1), sb)
+        assert r == isb.ISB_E_ARG
+        assert sb[0].flags & isb.FLAG_INVALID_ACTION and not sb[1].flags & isb.FLAG_INVALID_ACTION
+        assert sb[1].flags & isb.FLAG_CONVERGED
+        nv0 = int(w.body_v_off[1])
+        xh = w.x0 + w.scene["h"] * w.v0
+        assert np.allclose(x1.cpu().numpy()[:nv0], xh[:nv0], rtol=1e-15, atol=1e-15)   # body 0: x1 = x_init
     a[3] = np.nan
     with pytest.raises(IsbError) as e:
         ctx.step(_dev(w.x0), _dev(w.v0), _dev(a))
     assert e.value.status == isb.ISB_E_NONFINITE
+    with pytest.raises(IsbError) as e:
+        ctx.solve_adjoint(_dev(w.x0), _dev(w.x0), _dev(a), _dev(np.ones_like(w.x0)))
+    assert e.value.status == isb.ISB_E_NONFINITE
+    # a valid call afterwards reports only its own outcome
+    x1, v1, st, _ = ctx.step(_dev(w.x0), _dev(w.v0), _dev(w.actions[0]))
+    wv, sa, _ = ctx.solve_adjoint(x1, _dev(w.x0), _dev(w.actions[0]), _dev(np.ones_like(w.x0)))
+    assert all(s["flags"] & isb.FLAG_ADJ_CONVERGED and not s["flags"] & (isb.FLAG_INVALID_ACTION | 4) for s in sa)
     x0 = w.x0.copy()
     x0[2, 0] = np.inf
     with pytest.raises(IsbError) as e:
@@ -128,14 +161,18 @@ def test_error_paths():
     assert e.value.status == isb.ISB_E_ARG
 
 
+@pytest.mark.parametrize("block", [0, 512, 768, 1024])
 @pytest.mark.parametrize("dim", [2, 3])
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 1e-5)])
-def test_batched_step_and_adjoint_parity(dim, precision, tol):
-    """Bodies of uneven size in one persistent launch; each body against its own oracle solve."""
+def test_batched_step_and_adjoint_parity(dim, precision, tol, block):
+    """Bodies of uneven size in one persistent launch; each body against its own oracle solve, at
+    every workgroup size isb_autotune can choose (0 = the default of the dimension)."""
+    from paper_2102_05791_amd import isb
     shape = (10, 3) if dim == 2 else (3, 3, 2)
     w, rng = rand_workload(dim, seed=11, bodies=4, shape=shape)
     w = _tight(w)
     ctx = _ctx(w, precision=precision, solver=1)
+    ctx.set_option(isb.OPT_BLOCK, block)
     a = w.actions[0]
     x1, v1, st, _ = ctx.step(_dev(w.x0), _dev(w.v0), _dev(a))
     x1, v1 = x1.cpu().numpy(), v1.cpu().numpy()
@@ -147,6 +184,7 @@ def test_batched_step_and_adjoint_parity(dim, precision, tol):
         xr, vr, sr = solve.step(p, w.x0[sv], w.v0[sv], a[se], tol=1e-13)
         print(b, "oracle", sr["newton_iters"], "gpu", st[b])
         assert rel(x1[sv] - w.x0[sv], xr - w.x0[sv]) <= tol
+        assert rel_inf(x1[sv] - w.x0[sv], xr - w.x0[sv]) <= tol
         assert rel(v1[sv], vr) <= tol
     # adjoint at the oracle's x1 so that only the adjoint is compared
     xs = np.concatenate([solve.step(p, w.x0[slice(w.body_v_off[b], w.body_v_off[b + 1])],
@@ -161,6 +199,7 @@ def test_batched_step_and_adjoint_parity(dim, precision, tol):
         wr = solve.adjoint(p, xs[sv], w.x0[sv], a[se], xbar[sv], vbar[sv])
         print(b, "adjoint", st[b]["adj_cg_iters"], st[b]["adj_res_final"])
         assert rel(wg[sv], wr) <= tol
+        assert rel_inf(wg[sv], wr) <= tol
 
 
 def test_batched_matches_plain_per_body():
