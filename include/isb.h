@@ -324,6 +324,17 @@ isb_status isb_gradient(isb_ctx* ctx, isb_stream stream, const double* x, const 
  * FP32 element arithmetic in ISB_MIXED. device [n_v][dim] in/out. */
 isb_status isb_hessvec(isb_ctx* ctx, isb_stream stream, const double* x, const double* x0,
                        const double* a, const double* p, double* hp);
+/* isb_hessvec for callers that cannot allocate device memory during the call: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc. Same arguments, result and errors as
+ * isb_hessvec, from the same kernels; no allocation and no library routine that allocates. The
+ * product's staging (friction factor, vertex-term diagonal, masked operand, FP32 actuation in
+ * ISB_MIXED: 8 (n_v (1 + 2 dim)) + 4 n_e bytes, each part rounded up to 256 B) lives in a fixed
+ * 32 MiB array of device memory that every GPU the library runs on holds until the process ends;
+ * a mesh that needs more returns ISB_E_ARG. Every call on one GPU shares that array, so calls that
+ * overlap on one GPU (several streams or host threads) race; serialise them. Nothing in the array
+ * needs to start at zero: each call writes every entry it reads. */
+isb_status isb_hessvec_noalloc(isb_ctx* ctx, isb_stream stream, const double* x, const double* x0,
+                               const double* a, const double* p, double* hp);
 /* Element part of the Hessian-vector product only, added into hp: hp += sum_e W_e dP(F_e; dF_e(p)) Dm^-T
  * scattered to the element's vertices, plus the springs' K (p_j - p_i) (Eq. 10 without the vertex
  * terms and without the projection onto free DOFs), scaled by h^2 in backward Euler. This is the hot kernel of the CG iteration on

@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -180,9 +181,9 @@ static void spring_scatter(isb_ctx* c, int b, int op, const double* x, const dou
 // element scatter of op (PATCH_GRAD / PATCH_HV / PATCH_DIAG) over body b (all bodies when b < 0),
 // in the context's scatter mode: FP64 global atomics, colour passes, or LDS-staged patches. Only
 // the Hessian-vector product takes the context's precision; gradient and diagonal are FP64.
+// a32: the FP32 copy of the actuation that mixed Hessian-vector products read (nullptr: they read a)
 static void elem_scatter(isb_ctx* c, int b, int op, const double* x, const double* a, const double* p, double* out,
-                         const int* done, hipStream_t s, bool a32_copy = true) {
-  const float* a32 = a32_copy ? c->w_a32 : nullptr;
+                         const int* done, hipStream_t s, const float* a32 = nullptr) {
   const DevMesh m = devmesh(c);
   const DevScene sc = devscene(c);
   const int64_t ne_scope = b < 0 ? c->n_e : c->eoff[b + 1] - c->eoff[b];
@@ -279,7 +280,7 @@ static void enqueue_energy(isb_ctx* c, int b, const double* x, const double* dx,
 static void cg_iteration(isb_ctx* c, int b, const double* x, const double* a, hipStream_t s) {
   const BodyRange br = body_range(c, b);
   const int o = br.off;
-  elem_scatter(c, b, PATCH_HV, x, a, c->w_p, c->w_Hp, &c->scal->done, s);
+  elem_scatter(c, b, PATCH_HV, x, a, c->w_p, c->w_Hp, &c->scal->done, s, c->w_a32);
   launch_cg_dot(br.n, c->w_p + o, c->w_Hp + o, c->partials, c->scal, s);
   launch_cg_update(br.n, c->w_p + o, c->w_Hp + o, c->w_Dinvp + o, c->w_r + o, c->w_xs + o, c->partials, c->scal, s);
   launch_cg_p(br.n, c->w_r + o, c->w_Dinvp + o, c->w_vdiag + o, c->w_p + o, c->w_Hp + o, c->partials, c->scal, s);
@@ -706,7 +707,7 @@ static isb_status plain_adjoint(isb_ctx* c, hipStream_t s, const double* x1, con
         launch_mask(m, br.v0, br.v1, w, s);
         launch_copy(br.n, w + br.off, c->w_p + br.off, s);
         launch_mul(br.n, c->w_vdiag + br.off, c->w_p + br.off, c->w_Hp + br.off, s);
-        elem_scatter(c, b, PATCH_HV, x1, a, c->w_p, c->w_Hp, nullptr, s);
+        elem_scatter(c, b, PATCH_HV, x1, a, c->w_p, c->w_Hp, nullptr, s, c->w_a32);
         launch_mask(m, br.v0, br.v1, c->w_Hp, s);
         launch_axpy(br.n, c->w_G + br.off, -1.0, c->w_Hp + br.off, s);
       }
@@ -761,6 +762,78 @@ static isb_status alloc_workspaces(isb_ctx* c) {
 }
 
 // ---------------------------------------------------------------------------------------------
+// the Hessian-vector product of isb_hessvec and isb_hessvec_noalloc
+// ---------------------------------------------------------------------------------------------
+// Device memory the product stages besides its inputs and output: the friction factor cv [n_v],
+// the vertex-term diagonal vdiag [n_v*dim], the masked operand pm [n_v*dim] and, in mixed
+// precision, the FP32 actuation a32 [n_e]. Every entry is written before it is read.
+struct HvScratch {
+  double *cv, *vdiag, *pm;
+  float* a32;
+};
+
+// hp = P H(x) P p: vertex terms from the friction factor of x0, then the elements (and springs)
+static void enqueue_hessvec(isb_ctx* c, hipStream_t s, const double* x, const double* x0, const double* a,
+                            const double* p, double* hp, const HvScratch& w) {
+  const DevMesh m = devmesh(c);
+  const DevScene dsc = devscene(c);
+  const int n = c->n_v * c->dim;
+  if (c->precision == ISB_MIXED) launch_to_f32(c->n_e, a, w.a32, s);
+  launch_setup(m, dsc, 0, c->n_v, x0, nullptr, nullptr, nullptr, w.cv, s);
+  launch_vertex_hdiag(m, dsc, 0, c->n_v, x, w.cv, w.vdiag, s);
+  launch_copy(n, p, w.pm, s);
+  launch_mask(m, 0, c->n_v, w.pm, s);
+  launch_mul(n, w.vdiag, w.pm, hp, s);
+  elem_scatter(c, -1, PATCH_HV, x, a, w.pm, hp, nullptr, s, w.a32);
+  launch_mask(m, 0, c->n_v, hp, s);
+}
+
+// Scratch of isb_hessvec_noalloc: a fixed array in device memory, one copy per GPU for the life of
+// the process, shared by every call on that GPU (calls that overlap on one GPU race on it). Host
+// code must not pass the array's name to a kernel: its device address is resolved per device with
+// hipGetSymbolAddress (scratch_resolve, called by isb_create with the device current) and only that
+// address is used.
+static constexpr size_t kNoallocScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) double scratch[kNoallocScratchBytes / sizeof(double)];
+static constexpr int kMaxScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_dev[kMaxScratchDevices] = {};
+
+static isb_status scratch_resolve(int device) {
+  if (device < 0 || device >= kMaxScratchDevices) return fail(ISB_E_ARG, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_dev[device]) return ISB_OK;
+  void* ptr = nullptr;
+  ISB_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+  if (!ptr) return fail(ISB_E_HIP, "hipGetSymbolAddress returned no address for the scratch array");
+  g_scratch_dev[device] = ptr;
+  return ISB_OK;
+}
+
+static void* scratch_ptr(int device) {
+  if (device < 0 || device >= kMaxScratchDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_dev[device];
+}
+
+// word offsets of HvScratch inside the scratch array, each segment 256-byte aligned
+struct NoallocLayout {
+  size_t cv, vdiag, pm, a32, words;
+};
+
+static NoallocLayout noalloc_layout(const isb_ctx* c) {
+  auto up = [](size_t w) { return (w + 31) / 32 * 32; };
+  const size_t nv = (size_t)c->n_v, nd = nv * (size_t)c->dim;
+  NoallocLayout L;
+  L.cv = 0;
+  L.vdiag = L.cv + up(nv);
+  L.pm = L.vdiag + up(nd);
+  L.a32 = L.pm + up(nd);
+  L.words = L.a32 + (c->precision == ISB_MIXED ? up(((size_t)c->n_e + 1) / 2) : 0);
+  return L;
+}
+
+// ---------------------------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------------------------
 extern "C" {
@@ -774,6 +847,7 @@ isb_status isb_create(int device, int precision, isb_ctx** out) {
   ISB_HIP(hipGetDeviceCount(&n));
   if (device < 0 || device >= n) return fail(ISB_E_ARG, "device index out of range");
   ISB_HIP(hipSetDevice(device));
+  ISB_TRY(scratch_resolve(device));
   isb_ctx* c = new isb_ctx();
   c->device = device;
   c->precision = precision;
@@ -1317,18 +1391,25 @@ isb_status isb_hessvec(isb_ctx* c, isb_stream stream, const double* x, const dou
   clear_error();
   ISB_TRY(check_ctx(c, true));
   if (!x || !x0 || !a || !p || !hp) return fail(ISB_E_ARG, "NULL argument");
-  hipStream_t s = (hipStream_t)stream;
-  const DevMesh m = devmesh(c);
-  const DevScene dsc = devscene(c);
-  const int n = c->n_v * c->dim;
-  if (c->precision == ISB_MIXED) launch_to_f32(c->n_e, a, c->w_a32, s);
-  launch_setup(m, dsc, 0, c->n_v, x0, nullptr, c->w_xt, c->w_xhat, c->w_cv, s);
-  launch_vertex_hdiag(m, dsc, 0, c->n_v, x, c->w_cv, c->w_vdiag, s);
-  launch_copy(n, p, c->w_p, s);
-  launch_mask(m, 0, c->n_v, c->w_p, s);
-  launch_mul(n, c->w_vdiag, c->w_p, hp, s);
-  elem_scatter(c, -1, PATCH_HV, x, a, c->w_p, hp, nullptr, s);
-  launch_mask(m, 0, c->n_v, hp, s);
+  enqueue_hessvec(c, (hipStream_t)stream, x, x0, a, p, hp, HvScratch{c->w_cv, c->w_vdiag, c->w_p, c->w_a32});
+  ISB_HIP(hipGetLastError());
+  return ISB_OK;
+}
+
+isb_status isb_hessvec_noalloc(isb_ctx* c, isb_stream stream, const double* x, const double* x0, const double* a,
+                               const double* p, double* hp) {
+  clear_error();
+  ISB_TRY(check_ctx(c, true));
+  if (!x || !x0 || !a || !p || !hp) return fail(ISB_E_ARG, "NULL argument");
+  double* base = static_cast<double*>(scratch_ptr(c->device));
+  if (!base) return fail(ISB_E_STATE, "isb_hessvec_noalloc: scratch of this device not resolved");
+  const NoallocLayout L = noalloc_layout(c);
+  if (L.words * sizeof(double) > kNoallocScratchBytes)
+    return fail(ISB_E_ARG, "isb_hessvec_noalloc: the mesh needs " + std::to_string(L.words * sizeof(double)) +
+                               " B of scratch, the maximum is " + std::to_string(kNoallocScratchBytes) + " B");
+  const HvScratch w{base + L.cv, base + L.vdiag, base + L.pm,
+                    c->precision == ISB_MIXED ? reinterpret_cast<float*>(base + L.a32) : nullptr};
+  enqueue_hessvec(c, (hipStream_t)stream, x, x0, a, p, hp, w);
   ISB_HIP(hipGetLastError());
   return ISB_OK;
 }
@@ -1342,7 +1423,7 @@ isb_status isb_hessvec_elements(isb_ctx* c, isb_stream stream, const double* x, 
   const DevMesh m = devmesh(c);
   const DevScene dsc = devscene(c);
   // one pass: the element kernels read the FP64 actuation directly (no FP32 copy)
-  elem_scatter(c, -1, PATCH_HV, x, a, p, hp, nullptr, s, /*a32_copy=*/false);
+  elem_scatter(c, -1, PATCH_HV, x, a, p, hp, nullptr, s);
   ISB_HIP(hipGetLastError());
   return ISB_OK;
 }

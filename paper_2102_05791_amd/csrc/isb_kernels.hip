@@ -146,6 +146,8 @@ __device__ __forceinline__ bool tangential(int c) {
   return c != 1;
 }
 
+// x (the initial iterate), xhat (x0 + h v0) and cv (the friction factor of Eq. 17); x and xhat may be
+// null when only cv is wanted
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_setup(DevMesh m, DevScene sc, int v0, int v1,
                                                   const double* __restrict__ x0, const double* __restrict__ vel0,
@@ -155,8 +157,8 @@ __global__ void __launch_bounds__(kBlock) k_setup(DevMesh m, DevScene sc, int v0
     for (int c = 0; c < D; ++c) {
       const size_t i = (size_t)v * D + c;
       const double xh = (sc.be && vel0) ? x0[i] + sc.h * vel0[i] : x0[i];
-      xhat[i] = xh;
-      x[i] = m.pinned[i] ? x0[i] : xh;
+      if (xhat) xhat[i] = xh;
+      if (x) x[i] = m.pinned[i] ? x0[i] : xh;
     }
     cv[v] = fmax(-x0[(size_t)v * D + 1] + sc.eps, 0.0);
   }

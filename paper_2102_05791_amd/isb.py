@@ -34,7 +34,8 @@ EXPORTED = ("isb_create", "isb_destroy", "isb_last_error", "isb_version", "isb_v
             "isb_set_option", "isb_get_option", "isb_get_mass", "isb_step", "isb_solve_adjoint",
             "isb_vjp_params", "isb_energy", "isb_gradient", "isb_hessvec", "isb_hessvec_elements",
             "isb_hessdiag", "isb_stream_copy", "isb_spring_upload", "isb_vjp_spring_stiffness",
-            "isb_gradient_elements", "isb_locality_order", "isb_wave_order", "isb_autotune")
+            "isb_gradient_elements", "isb_locality_order", "isb_wave_order", "isb_autotune",
+            "isb_hessvec_noalloc")
 
 
 class IsbError(RuntimeError):
@@ -111,6 +112,7 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
         "isb_energy": [vp, vp, vp, vp, vp, vp, vp],
         "isb_gradient": [vp, vp, vp, vp, vp, vp, vp],
         "isb_hessvec": [vp, vp, vp, vp, vp, vp, vp],
+        "isb_hessvec_noalloc": [vp, vp, vp, vp, vp, vp, vp],
         "isb_hessvec_elements": [vp, vp, vp, vp, vp, vp],
         "isb_hessdiag": [vp, vp, vp, vp, vp, vp],
         "isb_gradient_elements": [vp, vp, vp, vp, vp],
@@ -442,6 +444,13 @@ class Context:
     def hessvec(self, x, x0, a, p):
         hp = self._empty(self.n_v, self.dim)
         _check(self.lib, self.lib.isb_hessvec(self.h, _stream(), _dev(x), _dev(x0), self._a(a), _dev(p), _dev(hp)))
+        return hp
+
+    def hessvec_noalloc(self, x, x0, a, p, hp):
+        """isb_hessvec_noalloc: hp = P H(x) P p into the caller's hp, staged in the library's fixed
+        device scratch (no allocation, here or in the library)."""
+        _check(self.lib, self.lib.isb_hessvec_noalloc(self.h, _stream(), _dev(x), _dev(x0), self._a(a), _dev(p),
+                                                      _dev(hp)))
         return hp
 
     def hessvec_elements(self, x, a, p, hp):
