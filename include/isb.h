@@ -100,7 +100,9 @@ typedef enum {
   ISB_OPT_GRAPH_SAFE = 2,   /* 1 = no host synchronisation inside step/adjoint/vjp (batched solver only) */
   ISB_OPT_BLOCK = 3,        /* batched solver workgroup size: 256, 512, 768 or 1024; 0 (default) = 768 for
                                triangles, 512 for tetrahedra */
-  ISB_OPT_CG_CHECK = 4,     /* plain solver: read the CG convergence flag every k iterations (default 4) */
+  ISB_OPT_CG_CHECK = 4,     /* plain solver: CG iterations are enqueued in batches of k (default 4); the host reads the
+                             * convergence flag of each batch while the next one is already queued, so up to 2k
+                             * iterations past convergence are enqueued and return at once */
   ISB_OPT_PRECISION = 5,    /* isb_precision; equals the value given to isb_create */
   ISB_OPT_ENERGY = 6,       /* isotropic element energy, one of isb_energy_model (default neo-Hookean); the
                              * batched solver runs the alternatives with the default workgroup size only */
@@ -118,6 +120,21 @@ typedef enum {
                              * correction, to the same tolerance on the residual of H w = b; 0 (default) =
                              * w is output only and CG starts from zero. An FP64 re-solve (ISB_OPT_FP64_FALLBACK)
                              * starts from the first attempt's w */
+  ISB_OPT_COMPACT_REST = 13, /* 1 (default) = when every element has the same (mu, lam, k_f) and every fibre
+                             * direction is the same coordinate axis, the kernels that have a compact variant
+                             * (the LDS-staged patch kernels, the batched solver) read per element only Dm^-1
+                             * and W, and take the material from three scalars and the fibre from a column of
+                             * Dm^-1 (the same FP64 values; ISB_INFO_COMPACT_AXIS tells whether it applies);
+                             * 0 = always the general per-element record */
+  ISB_OPT_PATCH_BLOCK = 14, /* threads per workgroup of the LDS-staged patch kernels: 256, 512 or 1024; 0 = the
+                             * default (512 for FP32 element math, 256 for FP64); the alternative energy models
+                             * run with the default only */
+  ISB_OPT_CG_SINGLE_REDUCTION = 15, /* plain solver: 1 (default) = where the Hessian-vector product is one
+                             * LDS-staged patch launch (bodies of >= 16,384 elements in ISB_OPT_SCATTER 2, no
+                             * springs), CG runs in the single-reduction form of Chronopoulos and Gear: the
+                             * product also returns its share of u^T H u and one vector kernel forms every
+                             * scalar from one reduction, two launches per iteration instead of four;
+                             * 0 = the classic form everywhere. Same iterates in exact arithmetic */
   ISB_OPT_CG_GRAPH = 10     /* plain solver: 1 = run CG as a graph of 8 iterations, captured once per solve and
                              * replayed until converged (one launch and one host read per 8 iterations);
                              * 0 (default) = one launch per kernel and a read every ISB_OPT_CG_CHECK iterations.
@@ -131,6 +148,7 @@ typedef enum {
 #define ISB_INFO_DIM 103
 #define ISB_INFO_N_COLOURS 104    /* colours of the element colouring (max over bodies) */
 #define ISB_INFO_LDS_BYTES 105    /* LDS bytes per workgroup of the batched solver for the largest body */
+#define ISB_INFO_COMPACT_AXIS 106 /* the fibre axis of the compact rest record in use, -1 when not in use */
 
 /* Per-body solver statistics (host memory). */
 typedef struct {

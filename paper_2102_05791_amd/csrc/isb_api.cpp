@@ -41,6 +41,9 @@ isb_ctx::~isb_ctx() {
   free_list(mesh_allocs);
   if (hscal) (void)hipHostFree(hscal);
   if (hcg) (void)hipHostFree(hcg);
+  if (hcg_ring) (void)hipHostFree(hcg_ring);
+  for (hipEvent_t& e : cg_ev)
+    if (e) (void)hipEventDestroy(e);
   if (cap_stream) (void)hipStreamDestroy(cap_stream);
 }
 
@@ -66,6 +69,11 @@ DevMesh devmesh(const isb_ctx* c) {
   m.mass = c->mass;
   m.pinned = c->pinned;
   m.model = c->model;
+  m.axis = c->compact_rest ? c->uni_axis : -1;
+  m.mu_u = c->uni_mu;
+  m.lam_u = c->uni_lam;
+  m.kf_u = c->uni_kf;
+  m.W32 = c->W32;
   return m;
 }
 
@@ -190,7 +198,9 @@ static void elem_scatter(isb_ctx* c, int b, int op, const double* x, const doubl
   if (c->scatter == 2 && ne_scope >= kPatchMinElems) {
     const int p0 = b < 0 ? 0 : c->body_patch_off[b];
     const int p1 = b < 0 ? c->n_patches : c->body_patch_off[b + 1];
-    launch_elem_patch(m, sc, c->plan, p0, p1, op, op == PATCH_HV ? c->precision : 0, x, a, a32, p, out, done, s);
+    PatchPlan plan = c->plan;
+    plan.block = c->patch_block;
+    launch_elem_patch(m, sc, plan, p0, p1, op, op == PATCH_HV ? c->precision : 0, x, a, a32, p, out, done, s);
   } else {
     elem_ranges(c, b, [&](ERange r, bool atomic) {
       if (op == PATCH_GRAD)
@@ -275,11 +285,32 @@ static void enqueue_energy(isb_ctx* c, int b, const double* x, const double* dx,
   launch_finalize(c->partials, nbe + nbs + nbv, 3, out, s);
 }
 
-// one CG iteration over body b: the Hessian-vector product, then the three vector kernels (every
-// kernel returns at once when the device flag says the solve is done)
+// The single-reduction CG runs where the Hessian-vector product is one patch launch that can also
+// return its curvature partials: LDS-staged patches, no springs (their curvature would need a pass
+// of its own).
+static bool single_reduction_cg(const isb_ctx* c, int b) {
+  const int64_t ne = b < 0 ? c->n_e : c->eoff[b + 1] - c->eoff[b];
+  return c->cg_single && c->scatter == 2 && ne >= kPatchMinElems && c->n_s == 0;
+}
+
+// one CG iteration over body b (every kernel returns at once when the device flag says the solve is
+// done). Classic PCG: the Hessian-vector product, then three vector kernels (p.Hp; x, r, r.z; the
+// next p). Single-reduction PCG: the Hessian-vector product with its curvature partials (w += H u),
+// then one vector kernel.
 static void cg_iteration(isb_ctx* c, int b, const double* x, const double* a, hipStream_t s) {
   const BodyRange br = body_range(c, b);
   const int o = br.off;
+  if (single_reduction_cg(c, b)) {
+    const int p0 = b < 0 ? 0 : c->body_patch_off[b];
+    const int p1 = b < 0 ? c->n_patches : c->body_patch_off[b + 1];
+    PatchPlan plan = c->plan;
+    plan.block = c->patch_block;
+    const int nhv = launch_elem_patch(devmesh(c), devscene(c), plan, p0, p1, PATCH_HV, c->precision, x, a, c->w_a32,
+                                      c->w_u, c->w_Hp, &c->scal->done, s, c->hv_part);
+    launch_cgcg_vec(br.n, c->hv_part, nhv, c->partials, c->w_Dinvp + o, c->w_vdiag + o, c->w_r + o, c->w_u + o,
+                    c->w_Hp + o, c->w_p + o, c->w_s + o, c->w_xs + o, c->scal, s);
+    return;
+  }
   elem_scatter(c, b, PATCH_HV, x, a, c->w_p, c->w_Hp, &c->scal->done, s, c->w_a32);
   launch_cg_dot(br.n, c->w_p + o, c->w_Hp + o, c->partials, c->scal, s);
   launch_cg_update(br.n, c->w_p + o, c->w_Hp + o, c->w_Dinvp + o, c->w_r + o, c->w_xs + o, c->partials, c->scal, s);
@@ -298,8 +329,13 @@ static isb_status run_cg(isb_ctx* c, int b, const double* x, const double* a, co
                          double tol, int max_cg, hipStream_t s, int* iters, bool* negcurv, double* rr) {
   const BodyRange br = body_range(c, b);
   const int o = br.off;
-  launch_cg_start(br.n, rhs + o, sign, c->w_Dinvp + o, c->w_vdiag + o, c->w_r + o, c->w_p + o, c->w_xs + o,
-                  c->w_Hp + o, c->partials, c->scal, tol * tol, max_cg, s);
+  const bool single = single_reduction_cg(c, b);
+  if (single)
+    launch_cgcg_start(br.n, rhs + o, sign, c->w_Dinvp + o, c->w_vdiag + o, c->w_r + o, c->w_u + o, c->w_Hp + o,
+                      c->w_p + o, c->w_s + o, c->w_xs + o, c->partials, c->scal, tol * tol, max_cg, s);
+  else
+    launch_cg_start(br.n, rhs + o, sign, c->w_Dinvp + o, c->w_vdiag + o, c->w_r + o, c->w_p + o, c->w_xs + o,
+                    c->w_Hp + o, c->partials, c->scal, tol * tol, max_cg, s);
   if (c->cg_graph && max_cg > kCgChunk) {
     if (!c->cap_stream) ISB_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     hipGraph_t graph = nullptr;
@@ -323,15 +359,28 @@ static isb_status run_cg(isb_ctx* c, int b, const double* x, const double* a, co
     (void)hipGraphExecDestroy(exec);
     if (st != ISB_OK) return st;
   } else {
+    // Batches of cg_check iterations with one batch of look-ahead: each batch ends with an
+    // asynchronous copy of the CG scalars to pinned host memory and an event; the host waits for the
+    // previous batch's event while the current batch is already queued, so the GPU does not drain at
+    // every check. Iterations enqueued after convergence return at once (the device flag).
     const int check = std::max(1, c->cg_check);
-    for (int it = 0; it < max_cg; ++it) {
-      cg_iteration(c, b, x, a, s);
-      if (it == 0 || (it + 1) % check == 0 || it + 1 == max_cg) {
-        ISB_TRY(read_cg(c, s));
-        if (c->hcg->done) break;
+    int k = 0, enq = 0;
+    bool pending = false;
+    while (enq < max_cg) {
+      const int n = std::min(check, max_cg - enq);
+      for (int j = 0; j < n; ++j) cg_iteration(c, b, x, a, s);
+      enq += n;
+      ISB_HIP(hipMemcpyAsync(c->hcg_ring + (k & 1), c->scal, sizeof(CgScal), hipMemcpyDeviceToHost, s));
+      ISB_HIP(hipEventRecord(c->cg_ev[k & 1], s));
+      if (pending) {
+        ISB_HIP(hipEventSynchronize(c->cg_ev[(k - 1) & 1]));
+        if (c->hcg_ring[(k - 1) & 1].done) break;
       }
+      pending = true;
+      ++k;
     }
   }
+  if (single) launch_cgcg_final(br.n, c->partials, c->scal, s);
   ISB_TRY(read_cg(c, s));
   *iters = c->hcg->iters;
   *negcurv = c->hcg->negcurv != 0;
@@ -745,8 +794,9 @@ static isb_status alloc_workspaces(isb_ctx* c) {
   const size_t nd = (size_t)c->n_v * c->dim;
   auto& L = c->work_allocs;
   for (double** p : {&c->w_x, &c->w_xt, &c->w_xhat, &c->w_G, &c->w_Gt, &c->w_xs, &c->w_r, &c->w_p, &c->w_Hp,
-                     &c->w_Dinvp, &c->w_vdiag, &c->w_diag})
+                     &c->w_Dinvp, &c->w_vdiag, &c->w_diag, &c->w_u, &c->w_s})
     ISB_TRY(dalloc(L, p, nd));
+  ISB_TRY(dalloc(L, &c->hv_part, (size_t)std::max(1, std::min(c->n_patches, kMaxPatchGrid))));
   ISB_TRY(dalloc(L, &c->w_cv, (size_t)c->n_v));
   ISB_TRY(dalloc(L, &c->w_a32, (size_t)c->n_e));
   ISB_TRY(dalloc(L, &c->partials, (size_t)12 * kMaxRedBlocks));
@@ -755,7 +805,7 @@ static isb_status alloc_workspaces(isb_ctx* c) {
   ISB_TRY(dalloc(L, &c->scal, (size_t)1));
   // zero the vectors once so that the Hessian-vector kernel never reads uninitialised memory
   for (double* p : {c->w_x, c->w_xt, c->w_xhat, c->w_G, c->w_Gt, c->w_xs, c->w_r, c->w_p, c->w_Hp, c->w_Dinvp,
-                    c->w_vdiag, c->w_diag})
+                    c->w_vdiag, c->w_diag, c->w_u, c->w_s})
     ISB_HIP(hipMemset(p, 0, nd * sizeof(double)));
   ISB_HIP(hipMemset(c->scal, 0, sizeof(CgScal)));
   return ISB_OK;
@@ -852,9 +902,12 @@ isb_status isb_create(int device, int precision, isb_ctx** out) {
   c->device = device;
   c->precision = precision;
   if (hipHostMalloc((void**)&c->hscal, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&c->hcg, sizeof(CgScal), hipHostMallocDefault) != hipSuccess) {
+      hipHostMalloc((void**)&c->hcg, sizeof(CgScal), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&c->hcg_ring, 2 * sizeof(CgScal), hipHostMallocDefault) != hipSuccess ||
+      hipEventCreateWithFlags(&c->cg_ev[0], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->cg_ev[1], hipEventDisableTiming) != hipSuccess) {
     delete c;
-    return fail(ISB_E_HIP, "pinned host allocation failed");
+    return fail(ISB_E_HIP, "pinned host allocation or event creation failed");
   }
   *out = c;
   return ISB_OK;
@@ -885,6 +938,8 @@ isb_status isb_mesh_upload(isb_ctx* c, int dim, int32_t n_bodies, const int64_t*
   c->free_list(c->mesh_allocs);
   c->have_mesh = c->have_material = false;
   c->dim = dim;
+  c->uni_axis = -1;
+  c->W32 = nullptr;
   c->n_bodies = n_bodies;
   c->n_v = (int)n_v;
   c->n_e = (int)n_e;
@@ -966,6 +1021,7 @@ isb_status isb_mesh_upload(isb_ctx* c, int dim, int32_t n_bodies, const int64_t*
   ISB_HIP(hipMemcpy(p_lconn, pt.lconn.data(), pt.lconn.size() * 2, hipMemcpyHostToDevice));
   c->plan = PatchPlan{p_eoff, p_voff, p_verts, p_lconn, pt.max_nv};
   if (c->precision == ISB_MIXED) {
+    ISB_TRY(dalloc(L, &c->W32, ne));
     ISB_TRY(dalloc(L, &c->Dinv32, (size_t)dim * dim * ne));
     ISB_TRY(dalloc(L, &c->gf32, (size_t)dim * ne));
     ISB_TRY(dalloc(L, &c->wmu32, ne));
@@ -977,6 +1033,7 @@ isb_status isb_mesh_upload(isb_ctx* c, int dim, int32_t n_bodies, const int64_t*
   ISB_HIP(hipMemcpy(c->pinned, dof_pinned, nd, hipMemcpyHostToDevice));
   ISB_HIP(hipMemcpy(c->clist, clist.data(), ne * sizeof(int32_t), hipMemcpyHostToDevice));
   launch_precompute_geom(dim, (int)n_e, c->X, c->conn, c->Dinv, c->W, nullptr);
+  if (c->W32) launch_to_f32((int)n_e, c->W, c->W32, nullptr);
   ISB_HIP(hipGetLastError());
   ISB_HIP(hipDeviceSynchronize());
   ISB_TRY(alloc_workspaces(c));
@@ -1029,6 +1086,24 @@ isb_status isb_material_upload(isb_ctx* c, const double* mu, const double* lam, 
   st = copy_all();
   c->free_list(tmp);
   if (st != ISB_OK) return st;
+  // compact rest record: one (mu, lam, k_f) for every element and every fibre along one coordinate axis
+  c->uni_axis = -1;
+  if (ne > 0) {
+    int axis = -1;
+    for (int k = 0; k < c->dim; ++k)
+      if (fibre_dir[k] == 1.0) axis = k;
+    bool uniform = axis >= 0;
+    for (size_t e = 0; e < ne && uniform; ++e) {
+      uniform = mu[e] == mu[0] && lam[e] == lam[0] && k_fibre[e] == k_fibre[0];
+      for (int k = 0; k < c->dim && uniform; ++k) uniform = fibre_dir[e * c->dim + k] == (k == axis ? 1.0 : 0.0);
+    }
+    if (uniform) {
+      c->uni_axis = axis;
+      c->uni_mu = mu[0];
+      c->uni_lam = lam[0];
+      c->uni_kf = k_fibre[0];
+    }
+  }
   c->scene = *scene;
   c->have_material = true;
   batched_release(c);
@@ -1083,6 +1158,20 @@ isb_status isb_set_option(isb_ctx* c, int key, int64_t value) {
       if (value != 0 && value != 1) return fail(ISB_E_ARG, "adjoint warm start must be 0 or 1");
       c->adj_warm = (int)value;
       return ISB_OK;
+    case ISB_OPT_CG_SINGLE_REDUCTION:
+      if (value != 0 && value != 1) return fail(ISB_E_ARG, "single-reduction CG must be 0 or 1");
+      c->cg_single = (int)value;
+      return ISB_OK;
+    case ISB_OPT_PATCH_BLOCK:
+      if (value != 0 && value != 256 && value != 512 && value != 1024)
+        return fail(ISB_E_ARG, "patch block must be 0 (default), 256, 512 or 1024");
+      c->patch_block = (int)value;
+      return ISB_OK;
+    case ISB_OPT_COMPACT_REST:
+      if (value != 0 && value != 1) return fail(ISB_E_ARG, "compact rest record must be 0 or 1");
+      c->compact_rest = (int)value;
+      batched_release(c);
+      return ISB_OK;
     case ISB_OPT_FORWARD:
       if (value != ISB_FORWARD_NEWTON && value != ISB_FORWARD_LBFGS)
         return fail(ISB_E_ARG, "forward must be ISB_FORWARD_NEWTON or ISB_FORWARD_LBFGS");
@@ -1116,6 +1205,10 @@ isb_status isb_get_option(isb_ctx* c, int key, int64_t* value) {
     case ISB_OPT_CG_GRAPH: *value = c->cg_graph; return ISB_OK;
     case ISB_OPT_FP64_FALLBACK: *value = c->fp64_fallback; return ISB_OK;
     case ISB_OPT_ADJ_WARM_START: *value = c->adj_warm; return ISB_OK;
+    case ISB_OPT_COMPACT_REST: *value = c->compact_rest; return ISB_OK;
+    case ISB_OPT_PATCH_BLOCK: *value = c->patch_block; return ISB_OK;
+    case ISB_OPT_CG_SINGLE_REDUCTION: *value = c->cg_single; return ISB_OK;
+    case ISB_INFO_COMPACT_AXIS: *value = c->have_material && c->compact_rest ? c->uni_axis : -1; return ISB_OK;
     case ISB_OPT_LBFGS_MEMORY: *value = c->lbfgs_m; return ISB_OK;
     case ISB_OPT_LBFGS_MAX_ITERS: *value = c->lbfgs_max_iters; return ISB_OK;
     case ISB_INFO_N_VERTICES: *value = c->n_v; return ISB_OK;

@@ -29,8 +29,12 @@ struct isb_ctx {
   int32_t* conn = nullptr;
   double *X = nullptr, *Dinv = nullptr, *W = nullptr, *gf = nullptr, *wmu = nullptr, *wlam = nullptr,
          *wkf = nullptr, *mass = nullptr, *rho = nullptr;
-  float *Dinv32 = nullptr, *gf32 = nullptr, *wmu32 = nullptr, *wlam32 = nullptr, *wkf32 = nullptr;
+  float *Dinv32 = nullptr, *gf32 = nullptr, *wmu32 = nullptr, *wlam32 = nullptr, *wkf32 = nullptr,
+        *W32 = nullptr;
   uint8_t* pinned = nullptr;
+  // the material is uniform with the fibre along axis `uni_axis` (-1: not); see DevMesh::axis
+  int uni_axis = -1;
+  double uni_mu = 0.0, uni_lam = 0.0, uni_kf = 0.0;
 
   // element colouring: elements of body b and colour k are clist[col_off[b*(nc+1)+k] .. +1)
   int n_colours = 0;
@@ -61,12 +65,17 @@ struct isb_ctx {
   int cg_graph = 0;                    // ISB_OPT_CG_GRAPH
   int fp64_fallback = 1;               // ISB_OPT_FP64_FALLBACK
   int adj_warm = 0;                    // ISB_OPT_ADJ_WARM_START
+  int compact_rest = 1;                // ISB_OPT_COMPACT_REST
+  int patch_block = 0;                 // ISB_OPT_PATCH_BLOCK (0: kPatchBlock)
+  int cg_single = 1;                   // ISB_OPT_CG_SINGLE_REDUCTION
   hipStream_t cap_stream = nullptr;    // internal stream the CG chunk is captured on
 
   // plain-solver workspaces, [n_v*dim] unless noted
   double *w_x = nullptr, *w_xt = nullptr, *w_xhat = nullptr, *w_cv = nullptr /*[n_v]*/, *w_G = nullptr,
          *w_Gt = nullptr, *w_xs = nullptr, *w_r = nullptr, *w_p = nullptr, *w_Hp = nullptr, *w_Dinvp = nullptr,
          *w_vdiag = nullptr, *w_diag = nullptr;
+  double *w_u = nullptr, *w_s = nullptr;  // single-reduction CG: u = D^-1 r and s = H p
+  double* hv_part = nullptr;        // [min(n_patches, kMaxPatchGrid)] curvature partials of the patch Hv
   float* w_a32 = nullptr;           // [n_e]
   double *w_lbS = nullptr, *w_lbY = nullptr;  // [lbfgs_m][n_v*dim] L-BFGS pairs (allocated on first use)
   int lbfgs_alloc_m = 0;
@@ -77,6 +86,8 @@ struct isb_ctx {
   isb::CgScal* scal = nullptr;      // device CG scalars
   double* hscal = nullptr;          // pinned host mirror of dscal
   isb::CgScal* hcg = nullptr;       // pinned host mirror of scal
+  isb::CgScal* hcg_ring = nullptr;  // [2] pinned copies of scal taken after alternate CG batches
+  hipEvent_t cg_ev[2] = {nullptr, nullptr};  // completion of the copy into hcg_ring[k]
 
   // batched-solver state (owned by the batched solver); batched64: the FP64 state of the mixed
   // solver's fallback, prepared on first use

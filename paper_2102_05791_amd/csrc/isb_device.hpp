@@ -52,10 +52,31 @@ __device__ __forceinline__ void load_conn(const DevMesh& m, int e, int v[D + 1])
   for (int k = 0; k <= D; ++k) v[k] = m.conn[(size_t)k * m.n_e + e];
 }
 
-template <int D, typename T>
+// Rest data of element e in the element precision T. CR: the compact record (m.axis >= 0): Dm^-1 and
+// W only, the W-scaled material from the mesh's uniform scalars and the fibre vector Dm^-1 d = column
+// m.axis of Dm^-1 (in FP64 the same values the general record holds).
+template <int D, typename T, bool CR = false>
 __device__ __forceinline__ void load_rest(const DevMesh& m, int e, ElemRest<D, T>& R) {
   const size_t ne = (size_t)m.n_e;
-  if constexpr (std::is_same<T, double>::value) {
+  if constexpr (CR) {
+    constexpr bool F64 = std::is_same<T, double>::value;
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+#pragma unroll
+      for (int c = 0; c < D; ++c)
+        R.Dinv[j][c] = F64 ? T(m.Dinv[(size_t)(j * D + c) * ne + e]) : T(m.Dinv32[(size_t)(j * D + c) * ne + e]);
+    const T w = F64 ? T(m.W[e]) : T(m.W32[e]);
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      T g = R.Dinv[j][0];
+#pragma unroll
+      for (int c = 1; c < D; ++c) g = m.axis == c ? R.Dinv[j][c] : g;
+      R.gf[j] = g;
+    }
+    R.wmu = w * T(m.mu_u);
+    R.wlam = w * T(m.lam_u);
+    R.wkf = w * T(m.kf_u);
+  } else if constexpr (std::is_same<T, double>::value) {
 #pragma unroll
     for (int j = 0; j < D; ++j) {
 #pragma unroll

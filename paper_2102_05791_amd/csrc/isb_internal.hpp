@@ -28,6 +28,13 @@ struct DevMesh {
   const double* mass;
   const uint8_t* pinned;
   int model;  // isotropic energy model (EM_* of isb_elem.hpp, ISB_ENERGY_* of the C ABI)
+  // Compact rest record: when every element has the same (mu, lam, k_f) and its fibre along the
+  // coordinate axis `axis`, kernels with a compact variant read only Dm^-1 and W per element (W32 in
+  // FP32 element math) and form W mu, W lam, W k_f from the scalars below and Dm^-1 d as column
+  // `axis` of Dm^-1. axis < 0: the general per-element record.
+  int axis;
+  double mu_u, lam_u, kf_u;
+  const float* W32;
 };
 
 // Vertex-pair springs, SoA over the caller's spring order:
@@ -62,6 +69,7 @@ struct PatchPlan {
   const int32_t* verts;   // distinct vertices of each patch, sorted
   const uint16_t* lconn;  // [(D+1)][n_e] corner index into the patch's vertex list
   int max_nv;             // largest vertex list
+  int block;              // threads per patch workgroup: 256, 512 or 1024 (0: the default)
 };
 
 constexpr int kPatchBlock = 512;        // threads per patch workgroup (FP32 element math; FP64 takes half)
@@ -84,7 +92,10 @@ struct CgScal {
   int it_cur;      // the iteration in progress
   int max_it;      // iteration cap
   int pad;
+  double alpha_prev, gamma_prev;  // single-reduction CG: alpha and r.u of the previous iteration
 };
+
+constexpr int kMaxPatchGrid = 65535;  // workgroups of one patch launch (grid-stride beyond)
 
 // ---- precompute ----
 void launch_precompute_geom(int D, int n_e, const double* X, const int32_t* conn, double* Dinv, double* W,
@@ -131,10 +142,20 @@ void launch_elem_minmax_J(const DevMesh& m, ERange r, const double* x, double* p
                           int* nblocks_out);
 void launch_to_f32(int n, const double* src, float* dst, hipStream_t s);
 // LDS-staged scatter over patches [p0, p1): op = PatchOp; p is the Hessian-vector operand (HV only);
-// out receives one global atomic add per distinct vertex DOF of each patch
-void launch_elem_patch(const DevMesh& m, const DevScene& sc, const PatchPlan& P, int p0, int p1, int op,
-                       int precision, const double* x, const double* a, const float* a32, const double* p,
-                       double* out, const int* done, hipStream_t s);
+// out receives one global atomic add per distinct vertex DOF of each patch. curv (HV only, may be
+// null): per-workgroup partials of p^T H_elem p (s_pot-scaled). Returns the number of workgroups.
+int launch_elem_patch(const DevMesh& m, const DevScene& sc, const PatchPlan& P, int p0, int p1, int op,
+                      int precision, const double* x, const double* a, const float* a32, const double* p,
+                      double* out, const int* done, hipStream_t s, double* curv = nullptr);
+
+// single-reduction PCG over the patch Hessian-vector kernel (partials: 6 x kMaxRedBlocks values)
+void launch_cgcg_start(int n, const double* b, double sign, const double* Dinvp, const double* vdiag, double* r,
+                       double* u, double* w, double* p, double* sv, double* xs, double* partials, CgScal* scal,
+                       double tol2, int max_it, hipStream_t s);
+void launch_cgcg_vec(int n, const double* hvpart, int nhv, double* partials, const double* Dinvp,
+                     const double* vdiag, double* r, double* u, double* w, double* p, double* sv, double* xs,
+                     CgScal* scal, hipStream_t s);
+void launch_cgcg_final(int n, const double* partials, CgScal* scal, hipStream_t s);
 
 // ---- spring kernels (isb_springs.hip): spring range r (ids through r.list when given); as = the
 // springs' actions (the action vector past the elements' entries); op = PatchOp; FP64 throughout ----

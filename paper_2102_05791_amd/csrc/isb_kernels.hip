@@ -8,6 +8,7 @@
 // order, so every sum is deterministic.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "isb_device.hpp"
@@ -960,24 +961,189 @@ void launch_min_count(int n, const double* a, double* partials, double* out, hip
 }
 
 // ---------------------------------------------------------------------------------------------
+// single-reduction PCG (Chronopoulos and Gear's s = 1 form) for the LDS-staged patch scatter
+// ---------------------------------------------------------------------------------------------
+// Vectors: r (residual), u = M r (M = D^-1), w = H u, p, s = H p, xs. Per iteration the patch
+// Hessian-vector kernel adds the element part of H u into w (which holds the vertex part vdiag u)
+// and leaves per-workgroup partials of u^T H_elem u; then k_cgcg_vec forms every scalar from one set
+// of partials: gamma = r.u, delta = u.H u, and r.r for the stop test, and updates
+//   beta = gamma / gamma_prev, p^T H p = delta - beta gamma / alpha_prev, alpha = gamma / p^T H p,
+//   p = u + beta p, s = w + beta s, xs += alpha p, r -= alpha s, u = M r, w = vdiag u,
+// writing the partials of the new (gamma, r.r, u^T vdiag u). Two launches per iteration instead of
+// four; the partials alternate between two banks of 3 x kMaxRedBlocks values by iteration parity.
+
+// r = b (masked), u = M r, w = vdiag u, p = s = xs = 0; bank-0 partials (r.u, r.r, u.vdiag u)
+__global__ void __launch_bounds__(kBlock) k_cgcg_start(int n, const double* __restrict__ b, double sign,
+                                                       const double* __restrict__ Dinvp,
+                                                       const double* __restrict__ vdiag, double* r, double* u,
+                                                       double* w, double* p, double* sv, double* xs,
+                                                       double* partials) {
+  __shared__ double sh[kBlock / 64];
+  double g = 0.0, rr = 0.0, dv = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const double ri = Dinvp[i] != 0.0 ? sign * b[i] : 0.0;
+    const double ui = Dinvp[i] * ri;
+    const double wi = vdiag[i] * ui;
+    r[i] = ri;
+    u[i] = ui;
+    w[i] = wi;
+    p[i] = 0.0;
+    sv[i] = 0.0;
+    xs[i] = 0.0;
+    g += ri * ui;
+    rr += ri * ri;
+    dv += ui * wi;
+  }
+  g = block_sum(g, sh);
+  rr = block_sum(rr, sh);
+  dv = block_sum(dv, sh);
+  if (threadIdx.x == 0) {
+    partials[3 * blockIdx.x] = g;
+    partials[3 * blockIdx.x + 1] = rr;
+    partials[3 * blockIdx.x + 2] = dv;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_cgcg_start_fin(const double* __restrict__ partials, int nb,
+                                                           CgScal* scal, double tol2, int max_it) {
+  __shared__ double sh[kBlock / 64 + 1];
+  const double rr = all_blocks_sum(partials, nb, 3, 1, sh);
+  if (threadIdx.x == 0) {
+    scal->rr = rr;
+    scal->rr0 = rr;
+    scal->pHp = 0.0;
+    scal->tol2 = tol2;
+    scal->max_it = max_it;
+    scal->done = (rr <= tol2 || max_it <= 0) ? 1 : 0;
+    scal->negcurv = 0;
+    scal->iters = 0;
+    scal->it_cur = 0;
+    scal->alpha_prev = 0.0;
+    scal->gamma_prev = 0.0;
+  }
+}
+
+// iteration it: the partials of r_it, u_it (bank it & 1) and the Hessian-vector kernel's nhv partials
+// of u_it^T H_elem u_it give alpha_it and beta_it; then the update to iterate it + 1
+__global__ void __launch_bounds__(kBlock) k_cgcg_vec(int n, int nb, const double* __restrict__ hvpart, int nhv,
+                                                     double* partials, const double* __restrict__ Dinvp,
+                                                     const double* __restrict__ vdiag, double* r, double* u,
+                                                     double* w, double* p, double* sv, double* xs, CgScal* scal) {
+  if (scal->done) return;
+  const int it = scal->iters;
+  const double* prev = partials + (it & 1) * 3 * kMaxRedBlocks;
+  double* next = partials + ((it + 1) & 1) * 3 * kMaxRedBlocks;
+  __shared__ double sh[kBlock / 64 + 1];
+  const double gamma = all_blocks_sum(prev, nb, 3, 0, sh);
+  const double rr = all_blocks_sum(prev, nb, 3, 1, sh);
+  const double delta = all_blocks_sum(prev, nb, 3, 2, sh) + all_blocks_sum(hvpart, nhv, 1, 0, sh);
+  if (rr <= scal->tol2) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      scal->done = 1;
+      scal->rr = rr;
+    }
+    return;
+  }
+  const double beta = it == 0 ? 0.0 : gamma / scal->gamma_prev;
+  const double pHp = it == 0 ? delta : delta - beta * gamma / scal->alpha_prev;
+  if (!(pHp > 0.0)) {
+    // non-positive curvature: stop; on the first iteration return the preconditioned
+    // steepest-descent direction p0 = u0 = D^-1 b (Nocedal & Wright, Alg. 7.1)
+    if (it == 0)
+      for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) xs[i] = u[i];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      scal->negcurv = 1;
+      scal->done = 1;
+      scal->pHp = pHp;
+      scal->rr = rr;
+    }
+    return;
+  }
+  const double alpha = gamma / pHp;
+  double g = 0.0, rn = 0.0, dv = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const double di = Dinvp[i], vi = vdiag[i];
+    const double pi = u[i] + beta * p[i];
+    const double si = w[i] + beta * sv[i];
+    xs[i] += alpha * pi;
+    const double ri = di != 0.0 ? r[i] - alpha * si : 0.0;
+    const double ui = di * ri;
+    const double wi = vi * ui;
+    p[i] = pi;
+    sv[i] = si;
+    r[i] = ri;
+    u[i] = ui;
+    w[i] = wi;
+    g += ri * ui;
+    rn += ri * ri;
+    dv += ui * wi;
+  }
+  g = block_sum(g, sh);
+  rn = block_sum(rn, sh);
+  dv = block_sum(dv, sh);
+  if (threadIdx.x == 0) {
+    next[3 * blockIdx.x] = g;
+    next[3 * blockIdx.x + 1] = rn;
+    next[3 * blockIdx.x + 2] = dv;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    scal->gamma_prev = gamma;
+    scal->alpha_prev = alpha;
+    scal->pHp = pHp;
+    scal->rr = rr;
+    scal->iters = it + 1;
+    if (it + 1 >= scal->max_it) scal->done = 1;  // the cap: k_cgcg_final reports the last r.r
+  }
+}
+
+// r.r of the final iterate (the partials of bank iters & 1, written by the last update or the start)
+__global__ void __launch_bounds__(kBlock) k_cgcg_final(const double* __restrict__ partials, int nb, CgScal* scal) {
+  __shared__ double sh[kBlock / 64 + 1];
+  const int it = scal->iters;
+  const double rr = all_blocks_sum(partials + (it & 1) * 3 * kMaxRedBlocks, nb, 3, 1, sh);
+  if (threadIdx.x == 0) scal->rr = rr;
+}
+
+void launch_cgcg_start(int n, const double* b, double sign, const double* Dinvp, const double* vdiag, double* r,
+                       double* u, double* w, double* p, double* sv, double* xs, double* partials, CgScal* scal,
+                       double tol2, int max_it, hipStream_t s) {
+  const int nb = red_blocks(n);
+  k_cgcg_start<<<nb, kBlock, 0, s>>>(n, b, sign, Dinvp, vdiag, r, u, w, p, sv, xs, partials);
+  k_cgcg_start_fin<<<1, kBlock, 0, s>>>(partials, nb, scal, tol2, max_it);
+}
+void launch_cgcg_vec(int n, const double* hvpart, int nhv, double* partials, const double* Dinvp,
+                     const double* vdiag, double* r, double* u, double* w, double* p, double* sv, double* xs,
+                     CgScal* scal, hipStream_t s) {
+  const int nb = red_blocks(n);
+  k_cgcg_vec<<<nb, kBlock, 0, s>>>(n, nb, hvpart, nhv, partials, Dinvp, vdiag, r, u, w, p, sv, xs, scal);
+}
+void launch_cgcg_final(int n, const double* partials, CgScal* scal, hipStream_t s) {
+  k_cgcg_final<<<1, kBlock, 0, s>>>(partials, red_blocks(n), scal);
+}
+
+// ---------------------------------------------------------------------------------------------
 // LDS-staged scatter over element patches
 // ---------------------------------------------------------------------------------------------
 // One workgroup per patch (grid-stride over patches): stage x (and p) of the patch's distinct
 // vertices in LDS, evaluate the elements with LDS gathers and accumulate with LDS atomics, then
 // add each distinct vertex DOF to the global output once. Global atomics drop from d(d+1) per
 // element to the patch's distinct DOFs, and they no longer collide inside a wavefront.
-template <int D, typename T, int OP, int PB, int EM>
+// CR: compact rest record (uniform material, fibre along an axis; see DevMesh)
+template <int D, typename T, int OP, int PB, int EM, bool CR>
 __global__ void __launch_bounds__(PB) k_elem_patch(DevMesh m, DevScene sc, PatchPlan P, int p0, int p1,
                                                             const double* __restrict__ x,
                                                             const double* __restrict__ a,
                                                             const float* __restrict__ a32,
                                                             const double* __restrict__ pv, double* out,
-                                                            const int* done) {
+                                                            const int* done, double* curv) {
   // LDS: x, the accumulator and the Hessian-vector operand p per patch DOF, all FP64 (the element
   // takes differences of x and of p, which must be formed before any rounding to T), then the
   // global id of each patch vertex, so that the flush needs no second load of the vertex list
   extern __shared__ double lds[];
   if (OP == PATCH_HV && done && *done) return;
+  // curv (Hessian-vector products only): this workgroup's share of p^T H_elem p, the sum over its
+  // elements of p_e . (H_e p_e), for a CG that needs no separate dot-product pass
+  double php = 0.0;
   const int nmax = P.max_nv * D;
   double* xs = lds;
   double* acc = lds + nmax;
@@ -1004,7 +1170,7 @@ __global__ void __launch_bounds__(PB) k_elem_patch(DevMesh m, DevScene sc, Patch
 #pragma unroll
       for (int k = 0; k <= D; ++k) l[k] = P.lconn[(size_t)k * m.n_e + e];
       ElemRest<D, T> R;
-      load_rest<D, T>(m, e, R);
+      load_rest<D, T, CR>(m, e, R);
       T Ds[D][D];
 #pragma unroll
       for (int j = 0; j < D; ++j)
@@ -1024,6 +1190,13 @@ __global__ void __launch_bounds__(PB) k_elem_patch(DevMesh m, DevScene sc, Patch
 #pragma unroll
           for (int c = 0; c < D; ++c) dDs[c][j] = T(ps[l[j + 1] * D + c] - ps[l[0] * D + c]);
         elem_hessvec<D, T, EM>(R, S, ae, dDs, o);
+        if (curv) {
+          // p_e . (H_e p_e) = sum_j o_{j+1} . (p_{j+1} - p_0), since o_0 = -sum_j o_{j+1}
+#pragma unroll
+          for (int j = 0; j < D; ++j)
+#pragma unroll
+            for (int c = 0; c < D; ++c) php += double(o[j + 1][c]) * (ps[l[j + 1] * D + c] - ps[l[0] * D + c]);
+        }
       } else {
         elem_hessdiag<D, T, EM>(R, S, ae, o);
       }
@@ -1039,37 +1212,67 @@ __global__ void __launch_bounds__(PB) k_elem_patch(DevMesh m, DevScene sc, Patch
     }
     __syncthreads();
   }
+  if (OP == PATCH_HV && curv) {
+    double* red = lds;  // free after the last flush (the launch sizes LDS to hold PB / 64 values)
+    php = wave_sum(php);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = php;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int w = 0; w < PB / 64; ++w) t += red[w];
+      curv[blockIdx.x] = sc.s_pot * t;
+    }
+  }
 }
 
 template <int D, typename T, int OP>
-static void patch_launch(const DevMesh& m, const DevScene& sc, const PatchPlan& P, int p0, int p1, const double* x,
-                         const double* a, const float* a32, const double* p, double* out, const int* done,
-                         hipStream_t s) {
-  const size_t lds = (size_t)P.max_nv * (D * sizeof(double) * (OP == PATCH_HV ? 3 : 2) + sizeof(int));
+static int patch_launch(const DevMesh& m, const DevScene& sc, const PatchPlan& P, int p0, int p1, const double* x,
+                        const double* a, const float* a32, const double* p, double* out, const int* done,
+                        double* curv, hipStream_t s) {
+  const size_t lds = std::max<size_t>((size_t)P.max_nv * (D * sizeof(double) * (OP == PATCH_HV ? 3 : 2) + sizeof(int)),
+                                      (1024 / 64) * sizeof(double));
   int grid = p1 - p0;
-  if (grid > 65535) grid = 65535;
-  // FP64 element math needs about twice the registers of FP32: 256-thread workgroups keep more of
-  // them resident per CU than 512-thread ones would
-  constexpr int PB = std::is_same<T, float>::value ? kPatchBlock : kPatchBlock / 2;
-  with_model(m.model, [&](auto em) {
+  if (grid > kMaxPatchGrid) grid = kMaxPatchGrid;
+  // workgroup size: P.block when it names a compiled size (the neo-Hookean kernels come in 256, 512
+  // and 1024 threads, the alternative models in the default only), else the default: 512 threads
+  // for FP32 element math, 256 for FP64. The kernels are bound by LDS traffic (gathers and FP64
+  // atomics) at about three patches per CU: larger workgroups only add contention.
+  constexpr int kDefault = std::is_same<T, float>::value ? kPatchBlock : kPatchBlock / 2;
+  const int pb = (m.model == EM_NH && (P.block == 256 || P.block == 512 || P.block == 1024)) ? P.block : kDefault;
+  auto go = [&](auto pbc, auto em) {
+    constexpr int PB = decltype(pbc)::value;
     constexpr int EM = decltype(em)::value;
-    k_elem_patch<D, T, OP, PB, EM><<<grid, PB, lds, s>>>(m, sc, P, p0, p1, x, a, a32, p, out, done);
-  });
+    if (m.axis >= 0)
+      k_elem_patch<D, T, OP, PB, EM, true><<<grid, PB, lds, s>>>(m, sc, P, p0, p1, x, a, a32, p, out, done, curv);
+    else
+      k_elem_patch<D, T, OP, PB, EM, false><<<grid, PB, lds, s>>>(m, sc, P, p0, p1, x, a, a32, p, out, done, curv);
+  };
+  if (m.model != EM_NH) {
+    with_model(m.model, [&](auto em) { go(std::integral_constant<int, kDefault>{}, em); });
+  } else if (pb == 256) {
+    go(std::integral_constant<int, 256>{}, std::integral_constant<int, EM_NH>{});
+  } else if (pb == 1024) {
+    go(std::integral_constant<int, 1024>{}, std::integral_constant<int, EM_NH>{});
+  } else {
+    go(std::integral_constant<int, 512>{}, std::integral_constant<int, EM_NH>{});
+  }
+  return grid;
 }
 
-void launch_elem_patch(const DevMesh& m, const DevScene& sc, const PatchPlan& P, int p0, int p1, int op,
-                       int precision, const double* x, const double* a, const float* a32, const double* p,
-                       double* out, const int* done, hipStream_t s) {
-  if (p1 <= p0) return;
+int launch_elem_patch(const DevMesh& m, const DevScene& sc, const PatchPlan& P, int p0, int p1, int op,
+                      int precision, const double* x, const double* a, const float* a32, const double* p,
+                      double* out, const int* done, hipStream_t s, double* curv) {
+  if (p1 <= p0) return 0;
+  if (op != PATCH_HV) curv = nullptr;
 #define ISB_PATCH_CASE(D_)                                                                          \
   if (op == PATCH_GRAD)                                                                             \
-    patch_launch<D_, double, PATCH_GRAD>(m, sc, P, p0, p1, x, a, a32, p, out, done, s);             \
+    return patch_launch<D_, double, PATCH_GRAD>(m, sc, P, p0, p1, x, a, a32, p, out, done, curv, s);  \
   else if (op == PATCH_HV && precision)                                                             \
-    patch_launch<D_, float, PATCH_HV>(m, sc, P, p0, p1, x, a, a32, p, out, done, s);                \
+    return patch_launch<D_, float, PATCH_HV>(m, sc, P, p0, p1, x, a, a32, p, out, done, curv, s);     \
   else if (op == PATCH_HV)                                                                          \
-    patch_launch<D_, double, PATCH_HV>(m, sc, P, p0, p1, x, a, a32, p, out, done, s);               \
+    return patch_launch<D_, double, PATCH_HV>(m, sc, P, p0, p1, x, a, a32, p, out, done, curv, s);    \
   else                                                                                              \
-    patch_launch<D_, double, PATCH_DIAG>(m, sc, P, p0, p1, x, a, a32, p, out, done, s);
+    return patch_launch<D_, double, PATCH_DIAG>(m, sc, P, p0, p1, x, a, a32, p, out, done, curv, s);
   if (m.dim == 2) {
     ISB_PATCH_CASE(2)
   } else {

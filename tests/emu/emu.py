@@ -26,7 +26,8 @@ vp, ci, cd = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
 class DevMesh(ctypes.Structure):
     _fields_ = [("dim", ci), ("n_v", ci), ("n_e", ci), ("conn", vp), ("Dinv", vp), ("gf", vp), ("W", vp),
                 ("wmu", vp), ("wlam", vp), ("wkf", vp), ("Dinv32", vp), ("gf32", vp), ("wmu32", vp),
-                ("wlam32", vp), ("wkf32", vp), ("mass", vp), ("pinned", vp), ("model", ci)]
+                ("wlam32", vp), ("wkf32", vp), ("mass", vp), ("pinned", vp), ("model", ci), ("axis", ci),
+                ("mu_u", cd), ("lam_u", cd), ("kf_u", cd), ("W32", vp)]
 
 
 class DevScene(ctypes.Structure):
@@ -62,6 +63,23 @@ def build():
 
 def _p(a):
     return a.ctypes.data_as(vp)
+
+
+def compact_axis(w):
+    """The library's test for the compact rest record: one (mu, lam, k_f) for every element and every
+    fibre along one coordinate axis; returns that axis, or -1."""
+    if w.n_e == 0:
+        return -1
+    d0 = w.fdir[0]
+    axes = [k for k in range(w.dim) if d0[k] == 1.0]
+    if not axes:
+        return -1
+    ax = axes[-1]
+    unit = np.zeros(w.dim)
+    unit[ax] = 1.0
+    same = (np.all(w.mu == w.mu[0]) and np.all(w.lam == w.lam[0]) and np.all(w.kf == w.kf[0])
+            and np.all(w.fdir == unit))
+    return ax if same else -1
 
 
 class EmuBatch:
@@ -104,7 +122,8 @@ class EmuBatch:
         self.m = DevMesh(d, w.n_v, w.n_e, _p(self.conn), _p(self.Dinv), _p(self.gf), _p(self.W), _p(self.wmu),
                          _p(self.wlam), _p(self.wkf), _p(f32(self.Dinv)), _p(f32(self.gf)), _p(f32(self.wmu)),
                          _p(f32(self.wlam)), _p(f32(self.wkf)), _p(self.mass), _p(self.pinned),
-                         {"nh": 0, "stvk": 1, "corot": 2, "snh": 3}[getattr(w, "model", "nh")])
+                         {"nh": 0, "stvk": 1, "corot": 2, "snh": 3}[getattr(w, "model", "nh")],
+                         compact_axis(w), float(w.mu[0]), float(w.lam[0]), float(w.kf[0]), _p(f32(self.W)))
         sc = w.scene
         be = sc["integrator"] == "be"
         self.sc = DevScene(int(be), sc["h"], sc["h"] ** 2 if be else 1.0, sc["gravity"], sc["k_contact"],

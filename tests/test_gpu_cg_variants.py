@@ -1,0 +1,140 @@
+"""The plain solver's CG forms and the compact rest record on bodies large enough for the LDS-staged
+patch scatter (>= 16,384 elements), through the C ABI against the FP64 oracle:
+
+* single-reduction PCG (Chronopoulos and Gear: the patch Hessian-vector kernel returns its share of
+  u^T H u, one vector kernel per iteration) against the classic four-kernel PCG and the oracle, for
+  the step (Eq. 14) and the adjoint (Eq. 9), in FP64 and mixed precision, eager and as replayed
+  graph chunks;
+* the compact rest record (uniform material, fibres along one axis: Dm^-1 and W per element, the
+  material from scalars) against the general per-element record, in the patch kernels' gradient,
+  Hessian-vector product and diagonal and in whole solves."""
+import numpy as np
+import pytest
+
+from oracle import solve
+from synth import meshes, scenes
+from synth.scenes import Workload
+from tests.gpu_util import problems, rand_workload, rel, rel_inf
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda:0")
+
+
+def _ctx(w, precision, **opts):
+    from paper_2102_05791_amd import Context, isb
+    ctx = Context.from_workload(w, precision=precision, scatter=2, solver=0)
+    for k, v in opts.items():
+        ctx.set_option(getattr(isb, "OPT_" + k.upper()), v)
+    return ctx
+
+
+def _uniform_block(nx=16, ny=16, nz=11, seed=91):
+    """A Kuhn-tet block with one material and fibres along x (the compact record applies), resting
+    above the ground with a random velocity, 16,896 tets."""
+    X, T = meshes.tet_grid(nx, ny, nz)
+    rng = np.random.default_rng([20210211, 3, seed])
+    n_e = T.shape[0]
+    mu, lam = scenes.lame(1e5, 0.45)
+    x0 = X + 0.01 * rng.normal(size=X.shape)
+    x0[:, 1] -= 0.02
+    return Workload("uniform_block", 3, X, T, np.zeros(X.shape, np.uint8), np.full(n_e, mu), np.full(n_e, lam),
+                    np.full(n_e, 1e5), meshes.x_fibres(n_e, 3), np.ones(n_e), scenes.scene("be", h=1.0 / 30.0),
+                    x0, 0.3 * rng.normal(size=X.shape), meshes.contraction_actuation(rng, (2, n_e))), rng
+
+
+def _bodies():
+    w3, r3 = rand_workload(3, seed=92, shape=(16, 16, 11))      # per-element material: general record
+    w2, r2 = rand_workload(2, seed=93, shape=(130, 65))        # 16,900 triangles
+    wu, ru = _uniform_block()
+    return {"3d-general": (w3, r3), "2d-general": (w2, r2), "3d-compact": (wu, ru)}
+
+
+@pytest.fixture(scope="module")
+def oracle_refs():
+    out = {}
+    for name, (w, rng) in _bodies().items():
+        w.scene.update(tol_rel=1e-13, adj_tol_rel=1e-13, max_newton=60, max_cg=6000)
+        p = problems(w)[0]
+        a = w.actions[0]
+        xr, vr, _ = solve.step(p, w.x0, w.v0, a, tol=1e-13)
+        xbar = rng.normal(size=xr.shape)
+        wr = solve.adjoint(p, xr, w.x0, a, xbar)
+        out[name] = (w, a, xr, vr, xbar, wr)
+    return out
+
+
+@pytest.mark.parametrize("body", ["3d-general", "2d-general", "3d-compact"])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 1e-5)])
+def test_single_reduction_cg_matches_classic_and_oracle(oracle_refs, body, precision, tol):
+    from paper_2102_05791_amd import isb
+    w, a, xr, vr, xbar, wr = oracle_refs[body]
+    res = {}
+    for single in (1, 0):
+        ctx = _ctx(w, precision, cg_single_reduction=single)
+        assert ctx.get_option(isb.OPT_CG_SINGLE_REDUCTION) == single
+        assert ctx.get_option(isb.INFO_COMPACT_AXIS) == (0 if body == "3d-compact" else -1)
+        x1, v1, st, _ = ctx.step(_dev(w.x0), _dev(w.v0), _dev(a))
+        wv, sa, _ = ctx.solve_adjoint(_dev(xr), _dev(w.x0), _dev(a), _dev(xbar))
+        res[single] = (x1.cpu().numpy(), v1.cpu().numpy(), wv.cpu().numpy(), st[0], sa[0])
+        x1, v1, wv = res[single][:3]
+        print(body, precision, "single" if single else "classic", st[0]["newton_iters"], st[0]["cg_iters"],
+              sa[0]["adj_cg_iters"], "errors", rel(x1 - w.x0, xr - w.x0), rel(wv, wr))
+        assert st[0]["flags"] & (isb.FLAG_CONVERGED | isb.FLAG_STAGNATED)
+        assert sa[0]["flags"] & isb.FLAG_ADJ_CONVERGED
+        assert rel(x1 - w.x0, xr - w.x0) <= tol and rel_inf(x1 - w.x0, xr - w.x0) <= tol
+        assert rel(v1, vr) <= tol
+        assert rel(wv, wr) <= tol and rel_inf(wv, wr) <= tol
+    # the same iterates in exact arithmetic: iteration counts agree up to rounding
+    s1, s0 = res[1][3]["cg_iters"], res[0][3]["cg_iters"]
+    assert abs(s1 - s0) <= 0.1 * s0 + 5
+    a1, a0 = res[1][4]["adj_cg_iters"], res[0][4]["adj_cg_iters"]
+    assert abs(a1 - a0) <= 0.1 * a0 + 5
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 1e-7)])
+def test_single_reduction_cg_graph_chunks(oracle_refs, precision, tol):
+    """The single-reduction CG captured as graph chunks of 8 iterations and replayed: the same
+    kernels in the same order as eager launches (the patch atomics may add in another order)."""
+    w, a, xr, vr, xbar, wr = oracle_refs["3d-compact"]
+    outs = []
+    for graph in (0, 1):
+        ctx = _ctx(w, precision, cg_graph=graph)
+        x1, v1, st, _ = ctx.step(_dev(w.x0), _dev(w.v0), _dev(a))
+        wv, sa, _ = ctx.solve_adjoint(x1, _dev(w.x0), _dev(a), _dev(xbar))
+        outs.append((x1.cpu().numpy(), wv.cpu().numpy(), st[0]["cg_iters"], sa[0]["adj_cg_iters"]))
+    assert rel(outs[1][0] - w.x0, outs[0][0] - w.x0) <= tol
+    assert rel(outs[1][1], outs[0][1]) <= 1e3 * tol
+    assert abs(outs[1][2] - outs[0][2]) <= 0.05 * outs[0][2] + 3
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 1e-6)])
+def test_compact_rest_record_matches_general(precision, tol):
+    """Patch gradient, Hessian-vector product and diagonal, and a whole step, with the compact record
+    and with the general one on the same uniform body."""
+    from paper_2102_05791_amd import isb
+    w, rng = _uniform_block(seed=94)
+    w.scene.update(tol_rel=1e-12, max_newton=60, max_cg=6000)
+    x = w.x0 + 0.03 * rng.normal(size=w.x0.shape)
+    pv = rng.normal(size=x.shape)
+    a = w.actions[0]
+    out = {}
+    for compact in (1, 0):
+        ctx = _ctx(w, precision, compact_rest=compact)
+        assert ctx.get_option(isb.INFO_COMPACT_AXIS) == (0 if compact else -1)
+        g = ctx.gradient(_dev(x), _dev(w.x0), _dev(w.v0), _dev(a)).cpu().numpy()
+        hp = ctx.hessvec(_dev(x), _dev(w.x0), _dev(a), _dev(pv)).cpu().numpy()
+        hd = ctx.hessdiag(_dev(x), _dev(w.x0), _dev(a)).cpu().numpy()
+        x1, _, st, _ = ctx.step(_dev(w.x0), _dev(w.v0), _dev(a))
+        out[compact] = (g, hp, hd, x1.cpu().numpy())
+    for k, name in enumerate(("gradient", "hessvec", "hessdiag")):
+        print(name, rel(out[1][k], out[0][k]))
+        assert rel(out[1][k], out[0][k]) <= (1e-13 if name != "hessvec" else tol)
+    assert rel(out[1][3] - w.x0, out[0][3] - w.x0) <= (1e-9 if precision == "fp64" else 1e-5)
+    p = problems(w)[0]
+    H = p.hessian(x, w.x0, a)
+    assert rel(out[1][1].ravel(), H @ pv.ravel(), abs(H) @ np.abs(pv.ravel())) <= (1e-12 if precision == "fp64"
+                                                                                    else 2e-6)
