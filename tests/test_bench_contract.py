@@ -19,8 +19,8 @@ def test_more_than_one_gpu_is_refused_with_a_message():
 
 
 def test_element_byte_model():
-    # 3D element Hessian-vector product: connectivity 16 B, Dm^-1 (9), gf (3), W mu, W lam, W k_f,
-    # actuation: 144 B in FP64; 80 + the FP64 actuation's extra 4 B = 84 B mixed
+    # the general per-element record of a tetrahedron: connectivity 16 B, Dm^-1 (9), gf (3), W mu,
+    # W lam, W k_f, actuation: 144 B in FP64; 80 + the FP64 actuation's extra 4 B = 84 B mixed
     assert bench.elem_bytes(3, 8) == 144
     assert bench.elem_bytes(3, 4) + 4 == 84
     assert bench.elem_bytes(2, 8) == 4 * 3 + 8 * (4 + 2 + 3 + 1)
@@ -47,3 +47,39 @@ def test_traffic_record_is_ignored_for_other_sources(tmp_path, monkeypatch):
     rec["source_hash"] = "0" * 64
     f.write_text("traffic-record: " + json.dumps(rec) + "\n")
     assert bench.measured_traffic(0) is None
+
+
+def test_octile_pick_takes_equal_shares_of_each_size_octile():
+    import numpy as np
+    sizes = np.random.default_rng(0).integers(128, 8193, size=512)
+    pick = bench.octile_pick(sizes, 64)
+    assert len(pick) == 64 and len(set(pick.tolist())) == 64
+    order = np.argsort(sizes, kind="stable")
+    rank = np.empty(512, int)
+    rank[order] = np.arange(512)
+    assert np.array_equal(np.bincount(rank[pick] // 64, minlength=8), np.full(8, 8))
+
+
+def test_bench_reference_matches_the_workloads_it_was_written_for():
+    """The stored oracle results bench.py compares against: one per leg, for the workloads the bench
+    builds (same vertex counts), with sampled vertices inside each body."""
+    from synth import scenes
+    g = bench.golden()
+    w = scenes.batched_strips(512, steps=1)
+    for ref in g["batched_strips_512"]:
+        b = ref["body"]
+        assert ref["n_v"] == w.body_v_off[b + 1] - w.body_v_off[b]
+        assert max(ref["vertices"]) < ref["n_v"] and len(ref["x1"]) == len(ref["vertices"])
+    assert set(g["energies"]) == {"stvk", "corot", "snh"}
+    assert g["be_strip_64x16_5_steps"]["steps"] == 5
+    assert g["policy_strip_64x16"]["horizon"] == 100 and g["policy_strip_64x16"]["grad_norm"] > 0
+
+
+def test_sampled_error_is_relative_to_the_displacement():
+    import numpy as np
+    x0 = np.zeros((10, 2))
+    ref = {"vertices": [1, 3], "x1": [[1.0, 0.0], [0.0, 1.0]]}
+    x = x0.copy()
+    x[1] = [1.0, 0.0]
+    x[3] = [0.0, 1.001]
+    assert abs(bench.sampled_error(x, ref, x0) - 0.001 / np.sqrt(2.0)) < 1e-15
