@@ -761,6 +761,31 @@ static isb_status plain_adjoint(isb_ctx* c, hipStream_t s, const double* x1, con
         launch_axpy(br.n, c->w_G + br.off, -1.0, c->w_Hp + br.off, s);
       }
       ISB_TRY(run_cg(c, b, x1, a, c->w_G, 1.0, c->scene.adj_tol_rel * bnorm, c->scene.max_cg, s, &iters, &neg, &rr));
+      if (!neg && c->precision == ISB_MIXED && single_reduction_cg(c, b)) {
+        // The single-reduction CG carries H p in a recurrence (s = w + beta s), in which the FP32
+        // operator's rounding accumulates: its recursive residual can fall below the tolerance before
+        // the true one does. Check the true residual G - H xs once and, if it is too large, solve for
+        // the correction from there (the adjoint is the solve whose accuracy the gradient inherits).
+        double* xs0 = c->w_Gt;
+        double* rt = c->w_xt;
+        launch_copy(br.n, c->w_xs + br.off, xs0 + br.off, s);
+        launch_mul(br.n, c->w_vdiag + br.off, xs0 + br.off, c->w_Hp + br.off, s);
+        elem_scatter(c, b, PATCH_HV, x1, a, xs0, c->w_Hp, nullptr, s, c->w_a32);
+        launch_mask(m, br.v0, br.v1, c->w_Hp, s);
+        launch_copy(br.n, c->w_G + br.off, rt + br.off, s);
+        launch_axpy(br.n, rt + br.off, -1.0, c->w_Hp + br.off, s);
+        enqueue_norm2(c, b, rt, 0, s);
+        ISB_TRY(read_scal(c, s, 1));
+        const double true_res = std::sqrt(c->hscal[0]);
+        if (true_res > c->scene.adj_tol_rel * bnorm) {
+          int it2 = 0;
+          ISB_TRY(run_cg(c, b, x1, a, rt, 1.0, c->scene.adj_tol_rel * bnorm, c->scene.max_cg, s, &it2, &neg, &rr));
+          iters += it2;
+          launch_axpy(br.n, c->w_xs + br.off, 1.0, xs0 + br.off, s);
+        } else {
+          rr = true_res * true_res;
+        }
+      }
       if (c->adj_warm)
         launch_axpy(br.n, w + br.off, 1.0, c->w_xs + br.off, s);
       else

@@ -704,12 +704,56 @@ __device__ __forceinline__ double all_blocks_sum(const double* partials, int nb,
   return r;
 }
 
+// the sums of the first nb pairs of interleaved partials in one pass and one block reduction,
+// identical in every block; sh: 2 * (kBlock / 64) + 2 values
+__device__ __forceinline__ void all_blocks_sum2(const double* partials, int nb, double* sh, double& a, double& b) {
+  double v0 = 0.0, v1 = 0.0;
+  for (int k = threadIdx.x; k < nb; k += blockDim.x) {
+    v0 += partials[2 * k];
+    v1 += partials[2 * k + 1];
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  v0 = wave_sum(v0);
+  v1 = wave_sum(v1);
+  if (lane == 0) {
+    sh[2 * wid] = v0;
+    sh[2 * wid + 1] = v1;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    double t = 0.0;
+    for (int w = 0; w < kBlock / 64; ++w) t += sh[2 * w + threadIdx.x];
+    sh[2 * (kBlock / 64) + threadIdx.x] = t;
+  }
+  __syncthreads();
+  a = sh[2 * (kBlock / 64)];
+  b = sh[2 * (kBlock / 64) + 1];
+  __syncthreads();
+}
+
+// this block's sums of two values into out[2 * blockIdx.x + k] (one barrier); sh: 2 * (kBlock / 64)
+__device__ __forceinline__ void block_partials2(double a, double b, double* sh, double* out) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  a = wave_sum(a);
+  b = wave_sum(b);
+  if (lane == 0) {
+    sh[2 * wid] = a;
+    sh[2 * wid + 1] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    double t = 0.0;
+    for (int w = 0; w < kBlock / 64; ++w) t += sh[2 * w + threadIdx.x];
+    out[2 * blockIdx.x + threadIdx.x] = t;
+  }
+}
+
 // r = b, x = 0, p = D^-1 r, Hp = vdiag p; partials (r.z, r.r); a single block then fills scal
 __global__ void __launch_bounds__(kBlock) k_cg_start(int n, const double* __restrict__ b, double sign,
                                                      const double* __restrict__ Dinvp,
                                                      const double* __restrict__ vdiag, double* r, double* p, double* xs,
                                                      double* Hp, double* partials) {
-  __shared__ double sh[kBlock / 64];
+  __shared__ double sh[2 * (kBlock / 64)];
   double rz = 0.0, rr = 0.0;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const double ri = Dinvp[i] != 0.0 ? sign * b[i] : 0.0;
@@ -721,19 +765,14 @@ __global__ void __launch_bounds__(kBlock) k_cg_start(int n, const double* __rest
     rz += ri * zi;
     rr += ri * ri;
   }
-  rz = block_sum(rz, sh);
-  rr = block_sum(rr, sh);
-  if (threadIdx.x == 0) {
-    partials[2 * blockIdx.x] = rz;
-    partials[2 * blockIdx.x + 1] = rr;
-  }
+  block_partials2(rz, rr, sh, partials);
 }
 
 __global__ void __launch_bounds__(kBlock) k_cg_start_fin(const double* __restrict__ partials, int nb, CgScal* scal,
                                                          double tol2, int max_it) {
-  __shared__ double sh[kBlock / 64 + 1];
-  const double rz = all_blocks_sum(partials, nb, 2, 0, sh);
-  const double rr = all_blocks_sum(partials, nb, 2, 1, sh);
+  __shared__ double sh[2 * (kBlock / 64) + 2];
+  double rz, rr;
+  all_blocks_sum2(partials, nb, sh, rz, rr);
   if (threadIdx.x == 0) {
     scal->rz[0] = rz;
     scal->rr = rr;
@@ -764,7 +803,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(int n, int nb, const doubl
                                                       double* r, double* xs, double* partials, CgScal* scal) {
   if (scal->done) return;
   const int it = scal->iters;
-  __shared__ double sh[kBlock / 64 + 1];
+  __shared__ double sh[2 * (kBlock / 64) + 2];
   const double pHp = all_blocks_sum(partials, nb, 1, 0, sh);
   __syncthreads();  // every block has read its partials before any overwrites them below
   const double rz = scal->rz[it & 1];
@@ -792,12 +831,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(int n, int nb, const doubl
     rr += ri * ri;
   }
   // the partials buffer is reused: this kernel reads nb single partials, then writes 2 per block
-  rz1 = block_sum(rz1, sh);
-  rr = block_sum(rr, sh);
-  if (threadIdx.x == 0) {
-    partials[kMaxRedBlocks + 2 * blockIdx.x] = rz1;
-    partials[kMaxRedBlocks + 2 * blockIdx.x + 1] = rr;
-  }
+  block_partials2(rz1, rr, sh, partials + kMaxRedBlocks);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     scal->pHp = pHp;
     scal->it_cur = it;
@@ -812,9 +846,9 @@ __global__ void __launch_bounds__(kBlock) k_cg_p(int n, int nb, const double* __
   if (scal->done) return;
   const int it = scal->it_cur;
   const double tol2 = scal->tol2;
-  __shared__ double sh[kBlock / 64 + 1];
-  const double rz1 = all_blocks_sum(partials + kMaxRedBlocks, nb, 2, 0, sh);
-  const double rr = all_blocks_sum(partials + kMaxRedBlocks, nb, 2, 1, sh);
+  __shared__ double sh[2 * (kBlock / 64) + 2];
+  double rz1, rr;
+  all_blocks_sum2(partials + kMaxRedBlocks, nb, sh, rz1, rr);
   if (rr <= tol2) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       scal->done = 1;
@@ -972,13 +1006,63 @@ void launch_min_count(int n, const double* a, double* partials, double* out, hip
 // writing the partials of the new (gamma, r.r, u^T vdiag u). Two launches per iteration instead of
 // four; the partials alternate between two banks of 3 x kMaxRedBlocks values by iteration parity.
 
+// The three interleaved partials (r.u, r.r, u.vdiag u) of nb blocks and nhv curvature partials,
+// summed in one pass (all loads in flight together) and one block reduction; every block of the
+// launch gets the same (gamma, r.r, delta). sh: 4 * (kBlock / 64) + 4 values.
+__device__ __forceinline__ void cgcg_scalars(const double* partials, int nb, const double* hvpart, int nhv,
+                                             double* sh, double& gamma, double& rr, double& delta) {
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+    v[0] += partials[3 * b];
+    v[1] += partials[3 * b + 1];
+    v[2] += partials[3 * b + 2];
+  }
+  for (int b = threadIdx.x; b < nhv; b += blockDim.x) v[3] += hvpart[b];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    v[k] = wave_sum(v[k]);
+    if (lane == 0) sh[4 * wid + k] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    double t = 0.0;
+    for (int w = 0; w < kBlock / 64; ++w) t += sh[4 * w + threadIdx.x];
+    sh[4 * (kBlock / 64) + threadIdx.x] = t;
+  }
+  __syncthreads();
+  gamma = sh[4 * (kBlock / 64)];
+  rr = sh[4 * (kBlock / 64) + 1];
+  delta = sh[4 * (kBlock / 64) + 2] + sh[4 * (kBlock / 64) + 3];
+  __syncthreads();  // sh is reused by the block sums below
+}
+
+// this block's sums of three values into out[3 * blockIdx.x + k] (one barrier); sh: 3 * (kBlock / 64)
+__device__ __forceinline__ void block_partials3(double a, double b, double c, double* sh, double* out) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  a = wave_sum(a);
+  b = wave_sum(b);
+  c = wave_sum(c);
+  if (lane == 0) {
+    sh[3 * wid] = a;
+    sh[3 * wid + 1] = b;
+    sh[3 * wid + 2] = c;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    double t = 0.0;
+    for (int w = 0; w < kBlock / 64; ++w) t += sh[3 * w + threadIdx.x];
+    out[3 * blockIdx.x + threadIdx.x] = t;
+  }
+}
+
 // r = b (masked), u = M r, w = vdiag u, p = s = xs = 0; bank-0 partials (r.u, r.r, u.vdiag u)
 __global__ void __launch_bounds__(kBlock) k_cgcg_start(int n, const double* __restrict__ b, double sign,
                                                        const double* __restrict__ Dinvp,
                                                        const double* __restrict__ vdiag, double* r, double* u,
                                                        double* w, double* p, double* sv, double* xs,
                                                        double* partials) {
-  __shared__ double sh[kBlock / 64];
+  __shared__ double sh[3 * (kBlock / 64)];
   double g = 0.0, rr = 0.0, dv = 0.0;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const double ri = Dinvp[i] != 0.0 ? sign * b[i] : 0.0;
@@ -994,14 +1078,7 @@ __global__ void __launch_bounds__(kBlock) k_cgcg_start(int n, const double* __re
     rr += ri * ri;
     dv += ui * wi;
   }
-  g = block_sum(g, sh);
-  rr = block_sum(rr, sh);
-  dv = block_sum(dv, sh);
-  if (threadIdx.x == 0) {
-    partials[3 * blockIdx.x] = g;
-    partials[3 * blockIdx.x + 1] = rr;
-    partials[3 * blockIdx.x + 2] = dv;
-  }
+  block_partials3(g, rr, dv, sh, partials);
 }
 
 __global__ void __launch_bounds__(kBlock) k_cgcg_start_fin(const double* __restrict__ partials, int nb,
@@ -1033,10 +1110,9 @@ __global__ void __launch_bounds__(kBlock) k_cgcg_vec(int n, int nb, const double
   const int it = scal->iters;
   const double* prev = partials + (it & 1) * 3 * kMaxRedBlocks;
   double* next = partials + ((it + 1) & 1) * 3 * kMaxRedBlocks;
-  __shared__ double sh[kBlock / 64 + 1];
-  const double gamma = all_blocks_sum(prev, nb, 3, 0, sh);
-  const double rr = all_blocks_sum(prev, nb, 3, 1, sh);
-  const double delta = all_blocks_sum(prev, nb, 3, 2, sh) + all_blocks_sum(hvpart, nhv, 1, 0, sh);
+  __shared__ double sh[4 * (kBlock / 64) + 4];
+  double gamma, rr, delta;
+  cgcg_scalars(prev, nb, hvpart, nhv, sh, gamma, rr, delta);
   if (rr <= scal->tol2) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       scal->done = 1;
@@ -1078,14 +1154,7 @@ __global__ void __launch_bounds__(kBlock) k_cgcg_vec(int n, int nb, const double
     rn += ri * ri;
     dv += ui * wi;
   }
-  g = block_sum(g, sh);
-  rn = block_sum(rn, sh);
-  dv = block_sum(dv, sh);
-  if (threadIdx.x == 0) {
-    next[3 * blockIdx.x] = g;
-    next[3 * blockIdx.x + 1] = rn;
-    next[3 * blockIdx.x + 2] = dv;
-  }
+  block_partials3(g, rn, dv, sh, next);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     scal->gamma_prev = gamma;
     scal->alpha_prev = alpha;

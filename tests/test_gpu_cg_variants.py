@@ -3,8 +3,8 @@ patch scatter (>= 16,384 elements), through the C ABI against the FP64 oracle:
 
 * single-reduction PCG (Chronopoulos and Gear: the patch Hessian-vector kernel returns its share of
   u^T H u, one vector kernel per iteration) against the classic four-kernel PCG and the oracle, for
-  the step (Eq. 14) and the adjoint (Eq. 9), in FP64 and mixed precision, eager and as replayed
-  graph chunks;
+  the step (Eq. 14) and the adjoint (Eq. 9, with its true-residual check and correction solve in
+  mixed precision), in FP64 and mixed precision, eager and as replayed graph chunks;
 * the compact rest record (uniform material, fibres along one axis: Dm^-1 and W per element, the
   material from scalars) against the general per-element record, in the patch kernels' gradient,
   Hessian-vector product and diagonal and in whole solves."""
@@ -88,11 +88,17 @@ def test_single_reduction_cg_matches_classic_and_oracle(oracle_refs, body, preci
         assert rel(x1 - w.x0, xr - w.x0) <= tol and rel_inf(x1 - w.x0, xr - w.x0) <= tol
         assert rel(v1, vr) <= tol
         assert rel(wv, wr) <= tol and rel_inf(wv, wr) <= tol
-    # the same iterates in exact arithmetic: iteration counts agree up to rounding
+    # the same iterates in exact arithmetic: iteration counts agree up to rounding. In mixed precision
+    # the single-reduction form's recurrence for H p drifts from the FP32 operator, so its adjoint
+    # checks the true residual once and, if needed, solves for the correction (at this 1e-13
+    # tolerance it always does: up to about twice the iterations)
     s1, s0 = res[1][3]["cg_iters"], res[0][3]["cg_iters"]
     assert abs(s1 - s0) <= 0.1 * s0 + 5
     a1, a0 = res[1][4]["adj_cg_iters"], res[0][4]["adj_cg_iters"]
-    assert abs(a1 - a0) <= 0.1 * a0 + 5
+    if precision == "fp64":
+        assert abs(a1 - a0) <= 0.1 * a0 + 5
+    else:
+        assert a0 - 5 <= a1 <= 2 * a0 + 5
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 1e-7)])
