@@ -38,14 +38,20 @@ MAX_POOL = 16  # host cores of one GPU's share of the machine
 METRIC = "Newton-CG steps/sec fwd+adjoint, batched FP32/64 vs plain FP64, 1e-6 residual"
 
 
-def kernel_source_hash():
-    """sha256 over the library's sources (name and contents, sorted): the measured-traffic figure in
-    profiles/ applies only while this matches the hash recorded with it."""
+# the sources the batched persistent kernel is compiled from (its body logic, the element and
+# spring math, the device helpers and data layout, the ABI header)
+BATCHED_SOURCES = ("isb_batched.hip", "isb_body.hpp", "isb_device.hpp", "isb_elem.hpp", "isb_spring.hpp",
+                   "isb_internal.hpp", "isb.h")
+
+
+def kernel_source_hash(files=BATCHED_SOURCES):
+    """sha256 over the named library sources (name and contents, in the order given): a
+    measured-traffic figure in profiles/ applies only while this matches the hash recorded with it."""
     import hashlib
     h = hashlib.sha256()
     src = os.path.join(HERE, "paper_2102_05791_amd", "csrc")
-    files = sorted(f for f in os.listdir(src) if f.endswith((".hpp", ".hip", ".cpp")))
-    for name, path in [(f, os.path.join(src, f)) for f in files] + [("isb.h", os.path.join(HERE, "include", "isb.h"))]:
+    for name in files:
+        path = os.path.join(HERE, "include", name) if name == "isb.h" else os.path.join(src, name)
         h.update(name.encode() + b"\0")
         with open(path, "rb") as fh:
             h.update(fh.read())
