@@ -637,14 +637,21 @@ struct BodySolver {
   // next p.
   static constexpr int kU = 2;
 
-  // the kU owned DOFs from i0 on of xs, D^-1, r and vdiag. Indices past the body are clamped to
-  // its last DOF, so every lane loads unconditionally; the caller ignores those values.
-  __device__ __forceinline__ void cg_load(int i0, const double* xs, double (&x)[kU], double (&d)[kU],
+  // the kU owned DOFs from i0 on of xs, D^-1, r and vdiag. Indices past the body load the DOF
+  // `own` instead, one this thread owns and has not yet written in the current pass, so that every
+  // lane loads unconditionally without reading a DOF another thread is updating; the caller ignores
+  // those values. own < 0: the thread owns no DOF of the body and loads nothing.
+  __device__ __forceinline__ void cg_load(int i0, int own, const double* xs, double (&x)[kU], double (&d)[kU],
                                           double (&rv)[kU], double (&v)[kU]) const {
+    if (own < 0) {
+#pragma unroll
+      for (int u = 0; u < kU; ++u) x[u] = d[u] = rv[u] = v[u] = 0.0;
+      return;
+    }
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
       const int iu = i0 + u * (int)blockDim.x;
-      const int i = iu < n ? iu : n - 1;
+      const int i = iu < n ? iu : own;
       const int g = base + i;
       x[u] = xs[g];
       d[u] = A.Dv[g];
@@ -714,10 +721,10 @@ struct BodySolver {
       double rz1 = 0.0, zz = 0.0, zp = 0.0, pp = 0.0;
       rr = 0.0;
       double cx[kU], cd[kU], cr[kU], cv[kU];
-      cg_load(threadIdx.x, xs, cx, cd, cr, cv);
+      cg_load(threadIdx.x, (int)threadIdx.x < n ? (int)threadIdx.x : -1, xs, cx, cd, cr, cv);
       for (int i0 = threadIdx.x; i0 < n; i0 += kU * B) {
         double nx[kU], nd[kU], nr[kU], nv[kU];
-        cg_load(i0 + kU * B, xs, nx, nd, nr, nv);
+        cg_load(i0 + kU * B, i0, xs, nx, nd, nr, nv);
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
           const int i = i0 + u * B;

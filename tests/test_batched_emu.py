@@ -201,3 +201,25 @@ def test_emulated_adjoint_warm_start(emu_mod, precision, tol):
         sv = slice(w.body_v_off[b], w.body_v_off[b + 1])
         wr = solve.adjoint(p, x1[sv], w.x0[sv], wb.actions[0], xbar[sv], vbar[sv])
         assert rel(w_warm[sv], wr) <= tol
+
+
+@pytest.mark.parametrize("block", [256, 768])
+def test_emulated_multi_wave_workgroups(emu_mod, block):
+    """Workgroups of 4 and 12 waves: the alternating reduction banks, the cross-wave sums and every
+    barrier of the step, CG and adjoint with more waves than the one-wave runs above exercise."""
+    w, rng = rand_workload(2, seed=25, bodies=2, shape=(4, 2))
+    w = _tight(w)
+    eb = emu_mod.EmuBatch(w, "fp64")
+    a = w.actions[0]
+    x1, v1, st = eb.step(w.x0, w.v0, a, block=block)
+    assert np.all(st["flags"] & 1)
+    xbar = rng.normal(size=x1.shape)
+    wv, sa = eb.adjoint(x1, w.x0, a, xbar, None, block=block)
+    assert np.all(sa["flags"] & 8)
+    for b, p in enumerate(problems(w)):
+        sv = slice(w.body_v_off[b], w.body_v_off[b + 1])
+        se = slice(w.body_e_off[b], w.body_e_off[b + 1])
+        xr, vr, _ = solve.step(p, w.x0[sv], w.v0[sv], a[se], tol=1e-13)
+        assert rel(x1[sv] - w.x0[sv], xr - w.x0[sv]) <= 1e-10
+        wr = solve.adjoint(p, x1[sv], w.x0[sv], a[se], xbar[sv])
+        assert rel(wv[sv], wr) <= 1e-10
