@@ -111,9 +111,11 @@ def parse():
 # ---------------------------------------------------------------------------------------------
 # algorithmic bytes (minimal traffic: every array element moved once per pass)
 # ---------------------------------------------------------------------------------------------
-def elem_bytes(dim, word):
-    """conn + Dm^-1 + fibre vector + W mu, W lam, W k_f + actuation, per element."""
-    return 4 * (dim + 1) + word * (dim * dim + dim + 3 + 1)
+def elem_bytes(dim, word, compact=False):
+    """conn + rest data + actuation, per element: the general record holds Dm^-1, the fibre vector
+    and W mu, W lam, W k_f; the compact one (uniform material, fibre along an axis) Dm^-1 and W."""
+    rest = dim * dim + 1 if compact else dim * dim + dim + 3
+    return 4 * (dim + 1) + word * (rest + 1)
 
 
 def hv_state_bytes(dim, word):
@@ -122,27 +124,27 @@ def hv_state_bytes(dim, word):
     return word * (10 if dim == 2 else dim * dim + dim)
 
 
-def hv_elem_bytes(dim, word):
+def hv_elem_bytes(dim, word, compact=False):
     """Element bytes of one batched Hessian-vector pass: 16-bit body-local connectivity + the
     stored state (triangles), or + rest data + actuation + the stored F, F d (tetrahedra)."""
     if dim == 2:
         return 2 * (dim + 1) + hv_state_bytes(dim, word)
-    return elem_bytes(dim, word) - 2 * (dim + 1) + hv_state_bytes(dim, word)
+    return elem_bytes(dim, word, compact) - 2 * (dim + 1) + hv_state_bytes(dim, word)
 
 
-def cg_iter_bytes(dim, ne, nv, word_hv):
+def cg_iter_bytes(dim, ne, nv, word_hv, compact=False):
     """One batched CG iteration: the Hessian-vector element pass (p is in LDS), and the x/r update
     pass (xs, r read and written, the FP32 preconditioner and the vertex diagonal in the element
     precision read); the direction pass touches LDS only."""
-    return hv_elem_bytes(dim, word_hv) * ne + (32 + 4 + word_hv) * nv * dim
+    return hv_elem_bytes(dim, word_hv, compact) * ne + (32 + 4 + word_hv) * nv * dim
 
 
-def trial_bytes(dim, ne, nv, word_hv):
+def trial_bytes(dim, ne, nv, word_hv, compact=False):
     """One fused line-search trial: 16-bit connectivity, FP64 rest data and actuation, E(x) read,
     E(x_t) written, the Hessian-vector state stored per element; x, dx, x0, xhat, pinned read and G
     (FP64), the vertex diagonal (element precision) and the FP32 preconditioner written per DOF;
     mass and c_v per vertex."""
-    return ((elem_bytes(dim, 8) - 2 * (dim + 1) + 16 + hv_state_bytes(dim, word_hv)) * ne
+    return ((elem_bytes(dim, 8, compact) - 2 * (dim + 1) + 16 + hv_state_bytes(dim, word_hv)) * ne
             + (41 + 8 + 4 + word_hv) * nv * dim + 16 * nv)
 
 
@@ -157,31 +159,31 @@ def spring_trial_bytes(dim, word):
     return 4 + 24 + 16 + word * dim * (dim + 1) // 2
 
 
-def step_launch_bytes(dim, ne, nv, st, word_hv, ns=0):
+def step_launch_bytes(dim, ne, nv, st, word_hv, ns=0, compact=False):
     """Algorithmic bytes of one body (ne elements, nv vertices, ns springs) in one step launch,
     from its solver statistics."""
     dof = nv * dim
     trials = 1 + st["newton_iters"] + st["ls_backtracks"]
     setup = 57 * dof + 16 * nv                 # x0, v0, pinned -> xhat, x; c_v; v1 at the end
     per_newton = (8 + 4 + word_hv + 24) * dof + 16 * dof + 24 * dof  # CG start; g.dx; x += alpha dx
-    return (setup + trials * (trial_bytes(dim, ne, nv, word_hv) + ns * spring_trial_bytes(dim, word_hv))
+    return (setup + trials * (trial_bytes(dim, ne, nv, word_hv, compact) + ns * spring_trial_bytes(dim, word_hv))
             - 8 * (ne + ns) + st["newton_iters"] * per_newton
-            + st["cg_iters"] * (cg_iter_bytes(dim, ne, nv, word_hv) + ns * spring_hv_bytes(dim, word_hv)))
+            + st["cg_iters"] * (cg_iter_bytes(dim, ne, nv, word_hv, compact) + ns * spring_hv_bytes(dim, word_hv)))
 
 
-def adjoint_launch_bytes(dim, ne, nv, st, word_hv, ns=0, warm=False):
+def adjoint_launch_bytes(dim, ne, nv, st, word_hv, ns=0, warm=False, compact=False):
     """Right-hand side (xbar, vbar, pinned -> G; c_v), the FP64 diagonal pass that also stores the
     Hessian-vector state, the warm start (one Hessian-vector pass over the given w; w read, G read
     and written, the vertex diagonal read, w parked and added back), the CG start and the CG
     iterations."""
     dof = nv * dim
     rhs = 25 * dof + 16 * nv
-    diag = ((elem_bytes(dim, 8) - 2 * (dim + 1) + hv_state_bytes(dim, word_hv)) * ne + (9 + 4 + word_hv) * dof
+    diag = ((elem_bytes(dim, 8, compact) - 2 * (dim + 1) + hv_state_bytes(dim, word_hv)) * ne + (9 + 4 + word_hv) * dof
             + 16 * nv + ns * (spring_trial_bytes(dim, word_hv) - 16))
-    start = (hv_elem_bytes(dim, word_hv) * ne + ns * spring_hv_bytes(dim, word_hv)
+    start = (hv_elem_bytes(dim, word_hv, compact) * ne + ns * spring_hv_bytes(dim, word_hv)
              + (8 + 16 + word_hv + 8 + 24) * dof) if warm else 0
     return (rhs + diag + start + (36 + 4 + word_hv) * dof
-            + st["adj_cg_iters"] * (cg_iter_bytes(dim, ne, nv, word_hv) + ns * spring_hv_bytes(dim, word_hv)))
+            + st["adj_cg_iters"] * (cg_iter_bytes(dim, ne, nv, word_hv, compact) + ns * spring_hv_bytes(dim, word_hv)))
 
 
 def octile_pick(sizes, n):
@@ -375,9 +377,10 @@ def main():
     _, _, st_f, st_a = bptt(stats=True)
     print("# statistics pass done", file=sys.stderr, flush=True)
     ne_b, nv_b = np.diff(w.body_e_off), np.diff(w.body_v_off)
-    fb = [sum(step_launch_bytes(2, ne_b[b], nv_b[b], s[b], 4) for b in range(nb)) for s in st_f]
+    cr = ctx.get_option(isb.INFO_COMPACT_AXIS) >= 0
+    fb = [sum(step_launch_bytes(2, ne_b[b], nv_b[b], s[b], 4, compact=cr) for b in range(nb)) for s in st_f]
     # st_a runs backward in time: the first adjoint starts from zero, every later one from the last w
-    ab = [sum(adjoint_launch_bytes(2, ne_b[b], nv_b[b], s[b], 4, warm=k > 0) for b in range(nb))
+    ab = [sum(adjoint_launch_bytes(2, ne_b[b], nv_b[b], s[b], 4, warm=k > 0, compact=cr) for b in range(nb))
           for k, s in enumerate(st_a)]
     it = {"newton_per_step": float(np.mean([[s["newton_iters"] for s in S] for S in st_f])),
           "cg_per_step": float(np.mean([[s["cg_iters"] for s in S] for S in st_f])),
@@ -592,8 +595,9 @@ def mall_leg(args, torch, Context, isb, scenes, ceiling):
     adj_ms = float(np.mean([a.elapsed_time(b) for a, b in adj_ev]))
     st_f, st_a = bptt(stats=True)
     ne_b, nv_b = np.diff(w.body_e_off), np.diff(w.body_v_off)
-    fb = [sum(step_launch_bytes(2, ne_b[b], nv_b[b], S[b], 4) for b in range(nb)) for S in st_f]
-    ab = [sum(adjoint_launch_bytes(2, ne_b[b], nv_b[b], S[b], 4, warm=k > 0) for b in range(nb))
+    cr = ctx.get_option(isb.INFO_COMPACT_AXIS) >= 0
+    fb = [sum(step_launch_bytes(2, ne_b[b], nv_b[b], S[b], 4, compact=cr) for b in range(nb)) for S in st_f]
+    ab = [sum(adjoint_launch_bytes(2, ne_b[b], nv_b[b], S[b], 4, warm=k > 0, compact=cr) for b in range(nb))
           for k, S in enumerate(st_a)]
     roof = batched_roofline(fb, ab, step_ms, adj_ms, TRAFFIC_PROFILE_4096)
     roof["frac_of_copy_ceiling"] = round(roof["achieved"] / ceiling["GBs"], 4)
@@ -683,7 +687,8 @@ def spring_leg(args, torch, Context, isb, scenes):
     step_ms = float(np.mean([a.elapsed_time(b) for a, b in step_ev]))
     _, st_f, st_a = bptt(stats=True)
     ne_b, nv_b, ns_b = np.diff(w.body_e_off), np.diff(w.body_v_off), np.diff(w.body_s_off)
-    fb = float(np.mean([sum(step_launch_bytes(2, ne_b[b], nv_b[b], S[b], 4, ns_b[b]) for b in range(nb))
+    cr = ctx.get_option(isb.INFO_COMPACT_AXIS) >= 0
+    fb = float(np.mean([sum(step_launch_bytes(2, ne_b[b], nv_b[b], S[b], 4, ns_b[b], compact=cr) for b in range(nb))
                         for S in st_f]))
     achieved = fb / (step_ms * 1e-3) / 1e9
     errs, bodies = [], []

@@ -385,6 +385,19 @@ static isb_status run_cg(isb_ctx* c, int b, const double* x, const double* a, co
   *iters = c->hcg->iters;
   *negcurv = c->hcg->negcurv != 0;
   *rr = c->hcg->rr;
+  if (single && *negcurv) {
+    // The single-reduction form obtains p^T H p from a recurrence, delta - beta gamma / alpha_prev,
+    // which cancels when beta^2 p_prev^T H p_prev approaches delta (long, slowly converging solves):
+    // a non-positive value there may be rounding. Solve again in the classic form, which forms
+    // p^T H p from a fresh product and decides the curvature itself.
+    const int keep = c->cg_single;
+    int it2 = 0;
+    c->cg_single = 0;
+    const isb_status st = run_cg(c, b, x, a, rhs, sign, tol, max_cg, s, &it2, negcurv, rr);
+    c->cg_single = keep;
+    ISB_TRY(st);
+    *iters += it2;
+  }
   return ISB_OK;
 }
 

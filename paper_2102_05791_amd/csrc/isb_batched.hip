@@ -13,18 +13,10 @@
 #include <utility>
 #include <vector>
 
-#include "isb_body.hpp"
+#include "isb_batched_kernel.hpp"
 #include "isb_ctx.hpp"
 
 namespace isb {
-
-// MODE 0: step, 1: adjoint. LB is the launch bound: 1024-thread workgroups get at most 128 VGPRs,
-// 768-thread ones 168 and 512-thread ones 256 (one workgroup per CU in every case).
-template <int D, typename T, int MODE, int LB, int EM = EM_NH>
-__global__ void __launch_bounds__(LB) k_batched(DevMesh m, DevScene sc, BatchArgs A) {
-  extern __shared__ double smem[];
-  batched_body<D, T, MODE, EM>(m, sc, A, smem, (int)blockIdx.x);
-}
 
 // ---------------------------------------------------------------------------------------------
 // host side
@@ -44,48 +36,17 @@ struct BatchedState {
   void* Sbuf = nullptr;                 // per-spring block K in the element precision
   int32_t *fb_order = nullptr, *fb_wgoff = nullptr;  // schedule of a fallback launch (FP64 state only)
   int nacc = 0, grid = 0, block = 0, precision = -1, dim = 0, model = 0;
+  bool compact = false;  // the compact rest record (the kernel variant the launches take)
   size_t lds = 0;
 };
 
-template <int D, typename T, int MODE, int LB, int EM = EM_NH>
-static void* kernel_ptr() {
-  return reinterpret_cast<void*>(&k_batched<D, T, MODE, LB, EM>);
-}
-
-// the alternative energy models come in the default workgroup size of each dimension only
-template <int EM>
-static void* pick_model(int dim, int precision, int mode) {
-  if (dim == 2) {
-    if (precision == ISB_MIXED) return mode ? kernel_ptr<2, float, 1, 768, EM>() : kernel_ptr<2, float, 0, 768, EM>();
-    return mode ? kernel_ptr<2, double, 1, 768, EM>() : kernel_ptr<2, double, 0, 768, EM>();
-  }
-  if (precision == ISB_MIXED) return mode ? kernel_ptr<3, float, 1, 512, EM>() : kernel_ptr<3, float, 0, 512, EM>();
-  return mode ? kernel_ptr<3, double, 1, 512, EM>() : kernel_ptr<3, double, 0, 512, EM>();
-}
-
-template <int LB>
-static void* pick_lb(int dim, int precision, int mode) {
-  if (dim == 2) {
-    if (precision == ISB_MIXED) return mode ? kernel_ptr<2, float, 1, LB>() : kernel_ptr<2, float, 0, LB>();
-    return mode ? kernel_ptr<2, double, 1, LB>() : kernel_ptr<2, double, 0, LB>();
-  }
-  if (precision == ISB_MIXED) return mode ? kernel_ptr<3, float, 1, LB>() : kernel_ptr<3, float, 0, LB>();
-  return mode ? kernel_ptr<3, double, 1, LB>() : kernel_ptr<3, double, 0, LB>();
-}
-
-static int default_block(int dim) { return dim == 2 ? 768 : 512; }
+static int default_block(int dim) { return batched_default_block(dim); }
 
 // nullptr: no kernel of this configuration (an alternative energy model at another block size)
-static void* pick_kernel(int dim, int precision, int mode, int block, int model) {
-  if (model != EM_NH) {
-    if (block != default_block(dim)) return nullptr;
-    if (model == EM_STVK) return pick_model<EM_STVK>(dim, precision, mode);
-    if (model == EM_COROT) return pick_model<EM_COROT>(dim, precision, mode);
-    return pick_model<EM_SNH>(dim, precision, mode);
-  }
-  if (block > 768) return pick_lb<1024>(dim, precision, mode);
-  if (block > 512) return pick_lb<768>(dim, precision, mode);
-  return pick_lb<512>(dim, precision, mode);
+static void* pick_kernel(int dim, int precision, int mode, int block, int model, bool compact) {
+  const int prec = precision == ISB_MIXED ? 1 : 0;
+  return dim == 2 ? batched_kernel_2d(prec, mode, block, model, compact)
+                  : batched_kernel_3d(prec, mode, block, model, compact);
 }
 
 // LDS of one workgroup: reduction slots, the FP64 accumulator and the FP64 CG direction, sized for
@@ -153,9 +114,11 @@ static void lpt_schedule(const std::vector<int32_t>& eoff, int nb, int G, std::v
 static isb_status prepare_state(isb_ctx* c, void** slot, int precision) {
   auto* st = static_cast<BatchedState*>(*slot);
   const int want_block = c->block > 0 ? c->block : default_block(c->dim);
-  if (st && st->block == want_block && st->precision == precision && st->dim == c->dim && st->model == c->model)
+  const bool compact = devmesh(c).axis >= 0;
+  if (st && st->block == want_block && st->precision == precision && st->dim == c->dim && st->model == c->model &&
+      st->compact == compact)
     return ISB_OK;
-  if (!pick_kernel(c->dim, precision, 0, want_block, c->model))
+  if (!pick_kernel(c->dim, precision, 0, want_block, c->model, compact))
     return fail(ISB_E_ARG, "batched solver: the alternative energy models run with the default workgroup size only");
   release_state(slot);
   st = new BatchedState();
@@ -167,6 +130,7 @@ static isb_status prepare_state(isb_ctx* c, void** slot, int precision) {
   st->precision = precision;
   st->dim = c->dim;
   st->model = c->model;
+  st->compact = compact;
   int max_lds = 0, n_cu = 0;
   ISB_HIP(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
   ISB_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, c->device));
@@ -175,7 +139,7 @@ static isb_status prepare_state(isb_ctx* c, void** slot, int precision) {
                                " B of LDS, the device allows " + std::to_string(max_lds) + " B per workgroup");
   int occ = 0;
   for (int mode = 0; mode < 2; ++mode) {
-    void* k = pick_kernel(c->dim, precision, mode, st->block, c->model);
+    void* k = pick_kernel(c->dim, precision, mode, st->block, c->model, compact);
     ISB_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)st->lds));
     int o = 0;
     ISB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, k, st->block, st->lds));
@@ -300,7 +264,7 @@ static BatchArgs make_args(isb_ctx* c, BatchedState* st) {
 }
 
 static isb_status launch(isb_ctx* c, BatchedState* st, hipStream_t s, int mode, const BatchArgs& A, int grid = 0) {
-  void* k = pick_kernel(c->dim, st->precision, mode, st->block, c->model);
+  void* k = pick_kernel(c->dim, st->precision, mode, st->block, c->model, st->compact);
   const DevMesh m = devmesh(c);
   const DevScene sc = devscene(c);
   void* args[] = {(void*)&m, (void*)&sc, (void*)&A};

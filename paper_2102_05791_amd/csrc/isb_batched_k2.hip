@@ -1,0 +1,10 @@
+// The batched persistent kernel's variants for triangles (see isb_batched_kernel.hpp).
+#include "isb_batched_kernel.hpp"
+
+namespace isb {
+
+void* batched_kernel_2d(int precision, int mode, int block, int model, bool compact) {
+  return batched_kernel_dim<2>(precision, mode, block, model, compact);
+}
+
+}  // namespace isb

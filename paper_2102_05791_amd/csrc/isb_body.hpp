@@ -162,7 +162,8 @@ __device__ __forceinline__ void wg_minmax(double& lo, double& hi, double* bank) 
   hi = wg_uniform(hi);
 }
 
-template <int D, typename T, int EM = EM_NH>
+// CR: the compact rest record (uniform material, fibre along an axis; see DevMesh::axis)
+template <int D, typename T, int EM = EM_NH, bool CR = false>
 struct BodySolver {
   const DevMesh& m;
   const DevScene& sc;
@@ -285,7 +286,7 @@ struct BodySolver {
           }
       } else {
         ElemRest<D, T> R;
-        load_rest<D, T>(m, e, R);
+        load_rest<D, T, CR>(m, e, R);
         T F[D][D], Fd[D];
 #pragma unroll
         for (int r = 0; r < D; ++r) {
@@ -411,7 +412,7 @@ struct BodySolver {
       int v[D + 1];
       load_lconn(e, v);
       ElemRest<D, double> R64;
-      load_rest<D, double>(m, e, R64);
+      load_rest<D, double, CR>(m, e, R64);
       const double ae = A.a[e];
       double Ds[D][D];
       gather_edges<D, double>(x, v, Ds);
@@ -491,7 +492,7 @@ struct BodySolver {
       int v[D + 1];
       load_lconn(e, v);
       ElemRest<D, double> R64;
-      load_rest<D, double>(m, e, R64);
+      load_rest<D, double, CR>(m, e, R64);
       const double ae = A.a[e];
       const double estored = Ecur ? Ecur[e] : 0.0;
       double Ds[D][D];
@@ -618,7 +619,7 @@ struct BodySolver {
       int v[D + 1];
       load_lconn(e, v);
       ElemRest<D, double> R;
-      load_rest<D, double>(m, e, R);
+      load_rest<D, double, CR>(m, e, R);
       double Ds[D][D];
       gather_edges<D, double>(x, v, Ds);
       ElemState<D, double> S;
@@ -1017,7 +1018,7 @@ struct BodySolver {
   }
 };
 
-template <int D, typename T, int MODE, int EM = EM_NH>  // MODE 0: step, 1: adjoint
+template <int D, typename T, int MODE, int EM = EM_NH, bool CR = false>  // MODE 0: step, 1: adjoint
 __device__ void batched_body(const DevMesh& m, const DevScene& sc, const BatchArgs& A, double* smem, int g) {
   double* red = smem;
   double* acc = smem + kRedSlots;
@@ -1033,7 +1034,7 @@ __device__ void batched_body(const DevMesh& m, const DevScene& sc, const BatchAr
     const int body = wg_uniform(A.order[k]);
     const int bv0 = wg_uniform(A.voff[body]), bv1 = wg_uniform(A.voff[body + 1]);
     const int be0 = wg_uniform(A.eoff[body]), be1 = wg_uniform(A.eoff[body + 1]);
-    BodySolver<D, T, EM> S{m, sc, A, acc, red, ps, bv0, bv1, be0, be1, (bv1 - bv0) * D, bv0 * D};
+    BodySolver<D, T, EM, CR> S{m, sc, A, acc, red, ps, bv0, bv1, be0, be1, (bv1 - bv0) * D, bv0 * D};
     if (A.n_s > 0) {
       S.s0 = wg_uniform(A.soff[body]);
       S.s1 = wg_uniform(A.soff[body + 1]);

@@ -36,11 +36,25 @@ static void run(int block, const isb::DevMesh* m, const isb::DevScene* sc, const
     th.emplace_back([&, t]() {
       threadIdx.x = t;
       isb_emu::wave_phase = 0;
+      // the compact rest record when the mesh has one (DevMesh::axis), as the library's launch does
+      const bool cr = m->axis >= 0;
       switch (m->model) {
-        case isb::EM_STVK: isb::batched_body<D, T, MODE, isb::EM_STVK>(*m, *sc, *A, smem.data(), 0); break;
-        case isb::EM_COROT: isb::batched_body<D, T, MODE, isb::EM_COROT>(*m, *sc, *A, smem.data(), 0); break;
-        case isb::EM_SNH: isb::batched_body<D, T, MODE, isb::EM_SNH>(*m, *sc, *A, smem.data(), 0); break;
-        default: isb::batched_body<D, T, MODE>(*m, *sc, *A, smem.data(), 0); break;
+        case isb::EM_STVK:
+          cr ? isb::batched_body<D, T, MODE, isb::EM_STVK, true>(*m, *sc, *A, smem.data(), 0)
+             : isb::batched_body<D, T, MODE, isb::EM_STVK, false>(*m, *sc, *A, smem.data(), 0);
+          break;
+        case isb::EM_COROT:
+          cr ? isb::batched_body<D, T, MODE, isb::EM_COROT, true>(*m, *sc, *A, smem.data(), 0)
+             : isb::batched_body<D, T, MODE, isb::EM_COROT, false>(*m, *sc, *A, smem.data(), 0);
+          break;
+        case isb::EM_SNH:
+          cr ? isb::batched_body<D, T, MODE, isb::EM_SNH, true>(*m, *sc, *A, smem.data(), 0)
+             : isb::batched_body<D, T, MODE, isb::EM_SNH, false>(*m, *sc, *A, smem.data(), 0);
+          break;
+        default:
+          cr ? isb::batched_body<D, T, MODE, isb::EM_NH, true>(*m, *sc, *A, smem.data(), 0)
+             : isb::batched_body<D, T, MODE, isb::EM_NH, false>(*m, *sc, *A, smem.data(), 0);
+          break;
       }
     });
   for (auto& x : th) x.join();

@@ -223,3 +223,22 @@ def test_emulated_multi_wave_workgroups(emu_mod, block):
         assert rel(x1[sv] - w.x0[sv], xr - w.x0[sv]) <= 1e-10
         wr = solve.adjoint(p, x1[sv], w.x0[sv], a[se], xbar[sv])
         assert rel(wv[sv], wr) <= 1e-10
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 1e-5)])
+def test_emulated_compact_rest_record(emu_mod, precision, tol):
+    """Bodies of one material with x fibres take the compact rest record (Dm^-1 and W per element,
+    the material from the mesh's scalars), as the library's batched launch does."""
+    from synth import scenes
+    w = scenes.batched_strips(2, steps=1, sizes=np.array([4, 5]))
+    w = _tight(w)
+    eb = emu_mod.EmuBatch(w, precision)
+    assert eb.m.axis == 0
+    a = w.actions[0]
+    x1, v1, st = eb.step(w.x0, w.v0, a, block=64)
+    assert np.all(st["flags"] & 1)
+    for b, p in enumerate(problems(w)):
+        sv = slice(w.body_v_off[b], w.body_v_off[b + 1])
+        wb = w.body(b)
+        xr, vr, _ = solve.step(p, wb.x0, wb.v0, wb.actions[0], tol=1e-13)
+        assert rel(x1[sv] - wb.x0, xr - wb.x0) <= tol

@@ -24,8 +24,12 @@ def test_element_byte_model():
     assert bench.elem_bytes(3, 8) == 144
     assert bench.elem_bytes(3, 4) + 4 == 84
     assert bench.elem_bytes(2, 8) == 4 * 3 + 8 * (4 + 2 + 3 + 1)
+    # the compact record of a uniform material with axis fibres: Dm^-1 and W (104 B, 60 B mixed)
+    assert bench.elem_bytes(3, 8, compact=True) == 104 and bench.elem_bytes(3, 4, compact=True) == 60
     # batched triangles: 16-bit body-local connectivity and the 10-word edge Hessian
     assert bench.hv_elem_bytes(2, 4) == 2 * 3 + 40
+    # a trial pass reads the FP64 rest data: 4 words fewer per triangle with the compact record
+    assert bench.trial_bytes(2, 1, 0, 4) - bench.trial_bytes(2, 1, 0, 4, compact=True) == 8 * 4
 
 
 def test_adjoint_warm_start_adds_one_hessian_vector_pass():

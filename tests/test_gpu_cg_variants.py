@@ -81,8 +81,8 @@ def test_single_reduction_cg_matches_classic_and_oracle(oracle_refs, body, preci
         wv, sa, _ = ctx.solve_adjoint(_dev(xr), _dev(w.x0), _dev(a), _dev(xbar))
         res[single] = (x1.cpu().numpy(), v1.cpu().numpy(), wv.cpu().numpy(), st[0], sa[0])
         x1, v1, wv = res[single][:3]
-        print(body, precision, "single" if single else "classic", st[0]["newton_iters"], st[0]["cg_iters"],
-              sa[0]["adj_cg_iters"], "errors", rel(x1 - w.x0, xr - w.x0), rel(wv, wr))
+        print(body, precision, "single" if single else "classic", st[0], sa[0]["adj_cg_iters"],
+              "errors", rel(x1 - w.x0, xr - w.x0), rel(wv, wr))
         assert st[0]["flags"] & (isb.FLAG_CONVERGED | isb.FLAG_STAGNATED)
         assert sa[0]["flags"] & isb.FLAG_ADJ_CONVERGED
         assert rel(x1 - w.x0, xr - w.x0) <= tol and rel_inf(x1 - w.x0, xr - w.x0) <= tol
@@ -144,3 +144,35 @@ def test_compact_rest_record_matches_general(precision, tol):
     H = p.hessian(x, w.x0, a)
     assert rel(out[1][1].ravel(), H @ pv.ravel(), abs(H) @ np.abs(pv.ravel())) <= (1e-12 if precision == "fp64"
                                                                                     else 2e-6)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 1e-5)])
+def test_batched_compact_rest_record(precision, tol):
+    """The batched solver on strips of one material with x fibres (the compact record) against the
+    same bodies with the general record and against the oracle, step and adjoint."""
+    from paper_2102_05791_amd import Context, isb
+    w = scenes.batched_strips(6, steps=1, sizes=np.array([4, 5, 7, 4, 6, 5]))
+    w.scene.update(tol_rel=1e-13, adj_tol_rel=1e-13, max_newton=60, max_cg=4000)
+    a = w.actions[0]
+    rng = np.random.default_rng(95)
+    xbar = rng.normal(size=w.x0.shape)
+    out = {}
+    for compact in (1, 0):
+        ctx = Context.from_workload(w, precision=precision, solver=1)
+        ctx.set_option(isb.OPT_COMPACT_REST, compact)
+        assert ctx.get_option(isb.INFO_COMPACT_AXIS) == (0 if compact else -1)
+        x1, v1, st, _ = ctx.step(_dev(w.x0), _dev(w.v0), _dev(a))
+        wv, sa, _ = ctx.solve_adjoint(x1, _dev(w.x0), _dev(a), _dev(xbar))
+        assert all(s["flags"] & isb.FLAG_CONVERGED for s in st)
+        assert all(s["flags"] & isb.FLAG_ADJ_CONVERGED for s in sa)
+        out[compact] = (x1.cpu().numpy(), wv.cpu().numpy())
+    for b, p in enumerate(problems(w)):
+        sv = slice(w.body_v_off[b], w.body_v_off[b + 1])
+        wb = w.body(b)
+        xr, _, _ = solve.step(p, wb.x0, wb.v0, wb.actions[0], tol=1e-13)
+        for compact in (1, 0):
+            x1, wv = out[compact]
+            assert rel(x1[sv] - wb.x0, xr - wb.x0) <= tol
+            wr = solve.adjoint(p, x1[sv], wb.x0, wb.actions[0], xbar[sv])
+            assert rel(wv[sv], wr) <= tol
+    assert rel(out[1][0] - w.x0, out[0][0] - w.x0) <= (1e-11 if precision == "fp64" else 1e-5)
