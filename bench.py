@@ -40,8 +40,8 @@ METRIC = "Newton-CG steps/sec fwd+adjoint, batched FP32/64 vs plain FP64, 1e-6 r
 
 # the sources the batched persistent kernel is compiled from (its body logic, the element and
 # spring math, the device helpers and data layout, the ABI header)
-BATCHED_SOURCES = ("isb_batched.hip", "isb_body.hpp", "isb_device.hpp", "isb_elem.hpp", "isb_spring.hpp",
-                   "isb_internal.hpp", "isb.h")
+BATCHED_SOURCES = ("isb_batched.hip", "isb_batched_kernel.hpp", "isb_batched_k2.hip", "isb_batched_k3.hip",
+                   "isb_body.hpp", "isb_device.hpp", "isb_elem.hpp", "isb_spring.hpp", "isb_internal.hpp", "isb.h")
 
 
 def kernel_source_hash(files=BATCHED_SOURCES):

@@ -135,6 +135,12 @@ typedef enum {
                              * product also returns its share of u^T H u and one vector kernel forms every
                              * scalar from one reduction, two launches per iteration instead of four;
                              * 0 = the classic form everywhere. Same iterates in exact arithmetic */
+  ISB_OPT_CG_RESIDENT = 16, /* plain solver: 1 (default) = where the single-reduction CG runs and the body's
+                             * resident patches (one workgroup per compute unit, the patch's CG vectors in
+                             * LDS; ISB_INFO_RESIDENT tells whether a body has them) can all be resident at
+                             * once, the whole CG solve is one cooperative launch with one grid barrier per
+                             * iteration; 0 = one Hessian-vector launch and one vector launch per iteration.
+                             * The same single-reduction iteration either way */
   ISB_OPT_CG_GRAPH = 10     /* plain solver: 1 = run CG as a graph of 8 iterations, captured once per solve and
                              * replayed until converged (one launch and one host read per 8 iterations);
                              * 0 (default) = one launch per kernel and a read every ISB_OPT_CG_CHECK iterations.
@@ -149,6 +155,7 @@ typedef enum {
 #define ISB_INFO_N_COLOURS 104    /* colours of the element colouring (max over bodies) */
 #define ISB_INFO_LDS_BYTES 105    /* LDS bytes per workgroup of the batched solver for the largest body */
 #define ISB_INFO_COMPACT_AXIS 106 /* the fibre axis of the compact rest record in use, -1 when not in use */
+#define ISB_INFO_RESIDENT 107     /* bodies that have a resident CG plan (ISB_OPT_CG_RESIDENT) */
 
 /* Per-body solver statistics (host memory). */
 typedef struct {

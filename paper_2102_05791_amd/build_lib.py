@@ -16,8 +16,8 @@ LIB = os.path.join(HERE, "libisb.so")
 ARCH = os.environ.get("ISB_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["isb_batched_k2.hip", "isb_batched_k3.hip", "isb_kernels.hip", "isb_springs.hip", "isb_batched.hip",
-           "isb_api.cpp", "isb_host.cpp"]
+SOURCES = ["isb_batched_k2.hip", "isb_batched_k3.hip", "isb_kernels.hip", "isb_resident.hip", "isb_springs.hip",
+           "isb_batched.hip", "isb_api.cpp", "isb_host.cpp"]
 # packed-FP32 instructions are disabled for all device code; the host pass ignores the feature
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-result"]

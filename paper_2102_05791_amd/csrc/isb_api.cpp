@@ -321,15 +321,38 @@ static void cg_iteration(isb_ctx* c, int b, const double* x, const double* a, hi
 // the solve is done; the iterations of the last chunk past that point return at once.
 static constexpr int kCgChunk = 8;
 
-// PCG on H(x) xs = sign * rhs over body b; returns iterations, sets negcurv and the final r.r.
+// The resident form of the single-reduction CG on body b (one cooperative launch for the whole
+// solve) where the body has a resident plan that fits the device; *ran = false when it does not run.
+static isb_status resident_cg(isb_ctx* c, int b, const double* x, const double* a, const double* rhs, double sign,
+                              double tol, int max_cg, hipStream_t s, bool* ran) {
+  *ran = false;
+  if (!c->cg_resident || b < 0 || (size_t)b >= c->res_ok.size() || !c->res_ok[b]) return ISB_OK;
+  PatchPlan P = c->rplan;
+  P.max_nv = c->res_max_nv[b];
+  const int p0 = c->res_patch_off[b], np = c->res_patch_off[b + 1] - p0;
+  // W0..W2 are the workspaces the launch-per-iteration form uses for H u, u and s
+  const hipError_t e = launch_cg_resident(devmesh(c), devscene(c), P, p0, np, c->res_cu, c->precision, x, a,
+                                          c->w_a32, rhs, sign, c->w_Dinvp, c->w_vdiag, c->w_xs, c->w_Hp, c->w_u,
+                                          c->w_s, c->partials, c->gbar, c->scal, tol * tol, max_cg, s);
+  if (e == hipErrorCooperativeLaunchTooLarge) {
+    c->res_ok[b] = 0;  // its workgroups cannot all be resident here: the launch-per-iteration form
+    return ISB_OK;
+  }
+  if (e != hipSuccess) return fail(ISB_E_HIP, std::string("resident CG launch: ") + hipGetErrorString(e));
+  ISB_TRY(read_cg(c, s));
+  if (c->hcg->fault) return fail(ISB_E_HIP, "resident CG: a grid barrier timed out");
+  *ran = true;
+  return ISB_OK;
+}
+
+// PCG on H(x) xs = sign * rhs over body b, one launch per kernel, leaving the outcome in c->hcg.
 // Graph mode (ISB_OPT_CG_GRAPH): a chunk of kCgChunk iterations is captured once per solve on an
-// internal stream and replayed on `s`, one launch and one host read per chunk instead of four
-// launches per iteration and a read every cg_check iterations.
-static isb_status run_cg(isb_ctx* c, int b, const double* x, const double* a, const double* rhs, double sign,
-                         double tol, int max_cg, hipStream_t s, int* iters, bool* negcurv, double* rr) {
+// internal stream and replayed on `s`, one launch and one host read per chunk instead of the
+// iteration's launches and a read every cg_check iterations.
+static isb_status launched_cg(isb_ctx* c, int b, const double* x, const double* a, const double* rhs, double sign,
+                              double tol, int max_cg, hipStream_t s, bool single) {
   const BodyRange br = body_range(c, b);
   const int o = br.off;
-  const bool single = single_reduction_cg(c, b);
   if (single)
     launch_cgcg_start(br.n, rhs + o, sign, c->w_Dinvp + o, c->w_vdiag + o, c->w_r + o, c->w_u + o, c->w_Hp + o,
                       c->w_p + o, c->w_s + o, c->w_xs + o, c->partials, c->scal, tol * tol, max_cg, s);
@@ -381,7 +404,16 @@ static isb_status run_cg(isb_ctx* c, int b, const double* x, const double* a, co
     }
   }
   if (single) launch_cgcg_final(br.n, c->partials, c->scal, s);
-  ISB_TRY(read_cg(c, s));
+  return read_cg(c, s);
+}
+
+// PCG on H(x) xs = sign * rhs over body b; returns iterations, sets negcurv and the final r.r.
+static isb_status run_cg(isb_ctx* c, int b, const double* x, const double* a, const double* rhs, double sign,
+                         double tol, int max_cg, hipStream_t s, int* iters, bool* negcurv, double* rr) {
+  const bool single = single_reduction_cg(c, b);
+  bool resident = false;
+  if (single) ISB_TRY(resident_cg(c, b, x, a, rhs, sign, tol, max_cg, s, &resident));
+  if (!resident) ISB_TRY(launched_cg(c, b, x, a, rhs, sign, tol, max_cg, s, single));
   *iters = c->hcg->iters;
   *negcurv = c->hcg->negcurv != 0;
   *rr = c->hcg->rr;
@@ -841,6 +873,7 @@ static isb_status alloc_workspaces(isb_ctx* c) {
   ISB_TRY(dalloc(L, &c->dscal, (size_t)64));
   ISB_TRY(dalloc(L, &c->ebuf, (size_t)3 * c->n_bodies));
   ISB_TRY(dalloc(L, &c->scal, (size_t)1));
+  ISB_TRY(dalloc(L, &c->gbar, (size_t)1));
   // zero the vectors once so that the Hessian-vector kernel never reads uninitialised memory
   for (double* p : {c->w_x, c->w_xt, c->w_xhat, c->w_G, c->w_Gt, c->w_xs, c->w_r, c->w_p, c->w_Hp, c->w_Dinvp,
                     c->w_vdiag, c->w_diag, c->w_u, c->w_s})
@@ -958,6 +991,56 @@ isb_status isb_destroy(isb_ctx* ctx) {
   return ISB_OK;
 }
 
+// The resident CG plan (after the patch plan, on the context's device): one patch per compute
+// unit for every body of at least kPatchMinElems elements whose patches fit the LDS a workgroup may
+// hold; bodies far too large for that are not cut at all. Nothing is uploaded when no body qualifies.
+static isb_status build_resident_plan(isb_ctx* c, const int32_t* T, const int64_t* body_e_off) {
+  const int dim = c->dim, nb = c->n_bodies;
+  c->res_ok.assign(nb, 0);
+  c->res_patch_off.assign(nb + 1, 0);
+  c->res_max_nv.assign(nb, 0);
+  c->rplan = PatchPlan{};
+  int n_cu = 0, max_lds = 0;
+  ISB_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, c->device));
+  ISB_HIP(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
+  // the partials of one solve (two banks of four per workgroup) live in the reduction workspace
+  if (n_cu < 1 || 8 * n_cu > 12 * kMaxRedBlocks) return ISB_OK;
+  const int max_verts = std::min(65535, max_lds / resident_vertex_bytes(dim));
+  bool any = false;
+  for (int b = 0; b < nb; ++b) {
+    const int64_t ne_b = body_e_off[b + 1] - body_e_off[b];
+    // a simplex mesh has at most about six elements per vertex: larger bodies cannot fit
+    any |= ne_b >= kPatchMinElems && ne_b <= (int64_t)n_cu * 8 * max_verts;
+  }
+  if (!any) return ISB_OK;
+  Patches rp;
+  std::vector<uint8_t> eligible;
+  ISB_TRY(build_resident_patches(dim, c->n_v, nb, c->voff.data(), body_e_off, T, n_cu, max_verts, &rp,
+                                 &c->res_patch_off, &eligible));
+  int n_ok = 0;
+  for (int b = 0; b < nb; ++b) {
+    c->res_ok[b] = eligible[b] && body_e_off[b + 1] - body_e_off[b] >= kPatchMinElems;
+    for (int k = c->res_patch_off[b]; k < c->res_patch_off[b + 1]; ++k)
+      c->res_max_nv[b] = std::max(c->res_max_nv[b], rp.voff[k + 1] - rp.voff[k]);
+    n_ok += c->res_ok[b];
+  }
+  if (n_ok == 0) return ISB_OK;
+  auto& L = c->mesh_allocs;
+  int32_t *r_eoff, *r_voff, *r_verts;
+  uint16_t* r_lconn;
+  ISB_TRY(dalloc(L, &r_eoff, rp.eoff.size()));
+  ISB_TRY(dalloc(L, &r_voff, rp.voff.size()));
+  ISB_TRY(dalloc(L, &r_verts, rp.verts.size()));
+  ISB_TRY(dalloc(L, &r_lconn, rp.lconn.size()));
+  ISB_HIP(hipMemcpy(r_eoff, rp.eoff.data(), rp.eoff.size() * 4, hipMemcpyHostToDevice));
+  ISB_HIP(hipMemcpy(r_voff, rp.voff.data(), rp.voff.size() * 4, hipMemcpyHostToDevice));
+  ISB_HIP(hipMemcpy(r_verts, rp.verts.data(), rp.verts.size() * 4, hipMemcpyHostToDevice));
+  ISB_HIP(hipMemcpy(r_lconn, rp.lconn.data(), rp.lconn.size() * 2, hipMemcpyHostToDevice));
+  c->rplan = PatchPlan{r_eoff, r_voff, r_verts, r_lconn, rp.max_nv};
+  c->res_cu = n_cu;
+  return ISB_OK;
+}
+
 isb_status isb_mesh_upload(isb_ctx* c, int dim, int32_t n_bodies, const int64_t* body_v_off,
                            const int64_t* body_e_off, const double* X_rest, const int32_t* T,
                            const uint8_t* dof_pinned) {
@@ -1058,6 +1141,7 @@ isb_status isb_mesh_upload(isb_ctx* c, int dim, int32_t n_bodies, const int64_t*
   ISB_HIP(hipMemcpy(p_verts, pt.verts.data(), pt.verts.size() * 4, hipMemcpyHostToDevice));
   ISB_HIP(hipMemcpy(p_lconn, pt.lconn.data(), pt.lconn.size() * 2, hipMemcpyHostToDevice));
   c->plan = PatchPlan{p_eoff, p_voff, p_verts, p_lconn, pt.max_nv};
+  ISB_TRY(build_resident_plan(c, T, body_e_off));
   if (c->precision == ISB_MIXED) {
     ISB_TRY(dalloc(L, &c->W32, ne));
     ISB_TRY(dalloc(L, &c->Dinv32, (size_t)dim * dim * ne));
@@ -1200,6 +1284,10 @@ isb_status isb_set_option(isb_ctx* c, int key, int64_t value) {
       if (value != 0 && value != 1) return fail(ISB_E_ARG, "single-reduction CG must be 0 or 1");
       c->cg_single = (int)value;
       return ISB_OK;
+    case ISB_OPT_CG_RESIDENT:
+      if (value != 0 && value != 1) return fail(ISB_E_ARG, "resident CG must be 0 or 1");
+      c->cg_resident = (int)value;
+      return ISB_OK;
     case ISB_OPT_PATCH_BLOCK:
       if (value != 0 && value != 256 && value != 512 && value != 1024)
         return fail(ISB_E_ARG, "patch block must be 0 (default), 256, 512 or 1024");
@@ -1246,6 +1334,13 @@ isb_status isb_get_option(isb_ctx* c, int key, int64_t* value) {
     case ISB_OPT_COMPACT_REST: *value = c->compact_rest; return ISB_OK;
     case ISB_OPT_PATCH_BLOCK: *value = c->patch_block; return ISB_OK;
     case ISB_OPT_CG_SINGLE_REDUCTION: *value = c->cg_single; return ISB_OK;
+    case ISB_OPT_CG_RESIDENT: *value = c->cg_resident; return ISB_OK;
+    case ISB_INFO_RESIDENT: {
+      int64_t n = 0;
+      for (uint8_t ok : c->res_ok) n += ok;
+      *value = n;
+      return ISB_OK;
+    }
     case ISB_INFO_COMPACT_AXIS: *value = c->have_material && c->compact_rest ? c->uni_axis : -1; return ISB_OK;
     case ISB_OPT_LBFGS_MEMORY: *value = c->lbfgs_m; return ISB_OK;
     case ISB_OPT_LBFGS_MAX_ITERS: *value = c->lbfgs_max_iters; return ISB_OK;

@@ -46,6 +46,15 @@ struct isb_ctx {
   std::vector<int32_t> body_patch_off;
   isb::PatchPlan plan{};
 
+  // the resident CG solver's plan (isb::build_resident_patches): body b's patches
+  // [res_patch_off[b], res_patch_off[b+1]) of rplan, largest vertex list res_max_nv[b]; res_ok[b]
+  // when the body takes the resident solver; res_cu: the compute units the plan was cut for
+  std::vector<int32_t> res_patch_off, res_max_nv;
+  std::vector<uint8_t> res_ok;
+  isb::PatchPlan rplan{};
+  int res_cu = 0;
+  isb::GridBar* gbar = nullptr;  // the resident solver's barrier (device)
+
   // vertex-pair springs (isb_spring_upload); body b owns springs [soff[b], soff[b+1]); colour k of
   // body b is sclist[scol_off[b*(nsc+1)+k] .. +1) as for the elements
   int n_s = 0, n_scolours = 0;
@@ -68,6 +77,7 @@ struct isb_ctx {
   int compact_rest = 1;                // ISB_OPT_COMPACT_REST
   int patch_block = 0;                 // ISB_OPT_PATCH_BLOCK (0: kPatchBlock)
   int cg_single = 1;                   // ISB_OPT_CG_SINGLE_REDUCTION
+  int cg_resident = 1;                 // ISB_OPT_CG_RESIDENT
   hipStream_t cap_stream = nullptr;    // internal stream the CG chunk is captured on
 
   // plain-solver workspaces, [n_v*dim] unless noted

@@ -91,7 +91,7 @@ isb_status colour_elements(int dim, int64_t n_v, int64_t n_e, const int32_t* T, 
 }
 
 isb_status build_patches(int dim, int64_t n_v, int n_bodies, const int64_t* eoff, const int32_t* T,
-                         int max_elems, int max_verts, Patches* out) {
+                         int max_elems, int max_verts, Patches* out, int per_body) {
   const int64_t n_e = eoff[n_bodies];
   out->eoff.assign(1, 0);
   out->voff.assign(1, 0);
@@ -103,9 +103,10 @@ isb_status build_patches(int dim, int64_t n_v, int n_bodies, const int64_t* eoff
   std::vector<int32_t> ids;
   int32_t patch = 0;
   for (int b = 0; b < n_bodies; ++b) {
-    // about a thousand patches per body when it is large enough, so that the launch fills the GPU;
+    // per_body patches per body when it is large enough (a thousand fill the GPU in one launch);
     // a whole number of 64-element wavefronts, so that every wavefront of a full patch is full
-    const int64_t per = ((eoff[b + 1] - eoff[b]) / 1024 + 63) / 64 * 64;
+    const int64_t ne_b = eoff[b + 1] - eoff[b];
+    const int64_t per = ((ne_b + per_body - 1) / per_body + 63) / 64 * 64;
     const int64_t me = std::min<int64_t>(max_elems, std::max<int64_t>(256, per));
     int64_t e = eoff[b];
     while (e < eoff[b + 1]) {
@@ -138,6 +139,36 @@ isb_status build_patches(int dim, int64_t n_v, int n_bodies, const int64_t* eoff
       ++patch;
     }
   }
+  return ISB_OK;
+}
+
+isb_status build_resident_patches(int dim, int64_t n_v, int n_bodies, const int64_t* voff, const int64_t* eoff,
+                                  const int32_t* T, int n_blocks, int max_verts, Patches* out,
+                                  std::vector<int32_t>* body_patch_off, std::vector<uint8_t>* eligible) {
+  if (n_blocks < 1) return fail(ISB_E_ARG, "resident plan: no workgroups");
+  const isb_status st = build_patches(dim, n_v, n_bodies, eoff, T, 1 << 30, max_verts, out, n_blocks);
+  if (st != ISB_OK) return st;
+  std::vector<uint8_t> owned((size_t)n_v, 0);
+  for (size_t i = 0; i < out->verts.size(); ++i) {
+    const int32_t v = out->verts[i];
+    if (owned[v])
+      out->verts[i] = ~v;
+    else
+      owned[v] = 1;
+  }
+  // patches of body b: those whose first element lies in it (a patch never spans two bodies)
+  const int np = (int)out->eoff.size() - 1;
+  body_patch_off->assign((size_t)n_bodies + 1, 0);
+  eligible->assign((size_t)n_bodies, 0);
+  int k = 0;
+  for (int b = 0; b < n_bodies; ++b) {
+    (*body_patch_off)[b] = k;
+    while (k < np && out->eoff[k] < eoff[b + 1]) ++k;
+    bool all_owned = true;  // a vertex no element uses would belong to no patch
+    for (int64_t v = voff[b]; v < voff[b + 1] && all_owned; ++v) all_owned = owned[v] != 0;
+    (*eligible)[b] = eoff[b + 1] > eoff[b] && k - (*body_patch_off)[b] <= n_blocks && all_owned;
+  }
+  (*body_patch_off)[n_bodies] = k;
   return ISB_OK;
 }
 

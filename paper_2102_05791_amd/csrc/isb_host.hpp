@@ -25,8 +25,20 @@ struct Patches {
   std::vector<uint16_t> lconn;
   int max_nv = 0;
 };
+// per_body: patches a body is cut into when that leaves at least 256 elements in each (rounded
+// to whole 64-element wavefronts); max_elems and max_verts cap every patch.
 isb_status build_patches(int dim, int64_t n_v, int n_bodies, const int64_t* eoff, const int32_t* T,
-                         int max_elems, int max_verts, Patches* out);
+                         int max_elems, int max_verts, Patches* out, int per_body = 1024);
+
+// The resident CG solver's plan: each body cut into at most n_blocks patches (one per resident
+// workgroup) of at most max_verts vertices. Each vertex is owned by the first patch that holds it;
+// verts stores v for an owned vertex and ~v (negative) for one that another patch owns. Body b's
+// patches are [body_patch_off[b], body_patch_off[b + 1]); eligible[b] when it has elements, no more
+// than n_blocks patches and no vertex that no element uses.
+isb_status build_resident_patches(int dim, int64_t n_v, int n_bodies, const int64_t* voff, const int64_t* eoff,
+                                  const int32_t* T, int n_blocks, int max_verts, Patches* out,
+                                  std::vector<int32_t>* body_patch_off, std::vector<uint8_t>* eligible);
+
 
 // The patch plan the context builds: at most kPatchMaxElems elements per patch, and as many
 // vertices as fit x, p, the FP64 accumulator and the vertex id in kPatchLdsBytes of LDS.

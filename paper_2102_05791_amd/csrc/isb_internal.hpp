@@ -91,11 +91,24 @@ struct CgScal {
   int iters;       // completed iterations
   int it_cur;      // the iteration in progress
   int max_it;      // iteration cap
-  int pad;
+  int fault;       // resident solver: a grid barrier waited past its limit and the launch gave up
   double alpha_prev, gamma_prev;  // single-reduction CG: alpha and r.u of the previous iteration
 };
 
 constexpr int kMaxPatchGrid = 65535;  // workgroups of one patch launch (grid-stride beyond)
+
+// Resident CG solver: threads per workgroup (one workgroup per CU), and LDS per patch vertex: nine
+// FP64 vectors of D components (x, u, r, p, s, the preconditioner, the vertex diagonal, the
+// accumulator, the solution) and the vertex id
+constexpr int kResidentBlockF32 = 1024;
+constexpr int kResidentBlockF64 = 512;
+constexpr int resident_vertex_bytes(int dim) { return 9 * dim * (int)sizeof(double) + 4; }
+
+// arrival counter and abort flag of the resident solver's grid barrier
+struct GridBar {
+  unsigned count;
+  unsigned abort;
+};
 
 // ---- precompute ----
 void launch_precompute_geom(int D, int n_e, const double* X, const int32_t* conn, double* Dinv, double* W,
@@ -156,6 +169,18 @@ void launch_cgcg_vec(int n, const double* hvpart, int nhv, double* partials, con
                      const double* vdiag, double* r, double* u, double* w, double* p, double* sv, double* xs,
                      CgScal* scal, hipStream_t s);
 void launch_cgcg_final(int n, const double* partials, CgScal* scal, hipStream_t s);
+
+// ---- resident single-reduction PCG (isb_resident.hip): body patches [p0, p0 + np) of the resident
+// plan P (P.max_nv: the largest of them), one cooperative workgroup each, solve H(x) xs = sign * rhs
+// to r.r <= tol2 in one launch and leave the outcome in *scal (fault = 1: a barrier timed out).
+// Vectors are the global [n_v][D] arrays; W0..W2 are [n_v][D] scratch, part 8 * np values.
+// Returns hipErrorCooperativeLaunchTooLarge, launching nothing, when np workgroups cannot all be
+// resident. ----
+hipError_t launch_cg_resident(const DevMesh& m, const DevScene& sc, const PatchPlan& P, int p0, int np, int n_cu,
+                              int precision, const double* x, const double* a, const float* a32, const double* rhs,
+                              double sign, const double* Dinvp, const double* vdiag, double* xs, double* W0,
+                              double* W1, double* W2, double* part, GridBar* bar, CgScal* scal, double tol2,
+                              int max_it, hipStream_t s);
 
 // ---- spring kernels (isb_springs.hip): spring range r (ids through r.list when given); as = the
 // springs' actions (the action vector past the elements' entries); op = PatchOp; FP64 throughout ----

@@ -14,6 +14,7 @@
 #include "isb_device.hpp"
 #include "isb_elem.hpp"
 #include "isb_internal.hpp"
+#include "isb_patch.hpp"
 
 namespace isb {
 
@@ -1234,46 +1235,7 @@ __global__ void __launch_bounds__(PB) k_elem_patch(DevMesh m, DevScene sc, Patch
       }
     }
     __syncthreads();
-    for (int e = eb + threadIdx.x; e < ee; e += blockDim.x) {
-      int l[D + 1];
-#pragma unroll
-      for (int k = 0; k <= D; ++k) l[k] = P.lconn[(size_t)k * m.n_e + e];
-      ElemRest<D, T> R;
-      load_rest<D, T, CR>(m, e, R);
-      T Ds[D][D];
-#pragma unroll
-      for (int j = 0; j < D; ++j)
-#pragma unroll
-        for (int c = 0; c < D; ++c) Ds[c][j] = T(xs[l[j + 1] * D + c] - xs[l[0] * D + c]);
-      ElemState<D, T> S;
-      elem_state<D, T>(Ds, R, S);
-      // actuation in the element precision: the FP32 copy when the caller made one
-      const T ae = (std::is_same<T, float>::value && a32) ? T(a32[e]) : T(a[e]);
-      T o[D + 1][D];
-      if constexpr (OP == PATCH_GRAD) {
-        elem_grad<D, T, EM>(R, S, ae, o);
-      } else if constexpr (OP == PATCH_HV) {
-        T dDs[D][D];
-#pragma unroll
-        for (int j = 0; j < D; ++j)
-#pragma unroll
-          for (int c = 0; c < D; ++c) dDs[c][j] = T(ps[l[j + 1] * D + c] - ps[l[0] * D + c]);
-        elem_hessvec<D, T, EM>(R, S, ae, dDs, o);
-        if (curv) {
-          // p_e . (H_e p_e) = sum_j o_{j+1} . (p_{j+1} - p_0), since o_0 = -sum_j o_{j+1}
-#pragma unroll
-          for (int j = 0; j < D; ++j)
-#pragma unroll
-            for (int c = 0; c < D; ++c) php += double(o[j + 1][c]) * (ps[l[j + 1] * D + c] - ps[l[0] * D + c]);
-        }
-      } else {
-        elem_hessdiag<D, T, EM>(R, S, ae, o);
-      }
-#pragma unroll
-      for (int k = 0; k <= D; ++k)
-#pragma unroll
-        for (int c = 0; c < D; ++c) unsafeAtomicAdd(acc + l[k] * D + c, sc.s_pot * double(o[k][c]));
-    }
+    patch_elements<D, T, OP, EM, CR>(m, sc, P.lconn, eb, ee, xs, ps, acc, a, a32, curv != nullptr, php);
     __syncthreads();
     for (int i = threadIdx.x; i < nv * D; i += blockDim.x) {
       const int vl = i / D, c = i - vl * D;

@@ -1,0 +1,68 @@
+// The element loop of one LDS-staged patch, shared by the patch scatter kernel and the resident
+// CG solver: each thread takes elements eb + threadIdx.x, eb + threadIdx.x + blockDim.x, ... of
+// the patch, gathers its corners from the patch's LDS copy of x (and of the Hessian-vector operand
+// p), evaluates the element operation (Eq. 3's gradient, Hessian-vector product or Jacobi
+// diagonal) and adds s_pot times its per-corner result into the LDS accumulator with LDS atomics.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "isb_device.hpp"
+#include "isb_elem.hpp"
+#include "isb_internal.hpp"
+
+namespace isb {
+
+// lconn: [(D+1)][n_e] patch-local corner ids; xs, ps, acc: [local vertex][D] in LDS, FP64 (edge
+// differences of x and p are formed in FP64, then rounded to T). php (Hessian-vector products with
+// want_curv): this thread's sum over its elements of p_e . (H_e p_e), unscaled by s_pot.
+template <int D, typename T, int OP, int EM, bool CR>
+__device__ __forceinline__ void patch_elements(const DevMesh& m, const DevScene& sc, const uint16_t* __restrict__ lconn,
+                                               int eb, int ee, const double* xs, const double* ps, double* acc,
+                                               const double* __restrict__ a, const float* __restrict__ a32,
+                                               bool want_curv, double& php) {
+  for (int e = eb + threadIdx.x; e < ee; e += blockDim.x) {
+    int l[D + 1];
+#pragma unroll
+    for (int k = 0; k <= D; ++k) l[k] = lconn[(size_t)k * m.n_e + e];
+    ElemRest<D, T> R;
+    load_rest<D, T, CR>(m, e, R);
+    T Ds[D][D];
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+#pragma unroll
+      for (int c = 0; c < D; ++c) Ds[c][j] = T(xs[l[j + 1] * D + c] - xs[l[0] * D + c]);
+    ElemState<D, T> S;
+    elem_state<D, T>(Ds, R, S);
+    // actuation in the element precision: the FP32 copy when the caller made one
+    const T ae = (std::is_same<T, float>::value && a32) ? T(a32[e]) : T(a[e]);
+    T o[D + 1][D];
+    if constexpr (OP == PATCH_GRAD) {
+      elem_grad<D, T, EM>(R, S, ae, o);
+    } else if constexpr (OP == PATCH_HV) {
+      T dDs[D][D];
+#pragma unroll
+      for (int j = 0; j < D; ++j)
+#pragma unroll
+        for (int c = 0; c < D; ++c) dDs[c][j] = T(ps[l[j + 1] * D + c] - ps[l[0] * D + c]);
+      elem_hessvec<D, T, EM>(R, S, ae, dDs, o);
+      if (want_curv) {
+        // p_e . (H_e p_e) = sum_j o_{j+1} . (p_{j+1} - p_0), since o_0 = -sum_j o_{j+1}
+#pragma unroll
+        for (int j = 0; j < D; ++j)
+#pragma unroll
+          for (int c = 0; c < D; ++c) php += double(o[j + 1][c]) * (ps[l[j + 1] * D + c] - ps[l[0] * D + c]);
+      }
+    } else {
+      elem_hessdiag<D, T, EM>(R, S, ae, o);
+    }
+#pragma unroll
+    for (int k = 0; k <= D; ++k)
+#pragma unroll
+      for (int c = 0; c < D; ++c) unsafeAtomicAdd(acc + l[k] * D + c, sc.s_pot * double(o[k][c]));
+  }
+}
+
+}  // namespace isb

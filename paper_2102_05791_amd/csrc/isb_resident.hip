@@ -1,0 +1,329 @@
+// Resident single-reduction PCG for one body whose element patches can all be resident on the
+// GPU at once (one workgroup per patch, every workgroup co-resident): the whole inner solve of a
+// Newton step (the linear system of Eq. 1 through Eq. 14) or of the adjoint (Eq. 9) is one
+// cooperative launch, with one grid barrier per iteration and the CG vectors of each patch in LDS.
+//
+// Each workgroup keeps x, u = M r, r, p, s = H p, M (= D^-1), the vertex diagonal, the solution and
+// an accumulator for every vertex of its patch, including the vertices it shares with other patches.
+// It updates all of them itself, with the same scalars and the same arithmetic as every other
+// workgroup that holds them, so the shared copies stay identical. Only the element part of H u
+// crosses workgroups: each patch adds its per-vertex sums into a global vector with FP64 atomics,
+// and every workgroup reads back the complete sums after the barrier. Three such vectors rotate
+// (summed into, read, cleared), so one barrier per iteration suffices. The curvature u^T H u comes
+// from the element pass itself (sum over elements of u_e . H_e u_e, plus the vertex diagonal's
+// part), so r.u, u^T H u and r.r of an iteration reach the next one as one set of per-workgroup
+// partials, which every workgroup folds in the same order: all of them take the same decisions.
+//
+// The iteration is the Chronopoulos-Gear form of the patch path's single-reduction CG:
+//   beta = gamma / gamma_prev, p^T H p = delta - beta gamma / alpha_prev, alpha = gamma / p^T H p,
+//   p = u + beta p, s = w + beta s, x += alpha p, r -= alpha s, u = M r, w = H u,
+// stopping when r.r <= tol^2, at the iteration cap, or on non-positive curvature (Nocedal and
+// Wright, Alg. 7.1: on the first iteration the preconditioned steepest-descent direction M b).
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "isb_device.hpp"
+#include "isb_elem.hpp"
+#include "isb_internal.hpp"
+#include "isb_patch.hpp"
+
+namespace isb {
+
+// longest wait at one grid barrier, in ticks of the 100 MHz wall clock (4 s): a workgroup that
+// waits longer marks the launch aborted, and every workgroup then leaves the solve
+constexpr uint64_t kBarrierTicks = 400000000ull;
+
+__device__ __forceinline__ double ld_agent(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Every value one workgroup passes to another (the sums of H u, the partials, the cleared sums)
+// goes through agent-scope loads, stores and atomics, which are coherent across the GPU's L2 slices
+// without cache maintenance. A barrier therefore needs no release/acquire fences (each would write
+// back and invalidate the whole L2 of the workgroup's XCD, several microseconds at every barrier):
+// each wave waits until its own stores and atomics have completed (vmcnt(0)), and the arrival and
+// the wait are relaxed atomics on a monotone counter (zeroed before the launch): barrier number k
+// waits until k * gridDim.x workgroups have arrived.
+__device__ __forceinline__ void wait_vm_stores() {
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0); expcnt and lgkmcnt not waited for
+}
+
+// Returns false on every thread of the workgroup when the launch has been aborted.
+__device__ __forceinline__ bool grid_barrier(GridBar* g, unsigned& epoch, int* ok_lds) {
+  wait_vm_stores();
+  __syncthreads();
+  ++epoch;
+  if (threadIdx.x == 0) {
+    const unsigned target = epoch * gridDim.x;
+    __hip_atomic_fetch_add(&g->count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t t0 = wall_clock64();
+    int ok = 1;
+    while (__hip_atomic_load(&g->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (__hip_atomic_load(&g->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
+          wall_clock64() - t0 > kBarrierTicks) {
+        __hip_atomic_store(&g->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    *ok_lds = ok;
+  }
+  __syncthreads();
+  return *ok_lds != 0;
+}
+
+// this workgroup's sums of three values, stored to out[0..3) (agent scope, for the other workgroups)
+template <int PB>
+__device__ __forceinline__ void workgroup_sums3(double a, double b, double c, double* red, double* out) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  a = wave_sum(a);
+  b = wave_sum(b);
+  c = wave_sum(c);
+  if (lane == 0) {
+    red[3 * wid] = a;
+    red[3 * wid + 1] = b;
+    red[3 * wid + 2] = c;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    double t = 0.0;
+    for (int w = 0; w < PB / 64; ++w) t += red[3 * w + threadIdx.x];
+    st_agent(out + threadIdx.x, t);
+  }
+  __syncthreads();
+}
+
+// (gamma, r.r, delta) from the partials of all workgroups (4 values each, the fourth unused), in
+// the same order on every workgroup and every thread
+template <int PB>
+__device__ __forceinline__ void fold_partials(const double* bank, double* red, double& gamma, double& rr,
+                                              double& delta) {
+  double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+  for (int b = threadIdx.x; b < (int)gridDim.x; b += PB) {
+    v0 += ld_agent(bank + 4 * b);
+    v1 += ld_agent(bank + 4 * b + 1);
+    v2 += ld_agent(bank + 4 * b + 2);
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  v0 = wave_sum(v0);
+  v1 = wave_sum(v1);
+  v2 = wave_sum(v2);
+  if (lane == 0) {
+    red[3 * wid] = v0;
+    red[3 * wid + 1] = v1;
+    red[3 * wid + 2] = v2;
+  }
+  __syncthreads();
+  gamma = rr = delta = 0.0;
+  for (int w = 0; w < PB / 64; ++w) {
+    gamma += red[3 * w];
+    rr += red[3 * w + 1];
+    delta += red[3 * w + 2];
+  }
+  __syncthreads();
+}
+
+// The workgroup of patch p0 + blockIdx.x. LDS: nine [max_nv][D] FP64 arrays, then the vertex ids
+// (v owned, ~v shared and owned elsewhere). W0..W2: [n_v][D] global sums of H_elem u; part: two
+// banks of 4 * gridDim.x partials; bar zeroed before the launch.
+template <int D, typename T, int EM, bool CR, int PB>
+__global__ void __launch_bounds__(PB)
+    k_cg_resident(DevMesh m, DevScene sc, PatchPlan P, int p0, const double* __restrict__ x,
+                  const double* __restrict__ a, const float* __restrict__ a32, const double* __restrict__ rhs,
+                  double sign, const double* __restrict__ Dinvp, const double* __restrict__ vdiag, double* xs_out,
+                  double* W0, double* W1, double* W2, double* part, GridBar* bar, CgScal* scal, double tol2,
+                  int max_it) {
+  extern __shared__ double lds[];
+  __shared__ double red[3 * (PB / 64)];
+  __shared__ int ok_lds;
+  const int pk = p0 + blockIdx.x;
+  const int vb = P.voff[pk], nv = P.voff[pk + 1] - vb, nd = nv * D;
+  const int eb = P.eoff[pk], ee = P.eoff[pk + 1];
+  const int nmax = P.max_nv * D;
+  double* xl = lds;
+  double* ul = xl + nmax;
+  double* rl = ul + nmax;
+  double* pl = rl + nmax;
+  double* sl = pl + nmax;
+  double* dl = sl + nmax;
+  double* vl = dl + nmax;
+  double* acc = vl + nmax;
+  double* xsl = acc + nmax;
+  int* vid = reinterpret_cast<int*>(xsl + nmax);
+  double* const Wr[3] = {W0, W1, W2};
+  unsigned epoch = 0;
+
+  for (int v = threadIdx.x; v < nv; v += PB) vid[v] = P.verts[vb + v];
+  __syncthreads();
+  // r = b on the free DOFs, u = M r, p = s = x_s = 0; clear W0 and W1 (owned DOFs)
+  double g_ = 0.0, r_ = 0.0, d_ = 0.0;
+  for (int i = threadIdx.x; i < nd; i += PB) {
+    const int v = i / D, c = i - v * D, raw = vid[v];
+    const size_t g = (size_t)(raw >= 0 ? raw : ~raw) * D + c;
+    const double di = Dinvp[g], vi = vdiag[g];
+    const double ri = di != 0.0 ? sign * rhs[g] : 0.0, ui = di * ri;
+    xl[i] = x[g];
+    dl[i] = di;
+    vl[i] = vi;
+    rl[i] = ri;
+    ul[i] = ui;
+    pl[i] = 0.0;
+    sl[i] = 0.0;
+    xsl[i] = 0.0;
+    acc[i] = 0.0;
+    if (raw >= 0) {
+      st_agent(W0 + g, 0.0);
+      st_agent(W1 + g, 0.0);
+      g_ += ri * ui;
+      r_ += ri * ri;
+      d_ += ui * (vi * ui);
+    }
+  }
+  bool ok = grid_barrier(bar, epoch, &ok_lds);
+  if (ok) {
+    // H u_0 into W0
+    double php = 0.0;
+    patch_elements<D, T, PATCH_HV, EM, CR>(m, sc, P.lconn, eb, ee, xl, ul, acc, a, a32, true, php);
+    __syncthreads();
+    for (int i = threadIdx.x; i < nd; i += PB) {
+      const int v = i / D, c = i - v * D, raw = vid[v];
+      unsafeAtomicAdd(W0 + (size_t)(raw >= 0 ? raw : ~raw) * D + c, acc[i]);
+    }
+    workgroup_sums3<PB>(g_, r_, d_ + sc.s_pot * php, red, part + 4 * blockIdx.x);
+    ok = grid_barrier(bar, epoch, &ok_lds);
+  }
+
+  int it = 0, negcurv = 0;
+  double rr = 0.0, rr0 = 0.0, pHp = 0.0, alpha_prev = 0.0, gamma_prev = 0.0;
+  while (ok) {
+    double gamma, delta;
+    fold_partials<PB>(part + (it & 1) * 4 * gridDim.x, red, gamma, rr, delta);
+    if (it == 0) rr0 = rr;
+    if (rr <= tol2 || it >= max_it) break;
+    const double beta = it == 0 ? 0.0 : gamma / gamma_prev;
+    pHp = it == 0 ? delta : delta - beta * gamma / alpha_prev;
+    if (!(pHp > 0.0)) {
+      negcurv = 1;
+      if (it == 0)
+        for (int i = threadIdx.x; i < nd; i += PB) xsl[i] = ul[i];
+      break;
+    }
+    const double alpha = gamma / pHp;
+    // W[it % 3] holds H_elem u_it; this iteration sums H_elem u_{it+1} into the next and clears the
+    // one after (read last in the previous iteration, before the barrier every workgroup has passed)
+    const double* Wc = Wr[it % 3];
+    double* Wn = Wr[(it + 1) % 3];
+    double* Wz = Wr[(it + 2) % 3];
+    g_ = r_ = d_ = 0.0;
+    for (int i = threadIdx.x; i < nd; i += PB) {
+      const int v = i / D, c = i - v * D, raw = vid[v];
+      const size_t g = (size_t)(raw >= 0 ? raw : ~raw) * D + c;
+      const double vi = vl[i], di = dl[i];
+      const double wi = vi * ul[i] + ld_agent(Wc + g);
+      const double pi = ul[i] + beta * pl[i];
+      const double si = wi + beta * sl[i];
+      xsl[i] += alpha * pi;
+      const double ri = di != 0.0 ? rl[i] - alpha * si : 0.0;
+      const double ui = di * ri;
+      pl[i] = pi;
+      sl[i] = si;
+      rl[i] = ri;
+      ul[i] = ui;
+      acc[i] = 0.0;
+      if (raw >= 0) {
+        st_agent(Wz + g, 0.0);
+        g_ += ri * ui;
+        r_ += ri * ri;
+        d_ += ui * (vi * ui);
+      }
+    }
+    __syncthreads();
+    double php = 0.0;
+    patch_elements<D, T, PATCH_HV, EM, CR>(m, sc, P.lconn, eb, ee, xl, ul, acc, a, a32, true, php);
+    __syncthreads();
+    for (int i = threadIdx.x; i < nd; i += PB) {
+      const int v = i / D, c = i - v * D, raw = vid[v];
+      unsafeAtomicAdd(Wn + (size_t)(raw >= 0 ? raw : ~raw) * D + c, acc[i]);
+    }
+    workgroup_sums3<PB>(g_, r_, d_ + sc.s_pot * php, red, part + ((it + 1) & 1) * 4 * gridDim.x + 4 * blockIdx.x);
+    gamma_prev = gamma;
+    alpha_prev = alpha;
+    ++it;
+    ok = grid_barrier(bar, epoch, &ok_lds);
+  }
+
+  for (int i = threadIdx.x; i < nd; i += PB) {
+    const int v = i / D, c = i - v * D, raw = vid[v];
+    if (raw >= 0) xs_out[(size_t)raw * D + c] = xsl[i];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    scal->rr = rr;
+    scal->rr0 = rr0;
+    scal->pHp = pHp;
+    scal->tol2 = tol2;
+    scal->done = 1;
+    scal->negcurv = negcurv;
+    scal->iters = it;
+    scal->it_cur = it;
+    scal->max_it = max_it;
+    scal->fault = ok ? 0 : 1;
+    scal->alpha_prev = alpha_prev;
+    scal->gamma_prev = gamma_prev;
+  }
+}
+
+__global__ void k_grid_bar_reset(GridBar* g) {
+  g->count = 0u;
+  g->abort = 0u;
+}
+
+template <int D, typename T, int EM, bool CR>
+static const void* resident_kernel_for() {
+  constexpr int PB = std::is_same<T, float>::value ? kResidentBlockF32 : kResidentBlockF64;
+  return reinterpret_cast<const void*>(&k_cg_resident<D, T, EM, CR, PB>);
+}
+
+template <int D, typename T>
+static const void* resident_kernel_dt(int model, bool compact) {
+  switch (model) {
+    case EM_STVK: return compact ? resident_kernel_for<D, T, EM_STVK, true>() : resident_kernel_for<D, T, EM_STVK, false>();
+    case EM_COROT: return compact ? resident_kernel_for<D, T, EM_COROT, true>() : resident_kernel_for<D, T, EM_COROT, false>();
+    case EM_SNH: return compact ? resident_kernel_for<D, T, EM_SNH, true>() : resident_kernel_for<D, T, EM_SNH, false>();
+    default: return compact ? resident_kernel_for<D, T, EM_NH, true>() : resident_kernel_for<D, T, EM_NH, false>();
+  }
+}
+
+hipError_t launch_cg_resident(const DevMesh& m, const DevScene& sc, const PatchPlan& P, int p0, int np, int n_cu,
+                              int precision, const double* x, const double* a, const float* a32, const double* rhs,
+                              double sign, const double* Dinvp, const double* vdiag, double* xs, double* W0,
+                              double* W1, double* W2, double* part, GridBar* bar, CgScal* scal, double tol2,
+                              int max_it, hipStream_t s) {
+  if (np < 1) return hipErrorInvalidValue;
+  const bool compact = m.axis >= 0;
+  const void* k = m.dim == 2 ? (precision ? resident_kernel_dt<2, float>(m.model, compact)
+                                          : resident_kernel_dt<2, double>(m.model, compact))
+                             : (precision ? resident_kernel_dt<3, float>(m.model, compact)
+                                          : resident_kernel_dt<3, double>(m.model, compact));
+  const int block = precision ? kResidentBlockF32 : kResidentBlockF64;
+  const size_t lds = (size_t)P.max_nv * resident_vertex_bytes(m.dim);
+  hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  int occ = 0;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k, block, lds);
+  if (e != hipSuccess) return e;
+  if (occ * n_cu < np) return hipErrorCooperativeLaunchTooLarge;
+  k_grid_bar_reset<<<1, 1, 0, s>>>(bar);
+  DevMesh mm = m;
+  DevScene ss = sc;
+  PatchPlan pp = P;
+  void* args[] = {&mm, &ss, &pp, &p0, &x, &a, &a32, &rhs, &sign, &Dinvp, &vdiag, &xs,
+                  &W0, &W1, &W2, &part, &bar, &scal, &tol2, &max_it};
+  return hipLaunchCooperativeKernel(k, dim3(np), dim3(block), args, (unsigned)lds, s);
+}
+
+}  // namespace isb

@@ -22,14 +22,14 @@ ISB_FP64, ISB_MIXED = 0, 1
 ISB_QUASISTATIC, ISB_BACKWARD_EULER = 0, 1
 (OPT_SOLVER, OPT_SCATTER, OPT_GRAPH_SAFE, OPT_BLOCK, OPT_CG_CHECK, OPT_PRECISION, OPT_ENERGY, OPT_FORWARD,
  OPT_LBFGS_MEMORY, OPT_LBFGS_MAX_ITERS, OPT_CG_GRAPH, OPT_FP64_FALLBACK, OPT_ADJ_WARM_START,
- OPT_COMPACT_REST, OPT_PATCH_BLOCK, OPT_CG_SINGLE_REDUCTION) = range(16)
+ OPT_COMPACT_REST, OPT_PATCH_BLOCK, OPT_CG_SINGLE_REDUCTION, OPT_CG_RESIDENT) = range(17)
 FLAG_CONVERGED, FLAG_STAGNATED, FLAG_NONFINITE, FLAG_ADJ_CONVERGED, FLAG_FP64_FALLBACK = 1, 2, 4, 8, 16
 FLAG_INVALID_ACTION = 32
 FORWARD_NEWTON, FORWARD_LBFGS = 0, 1
 # isotropic element energies (ISB_ENERGY_*), by the names the synthetic workloads use
 ENERGY = {"nh": 0, "stvk": 1, "corot": 2, "snh": 3}
 (INFO_N_VERTICES, INFO_N_ELEMENTS, INFO_N_BODIES, INFO_DIM, INFO_N_COLOURS, INFO_LDS_BYTES,
- INFO_COMPACT_AXIS) = range(100, 107)
+ INFO_COMPACT_AXIS, INFO_RESIDENT) = range(100, 108)
 
 EXPORTED = ("isb_create", "isb_destroy", "isb_last_error", "isb_version", "isb_validate_mesh",
             "isb_colour_elements", "isb_mesh_upload", "isb_material_upload", "isb_set_scene",

@@ -21,6 +21,7 @@
 #define __restrict__
 
 typedef void* hipStream_t;
+typedef int hipError_t;  // only named by declarations of the library's launch functions
 
 struct isb_emu_dim3 {
   unsigned x = 0, y = 0, z = 0;

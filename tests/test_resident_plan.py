@@ -1,0 +1,115 @@
+"""The resident CG solver's patch plan (isb_host.cpp, built with g++ and driven on the CPU): each body
+cut into at most one patch per resident workgroup, every element in exactly one patch of its own body,
+each patch's vertex list exactly its elements' vertices, the patch-local corners pointing at them,
+every vertex owned by exactly one patch (the first that holds it) and the eligibility rules: too many
+patches, or a vertex no element uses, keep a body off the resident solver."""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+from synth import meshes
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(ROOT, "paper_2102_05791_amd", "csrc")
+OUT = os.path.join(HERE, "emu", "_build", "libisb_plan.so")
+SRCS = [os.path.join(HERE, "emu", "plan_shim.cpp"), os.path.join(CSRC, "isb_host.cpp")]
+DEPS = SRCS + [os.path.join(CSRC, "isb_host.hpp"), os.path.join(ROOT, "include", "isb.h")]
+
+
+@pytest.fixture(scope="module")
+def lib():
+    os.makedirs(os.path.dirname(OUT), exist_ok=True)
+    if not (os.path.exists(OUT) and all(os.path.getmtime(OUT) >= os.path.getmtime(d) for d in DEPS)):
+        subprocess.run(["g++", "-std=c++17", "-O1", "-fPIC", "-shared", "-I", CSRC, *SRCS, "-o", OUT + ".tmp"],
+                       check=True, capture_output=True, text=True)
+        os.replace(OUT + ".tmp", OUT)
+    return ctypes.CDLL(OUT)
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def plan(lib, dim, X, T, voff, eoff, n_blocks, max_verts):
+    n_v, n_e, nb = X.shape[0], T.shape[0], len(voff) - 1
+    T = np.ascontiguousarray(T, np.int32)
+    voff = np.ascontiguousarray(voff, np.int64)
+    eoff = np.ascontiguousarray(eoff, np.int64)
+    pe, pv = np.zeros(n_e + 1, np.int32), np.zeros(n_e + 1, np.int32)
+    verts, lconn = np.zeros((dim + 1) * n_e, np.int32), np.zeros((dim + 1) * n_e, np.uint16)
+    bpo, ok, cnt = np.zeros(nb + 1, np.int32), np.zeros(nb, np.uint8), np.zeros(3, np.int32)
+    st = lib.emu_resident_plan(dim, ctypes.c_int64(n_v), nb, _p(voff), _p(eoff), _p(T), n_blocks, max_verts, _p(pe),
+                               _p(pv), _p(verts), _p(lconn), _p(bpo), _p(ok), _p(cnt))
+    assert st == 0
+    npch, nsl = int(cnt[0]), int(cnt[1])
+    return dict(eoff=pe[:npch + 1], voff=pv[:npch + 1], verts=verts[:nsl], lconn=lconn.reshape(dim + 1, n_e),
+                bpo=bpo, ok=ok.astype(bool), max_nv=int(cnt[2]))
+
+
+def check_plan(P, dim, T, voff, eoff, n_blocks, max_verts):
+    n_e = T.shape[0]
+    pe, pv, verts = P["eoff"], P["voff"], P["verts"]
+    npch = len(pe) - 1
+    assert pe[0] == 0 and pe[-1] == n_e and np.all(np.diff(pe) > 0)
+    decoded = np.where(verts >= 0, verts, ~verts)
+    owners = np.zeros(int(voff[-1]), np.int64)
+    first = np.full(int(voff[-1]), -1)
+    for k in range(npch):
+        e0, e1 = pe[k], pe[k + 1]
+        b = np.searchsorted(eoff, e0, side="right") - 1
+        assert eoff[b] <= e0 and e1 <= eoff[b + 1], "a patch spans two bodies"
+        assert P["bpo"][b] <= k < P["bpo"][b + 1]
+        vk = decoded[pv[k]:pv[k + 1]]
+        assert len(vk) <= max_verts and len(vk) <= P["max_nv"]
+        assert np.array_equal(vk, np.unique(T[e0:e1].ravel())), "patch vertices != its elements' vertices"
+        for c in range(dim + 1):
+            assert np.array_equal(vk[P["lconn"][c, e0:e1]], T[e0:e1, c])
+        own = verts[pv[k]:pv[k + 1]] >= 0
+        owners[vk[own]] += 1
+        newly = first[vk] < 0
+        first[vk[newly]] = k
+        assert np.all(first[vk[own]] == k), "a vertex is owned by a later patch than its first"
+    used = np.unique(T.ravel())
+    assert np.all(owners[used] == 1), "every used vertex has exactly one owner"
+    for b in range(len(eoff) - 1):
+        n_p = P["bpo"][b + 1] - P["bpo"][b]
+        all_used = np.isin(np.arange(voff[b], voff[b + 1]), used).all()
+        assert P["ok"][b] == (eoff[b + 1] > eoff[b] and n_p <= n_blocks and all_used)
+
+
+def test_resident_plan_tets_three_bodies(lib):
+    X, T = meshes.tet_grid(8, 6, 5)
+    Xb, Tb, _, vo, eo = meshes.concat_bodies([(X, T, np.zeros(X.shape, np.uint8))] * 3)
+    P = plan(lib, 3, Xb, Tb, vo, eo, 16, 4000)
+    check_plan(P, 3, Tb, vo, eo, 16, 4000)
+    assert P["ok"].all()
+    # about n_e / 16 elements per patch (whole wavefronts of 64)
+    assert all(P["bpo"][b + 1] - P["bpo"][b] <= 16 for b in range(3))
+
+
+def test_resident_plan_triangles_vertex_cap(lib):
+    X, T = meshes.tri_grid(40, 20)
+    vo, eo = np.array([0, X.shape[0]]), np.array([0, T.shape[0]])
+    P = plan(lib, 2, X, T, vo, eo, 8, 4000)
+    check_plan(P, 2, T, vo, eo, 8, 4000)
+    assert P["ok"][0]
+    # a vertex budget too small for eight patches: more patches than workgroups, not eligible
+    P = plan(lib, 2, X, T, vo, eo, 8, 60)
+    check_plan(P, 2, T, vo, eo, 8, 60)
+    assert not P["ok"][0] and P["bpo"][1] > 8
+
+
+def test_resident_plan_unused_vertex_not_eligible(lib):
+    X, T = meshes.tet_grid(6, 4, 4)
+    parts = [(X, T, np.zeros(X.shape, np.uint8))]
+    Xc, Tc, _, vo, eo = meshes.concat_bodies(parts * 2)
+    Xc = np.vstack([Xc, [[9.0, 9.0, 9.0]]])     # a vertex no element uses, appended to body 1
+    vo = vo.copy()
+    vo[-1] += 1
+    P = plan(lib, 3, Xc, Tc, vo, eo, 16, 4000)
+    check_plan(P, 3, Tc, vo, eo, 16, 4000)
+    assert P["ok"][0] and not P["ok"][1]
