@@ -100,7 +100,7 @@ constexpr int kMaxPatchGrid = 65535;  // workgroups of one patch launch (grid-st
 // Resident CG solver: threads per workgroup (one workgroup per CU), and LDS per patch vertex: nine
 // FP64 vectors of D components (x, u, r, p, s, the preconditioner, the vertex diagonal, the
 // accumulator, the solution) and the vertex id
-constexpr int kResidentBlockF32 = 1024;
+constexpr int kResidentBlockF32 = 512;
 constexpr int kResidentBlockF64 = 512;
 constexpr int resident_vertex_bytes(int dim) { return 9 * dim * (int)sizeof(double) + 4; }
 

@@ -128,6 +128,31 @@ __device__ __forceinline__ void fold_partials(const double* bank, double* red, d
   __syncthreads();
 }
 
+// Elements whose rest data and state stay in registers for the whole solve (x does not change
+// during it): the first KE * PB elements of the patch, KE per thread. FP32 neo-Hookean only, whose
+// state fits a 512-thread workgroup's register budget beside the Hessian-vector product; other
+// configurations keep none and evaluate every element's state at every product.
+template <typename T, int EM, int PB>
+constexpr int resident_cached_per_thread() {
+  return (std::is_same<T, float>::value && EM == EM_NH && PB <= 512) ? 3 : 0;
+}
+
+// H_elem u of the patch into acc: the cached elements [eb, ec) from registers, the rest [ec, ee)
+// from LDS x and the rest data in memory
+template <int D, typename T, int EM, bool CR, int PB, int KE, int KS>
+__device__ __forceinline__ void resident_hv_pass(const DevMesh& m, const DevScene& sc, const PatchPlan& P, int eb,
+                                                 int ec, int ee, const double* xl, const double* ul, double* acc,
+                                                 const double* __restrict__ a, const float* __restrict__ a32,
+                                                 const ElemRest<D, T> (&cR)[KS], const ElemState<D, T> (&cS)[KS],
+                                                 const T (&ca)[KS], const int (&cl)[KS][D + 1], double& php) {
+#pragma unroll
+  for (int k = 0; k < KE; ++k) {
+    const int e = eb + threadIdx.x + k * PB;
+    if (e < ec) patch_hv_element<D, T, EM>(cR[k], cS[k], ca[k], cl[k], ul, acc, sc.s_pot, true, php);
+  }
+  patch_elements<D, T, PATCH_HV, EM, CR>(m, sc, P.lconn, ec, ee, xl, ul, acc, a, a32, true, php);
+}
+
 // The workgroup of patch p0 + blockIdx.x. LDS: nine [max_nv][D] FP64 arrays, then the vertex ids
 // (v owned, ~v shared and owned elsewhere). W0..W2: [n_v][D] global sums of H_elem u; part: two
 // banks of 4 * gridDim.x partials; bar zeroed before the launch.
@@ -184,11 +209,35 @@ __global__ void __launch_bounds__(PB)
       d_ += ui * (vi * ui);
     }
   }
+  __syncthreads();  // x of every patch vertex in LDS
+  constexpr int KE = resident_cached_per_thread<T, EM, PB>();
+  constexpr int KS = KE > 0 ? KE : 1;
+  const int ec = min(ee, eb + KE * PB);
+  ElemRest<D, T> cR[KS];
+  ElemState<D, T> cS[KS];
+  T ca[KS];
+  int cl[KS][D + 1];
+#pragma unroll
+  for (int k = 0; k < KE; ++k) {
+    const int e = eb + threadIdx.x + k * PB;
+    if (e < ec) {
+#pragma unroll
+      for (int q = 0; q <= D; ++q) cl[k][q] = P.lconn[(size_t)q * m.n_e + e];
+      load_rest<D, T, CR>(m, e, cR[k]);
+      T Ds[D][D];
+#pragma unroll
+      for (int j = 0; j < D; ++j)
+#pragma unroll
+        for (int c = 0; c < D; ++c) Ds[c][j] = T(xl[cl[k][j + 1] * D + c] - xl[cl[k][0] * D + c]);
+      elem_state<D, T>(Ds, cR[k], cS[k]);
+      ca[k] = (std::is_same<T, float>::value && a32) ? T(a32[e]) : T(a[e]);
+    }
+  }
   bool ok = grid_barrier(bar, epoch, &ok_lds);
   if (ok) {
     // H u_0 into W0
     double php = 0.0;
-    patch_elements<D, T, PATCH_HV, EM, CR>(m, sc, P.lconn, eb, ee, xl, ul, acc, a, a32, true, php);
+    resident_hv_pass<D, T, EM, CR, PB, KE, KS>(m, sc, P, eb, ec, ee, xl, ul, acc, a, a32, cR, cS, ca, cl, php);
     __syncthreads();
     for (int i = threadIdx.x; i < nd; i += PB) {
       const int v = i / D, c = i - v * D, raw = vid[v];
@@ -244,7 +293,7 @@ __global__ void __launch_bounds__(PB)
     }
     __syncthreads();
     double php = 0.0;
-    patch_elements<D, T, PATCH_HV, EM, CR>(m, sc, P.lconn, eb, ee, xl, ul, acc, a, a32, true, php);
+    resident_hv_pass<D, T, EM, CR, PB, KE, KS>(m, sc, P, eb, ec, ee, xl, ul, acc, a, a32, cR, cS, ca, cl, php);
     __syncthreads();
     for (int i = threadIdx.x; i < nd; i += PB) {
       const int v = i / D, c = i - v * D, raw = vid[v];
