@@ -93,7 +93,8 @@ def parse():
     ap.add_argument("--profile-elements", action="store_true",
                     help="the element kernels alone on the --elem-grid mesh in wave order (for rocprofv3)")
     ap.add_argument("--profile-tet", action="store_true",
-                    help="the tet-block leg alone, 2 steps fwd + adjoint (for rocprofv3)")
+                    help="the tet block's CG, resident and with two launches per iteration, 1 + 2 steps "
+                         "fwd + adjoint each, with every CG iteration counted (for rocprofv3)")
     ap.add_argument("--no-tet", action="store_true", help="skip the 3D tet-block leg")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay leg")
     ap.add_argument("--no-policy", action="store_true", help="skip the policy-training leg")
@@ -283,9 +284,7 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     if args.profile_tet:
-        args.tet_steps = 2
-        out = tet_leg(args, torch, Context, isb, scenes)
-        print(json.dumps({"profile_pass": "tet_block", **out}))
+        print(json.dumps({"profile_pass": "tet_block", **tet_profile_pass(torch, Context, isb, scenes)}))
         return
     if args.profile_elements:
         out = element_roofline_mesh(args.elem_grid, torch, Context, isb, scenes, block_order=False)
@@ -906,6 +905,7 @@ def tet_leg(args, torch, Context, isb, scenes):
                "v1_rel_err": float(np.linalg.norm(v1.cpu().numpy()[vs] - np.asarray(g["v1"])) /
                                    np.linalg.norm(np.asarray(g["v1"]))),
                "note": "first step at tol 1e-6 vs the oracle's at 1e-12 (tests/golden/tet_block_step.json)"}
+    resident = ctx.get_option(isb.INFO_RESIDENT) > 0 and ctx.get_option(isb.OPT_CG_RESIDENT) == 1
     run(1, False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -913,7 +913,27 @@ def tet_leg(args, torch, Context, isb, scenes):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     st, sa = run(2, True)
+    # the same steps with the single-reduction CG as two launches per iteration (the resident solve off)
+    launched = None
+    if resident:
+        ctx.set_option(isb.OPT_CG_RESIDENT, 0)
+        run(1, False)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        run(args.tet_steps, False)
+        torch.cuda.synchronize()
+        launched = round(args.tet_steps / (time.perf_counter() - t1), 3)
+        ctx.set_option(isb.OPT_CG_RESIDENT, 1)
     print("# tet-block leg done", file=sys.stderr, flush=True)
+    cg_its = float(np.mean([s[0]["cg_iters"] for s in st])) + float(np.mean([s[0]["adj_cg_iters"] for s in sa]))
+    # one mixed CG iteration by the per-unit bytes of the measurement plan: Hessian-vector product
+    # (element word 4 B: conn + Dm^-1 + W + a, 60 B per tet; x, p in and Hp out, 36 B per vertex) and
+    # 13 FP64 words of CG vectors per DOF
+    it_bytes = w.n_e * (4 * 4 + 4 * (9 + 2)) + w.n_v * 3 * 3 * 4 + 13 * 8 * 3 * w.n_v
+    it_us = dt / args.tet_steps / cg_its * 1e6
+    cg_form = ("single-reduction, resident (one cooperative launch per solve)" if resident else
+               "single-reduction, two launches per iteration" if ctx.get_option(isb.OPT_CG_SINGLE_REDUCTION)
+               else "classic")
     return {"workload": f"tet_block 64x32x32 Kuhn tets ({w.n_e} tets, {w.n_v} vertices; block order, then "
                         f"isb_wave_order), {args.tet_steps} backward-Euler steps fwd + adjoint + VJP",
             "solver": "plain grid-wide Newton-PCG, mixed", "value": round(args.tet_steps / dt, 3),
@@ -921,8 +941,54 @@ def tet_leg(args, torch, Context, isb, scenes):
             "newton_per_step": float(np.mean([s[0]["newton_iters"] for s in st])),
             "cg_per_step": float(np.mean([s[0]["cg_iters"] for s in st])),
             "adj_cg_per_step": float(np.mean([s[0]["adj_cg_iters"] for s in sa])),
-            "cg_form": "single-reduction" if ctx.get_option(isb.OPT_CG_SINGLE_REDUCTION) else "classic",
+            "cg_form": cg_form, "launch_per_iteration_steps_per_s": launched,
+            "cg_iteration": {"us_upper_bound": round(it_us, 2),
+                             "note": "whole step time (Newton passes, line search, VJP included) over the "
+                                     "forward and adjoint CG iterations",
+                             "bytes_per_iteration": it_bytes,
+                             "frac_of_8TBs_at_that_rate": round(it_bytes / (it_us * 1e-6) / 8e12, 4)},
             "error_vs_oracle": tet_err}
+
+
+def tet_profile_pass(torch, Context, isb, scenes):
+    """For a kernel trace of the tet block's CG: 2 backward-Euler steps forward + 2 adjoints with the
+    resident single-reduction CG, then the same with two launches per iteration, each after one
+    untimed warm-up step; reports every CG iteration each form ran, so that a trace's kernel time
+    divides into time per iteration."""
+    dev = torch.device("cuda:0")
+    w = scenes.tet_block(steps=2)
+    w = w.permute_elements(isb.wave_order(3, w.n_v, w.T, w.body_e_off))
+    ctx = Context.from_workload(w, precision="mixed", solver=0)
+    x0 = torch.tensor(w.x0, device=dev)
+    v0 = torch.tensor(w.v0, device=dev)
+    acts = torch.tensor(w.actions, device=dev)
+    m = ctx.mass()
+    out = {"workload": f"tet_block ({w.n_e} tets, {w.n_v} vertices), mixed"}
+    for form, resident in (("resident", 1), ("two_launches", 0)):
+        ctx.set_option(isb.OPT_CG_RESIDENT, resident)
+        its, solves = 0, 0
+        for steps in (1, 2):
+            xs, vs = [x0], [v0]
+            for t in range(steps):
+                x1, v1, s, _ = ctx.step(xs[-1], vs[-1], acts[t], stats=True)
+                xs.append(x1)
+                vs.append(v1)
+                its += s[0]["cg_iters"]
+                solves += s[0]["newton_iters"]
+            xb = torch.zeros_like(x0)
+            xb[:, 0] = -m / m.sum()
+            vb = torch.zeros_like(x0)
+            wv = None
+            for t in range(steps - 1, -1, -1):
+                wv, s, _ = ctx.solve_adjoint(xs[t + 1], xs[t], acts[t], xb, vb, stats=True, w=wv, w_init=wv)
+                its += s[0]["adj_cg_iters"]
+                solves += 1
+                o = ctx.vjp_params(wv, xs[t + 1], xs[t], acts[t], vb, want=("a_bar", "x0_bar", "v0_bar"))
+                xb, vb = o["x0_bar"], o["v0_bar"]
+        torch.cuda.synchronize()
+        out[form] = {"cg_iterations": int(its), "cg_solves_at_least": int(solves),
+                     "resident_bodies": int(ctx.get_option(isb.INFO_RESIDENT)) if resident else 0}
+    return out
 
 
 def element_roofline_leg(args, torch, Context, isb, scenes):
