@@ -47,6 +47,32 @@ def test_lbfgs_step_reaches_oracle_minimiser(dim, precision):
         assert rel(v1[sv], vr) <= 1e-7
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_lbfgs_step_tight_at_the_fp64_bar(dim, precision):
+    """Solved to a 1e-13 relative gradient, the L-BFGS step lands on the oracle's minimiser at the
+    FP64 bar of 1e-10 (the first-order solver never applies the Hessian, so its arithmetic is FP64
+    in either precision mode), in the 2-norm and in the worst entry."""
+    from paper_2102_05791_amd import isb
+    from tests.gpu_util import rel_inf
+    shape = (10, 3) if dim == 2 else (3, 3, 2)
+    w, rng = rand_workload(dim, seed=65, bodies=2, shape=shape)
+    w.scene.update(tol_rel=1e-13, max_newton=60)
+    ctx = _ctx(w, isb.FORWARD_LBFGS, precision)
+    a = w.actions[0]
+    x1, v1, st, _ = ctx.step(_dev(w.x0), _dev(w.v0), _dev(a), allow_not_converged=True)
+    x1, v1 = x1.cpu().numpy(), v1.cpu().numpy()
+    for b, p in enumerate(problems(w)):
+        sv = slice(w.body_v_off[b], w.body_v_off[b + 1])
+        se = slice(w.body_e_off[b], w.body_e_off[b + 1])
+        xr, vr, _ = solve.step(p, w.x0[sv], w.v0[sv], a[se], tol=1e-13)
+        err, err_inf = rel(x1[sv] - w.x0[sv], xr - w.x0[sv]), rel_inf(x1[sv] - w.x0[sv], xr - w.x0[sv])
+        print(dim, precision, b, st[b]["newton_iters"], st[b]["res_final"] / st[b]["res0"], err, err_inf)
+        assert st[b]["flags"] & (isb.FLAG_CONVERGED | isb.FLAG_STAGNATED)
+        assert err <= 1e-10 and err_inf <= 1e-10
+        assert rel(v1[sv], vr) <= 1e-10
+
+
 def test_lbfgs_adjoint_matches_newton_adjoint():
     from paper_2102_05791_amd import isb
     w, rng = rand_workload(2, seed=62, shape=(12, 4))
