@@ -19,8 +19,9 @@ def _dev(a):
     return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda:0")
 
 
-@pytest.mark.parametrize("precision,tol,order", [("fp64", 1e-9, "given"), ("mixed", 1e-5, "given"),
-                                               ("fp64", 1e-9, "wave"), ("mixed", 1e-5, "wave")])
+# FP64 at the 1e-10 bar (measured about 1e-12: both sides solve to a 1e-12 relative gradient)
+@pytest.mark.parametrize("precision,tol,order", [("fp64", 1e-10, "given"), ("mixed", 1e-5, "given"),
+                                               ("fp64", 1e-10, "wave"), ("mixed", 1e-5, "wave")])
 def test_tet_block_step_and_adjoint_vs_oracle_samples(precision, tol, order):
     """order "wave": the elements permuted by isb_wave_order (as the benchmark runs the block); the
     sampled element outputs are read back at each element's new position."""
