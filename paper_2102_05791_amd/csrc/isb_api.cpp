@@ -327,6 +327,7 @@ static isb_status resident_cg(isb_ctx* c, int b, const double* x, const double* 
                               double tol, int max_cg, hipStream_t s, bool* ran) {
   *ran = false;
   if (!c->cg_resident || b < 0 || (size_t)b >= c->res_ok.size() || !c->res_ok[b]) return ISB_OK;
+  const TraceRange trace("isb: CG solve, resident");
   PatchPlan P = c->rplan;
   P.max_nv = c->res_max_nv[b];
   const int p0 = c->res_patch_off[b], np = c->res_patch_off[b + 1] - p0;
@@ -351,6 +352,7 @@ static isb_status resident_cg(isb_ctx* c, int b, const double* x, const double* 
 // iteration's launches and a read every cg_check iterations.
 static isb_status launched_cg(isb_ctx* c, int b, const double* x, const double* a, const double* rhs, double sign,
                               double tol, int max_cg, hipStream_t s, bool single) {
+  const TraceRange trace("isb: CG solve, launch per kernel");
   const BodyRange br = body_range(c, b);
   const int o = br.off;
   if (single)
@@ -446,6 +448,7 @@ static isb_status run_cg(isb_ctx* c, int b, const double* x, const double* a, co
 static isb_status line_search(isb_ctx* c, int b, hipStream_t s, const double* x0, const double* a, const double* dx,
                               double gTd, double res_stop, bool first_order, double** px, double** pxt, double** pG,
                               double** pGt, double* res, isb_stats* st, bool* accepted_out, double* alpha_out) {
+  const TraceRange trace("isb: line search");
   const BodyRange br = body_range(c, b);
   double *x = *px, *xt = *pxt, *G = *pG, *Gt = *pGt;
   double alpha = 1.0;
@@ -506,6 +509,7 @@ static isb_status line_search(isb_ctx* c, int b, hipStream_t s, const double* x0
 
 static isb_status plain_newton(isb_ctx* c, int b, hipStream_t s, const double* x0, const double* a, double** px,
                                double** pxt, double** pG, double** pGt, isb_stats* st) {
+  const TraceRange trace("isb: Newton solve");
   const BodyRange br = body_range(c, b);
   const isb_scene& sc = c->scene;
   double *x = *px, *xt = *pxt, *G = *pG, *Gt = *pGt;
@@ -600,6 +604,7 @@ static isb_status body_dot(isb_ctx* c, int b, const double* u, const double* v, 
 // are reported as newton_iters.
 static isb_status plain_lbfgs(isb_ctx* c, int b, hipStream_t s, const double* x0, const double* a, double** px,
                               double** pxt, double** pG, double** pGt, isb_stats* st) {
+  const TraceRange trace("isb: L-BFGS solve");
   const BodyRange br = body_range(c, b);
   const isb_scene& sc = c->scene;
   const int m = c->lbfgs_m, n = br.n, o = br.off;
@@ -737,6 +742,7 @@ static isb_status check_actuation(isb_ctx* c, hipStream_t s, const double* a) {
 
 static isb_status plain_step(isb_ctx* c, hipStream_t s, const double* x0, const double* v0, const double* a,
                              double* x1, double* v1, isb_stats* per_body) {
+  const TraceRange trace("isb: step, plain");
   const DevMesh m = devmesh(c);
   const DevScene dsc = devscene(c);
   if (c->precision == ISB_MIXED) launch_to_f32(c->n_e, a, c->w_a32, s);
@@ -776,6 +782,7 @@ static isb_status plain_step(isb_ctx* c, hipStream_t s, const double* x0, const 
 
 static isb_status plain_adjoint(isb_ctx* c, hipStream_t s, const double* x1, const double* x0, const double* a,
                                 const double* x1_bar, const double* v1_bar, double* w, isb_stats* per_body) {
+  const TraceRange trace("isb: adjoint, plain");
   const DevMesh m = devmesh(c);
   const DevScene dsc = devscene(c);
   if (c->precision == ISB_MIXED) launch_to_f32(c->n_e, a, c->w_a32, s);
@@ -1393,6 +1400,7 @@ isb_status isb_solve_adjoint(isb_ctx* c, isb_stream stream, const double* x1, co
 isb_status isb_vjp_params(isb_ctx* c, isb_stream stream, const double* w, const double* x1, const double* x0,
                           const double* a, const double* v1_bar, double* a_bar, double* x0_bar, double* v0_bar,
                           double* mu_bar, double* lam_bar, double* kf_bar) {
+  const TraceRange trace("isb: VJP");
   clear_error();
   ISB_TRY(check_ctx(c, true));
   if (!w || !x1 || !x0 || !a) return fail(ISB_E_ARG, "NULL vjp argument");

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 #include <stdint.h>
 
 #include <string>
@@ -16,6 +17,18 @@
     hipError_t e_ = (expr);                                                                            \
     if (e_ != hipSuccess) return ::isb::fail(ISB_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
   } while (0)
+
+namespace isb {
+// A named roctx range over a scope: the solver's phases (step, Newton solve, line search, CG
+// solve, adjoint, VJP, batched launches) appear in a rocprofv3 marker trace; without a tool
+// attached a range costs two library calls.
+struct TraceRange {
+  explicit TraceRange(const char* name) { roctxRangePushA(name); }
+  ~TraceRange() { roctxRangePop(); }
+  TraceRange(const TraceRange&) = delete;
+  TraceRange& operator=(const TraceRange&) = delete;
+};
+}  // namespace isb
 
 struct isb_ctx {
   int device = 0;
