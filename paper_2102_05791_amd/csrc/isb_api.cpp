@@ -1380,6 +1380,7 @@ isb_status isb_step(isb_ctx* c, isb_stream stream, const double* x0, const doubl
   if (c->solver == 1) {
     if (c->forward != ISB_FORWARD_NEWTON)
       return fail(ISB_E_ARG, "the batched solver runs Newton-PCG only (ISB_OPT_FORWARD)");
+    const TraceRange trace("isb: step, batched");
     return batched_step(c, s, x0, be ? v0 : nullptr, a, x1, be ? v1 : nullptr, per_body);
   }
   ISB_TRY(check_actuation(c, s, a));
@@ -1392,7 +1393,10 @@ isb_status isb_solve_adjoint(isb_ctx* c, isb_stream stream, const double* x1, co
   ISB_TRY(check_ctx(c, true));
   if (!x1 || !x0 || !a || !x1_bar || !w) return fail(ISB_E_ARG, "NULL adjoint argument");
   hipStream_t s = (hipStream_t)stream;
-  if (c->solver == 1) return batched_adjoint(c, s, x1, x0, a, x1_bar, v1_bar, w, per_body);
+  if (c->solver == 1) {
+    const TraceRange trace("isb: adjoint, batched");
+    return batched_adjoint(c, s, x1, x0, a, x1_bar, v1_bar, w, per_body);
+  }
   ISB_TRY(check_actuation(c, s, a));
   return plain_adjoint(c, s, x1, x0, a, x1_bar, v1_bar, w, per_body);
 }

@@ -351,7 +351,6 @@ static isb_status collect(isb_ctx* c, BatchedState* st, hipStream_t s, isb_stats
 
 isb_status batched_step(isb_ctx* c, hipStream_t s, const double* x0, const double* v0, const double* a, double* x1,
                         double* v1, isb_stats* per_body) {
-  const TraceRange trace("isb: step, batched");
   isb_status r = batched_prepare(c);
   if (r != ISB_OK) return r;
   auto* st = static_cast<BatchedState*>(c->batched);
@@ -370,7 +369,6 @@ isb_status batched_step(isb_ctx* c, hipStream_t s, const double* x0, const doubl
 
 isb_status batched_adjoint(isb_ctx* c, hipStream_t s, const double* x1, const double* x0, const double* a,
                            const double* x1_bar, const double* v1_bar, double* w, isb_stats* per_body) {
-  const TraceRange trace("isb: adjoint, batched");
   isb_status r = batched_prepare(c);
   if (r != ISB_OK) return r;
   auto* st = static_cast<BatchedState*>(c->batched);
