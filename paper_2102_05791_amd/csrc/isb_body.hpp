@@ -194,7 +194,7 @@ struct BodySolver {
   // LDS arrays hold one component plane after the other (vertex vl, axis c at c * nvs + vl), so
   // that the FP64 atomics of a wave, which touch runs of nearby vertices, spread over the banks;
   // the interleaved layout of the global vectors would put vertices 8 apart on one bank.
-  __device__ __forceinline__ int lv(int vl, int c) const { return c * (A.nacc / D) + vl; }
+  __device__ __forceinline__ int lv(int vl, int c) const { return c * (A.nacc / D) + ISB_CHECKED(vl, v1 - v0, 1); }
   __device__ __forceinline__ int ld(int i) const { return lv(i / D, i % D); }  // body DOF i = vl * D + c
 
   __device__ __forceinline__ bool pinned(int i) const { return m.pinned[base + i] != 0; }
@@ -204,7 +204,7 @@ struct BodySolver {
   __device__ __forceinline__ void load_lconn(int e, int v[D + 1]) const {
     const size_t ne = (size_t)m.n_e;
 #pragma unroll
-    for (int k = 0; k <= D; ++k) v[k] = v0 + (int)A.lconn[(size_t)k * ne + e];
+    for (int k = 0; k <= D; ++k) v[k] = v0 + ISB_CHECKED((int)A.lconn[(size_t)k * ne + e], v1 - v0, 2);
   }
 
   // preconditioner entry of a free DOF with Hessian diagonal d (1 where d is 0), as stored
@@ -231,8 +231,8 @@ struct BodySolver {
   static constexpr int kSW = spring_state_words(D);
   __device__ __forceinline__ T* Sb() const { return reinterpret_cast<T*>(A.Sbuf); }
   __device__ __forceinline__ void spring_ends(int s, int& i, int& j) const {
-    i = (int)A.slconn[s];
-    j = (int)A.slconn[(size_t)A.n_s + s];
+    i = ISB_CHECKED((int)A.slconn[s], v1 - v0, 3);
+    j = ISB_CHECKED((int)A.slconn[(size_t)A.n_s + s], v1 - v0, 3);
   }
   // +y at vertex j and -y at vertex i (both_plus: +y at both) into the LDS array dst
   __device__ __forceinline__ void spring_lds(double* dst, int i, int j, const double y[D], bool both_plus) const {

@@ -12,6 +12,24 @@
 
 namespace isb {
 
+// Index checks of the debug build (-DISB_DEBUG; the CPU emulator of the batched solver is built
+// with it): an index outside [0, n) stores the number of the check that saw it in g_isb_debug_site
+// and reads as 0, so that the code goes on in bounds and the caller can report the site. Without
+// ISB_DEBUG a check is the index itself.
+#ifdef ISB_DEBUG
+__device__ inline int g_isb_debug_site = 0;
+__device__ __forceinline__ int isb_checked(int i, int n, int site) {
+  if (i < 0 || i >= n) {
+    __atomic_store_n(&g_isb_debug_site, site, __ATOMIC_RELAXED);
+    return 0;
+  }
+  return i;
+}
+#define ISB_CHECKED(i, n, site) ::isb::isb_checked((i), (n), (site))
+#else
+#define ISB_CHECKED(i, n, site) (i)
+#endif
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);

@@ -1,5 +1,6 @@
 // Runs the batched solver's body logic (isb_body.hpp) on the CPU: one workgroup of `block`
-// host threads solves every body, largest first. The emulated LDS starts filled with
+// host threads solves every body, largest first. Built with ISB_DEBUG: the body logic's index
+// checks are active (emu_debug_site). The emulated LDS starts filled with
 // `lds_fill`, standing in for whatever an earlier kernel left there; the largest |value| left in
 // its two accumulators afterwards is returned in *lds_left. Test infrastructure only.
 #include <hip/hip_runtime.h>
@@ -80,6 +81,14 @@ extern "C" int emu_batched(int dim, int precision, int mode, int block, const is
       mode ? run<3, double, 1>(block, m, sc, A, lds_fill, lds_left) : run<3, double, 0>(block, m, sc, A, lds_fill, lds_left);
   }
   return 0;
+}
+
+// the debug build's index checks (ISB_DEBUG, which this emulator is always built with): the number of
+// the last check that saw an index out of range, 0 if none; reset clears it
+extern "C" int emu_debug_site(int reset) {
+  const int site = __atomic_load_n(&isb::g_isb_debug_site, __ATOMIC_RELAXED);
+  if (reset) __atomic_store_n(&isb::g_isb_debug_site, 0, __ATOMIC_RELAXED);
+  return site;
 }
 
 extern "C" int emu_sizes(int* out) {

@@ -54,8 +54,8 @@ def build():
     os.makedirs(os.path.dirname(OUT), exist_ok=True)
     if os.path.exists(OUT) and all(os.path.getmtime(OUT) >= os.path.getmtime(s) for s in SRCS):
         return OUT
-    cmd = ["g++", "-std=c++20", "-O1", "-fPIC", "-shared", "-pthread", "-I", os.path.join(HERE, "include"),
-           "-I", CSRC, SRCS[0], "-o", OUT + ".tmp"]
+    cmd = ["g++", "-std=c++20", "-O1", "-fPIC", "-shared", "-pthread", "-DISB_DEBUG", "-I",
+           os.path.join(HERE, "include"), "-I", CSRC, SRCS[0], "-o", OUT + ".tmp"]
     subprocess.run(cmd, check=True, capture_output=True, text=True)
     os.replace(OUT + ".tmp", OUT)
     return OUT
@@ -87,6 +87,8 @@ class EmuBatch:
 
     def __init__(self, w, precision="fp64"):
         self.lib = ctypes.CDLL(build())
+        self.allow_index_errors = False
+        self.last_index_site = 0
         self._left = ctypes.c_double(0.0)
         self.lds_left = None
         sizes = (ci * 4)()
@@ -193,7 +195,17 @@ class EmuBatch:
         self.lib.emu_batched(self.w.dim, self.prec, 0, block, ctypes.byref(self.m), ctypes.byref(self.sc),
                              ctypes.byref(A), ctypes.c_double(lds_fill), ctypes.byref(self._left))
         self.lds_left = self._left.value
+        self._check_indices()
         return x1, (v1 if self.be else None), self.stats.copy()
+
+    def _check_indices(self):
+        """The body logic's index checks (built with ISB_DEBUG): raise IndexError naming the check
+        that saw an index out of range during the last launch (1: LDS vertex, 2: element corner,
+        3: spring end); the check resets."""
+        site = self.lib.emu_debug_site(1)
+        if site != 0 and not self.allow_index_errors:
+            raise IndexError(f"index check {site} saw an index out of range")
+        self.last_index_site = site
 
     def adjoint(self, x1, x0, a, xbar, vbar=None, block=128, lds_fill=-12345.0, w_init=None):
         """w_init: the starting point of the adjoint CG (ISB_OPT_ADJ_WARM_START), else zero."""
@@ -206,4 +218,5 @@ class EmuBatch:
         self.lib.emu_batched(self.w.dim, self.prec, 1, block, ctypes.byref(self.m), ctypes.byref(self.sc),
                              ctypes.byref(A), ctypes.c_double(lds_fill), ctypes.byref(self._left))
         self.lds_left = self._left.value
+        self._check_indices()
         return wv, self.stats.copy()

@@ -123,6 +123,23 @@ def test_emulated_batched_energy_models(emu_mod, model, dim):
             assert rel(wv[sv], wr) <= adj_tol
 
 
+def test_emulated_index_checks_report_a_bad_corner(emu_mod):
+    """The debug build's index checks: an element corner planted out of its body's range (on the
+    CPU, in the emulator's copy of the connectivity) is reported as check 2 and read as corner 0,
+    so the run stays in bounds; the same body with its real corners reports nothing."""
+    w, _ = rand_workload(2, seed=23, bodies=2, shape=(3, 2))
+    eb = emu_mod.EmuBatch(w, "fp64")
+    eb.step(w.x0, w.v0, w.actions[0], block=64)
+    assert eb.last_index_site == 0
+    eb.lconn[1, 0] = 60000
+    eb.allow_index_errors = True
+    eb.step(w.x0, w.v0, w.actions[0], block=64)
+    assert eb.last_index_site == 2
+    eb.allow_index_errors = False
+    with pytest.raises(IndexError):
+        eb.step(w.x0, w.v0, w.actions[0], block=64)
+
+
 def test_emulated_static_assignment_covers_every_body_once(emu_mod):
     """With more bodies than rounds x workgroups boundaries, every body is solved exactly once."""
     w, _ = rand_workload(2, seed=22, bodies=5, shape=(3, 2))

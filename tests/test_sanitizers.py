@@ -1,6 +1,6 @@
 """The host C++ under AddressSanitizer and UndefinedBehaviorSanitizer, and the batched solver's body
-logic (isb_body.hpp, run by host threads as emulated workgroups of 2 and 4 waves) under
-ThreadSanitizer. CPU only: the sanitized libraries are built with g++ from the same sources
+logic (isb_body.hpp, run by host threads as emulated workgroups of 2 and 4 waves, with its debug
+index checks) under ThreadSanitizer and under AddressSanitizer with UndefinedBehaviorSanitizer. CPU only: the sanitized libraries are built with g++ from the same sources
 (the host-only isb_host.cpp; the emulator of tests/emu) and driven by tests/san_driver.py in a child
 process with the sanitizer runtime preloaded, so that a report fails the test."""
 import os
@@ -62,7 +62,21 @@ def test_emulated_batched_solver_under_tsan():
     from tests.emu import emu
     src = os.path.join(EMU, "batched_emu.cpp")
     lib = _build(os.path.join(BUILD, "libisb_emu_tsan.so"), [src],
-                 ["-std=c++20", "-pthread", "-fsanitize=thread", "-I", os.path.join(EMU, "include"), "-I", CSRC],
-                 emu.SRCS)
+                 ["-std=c++20", "-pthread", "-fsanitize=thread", "-DISB_DEBUG", "-I", os.path.join(EMU, "include"),
+                  "-I", CSRC], emu.SRCS)
     out = _drive("emu", lib, _runtime("libtsan.so"), {"TSAN_OPTIONS": "halt_on_error=1:exitcode=66"}, 900)
+    assert "emulated batched solver checks passed" in out
+
+
+@pytest.mark.slow
+def test_emulated_batched_solver_under_asan_and_ubsan():
+    """The same emulated runs with AddressSanitizer and UndefinedBehaviorSanitizer: every access of
+    the body logic to the element, vertex and LDS arrays stays inside its allocation."""
+    from tests.emu import emu
+    src = os.path.join(EMU, "batched_emu.cpp")
+    lib = _build(os.path.join(BUILD, "libisb_emu_asan.so"), [src],
+                 ["-std=c++20", "-pthread", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                  "-DISB_DEBUG", "-I", os.path.join(EMU, "include"), "-I", CSRC], emu.SRCS)
+    out = _drive("emu", lib, _runtime("libasan.so"), {"ASAN_OPTIONS": "detect_leaks=0:abort_on_error=1",
+                                                      "UBSAN_OPTIONS": "print_stacktrace=1"}, 900)
     assert "emulated batched solver checks passed" in out
