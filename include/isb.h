@@ -141,9 +141,12 @@ typedef enum {
                              * once, the whole CG solve is one cooperative launch with one grid barrier per
                              * iteration; 0 = one Hessian-vector launch and one vector launch per iteration.
                              * The same single-reduction iteration either way. A barrier that waits longer
-                             * than 4 s (workgroups that are not all resident) ends the launch, and the
-                             * call returns ISB_E_HIP; the device or another context running cooperative
-                             * work at the same time is the usual cause */
+                             * than ISB_OPT_CG_BARRIER_LIMIT_US (workgroups that are not all resident) ends
+                             * the launch, and the call returns ISB_E_HIP */
+  ISB_OPT_CG_BARRIER_LIMIT_US = 17, /* resident CG: the longest wait at one grid barrier, in microseconds,
+                             * 1 .. 60,000,000 (default 4,000,000); a barrier that waits longer ends the
+                             * launch and the call returns ISB_E_HIP. A small value forces that path, for
+                             * tests of the error handling; every workgroup still leaves the launch */
   ISB_OPT_CG_GRAPH = 10     /* plain solver: 1 = run CG as a graph of 8 iterations, captured once per solve and
                              * replayed until converged (one launch and one host read per 8 iterations);
                              * 0 (default) = one launch per kernel and a read every ISB_OPT_CG_CHECK iterations.

@@ -334,7 +334,8 @@ static isb_status resident_cg(isb_ctx* c, int b, const double* x, const double* 
   // W0..W2 are the workspaces the launch-per-iteration form uses for H u, u and s
   const hipError_t e = launch_cg_resident(devmesh(c), devscene(c), P, p0, np, c->res_cu, c->precision, x, a,
                                           c->w_a32, rhs, sign, c->w_Dinvp, c->w_vdiag, c->w_xs, c->w_Hp, c->w_u,
-                                          c->w_s, c->partials, c->gbar, c->scal, tol * tol, max_cg, s);
+                                          c->w_s, c->partials, c->gbar, c->scal, tol * tol, max_cg,
+                                          c->barrier_limit_us, s);
   if (e == hipErrorCooperativeLaunchTooLarge) {
     c->res_ok[b] = 0;  // its workgroups cannot all be resident here: the launch-per-iteration form
     return ISB_OK;
@@ -1295,6 +1296,10 @@ isb_status isb_set_option(isb_ctx* c, int key, int64_t value) {
       if (value != 0 && value != 1) return fail(ISB_E_ARG, "resident CG must be 0 or 1");
       c->cg_resident = (int)value;
       return ISB_OK;
+    case ISB_OPT_CG_BARRIER_LIMIT_US:
+      if (value < 1 || value > 60000000) return fail(ISB_E_ARG, "barrier limit must be in [1, 6e7] us");
+      c->barrier_limit_us = value;
+      return ISB_OK;
     case ISB_OPT_PATCH_BLOCK:
       if (value != 0 && value != 256 && value != 512 && value != 1024)
         return fail(ISB_E_ARG, "patch block must be 0 (default), 256, 512 or 1024");
@@ -1342,6 +1347,7 @@ isb_status isb_get_option(isb_ctx* c, int key, int64_t* value) {
     case ISB_OPT_PATCH_BLOCK: *value = c->patch_block; return ISB_OK;
     case ISB_OPT_CG_SINGLE_REDUCTION: *value = c->cg_single; return ISB_OK;
     case ISB_OPT_CG_RESIDENT: *value = c->cg_resident; return ISB_OK;
+    case ISB_OPT_CG_BARRIER_LIMIT_US: *value = c->barrier_limit_us; return ISB_OK;
     case ISB_INFO_RESIDENT: {
       int64_t n = 0;
       for (uint8_t ok : c->res_ok) n += ok;

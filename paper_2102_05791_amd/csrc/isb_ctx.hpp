@@ -91,6 +91,7 @@ struct isb_ctx {
   int patch_block = 0;                 // ISB_OPT_PATCH_BLOCK (0: kPatchBlock)
   int cg_single = 1;                   // ISB_OPT_CG_SINGLE_REDUCTION
   int cg_resident = 1;                 // ISB_OPT_CG_RESIDENT
+  int64_t barrier_limit_us = 4000000;  // ISB_OPT_CG_BARRIER_LIMIT_US
   hipStream_t cap_stream = nullptr;    // internal stream the CG chunk is captured on
 
   // plain-solver workspaces, [n_v*dim] unless noted

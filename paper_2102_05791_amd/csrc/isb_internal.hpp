@@ -172,7 +172,8 @@ void launch_cgcg_final(int n, const double* partials, CgScal* scal, hipStream_t 
 
 // ---- resident single-reduction PCG (isb_resident.hip): body patches [p0, p0 + np) of the resident
 // plan P (P.max_nv: the largest of them), one cooperative workgroup each, solve H(x) xs = sign * rhs
-// to r.r <= tol2 in one launch and leave the outcome in *scal (fault = 1: a barrier timed out).
+// to r.r <= tol2 in one launch and leave the outcome in *scal (fault = 1: a barrier waited longer
+// than barrier_limit_us and every workgroup left the launch).
 // Vectors are the global [n_v][D] arrays; W0..W2 are [n_v][D] scratch, part 8 * np values.
 // Returns hipErrorCooperativeLaunchTooLarge, launching nothing, when np workgroups cannot all be
 // resident. ----
@@ -180,7 +181,7 @@ hipError_t launch_cg_resident(const DevMesh& m, const DevScene& sc, const PatchP
                               int precision, const double* x, const double* a, const float* a32, const double* rhs,
                               double sign, const double* Dinvp, const double* vdiag, double* xs, double* W0,
                               double* W1, double* W2, double* part, GridBar* bar, CgScal* scal, double tol2,
-                              int max_it, hipStream_t s);
+                              int max_it, int64_t barrier_limit_us, hipStream_t s);
 
 // ---- spring kernels (isb_springs.hip): spring range r (ids through r.list when given); as = the
 // springs' actions (the action vector past the elements' entries); op = PatchOp; FP64 throughout ----

@@ -30,10 +30,6 @@
 
 namespace isb {
 
-// longest wait at one grid barrier, in ticks of the 100 MHz wall clock (4 s): a workgroup that
-// waits longer marks the launch aborted, and every workgroup then leaves the solve
-constexpr uint64_t kBarrierTicks = 400000000ull;
-
 __device__ __forceinline__ double ld_agent(const double* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -52,8 +48,10 @@ __device__ __forceinline__ void wait_vm_stores() {
   __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0); expcnt and lgkmcnt not waited for
 }
 
-// Returns false on every thread of the workgroup when the launch has been aborted.
-__device__ __forceinline__ bool grid_barrier(GridBar* g, unsigned& epoch, int* ok_lds) {
+// Returns false on every thread of the workgroup when the launch has been aborted: a workgroup that
+// waits more than max_ticks of the constant-rate wall clock marks the launch aborted, and every
+// workgroup then leaves the solve.
+__device__ __forceinline__ bool grid_barrier(GridBar* g, unsigned& epoch, int* ok_lds, uint64_t max_ticks) {
   wait_vm_stores();
   __syncthreads();
   ++epoch;
@@ -64,7 +62,7 @@ __device__ __forceinline__ bool grid_barrier(GridBar* g, unsigned& epoch, int* o
     int ok = 1;
     while (__hip_atomic_load(&g->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
       if (__hip_atomic_load(&g->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
-          wall_clock64() - t0 > kBarrierTicks) {
+          wall_clock64() - t0 > max_ticks) {
         __hip_atomic_store(&g->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         ok = 0;
         break;
@@ -162,7 +160,7 @@ __global__ void __launch_bounds__(PB)
                   const double* __restrict__ a, const float* __restrict__ a32, const double* __restrict__ rhs,
                   double sign, const double* __restrict__ Dinvp, const double* __restrict__ vdiag, double* xs_out,
                   double* W0, double* W1, double* W2, double* part, GridBar* bar, CgScal* scal, double tol2,
-                  int max_it) {
+                  int max_it, uint64_t max_ticks) {
   extern __shared__ double lds[];
   __shared__ double red[3 * (PB / 64)];
   __shared__ int ok_lds;
@@ -233,7 +231,7 @@ __global__ void __launch_bounds__(PB)
       ca[k] = (std::is_same<T, float>::value && a32) ? T(a32[e]) : T(a[e]);
     }
   }
-  bool ok = grid_barrier(bar, epoch, &ok_lds);
+  bool ok = grid_barrier(bar, epoch, &ok_lds, max_ticks);
   if (ok) {
     // H u_0 into W0
     double php = 0.0;
@@ -244,7 +242,7 @@ __global__ void __launch_bounds__(PB)
       unsafeAtomicAdd(W0 + (size_t)(raw >= 0 ? raw : ~raw) * D + c, acc[i]);
     }
     workgroup_sums3<PB>(g_, r_, d_ + sc.s_pot * php, red, part + 4 * blockIdx.x);
-    ok = grid_barrier(bar, epoch, &ok_lds);
+    ok = grid_barrier(bar, epoch, &ok_lds, max_ticks);
   }
 
   int it = 0, negcurv = 0;
@@ -303,7 +301,7 @@ __global__ void __launch_bounds__(PB)
     gamma_prev = gamma;
     alpha_prev = alpha;
     ++it;
-    ok = grid_barrier(bar, epoch, &ok_lds);
+    ok = grid_barrier(bar, epoch, &ok_lds, max_ticks);
   }
 
   for (int i = threadIdx.x; i < nd; i += PB) {
@@ -351,7 +349,7 @@ hipError_t launch_cg_resident(const DevMesh& m, const DevScene& sc, const PatchP
                               int precision, const double* x, const double* a, const float* a32, const double* rhs,
                               double sign, const double* Dinvp, const double* vdiag, double* xs, double* W0,
                               double* W1, double* W2, double* part, GridBar* bar, CgScal* scal, double tol2,
-                              int max_it, hipStream_t s) {
+                              int max_it, int64_t barrier_limit_us, hipStream_t s) {
   if (np < 1) return hipErrorInvalidValue;
   const bool compact = m.axis >= 0;
   const void* k = m.dim == 2 ? (precision ? resident_kernel_dt<2, float>(m.model, compact)
@@ -366,12 +364,20 @@ hipError_t launch_cg_resident(const DevMesh& m, const DevScene& sc, const PatchP
   e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k, block, lds);
   if (e != hipSuccess) return e;
   if (occ * n_cu < np) return hipErrorCooperativeLaunchTooLarge;
+  int rate_khz = 0;  // the wall clock's rate
+  int dev = 0;
+  e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev);
+  if (e != hipSuccess) return e;
+  if (rate_khz <= 0) return hipErrorInvalidValue;
+  uint64_t max_ticks = (uint64_t)barrier_limit_us * (uint64_t)rate_khz / 1000ull;
+  if (max_ticks < 1) max_ticks = 1;
   k_grid_bar_reset<<<1, 1, 0, s>>>(bar);
   DevMesh mm = m;
   DevScene ss = sc;
   PatchPlan pp = P;
   void* args[] = {&mm, &ss, &pp, &p0, &x, &a, &a32, &rhs, &sign, &Dinvp, &vdiag, &xs,
-                  &W0, &W1, &W2, &part, &bar, &scal, &tol2, &max_it};
+                  &W0, &W1, &W2, &part, &bar, &scal, &tol2, &max_it, &max_ticks};
   return hipLaunchCooperativeKernel(k, dim3(np), dim3(block), args, (unsigned)lds, s);
 }
 

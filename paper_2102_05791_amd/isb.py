@@ -22,7 +22,8 @@ ISB_FP64, ISB_MIXED = 0, 1
 ISB_QUASISTATIC, ISB_BACKWARD_EULER = 0, 1
 (OPT_SOLVER, OPT_SCATTER, OPT_GRAPH_SAFE, OPT_BLOCK, OPT_CG_CHECK, OPT_PRECISION, OPT_ENERGY, OPT_FORWARD,
  OPT_LBFGS_MEMORY, OPT_LBFGS_MAX_ITERS, OPT_CG_GRAPH, OPT_FP64_FALLBACK, OPT_ADJ_WARM_START,
- OPT_COMPACT_REST, OPT_PATCH_BLOCK, OPT_CG_SINGLE_REDUCTION, OPT_CG_RESIDENT) = range(17)
+ OPT_COMPACT_REST, OPT_PATCH_BLOCK, OPT_CG_SINGLE_REDUCTION, OPT_CG_RESIDENT,
+ OPT_CG_BARRIER_LIMIT_US) = range(18)
 FLAG_CONVERGED, FLAG_STAGNATED, FLAG_NONFINITE, FLAG_ADJ_CONVERGED, FLAG_FP64_FALLBACK = 1, 2, 4, 8, 16
 FLAG_INVALID_ACTION = 32
 FORWARD_NEWTON, FORWARD_LBFGS = 0, 1

@@ -114,6 +114,28 @@ def test_single_reduction_cg_matches_classic_and_oracle(oracle_refs, body, preci
     assert abs(res["resident"][3]["cg_iters"] - res["launched"][3]["cg_iters"]) <= 0.02 * s0 + 2
 
 
+def test_resident_barrier_limit_ends_the_launch_cleanly(oracle_refs):
+    """The resident solve's bounded barrier wait, forced from the host: with a 1 us limit the
+    workgroups give up at a barrier and every one of them leaves the launch; the call reports
+    ISB_E_HIP, and with the default limit back the same context solves to the oracle's minimiser."""
+    from paper_2102_05791_amd import IsbError, isb
+    w, a, xr, vr, xbar, wr = oracle_refs["3d-compact"]
+    ctx = _ctx(w, "fp64")
+    assert ctx.get_option(isb.INFO_RESIDENT) == 1
+    assert ctx.get_option(isb.OPT_CG_BARRIER_LIMIT_US) == 4000000
+    for bad in (0, 60000001):
+        with pytest.raises(IsbError):
+            ctx.set_option(isb.OPT_CG_BARRIER_LIMIT_US, bad)
+    ctx.set_option(isb.OPT_CG_BARRIER_LIMIT_US, 1)
+    with pytest.raises(IsbError) as e:
+        ctx.step(_dev(w.x0), _dev(w.v0), _dev(a))
+    assert e.value.status == isb.ISB_E_HIP and "barrier" in str(e.value)
+    ctx.set_option(isb.OPT_CG_BARRIER_LIMIT_US, 4000000)
+    x1, v1, st, _ = ctx.step(_dev(w.x0), _dev(w.v0), _dev(a))
+    assert rel(x1.cpu().numpy() - w.x0, xr - w.x0) <= 1e-10
+    assert rel(v1.cpu().numpy(), vr) <= 1e-10
+
+
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 1e-7)])
 def test_single_reduction_cg_graph_chunks(oracle_refs, precision, tol):
     """The single-reduction CG captured as graph chunks of 8 iterations and replayed: the same
