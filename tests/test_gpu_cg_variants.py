@@ -114,6 +114,37 @@ def test_single_reduction_cg_matches_classic_and_oracle(oracle_refs, body, preci
     assert abs(res["resident"][3]["cg_iters"] - res["launched"][3]["cg_iters"]) <= 0.02 * s0 + 2
 
 
+@pytest.mark.parametrize("model,dim", [("stvk", 2), ("corot", 2), ("snh", 2), ("corot", 3)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 1e-5)])
+def test_resident_cg_alternative_energies(model, dim, precision, tol):
+    """The resident solve with the alternative energies of Sec. 3 (their element state is evaluated
+    at every product; only neo-Hookean FP32 elements are cached in registers), on bodies large
+    enough for it: step and adjoint against the oracle, and against the two-launch form."""
+    from paper_2102_05791_amd import isb
+    shape = (130, 65) if dim == 2 else (16, 16, 11)
+    w, rng = rand_workload(dim, seed=95, shape=shape)
+    w.model = model
+    w.scene.update(tol_rel=1e-13, adj_tol_rel=1e-13, max_newton=60, max_cg=6000)
+    p = problems(w)[0]
+    a = w.actions[0]
+    xr, vr, _ = solve.step(p, w.x0, w.v0, a, tol=1e-13)
+    xbar = rng.normal(size=xr.shape)
+    wr = solve.adjoint(p, xr, w.x0, a, xbar)
+    outs = {}
+    for resident in (1, 0):
+        ctx = _ctx(w, precision, cg_resident=resident)
+        assert ctx.get_option(isb.INFO_RESIDENT) == 1
+        x1, v1, st, _ = ctx.step(_dev(w.x0), _dev(w.v0), _dev(a))
+        wv, sa, _ = ctx.solve_adjoint(_dev(xr), _dev(w.x0), _dev(a), _dev(xbar))
+        x1, wv = x1.cpu().numpy(), wv.cpu().numpy()
+        print(model, dim, precision, resident, st[0]["cg_iters"], sa[0]["adj_cg_iters"],
+              rel(x1 - w.x0, xr - w.x0), rel(wv, wr))
+        assert rel(x1 - w.x0, xr - w.x0) <= tol and rel_inf(x1 - w.x0, xr - w.x0) <= tol
+        assert rel(wv, wr) <= tol and rel_inf(wv, wr) <= tol
+        outs[resident] = st[0]["cg_iters"]
+    assert abs(outs[1] - outs[0]) <= 0.05 * outs[0] + 3
+
+
 def test_resident_barrier_limit_ends_the_launch_cleanly(oracle_refs):
     """The resident solve's bounded barrier wait, forced from the host: with a 1 us limit the
     workgroups give up at a barrier and every one of them leaves the launch; the call reports
