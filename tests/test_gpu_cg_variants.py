@@ -145,6 +145,32 @@ def test_resident_cg_alternative_energies(model, dim, precision, tol):
     assert abs(outs[1] - outs[0]) <= 0.05 * outs[0] + 3
 
 
+@pytest.mark.parametrize("integrator", ["qs", "be"])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 1e-5)])
+def test_resident_cg_pinned_body(integrator, precision, tol):
+    """The resident solve on a body with its left column pinned (the pinned DOFs have no
+    preconditioner entry, so their residual is masked), quasistatic and backward Euler: step and
+    adjoint against the oracle."""
+    from paper_2102_05791_amd import isb
+    w, rng = rand_workload(2, seed=96, integrator=integrator, pinned_left=True, shape=(130, 65))
+    w.scene.update(tol_rel=1e-13, adj_tol_rel=1e-13, max_newton=60, max_cg=8000)
+    p = problems(w)[0]
+    a = w.actions[0]
+    xr, vr, _ = solve.step(p, w.x0, w.v0, a, tol=1e-13)
+    xbar = rng.normal(size=xr.shape)
+    wr = solve.adjoint(p, xr, w.x0, a, xbar)
+    ctx = _ctx(w, precision)
+    assert ctx.get_option(isb.INFO_RESIDENT) == 1 and ctx.get_option(isb.OPT_CG_RESIDENT) == 1
+    x1, _, st, _ = ctx.step(_dev(w.x0), _dev(w.v0), _dev(a))
+    wv, sa, _ = ctx.solve_adjoint(_dev(xr), _dev(w.x0), _dev(a), _dev(xbar))
+    x1, wv = x1.cpu().numpy(), wv.cpu().numpy()
+    print(integrator, precision, st[0]["cg_iters"], sa[0]["adj_cg_iters"], rel(x1 - w.x0, xr - w.x0), rel(wv, wr))
+    pinned = w.pinned.astype(bool)
+    assert np.all(x1[pinned] == w.x0[pinned]) and np.all(wv[pinned] == 0.0)
+    assert rel(x1 - w.x0, xr - w.x0) <= tol and rel_inf(x1 - w.x0, xr - w.x0) <= tol
+    assert rel(wv, wr) <= tol and rel_inf(wv, wr) <= tol
+
+
 def test_resident_barrier_limit_ends_the_launch_cleanly(oracle_refs):
     """The resident solve's bounded barrier wait, forced from the host: with a 1 us limit the
     workgroups give up at a barrier and every one of them leaves the launch; the call reports
