@@ -125,7 +125,12 @@ def test_negative_curvature_exits_and_minimiser(solver, precision, tol):
     Hf = p.hessian(xr, w.x0, a).toarray()
     assert np.linalg.eigvalsh(Hf[np.ix_(free, free)])[0] > 0      # the oracle's end point is a minimum
     assert rel(x1 - w.x0, xr - w.x0) <= tol
-    assert rel_inf(x1 - w.x0, xr - w.x0) <= tol
+    # the worst entry: from this squeezed start both solves end at the FP64 rounding floor of the
+    # gradient sum (converged or stagnated), about 1e-10 in x, where the order of the GPU's atomic
+    # additions moves the last digits from run to run; the rest shape, the exact minimiser, pins both
+    tol_inf = 3e-10 if precision == "fp64" else tol
+    assert rel_inf(x1 - w.x0, xr - w.x0) <= tol_inf
+    assert rel_inf(x1 - w.x0, w.X - w.x0) <= tol_inf
     assert rel(xr - w.x0, w.X - w.x0) <= 1e-10       # the oracle found the rest shape
 
 
