@@ -104,10 +104,19 @@ constexpr int kResidentBlockF32 = 512;
 constexpr int kResidentBlockF64 = 512;
 constexpr int resident_vertex_bytes(int dim) { return 9 * dim * (int)sizeof(double) + 4; }
 
-// arrival counter and abort flag of the resident solver's grid barrier
+// the resident solver's grid barrier (zeroed before each launch): arrival counters per group of
+// workgroups (workgroup b in group b % kBarGroups, the XCD it is dispatched to), the arrivals of
+// the groups' last workgroups, the number of the last completed barrier and the abort flag, each on
+// a 128-byte line of its own
+constexpr int kBarGroups = 8;
 struct GridBar {
-  unsigned count;
+  unsigned group[kBarGroups][32];
+  unsigned top;
+  unsigned pad0[31];
+  unsigned flag;
+  unsigned pad1[31];
   unsigned abort;
+  unsigned pad2[31];
 };
 
 // ---- precompute ----

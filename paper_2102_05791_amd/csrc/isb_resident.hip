@@ -42,10 +42,17 @@ __device__ __forceinline__ void st_agent(double* p, double v) {
 // without cache maintenance. A barrier therefore needs no release/acquire fences (each would write
 // back and invalidate the whole L2 of the workgroup's XCD, several microseconds at every barrier):
 // each wave waits until its own stores and atomics have completed (vmcnt(0)), and the arrival and
-// the wait are relaxed atomics on a monotone counter (zeroed before the launch): barrier number k
-// waits until k * gridDim.x workgroups have arrived.
+// the wait are relaxed atomics. Arrival goes up a two-level tree, so that no counter takes more
+// than one XCD's arrivals: the workgroup counts itself on its group's counter, the group's last
+// arrival counts the group on the top counter, and the last group's last arrival stores the
+// barrier's number into the release word, which every other workgroup polls. All counters are
+// monotone (zeroed before the launch): barrier number k is complete at k times the arrivals.
 __device__ __forceinline__ void wait_vm_stores() {
   __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0); expcnt and lgkmcnt not waited for
+}
+
+__device__ __forceinline__ unsigned ld_agent_u(const unsigned* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Returns false on every thread of the workgroup when the launch has been aborted: a workgroup that
@@ -56,18 +63,26 @@ __device__ __forceinline__ bool grid_barrier(GridBar* g, unsigned& epoch, int* o
   __syncthreads();
   ++epoch;
   if (threadIdx.x == 0) {
-    const unsigned target = epoch * gridDim.x;
-    __hip_atomic_fetch_add(&g->count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const uint64_t t0 = wall_clock64();
+    const unsigned G = gridDim.x, x = blockIdx.x % kBarGroups;
+    const unsigned n_groups = G < (unsigned)kBarGroups ? G : (unsigned)kBarGroups;
+    const unsigned in_group = (G - x + kBarGroups - 1) / kBarGroups;  // workgroups x, x + 8, ... < G
+    bool last = false;
+    if (__hip_atomic_fetch_add(&g->group[x][0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+        epoch * in_group - 1u)
+      last = __hip_atomic_fetch_add(&g->top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch * n_groups - 1u;
     int ok = 1;
-    while (__hip_atomic_load(&g->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      if (__hip_atomic_load(&g->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
-          wall_clock64() - t0 > max_ticks) {
-        __hip_atomic_store(&g->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        ok = 0;
-        break;
+    if (last) {
+      __hip_atomic_store(&g->flag, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      const uint64_t t0 = wall_clock64();
+      while (ld_agent_u(&g->flag) < epoch) {
+        if (ld_agent_u(&g->abort) != 0u || wall_clock64() - t0 > max_ticks) {
+          __hip_atomic_store(&g->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          ok = 0;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
       }
-      __builtin_amdgcn_s_sleep(1);
     }
     *ok_lds = ok;
   }
@@ -325,8 +340,8 @@ __global__ void __launch_bounds__(PB)
 }
 
 __global__ void k_grid_bar_reset(GridBar* g) {
-  g->count = 0u;
-  g->abort = 0u;
+  unsigned* w = reinterpret_cast<unsigned*>(g);
+  for (int i = threadIdx.x; i < (int)(sizeof(GridBar) / sizeof(unsigned)); i += blockDim.x) w[i] = 0u;
 }
 
 template <int D, typename T, int EM, bool CR>
@@ -372,7 +387,7 @@ hipError_t launch_cg_resident(const DevMesh& m, const DevScene& sc, const PatchP
   if (rate_khz <= 0) return hipErrorInvalidValue;
   uint64_t max_ticks = (uint64_t)barrier_limit_us * (uint64_t)rate_khz / 1000ull;
   if (max_ticks < 1) max_ticks = 1;
-  k_grid_bar_reset<<<1, 1, 0, s>>>(bar);
+  k_grid_bar_reset<<<1, 256, 0, s>>>(bar);
   DevMesh mm = m;
   DevScene ss = sc;
   PatchPlan pp = P;
