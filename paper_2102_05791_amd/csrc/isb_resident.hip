@@ -193,7 +193,6 @@ __global__ void __launch_bounds__(PB)
   double* acc = vl + nmax;
   double* xsl = acc + nmax;
   int* vid = reinterpret_cast<int*>(xsl + nmax);
-  double* const Wr[3] = {W0, W1, W2};
   unsigned epoch = 0;
 
   for (int v = threadIdx.x; v < nv; v += PB) vid[v] = P.verts[vb + v];
@@ -262,7 +261,29 @@ __global__ void __launch_bounds__(PB)
 
   int it = 0, negcurv = 0;
   double rr = 0.0, rr0 = 0.0, pHp = 0.0, alpha_prev = 0.0, gamma_prev = 0.0;
+  // DOF slots per thread (DOFs threadIdx.x + k * PB) whose sums are prefetched: three, and none
+  // where the element cache holds the registers (the prefetch's registers then spill, which costs
+  // more than it saves); later slots load their sums in the update pass
+  constexpr int KP = KE > 0 ? 0 : 3;
   while (ok) {
+    // W[it % 3] holds H_elem u_it (complete since the barrier). This thread's entries are loaded
+    // first, all together and before the partials, so that one round trip covers the global reads
+    // of the iteration; a slot past the patch loads its last DOF again and is not used.
+    const double* Wc = it % 3 == 0 ? W0 : (it % 3 == 1 ? W1 : W2);
+    double wv[KP > 0 ? KP : 1];
+#pragma unroll
+    for (int k = 0; k < (KP > 0 ? KP : 1); ++k) wv[k] = 0.0;
+    if (nd > 0) {
+#pragma unroll
+      for (int k = 0; k < KP; ++k) {
+        int i = min((int)threadIdx.x + k * PB, nd - 1);
+        // the slot's index is formed anew each iteration, not hoisted out of the loop and held
+        // through the element pass
+        asm volatile("" : "+v"(i));
+        const int v = i / D, c = i - v * D, raw = vid[v];
+        wv[k] = ld_agent(Wc + (size_t)(raw >= 0 ? raw : ~raw) * D + c);
+      }
+    }
     double gamma, delta;
     fold_partials<PB>(part + (it & 1) * 4 * gridDim.x, red, gamma, rr, delta);
     if (it == 0) rr0 = rr;
@@ -276,17 +297,19 @@ __global__ void __launch_bounds__(PB)
       break;
     }
     const double alpha = gamma / pHp;
-    // W[it % 3] holds H_elem u_it; this iteration sums H_elem u_{it+1} into the next and clears the
-    // one after (read last in the previous iteration, before the barrier every workgroup has passed)
-    const double* Wc = Wr[it % 3];
-    double* Wn = Wr[(it + 1) % 3];
-    double* Wz = Wr[(it + 2) % 3];
+    // this iteration sums H_elem u_{it+1} into the next W and clears the one after (read last in
+    // the previous iteration, before the barrier every workgroup has passed)
+    double* Wn = it % 3 == 0 ? W1 : (it % 3 == 1 ? W2 : W0);
+    double* Wz = it % 3 == 0 ? W2 : (it % 3 == 1 ? W0 : W1);
     g_ = r_ = d_ = 0.0;
-    for (int i = threadIdx.x; i < nd; i += PB) {
+    for (int i = threadIdx.x, k = 0; i < nd; i += PB, ++k) {
       const int v = i / D, c = i - v * D, raw = vid[v];
       const size_t g = (size_t)(raw >= 0 ? raw : ~raw) * D + c;
       const double vi = vl[i], di = dl[i];
-      const double wi = vi * ul[i] + ld_agent(Wc + g);
+      double wk = k < KP ? wv[0] : ld_agent(Wc + g);
+#pragma unroll
+      for (int q = 1; q < KP; ++q) wk = k == q ? wv[q] : wk;
+      const double wi = vi * ul[i] + wk;
       const double pi = ul[i] + beta * pl[i];
       const double si = wi + beta * sl[i];
       xsl[i] += alpha * pi;
