@@ -43,7 +43,7 @@ def test_policy_gradient_matches_oracle(solver):
     r_o.backward()
     g_cpu = [t.grad.numpy() for t in pol_o.parameters()]
 
-    assert abs(float(r) - float(r_o)) <= 1e-10 * max(1.0, abs(float(r_o)))
+    assert abs(float(r.detach()) - float(r_o.detach())) <= 1e-10 * max(1.0, abs(float(r_o.detach())))
     for gg, go in zip(g_gpu, g_cpu):
         assert np.linalg.norm(gg - go) <= 1e-7 * np.linalg.norm(go)
     assert max(np.linalg.norm(go) for go in g_cpu) > 0.0
