@@ -23,6 +23,7 @@
 
 #include <type_traits>
 
+#include "isb_body.hpp"
 #include "isb_device.hpp"
 #include "isb_elem.hpp"
 #include "isb_internal.hpp"
@@ -94,9 +95,9 @@ __device__ __forceinline__ bool grid_barrier(GridBar* g, unsigned& epoch, int* o
 template <int PB>
 __device__ __forceinline__ void workgroup_sums3(double a, double b, double c, double* red, double* out) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  a = wave_sum(a);
-  b = wave_sum(b);
-  c = wave_sum(c);
+  a = wave_total(a);
+  b = wave_total(b);
+  c = wave_total(c);
   if (lane == 0) {
     red[3 * wid] = a;
     red[3 * wid + 1] = b;
@@ -123,9 +124,9 @@ __device__ __forceinline__ void fold_partials(const double* bank, double* red, d
     v2 += ld_agent(bank + 4 * b + 2);
   }
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  v0 = wave_sum(v0);
-  v1 = wave_sum(v1);
-  v2 = wave_sum(v2);
+  v0 = wave_total(v0);
+  v1 = wave_total(v1);
+  v2 = wave_total(v2);
   if (lane == 0) {
     red[3 * wid] = v0;
     red[3 * wid + 1] = v1;
