@@ -328,7 +328,7 @@ static isb_status resident_cg(isb_ctx* c, int b, const double* x, const double* 
   *ran = false;
   if (!c->cg_resident || b < 0 || (size_t)b >= c->res_ok.size() || !c->res_ok[b]) return ISB_OK;
   const TraceRange trace("isb: CG solve, resident");
-  PatchPlan P = c->rplan;
+  PatchPlan P = resident_caches_elements(c->precision, c->model) ? c->rplan : c->rplan_fixed;
   P.max_nv = c->res_max_nv[b];
   const int p0 = c->res_patch_off[b], np = c->res_patch_off[b + 1] - p0;
   // W0..W2 are the workspaces the launch-per-iteration form uses for H u, u and s
@@ -1007,7 +1007,7 @@ static isb_status build_resident_plan(isb_ctx* c, const int32_t* T, const int64_
   c->res_ok.assign(nb, 0);
   c->res_patch_off.assign(nb + 1, 0);
   c->res_max_nv.assign(nb, 0);
-  c->rplan = PatchPlan{};
+  c->rplan = c->rplan_fixed = PatchPlan{};
   int n_cu = 0, max_lds = 0;
   ISB_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, c->device));
   ISB_HIP(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
@@ -1021,9 +1021,10 @@ static isb_status build_resident_plan(isb_ctx* c, const int32_t* T, const int64_
     any |= ne_b >= kPatchMinElems && ne_b <= (int64_t)n_cu * 8 * max_verts;
   }
   if (!any) return ISB_OK;
-  Patches rp;
+  Patches rp, rp0;
   std::vector<uint8_t> eligible;
-  ISB_TRY(build_resident_patches(dim, c->n_v, nb, c->voff.data(), body_e_off, T, n_cu, max_verts, &rp,
+  std::vector<int32_t> bpo0;
+  ISB_TRY(build_resident_patches(dim, c->n_v, nb, c->voff.data(), body_e_off, T, n_cu, max_verts, true, &rp,
                                  &c->res_patch_off, &eligible));
   int n_ok = 0;
   for (int b = 0; b < nb; ++b) {
@@ -1033,9 +1034,21 @@ static isb_status build_resident_plan(isb_ctx* c, const int32_t* T, const int64_
     n_ok += c->res_ok[b];
   }
   if (n_ok == 0) return ISB_OK;
+  // the same patches with the elements left in place (their vertex sets and owners are the same)
+  std::vector<uint8_t> eligible0;
+  ISB_TRY(build_resident_patches(dim, c->n_v, nb, c->voff.data(), body_e_off, T, n_cu, max_verts, false, &rp0,
+                                 &bpo0, &eligible0));
+  if (bpo0 != c->res_patch_off || rp0.eoff != rp.eoff || rp0.voff != rp.voff)
+    return fail(ISB_E_STATE, "resident plan: the two patch orders disagree");
   auto& L = c->mesh_allocs;
-  int32_t *r_eoff, *r_voff, *r_verts;
-  uint16_t* r_lconn;
+  int32_t *r_eoff, *r_voff, *r_verts, *r_eperm, *r_verts0;
+  uint16_t *r_lconn, *r_lconn0;
+  ISB_TRY(dalloc(L, &r_eperm, rp.eperm.size()));
+  ISB_HIP(hipMemcpy(r_eperm, rp.eperm.data(), rp.eperm.size() * 4, hipMemcpyHostToDevice));
+  ISB_TRY(dalloc(L, &r_verts0, rp0.verts.size()));
+  ISB_HIP(hipMemcpy(r_verts0, rp0.verts.data(), rp0.verts.size() * 4, hipMemcpyHostToDevice));
+  ISB_TRY(dalloc(L, &r_lconn0, rp0.lconn.size()));
+  ISB_HIP(hipMemcpy(r_lconn0, rp0.lconn.data(), rp0.lconn.size() * 2, hipMemcpyHostToDevice));
   ISB_TRY(dalloc(L, &r_eoff, rp.eoff.size()));
   ISB_TRY(dalloc(L, &r_voff, rp.voff.size()));
   ISB_TRY(dalloc(L, &r_verts, rp.verts.size()));
@@ -1044,7 +1057,8 @@ static isb_status build_resident_plan(isb_ctx* c, const int32_t* T, const int64_
   ISB_HIP(hipMemcpy(r_voff, rp.voff.data(), rp.voff.size() * 4, hipMemcpyHostToDevice));
   ISB_HIP(hipMemcpy(r_verts, rp.verts.data(), rp.verts.size() * 4, hipMemcpyHostToDevice));
   ISB_HIP(hipMemcpy(r_lconn, rp.lconn.data(), rp.lconn.size() * 2, hipMemcpyHostToDevice));
-  c->rplan = PatchPlan{r_eoff, r_voff, r_verts, r_lconn, rp.max_nv};
+  c->rplan = PatchPlan{r_eoff, r_voff, r_verts, r_lconn, rp.max_nv, 0, r_eperm};
+  c->rplan_fixed = PatchPlan{r_eoff, r_voff, r_verts0, r_lconn0, rp0.max_nv, 0, nullptr};
   c->res_cu = n_cu;
   return ISB_OK;
 }

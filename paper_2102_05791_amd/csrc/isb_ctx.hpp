@@ -61,10 +61,12 @@ struct isb_ctx {
 
   // the resident CG solver's plan (isb::build_resident_patches): body b's patches
   // [res_patch_off[b], res_patch_off[b+1]) of rplan, largest vertex list res_max_nv[b]; res_ok[b]
-  // when the body takes the resident solver; res_cu: the compute units the plan was cut for
+  // when the body takes the resident solver; res_cu: the compute units the plan was cut for.
+  // rplan regroups each patch's elements (eperm) for the kernel that holds them in registers;
+  // rplan_fixed keeps the elements' order (its loads stay coalesced) and only renumbers vertices.
   std::vector<int32_t> res_patch_off, res_max_nv;
   std::vector<uint8_t> res_ok;
-  isb::PatchPlan rplan{};
+  isb::PatchPlan rplan{}, rplan_fixed{};
   int res_cu = 0;
   isb::GridBar* gbar = nullptr;  // the resident solver's barrier (device)
 

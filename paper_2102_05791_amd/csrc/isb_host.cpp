@@ -142,12 +142,212 @@ isb_status build_patches(int dim, int64_t n_v, int n_bodies, const int64_t* eoff
   return ISB_OK;
 }
 
+
+// ---- LDS bank balance of a resident patch (see isb_host.hpp) ----
+namespace {
+
+constexpr int kLanes = 64;
+
+// splitmix64: a small deterministic generator for the local search
+struct Mix {
+  uint64_t s;
+  uint64_t next() {
+    uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  }
+  int below(int n) { return (int)(next() % (uint64_t)n); }
+};
+
+int bank_classes(int dim) { return dim == 3 ? 32 : 16; }
+
+}  // namespace
+
+void balance_patch(int dim, int ne, int nv, const int32_t* tloc, bool move_elements, std::vector<int32_t>* order,
+                   std::vector<int32_t>* newid) {
+  const int nk = dim + 1, nc = bank_classes(dim);
+  const int ng = (ne + kLanes - 1) / kLanes;
+  // the change of the sum of squared counts when one count goes from c to c + 1 or c - 1
+  auto up = [](int64_t c) { return 2 * c + 1; };
+  auto down = [](int64_t c) { return -2 * c + 1; };
+  order->resize(ne);
+  newid->resize(nv);
+  for (int v = 0; v < nv; ++v) (*newid)[v] = v;
+  if (ne == 0) return;
+  std::vector<int32_t>& id = *newid;
+  // cnt[(g * nk + q) * nc + class]: lanes of group g whose corner q has that class
+  std::vector<int32_t> cnt((size_t)ng * nk * nc, 0);
+  std::vector<int32_t> grp(ne, -1), fill(ng, 0), cap(ng, kLanes);
+  cap[ng - 1] = ne - (ng - 1) * kLanes;
+  auto at = [&](int g, int q, int v) -> int32_t& { return cnt[((size_t)g * nk + q) * nc + id[v] % nc]; };
+  // greedy: each element to the group with room where its corners' classes are least used (in
+  // slot order when the elements stay where they are)
+  for (int e = 0; e < ne; ++e) {
+    const int32_t* t = tloc + (size_t)e * nk;
+    int best = move_elements ? -1 : e / kLanes;
+    int64_t bc = 0;
+    for (int g = 0; g < ng && move_elements; ++g) {
+      if (fill[g] >= cap[g]) continue;
+      int64_t c = 0;
+      for (int q = 0; q < nk; ++q) c += up(at(g, q, t[q]));
+      if (best < 0 || c < bc) {
+        best = g;
+        bc = c;
+      }
+    }
+    grp[e] = best;
+    ++fill[best];
+    for (int q = 0; q < nk; ++q) ++at(best, q, t[q]);
+  }
+  // incidences of each vertex: (element, corner)
+  std::vector<int32_t> ioff(nv + 1, 0), inc((size_t)ne * nk);
+  for (int e = 0; e < ne; ++e)
+    for (int q = 0; q < nk; ++q) ++ioff[tloc[(size_t)e * nk + q] + 1];
+  for (int v = 0; v < nv; ++v) ioff[v + 1] += ioff[v];
+  {
+    std::vector<int32_t> pos(ioff.begin(), ioff.end() - 1);
+    for (int e = 0; e < ne; ++e)
+      for (int q = 0; q < nk; ++q) inc[pos[tloc[(size_t)e * nk + q]]++] = e * nk + q;
+  }
+  Mix rng{0x51A7E5EEDull + (uint64_t)ne * 131 + (uint64_t)nv};
+  std::vector<int32_t> pos_of(nv);  // the vertex holding each local id
+  for (int v = 0; v < nv; ++v) pos_of[id[v]] = v;
+  for (int round = 0; round < 2; ++round) {
+    // element swaps between two groups
+    if (ng > 1 && move_elements)
+      for (int it = 0; it < 4 * ne; ++it) {
+        const int a = rng.below(ne), b = rng.below(ne);
+        const int ga = grp[a], gb = grp[b];
+        if (ga == gb) continue;
+        const int32_t *ta = tloc + (size_t)a * nk, *tb = tloc + (size_t)b * nk;
+        int64_t d = 0;
+        for (int q = 0; q < nk; ++q) {
+          const int ca = id[ta[q]] % nc, cb = id[tb[q]] % nc;
+          if (ca == cb) continue;
+          // a leaves ga and enters gb; b leaves gb and enters ga
+          d += down(cnt[((size_t)ga * nk + q) * nc + ca]) + up(cnt[((size_t)gb * nk + q) * nc + ca]);
+          d += down(cnt[((size_t)gb * nk + q) * nc + cb]) + up(cnt[((size_t)ga * nk + q) * nc + cb]);
+        }
+        if (d >= 0) continue;
+        for (int q = 0; q < nk; ++q) {
+          --at(ga, q, ta[q]);
+          ++at(gb, q, ta[q]);
+          --at(gb, q, tb[q]);
+          ++at(ga, q, tb[q]);
+        }
+        grp[a] = gb;
+        grp[b] = ga;
+      }
+    // exchanges of two vertices' local ids (their classes), only within a window of nc consecutive
+    // ids: the patch's per-DOF loops walk the ids in order, so each wavefront's global loads and
+    // stores then stay on the cache lines of the sorted order
+    for (int it = 0; it < 4 * nv; ++it) {
+      const int u = rng.below(nv);
+      const int base = id[u] / nc * nc, span = std::min(nc, nv - base);
+      const int w = pos_of[base + rng.below(span)];
+      const int cu = id[u] % nc, cw = id[w] % nc;
+      if (cu == cw) continue;
+      // moving u's incidences from class cu to cw and w's from cw to cu; where u and w share a
+      // (group, corner) the two moves cancel, so apply them one at a time to the counts
+      int64_t d = 0;
+      for (int k = ioff[u]; k < ioff[u + 1]; ++k) {
+        const int e = inc[k] / nk, q = inc[k] % nk;
+        int32_t* c = &cnt[((size_t)grp[e] * nk + q) * nc];
+        d += down(c[cu]);
+        --c[cu];
+        d += up(c[cw]);
+        ++c[cw];
+      }
+      for (int k = ioff[w]; k < ioff[w + 1]; ++k) {
+        const int e = inc[k] / nk, q = inc[k] % nk;
+        int32_t* c = &cnt[((size_t)grp[e] * nk + q) * nc];
+        d += down(c[cw]);
+        --c[cw];
+        d += up(c[cu]);
+        ++c[cu];
+      }
+      if (d < 0) {
+        std::swap(id[u], id[w]);
+        pos_of[id[u]] = u;
+        pos_of[id[w]] = w;
+        continue;
+      }
+      // undo
+      for (int k = ioff[w]; k < ioff[w + 1]; ++k) {
+        const int e = inc[k] / nk, q = inc[k] % nk;
+        int32_t* c = &cnt[((size_t)grp[e] * nk + q) * nc];
+        --c[cu];
+        ++c[cw];
+      }
+      for (int k = ioff[u]; k < ioff[u + 1]; ++k) {
+        const int e = inc[k] / nk, q = inc[k] % nk;
+        int32_t* c = &cnt[((size_t)grp[e] * nk + q) * nc];
+        --c[cw];
+        ++c[cu];
+      }
+    }
+  }
+  // slots: group by group, each in the original element order
+  std::fill(fill.begin(), fill.end(), 0);
+  for (int e = 0; e < ne; ++e) {
+    const int g = grp[e];
+    (*order)[(size_t)g * kLanes + fill[g]++] = e;
+  }
+  // the search lowers the sum of squared counts, not always the largest count: keep the layout it
+  // started from unless the largest counts fall
+  std::vector<int32_t> ident_e(ne), ident_v(nv);
+  for (int e = 0; e < ne; ++e) ident_e[e] = e;
+  for (int v = 0; v < nv; ++v) ident_v[v] = v;
+  if (patch_bank_load(dim, ne, tloc, order->data(), id.data()) >=
+      patch_bank_load(dim, ne, tloc, ident_e.data(), ident_v.data())) {
+    *order = ident_e;
+    id = ident_v;
+  }
+}
+
+double patch_bank_load(int dim, int ne, const int32_t* tloc, const int32_t* order, const int32_t* newid) {
+  const int nk = dim + 1, nc = bank_classes(dim);
+  const int ng = (ne + kLanes - 1) / kLanes;
+  if (ng == 0) return 0.0;
+  double tot = 0.0;
+  std::vector<int> c(nc);
+  for (int g = 0; g < ng; ++g)
+    for (int q = 0; q < nk; ++q) {
+      std::fill(c.begin(), c.end(), 0);
+      int mx = 0;
+      for (int s = g * kLanes; s < std::min(ne, (g + 1) * kLanes); ++s)
+        mx = std::max(mx, ++c[newid[tloc[(size_t)order[s] * nk + q]] % nc]);
+      tot += mx;
+    }
+  return tot / (ng * nk);
+}
+
 isb_status build_resident_patches(int dim, int64_t n_v, int n_bodies, const int64_t* voff, const int64_t* eoff,
-                                  const int32_t* T, int n_blocks, int max_verts, Patches* out,
+                                  const int32_t* T, int n_blocks, int max_verts, bool move_elements, Patches* out,
                                   std::vector<int32_t>* body_patch_off, std::vector<uint8_t>* eligible) {
   if (n_blocks < 1) return fail(ISB_E_ARG, "resident plan: no workgroups");
   const isb_status st = build_patches(dim, n_v, n_bodies, eoff, T, 1 << 30, max_verts, out, n_blocks);
   if (st != ISB_OK) return st;
+  // bank-balanced element slots and vertex numbering in every patch
+  const int nk = dim + 1;
+  const int64_t n_e = eoff[n_bodies];
+  out->eperm.resize((size_t)n_e);
+  std::vector<int32_t> tloc, order, newid, vnew;
+  for (size_t k = 0; k + 1 < out->eoff.size(); ++k) {
+    const int e0 = out->eoff[k], ne = out->eoff[k + 1] - e0;
+    const int v0 = out->voff[k], nv = out->voff[k + 1] - v0;
+    tloc.resize((size_t)ne * nk);
+    for (int e = 0; e < ne; ++e)
+      for (int q = 0; q < nk; ++q) tloc[(size_t)e * nk + q] = out->lconn[(size_t)q * n_e + e0 + e];
+    balance_patch(dim, ne, nv, tloc.data(), move_elements, &order, &newid);
+    for (int s = 0; s < ne; ++s) out->eperm[(size_t)e0 + s] = e0 + order[s];
+    for (int e = 0; e < ne; ++e)
+      for (int q = 0; q < nk; ++q) out->lconn[(size_t)q * n_e + e0 + e] = (uint16_t)newid[tloc[(size_t)e * nk + q]];
+    vnew.resize(nv);
+    for (int v = 0; v < nv; ++v) vnew[newid[v]] = out->verts[(size_t)v0 + v];
+    std::copy(vnew.begin(), vnew.end(), out->verts.begin() + v0);
+  }
   std::vector<uint8_t> owned((size_t)n_v, 0);
   for (size_t i = 0; i < out->verts.size(); ++i) {
     const int32_t v = out->verts[i];

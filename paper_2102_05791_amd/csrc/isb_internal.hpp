@@ -66,10 +66,11 @@ struct ERange {
 struct PatchPlan {
   const int32_t* eoff;    // [n_patch+1] element range of each patch
   const int32_t* voff;    // [n_patch+1] range of each patch's vertex list
-  const int32_t* verts;   // distinct vertices of each patch, sorted
+  const int32_t* verts;   // distinct vertices of each patch (sorted, but in the resident plan)
   const uint16_t* lconn;  // [(D+1)][n_e] corner index into the patch's vertex list
   int max_nv;             // largest vertex list
   int block;              // threads per patch workgroup: 256, 512 or 1024 (0: the default)
+  const int32_t* eperm;   // [n_e] element of each slot of a patch's range (null: the slot itself)
 };
 
 constexpr int kPatchBlock = 512;        // threads per patch workgroup (FP32 element math; FP64 takes half)
@@ -186,6 +187,9 @@ void launch_cgcg_final(int n, const double* partials, CgScal* scal, hipStream_t 
 // Vectors are the global [n_v][D] arrays; W0..W2 are [n_v][D] scratch, part 8 * np values.
 // Returns hipErrorCooperativeLaunchTooLarge, launching nothing, when np workgroups cannot all be
 // resident. ----
+// whether the resident kernel for this precision (1: mixed) and energy model keeps its elements'
+// state in registers (and so takes the plan whose element slots are regrouped)
+bool resident_caches_elements(int precision, int model);
 hipError_t launch_cg_resident(const DevMesh& m, const DevScene& sc, const PatchPlan& P, int p0, int np, int n_cu,
                               int precision, const double* x, const double* a, const float* a32, const double* rhs,
                               double sign, const double* Dinvp, const double* vdiag, double* xs, double* W0,

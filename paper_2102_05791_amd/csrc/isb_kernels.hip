@@ -1235,7 +1235,7 @@ __global__ void __launch_bounds__(PB) k_elem_patch(DevMesh m, DevScene sc, Patch
       }
     }
     __syncthreads();
-    patch_elements<D, T, OP, EM, CR>(m, sc, P.lconn, eb, ee, xs, ps, acc, a, a32, curv != nullptr, php);
+    patch_elements<D, T, OP, EM, CR>(m, sc, P.lconn, P.eperm, eb, ee, xs, ps, acc, a, a32, curv != nullptr, php);
     __syncthreads();
     for (int i = threadIdx.x; i < nv * D; i += blockDim.x) {
       const int vl = i / D, c = i - vl * D;

@@ -42,14 +42,16 @@ __device__ __forceinline__ void patch_hv_element(const ElemRest<D, T>& R, const 
 }
 
 // lconn: [(D+1)][n_e] patch-local corner ids; xs, ps, acc: [local vertex][D] in LDS, FP64 (edge
-// differences of x and p are formed in FP64, then rounded to T). php (Hessian-vector products with
+// differences of x and p are formed in FP64, then rounded to T). Slots [eb, ee) hold the elements
+// eperm[slot] (the slots themselves when eperm is null). php (Hessian-vector products with
 // want_curv): this thread's sum over its elements of p_e . (H_e p_e), unscaled by s_pot.
 template <int D, typename T, int OP, int EM, bool CR>
 __device__ __forceinline__ void patch_elements(const DevMesh& m, const DevScene& sc, const uint16_t* __restrict__ lconn,
-                                               int eb, int ee, const double* xs, const double* ps, double* acc,
-                                               const double* __restrict__ a, const float* __restrict__ a32,
-                                               bool want_curv, double& php) {
-  for (int e = eb + threadIdx.x; e < ee; e += blockDim.x) {
+                                               const int32_t* __restrict__ eperm, int eb, int ee, const double* xs,
+                                               const double* ps, double* acc, const double* __restrict__ a,
+                                               const float* __restrict__ a32, bool want_curv, double& php) {
+  for (int slot = eb + threadIdx.x; slot < ee; slot += blockDim.x) {
+    const int e = eperm ? eperm[slot] : slot;
     int l[D + 1];
 #pragma unroll
     for (int k = 0; k <= D; ++k) l[k] = lconn[(size_t)k * m.n_e + e];

@@ -161,10 +161,10 @@ __device__ __forceinline__ void resident_hv_pass(const DevMesh& m, const DevScen
                                                  const T (&ca)[KS], const int (&cl)[KS][D + 1], double& php) {
 #pragma unroll
   for (int k = 0; k < KE; ++k) {
-    const int e = eb + threadIdx.x + k * PB;
-    if (e < ec) patch_hv_element<D, T, EM>(cR[k], cS[k], ca[k], cl[k], ul, acc, sc.s_pot, true, php);
+    if (eb + (int)threadIdx.x + k * PB < ec)
+      patch_hv_element<D, T, EM>(cR[k], cS[k], ca[k], cl[k], ul, acc, sc.s_pot, true, php);
   }
-  patch_elements<D, T, PATCH_HV, EM, CR>(m, sc, P.lconn, ec, ee, xl, ul, acc, a, a32, true, php);
+  patch_elements<D, T, PATCH_HV, EM, CR>(m, sc, P.lconn, P.eperm, ec, ee, xl, ul, acc, a, a32, true, php);
 }
 
 // The workgroup of patch p0 + blockIdx.x. LDS: nine [max_nv][D] FP64 arrays, then the vertex ids
@@ -232,8 +232,9 @@ __global__ void __launch_bounds__(PB)
   int cl[KS][D + 1];
 #pragma unroll
   for (int k = 0; k < KE; ++k) {
-    const int e = eb + threadIdx.x + k * PB;
-    if (e < ec) {
+    const int slot = eb + threadIdx.x + k * PB;
+    if (slot < ec) {
+      const int e = P.eperm ? P.eperm[slot] : slot;
 #pragma unroll
       for (int q = 0; q <= D; ++q) cl[k][q] = P.lconn[(size_t)q * m.n_e + e];
       load_rest<D, T, CR>(m, e, cR[k]);
@@ -382,6 +383,11 @@ static const void* resident_kernel_dt(int model, bool compact) {
     case EM_SNH: return compact ? resident_kernel_for<D, T, EM_SNH, true>() : resident_kernel_for<D, T, EM_SNH, false>();
     default: return compact ? resident_kernel_for<D, T, EM_NH, true>() : resident_kernel_for<D, T, EM_NH, false>();
   }
+}
+
+bool resident_caches_elements(int precision, int model) {
+  return precision ? resident_cached_per_thread<float, EM_NH, kResidentBlockF32>() > 0 && model == EM_NH
+                   : resident_cached_per_thread<double, EM_NH, kResidentBlockF64>() > 0 && model == EM_NH;
 }
 
 hipError_t launch_cg_resident(const DevMesh& m, const DevScene& sc, const PatchPlan& P, int p0, int np, int n_cu,

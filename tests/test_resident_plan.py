@@ -2,7 +2,10 @@
 cut into at most one patch per resident workgroup, every element in exactly one patch of its own body,
 each patch's vertex list exactly its elements' vertices, the patch-local corners pointing at them,
 every vertex owned by exactly one patch (the first that holds it) and the eligibility rules: too many
-patches, or a vertex no element uses, keep a body off the resident solver."""
+patches, or a vertex no element uses, keep a body off the resident solver. Both forms of the plan are
+checked: element slots regrouped (eperm a permutation of each patch's range) and kept in place (eperm
+the identity). The LDS bank balance of a patch is checked against the load it starts from, against a
+brute-force count of the same measure, and for keeping vertex ids inside their 32-id windows."""
 import ctypes
 import os
 import subprocess
@@ -34,20 +37,21 @@ def _p(a):
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
-def plan(lib, dim, X, T, voff, eoff, n_blocks, max_verts):
+def plan(lib, dim, X, T, voff, eoff, n_blocks, max_verts, move=True):
     n_v, n_e, nb = X.shape[0], T.shape[0], len(voff) - 1
     T = np.ascontiguousarray(T, np.int32)
     voff = np.ascontiguousarray(voff, np.int64)
     eoff = np.ascontiguousarray(eoff, np.int64)
     pe, pv = np.zeros(n_e + 1, np.int32), np.zeros(n_e + 1, np.int32)
     verts, lconn = np.zeros((dim + 1) * n_e, np.int32), np.zeros((dim + 1) * n_e, np.uint16)
+    eperm = np.full(n_e, -1, np.int32)
     bpo, ok, cnt = np.zeros(nb + 1, np.int32), np.zeros(nb, np.uint8), np.zeros(3, np.int32)
-    st = lib.emu_resident_plan(dim, ctypes.c_int64(n_v), nb, _p(voff), _p(eoff), _p(T), n_blocks, max_verts, _p(pe),
-                               _p(pv), _p(verts), _p(lconn), _p(bpo), _p(ok), _p(cnt))
+    st = lib.emu_resident_plan(dim, ctypes.c_int64(n_v), nb, _p(voff), _p(eoff), _p(T), n_blocks, max_verts,
+                               int(move), _p(pe), _p(pv), _p(verts), _p(lconn), _p(eperm), _p(bpo), _p(ok), _p(cnt))
     assert st == 0
     npch, nsl = int(cnt[0]), int(cnt[1])
     return dict(eoff=pe[:npch + 1], voff=pv[:npch + 1], verts=verts[:nsl], lconn=lconn.reshape(dim + 1, n_e),
-                bpo=bpo, ok=ok.astype(bool), max_nv=int(cnt[2]))
+                eperm=eperm, bpo=bpo, ok=ok.astype(bool), max_nv=int(cnt[2]), move=move)
 
 
 def check_plan(P, dim, T, voff, eoff, n_blocks, max_verts):
@@ -65,9 +69,19 @@ def check_plan(P, dim, T, voff, eoff, n_blocks, max_verts):
         assert P["bpo"][b] <= k < P["bpo"][b + 1]
         vk = decoded[pv[k]:pv[k + 1]]
         assert len(vk) <= max_verts and len(vk) <= P["max_nv"]
-        assert np.array_equal(vk, np.unique(T[e0:e1].ravel())), "patch vertices != its elements' vertices"
+        assert np.array_equal(np.sort(vk), np.unique(T[e0:e1].ravel())), "patch vertices != its elements' vertices"
+        # ids move only inside windows of 32 (3D) or 16 (2D): the sorted vertex at position j keeps
+        # an id in the same window
+        win = 32 if dim == 3 else 16
+        order = np.argsort(vk)
+        assert np.array_equal(order // win, np.arange(len(vk)) // win), "a vertex id left its window"
         for c in range(dim + 1):
             assert np.array_equal(vk[P["lconn"][c, e0:e1]], T[e0:e1, c])
+        slots = P["eperm"][e0:e1]
+        if P["move"]:
+            assert np.array_equal(np.sort(slots), np.arange(e0, e1)), "slots are not a permutation of the patch"
+        else:
+            assert np.array_equal(slots, np.arange(e0, e1))
         own = verts[pv[k]:pv[k + 1]] >= 0
         owners[vk[own]] += 1
         newly = first[vk] < 0
@@ -113,3 +127,46 @@ def test_resident_plan_unused_vertex_not_eligible(lib):
     P = plan(lib, 3, Xc, Tc, vo, eo, 16, 4000)
     check_plan(P, 3, Tc, vo, eo, 16, 4000)
     assert P["ok"][0] and not P["ok"][1]
+
+
+@pytest.mark.parametrize("move", [True, False])
+def test_resident_plan_both_slot_forms(lib, move):
+    X, T = meshes.tet_grid(12, 8, 6)
+    vo, eo = np.array([0, X.shape[0]]), np.array([0, T.shape[0]])
+    P = plan(lib, 3, X, T, vo, eo, 8, 4000, move=move)
+    check_plan(P, 3, T, vo, eo, 8, 4000)
+    assert P["ok"][0]
+
+
+def _class_load(dim, tloc, order, newid):
+    """mean over (group of 64 slots, corner) of the most lanes whose vertex ids share a bank class"""
+    nc = 32 if dim == 3 else 16
+    loads = []
+    for g in range(0, len(order), 64):
+        for q in range(dim + 1):
+            cls = newid[tloc[order[g:g + 64], q]] % nc
+            loads.append(np.bincount(cls, minlength=nc).max())
+    return float(np.mean(loads))
+
+
+@pytest.mark.parametrize("dim,move", [(3, True), (3, False), (2, True)])
+def test_patch_bank_balance(lib, dim, move):
+    X, T = meshes.tet_grid(8, 8, 4) if dim == 3 else meshes.tri_grid(40, 24)
+    T = T[:1536] if dim == 3 else T[:1920]
+    ids = np.unique(T.ravel())
+    tloc = np.ascontiguousarray(np.searchsorted(ids, T).astype(np.int32))
+    ne, nv = tloc.shape[0], len(ids)
+    order, newid, loads = np.zeros(ne, np.int32), np.zeros(nv, np.int32), np.zeros(2)
+    lib.emu_patch_balance(dim, ne, nv, _p(tloc), int(move), _p(order), _p(newid), _p(loads))
+    assert np.array_equal(np.sort(order), np.arange(ne))
+    assert np.array_equal(np.sort(newid), np.arange(nv))
+    if not move:
+        assert np.array_equal(order, np.arange(ne))
+    # the library's measure agrees with a brute-force count, before and after
+    assert loads[0] == pytest.approx(_class_load(dim, tloc, np.arange(ne), np.arange(nv)))
+    assert loads[1] == pytest.approx(_class_load(dim, tloc, order, newid))
+    assert loads[1] <= loads[0]
+    if dim == 3:
+        # a 1,536-element Kuhn patch: about 6 lanes per class in the grid's order; 3 after with the
+        # elements regrouped, below 5 with the vertex ids alone
+        assert loads[0] >= 5.0 and loads[1] <= (3.3 if move else 5.0)
