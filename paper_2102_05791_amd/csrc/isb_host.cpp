@@ -323,15 +323,8 @@ double patch_bank_load(int dim, int ne, const int32_t* tloc, const int32_t* orde
   return tot / (ng * nk);
 }
 
-isb_status build_resident_patches(int dim, int64_t n_v, int n_bodies, const int64_t* voff, const int64_t* eoff,
-                                  const int32_t* T, int n_blocks, int max_verts, bool move_elements, Patches* out,
-                                  std::vector<int32_t>* body_patch_off, std::vector<uint8_t>* eligible) {
-  if (n_blocks < 1) return fail(ISB_E_ARG, "resident plan: no workgroups");
-  const isb_status st = build_patches(dim, n_v, n_bodies, eoff, T, 1 << 30, max_verts, out, n_blocks);
-  if (st != ISB_OK) return st;
-  // bank-balanced element slots and vertex numbering in every patch
+void balance_patches(int dim, int64_t n_e, bool move_elements, Patches* out) {
   const int nk = dim + 1;
-  const int64_t n_e = eoff[n_bodies];
   out->eperm.resize((size_t)n_e);
   std::vector<int32_t> tloc, order, newid, vnew;
   for (size_t k = 0; k + 1 < out->eoff.size(); ++k) {
@@ -348,6 +341,15 @@ isb_status build_resident_patches(int dim, int64_t n_v, int n_bodies, const int6
     for (int v = 0; v < nv; ++v) vnew[newid[v]] = out->verts[(size_t)v0 + v];
     std::copy(vnew.begin(), vnew.end(), out->verts.begin() + v0);
   }
+}
+
+isb_status build_resident_patches(int dim, int64_t n_v, int n_bodies, const int64_t* voff, const int64_t* eoff,
+                                  const int32_t* T, int n_blocks, int max_verts, bool move_elements, Patches* out,
+                                  std::vector<int32_t>* body_patch_off, std::vector<uint8_t>* eligible) {
+  if (n_blocks < 1) return fail(ISB_E_ARG, "resident plan: no workgroups");
+  const isb_status st = build_patches(dim, n_v, n_bodies, eoff, T, 1 << 30, max_verts, out, n_blocks);
+  if (st != ISB_OK) return st;
+  balance_patches(dim, eoff[n_bodies], move_elements, out);
   std::vector<uint8_t> owned((size_t)n_v, 0);
   for (size_t i = 0; i < out->verts.size(); ++i) {
     const int32_t v = out->verts[i];

@@ -66,6 +66,9 @@ constexpr int patch_max_verts(int dim) { return kPatchLdsBytes / (3 * dim * (int
 // the vertex numbering is chosen.
 void balance_patch(int dim, int ne, int nv, const int32_t* tloc, bool move_elements, std::vector<int32_t>* order,
                    std::vector<int32_t>* newid);
+// balance_patch on every patch of out (n_e elements in all): eperm receives each patch's slots
+// (the identity without move_elements), lconn and verts the new vertex numbering
+void balance_patches(int dim, int64_t n_e, bool move_elements, Patches* out);
 // mean over (group, corner) of the largest class count, for the slots and numbering given
 double patch_bank_load(int dim, int ne, const int32_t* tloc, const int32_t* order, const int32_t* newid);
 
