@@ -1038,11 +1038,13 @@ static isb_status build_resident_plan(isb_ctx* c, const int32_t* T, const int64_
   std::vector<uint8_t> eligible0;
   ISB_TRY(build_resident_patches(dim, c->n_v, nb, c->voff.data(), body_e_off, T, n_cu, max_verts, false, &rp0,
                                  &bpo0, &eligible0));
-  if (bpo0 != c->res_patch_off || rp0.eoff != rp.eoff || rp0.voff != rp.voff)
+  if (bpo0 != c->res_patch_off || rp0.eoff != rp.eoff || rp0.voff != rp.voff || rp0.nshared != rp.nshared)
     return fail(ISB_E_STATE, "resident plan: the two patch orders disagree");
   auto& L = c->mesh_allocs;
-  int32_t *r_eoff, *r_voff, *r_verts, *r_eperm, *r_verts0;
+  int32_t *r_eoff, *r_voff, *r_verts, *r_eperm, *r_verts0, *r_nsh;
   uint16_t *r_lconn, *r_lconn0;
+  ISB_TRY(dalloc(L, &r_nsh, rp.nshared.size()));
+  ISB_HIP(hipMemcpy(r_nsh, rp.nshared.data(), rp.nshared.size() * 4, hipMemcpyHostToDevice));
   ISB_TRY(dalloc(L, &r_eperm, rp.eperm.size()));
   ISB_HIP(hipMemcpy(r_eperm, rp.eperm.data(), rp.eperm.size() * 4, hipMemcpyHostToDevice));
   ISB_TRY(dalloc(L, &r_verts0, rp0.verts.size()));
@@ -1057,8 +1059,8 @@ static isb_status build_resident_plan(isb_ctx* c, const int32_t* T, const int64_
   ISB_HIP(hipMemcpy(r_voff, rp.voff.data(), rp.voff.size() * 4, hipMemcpyHostToDevice));
   ISB_HIP(hipMemcpy(r_verts, rp.verts.data(), rp.verts.size() * 4, hipMemcpyHostToDevice));
   ISB_HIP(hipMemcpy(r_lconn, rp.lconn.data(), rp.lconn.size() * 2, hipMemcpyHostToDevice));
-  c->rplan = PatchPlan{r_eoff, r_voff, r_verts, r_lconn, rp.max_nv, 0, r_eperm};
-  c->rplan_fixed = PatchPlan{r_eoff, r_voff, r_verts0, r_lconn0, rp0.max_nv, 0, nullptr};
+  c->rplan = PatchPlan{r_eoff, r_voff, r_verts, r_lconn, rp.max_nv, 0, r_eperm, r_nsh};
+  c->rplan_fixed = PatchPlan{r_eoff, r_voff, r_verts0, r_lconn0, rp0.max_nv, 0, nullptr, r_nsh};
   c->res_cu = n_cu;
   return ISB_OK;
 }

@@ -146,7 +146,7 @@ isb_status build_patches(int dim, int64_t n_v, int n_bodies, const int64_t* eoff
 // ---- LDS bank balance of a resident patch (see isb_host.hpp) ----
 namespace {
 
-constexpr int kLanes = 64;
+constexpr int kLanes = 32;  // lanes the LDS serves together in one FP64 pass: half a wavefront
 
 // splitmix64: a small deterministic generator for the local search
 struct Mix {
@@ -164,8 +164,8 @@ int bank_classes(int dim) { return dim == 3 ? 32 : 16; }
 
 }  // namespace
 
-void balance_patch(int dim, int ne, int nv, const int32_t* tloc, bool move_elements, std::vector<int32_t>* order,
-                   std::vector<int32_t>* newid) {
+void balance_patch(int dim, int ne, int nv, const int32_t* tloc, bool move_elements, int split,
+                   std::vector<int32_t>* order, std::vector<int32_t>* newid) {
   const int nk = dim + 1, nc = bank_classes(dim);
   const int ng = (ne + kLanes - 1) / kLanes;
   // the change of the sum of squared counts when one count goes from c to c + 1 or c - 1
@@ -176,11 +176,16 @@ void balance_patch(int dim, int ne, int nv, const int32_t* tloc, bool move_eleme
   for (int v = 0; v < nv; ++v) (*newid)[v] = v;
   if (ne == 0) return;
   std::vector<int32_t>& id = *newid;
-  // cnt[(g * nk + q) * nc + class]: lanes of group g whose corner q has that class
+  // cnt[(g * nk + q) * nc + class]: lanes of group g whose corner q has that class; dup[(g * nk +
+  // q) * nv + v]: lanes of group g whose corner q is vertex v. Two lanes at one vertex serialise
+  // their atomics outright, so the element moves weigh a repeated vertex kDup times a class clash.
+  constexpr int64_t kDup = 16;
   std::vector<int32_t> cnt((size_t)ng * nk * nc, 0);
+  std::vector<int32_t> dup(move_elements ? (size_t)ng * nk * nv : 0, 0);
   std::vector<int32_t> grp(ne, -1), fill(ng, 0), cap(ng, kLanes);
   cap[ng - 1] = ne - (ng - 1) * kLanes;
   auto at = [&](int g, int q, int v) -> int32_t& { return cnt[((size_t)g * nk + q) * nc + id[v] % nc]; };
+  auto dv = [&](int g, int q, int v) -> int32_t& { return dup[((size_t)g * nk + q) * nv + v]; };
   // greedy: each element to the group with room where its corners' classes are least used (in
   // slot order when the elements stay where they are)
   for (int e = 0; e < ne; ++e) {
@@ -190,7 +195,7 @@ void balance_patch(int dim, int ne, int nv, const int32_t* tloc, bool move_eleme
     for (int g = 0; g < ng && move_elements; ++g) {
       if (fill[g] >= cap[g]) continue;
       int64_t c = 0;
-      for (int q = 0; q < nk; ++q) c += up(at(g, q, t[q]));
+      for (int q = 0; q < nk; ++q) c += up(at(g, q, t[q])) + kDup * up(dv(g, q, t[q]));
       if (best < 0 || c < bc) {
         best = g;
         bc = c;
@@ -198,7 +203,10 @@ void balance_patch(int dim, int ne, int nv, const int32_t* tloc, bool move_eleme
     }
     grp[e] = best;
     ++fill[best];
-    for (int q = 0; q < nk; ++q) ++at(best, q, t[q]);
+    for (int q = 0; q < nk; ++q) {
+      ++at(best, q, t[q]);
+      if (move_elements) ++dv(best, q, t[q]);
+    }
   }
   // incidences of each vertex: (element, corner)
   std::vector<int32_t> ioff(nv + 1, 0), inc((size_t)ne * nk);
@@ -223,6 +231,8 @@ void balance_patch(int dim, int ne, int nv, const int32_t* tloc, bool move_eleme
         const int32_t *ta = tloc + (size_t)a * nk, *tb = tloc + (size_t)b * nk;
         int64_t d = 0;
         for (int q = 0; q < nk; ++q) {
+          if (ta[q] != tb[q])
+            d += kDup * (down(dv(ga, q, ta[q])) + up(dv(gb, q, ta[q])) + down(dv(gb, q, tb[q])) + up(dv(ga, q, tb[q])));
           const int ca = id[ta[q]] % nc, cb = id[tb[q]] % nc;
           if (ca == cb) continue;
           // a leaves ga and enters gb; b leaves gb and enters ga
@@ -235,6 +245,10 @@ void balance_patch(int dim, int ne, int nv, const int32_t* tloc, bool move_eleme
           ++at(gb, q, ta[q]);
           --at(gb, q, tb[q]);
           ++at(ga, q, tb[q]);
+          --dv(ga, q, ta[q]);
+          ++dv(gb, q, ta[q]);
+          --dv(gb, q, tb[q]);
+          ++dv(ga, q, tb[q]);
         }
         grp[a] = gb;
         grp[b] = ga;
@@ -244,8 +258,9 @@ void balance_patch(int dim, int ne, int nv, const int32_t* tloc, bool move_eleme
     // stores then stay on the cache lines of the sorted order
     for (int it = 0; it < 4 * nv; ++it) {
       const int u = rng.below(nv);
-      const int base = id[u] / nc * nc, span = std::min(nc, nv - base);
-      const int w = pos_of[base + rng.below(span)];
+      const int lo = std::max(id[u] / nc * nc, id[u] < split ? 0 : split);
+      const int hi = std::min(id[u] / nc * nc + nc, id[u] < split ? split : nv);
+      const int w = pos_of[lo + rng.below(hi - lo)];
       const int cu = id[u] % nc, cw = id[w] % nc;
       if (cu == cw) continue;
       // moving u's incidences from class cu to cw and w's from cw to cu; where u and w share a
@@ -325,6 +340,7 @@ double patch_bank_load(int dim, int ne, const int32_t* tloc, const int32_t* orde
 
 void balance_patches(int dim, int64_t n_e, bool move_elements, Patches* out) {
   const int nk = dim + 1;
+  const bool split = out->nshared.size() + 1 == out->eoff.size();
   out->eperm.resize((size_t)n_e);
   std::vector<int32_t> tloc, order, newid, vnew;
   for (size_t k = 0; k + 1 < out->eoff.size(); ++k) {
@@ -333,7 +349,7 @@ void balance_patches(int dim, int64_t n_e, bool move_elements, Patches* out) {
     tloc.resize((size_t)ne * nk);
     for (int e = 0; e < ne; ++e)
       for (int q = 0; q < nk; ++q) tloc[(size_t)e * nk + q] = out->lconn[(size_t)q * n_e + e0 + e];
-    balance_patch(dim, ne, nv, tloc.data(), move_elements, &order, &newid);
+    balance_patch(dim, ne, nv, tloc.data(), move_elements, split ? out->nshared[k] : nv, &order, &newid);
     for (int s = 0; s < ne; ++s) out->eperm[(size_t)e0 + s] = e0 + order[s];
     for (int e = 0; e < ne; ++e)
       for (int q = 0; q < nk; ++q) out->lconn[(size_t)q * n_e + e0 + e] = (uint16_t)newid[tloc[(size_t)e * nk + q]];
@@ -349,6 +365,33 @@ isb_status build_resident_patches(int dim, int64_t n_v, int n_bodies, const int6
   if (n_blocks < 1) return fail(ISB_E_ARG, "resident plan: no workgroups");
   const isb_status st = build_patches(dim, n_v, n_bodies, eoff, T, 1 << 30, max_verts, out, n_blocks);
   if (st != ISB_OK) return st;
+  // each patch's vertices: those other patches hold too first, then its interior ones (each part in
+  // the sorted order), so that the kernel's per-DOF loops meet the interior DOFs in whole wavefronts
+  {
+    std::vector<uint8_t> holders((size_t)n_v, 0);
+    for (const int32_t v : out->verts) holders[v] = (uint8_t)std::min(2, holders[v] + 1);
+    const int np = (int)out->eoff.size() - 1;
+    const int nk = dim + 1;
+    const int64_t n_e = eoff[n_bodies];
+    out->nshared.assign(np, 0);
+    std::vector<int32_t> ids, newid;
+    for (int k = 0; k < np; ++k) {
+      const int v0 = out->voff[k], nv = out->voff[k + 1] - v0;
+      ids.assign(out->verts.begin() + v0, out->verts.begin() + v0 + nv);
+      newid.resize(nv);
+      int ns = 0;
+      for (int v = 0; v < nv; ++v) ns += holders[ids[v]] > 1;
+      int a = 0, b = ns;
+      for (int v = 0; v < nv; ++v) newid[v] = holders[ids[v]] > 1 ? a++ : b++;
+      for (int v = 0; v < nv; ++v) out->verts[(size_t)v0 + newid[v]] = ids[v];
+      for (int e = out->eoff[k]; e < out->eoff[k + 1]; ++e)
+        for (int q = 0; q < nk; ++q) {
+          uint16_t& l = out->lconn[(size_t)q * n_e + e];
+          l = (uint16_t)newid[l];
+        }
+      out->nshared[k] = ns;
+    }
+  }
   balance_patches(dim, eoff[n_bodies], move_elements, out);
   std::vector<uint8_t> owned((size_t)n_v, 0);
   for (size_t i = 0; i < out->verts.size(); ++i) {

@@ -21,9 +21,10 @@ isb_status colour_elements(int dim, int64_t n_v, int64_t n_e, const int32_t* T, 
 // [eoff[k], eoff[k+1]) of one body and the sorted distinct vertices verts[voff[k] .. voff[k+1]);
 // lconn[(d+1)][n_e] gives each element corner's index into its patch's vertex list. eperm (the
 // resident plan only; empty otherwise): the element in each slot of [eoff[k], eoff[k+1]), the
-// order in which the workgroup's lanes take them.
+// order in which the workgroup's lanes take them. nshared (resident plan only): patch k's vertex
+// list holds first the nshared[k] vertices other patches hold too, then those only it holds.
 struct Patches {
-  std::vector<int32_t> eoff, voff, verts, eperm;
+  std::vector<int32_t> eoff, voff, verts, eperm, nshared;
   std::vector<uint16_t> lconn;
   int max_nv = 0;
 };
@@ -36,9 +37,10 @@ isb_status build_patches(int dim, int64_t n_v, int n_bodies, const int64_t* eoff
 // workgroup) of at most max_verts vertices. Each vertex is owned by the first patch that holds it;
 // verts stores v for an owned vertex and ~v (negative) for one that another patch owns. Body b's
 // patches are [body_patch_off[b], body_patch_off[b + 1]); eligible[b] when it has elements, no more
-// than n_blocks patches and no vertex that no element uses. Within each patch the vertex order,
-// and with move_elements the element slots (eperm; else eperm is the identity), are chosen by
-// balance_patch, so the patch's vertex list is not sorted.
+// than n_blocks patches and no vertex that no element uses. Each patch lists the vertices it
+// shares with other patches first (nshared[k] of them), then its interior ones; within each part
+// the vertex order, and with move_elements the element slots (eperm; else eperm is the identity),
+// are chosen by balance_patch, so neither part is sorted.
 isb_status build_resident_patches(int dim, int64_t n_v, int n_bodies, const int64_t* voff, const int64_t* eoff,
                                   const int32_t* T, int n_blocks, int max_verts, bool move_elements, Patches* out,
                                   std::vector<int32_t>* body_patch_off, std::vector<uint8_t>* eligible);
@@ -51,21 +53,24 @@ constexpr int kPatchLdsBytes = 64 * 1024;  // LDS per patch workgroup (two workg
 constexpr int patch_max_verts(int dim) { return kPatchLdsBytes / (3 * dim * (int)sizeof(double) + 4); }
 
 // LDS bank balance of one patch of the resident plan. The kernel's lanes take the patch's element
-// slots in groups of 64 (one wavefront at one step), and a vertex with local id v keeps its FP64
-// values at byte offsets 8 (D v + c), which fall in the pair of 4-byte banks (6 v + 2 c) mod 64
-// (3D; 4 v + 2 c in 2D): the bank class of v is v mod 32 (3D) or v mod 16 (2D), the same for all
-// components. A wavefront-wide LDS atomic or gather at corner q of its elements costs about as many
-// passes as the most lanes that share a class. On the nk-corner elements tloc[ne][nk] (patch-local
+// slots 64 at a time (one wavefront at one step), and the LDS serves an FP64 access in two passes
+// of 32 lanes. A vertex with local id v keeps its FP64 values at byte offsets 8 (D v + c), which
+// fall in the pair of 4-byte banks (6 v + 2 c) mod 64 (3D; 4 v + 2 c in 2D): the bank class of v is
+// v mod 32 (3D) or v mod 16 (2D), the same for all components. A half-wavefront's LDS atomic or
+// gather at corner q of its elements costs about as many cycles as the most lanes that share a
+// class (measured on one CU: 8.2 cycles per wavefront FP64 atomic with one lane per class in each
+// half, 24.1 at random vertices). On the nk-corner elements tloc[ne][nk] (patch-local
 // vertex ids < nv), order[s] receives the element of slot s and newid[v] the new local id of vertex
-// v: a greedy grouping, then a short local search over element swaps between groups and exchanges
-// of vertex ids, lowering the sum over groups, corners and classes of count squared. On a Kuhn-tet
-// block's 1,536-element patches the mean largest count falls from 8.5 (5 to 6 for a random order)
-// to 3; the ideal 2 (64 lanes over 32 classes) is out of reach where the vertices fill the corner
-// slots unevenly. Deterministic.
+// v: a greedy grouping of the slots in groups of 32, then a short local search over element swaps
+// between groups and exchanges of vertex ids, lowering the sum over groups, corners and classes of
+// count squared (and, when elements move, a steep cost on two lanes of a group at one vertex, whose
+// atomics serialise outright). On the Kuhn-tet block's 1,536-element patches in wave order the mean
+// largest count per half-wavefront falls from about 2.4 to 2.0 (ideal 1). Deterministic.
 // With move_elements false the slots keep the elements' order (order is the identity) and only
-// the vertex numbering is chosen.
-void balance_patch(int dim, int ne, int nv, const int32_t* tloc, bool move_elements, std::vector<int32_t>* order,
-                   std::vector<int32_t>* newid);
+// the vertex numbering is chosen. Vertex ids change only inside a window of consecutive ids (one id
+// per class) and never across split: ids below it stay below it.
+void balance_patch(int dim, int ne, int nv, const int32_t* tloc, bool move_elements, int split,
+                   std::vector<int32_t>* order, std::vector<int32_t>* newid);
 // balance_patch on every patch of out (n_e elements in all): eperm receives each patch's slots
 // (the identity without move_elements), lconn and verts the new vertex numbering
 void balance_patches(int dim, int64_t n_e, bool move_elements, Patches* out);

@@ -71,6 +71,9 @@ struct PatchPlan {
   int max_nv;             // largest vertex list
   int block;              // threads per patch workgroup: 256, 512 or 1024 (0: the default)
   const int32_t* eperm;   // [n_e] element of each slot of a patch's range (null: the slot itself)
+  // [n_patch] the first nshared[k] vertices of patch k are held by other patches too, the rest by
+  // it alone (null: no such split)
+  const int32_t* nshared;
 };
 
 constexpr int kPatchBlock = 512;        // threads per patch workgroup (FP32 element math; FP64 takes half)

@@ -7,9 +7,11 @@
 // an accumulator for every vertex of its patch, including the vertices it shares with other patches.
 // It updates all of them itself, with the same scalars and the same arithmetic as every other
 // workgroup that holds them, so the shared copies stay identical. Only the element part of H u
-// crosses workgroups: each patch adds its per-vertex sums into a global vector with FP64 atomics,
-// and every workgroup reads back the complete sums after the barrier. Three such vectors rotate
-// (summed into, read, cleared), so one barrier per iteration suffices. The curvature u^T H u comes
+// crosses workgroups, and only at the vertices two or more patches hold (listed first in each
+// patch): each patch adds its sums there into a global vector with FP64 atomics, and every
+// workgroup reads back the complete sums after the barrier; at its interior vertices the sums stay
+// in LDS. Three such vectors rotate (summed into, read, cleared), so one barrier per iteration
+// suffices. The curvature u^T H u comes
 // from the element pass itself (sum over elements of u_e . H_e u_e, plus the vertex diagonal's
 // part), so r.u, u^T H u and r.r of an iteration reach the next one as one set of per-workgroup
 // partials, which every workgroup folds in the same order: all of them take the same decisions.
@@ -182,6 +184,9 @@ __global__ void __launch_bounds__(PB)
   __shared__ int ok_lds;
   const int pk = p0 + blockIdx.x;
   const int vb = P.voff[pk], nv = P.voff[pk + 1] - vb, nd = nv * D;
+  // DOFs [0, nds) belong to vertices other patches hold too and go through the global sums; the
+  // element part of H u at the rest (vertices only this patch holds) stays in acc
+  const int nds = (P.nshared ? P.nshared[pk] : nv) * D;
   const int eb = P.eoff[pk], ee = P.eoff[pk + 1];
   const int nmax = P.max_nv * D;
   double* xl = lds;
@@ -198,7 +203,7 @@ __global__ void __launch_bounds__(PB)
 
   for (int v = threadIdx.x; v < nv; v += PB) vid[v] = P.verts[vb + v];
   __syncthreads();
-  // r = b on the free DOFs, u = M r, p = s = x_s = 0; clear W0 and W1 (owned DOFs)
+  // r = b on the free DOFs, u = M r, p = s = x_s = 0; clear W0 and W1 (owned shared DOFs)
   double g_ = 0.0, r_ = 0.0, d_ = 0.0;
   for (int i = threadIdx.x; i < nd; i += PB) {
     const int v = i / D, c = i - v * D, raw = vid[v];
@@ -215,8 +220,10 @@ __global__ void __launch_bounds__(PB)
     xsl[i] = 0.0;
     acc[i] = 0.0;
     if (raw >= 0) {
-      st_agent(W0 + g, 0.0);
-      st_agent(W1 + g, 0.0);
+      if (i < nds) {
+        st_agent(W0 + g, 0.0);
+        st_agent(W1 + g, 0.0);
+      }
       g_ += ri * ui;
       r_ += ri * ri;
       d_ += ui * (vi * ui);
@@ -253,7 +260,7 @@ __global__ void __launch_bounds__(PB)
     double php = 0.0;
     resident_hv_pass<D, T, EM, CR, PB, KE, KS>(m, sc, P, eb, ec, ee, xl, ul, acc, a, a32, cR, cS, ca, cl, php);
     __syncthreads();
-    for (int i = threadIdx.x; i < nd; i += PB) {
+    for (int i = threadIdx.x; i < nds; i += PB) {
       const int v = i / D, c = i - v * D, raw = vid[v];
       unsafeAtomicAdd(W0 + (size_t)(raw >= 0 ? raw : ~raw) * D + c, acc[i]);
     }
@@ -275,10 +282,10 @@ __global__ void __launch_bounds__(PB)
     double wv[KP > 0 ? KP : 1];
 #pragma unroll
     for (int k = 0; k < (KP > 0 ? KP : 1); ++k) wv[k] = 0.0;
-    if (nd > 0) {
+    if (nds > 0) {
 #pragma unroll
       for (int k = 0; k < KP; ++k) {
-        int i = min((int)threadIdx.x + k * PB, nd - 1);
+        int i = min((int)threadIdx.x + k * PB, nds - 1);
         // the slot's index is formed anew each iteration, not hoisted out of the loop and held
         // through the element pass
         asm volatile("" : "+v"(i));
@@ -308,9 +315,9 @@ __global__ void __launch_bounds__(PB)
       const int v = i / D, c = i - v * D, raw = vid[v];
       const size_t g = (size_t)(raw >= 0 ? raw : ~raw) * D + c;
       const double vi = vl[i], di = dl[i];
-      double wk = k < KP ? wv[0] : ld_agent(Wc + g);
+      double wk = i >= nds ? acc[i] : (k < KP ? wv[0] : ld_agent(Wc + g));
 #pragma unroll
-      for (int q = 1; q < KP; ++q) wk = k == q ? wv[q] : wk;
+      for (int q = 1; q < KP; ++q) wk = (k == q && i < nds) ? wv[q] : wk;
       const double wi = vi * ul[i] + wk;
       const double pi = ul[i] + beta * pl[i];
       const double si = wi + beta * sl[i];
@@ -323,7 +330,7 @@ __global__ void __launch_bounds__(PB)
       ul[i] = ui;
       acc[i] = 0.0;
       if (raw >= 0) {
-        st_agent(Wz + g, 0.0);
+        if (i < nds) st_agent(Wz + g, 0.0);
         g_ += ri * ui;
         r_ += ri * ri;
         d_ += ui * (vi * ui);
@@ -333,7 +340,7 @@ __global__ void __launch_bounds__(PB)
     double php = 0.0;
     resident_hv_pass<D, T, EM, CR, PB, KE, KS>(m, sc, P, eb, ec, ee, xl, ul, acc, a, a32, cR, cS, ca, cl, php);
     __syncthreads();
-    for (int i = threadIdx.x; i < nd; i += PB) {
+    for (int i = threadIdx.x; i < nds; i += PB) {
       const int v = i / D, c = i - v * D, raw = vid[v];
       unsafeAtomicAdd(Wn + (size_t)(raw >= 0 ? raw : ~raw) * D + c, acc[i]);
     }
