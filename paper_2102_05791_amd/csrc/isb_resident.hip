@@ -311,13 +311,9 @@ __global__ void __launch_bounds__(PB)
     double* Wn = it % 3 == 0 ? W1 : (it % 3 == 1 ? W2 : W0);
     double* Wz = it % 3 == 0 ? W2 : (it % 3 == 1 ? W0 : W1);
     g_ = r_ = d_ = 0.0;
-    for (int i = threadIdx.x, k = 0; i < nd; i += PB, ++k) {
-      const int v = i / D, c = i - v * D, raw = vid[v];
-      const size_t g = (size_t)(raw >= 0 ? raw : ~raw) * D + c;
+    // the update of DOF i (global index g, encoded vertex raw) given the element part wk of H u
+    auto update_dof = [&](int i, size_t g, int raw, double wk) {
       const double vi = vl[i], di = dl[i];
-      double wk = i >= nds ? acc[i] : (k < KP ? wv[0] : ld_agent(Wc + g));
-#pragma unroll
-      for (int q = 1; q < KP; ++q) wk = (k == q && i < nds) ? wv[q] : wk;
       const double wi = vi * ul[i] + wk;
       const double pi = ul[i] + beta * pl[i];
       const double si = wi + beta * sl[i];
@@ -334,6 +330,36 @@ __global__ void __launch_bounds__(PB)
         g_ += ri * ui;
         r_ += ri * ri;
         d_ += ui * (vi * ui);
+      }
+    };
+    if constexpr (KP == 0) {
+      // two DOF slots per trip, both sums requested before either is used: one round trip
+      // for both, without holding prefetched values through the fold
+      for (int i = threadIdx.x; i < nd; i += 2 * PB) {
+        const int j = i + PB;
+        const int vi_ = i / D, raw_i = vid[vi_];
+        const size_t g_i = (size_t)(raw_i >= 0 ? raw_i : ~raw_i) * D + (i - vi_ * D);
+        const double w_i = i < nds ? ld_agent(Wc + g_i) : acc[i];
+        int raw_j = 0;
+        size_t g_j = 0;
+        double w_j = 0.0;
+        if (j < nd) {
+          const int vj_ = j / D;
+          raw_j = vid[vj_];
+          g_j = (size_t)(raw_j >= 0 ? raw_j : ~raw_j) * D + (j - vj_ * D);
+          w_j = j < nds ? ld_agent(Wc + g_j) : acc[j];
+        }
+        update_dof(i, g_i, raw_i, w_i);
+        if (j < nd) update_dof(j, g_j, raw_j, w_j);
+      }
+    } else {
+      for (int i = threadIdx.x, k = 0; i < nd; i += PB, ++k) {
+        const int v = i / D, c = i - v * D, raw = vid[v];
+        const size_t g = (size_t)(raw >= 0 ? raw : ~raw) * D + c;
+        double wk = i >= nds ? acc[i] : (k < KP ? wv[0] : ld_agent(Wc + g));
+#pragma unroll
+        for (int q = 1; q < KP; ++q) wk = (k == q && i < nds) ? wv[q] : wk;
+        update_dof(i, g, raw, wk);
       }
     }
     __syncthreads();
