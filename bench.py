@@ -875,10 +875,11 @@ def tet_leg(args, torch, Context, isb, scenes):
     acts = torch.tensor(w.actions, device=dev)
     m = ctx.mass()
 
-    def run(S, stats):
+    def run(S, stats, c=None):
+        c = c or ctx
         xs, vs, st = [x0], [v0], []
         for t in range(S):
-            x1, v1, s, _ = ctx.step(xs[-1], vs[-1], acts[t], stats=stats)
+            x1, v1, s, _ = c.step(xs[-1], vs[-1], acts[t], stats=stats)
             xs.append(x1)
             vs.append(v1)
             st.append(s)
@@ -888,8 +889,8 @@ def tet_leg(args, torch, Context, isb, scenes):
         sa = []
         wv = None
         for t in range(S - 1, -1, -1):
-            wv, s, _ = ctx.solve_adjoint(xs[t + 1], xs[t], acts[t], xb, vb, stats=stats, w=wv, w_init=wv)
-            out = ctx.vjp_params(wv, xs[t + 1], xs[t], acts[t], vb, want=("a_bar", "x0_bar", "v0_bar"))
+            wv, s, _ = c.solve_adjoint(xs[t + 1], xs[t], acts[t], xb, vb, stats=stats, w=wv, w_init=wv)
+            out = c.vjp_params(wv, xs[t + 1], xs[t], acts[t], vb, want=("a_bar", "x0_bar", "v0_bar"))
             xb, vb = out["x0_bar"], out["v0_bar"]
             sa.append(s)
         return st, sa
@@ -924,6 +925,16 @@ def tet_leg(args, torch, Context, isb, scenes):
         torch.cuda.synchronize()
         launched = round(args.tet_steps / (time.perf_counter() - t1), 3)
         ctx.set_option(isb.OPT_CG_RESIDENT, 1)
+    # the same steps in FP64 (every product in FP64; resident CG where the body's plan fits)
+    ctx64 = Context.from_workload(w, precision="fp64", solver=0)
+    run(1, False, ctx64)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    run(args.tet_steps, False, ctx64)
+    torch.cuda.synchronize()
+    fp64_rate = round(args.tet_steps / (time.perf_counter() - t2), 3)
+    fp64_resident = ctx64.get_option(isb.INFO_RESIDENT) > 0 and ctx64.get_option(isb.OPT_CG_RESIDENT) == 1
+    del ctx64
     print("# tet-block leg done", file=sys.stderr, flush=True)
     cg_its = float(np.mean([s[0]["cg_iters"] for s in st])) + float(np.mean([s[0]["adj_cg_iters"] for s in sa]))
     # one mixed CG iteration by the per-unit bytes of the measurement plan: Hessian-vector product
@@ -942,6 +953,8 @@ def tet_leg(args, torch, Context, isb, scenes):
             "cg_per_step": float(np.mean([s[0]["cg_iters"] for s in st])),
             "adj_cg_per_step": float(np.mean([s[0]["adj_cg_iters"] for s in sa])),
             "cg_form": cg_form, "launch_per_iteration_steps_per_s": launched,
+            "fp64": {"value": fp64_rate, "unit": "steps/s",
+                     "cg_form": "resident" if fp64_resident else "launch per iteration"},
             "cg_iteration": {"us_upper_bound": round(it_us, 2),
                              "note": "whole step time (Newton passes, line search, VJP included) over the "
                                      "forward and adjoint CG iterations",
