@@ -850,6 +850,7 @@ struct BodySolver {
     trial(x, nullptr, 0.0, G, nullptr, Ecur, tr);
     const double res0 = sqrt(tr[3]);
     double res = res0, gcur = tr[2];
+    double eta = 0.5, res_prev = res0;  // forcing term and the gradient norm it was set from
     st.res0 = res0;
     if (!isfinite(res0)) st.flags |= ISB_FLAG_NONFINITE;
     while (isfinite(res)) {
@@ -858,9 +859,19 @@ struct BodySolver {
         break;
       }
       if (st.newton_iters >= A.max_newton) break;
-      // forcing term: the CG tolerance tightens as the gradient falls, but not below half the
-      // Newton stopping threshold, which a more accurate last step could not improve on
-      const double eta = fmin(0.5, sqrt(res / res0));
+      // forcing term (Eisenstat and Walker's second choice, with its safeguard): eta follows the
+      // square of the last Newton step's reduction of the gradient, tight while Newton converges
+      // fast and loose where it stalls (each Newton iteration costs a trial pass of about three CG
+      // iterations, so tighter solves that save Newton iterations pay); the CG target stays above
+      // half the Newton stopping threshold, which a more accurate last step could not improve on
+      if (st.newton_iters > 0) {
+        const double q = res / res_prev;
+        double e = 0.9 * q * q;
+        const double guard = 0.9 * eta * eta;
+        if (guard > 0.1) e = fmax(e, guard);
+        eta = fmin(0.5, e);
+      }
+      res_prev = res;
       int it = 0;
       bool neg = false;
       cg(G, -1.0, fmax(eta * res, 0.5 * A.tol * res0), A.max_cg, dx, it, neg);
