@@ -54,10 +54,11 @@ def build():
     os.makedirs(os.path.dirname(OUT), exist_ok=True)
     if os.path.exists(OUT) and all(os.path.getmtime(OUT) >= os.path.getmtime(s) for s in SRCS):
         return OUT
+    tmp = f"{OUT}.{os.getpid()}.tmp"  # parallel test workers build apart, then one rename wins
     cmd = ["g++", "-std=c++20", "-O1", "-fPIC", "-shared", "-pthread", "-DISB_DEBUG", "-I",
-           os.path.join(HERE, "include"), "-I", CSRC, SRCS[0], "-o", OUT + ".tmp"]
+           os.path.join(HERE, "include"), "-I", CSRC, SRCS[0], "-o", tmp]
     subprocess.run(cmd, check=True, capture_output=True, text=True)
-    os.replace(OUT + ".tmp", OUT)
+    os.replace(tmp, OUT)
     return OUT
 
 

@@ -27,9 +27,10 @@ DEPS = SRCS + [os.path.join(CSRC, "isb_host.hpp"), os.path.join(ROOT, "include",
 def lib():
     os.makedirs(os.path.dirname(OUT), exist_ok=True)
     if not (os.path.exists(OUT) and all(os.path.getmtime(OUT) >= os.path.getmtime(d) for d in DEPS)):
-        subprocess.run(["g++", "-std=c++17", "-O1", "-fPIC", "-shared", "-I", CSRC, *SRCS, "-o", OUT + ".tmp"],
+        tmp = f"{OUT}.{os.getpid()}.tmp"  # parallel test workers build apart, then one rename wins
+        subprocess.run(["g++", "-std=c++17", "-O1", "-fPIC", "-shared", "-I", CSRC, *SRCS, "-o", tmp],
                        check=True, capture_output=True, text=True)
-        os.replace(OUT + ".tmp", OUT)
+        os.replace(tmp, OUT)
     return ctypes.CDLL(OUT)
 
 

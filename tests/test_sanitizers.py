@@ -29,10 +29,11 @@ def _build(out, srcs, flags, deps):
     os.makedirs(BUILD, exist_ok=True)
     if os.path.exists(out) and all(os.path.getmtime(out) >= os.path.getmtime(d) for d in deps):
         return out
-    cmd = ["g++", "-O1", "-g", "-fPIC", "-shared", "-fno-omit-frame-pointer", *flags, *srcs, "-o", out + ".tmp"]
+    tmp = f"{out}.{os.getpid()}.tmp"  # parallel test workers build apart, then one rename wins
+    cmd = ["g++", "-O1", "-g", "-fPIC", "-shared", "-fno-omit-frame-pointer", *flags, *srcs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     assert r.returncode == 0, r.stderr[-3000:]
-    os.replace(out + ".tmp", out)
+    os.replace(tmp, out)
     return out
 
 
