@@ -519,6 +519,10 @@ static isb_status plain_newton(isb_ctx* c, int b, hipStream_t s, const double* x
   ISB_TRY(read_scal(c, s, 1));
   const double res0 = std::sqrt(c->hscal[0]);
   double res = res0;
+  double eta = 0.5, res_prev = res0;  // forcing term and the gradient norm it was set from
+  // a body large enough for the resident CG plan (whichever CG form runs, so that the Newton path
+  // does not depend on it)
+  const bool large = b >= 0 && (size_t)b < c->res_ok.size() && c->res_ok[b];
   st->res0 = res0;
   isb_status status = ISB_OK;
   if (!std::isfinite(res0)) {
@@ -535,9 +539,22 @@ static isb_status plain_newton(isb_ctx* c, int b, hipStream_t s, const double* x
       break;
     }
     eval_precond(c, b, x, a, s);
-    // inexact Newton forcing term: the CG tolerance tightens as the gradient falls, but not below
-    // half the Newton stopping threshold, which a more accurate last step could not improve on
-    const double eta = std::min(0.5, std::sqrt(res / res0));
+    // the CG tolerance eta |g| never goes below half the Newton stopping threshold, which a more
+    // accurate last step could not improve on
+    // inexact Newton forcing: on a small body each Newton iteration costs as much as several CG
+    // iterations (launches and host round trips), and Eisenstat and Walker's second choice (eta
+    // following the square of the last step's reduction of the gradient, with its safeguard)
+    // saves Newton iterations; on a large body CG iterations dominate, and the square-root rule,
+    // which spends fewer of them, is the faster
+    if (large) {
+      eta = std::min(0.5, std::sqrt(res / res0));
+    } else if (st->newton_iters > 0) {
+      const double q = res / res_prev;
+      double e = 0.9 * q * q;
+      if (0.9 * eta * eta > 0.1) e = std::max(e, 0.9 * eta * eta);
+      eta = std::min(0.5, e);
+    }
+    res_prev = res;
     const double cg_tol = std::max(eta * res, 0.5 * sc.tol_rel * res0);
     int cg_it = 0;
     bool neg = false;
