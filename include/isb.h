@@ -248,7 +248,10 @@ isb_status isb_locality_order(int dim, int64_t n_v, const double* X, int64_t n_e
  * patches, their vertex sets and the plan's boundaries are unchanged. Inside a patch, each group of
  * 64 consecutive elements from the patch's first (one wavefront of the patch kernels) receives
  * elements with distinct vertices in each corner slot where a greedy placement finds them, so that
- * the lanes of one LDS atomic add address distinct vertices. A caller applies the permutation to T
+ * the lanes of one LDS atomic add address distinct vertices; then elements move between the groups
+ * of 32 (the lanes the LDS serves together in an FP64 access) so that each group's vertices in a
+ * corner slot spread over the LDS bank classes (the plan's local id mod 32 in 3D, mod 16 in 2D),
+ * where a short local search lowers the largest class counts. A caller applies the permutation to T
  * and to every per-element array once, before isb_mesh_upload; results change only by the
  * rounding of the summation order. Deterministic; ISB_E_MESH for an out-of-range vertex,
  * ISB_E_ARG otherwise. */

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/isb.h"
@@ -165,7 +166,7 @@ int bank_classes(int dim) { return dim == 3 ? 32 : 16; }
 }  // namespace
 
 void balance_patch(int dim, int ne, int nv, const int32_t* tloc, bool move_elements, int split,
-                   std::vector<int32_t>* order, std::vector<int32_t>* newid) {
+                   std::vector<int32_t>* order, std::vector<int32_t>* newid, bool renumber) {
   const int nk = dim + 1, nc = bank_classes(dim);
   const int ng = (ne + kLanes - 1) / kLanes;
   // the change of the sum of squared counts when one count goes from c to c + 1 or c - 1
@@ -256,7 +257,7 @@ void balance_patch(int dim, int ne, int nv, const int32_t* tloc, bool move_eleme
     // exchanges of two vertices' local ids (their classes), only within a window of nc consecutive
     // ids: the patch's per-DOF loops walk the ids in order, so each wavefront's global loads and
     // stores then stay on the cache lines of the sorted order
-    for (int it = 0; it < 4 * nv; ++it) {
+    for (int it = 0; renumber && it < 4 * nv; ++it) {
       const int u = rng.below(nv);
       const int lo = std::max(id[u] / nc * nc, id[u] < split ? 0 : split);
       const int hi = std::min(id[u] / nc * nc + nc, id[u] < split ? split : nv);
@@ -427,6 +428,7 @@ isb_status wave_order(int dim, int64_t n_v, int n_bodies, const int64_t* eoff, c
   std::vector<uint32_t> mask((size_t)n_v * nk, 0);
   std::vector<int> fill, cap;
   std::vector<int64_t> slots;
+  const int64_t n_e = eoff[n_bodies];
   static_assert(kPatchMaxElems / kWave <= 32, "groups of one patch must fit the 32-bit mask");
   for (size_t q = 0; q + 1 < pt.eoff.size(); ++q) {
     const int64_t s = pt.eoff[q], e1 = pt.eoff[q + 1];
@@ -468,6 +470,30 @@ isb_status wave_order(int dim, int64_t n_v, int n_bodies, const int64_t* eoff, c
     for (int w = 0; w < nw; ++w)
       for (int i = 0; i < fill[w]; ++i) perm[o++] = slots[(size_t)w * kWave + i];
   }
+  // bank balance of each packed patch: the plan numbers a patch's vertices by sorted global id, and
+  // the same patch comes back when the caller applies the order (a permutation inside the patch
+  // takes the same vertex set, so the builder cuts where it cut before). Patches are independent,
+  // so threads take them in turn; each patch's result does not depend on the thread count.
+  const int n_patch = (int)pt.eoff.size() - 1;
+  const int n_thr = std::max(1, std::min<int>({(int)std::thread::hardware_concurrency(), 16, n_patch}));
+  auto balance_some = [&](int t0) {
+    std::vector<int32_t> tloc, order, newid;
+    std::vector<int64_t> packed;
+    for (int q = t0; q < n_patch; q += n_thr) {
+      const int64_t s = pt.eoff[q];
+      const int len = (int)(pt.eoff[q + 1] - s), nv = pt.voff[q + 1] - pt.voff[q];
+      tloc.resize((size_t)len * nk);
+      for (int i = 0; i < len; ++i)
+        for (int k = 0; k < nk; ++k) tloc[(size_t)i * nk + k] = pt.lconn[(size_t)k * n_e + perm[s + i]];
+      balance_patch(dim, len, nv, tloc.data(), true, nv, &order, &newid, false);
+      packed.assign(perm + s, perm + s + len);
+      for (int i = 0; i < len; ++i) perm[s + i] = packed[order[i]];
+    }
+  };
+  std::vector<std::thread> pool;
+  for (int t = 1; t < n_thr; ++t) pool.emplace_back(balance_some, t);
+  balance_some(0);
+  for (std::thread& th : pool) th.join();
   return ISB_OK;
 }
 

@@ -67,18 +67,22 @@ constexpr int patch_max_verts(int dim) { return kPatchLdsBytes / (3 * dim * (int
 // atomics serialise outright). On the Kuhn-tet block's 1,536-element patches in wave order the mean
 // largest count per half-wavefront falls from about 2.4 to 2.0 (ideal 1). Deterministic.
 // With move_elements false the slots keep the elements' order (order is the identity) and only
-// the vertex numbering is chosen. Vertex ids change only inside a window of consecutive ids (one id
+// the vertex numbering is chosen; with renumber false the numbering is kept (newid is the identity)
+// and only the slots are chosen. Vertex ids change only inside a window of consecutive ids (one id
 // per class) and never across split: ids below it stay below it.
 void balance_patch(int dim, int ne, int nv, const int32_t* tloc, bool move_elements, int split,
-                   std::vector<int32_t>* order, std::vector<int32_t>* newid);
+                   std::vector<int32_t>* order, std::vector<int32_t>* newid, bool renumber = true);
 // balance_patch on every patch of out (n_e elements in all): eperm receives each patch's slots
 // (the identity without move_elements), lconn and verts the new vertex numbering
 void balance_patches(int dim, int64_t n_e, bool move_elements, Patches* out);
 // mean over (group, corner) of the largest class count, for the slots and numbering given
 double patch_bank_load(int dim, int ne, const int32_t* tloc, const int32_t* order, const int32_t* newid);
 
-// Element order inside each patch of that plan in which the wavefront groups (64 consecutive
-// elements from the patch's first) hold distinct vertices per corner slot where possible.
+// Element order inside each patch of that plan: first the wavefront groups (64 consecutive
+// elements from the patch's first) are packed with distinct vertices per corner slot where
+// possible; then balance_patch moves elements between the half-wavefront groups, with the plan's
+// vertex numbering (sorted global ids) kept, so that each half-wavefront's corners spread over the
+// LDS bank classes, and the packed order stays where that does not lower the largest class counts.
 isb_status wave_order(int dim, int64_t n_v, int n_bodies, const int64_t* eoff, const int32_t* T, int64_t* perm);
 
 }  // namespace isb

@@ -169,6 +169,23 @@ def _patch_bounds(T, n_v, eoff, dim):
     return np.array(out)
 
 
+def _half_wave_bank_load(T, bounds, dim):
+    """Mean over (half-wavefront group of 32 consecutive elements from a patch's first, corner slot)
+    of the most lanes whose vertex falls in one LDS bank class: the plan numbers a patch's vertices
+    by sorted global id, and FP64 [vertex][dim] rows put local id v in class v mod 32 (3D) or
+    v mod 16 (2D)."""
+    nc = 32 if dim == 3 else 16
+    loads = []
+    for s, e in zip(bounds[:-1], bounds[1:]):
+        P = T[s:e]
+        loc = np.searchsorted(np.unique(P), P) % nc
+        g = np.arange(e - s) // 32
+        for k in range(T.shape[1]):
+            cnt = np.bincount(g * nc + loc[:, k], minlength=(g[-1] + 1) * nc).reshape(-1, nc)
+            loads.append(cnt.max(axis=1))
+    return float(np.mean(np.concatenate(loads)))
+
+
 def _slot_clashes(T, bounds, wave=64):
     """Lanes of a wavefront group (64 consecutive elements from a patch's first) whose vertex in
     some corner slot another lane of the group already has there, per element corner."""
@@ -196,6 +213,9 @@ def test_wave_order_keeps_patches_and_separates_slot_vertices():
     # groups cannot separate them all: fewer clashes, not none
     before, after = _slot_clashes(T, bounds), _slot_clashes(T[perm], bounds)
     assert before > 0.5 and after < 0.5 * before, (before, after)
+    # and each half-wavefront's corners spread over the LDS bank classes (ideal 1 lane per class)
+    lb, la = _half_wave_bank_load(T, bounds, 3), _half_wave_bank_load(T[perm], bounds, 3)
+    assert lb > 2.9 and la < 2.2, (lb, la)
     # 393,216 tets: 384-element patches of six groups, one per tetrahedron of a cube: no clash left
     X6, T6 = meshes.tet_grid(64, 32, 32)
     b6 = _patch_bounds(T6, X6.shape[0], [0, T6.shape[0]], 3)
