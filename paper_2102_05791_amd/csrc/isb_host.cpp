@@ -3,9 +3,11 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <string>
+#include <system_error>
 #include <thread>
 #include <vector>
 
@@ -472,14 +474,16 @@ isb_status wave_order(int dim, int64_t n_v, int n_bodies, const int64_t* eoff, c
   }
   // bank balance of each packed patch: the plan numbers a patch's vertices by sorted global id, and
   // the same patch comes back when the caller applies the order (a permutation inside the patch
-  // takes the same vertex set, so the builder cuts where it cut before). Patches are independent,
-  // so threads take them in turn; each patch's result does not depend on the thread count.
+  // takes the same vertex set, so the builder cuts where it cut before). Patches are independent:
+  // threads take them from a shared counter, and each patch's result does not depend on which
+  // thread took it or on how many started (the calling thread alone finishes the work if none can).
   const int n_patch = (int)pt.eoff.size() - 1;
   const int n_thr = std::max(1, std::min<int>({(int)std::thread::hardware_concurrency(), 16, n_patch}));
-  auto balance_some = [&](int t0) {
+  std::atomic<int> next{0};
+  auto balance_some = [&]() {
     std::vector<int32_t> tloc, order, newid;
     std::vector<int64_t> packed;
-    for (int q = t0; q < n_patch; q += n_thr) {
+    for (int q = next++; q < n_patch; q = next++) {
       const int64_t s = pt.eoff[q];
       const int len = (int)(pt.eoff[q + 1] - s), nv = pt.voff[q + 1] - pt.voff[q];
       tloc.resize((size_t)len * nk);
@@ -491,8 +495,13 @@ isb_status wave_order(int dim, int64_t n_v, int n_bodies, const int64_t* eoff, c
     }
   };
   std::vector<std::thread> pool;
-  for (int t = 1; t < n_thr; ++t) pool.emplace_back(balance_some, t);
-  balance_some(0);
+  pool.reserve(n_thr);
+  try {
+    for (int t = 1; t < n_thr; ++t) pool.emplace_back(balance_some);
+  } catch (const std::system_error&) {
+    // fewer helper threads than asked for: the ones that started and this thread share the rest
+  }
+  balance_some();
   for (std::thread& th : pool) th.join();
   return ISB_OK;
 }

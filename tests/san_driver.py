@@ -69,6 +69,12 @@ def host(path):
         assert lib.isb_locality_order(dim, n_v, _p(Xb), n_e, _p(t), 3, _p(eo), _p(perm)) != 0
         assert lib.isb_wave_order(dim, n_v, n_e, _p(t), 3, _p(eo), _p(perm)) != 0
         checks += 3
+    # a mesh of 72 patches, so that the wave order's per-patch balance runs on several threads
+    X, T = meshes.tet_grid(24, 16, 8)
+    T = np.ascontiguousarray(T, np.int32)
+    perm = np.zeros(T.shape[0], np.int64)
+    assert lib.isb_wave_order(3, X.shape[0], T.shape[0], _p(T), 1, None, _p(perm)) == 0
+    assert np.array_equal(np.sort(perm), np.arange(T.shape[0]))
     print(f"host ABI checks passed ({checks} rejections)")
 
 

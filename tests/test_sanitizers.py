@@ -1,4 +1,4 @@
-"""The host C++ under AddressSanitizer and UndefinedBehaviorSanitizer, and the batched solver's body
+"""The host C++ under AddressSanitizer with UndefinedBehaviorSanitizer and under ThreadSanitizer, and the batched solver's body
 logic (isb_body.hpp, run by host threads as emulated workgroups of 2 and 4 waves, with its debug
 index checks) under ThreadSanitizer and under AddressSanitizer with UndefinedBehaviorSanitizer. CPU only: the sanitized libraries are built with g++ from the same sources
 (the host-only isb_host.cpp; the emulator of tests/emu) and driven by tests/san_driver.py in a child
@@ -55,6 +55,15 @@ def test_host_abi_under_asan_and_ubsan():
                  [src, os.path.join(CSRC, "isb_host.hpp"), os.path.join(ROOT, "include", "isb.h")])
     out = _drive("host", lib, _runtime("libasan.so"), {"ASAN_OPTIONS": "detect_leaks=0:abort_on_error=1",
                                                        "UBSAN_OPTIONS": "print_stacktrace=1"}, 300)
+    assert "host ABI checks passed" in out
+
+
+def test_host_abi_under_tsan():
+    """The host library under ThreadSanitizer: isb_wave_order balances its patches on threads."""
+    src = os.path.join(CSRC, "isb_host.cpp")
+    lib = _build(os.path.join(BUILD, "libisb_host_tsan.so"), [src], ["-std=c++17", "-pthread", "-fsanitize=thread"],
+                 [src, os.path.join(CSRC, "isb_host.hpp"), os.path.join(ROOT, "include", "isb.h")])
+    out = _drive("host", lib, _runtime("libtsan.so"), {"TSAN_OPTIONS": "halt_on_error=1:exitcode=66"}, 300)
     assert "host ABI checks passed" in out
 
 
