@@ -1029,7 +1029,9 @@ def element_roofline_mesh(grid, torch, Context, isb, scenes, block_order=True):
     a_np = meshes.contraction_actuation(rng, n_e)
     perm = isb.wave_order(3, n_v, Tm)
     out = {"mesh": f"tet_grid {nx}x{ny}x{nz}: {n_e} tets, {n_v} vertices; 4x4x4-cube block element order, "
-                   "then isb_wave_order inside each patch"}
+                   "then isb_wave_order inside each patch",
+           "timing": f"per kernel: untimed launches for at least {ELEM_WARMUP_S} s and {ELEM_WARMUP_MIN_LAUNCHES} "
+                     f"launches, then the median of {ELEM_TIMED_LAUNCHES} launches (HIP events)"}
     out.update(element_times(X, np.ascontiguousarray(Tm[perm]), x, p, torch.tensor(a_np[perm], device=dev),
                              torch, Context, scenes))
     if block_order:
@@ -1039,17 +1041,30 @@ def element_roofline_mesh(grid, torch, Context, isb, scenes, block_order=True):
     return out
 
 
+ELEM_WARMUP_S = 0.1            # element kernels: untimed launches for at least this long ...
+ELEM_WARMUP_MIN_LAUNCHES = 20  # ... and at least this many, before the 20 timed ones
+ELEM_TIMED_LAUNCHES = 20
+
+
 def element_times(X, Tm, x, p, a, torch, Context, scenes):
     from synth import meshes
     n_e, n_v = Tm.shape[0], X.shape[0]
     mu, lam = scenes.lame(1e5, 0.45)
 
     def median_ms(fn):
-        for _ in range(3):
+        # a sustained warm-up, as inside a CG solve that runs the product hundreds of times in a row:
+        # the core clock rises under load over tens of milliseconds, and the LDS-bound products follow
+        # it (after 3 launches the FP64 product at 9.4 M tets takes 0.25 ms, after 200 0.215 ms; the
+        # HBM-bound gradient does not change). The 20 launches after it are the timed ones.
+        t0, n = time.perf_counter(), 0
+        while n < ELEM_WARMUP_MIN_LAUNCHES or time.perf_counter() - t0 < ELEM_WARMUP_S:
             fn()
+            n += 1
+            if n % 20 == 0:
+                torch.cuda.synchronize()
         torch.cuda.synchronize()
         evs = []
-        for _ in range(20):
+        for _ in range(ELEM_TIMED_LAUNCHES):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record()
             fn()
