@@ -154,13 +154,17 @@ def test_strip_100_steps_mixed_vs_oracle(strip_oracle, solver):
     xr, vr = states[-1]
     ex = np.linalg.norm(xT.detach().cpu().numpy() - xr) / np.linalg.norm(xr - w.x0)
     ev = np.linalg.norm(vT.detach().cpu().numpy() - vr) / np.linalg.norm(vr)
+    exi = np.max(np.abs(xT.detach().cpu().numpy() - xr)) / np.max(np.abs(xr - w.x0))
+    evi = np.max(np.abs(vT.detach().cpu().numpy() - vr)) / np.max(np.abs(vr))
     L = _com_loss(torch, ctx.mass(), xT)
     L.backward()
     g = acts.grad.cpu().numpy()
     eg = np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref)
     egi = np.max(np.abs(g - g_ref)) / np.max(np.abs(g_ref))
-    print(f"mixed {solver}: x_100 err {ex:.2e} v_100 err {ev:.2e} grad err {eg:.2e} (worst entry {egi:.2e})")
+    print(f"mixed {solver}: x_100 err {ex:.2e} v_100 err {ev:.2e} grad err {eg:.2e} "
+          f"(worst entry: x_100 {exi:.2e} v_100 {evi:.2e} grad {egi:.2e})")
     assert ex <= 1e-5 and ev <= 1e-5
+    assert exi <= 1e-5 and evi <= 1e-5
     assert eg <= 1e-5 and egi <= 1e-5
 
 

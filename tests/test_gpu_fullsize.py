@@ -55,9 +55,16 @@ def test_batched_strips_full_size_sampled(batch, precision, tol):
         ar = solve.vjp_params(p, wr, xr, wb.x0, wb.actions[0])["a_bar"]
         ew = np.linalg.norm(wg[sv] - wr) / np.linalg.norm(wr)
         ea = np.linalg.norm(abar[se] - ar) / np.linalg.norm(ar)
+        # the worst entry, over the largest reference entry
+        exi = np.max(np.abs(x1[sv] - xr)) / np.max(np.abs(xr - wb.x0))
+        evi = np.max(np.abs(v1[sv] - vr)) / np.max(np.abs(vr))
+        ewi = np.max(np.abs(wg[sv] - wr)) / np.max(np.abs(wr))
+        eai = np.max(np.abs(abar[se] - ar)) / np.max(np.abs(ar))
         print(f"body {b} ({wb.n_e} tris): x1 {ex:.2e} v1 {ev:.2e} w {ew:.2e} a_bar {ea:.2e} "
+              f"(worst entry {exi:.2e} {evi:.2e} {ewi:.2e} {eai:.2e}) "
               f"newton {st[b]['newton_iters']} cg {st[b]['cg_iters']} adj_cg {sta[b]['adj_cg_iters']}")
         assert ex <= tol and ev <= tol and ew <= tol and ea <= tol
+        assert exi <= tol and evi <= tol and ewi <= tol and eai <= tol
 
 
 def test_batched_strips_metric_tolerance_error_reported(batch):

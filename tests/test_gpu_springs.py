@@ -8,7 +8,7 @@ import pytest
 from oracle import fem, solve
 from oracle.fem import Problem
 from synth import scenes
-from tests.gpu_util import abs_assembly, rand_workload, rel, with_springs
+from tests.gpu_util import abs_assembly, rand_workload, rel, rel_inf, with_springs
 
 pytestmark = pytest.mark.gpu
 
@@ -171,6 +171,8 @@ def test_spring_step_adjoint_vjp_parity(solver, dim, precision, tol):
         print(b, "gpu", st[b])
         assert rel(x1[sv] - wb.x0, xr - wb.x0) <= tol
         assert rel(v1[sv], vr) <= tol
+        assert rel_inf(x1[sv] - wb.x0, xr - wb.x0) <= tol
+        assert rel_inf(v1[sv], vr) <= tol
         ee, ev = p.energy_terms(xr, wb.x0, wb.v0, wb.actions[0])
         assert st[b]["energy"] == pytest.approx(ee.sum() + ev.sum(), rel=1e-8)
     # adjoint and VJP at the oracle's x1, so that only they are compared
@@ -186,8 +188,10 @@ def test_spring_step_adjoint_vjp_parity(solver, dim, precision, tol):
         sv = slice(w.body_v_off[b], w.body_v_off[b + 1])
         wr = solve.adjoint(p, xs[sv], wb.x0, wb.actions[0], xbar[sv], vbar[sv])
         assert rel(wg[sv], wr) <= tol
+        assert rel_inf(wg[sv], wr) <= tol
         ref = solve.vjp_params(p, wr, xs[sv], wb.x0, wb.actions[0], v1_bar=vbar[sv])
         assert rel(_body_acts(w, abar, b), ref["a_bar"]) <= tol
+        assert rel_inf(_body_acts(w, abar, b), ref["a_bar"]) <= tol
 
 
 def test_spring_colour_scatter_is_bitwise_reproducible():
@@ -216,6 +220,8 @@ def test_spring_strip_full_size(solver, precision, tol):
         x, v, _ = solve.step(p, x, v, w.actions[t], tol=1e-13)
         assert rel(xg.cpu().numpy() - w.x0, x - w.x0) <= tol
         assert rel(vg.cpu().numpy(), v) <= tol
+        assert rel_inf(xg.cpu().numpy() - w.x0, x - w.x0) <= tol
+        assert rel_inf(vg.cpu().numpy(), v) <= tol
 
 
 def test_batched_spring_strips_sampled_bodies():

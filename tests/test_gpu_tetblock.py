@@ -51,6 +51,12 @@ def test_tet_block_step_and_adjoint_vs_oracle_samples(precision, tol, order):
     a_bar = np.empty(w.n_e)
     a_bar[perm] = out["a_bar"].cpu().numpy()          # new position i holds element perm[i]
     ea = np.linalg.norm(a_bar[es] - np.array(g["a_bar"])) / np.linalg.norm(np.array(g["a_bar"]))
+    # the worst sampled entry, over the largest reference entry
+    inf = lambda a, r, d=None: np.max(np.abs(a - r)) / np.max(np.abs(r if d is None else d))
+    exi, evi = inf(x1s, gx, gx - w.x0[vs]), inf(v1.cpu().numpy()[vs], np.array(g["v1"]))
+    ewi, eai = inf(wv.cpu().numpy()[vs], np.array(g["w"])), inf(a_bar[es], np.array(g["a_bar"]))
     print(f"{precision} {order}: newton {st[0]['newton_iters']} cg {st[0]['cg_iters']} adj_cg {sa[0]['adj_cg_iters']} "
-          f"min_J {st[0]['min_J']:.3f} max_J {st[0]['max_J']:.3f} | x1 {ex:.2e} v1 {ev:.2e} w {ew:.2e} a_bar {ea:.2e}")
+          f"min_J {st[0]['min_J']:.3f} max_J {st[0]['max_J']:.3f} | x1 {ex:.2e} v1 {ev:.2e} w {ew:.2e} a_bar {ea:.2e} "
+          f"| worst entry x1 {exi:.2e} v1 {evi:.2e} w {ewi:.2e} a_bar {eai:.2e}")
     assert ex <= tol and ev <= tol and ew <= tol and ea <= tol
+    assert exi <= tol and evi <= tol and ewi <= tol and eai <= tol
