@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 from oracle import solve
-from tests.gpu_util import abs_assembly, problems, rand_workload, rel
+from tests.gpu_util import abs_assembly, problems, rand_workload, rel, rel_inf
 
 pytestmark = pytest.mark.gpu
 
@@ -46,6 +46,7 @@ def test_gradient_energy_parity_fp64(case, scatter):
         Gref[p.pinned] = 0.0
         scale = abs_assembly(p, xb, x0b, vb, ab)
         assert rel(G[v0:v1], Gref, scale) <= 1e-13
+        assert rel_inf(G[v0:v1], Gref, scale) <= 1e-13
         ee, ev = p.energy_terms(xb, x0b, vb, ab)
         assert abs(E[b] - (ee.sum() + ev.sum())) <= 1e-13 * (np.abs(ee).sum() + np.abs(ev).sum())
 
@@ -71,8 +72,10 @@ def test_hessvec_hessdiag_parity(case, precision, tol, scatter):
         ref = (H @ pm) * free
         absref = (abs(H) @ np.abs(pm)) * free
         assert rel(Hp[v0:v1].ravel(), ref, absref) <= tol
+        assert rel_inf(Hp[v0:v1].ravel(), ref, absref) <= tol
         dref = np.where(free, H.diagonal(), 1.0)
         assert rel(Hd[v0:v1].ravel(), dref) <= tol
+        assert rel_inf(Hd[v0:v1].ravel(), dref) <= tol
 
 
 @pytest.mark.parametrize("case", CASES, ids=IDS)
@@ -93,11 +96,13 @@ def test_vjp_parity_fp64(case):
         ref = solve.vjp_params(p, wv[v0:v1], x1[v0:v1], w.x0[v0:v1], a[e0:e1], v1_bar=vbar[v0:v1])
         for k in ("a_bar", "mu_bar", "lam_bar", "kf_bar"):
             assert rel(out[k][e0:e1], ref[k]) <= 1e-12, k
+            assert rel_inf(out[k][e0:e1], ref[k]) <= 1e-12, k
         for k in ("x0_bar", "v0_bar"):
             if integ == "qs" and k == "v0_bar":
                 assert np.all(out[k][v0:v1] == 0.0)
                 continue
             assert rel(out[k][v0:v1], ref[k]) <= 1e-12, k
+            assert rel_inf(out[k][v0:v1], ref[k]) <= 1e-12, k
 
 
 def test_mass_matches_oracle():
@@ -106,6 +111,7 @@ def test_mass_matches_oracle():
     m = ctx.mass().cpu().numpy()
     ref = problems(w)[0].mesh.mass
     assert rel(m, ref) <= 1e-15
+    assert rel_inf(m, ref) <= 1e-15
 
 
 @pytest.mark.parametrize("order", ["given", "wave"])
@@ -127,14 +133,18 @@ def test_patch_scatter_large_mesh(dim, shape, precision, tol, order):
     G = ctx.gradient(_dev(x), _dev(w.x0), _dev(w.v0), _dev(a)).cpu().numpy()
     Gref = p.grad(x, w.x0, w.v0, a)
     assert rel(G, Gref, abs_assembly(p, x, w.x0, w.v0, a)) <= 1e-13
+    assert rel_inf(G, Gref, abs_assembly(p, x, w.x0, w.v0, a)) <= 1e-13
     H = p.hessian(x, w.x0, a)
     Hp = ctx.hessvec(_dev(x), _dev(w.x0), _dev(a), _dev(pv)).cpu().numpy().ravel()
     assert rel(Hp, H @ pv.ravel(), abs(H) @ np.abs(pv.ravel())) <= tol
+    assert rel_inf(Hp, H @ pv.ravel(), abs(H) @ np.abs(pv.ravel())) <= tol
     Hd = ctx.hessdiag(_dev(x), _dev(w.x0), _dev(a)).cpu().numpy().ravel()
     assert rel(Hd, H.diagonal()) <= tol
+    assert rel_inf(Hd, H.diagonal()) <= tol
     he = ctx.hessvec_elements(_dev(x), _dev(a), _dev(pv), _dev(np.zeros_like(x))).cpu().numpy().ravel()
     Hv_vertex = _elem_free_hessian(p, x, w.x0, a) @ pv.ravel()
     assert rel(he, H @ pv.ravel() - Hv_vertex, abs(H) @ np.abs(pv.ravel())) <= tol
+    assert rel_inf(he, H @ pv.ravel() - Hv_vertex, abs(H) @ np.abs(pv.ravel())) <= tol
 
 
 def _elem_free_hessian(p, x, x0, a):
@@ -165,3 +175,4 @@ def test_mixed_hessvec_smooth_operand(dim, shape, scatter):
     Hp = (p.hessian(x, w.x0, a) - _elem_free_hessian(p, x, w.x0, a)) @ pv.ravel()
     scale = abs(p.hessian(x, w.x0, a) - _elem_free_hessian(p, x, w.x0, a)) @ np.abs(pv - pv.mean()).ravel()
     assert rel(he, Hp, scale) <= 1e-5
+    assert rel_inf(he, Hp, scale) <= 1e-5

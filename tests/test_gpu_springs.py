@@ -72,6 +72,7 @@ def test_spring_gradient_energy_parity_fp64(case, scatter):
         Gref = p.grad(xb, wb.x0, wb.v0, ab)
         Gref[p.pinned] = 0.0
         assert rel(G[sv], Gref, abs_assembly(p, xb, wb.x0, wb.v0, ab)) <= 1e-13
+        assert rel_inf(G[sv], Gref, abs_assembly(p, xb, wb.x0, wb.v0, ab)) <= 1e-13
         ee, ev = p.energy_terms(xb, wb.x0, wb.v0, ab)
         assert abs(E[b] - (ee.sum() + ev.sum())) <= 1e-13 * (np.abs(ee).sum() + np.abs(ev).sum())
 
@@ -98,8 +99,10 @@ def test_spring_hessvec_hessdiag_parity(case, precision, tol, scatter):
         ref = (H @ pm) * free
         absref = (abs(H) @ np.abs(pm)) * free
         assert rel(Hp[sv].ravel(), ref, absref) <= tol
+        assert rel_inf(Hp[sv].ravel(), ref, absref) <= tol
         # the diagonal is FP64 in both precisions
         assert rel(Hd[sv].ravel(), np.where(free, H.diagonal(), 1.0)) <= 1e-12
+        assert rel_inf(Hd[sv].ravel(), np.where(free, H.diagonal(), 1.0)) <= 1e-12
 
 
 def test_spring_hessvec_elements_includes_springs():
@@ -118,12 +121,14 @@ def test_spring_hessvec_elements_includes_springs():
                 w.S, w.ks)
     ref = p.s_pot * (q.hessian(x, w.x0, a) @ pv.ravel())
     assert rel(hp.cpu().numpy().ravel(), ref) <= 1e-12
+    assert rel_inf(hp.cpu().numpy().ravel(), ref) <= 1e-12
     # isb_gradient_elements: the element and spring forces alone, added into g
     g = torch.ones(w.n_v, 2, dtype=torch.float64, device="cuda:0")
     ctx.gradient_elements(_dev(x), _dev(a), g)
     ae, as_ = p.split(a)
     gref = 1.0 + p.s_pot * (p.element_grad(x, ae) + fem.spring_grad(x, p.S, p.ks, p.l0, as_))
     assert rel(g.cpu().numpy(), gref) <= 1e-13
+    assert rel_inf(g.cpu().numpy(), gref) <= 1e-13
 
 
 @pytest.mark.parametrize("case", CASES, ids=IDS)
@@ -145,9 +150,12 @@ def test_spring_vjp_parity_fp64(case):
         sv = slice(w.body_v_off[b], w.body_v_off[b + 1])
         ref = solve.vjp_params(p, wv[sv], x1[sv], wb.x0, wb.actions[2], v1_bar=vbar[sv])
         assert rel(_body_acts(w, out["a_bar"], b), ref["a_bar"]) <= 1e-12
+        assert rel_inf(_body_acts(w, out["a_bar"], b), ref["a_bar"]) <= 1e-12
         assert rel(kb[w.body_s_off[b]:w.body_s_off[b + 1]], ref["ks_bar"]) <= 1e-12
+        assert rel_inf(kb[w.body_s_off[b]:w.body_s_off[b + 1]], ref["ks_bar"]) <= 1e-12
         for k in ("x0_bar",) + (("v0_bar",) if integ == "be" else ()):
             assert rel(out[k][sv], ref[k]) <= 1e-12, k
+            assert rel_inf(out[k][sv], ref[k]) <= 1e-12, k
 
 
 @pytest.mark.parametrize("solver", [0, 1], ids=["plain", "batched"])
@@ -240,6 +248,7 @@ def test_batched_spring_strips_sampled_bodies():
         sv = slice(w.body_v_off[b], w.body_v_off[b + 1])
         # a 1e-6 relative residual leaves an error of the same order in the step
         assert rel(x1[sv] - wb.x0, xr - wb.x0) <= 1e-4
+        assert rel_inf(x1[sv] - wb.x0, xr - wb.x0) <= 1e-4
 
 
 def test_spring_upload_errors_and_action_length():
