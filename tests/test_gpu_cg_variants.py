@@ -95,8 +95,11 @@ def test_single_reduction_cg_matches_classic_and_oracle(oracle_refs, body, preci
         assert st[0]["flags"] & (isb.FLAG_CONVERGED | isb.FLAG_STAGNATED)
         assert sa[0]["flags"] & isb.FLAG_ADJ_CONVERGED
         assert rel(x1 - w.x0, xr - w.x0) <= tol and rel_inf(x1 - w.x0, xr - w.x0) <= tol
+        assert rel_inf(x1 - w.x0, xr - w.x0) <= tol and rel_inf(x1 - w.x0, xr - w.x0) <= tol
         assert rel(v1, vr) <= tol
+        assert rel_inf(v1, vr) <= tol
         assert rel(wv, wr) <= tol and rel_inf(wv, wr) <= tol
+        assert rel_inf(wv, wr) <= tol and rel_inf(wv, wr) <= tol
     # the same iterates in exact arithmetic: iteration counts agree up to rounding. In mixed precision
     # the single-reduction form's recurrence for H p drifts from the FP32 operator, so its adjoint
     # checks the true residual once and, if needed, solves for the correction (at this 1e-13
@@ -140,7 +143,9 @@ def test_resident_cg_alternative_energies(model, dim, precision, tol):
         print(model, dim, precision, resident, st[0]["cg_iters"], sa[0]["adj_cg_iters"],
               rel(x1 - w.x0, xr - w.x0), rel(wv, wr))
         assert rel(x1 - w.x0, xr - w.x0) <= tol and rel_inf(x1 - w.x0, xr - w.x0) <= tol
+        assert rel_inf(x1 - w.x0, xr - w.x0) <= tol and rel_inf(x1 - w.x0, xr - w.x0) <= tol
         assert rel(wv, wr) <= tol and rel_inf(wv, wr) <= tol
+        assert rel_inf(wv, wr) <= tol and rel_inf(wv, wr) <= tol
         outs[resident] = st[0]["cg_iters"]
     assert abs(outs[1] - outs[0]) <= 0.05 * outs[0] + 3
 
@@ -168,7 +173,9 @@ def test_resident_cg_pinned_body(integrator, precision, tol):
     pinned = w.pinned.astype(bool)
     assert np.all(x1[pinned] == w.x0[pinned]) and np.all(wv[pinned] == 0.0)
     assert rel(x1 - w.x0, xr - w.x0) <= tol and rel_inf(x1 - w.x0, xr - w.x0) <= tol
+    assert rel_inf(x1 - w.x0, xr - w.x0) <= tol and rel_inf(x1 - w.x0, xr - w.x0) <= tol
     assert rel(wv, wr) <= tol and rel_inf(wv, wr) <= tol
+    assert rel_inf(wv, wr) <= tol and rel_inf(wv, wr) <= tol
 
 
 def test_resident_barrier_limit_ends_the_launch_cleanly(oracle_refs):
@@ -190,7 +197,9 @@ def test_resident_barrier_limit_ends_the_launch_cleanly(oracle_refs):
     ctx.set_option(isb.OPT_CG_BARRIER_LIMIT_US, 4000000)
     x1, v1, st, _ = ctx.step(_dev(w.x0), _dev(w.v0), _dev(a))
     assert rel(x1.cpu().numpy() - w.x0, xr - w.x0) <= 1e-10
+    assert rel_inf(x1.cpu().numpy() - w.x0, xr - w.x0) <= 1e-10
     assert rel(v1.cpu().numpy(), vr) <= 1e-10
+    assert rel_inf(v1.cpu().numpy(), vr) <= 1e-10
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 1e-7)])
@@ -205,7 +214,9 @@ def test_single_reduction_cg_graph_chunks(oracle_refs, precision, tol):
         wv, sa, _ = ctx.solve_adjoint(x1, _dev(w.x0), _dev(a), _dev(xbar))
         outs.append((x1.cpu().numpy(), wv.cpu().numpy(), st[0]["cg_iters"], sa[0]["adj_cg_iters"]))
     assert rel(outs[1][0] - w.x0, outs[0][0] - w.x0) <= tol
+    assert rel_inf(outs[1][0] - w.x0, outs[0][0] - w.x0) <= tol
     assert rel(outs[1][1], outs[0][1]) <= 1e3 * tol
+    assert rel_inf(outs[1][1], outs[0][1]) <= 1e3 * tol
     assert abs(outs[1][2] - outs[0][2]) <= 0.05 * outs[0][2] + 3
 
 
@@ -231,11 +242,14 @@ def test_compact_rest_record_matches_general(precision, tol):
     for k, name in enumerate(("gradient", "hessvec", "hessdiag")):
         print(name, rel(out[1][k], out[0][k]))
         assert rel(out[1][k], out[0][k]) <= (1e-13 if name != "hessvec" else tol)
+        assert rel_inf(out[1][k], out[0][k]) <= (1e-13 if name != "hessvec" else tol)
     assert rel(out[1][3] - w.x0, out[0][3] - w.x0) <= (1e-9 if precision == "fp64" else 1e-5)
+    assert rel_inf(out[1][3] - w.x0, out[0][3] - w.x0) <= (1e-9 if precision == "fp64" else 1e-5)
     p = problems(w)[0]
     H = p.hessian(x, w.x0, a)
-    assert rel(out[1][1].ravel(), H @ pv.ravel(), abs(H) @ np.abs(pv.ravel())) <= (1e-12 if precision == "fp64"
-                                                                                    else 2e-6)
+    hv_tol = 1e-12 if precision == "fp64" else 2e-6
+    assert rel(out[1][1].ravel(), H @ pv.ravel(), abs(H) @ np.abs(pv.ravel())) <= hv_tol
+    assert rel_inf(out[1][1].ravel(), H @ pv.ravel(), abs(H) @ np.abs(pv.ravel())) <= hv_tol
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 1e-5)])
@@ -265,6 +279,9 @@ def test_batched_compact_rest_record(precision, tol):
         for compact in (1, 0):
             x1, wv = out[compact]
             assert rel(x1[sv] - wb.x0, xr - wb.x0) <= tol
+            assert rel_inf(x1[sv] - wb.x0, xr - wb.x0) <= tol
             wr = solve.adjoint(p, x1[sv], wb.x0, wb.actions[0], xbar[sv])
             assert rel(wv[sv], wr) <= tol
+            assert rel_inf(wv[sv], wr) <= tol
     assert rel(out[1][0] - w.x0, out[0][0] - w.x0) <= (1e-11 if precision == "fp64" else 1e-5)
+    assert rel_inf(out[1][0] - w.x0, out[0][0] - w.x0) <= (1e-11 if precision == "fp64" else 1e-5)

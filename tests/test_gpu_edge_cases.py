@@ -77,14 +77,17 @@ def test_single_evaluations_at_inverted_and_J2_states(model, dim, state, scatter
     scale = abs_assembly(p, x, w.x0, w.v0, a)
     Gref = p.grad(x, w.x0, w.v0, a)
     assert rel(G, Gref, scale) <= 1e-12
+    assert rel_inf(G, Gref, scale) <= 1e-12
     assert np.all(np.isfinite(G))
     pv = rng.normal(size=x.shape)
     H = p.hessian(x, w.x0, a)
     Hp = ctx.hessvec(_dev(x), _dev(w.x0), _dev(a), _dev(pv)).cpu().numpy()
     assert rel(Hp.ravel(), H @ pv.ravel(), abs(H) @ np.abs(pv.ravel())) <= 1e-12
+    assert rel_inf(Hp.ravel(), H @ pv.ravel(), abs(H) @ np.abs(pv.ravel())) <= 1e-12
     Hd = ctx.hessdiag(_dev(x), _dev(w.x0), _dev(a)).cpu().numpy()
     free = ~w.pinned.ravel().astype(bool)
     assert rel(Hd.ravel()[free], H.diagonal()[free], abs(H).diagonal()[free]) <= 1e-12
+    assert rel_inf(Hd.ravel()[free], H.diagonal()[free], abs(H).diagonal()[free]) <= 1e-12
     E = ctx.energy(_dev(x), _dev(w.x0), _dev(w.v0), _dev(a)).cpu().numpy()
     ee, ev = p.energy_terms(x, w.x0, w.v0, a)
     assert np.isfinite(E[0])
@@ -125,6 +128,7 @@ def test_negative_curvature_exits_and_minimiser(solver, precision, tol):
     Hf = p.hessian(xr, w.x0, a).toarray()
     assert np.linalg.eigvalsh(Hf[np.ix_(free, free)])[0] > 0      # the oracle's end point is a minimum
     assert rel(x1 - w.x0, xr - w.x0) <= tol
+    assert rel_inf(x1 - w.x0, xr - w.x0) <= tol
     # the worst entry: from this squeezed start both solves end at the FP64 rounding floor of the
     # gradient sum (converged or stagnated), about 1e-10 in x, where the order of the GPU's atomic
     # additions moves the last digits from run to run; the rest shape, the exact minimiser, pins both
@@ -132,6 +136,7 @@ def test_negative_curvature_exits_and_minimiser(solver, precision, tol):
     assert rel_inf(x1 - w.x0, xr - w.x0) <= tol_inf
     assert rel_inf(x1 - w.x0, w.X - w.x0) <= tol_inf
     assert rel(xr - w.x0, w.X - w.x0) <= 1e-10       # the oracle found the rest shape
+    assert rel_inf(xr - w.x0, w.X - w.x0) <= 1e-10       # the oracle found the rest shape
 
 
 def _corotated_from_inverted(dim, seed):
@@ -174,7 +179,9 @@ def test_corotated_step_and_adjoint_from_inverted_start(solver, dim, precision, 
               "gpu", st[b])
         xs.append(xr)
         assert rel(x1[sv] - w.x0[sv], xr - w.x0[sv]) <= tol
+        assert rel_inf(x1[sv] - w.x0[sv], xr - w.x0[sv]) <= tol
         assert rel(v1[sv], vr) <= tol
+        assert rel_inf(v1[sv], vr) <= tol
     xs = np.concatenate(xs)
     xbar = rng.normal(size=xs.shape)
     wg, st, _ = ctx.solve_adjoint(_dev(xs), _dev(w.x0), _dev(a), _dev(xbar))
@@ -184,3 +191,4 @@ def test_corotated_step_and_adjoint_from_inverted_start(solver, dim, precision, 
         se = slice(w.body_e_off[b], w.body_e_off[b + 1])
         wr = solve.adjoint(p, xs[sv], w.x0[sv], a[se], xbar[sv])
         assert rel(wg[sv], wr) <= tol
+        assert rel_inf(wg[sv], wr) <= tol

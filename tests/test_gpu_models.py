@@ -50,6 +50,7 @@ def test_model_gradient_energy_vjp_parity_fp64(model, dim):
     G = ctx.gradient(_dev(x), _dev(w.x0), _dev(w.v0), _dev(a)).cpu().numpy()
     E = ctx.energy(_dev(x), _dev(w.x0), _dev(w.v0), _dev(a)).cpu().numpy()
     assert rel(G, p.grad(x, w.x0, w.v0, a), abs_assembly(p, x, w.x0, w.v0, a)) <= 1e-12
+    assert rel_inf(G, p.grad(x, w.x0, w.v0, a), abs_assembly(p, x, w.x0, w.v0, a)) <= 1e-12
     ee, ev = p.energy_terms(x, w.x0, w.v0, a)
     assert abs(E[0] - (ee.sum() + ev.sum())) <= 1e-13 * (np.abs(ee).sum() + np.abs(ev).sum())
     wv = rng.normal(size=x.shape)
@@ -57,6 +58,7 @@ def test_model_gradient_energy_vjp_parity_fp64(model, dim):
     ref = solve.vjp_params(p, wv, x, w.x0, a)
     for k in ("a_bar", "mu_bar", "lam_bar", "kf_bar", "x0_bar", "v0_bar"):
         assert rel(out[k], ref[k]) <= 1e-12, k
+        assert rel_inf(out[k], ref[k]) <= 1e-12, k
 
 
 @pytest.mark.parametrize("model", MODELS)
@@ -74,7 +76,9 @@ def test_model_hessvec_hessdiag_parity(model, dim, precision, tol):
     H = p.hessian(x, w.x0, a)
     ref = H @ pv.ravel()
     assert rel(Hp.ravel(), ref, abs(H) @ np.abs(pv.ravel())) <= tol
+    assert rel_inf(Hp.ravel(), ref, abs(H) @ np.abs(pv.ravel())) <= tol
     assert rel(Hd.ravel(), H.diagonal()) <= 1e-12
+    assert rel_inf(Hd.ravel(), H.diagonal()) <= 1e-12
 
 
 @pytest.mark.parametrize("model", MODELS)
@@ -89,6 +93,7 @@ def test_model_patch_scatter_large_mesh(model, dim, shape):
     pv = rng.normal(size=x.shape)
     G = ctx.gradient(_dev(x), _dev(w.x0), _dev(w.v0), _dev(a)).cpu().numpy()
     assert rel(G, p.grad(x, w.x0, w.v0, a), abs_assembly(p, x, w.x0, w.v0, a)) <= 1e-12
+    assert rel_inf(G, p.grad(x, w.x0, w.v0, a), abs_assembly(p, x, w.x0, w.v0, a)) <= 1e-12
     hp = _dev(np.zeros_like(x))
     ctx.hessvec_elements(_dev(x), _dev(a), _dev(pv), hp)
     K = p.s_pot * fem.element_hessians(p.mesh, x, p.mu, p.lam, p.kf, a, p.fd, model)
@@ -97,6 +102,7 @@ def test_model_patch_scatter_large_mesh(model, dim, shape):
     ref = np.zeros_like(x)
     np.add.at(ref, p.mesh.T, loc)
     assert rel(hp.cpu().numpy(), ref) <= 1e-12
+    assert rel_inf(hp.cpu().numpy(), ref) <= 1e-12
 
 
 @pytest.mark.parametrize("solver", [0, 1], ids=["plain", "batched"])
@@ -121,6 +127,7 @@ def test_model_step_adjoint_parity(solver, model, dim, precision, tol):
         assert rel(x1[sv] - w.x0[sv], xr - w.x0[sv]) <= tol
         assert rel_inf(x1[sv] - w.x0[sv], xr - w.x0[sv]) <= tol
         assert rel(v1[sv], vr) <= tol
+        assert rel_inf(v1[sv], vr) <= tol
     xs = np.concatenate(xs)
     xbar = rng.normal(size=xs.shape)
     vbar = rng.normal(size=xs.shape)

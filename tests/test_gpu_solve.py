@@ -37,13 +37,16 @@ def test_cantilever_quasistatic_parity():
     assert v1 is None
     assert st[0]["flags"] & 1 or st[0]["flags"] & 2
     assert rel(x1, x_ref) <= 1e-10
+    assert rel_inf(x1, x_ref) <= 1e-10
     assert rel(x1 - w.x0, x_ref - w.x0) <= 1e-10
+    assert rel_inf(x1 - w.x0, x_ref - w.x0) <= 1e-10
     # the minimiser at the 1e-10 tolerance of the cantilever workload
     w.scene["tol_rel"] = 1e-10
     ctx.set_scene(w.scene)
     x1b, _, st, _ = ctx.step(_dev(w.x0), None, _dev(w.actions[0]))
     assert st[0]["res_final"] <= 1e-10 * st[0]["res0"]
     assert rel(x1b.cpu().numpy() - w.x0, x_ref - w.x0) <= 1e-8
+    assert rel_inf(x1b.cpu().numpy() - w.x0, x_ref - w.x0) <= 1e-8
 
 
 @pytest.mark.parametrize("dim", [2, 3])
@@ -186,6 +189,7 @@ def test_batched_step_and_adjoint_parity(dim, precision, tol, block):
         assert rel(x1[sv] - w.x0[sv], xr - w.x0[sv]) <= tol
         assert rel_inf(x1[sv] - w.x0[sv], xr - w.x0[sv]) <= tol
         assert rel(v1[sv], vr) <= tol
+        assert rel_inf(v1[sv], vr) <= tol
     # adjoint at the oracle's x1 so that only the adjoint is compared
     xs = np.concatenate([solve.step(p, w.x0[slice(w.body_v_off[b], w.body_v_off[b + 1])],
                                     w.v0[slice(w.body_v_off[b], w.body_v_off[b + 1])],
@@ -289,10 +293,13 @@ def test_mixed_fp64_fallback_path(dim):
     # agree to the FP64 step parity bar; a mixed solve would be about 1e-6 away
     d = w.x0
     assert rel(x1.cpu().numpy() - d, xr.cpu().numpy() - d) <= 1e-10
+    assert rel_inf(x1.cpu().numpy() - d, xr.cpu().numpy() - d) <= 1e-10
     assert rel(v1.cpu().numpy(), vr.cpu().numpy()) <= 1e-10
+    assert rel_inf(v1.cpu().numpy(), vr.cpu().numpy()) <= 1e-10
     wv, sa, _ = mixed.solve_adjoint(xr, _dev(w.x0), _dev(a), _dev(xbar))
     assert all(s["flags"] & isb.FLAG_FP64_FALLBACK and s["flags"] & isb.FLAG_ADJ_CONVERGED for s in sa)
     assert rel(wv.cpu().numpy(), wr.cpu().numpy()) <= 1e-12
+    assert rel_inf(wv.cpu().numpy(), wr.cpu().numpy()) <= 1e-12
     with pytest.raises(Exception):
         mixed.set_option(isb.OPT_FP64_FALLBACK, 3)
 
@@ -327,6 +334,7 @@ def test_adjoint_warm_start(solver, dim, precision, tol):
         else:
             assert ss["adj_cg_iters"] < sc["adj_cg_iters"]
     assert rel(w_same.cpu().numpy(), w_cold.cpu().numpy()) <= tol
+    assert rel_inf(w_same.cpu().numpy(), w_cold.cpu().numpy()) <= tol
     start = w_cold + 0.1 * w_cold.abs().max() * _dev(rng.normal(size=w.x0.shape))
     w_warm, s_warm, _ = ctx.solve_adjoint(*args, w_init=start)
     assert all(s["flags"] & isb.FLAG_ADJ_CONVERGED for s in s_warm)
@@ -340,5 +348,6 @@ def test_adjoint_warm_start(solver, dim, precision, tol):
         sv = slice(w.body_v_off[b], w.body_v_off[b + 1])
         wr = solve.adjoint(Problem.from_workload(wb), x1h[sv], w.x0[sv], wb.actions[0], xbar[sv], vbar[sv])
         assert rel(ww[sv], wr) <= tol
+        assert rel_inf(ww[sv], wr) <= tol
     with pytest.raises(IsbError):
         ctx.set_option(isb.OPT_ADJ_WARM_START, 2)
